@@ -1,0 +1,207 @@
+/*
+ * pmmf.h — C ABI of the MI355X (gfx950) pMMF library.
+ *
+ * Parallel Multiresolution Matrix Factorization (Kondor, Teneva & Mudrakarta, "Parallel MMF: a
+ * Multiresolution Approach to Matrix Computation"): a symmetric A in R^{n x n} is factored as
+ *     A ~ U^T H U,   U = Qbar_P ... Qbar_1                               (Sec. 2, Eq. 1 and Eq. 4)
+ * where each stage Qbar_p is a product of Givens (k = 2) or 3-point (k = 3) rotations that is
+ * block diagonal in that stage's clustering (Def. 1), and H is core-diagonal: a dense core on the
+ * final active set plus the diagonal entries of the retired ("wavelet") indices.
+ *
+ * Conventions shared by every call:
+ *   - All functions return int: MMF_OK (0) or a negative MMF_E* code; no C++ exception crosses
+ *     the ABI.  mmf_last_error() returns a thread-local message for the last failure.
+ *   - Pointers prefixed d_ are device pointers (HIP global memory on the current device); all
+ *     other pointers are host pointers.  Inputs are borrowed for the duration of the call; outputs
+ *     are caller-allocated.  Work is enqueued on `stream` (a hipStream_t; NULL = default stream).
+ *   - Matrices are 0-based CSR: int64 row pointers [n+1], int32 column indices (strictly ascending
+ *     within each row) and float32 values [nnz], both triangles present.  Dense blocks of vectors are row-major [n][ld] float32 with
+ *     ld >= nrhs, so a rotation of indices (i, j) touches two contiguous rows.
+ *   - Global indices (retired ids, core ids, rotation ids) are row numbers of A.
+ *   - A handle is not safe for concurrent use on two streams.  Device faults surface as
+ *     MMF_EDEVICE at the next synchronizing call.
+ */
+#ifndef PMMF_H
+#define PMMF_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+  MMF_OK = 0,
+  MMF_EINVAL = -1,      /* bad size, k, eta, core size or cluster bounds                        */
+  MMF_ENOTSYM = -2,     /* MMF_CHECK_SYMMETRY was set and A is not exactly symmetric            */
+  MMF_ENONFINITE = -3,  /* NaN or Inf in the input                                              */
+  MMF_ENOMEM = -4,      /* device allocation failed                                            */
+  MMF_EDEVICE = -5,     /* a HIP runtime error; its text is in mmf_last_error()                 */
+  MMF_ESINGULAR = -6,   /* H cannot be inverted: a zero retired diagonal or a core that is not
+                           positive definite                                                    */
+  MMF_ESTATE = -7,      /* NULL or destroyed handle, or a call that does not fit its state     */
+  MMF_ECAPACITY = -8    /* a fixed device capacity was exceeded (message names it)             */
+};
+
+/* flags */
+#define MMF_CHECK_SYMMETRY   0x1u  /* verify A == A^T on the device before factoring            */
+#define MMF_EVEN_CLUSTERS    0x2u  /* round every cluster size but the last down to even (tests) */
+
+/* Factorization parameters (Sec. 2, Alg. 1 and Alg. 2). */
+typedef struct {
+  int32_t  k;            /* rotation order: 2 (Givens) or 3 (3-point rotations), Sec. 2 item 1  */
+  double   eta;          /* fraction of the active set retired per stage, in (0, 0.5] (Alg. 2's
+                            "compression ratio"): stage p performs
+                            t_p = min(|S| - core_size, floor(eta |S|)) rotations               */
+  int64_t  core_size;    /* delta_L, size of the dense core of H, 1 <= core_size <= n            */
+  int32_t  cluster_min;  /* lo, hi: random uneven cluster sizes in [lo, hi], hi >= 2 lo >= 4;   */
+  int32_t  cluster_max;  /* (0, 0) = one cluster per stage (plain MMF).  Sec. 2.1 clustering     */
+  uint64_t seed;         /* drives the random seed rows (Alg. 2) and the cluster sizes          */
+  int32_t  gram_mode;    /* 0 = FP32 cluster Gram (the only mode this build provides)           */
+  uint32_t flags;        /* MMF_* flags above                                                   */
+} mmf_params;
+
+typedef struct mmf_plan* mmf_handle;
+
+typedef struct {
+  int64_t n;             /* dimension of A                                                      */
+  int64_t core_size;     /* delta_L                                                             */
+  int32_t k;             /* rotation order                                                      */
+  int32_t num_stages;    /* P                                                                   */
+  int64_t num_rotations; /* n - delta_L (one index retired per rotation)                         */
+  int64_t max_clusters;  /* largest number of clusters in any stage                             */
+  double  loss;          /* exact residual ||A - U^T H U||_F^2 = 2 sum_e m_e, FP64 accumulation   */
+  double  loss_literal;  /* sum over retirements of 2 off^2 (an upper bound of loss)            */
+  double  fro2_a;        /* ||A||_F^2, FP64 accumulation                                        */
+  double  fro2_h;        /* ||H||_F^2, FP64 accumulation; loss ~ fro2_a - fro2_h                */
+  double  trace_a;       /* trace(A); trace(H) equals it up to rounding                         */
+  double  trace_h;
+  double  factor_ms;     /* device time of mmf_factor measured with HIP events                  */
+} mmf_info;
+
+typedef struct {
+  int64_t size;          /* |S_{p-1}|: active indices at the start of the stage                 */
+  int64_t rotations;     /* t_p                                                                 */
+  int64_t clusters;      /* m_p                                                                 */
+  int64_t nnz;           /* nonzeros of the stage's active matrix A_{p-1}[S_{p-1}, S_{p-1}]     */
+  int64_t max_cluster;   /* largest cluster of the stage                                        */
+  int32_t max_depth;     /* deepest chain of dependent rotations inside one cluster             */
+  int32_t pad;
+  double  loss;          /* residual contributed by this stage's retirements (FP64)             */
+} mmf_stage_info;
+
+/*
+ * mmf_factor — Alg. 1 with Alg. 2 inside.  For each stage: cluster the active set, form every
+ * cluster's Gram matrix and diagonal block, run the randomized greedy rotation search in each
+ * cluster, rotate the active matrix from both sides with the stage's rotations, and peel the
+ * retired rows and columns into H.  H's core is the final active block.
+ *   n, nnz, d_rowptr, d_colind, d_val : A in CSR (device), exactly symmetric.
+ *   p      : parameters (host, borrowed).
+ *   out    : receives a new handle owning all device state of the factorization.
+ * Synchronizes `stream` once per stage (to size the next stage's sparse storage) and at the end.
+ * Errors: MMF_EINVAL, MMF_ENOTSYM, MMF_ENONFINITE, MMF_ENOMEM, MMF_EDEVICE, MMF_ECAPACITY.
+ */
+int mmf_factor(int64_t n, int64_t nnz, const int64_t* d_rowptr, const int32_t* d_colind,
+               const float* d_val, const mmf_params* p, void* stream, mmf_handle* out);
+
+/*
+ * mmf_apply — matrix-free product Y = U^T H U X (Sec. 2.4): the stages' rotations in order, the
+ * retired diagonal and the dense core of H, then the transposed rotations in reverse order.
+ *   d_x : [n][ld] input (device, read only); d_y : [n][ld] output (device), may not alias d_x.
+ * Asynchronous on `stream`.  Errors: MMF_ESTATE, MMF_EINVAL, MMF_ENOMEM, MMF_EDEVICE.
+ */
+int mmf_apply(mmf_handle h, const float* d_x, float* d_y, int64_t nrhs, int64_t ld, void* stream);
+
+/*
+ * mmf_apply_inverse — Y = U^T H^{-1} U X (Sec. 2.4, inversion): reciprocal retired diagonal and
+ * the inverse of the core (an FP32 Cholesky factor computed on first use and kept).
+ * Errors as mmf_apply, plus MMF_ESINGULAR.
+ */
+int mmf_apply_inverse(mmf_handle h, const float* d_x, float* d_y, int64_t nrhs, int64_t ld,
+                      void* stream);
+
+/*
+ * mmf_backward — adjoint of Y = U^T H U X (from Eq. 1; the paper has no gradient) given Ybar:
+ *   d_xbar      [n][ld]         = U^T H^T U Ybar
+ *   d_hdiag_bar [n]             : sum over columns of (U Ybar)_e (U X)_e on retired e (0 on core)
+ *   d_hcore_bar [core][core]    : (U Ybar)_core (U X)_core^T, row-major
+ *   d_theta_bar [num_rotations] : d<Ybar, Y>/d theta_t for the Givens angle of rotation t, in the
+ *                                 order of mmf_export (k = 2 only; pass NULL for k = 3)
+ * Any of the four outputs may be NULL to skip it.  Stage states are recomputed by undoing
+ * rotations, not stored.  Asynchronous.  Errors: MMF_ESTATE, MMF_EINVAL, MMF_ENOMEM, MMF_EDEVICE.
+ */
+int mmf_backward(mmf_handle h, const float* d_x, const float* d_ybar, float* d_xbar,
+                 float* d_hdiag_bar, float* d_hcore_bar, float* d_theta_bar, int64_t nrhs,
+                 int64_t ld, void* stream);
+
+/* Summary of a finished factorization (host struct).  Errors: MMF_ESTATE. */
+int mmf_get_info(mmf_handle h, mmf_info* out);
+
+/* Per-stage summary, stage in [0, num_stages).  Errors: MMF_ESTATE, MMF_EINVAL. */
+int mmf_get_stage_info(mmf_handle h, int32_t stage, mmf_stage_info* out);
+
+/*
+ * mmf_export — copy the factorization to caller-allocated host arrays (any may be NULL):
+ *   rot_ids     int32 [num_rotations][k]   global ids, slot order (seed row first)
+ *   rot_o       float [num_rotations][k][k] rotation block O: x[ids] <- O x[ids]
+ *   rot_retired int32 [num_rotations]      global id eliminated by each rotation
+ *   rot_margin  float [num_rotations]      smallest relative decision margin of the step
+ *   hdiag       float [n]                  retired diagonal of H (0 on core indices)
+ *   core_ids    int32 [core_size]          ascending global ids of the core
+ *   hcore       float [core_size][core_size]
+ * Rotations are ordered by stage, then cluster, then step.  Synchronizes the handle's stream.
+ */
+int mmf_export(mmf_handle h, int32_t* rot_ids, float* rot_o, int32_t* rot_retired,
+               float* rot_margin, float* hdiag, int32_t* core_ids, float* hcore);
+
+/*
+ * mmf_import — build a handle for mmf_apply / mmf_apply_inverse / mmf_backward from a host-side
+ * factorization in the mmf_export layout plus its stage geometry:
+ *   n, k, core_size, num_stages
+ *   stage_sizes    int64 [num_stages]      |S_{p-1}|
+ *   stage_clusters int64 [num_stages]      m_p
+ *   cluster_sizes  int64 [sum m_p]         sizes of the contiguous clusters, stage by stage
+ *   rotation arrays as in mmf_export (rot_margin may be NULL), hdiag, core_ids, hcore.
+ * The active set of each stage is derived from the retirements.  Errors: MMF_EINVAL, MMF_ENOMEM,
+ * MMF_EDEVICE.
+ */
+int mmf_import(int64_t n, int32_t k, int64_t core_size, int32_t num_stages,
+               const int64_t* stage_sizes, const int64_t* stage_clusters,
+               const int64_t* cluster_sizes, const int32_t* rot_ids, const float* rot_o,
+               const int32_t* rot_retired, const float* hdiag, const int32_t* core_ids,
+               const float* hcore, void* stream, mmf_handle* out);
+
+/*
+ * mmf_param_ptrs — device pointers to the handle-owned parameters used by apply and backward:
+ *   theta [num_rotations] Givens angles (k = 2; NULL for k = 3), hdiag [n], hcore [core][core].
+ * They may be updated in place (e.g. by an optimizer); after changing theta call
+ * mmf_sync_angles so the rotations use the new angles.  Errors: MMF_ESTATE.
+ */
+int mmf_param_ptrs(mmf_handle h, float** theta, float** hdiag, float** hcore);
+
+/* Recompute the stored (cos, sin) of every Givens rotation from theta, on `stream`.  Also drops
+ * the cached core factor used by mmf_apply_inverse.  Errors: MMF_ESTATE, MMF_EDEVICE. */
+int mmf_sync_angles(mmf_handle h, void* stream);
+
+/*
+ * mmf_set_params — copy new parameters from caller device buffers into the handle, on `stream`:
+ *   d_theta [num_rotations] (k = 2 only), d_hdiag [n], d_hcore [core][core]; any may be NULL.
+ * Recomputes the rotations from theta when it is given and drops the cached core factor.
+ * Used by gradient refinement of the angles (the parameters of y = U^T H U x).
+ * Errors: MMF_ESTATE, MMF_EINVAL (theta for k = 3), MMF_EDEVICE.
+ */
+int mmf_set_params(mmf_handle h, const float* d_theta, const float* d_hdiag, const float* d_hcore,
+                   void* stream);
+
+/* Free the handle and all device memory it owns (synchronizes its stream). */
+int mmf_destroy(mmf_handle h);
+
+/* Thread-local text of the last error reported on this thread ("" if none). */
+const char* mmf_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* PMMF_H */

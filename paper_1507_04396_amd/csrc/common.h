@@ -1,0 +1,79 @@
+// Shared device helpers for the pMMF kernels (gfx950, wave64).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#define PMMF_WAVE 64
+
+// SplitMix64 output finalizer (Steele, Lea & Flood, OOPSLA 2014).  The seed row of each greedy
+// step and the cluster sizes are drawn from chains of it, so host and device agree bit for bit.
+__host__ __device__ inline uint64_t pmmf_mix64(uint64_t z) {
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+  return z ^ (z >> 31);
+}
+
+// x <- mix64((x xor v) + golden ratio constant), for v = a, b, c, d in turn, from x = seed.
+__host__ __device__ inline uint64_t pmmf_hash4(uint64_t seed, uint64_t a, uint64_t b, uint64_t c,
+                                               uint64_t d) {
+  const uint64_t g = 0x9E3779B97F4A7C15ull;
+  uint64_t x = seed;
+  x = pmmf_mix64((x ^ a) + g);
+  x = pmmf_mix64((x ^ b) + g);
+  x = pmmf_mix64((x ^ c) + g);
+  x = pmmf_mix64((x ^ d) + g);
+  return x;
+}
+
+// floor(x * n / 2^64): uniform index in [0, n) from a 64-bit hash (multiply-shift).
+__host__ __device__ inline uint64_t pmmf_mulhi(uint64_t x, uint64_t n) {
+#if defined(__HIP_DEVICE_COMPILE__)
+  return __umul64hi(x, n);
+#else
+  return (uint64_t)(((unsigned __int128)x * (unsigned __int128)n) >> 64);
+#endif
+}
+
+constexpr uint64_t PMMF_TAG_SEED_ROW = 1;
+constexpr uint64_t PMMF_TAG_CLUSTER_SIZE = 2;
+
+__device__ inline int pmmf_lane() { return threadIdx.x & (PMMF_WAVE - 1); }
+__device__ inline int pmmf_wave() { return threadIdx.x / PMMF_WAVE; }
+
+__device__ inline int pmmf_wave_sum_int(int v) {
+  for (int o = PMMF_WAVE / 2; o > 0; o >>= 1) v += __shfl_xor(v, o);
+  return v;
+}
+__device__ inline int pmmf_wave_min_int(int v) {
+  for (int o = PMMF_WAVE / 2; o > 0; o >>= 1) v = min(v, __shfl_xor(v, o));
+  return v;
+}
+__device__ inline int pmmf_wave_max_int(int v) {
+  for (int o = PMMF_WAVE / 2; o > 0; o >>= 1) v = max(v, __shfl_xor(v, o));
+  return v;
+}
+__device__ inline double pmmf_wave_sum_double(double v) {
+  for (int o = PMMF_WAVE / 2; o > 0; o >>= 1) v += __shfl_xor(v, o);
+  return v;
+}
+__device__ inline float pmmf_wave_sum_float(float v) {
+  for (int o = PMMF_WAVE / 2; o > 0; o >>= 1) v += __shfl_xor(v, o);
+  return v;
+}
+// inclusive prefix sum over the lanes of a wave
+__device__ inline int pmmf_wave_incl_scan(int v) {
+  const int lane = pmmf_lane();
+  for (int o = 1; o < PMMF_WAVE; o <<= 1) {
+    int t = __shfl_up(v, o);
+    if (lane >= o) v += t;
+  }
+  return v;
+}
+
+// Number of set bits of a 64-bit ballot below this lane.
+__device__ inline int pmmf_lanes_below(uint64_t mask) {
+  const int lane = pmmf_lane();
+  uint64_t below = lane == 0 ? 0ull : (mask & ((~0ull) >> (64 - lane)));
+  return __popcll(below);
+}

@@ -1,0 +1,84 @@
+// Kernels of the pMMF factorization (Alg. 1 with Alg. 2 inside), gfx950.
+//
+// Every stage works on the active matrix A_{p-1}[S_{p-1}, S_{p-1}] in CSR over "positions":
+// position q is the q-th smallest global index still active at the start of the stage.  The
+// stage's clusters are contiguous position ranges [off_u, off_u + c_u).
+#pragma once
+
+#include "common.h"
+
+namespace pmmf {
+
+struct FindArgs {
+  int p;                     // stage number, 1-based (enters the seed-row hash)
+  int k;                     // 2 or 3
+  uint64_t seed;
+  const int32_t* order;      // launch slot -> cluster id (largest clusters first)
+  const int32_t* off;        // [m+1] cluster offsets (positions)
+  const int32_t* rcnt;       // [m] rotations of each cluster
+  const int32_t* roff;       // [m+1] first stage-local rotation of each cluster
+  const int64_t* gbase;      // [m] offset of each cluster's c x c blocks in the pools
+  float* G;                  // Gram pool
+  float* D;                  // diagonal-block pool
+  float* Q;                  // accumulated-rotation pool
+  const int32_t* gid;        // [S] global id of each position
+  int64_t rot0;              // global index of the stage's first rotation
+  int32_t* rot_loc;          // [R][3] cluster-local ids, slot order
+  int32_t* rot_gid;          // [R][3] global ids, slot order
+  float* rot_o;              // [R][9] k x k block (row-major, leading dim 3)
+  int32_t* rot_ret;          // [R] retired global id
+  float* rot_margin;         // [R] smallest relative decision margin
+  float* theta;              // [R] Givens angle (k = 2)
+  double* rot_lit;           // [R] 2 off^2 of the retired index (literal loss term)
+  float* hdiag;              // [n] retired diagonal of H
+  uint8_t* retflag;          // [S] 1 if the position retires in this stage
+  int32_t* err;              // set to 1 if a cluster finds no partner (never expected)
+};
+
+}  // namespace pmmf
+
+// launchers (factor_kernels.hip)
+namespace pmmf {
+hipError_t launch_fill_cluster_of(const int32_t* off, int m, int S, int32_t* cl_of, hipStream_t s);
+hipError_t launch_gram(int S, const int64_t* rp, const int32_t* ci, const float* cv,
+                       const int32_t* off, const int32_t* cl_of, const int64_t* gbase, float* G,
+                       float* D, float* Q, int cmax, hipStream_t s);
+hipError_t launch_find(const FindArgs& a, int m, int cmax, hipStream_t s);
+hipError_t launch_levelize(int m, int k, const int32_t* off, const int32_t* rcnt,
+                           const int32_t* roff, int64_t rot0, const int32_t* rot_loc,
+                           const float* rot_o, int lvl_stride, int32_t* lvl_ptr, int32_t* depth,
+                           int32_t* sw_loc, float* sw_o, int32_t* sw_idx, int cmax, hipStream_t s);
+hipError_t launch_transpose_blocks(int m, const int32_t* off, const int64_t* gbase,
+                                   const int64_t* tbase, int64_t ntiles, const float* src,
+                                   float* dst, hipStream_t s);
+hipError_t launch_qbar_count(int S, const int32_t* off, const int32_t* cl_of,
+                             const int64_t* gbase, const float* Q, int32_t* cnt, hipStream_t s);
+hipError_t launch_qbar_fill(int S, const int32_t* off, const int32_t* cl_of,
+                            const int64_t* gbase, const float* Q, const int64_t* rp, int32_t* ci,
+                            float* cv, hipStream_t s);
+hipError_t launch_right(int S, int fill, const int64_t* rp, const int32_t* ci, const float* cv,
+                        const int32_t* off, const int32_t* cl_of, const int64_t* qrp,
+                        const int32_t* qci, const float* qcv, int32_t* cnt, const int64_t* orp,
+                        int32_t* oci, float* ocv, int cmax, hipStream_t s);
+hipError_t launch_left(int S, int fill, const int64_t* qrp, const int32_t* qci, const float* qcv,
+                       const int64_t* wrp, const int32_t* wci, const float* wcv,
+                       const int32_t* off, const int32_t* cl_of, const int32_t* next,
+                       int32_t* cnt, const int64_t* orp, int32_t* oci, float* ocv,
+                       double* loss_row, int32_t* overflow, int cmax, hipStream_t s);
+hipError_t launch_next_positions(int S, const uint8_t* retflag, const int64_t* scan,
+                                 const int32_t* gid, int32_t* next, int32_t* gid_new,
+                                 hipStream_t s);
+hipError_t launch_keep_flags(int S, const uint8_t* retflag, int32_t* keep, hipStream_t s);
+hipError_t launch_scan(const int32_t* in, int64_t* out, int64_t n, int64_t* tmp, hipStream_t s);
+int64_t scan_tmp_elems(int64_t n);
+hipError_t launch_sum_double(const double* in, int64_t n, double* out, hipStream_t s);
+hipError_t launch_csr_stats(int64_t n, const int64_t* rp, const int32_t* ci, const float* cv,
+                            int check_sym, double* fro2_trace, int32_t* flags, hipStream_t s);
+hipError_t launch_core_dense(int S, const int64_t* rp, const int32_t* ci, const float* cv,
+                             float* hcore, hipStream_t s);
+hipError_t launch_h_stats(int64_t n, const float* hdiag, int64_t core, const float* hcore,
+                          double* out, hipStream_t s);
+hipError_t launch_copy_csr(int64_t n, const int64_t* rp, const int32_t* ci, const float* cv,
+                           int64_t* orp, int32_t* oci, float* ocv, hipStream_t s);
+hipError_t launch_iota(int32_t* a, int64_t n, hipStream_t s);
+}  // namespace pmmf

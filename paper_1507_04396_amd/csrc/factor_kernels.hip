@@ -1,0 +1,1112 @@
+// Factorization kernels for pMMF on gfx950 (wave64).  See factor_kernels.h for the data layout.
+#include "factor_kernels.h"
+
+#include <climits>
+
+namespace pmmf {
+
+// ------------------------------------------------------------------------------------------
+// cluster of every position
+__global__ void k_fill_cluster_of(const int32_t* __restrict__ off, int m, int S,
+                                  int32_t* __restrict__ cl_of) {
+  int q = blockIdx.x * blockDim.x + threadIdx.x;
+  if (q >= S) return;
+  int lo = 0, hi = m - 1;  // last u with off[u] <= q
+  while (lo < hi) {
+    int mid = (lo + hi + 1) >> 1;
+    if (off[mid] <= q) lo = mid; else hi = mid - 1;
+  }
+  cl_of[q] = lo;
+}
+
+hipError_t launch_fill_cluster_of(const int32_t* off, int m, int S, int32_t* cl_of, hipStream_t s) {
+  if (S == 0) return hipSuccess;
+  k_fill_cluster_of<<<(S + 255) / 256, 256, 0, s>>>(off, m, S, cl_of);
+  return hipGetLastError();
+}
+
+__device__ inline int64_t lower_bound_i32(const int32_t* __restrict__ a, int64_t lo, int64_t hi,
+                                          int32_t key) {
+  while (lo < hi) {
+    int64_t mid = (lo + hi) >> 1;
+    if (a[mid] < key) lo = mid + 1; else hi = mid;
+  }
+  return lo;
+}
+
+// ------------------------------------------------------------------------------------------
+// Cluster Gram, diagonal block and identity rotation accumulator (Sec. 2.1: G^u = A_Bu^T A_Bu).
+// One wave per position a (row la of its cluster u).  Row la of G is
+//     G[la, b] = sum_r M[a, r] * M[r, o_u + b],  b in [0, c_u)
+// i.e. the inner products of column a with the cluster's columns over all active rows r (M is
+// symmetric, so column a's entries are row a's).  The row is accumulated in LDS in ascending r
+// (deterministic) and written densely, which also clears the previous stage's contents.
+__global__ void __launch_bounds__(256) k_gram(int S, const int64_t* __restrict__ rp,
+                                              const int32_t* __restrict__ ci,
+                                              const float* __restrict__ cv,
+                                              const int32_t* __restrict__ off,
+                                              const int32_t* __restrict__ cl_of,
+                                              const int64_t* __restrict__ gbase,
+                                              float* __restrict__ G, float* __restrict__ D,
+                                              float* __restrict__ Q, int cmax) {
+  extern __shared__ float lds_f[];
+  const int wpb = blockDim.x / PMMF_WAVE;
+  const int w = pmmf_wave(), lane = pmmf_lane();
+  float* acc = lds_f + (size_t)w * cmax;
+  const int a = blockIdx.x * wpb + w;
+  if (a >= S) return;
+  const int u = cl_of[a];
+  const int o = off[u];
+  const int c = off[u + 1] - o;
+  const int la = a - o;
+  for (int j = lane; j < c; j += PMMF_WAVE) acc[j] = 0.f;
+  const int64_t a0 = rp[a], a1 = rp[a + 1];
+  for (int64_t kk = a0; kk < a1; ++kk) {
+    const int r = ci[kk];
+    const float war = cv[kk];
+    const int64_t lb = lower_bound_i32(ci, rp[r], rp[r + 1], o);
+    const int64_t ub = lower_bound_i32(ci, lb, rp[r + 1], o + c);
+    for (int64_t t = lb + lane; t < ub; t += PMMF_WAVE) acc[ci[t] - o] += war * cv[t];
+  }
+  const size_t base = (size_t)gbase[u] + (size_t)la * c;
+  for (int j = lane; j < c; j += PMMF_WAVE) {
+    G[base + j] = acc[j];
+    acc[j] = 0.f;
+    Q[base + j] = (j == la) ? 1.f : 0.f;
+  }
+  const int64_t lb = lower_bound_i32(ci, a0, a1, o);
+  const int64_t ub = lower_bound_i32(ci, lb, a1, o + c);
+  for (int64_t t = lb + lane; t < ub; t += PMMF_WAVE) acc[ci[t] - o] = cv[t];
+  for (int j = lane; j < c; j += PMMF_WAVE) D[base + j] = acc[j];
+}
+
+hipError_t launch_gram(int S, const int64_t* rp, const int32_t* ci, const float* cv,
+                       const int32_t* off, const int32_t* cl_of, const int64_t* gbase, float* G,
+                       float* D, float* Q, int cmax, hipStream_t s) {
+  if (S == 0) return hipSuccess;
+  int wpb = 4;
+  while (wpb > 1 && (size_t)wpb * cmax * 4 > 64 * 1024) wpb >>= 1;
+  const size_t lds = (size_t)wpb * cmax * sizeof(float);
+  k_gram<<<(S + wpb - 1) / wpb, wpb * PMMF_WAVE, lds, s>>>(S, rp, ci, cv, off, cl_of, gbase, G, D,
+                                                           Q, cmax);
+  return hipGetLastError();
+}
+
+// ------------------------------------------------------------------------------------------
+// FP64 k x k rotations (Sec. 2.2: the rotation diagonalizes the k x k Gram block).
+
+// 2x2 symmetric Schur decomposition (Golub & Van Loan Alg. 8.4.1) with |theta| <= pi/4.
+// Returns O = [[c, -s], [s, c]] with O g O^T diagonal; O = I when the coupling is zero.
+__device__ inline void rot2(double a, double b, double d, double& c, double& s, double& tau_abs) {
+  if (b == 0.0) {
+    c = 1.0; s = 0.0; tau_abs = 1e300;
+    return;
+  }
+  const double tau = (d - a) / (2.0 * b);
+  const double sg = tau >= 0.0 ? 1.0 : -1.0;
+  const double t = sg / (fabs(tau) + hypot(1.0, tau));
+  c = 1.0 / sqrt(1.0 + t * t);
+  s = t * c;
+  tau_abs = fabs(tau);
+}
+
+// 3x3: cyclic Jacobi eigendecomposition, eigenvectors in descending eigenvalue order as rows,
+// then the row permutation and signs maximizing trace(O) with O_rr >= 0 (lexicographically
+// smallest permutation on ties).
+__device__ inline void rot3(const double g[3][3], double O[3][3], double& trace_margin,
+                            double& eig_margin) {
+  double A[3][3], V[3][3];
+  for (int i = 0; i < 3; ++i)
+    for (int j = 0; j < 3; ++j) { A[i][j] = g[i][j]; V[i][j] = (i == j) ? 1.0 : 0.0; }
+  for (int sweep = 0; sweep < 16; ++sweep) {
+    const double offd = A[0][1] * A[0][1] + A[0][2] * A[0][2] + A[1][2] * A[1][2];
+    const double dg = A[0][0] * A[0][0] + A[1][1] * A[1][1] + A[2][2] * A[2][2];
+    if (offd <= 1e-36 * dg || offd == 0.0) break;
+    for (int pq = 0; pq < 3; ++pq) {
+      const int p = pq == 2 ? 1 : 0;
+      const int q = pq == 0 ? 1 : 2;
+      if (A[p][q] == 0.0) continue;
+      const double tau = (A[q][q] - A[p][p]) / (2.0 * A[p][q]);
+      const double sg = tau >= 0.0 ? 1.0 : -1.0;
+      const double t = sg / (fabs(tau) + hypot(1.0, tau));
+      const double c = 1.0 / sqrt(1.0 + t * t);
+      const double s = t * c;
+      // A <- J^T A J with J = [[c, s], [-s, c]] on (p, q); V <- V J
+      for (int r = 0; r < 3; ++r) {
+        const double arp = A[r][p], arq = A[r][q];
+        A[r][p] = c * arp - s * arq;
+        A[r][q] = s * arp + c * arq;
+      }
+      for (int r = 0; r < 3; ++r) {
+        const double apr = A[p][r], aqr = A[q][r];
+        A[p][r] = c * apr - s * aqr;
+        A[q][r] = s * apr + c * aqr;
+      }
+      A[p][q] = A[q][p] = 0.0;
+      for (int r = 0; r < 3; ++r) {
+        const double vrp = V[r][p], vrq = V[r][q];
+        V[r][p] = c * vrp - s * vrq;
+        V[r][q] = s * vrp + c * vrq;
+      }
+    }
+  }
+  // descending eigenvalues
+  int idx[3] = {0, 1, 2};
+  double ev[3] = {A[0][0], A[1][1], A[2][2]};
+  for (int i = 0; i < 3; ++i)
+    for (int j = i + 1; j < 3; ++j)
+      if (ev[idx[j]] > ev[idx[i]]) { int t = idx[i]; idx[i] = idx[j]; idx[j] = t; }
+  double base[3][3];  // base[r] = eigenvector of the r-th largest eigenvalue
+  for (int r = 0; r < 3; ++r)
+    for (int j = 0; j < 3; ++j) base[r][j] = V[j][idx[r]];
+  const double emax = fmax(fabs(ev[idx[0]]), fabs(ev[idx[2]]));
+  const double gap = fmin(ev[idx[0]] - ev[idx[1]], ev[idx[1]] - ev[idx[2]]);
+  eig_margin = emax > 0.0 ? gap / emax : 0.0;
+  const int perms[6][3] = {{0, 1, 2}, {0, 2, 1}, {1, 0, 2}, {1, 2, 0}, {2, 0, 1}, {2, 1, 0}};
+  double tr[6];
+  int best = 0;
+  for (int q = 0; q < 6; ++q) {
+    tr[q] = fabs(base[perms[q][0]][0]) + fabs(base[perms[q][1]][1]) + fabs(base[perms[q][2]][2]);
+    if (tr[q] > tr[best]) best = q;
+  }
+  double second = -1.0;
+  for (int q = 0; q < 6; ++q)
+    if (q != best) second = fmax(second, tr[q]);
+  trace_margin = tr[best] > 0.0 ? (tr[best] - second) / tr[best] : 0.0;
+  for (int r = 0; r < 3; ++r) {
+    const double* row = base[perms[best][r]];
+    const double sg = row[r] >= 0.0 ? 1.0 : -1.0;
+    for (int j = 0; j < 3; ++j) O[r][j] = sg * row[j];
+  }
+}
+
+// ------------------------------------------------------------------------------------------
+// Randomized greedy rotation search inside one cluster (Alg. 2), one workgroup per cluster.
+struct Cand {
+  float s;
+  int j;
+};
+__device__ inline bool better(const Cand& a, const Cand& b) {
+  return a.s > b.s || (a.s == b.s && a.j < b.j);
+}
+__device__ inline void merge2(Cand& b1, Cand& b2, const Cand& o1, const Cand& o2) {
+  if (better(o1, b1)) {
+    b2 = better(b1, o2) ? b1 : o2;
+    b1 = o1;
+  } else if (better(o1, b2)) {
+    b2 = o1;
+  }
+}
+
+// i-th set bit (0-based rank) of the active bitmask held in LDS; called by one whole wave.
+__device__ inline int select_active(const uint32_t* mask, int nw, int rank) {
+  const int lane = pmmf_lane();
+  const int wpl = (nw + PMMF_WAVE - 1) / PMMF_WAVE;
+  const int w0 = lane * wpl;
+  int cnt = 0;
+  for (int t = 0; t < wpl; ++t)
+    if (w0 + t < nw) cnt += __popc(mask[w0 + t]);
+  const int incl = pmmf_wave_incl_scan(cnt);
+  int found = -1;
+  int excl = incl - cnt;
+  if (rank >= excl && rank < incl) {
+    for (int t = 0; t < wpl; ++t) {
+      uint32_t m = mask[w0 + t];
+      const int pc = __popc(m);
+      if (rank - excl < pc) {
+        int rr = rank - excl;
+        for (int q = 0; q < rr; ++q) m &= m - 1;
+        found = (w0 + t) * 32 + (__ffs(m) - 1);
+        break;
+      }
+      excl += pc;
+    }
+  }
+  // exactly one lane found it
+  uint64_t b = __ballot(found >= 0);
+  const int src = __ffsll((unsigned long long)b) - 1;
+  return __shfl(found, src);
+}
+
+template <int NT>
+__global__ void __launch_bounds__(NT) k_find(FindArgs A, int cmax) {
+  extern __shared__ float lds_f[];
+  float* gdiag = lds_f;
+  float* ddiag = gdiag + cmax;
+  float* rowGi = ddiag + cmax;
+  float* rowDi = rowGi + cmax;
+  uint32_t* mask = reinterpret_cast<uint32_t*>(rowDi + cmax);
+  __shared__ Cand red1[NT / PMMF_WAVE], red2[NT / PMMF_WAVE];
+  __shared__ int sh_i, sh_T[3], sh_kk, sh_bad;
+  __shared__ float sh_O[9];
+
+  const int tid = threadIdx.x;
+  const int u = A.order[blockIdx.x];
+  const int o = A.off[u];
+  const int c = A.off[u + 1] - o;
+  const int r = A.rcnt[u];
+  const int rb = A.roff[u];
+  const int nw = (c + 31) / 32;
+  float* G = A.G + A.gbase[u];
+  float* D = A.D + A.gbase[u];
+  float* Q = A.Q + A.gbase[u];
+
+  for (int j = tid; j < c; j += NT) {
+    gdiag[j] = G[(size_t)j * c + j];
+    ddiag[j] = D[(size_t)j * c + j];
+  }
+  for (int q = tid; q < nw; q += NT) {
+    const int rem = c - q * 32;
+    mask[q] = rem >= 32 ? 0xffffffffu : ((1u << rem) - 1u);
+  }
+  __syncthreads();
+
+  for (int s = 0; s < r; ++s) {
+    // seed row, uniform over the active set (ascending local order)
+    if (tid < PMMF_WAVE) {
+      const int live = c - s;
+      const uint64_t h = pmmf_hash4(A.seed, PMMF_TAG_SEED_ROW, (uint64_t)A.p, (uint64_t)u,
+                                    (uint64_t)s);
+      const int rank = (int)pmmf_mulhi(h, (uint64_t)live);
+      const int i = select_active(mask, nw, rank);
+      if (tid == 0) {
+        sh_i = i;
+        sh_kk = A.k;  // the host guarantees at least k live indices at every step
+      }
+    }
+    __syncthreads();
+    const int i = sh_i;
+    const int kk = sh_kk;
+
+    // partner scores |G_ij| / sqrt(G_jj) over the active set, top (k - 1), lower j on ties
+    Cand b1{-1.f, INT_MAX}, b2{-1.f, INT_MAX};
+    {
+      const float* Gi = G + (size_t)i * c;
+      const float* Di = D + (size_t)i * c;
+      for (int j = tid; j < c; j += NT) {
+        const float g = Gi[j];
+        rowGi[j] = g;
+        rowDi[j] = Di[j];
+        const bool act = (mask[j >> 5] >> (j & 31)) & 1u;
+        if (act && j != i) {
+          const float gd = gdiag[j];
+          float sc = gd > 0.f ? fabsf(g) / sqrtf(gd) : 0.f;
+          if (!(sc >= 0.f)) sc = 0.f;  // NaN from an overflowed Gram entry scores 0
+          Cand cnd{sc, j};
+          if (better(cnd, b1)) { b2 = b1; b1 = cnd; }
+          else if (better(cnd, b2)) b2 = cnd;
+        }
+      }
+    }
+    for (int ofs = PMMF_WAVE / 2; ofs > 0; ofs >>= 1) {
+      Cand o1{__shfl_xor(b1.s, ofs), __shfl_xor(b1.j, ofs)};
+      Cand o2{__shfl_xor(b2.s, ofs), __shfl_xor(b2.j, ofs)};
+      merge2(b1, b2, o1, o2);
+    }
+    if (pmmf_lane() == 0) { red1[pmmf_wave()] = b1; red2[pmmf_wave()] = b2; }
+    __syncthreads();
+
+    if (tid == 0) {
+      Cand f1 = red1[0], f2 = red2[0];
+      for (int q = 1; q < NT / PMMF_WAVE; ++q) merge2(f1, f2, red1[q], red2[q]);
+      sh_bad = (f1.j >= c || (kk == 3 && f2.j >= c)) ? 1 : 0;
+    }
+    __syncthreads();
+    if (sh_bad) {  // no partner found: impossible with >= k live indices; report and stop
+      if (tid == 0) atomicOr(A.err, 1);
+      return;
+    }
+    if (tid == 0) {
+      Cand f1 = red1[0], f2 = red2[0];
+      for (int q = 1; q < NT / PMMF_WAVE; ++q) merge2(f1, f2, red1[q], red2[q]);
+      int T[3] = {i, f1.j, f2.j};
+      double margin = 1e300;
+      // k = 2: relative gap between the chosen partner and the runner-up
+      if (kk == 2 && f2.j != INT_MAX)
+        margin = fmin(margin, f1.s > 0.f ? (double)(f1.s - f2.s) / f1.s : 0.0);
+      double g[3][3], d[3][3], O[3][3];
+      for (int a = 0; a < kk; ++a)
+        for (int b = 0; b < kk; ++b) {
+          if (a == b) {
+            g[a][a] = gdiag[T[a]];
+            d[a][a] = ddiag[T[a]];
+          } else if (a == 0 || b == 0) {
+            const int other = a == 0 ? T[b] : T[a];
+            g[a][b] = rowGi[other];
+            d[a][b] = rowDi[other];
+          } else {
+            g[a][b] = G[(size_t)T[a] * c + T[b]];
+            d[a][b] = D[(size_t)T[a] * c + T[b]];
+          }
+        }
+      if (kk == 3) {  // symmetrize the partner-partner entry
+        g[1][2] = g[2][1] = 0.5 * (g[1][2] + g[2][1]);
+        d[1][2] = d[2][1] = 0.5 * (d[1][2] + d[2][1]);
+      }
+      if (kk == 2) {
+        double cc, ss, ta;
+        rot2(g[0][0], g[0][1], g[1][1], cc, ss, ta);
+        O[0][0] = cc; O[0][1] = -ss; O[1][0] = ss; O[1][1] = cc;
+        margin = fmin(margin, ta);
+      } else {
+        double tm, em;
+        rot3(g, O, tm, em);
+        margin = fmin(margin, fmin(tm, em));
+      }
+      // rotated k x k blocks: O g O^T and O d O^T
+      double gn[3][3], dn[3][3];
+      for (int a = 0; a < kk; ++a)
+        for (int b = 0; b < kk; ++b) {
+          double sg = 0.0, sd = 0.0;
+          for (int x = 0; x < kk; ++x) {
+            double tg = 0.0, td = 0.0;
+            for (int y = 0; y < kk; ++y) { tg += g[x][y] * O[b][y]; td += d[x][y] * O[b][y]; }
+            sg += O[a][x] * tg;
+            sd += O[a][x] * td;
+          }
+          gn[a][b] = sg;
+          dn[a][b] = sd;
+        }
+      // eliminate the slot with the smallest off-diagonal norm (ties: later slot)
+      double off2[3];
+      int es = 0;
+      for (int a = 0; a < kk; ++a) {
+        off2[a] = fmax(0.0, gn[a][a] - dn[a][a] * dn[a][a]);
+        if (a > 0 && off2[a] <= off2[es]) es = a;
+      }
+      {
+        double lo1 = 1e300, lo2 = 1e300;
+        for (int a = 0; a < kk; ++a) {
+          if (off2[a] < lo1) { lo2 = lo1; lo1 = off2[a]; }
+          else if (off2[a] < lo2) lo2 = off2[a];
+        }
+        margin = fmin(margin, lo2 > 0.0 ? (lo2 - lo1) / lo2 : 0.0);
+      }
+      const int e = T[es];
+      // log
+      const int64_t ridx = A.rot0 + rb + s;
+      for (int a = 0; a < 3; ++a) {
+        A.rot_loc[ridx * 3 + a] = a < kk ? T[a] : -1;
+        A.rot_gid[ridx * 3 + a] = a < kk ? A.gid[o + T[a]] : -1;
+      }
+      for (int a = 0; a < 9; ++a) A.rot_o[ridx * 9 + a] = 0.f;
+      for (int a = 0; a < kk; ++a)
+        for (int b = 0; b < kk; ++b) A.rot_o[ridx * 9 + a * 3 + b] = (float)O[a][b];
+      A.rot_ret[ridx] = A.gid[o + e];
+      A.rot_margin[ridx] = (float)fmin(margin, 3.0e38);
+      A.rot_lit[ridx] = 2.0 * off2[es];
+      if (kk == 2) A.theta[ridx] = (float)atan2(O[1][0], O[0][0]);
+      A.hdiag[A.gid[o + e]] = (float)dn[es][es];
+      A.retflag[o + e] = 1;
+      for (int a = 0; a < kk; ++a) {
+        gdiag[T[a]] = (float)gn[a][a];
+        ddiag[T[a]] = (float)dn[a][a];
+        for (int b = 0; b < kk; ++b) {
+          G[(size_t)T[a] * c + T[b]] = (float)gn[a][b];
+          D[(size_t)T[a] * c + T[b]] = (float)dn[a][b];
+        }
+      }
+      mask[e >> 5] &= ~(1u << (e & 31));
+      for (int a = 0; a < 3; ++a) sh_T[a] = a < kk ? T[a] : -1;
+      for (int a = 0; a < kk; ++a)
+        for (int b = 0; b < kk; ++b) sh_O[a * 3 + b] = (float)O[a][b];
+    }
+    __syncthreads();
+
+    // G <- O G O^T, D <- O D O^T on rows/columns T (active columns only: retired columns are
+    // never read again), Q <- O Q on rows T (all columns)
+    {
+      const int t0 = sh_T[0], t1 = sh_T[1], t2 = sh_T[2];
+      float o_[9];
+      for (int a = 0; a < 9; ++a) o_[a] = sh_O[a];
+      for (int j = tid; j < c; j += NT) {
+        if (kk == 2) {
+          const float q0 = Q[(size_t)t0 * c + j], q1 = Q[(size_t)t1 * c + j];
+          Q[(size_t)t0 * c + j] = o_[0] * q0 + o_[1] * q1;
+          Q[(size_t)t1 * c + j] = o_[3] * q0 + o_[4] * q1;
+        } else {
+          const float q0 = Q[(size_t)t0 * c + j], q1 = Q[(size_t)t1 * c + j],
+                      q2 = Q[(size_t)t2 * c + j];
+          Q[(size_t)t0 * c + j] = o_[0] * q0 + o_[1] * q1 + o_[2] * q2;
+          Q[(size_t)t1 * c + j] = o_[3] * q0 + o_[4] * q1 + o_[5] * q2;
+          Q[(size_t)t2 * c + j] = o_[6] * q0 + o_[7] * q1 + o_[8] * q2;
+        }
+        const bool act = (mask[j >> 5] >> (j & 31)) & 1u;
+        if (!act || j == t0 || j == t1 || j == t2) continue;
+        float gv[3], dv[3], gn[3], dn[3];
+        gv[0] = rowGi[j];
+        dv[0] = rowDi[j];
+        gv[1] = G[(size_t)t1 * c + j];
+        dv[1] = D[(size_t)t1 * c + j];
+        if (kk == 3) {
+          gv[2] = G[(size_t)t2 * c + j];
+          dv[2] = D[(size_t)t2 * c + j];
+        }
+        for (int a = 0; a < kk; ++a) {
+          float sg = 0.f, sd = 0.f;
+          for (int b = 0; b < kk; ++b) {
+            sg += o_[a * 3 + b] * gv[b];
+            sd += o_[a * 3 + b] * dv[b];
+          }
+          gn[a] = sg;
+          dn[a] = sd;
+        }
+        const int Tt[3] = {t0, t1, t2};
+        for (int a = 0; a < kk; ++a) {
+          G[(size_t)Tt[a] * c + j] = gn[a];
+          D[(size_t)Tt[a] * c + j] = dn[a];
+          if (gn[a] != 0.f || gv[a] != 0.f) G[(size_t)j * c + Tt[a]] = gn[a];
+          if (dn[a] != 0.f || dv[a] != 0.f) D[(size_t)j * c + Tt[a]] = dn[a];
+        }
+      }
+    }
+    __syncthreads();
+  }
+}
+
+hipError_t launch_find(const FindArgs& a, int m, int cmax, hipStream_t s) {
+  if (m == 0) return hipSuccess;
+  const size_t lds = (size_t)cmax * 4 * sizeof(float) + (size_t)((cmax + 31) / 32) * 4;
+  if (lds > 64 * 1024) {
+    hipError_t e = hipFuncSetAttribute((const void*)k_find<256>,
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e != hipSuccess) return e;
+  }
+  k_find<256><<<m, 256, lds, s>>>(a, cmax);
+  return hipGetLastError();
+}
+
+// ------------------------------------------------------------------------------------------
+// Levels of each cluster's rotation sequence: rotation s sits one level above the latest
+// earlier rotation sharing an index with it.  Rotations of one level touch disjoint indices, so
+// they commute and can be applied together.  Writes the stage's sweep log in level order.
+__global__ void k_levelize(int k, const int32_t* __restrict__ off, const int32_t* __restrict__ rcnt,
+                           const int32_t* __restrict__ roff, int64_t rot0,
+                           const int32_t* __restrict__ rot_loc, const float* __restrict__ rot_o,
+                           int lvl_stride, int32_t* __restrict__ lvl_ptr,
+                           int32_t* __restrict__ depth_out, int32_t* __restrict__ sw_loc,
+                           float* __restrict__ sw_o, int32_t* __restrict__ sw_idx, int cmax) {
+  extern __shared__ int lds_i[];
+  int* last = lds_i;          // [cmax]
+  int* lvl = last + cmax;     // [cmax]
+  int* start = lvl + cmax;    // [cmax + 2]
+  const int u = blockIdx.x;
+  const int c = off[u + 1] - off[u];
+  const int r = rcnt[u];
+  const int rb = roff[u];
+  for (int j = threadIdx.x; j < c; j += blockDim.x) last[j] = 0;
+  for (int j = threadIdx.x; j < c + 2; j += blockDim.x) start[j] = 0;
+  __syncthreads();
+  if (threadIdx.x != 0) return;
+  int depth = 0;
+  for (int s = 0; s < r; ++s) {
+    const int64_t ridx = rot0 + rb + s;
+    int L = 0;
+    for (int a = 0; a < 3; ++a) {
+      const int id = rot_loc[ridx * 3 + a];
+      if (id >= 0) L = max(L, last[id]);
+    }
+    L += 1;
+    for (int a = 0; a < 3; ++a) {
+      const int id = rot_loc[ridx * 3 + a];
+      if (id >= 0) last[id] = L;
+    }
+    lvl[s] = L;
+    start[L] += 1;
+    depth = max(depth, L);
+  }
+  int acc = 0;
+  for (int l = 1; l <= depth; ++l) {
+    const int cnt = start[l];
+    start[l] = acc;
+    lvl_ptr[(size_t)u * lvl_stride + (l - 1)] = rb + acc;
+    acc += cnt;
+  }
+  lvl_ptr[(size_t)u * lvl_stride + depth] = rb + r;
+  depth_out[u] = depth;
+  const int kk2 = k * k;
+  for (int s = 0; s < r; ++s) {
+    const int64_t ridx = rot0 + rb + s;
+    const int pos = rb + start[lvl[s]]++;
+    for (int a = 0; a < k; ++a) sw_loc[(size_t)pos * k + a] = rot_loc[ridx * 3 + a];
+    for (int a = 0; a < k; ++a)
+      for (int b = 0; b < k; ++b) sw_o[(size_t)pos * kk2 + a * k + b] = rot_o[ridx * 9 + a * 3 + b];
+    sw_idx[pos] = (int32_t)ridx;
+  }
+}
+
+hipError_t launch_levelize(int m, int k, const int32_t* off, const int32_t* rcnt,
+                           const int32_t* roff, int64_t rot0, const int32_t* rot_loc,
+                           const float* rot_o, int lvl_stride, int32_t* lvl_ptr, int32_t* depth,
+                           int32_t* sw_loc, float* sw_o, int32_t* sw_idx, int cmax,
+                           hipStream_t s) {
+  if (m == 0) return hipSuccess;
+  const size_t lds = (size_t)(3 * cmax + 2) * sizeof(int);
+  if (lds > 64 * 1024) {
+    hipError_t e = hipFuncSetAttribute((const void*)k_levelize,
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e != hipSuccess) return e;
+  }
+  k_levelize<<<m, 64, lds, s>>>(k, off, rcnt, roff, rot0, rot_loc, rot_o, lvl_stride, lvl_ptr,
+                                depth, sw_loc, sw_o, sw_idx, cmax);
+  return hipGetLastError();
+}
+
+// ------------------------------------------------------------------------------------------
+// Dense transpose of every cluster's c x c block (src -> dst, same pool layout), 32 x 32 tiles
+// through LDS so both sides are coalesced.  grid.x = tile index over all clusters.
+__global__ void k_transpose_blocks(int m, const int32_t* __restrict__ off,
+                                   const int64_t* __restrict__ gbase,
+                                   const int64_t* __restrict__ tbase,
+                                   const float* __restrict__ src, float* __restrict__ dst) {
+  __shared__ float tile[32][33];
+  // find the cluster owning this tile (tbase = prefix of tiles per cluster)
+  const int64_t t = blockIdx.x;
+  int lo = 0, hi = m - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (tbase[mid] <= t) lo = mid; else hi = mid - 1;
+  }
+  const int u = lo;
+  const int c = off[u + 1] - off[u];
+  const int nt = (c + 31) / 32;
+  const int64_t lt = t - tbase[u];
+  const int tr = (int)(lt / nt), tc = (int)(lt % nt);
+  const float* S = src + gbase[u];
+  float* Dd = dst + gbase[u];
+  const int x = threadIdx.x & 31, y0 = threadIdx.x >> 5;
+  for (int y = y0; y < 32; y += blockDim.x / 32) {
+    const int r = tr * 32 + y, cc = tc * 32 + x;
+    tile[y][x] = (r < c && cc < c) ? S[(size_t)r * c + cc] : 0.f;
+  }
+  __syncthreads();
+  for (int y = y0; y < 32; y += blockDim.x / 32) {
+    const int r = tc * 32 + y, cc = tr * 32 + x;
+    if (r < c && cc < c) Dd[(size_t)r * c + cc] = tile[x][y];
+  }
+}
+hipError_t launch_transpose_blocks(int m, const int32_t* off, const int64_t* gbase,
+                                   const int64_t* tbase, int64_t ntiles, const float* src,
+                                   float* dst, hipStream_t s) {
+  if (ntiles == 0) return hipSuccess;
+  k_transpose_blocks<<<(unsigned)ntiles, 256, 0, s>>>(m, off, gbase, tbase, src, dst);
+  return hipGetLastError();
+}
+
+// ------------------------------------------------------------------------------------------
+// Sparse rows of Qbar from the dense per-cluster accumulators (rows of Qbar^T from their
+// transposes); one wave per position, entries in ascending column order.
+__global__ void k_qbar(int S, int fill, const int32_t* __restrict__ off,
+                       const int32_t* __restrict__ cl_of, const int64_t* __restrict__ gbase,
+                       const float* __restrict__ Q, int32_t* __restrict__ cnt,
+                       const int64_t* __restrict__ rp, int32_t* __restrict__ ci,
+                       float* __restrict__ cv) {
+  const int wpb = blockDim.x / PMMF_WAVE;
+  const int a = blockIdx.x * wpb + pmmf_wave();
+  const int lane = pmmf_lane();
+  if (a >= S) return;
+  const int u = cl_of[a];
+  const int o = off[u];
+  const int c = off[u + 1] - o;
+  const int la = a - o;
+  const float* Qu = Q + gbase[u];
+  int64_t cur = fill ? rp[a] : 0;
+  int total = 0;
+  for (int j0 = 0; j0 < c; j0 += PMMF_WAVE) {
+    const int j = j0 + lane;
+    float v = 0.f;
+    if (j < c) v = Qu[(size_t)la * c + j];
+    const uint64_t b = __ballot(v != 0.f);
+    if (fill && v != 0.f) {
+      const int64_t pos = cur + pmmf_lanes_below(b);
+      ci[pos] = o + j;
+      cv[pos] = v;
+    }
+    cur += __popcll(b);
+    total += __popcll(b);
+  }
+  if (!fill && lane == 0) cnt[a] = total;
+}
+
+hipError_t launch_qbar_count(int S, const int32_t* off, const int32_t* cl_of,
+                             const int64_t* gbase, const float* Q, int32_t* cnt, hipStream_t s) {
+  if (S == 0) return hipSuccess;
+  k_qbar<<<(S + 3) / 4, 256, 0, s>>>(S, 0, off, cl_of, gbase, Q, cnt, nullptr, nullptr,
+                                     nullptr);
+  return hipGetLastError();
+}
+hipError_t launch_qbar_fill(int S, const int32_t* off, const int32_t* cl_of,
+                            const int64_t* gbase, const float* Q, const int64_t* rp, int32_t* ci,
+                            float* cv, hipStream_t s) {
+  if (S == 0) return hipSuccess;
+  k_qbar<<<(S + 3) / 4, 256, 0, s>>>(S, 1, off, cl_of, gbase, Q, nullptr, rp, ci, cv);
+  return hipGetLastError();
+}
+
+// ------------------------------------------------------------------------------------------
+// Right rotation W = M Qbar^T (the column half of [[A_p]]_{u,v} = Qbar_u [[A_{p-1}]]_{u,v}
+// Qbar_v^T in Alg. 1).  One wave per row x; the row's entries are grouped into runs of one
+// cluster v, and each run is expanded through Qbar_v^T in a dense LDS accumulator of c_v slots,
+// summing in ascending entry order (deterministic).  fill = 0 counts, fill = 1 writes.
+__global__ void __launch_bounds__(256) k_right(int S, int fill, const int64_t* __restrict__ rp,
+                                               const int32_t* __restrict__ ci,
+                                               const float* __restrict__ cv,
+                                               const int32_t* __restrict__ off,
+                                               const int32_t* __restrict__ cl_of,
+                                               const int64_t* __restrict__ qrp,
+                                               const int32_t* __restrict__ qci,
+                                               const float* __restrict__ qcv,
+                                               int32_t* __restrict__ cnt,
+                                               const int64_t* __restrict__ orp,
+                                               int32_t* __restrict__ oci,
+                                               float* __restrict__ ocv, int cmax) {
+  extern __shared__ float lds_f[];
+  const int wpb = blockDim.x / PMMF_WAVE;
+  const int w = pmmf_wave(), lane = pmmf_lane();
+  float* acc = lds_f + (size_t)w * cmax;
+  const int x = blockIdx.x * wpb + w;
+  if (x >= S) return;
+  for (int j = lane; j < cmax; j += PMMF_WAVE) acc[j] = 0.f;
+  const int64_t end = rp[x + 1];
+  int64_t k = rp[x];
+  int64_t cur = fill ? orp[x] : 0;
+  while (k < end) {
+    const int v = cl_of[ci[k]];
+    const int ov = off[v];
+    const int lim = off[v + 1];
+    int64_t kend = k;
+    while (true) {
+      const int64_t idx = kend + lane;
+      const bool in = idx < end && ci[idx] < lim;
+      const int n = __popcll(__ballot(in));
+      kend += n;
+      if (n < PMMF_WAVE) break;
+    }
+    int bmin = INT_MAX, bmax = -1;
+    for (int64_t t = k; t < kend; ++t) {
+      const int y = ci[t];
+      const float mv = cv[t];
+      const int64_t q0 = qrp[y], q1 = qrp[y + 1];
+      for (int64_t e = q0 + lane; e < q1; e += PMMF_WAVE) {
+        const int b = qci[e] - ov;
+        acc[b] += mv * qcv[e];
+        bmin = min(bmin, b);
+        bmax = max(bmax, b);
+      }
+    }
+    bmin = pmmf_wave_min_int(bmin);
+    bmax = pmmf_wave_max_int(bmax);
+    for (int base = bmin; base <= bmax; base += PMMF_WAVE) {
+      const int j = base + lane;
+      float val = 0.f;
+      if (j <= bmax) { val = acc[j]; acc[j] = 0.f; }
+      const uint64_t b = __ballot(val != 0.f);
+      if (fill && val != 0.f) {
+        const int64_t pos = cur + pmmf_lanes_below(b);
+        oci[pos] = ov + j;
+        ocv[pos] = val;
+      }
+      cur += __popcll(b);
+    }
+    k = kend;
+  }
+  if (!fill && lane == 0) cnt[x] = (int32_t)cur;
+}
+
+hipError_t launch_right(int S, int fill, const int64_t* rp, const int32_t* ci, const float* cv,
+                        const int32_t* off, const int32_t* cl_of, const int64_t* qrp,
+                        const int32_t* qci, const float* qcv, int32_t* cnt, const int64_t* orp,
+                        int32_t* oci, float* ocv, int cmax, hipStream_t s) {
+  if (S == 0) return hipSuccess;
+  int wpb = 4;
+  while (wpb > 1 && (size_t)wpb * cmax * 4 > 64 * 1024) wpb >>= 1;
+  const size_t lds = (size_t)wpb * cmax * sizeof(float);
+  k_right<<<(S + wpb - 1) / wpb, wpb * PMMF_WAVE, lds, s>>>(S, fill, rp, ci, cv, off, cl_of, qrp,
+                                                            qci, qcv, cnt, orp, oci, ocv, cmax);
+  return hipGetLastError();
+}
+
+// ------------------------------------------------------------------------------------------
+// Left rotation and peel: rows of A_p = Qbar W for every position a of the stage.  Row a merges
+// the rows W_x, x in supp(Qbar_a) (all inside a's cluster), cluster run by cluster run through a
+// dense LDS accumulator (lists in ascending x, deterministic).  A surviving row keeps only its
+// surviving columns, renumbered to the next stage's positions; a retired row contributes
+//     2 sum_{b survives} A_p[a,b]^2 + sum_{b retired, b != a} A_p[a,b]^2
+// to the exact residual (FP64), which totals 2 sum_e m_e over the stage's retirements.
+constexpr int LEFT_QMAX = 512;
+
+__global__ void __launch_bounds__(256) k_left(int S, int fill, const int64_t* __restrict__ qrp,
+                                              const int32_t* __restrict__ qci,
+                                              const float* __restrict__ qcv,
+                                              const int64_t* __restrict__ wrp,
+                                              const int32_t* __restrict__ wci,
+                                              const float* __restrict__ wcv,
+                                              const int32_t* __restrict__ off,
+                                              const int32_t* __restrict__ cl_of,
+                                              const int32_t* __restrict__ next,
+                                              int32_t* __restrict__ cnt,
+                                              const int64_t* __restrict__ orp,
+                                              int32_t* __restrict__ oci,
+                                              float* __restrict__ ocv,
+                                              double* __restrict__ loss_row,
+                                              int32_t* __restrict__ overflow, int cmax) {
+  extern __shared__ float lds_f[];
+  const int wpb = blockDim.x / PMMF_WAVE;
+  const int w = pmmf_wave(), lane = pmmf_lane();
+  // per wave: acc[cmax] floats, then cur[QMAX], en[QMAX] (int64), qv[QMAX] (float)
+  char* base = reinterpret_cast<char*>(lds_f) +
+               (size_t)w * ((size_t)cmax * 4 + (size_t)LEFT_QMAX * 20);
+  float* acc = reinterpret_cast<float*>(base);
+  int64_t* cur = reinterpret_cast<int64_t*>(base + (size_t)cmax * 4);
+  int64_t* en = cur + LEFT_QMAX;
+  float* qv = reinterpret_cast<float*>(en + LEFT_QMAX);
+  const int a = blockIdx.x * wpb + w;
+  if (a >= S) return;
+  const int64_t q0 = qrp[a];
+  const int nq = (int)(qrp[a + 1] - q0);
+  if (nq > LEFT_QMAX) {
+    if (lane == 0) {
+      atomicOr(overflow, 1);
+      if (!fill && next[a] >= 0) cnt[next[a]] = 0;
+      if (fill) loss_row[a] = 0.0;
+    }
+    return;
+  }
+  for (int j = lane; j < cmax; j += PMMF_WAVE) acc[j] = 0.f;
+  for (int li = lane; li < nq; li += PMMF_WAVE) {
+    const int x = qci[q0 + li];
+    cur[li] = wrp[x];
+    en[li] = wrp[x + 1];
+    qv[li] = qcv[q0 + li];
+  }
+  const int na = next[a];
+  const bool surv = na >= 0;
+  int64_t ocur = (fill && surv) ? orp[na] : 0;
+  double loss = 0.0;
+  while (true) {
+    int vmin = INT_MAX;
+    for (int li = lane; li < nq; li += PMMF_WAVE)
+      if (cur[li] < en[li]) vmin = min(vmin, cl_of[wci[cur[li]]]);
+    vmin = pmmf_wave_min_int(vmin);
+    if (vmin == INT_MAX) break;
+    const int ov = off[vmin];
+    const int lim = off[vmin + 1];
+    int bmin = INT_MAX, bmax = -1;
+    for (int li = 0; li < nq; ++li) {
+      int64_t cu = cur[li];
+      const int64_t e = en[li];
+      const float qq = qv[li];
+      while (cu < e) {
+        const int64_t idx = cu + lane;
+        const int col = idx < e ? wci[idx] : INT_MAX;
+        const bool in = col < lim;
+        const int n = __popcll(__ballot(in));
+        if (in) {
+          const int b = col - ov;
+          acc[b] += qq * wcv[idx];
+          bmin = min(bmin, b);
+          bmax = max(bmax, b);
+        }
+        cu += n;
+        if (n < PMMF_WAVE) break;
+      }
+      if (lane == 0) cur[li] = cu;
+    }
+    bmin = pmmf_wave_min_int(bmin);
+    bmax = pmmf_wave_max_int(bmax);
+    for (int bb = bmin; bb <= bmax; bb += PMMF_WAVE) {
+      const int j = bb + lane;
+      float val = 0.f;
+      if (j <= bmax) { val = acc[j]; acc[j] = 0.f; }
+      const int colpos = ov + j;
+      if (surv) {
+        const bool keep = val != 0.f && next[colpos] >= 0;
+        const uint64_t b = __ballot(keep);
+        if (fill && keep) {
+          const int64_t pos = ocur + pmmf_lanes_below(b);
+          oci[pos] = next[colpos];
+          ocv[pos] = val;
+        }
+        ocur += __popcll(b);
+      } else if (fill && val != 0.f && colpos != a) {
+        const double v2 = (double)val * (double)val;
+        loss += next[colpos] >= 0 ? 2.0 * v2 : v2;
+      }
+    }
+  }
+  if (fill && !surv) {
+    loss = pmmf_wave_sum_double(loss);
+    if (lane == 0) loss_row[a] = loss;
+  } else if (fill && lane == 0) {
+    loss_row[a] = 0.0;
+  }
+  if (!fill && lane == 0 && surv) cnt[na] = (int32_t)ocur;
+}
+
+hipError_t launch_left(int S, int fill, const int64_t* qrp, const int32_t* qci, const float* qcv,
+                       const int64_t* wrp, const int32_t* wci, const float* wcv,
+                       const int32_t* off, const int32_t* cl_of, const int32_t* next,
+                       int32_t* cnt, const int64_t* orp, int32_t* oci, float* ocv,
+                       double* loss_row, int32_t* overflow, int cmax, hipStream_t s) {
+  if (S == 0) return hipSuccess;
+  const size_t per_wave = (size_t)cmax * 4 + (size_t)LEFT_QMAX * 20;
+  int wpb = 4;
+  while (wpb > 1 && wpb * per_wave > 64 * 1024) wpb >>= 1;
+  const size_t lds = wpb * per_wave;
+  if (lds > 64 * 1024) {
+    hipError_t e = hipFuncSetAttribute((const void*)k_left,
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e != hipSuccess) return e;
+  }
+  k_left<<<(S + wpb - 1) / wpb, wpb * PMMF_WAVE, lds, s>>>(S, fill, qrp, qci, qcv, wrp, wci, wcv,
+                                                           off, cl_of, next, cnt, orp, oci, ocv,
+                                                           loss_row, overflow, cmax);
+  return hipGetLastError();
+}
+
+// ------------------------------------------------------------------------------------------
+// positions of the survivors in the next stage, and the global ids there
+__global__ void k_keep_flags(int S, const uint8_t* __restrict__ retflag, int32_t* __restrict__ keep) {
+  int q = blockIdx.x * blockDim.x + threadIdx.x;
+  if (q < S) keep[q] = retflag[q] ? 0 : 1;
+}
+hipError_t launch_keep_flags(int S, const uint8_t* retflag, int32_t* keep, hipStream_t s) {
+  if (S == 0) return hipSuccess;
+  k_keep_flags<<<(S + 255) / 256, 256, 0, s>>>(S, retflag, keep);
+  return hipGetLastError();
+}
+
+__global__ void k_next_positions(int S, const uint8_t* __restrict__ retflag,
+                                 const int64_t* __restrict__ scan, const int32_t* __restrict__ gid,
+                                 int32_t* __restrict__ next, int32_t* __restrict__ gid_new) {
+  int q = blockIdx.x * blockDim.x + threadIdx.x;
+  if (q >= S) return;
+  if (retflag[q]) {
+    next[q] = -gid[q] - 1;
+  } else {
+    const int np = (int)scan[q];
+    next[q] = np;
+    gid_new[np] = gid[q];
+  }
+}
+hipError_t launch_next_positions(int S, const uint8_t* retflag, const int64_t* scan,
+                                 const int32_t* gid, int32_t* next, int32_t* gid_new,
+                                 hipStream_t s) {
+  if (S == 0) return hipSuccess;
+  k_next_positions<<<(S + 255) / 256, 256, 0, s>>>(S, retflag, scan, gid, next, gid_new);
+  return hipGetLastError();
+}
+
+// ------------------------------------------------------------------------------------------
+// exclusive scan of int32 counts into int64 offsets out[0..n] (out[n] = total)
+constexpr int SCAN_T = 256;
+constexpr int SCAN_I = 8;
+constexpr int SCAN_B = SCAN_T * SCAN_I;
+
+__global__ void k_scan_block(const int32_t* __restrict__ in32, const int64_t* __restrict__ in64,
+                             int64_t n, int64_t* __restrict__ out, int64_t* __restrict__ bsum) {
+  __shared__ int64_t wsum[SCAN_T / PMMF_WAVE];
+  const int64_t b0 = (int64_t)blockIdx.x * SCAN_B;
+  int64_t v[SCAN_I];
+  int64_t tot = 0;
+  for (int q = 0; q < SCAN_I; ++q) {
+    const int64_t idx = b0 + (int64_t)threadIdx.x * SCAN_I + q;
+    int64_t x = 0;
+    if (idx < n) x = in32 ? (int64_t)in32[idx] : in64[idx];
+    v[q] = tot;
+    tot += x;
+  }
+  // exclusive scan of thread totals across the block
+  int64_t incl = tot;
+  const int lane = pmmf_lane();
+  for (int o = 1; o < PMMF_WAVE; o <<= 1) {
+    int64_t t = __shfl_up(incl, o);
+    if (lane >= o) incl += t;
+  }
+  if (lane == PMMF_WAVE - 1) wsum[pmmf_wave()] = incl;
+  __syncthreads();
+  int64_t wpre = 0;
+  for (int q = 0; q < pmmf_wave(); ++q) wpre += wsum[q];
+  const int64_t texcl = wpre + incl - tot;
+  for (int q = 0; q < SCAN_I; ++q) {
+    const int64_t idx = b0 + (int64_t)threadIdx.x * SCAN_I + q;
+    if (idx < n) out[idx] = texcl + v[q];
+  }
+  if (threadIdx.x == SCAN_T - 1) bsum[blockIdx.x] = texcl + tot;
+}
+
+__global__ void k_scan_add(int64_t n, int64_t* __restrict__ out, const int64_t* __restrict__ boff) {
+  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx < n) out[idx] += boff[idx / SCAN_B];
+}
+
+int64_t scan_tmp_elems(int64_t n) {
+  int64_t tot = 0;
+  int64_t m = n;
+  while (true) {
+    const int64_t nb = (m + SCAN_B - 1) / SCAN_B;
+    tot += 2 * (nb + 1);
+    if (nb <= 1) break;
+    m = nb;
+  }
+  return tot + 8;
+}
+
+static hipError_t scan_rec(const int32_t* in32, const int64_t* in64, int64_t n, int64_t* out,
+                           int64_t* tmp, hipStream_t s) {
+  const int64_t nb = (n + SCAN_B - 1) / SCAN_B;
+  int64_t* bsum = tmp;
+  int64_t* boff = tmp + nb + 1;
+  k_scan_block<<<(unsigned)nb, SCAN_T, 0, s>>>(in32, in64, n, out, bsum);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  if (nb > 1) {
+    e = scan_rec(nullptr, bsum, nb, boff, tmp + 2 * (nb + 1), s);
+    if (e != hipSuccess) return e;
+    k_scan_add<<<(unsigned)((n + 255) / 256), 256, 0, s>>>(n, out, boff);
+    e = hipGetLastError();
+  }
+  return e;
+}
+
+// total is written to out[n]
+__global__ void k_scan_total(const int32_t* __restrict__ in, int64_t n, int64_t* __restrict__ out) {
+  out[n] = (n > 0 ? out[n - 1] + in[n - 1] : 0);
+}
+
+hipError_t launch_scan(const int32_t* in, int64_t* out, int64_t n, int64_t* tmp, hipStream_t s) {
+  if (n > 0) {
+    hipError_t e = scan_rec(in, nullptr, n, out, tmp, s);
+    if (e != hipSuccess) return e;
+  }
+  k_scan_total<<<1, 1, 0, s>>>(in, n, out);
+  return hipGetLastError();
+}
+
+// deterministic FP64 sum (one block, fixed order)
+__global__ void k_sum_double(const double* __restrict__ in, int64_t n, double* __restrict__ out) {
+  __shared__ double part[1024 / PMMF_WAVE];
+  double v = 0.0;
+  for (int64_t i = threadIdx.x; i < n; i += blockDim.x) v += in[i];
+  v = pmmf_wave_sum_double(v);
+  if (pmmf_lane() == 0) part[pmmf_wave()] = v;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double t = 0.0;
+    for (int q = 0; q < (int)(blockDim.x / PMMF_WAVE); ++q) t += part[q];
+    *out = t;
+  }
+}
+hipError_t launch_sum_double(const double* in, int64_t n, double* out, hipStream_t s) {
+  k_sum_double<<<1, 1024, 0, s>>>(in, n, out);
+  return hipGetLastError();
+}
+
+// ------------------------------------------------------------------------------------------
+// input checks and statistics: per row FP64 partial sums of squares (fro2_trace[2*row]) and the
+// diagonal (fro2_trace[2*row+1]); flags bit 0 = non-finite, bit 1 = not symmetric
+__global__ void k_csr_stats(int64_t n, const int64_t* __restrict__ rp, const int32_t* __restrict__ ci,
+                            const float* __restrict__ cv, int check_sym,
+                            double* __restrict__ part, int32_t* __restrict__ flags) {
+  const int64_t a = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (a >= n) return;
+  double f2 = 0.0, tr = 0.0;
+  int fl = 0;
+  for (int64_t t = rp[a]; t < rp[a + 1]; ++t) {
+    const float v = cv[t];
+    const int b = ci[t];
+    if (!isfinite(v)) fl |= 1;
+    if (b < 0 || b >= n) fl |= 4;
+    if (t > rp[a] && b <= ci[t - 1]) fl |= 8;
+    f2 += (double)v * v;
+    if (b == a) tr += v;
+    if (check_sym && b >= 0 && b < n) {
+      const int64_t q = lower_bound_i32(ci, rp[b], rp[b + 1], (int32_t)a);
+      if (q >= rp[b + 1] || ci[q] != a || __float_as_uint(cv[q]) != __float_as_uint(v)) fl |= 2;
+    }
+  }
+  part[a] = f2;
+  part[n + a] = tr;
+  if (fl) atomicOr(flags, fl);
+}
+hipError_t launch_csr_stats(int64_t n, const int64_t* rp, const int32_t* ci, const float* cv,
+                            int check_sym, double* part, int32_t* flags, hipStream_t s) {
+  if (n == 0) return hipSuccess;
+  k_csr_stats<<<(unsigned)((n + 255) / 256), 256, 0, s>>>(n, rp, ci, cv, check_sym, part, flags);
+  return hipGetLastError();
+}
+
+__global__ void k_core_dense(int S, const int64_t* __restrict__ rp, const int32_t* __restrict__ ci,
+                             const float* __restrict__ cv, float* __restrict__ hcore) {
+  const int a = blockIdx.x;
+  for (int64_t t = rp[a] + threadIdx.x; t < rp[a + 1]; t += blockDim.x)
+    hcore[(size_t)a * S + ci[t]] = cv[t];
+}
+hipError_t launch_core_dense(int S, const int64_t* rp, const int32_t* ci, const float* cv,
+                             float* hcore, hipStream_t s) {
+  if (S == 0) return hipSuccess;
+  k_core_dense<<<S, 64, 0, s>>>(S, rp, ci, cv, hcore);
+  return hipGetLastError();
+}
+
+// out[0] = ||H||_F^2, out[1] = trace(H), FP64 accumulation in a fixed order
+__global__ void k_h_stats(int64_t n, const float* __restrict__ hdiag, int64_t core,
+                          const float* __restrict__ hcore, double* __restrict__ out) {
+  __shared__ double p1[1024 / PMMF_WAVE], p2[1024 / PMMF_WAVE];
+  double f = 0.0, t = 0.0;
+  for (int64_t i = threadIdx.x; i < n; i += blockDim.x) {
+    const double v = hdiag[i];
+    f += v * v;
+    t += v;
+  }
+  for (int64_t i = threadIdx.x; i < core * core; i += blockDim.x) {
+    const double v = hcore[i];
+    f += v * v;
+    if (i / core == i % core) t += v;
+  }
+  f = pmmf_wave_sum_double(f);
+  t = pmmf_wave_sum_double(t);
+  if (pmmf_lane() == 0) { p1[pmmf_wave()] = f; p2[pmmf_wave()] = t; }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double a = 0.0, b = 0.0;
+    for (int q = 0; q < (int)(blockDim.x / PMMF_WAVE); ++q) { a += p1[q]; b += p2[q]; }
+    out[0] = a;
+    out[1] = b;
+  }
+}
+hipError_t launch_h_stats(int64_t n, const float* hdiag, int64_t core, const float* hcore,
+                          double* out, hipStream_t s) {
+  k_h_stats<<<1, 1024, 0, s>>>(n, hdiag, core, hcore, out);
+  return hipGetLastError();
+}
+
+__global__ void k_copy_csr(int64_t n, const int64_t* __restrict__ rp, const int32_t* __restrict__ ci,
+                           const float* __restrict__ cv, int64_t* __restrict__ orp,
+                           int32_t* __restrict__ oci, float* __restrict__ ocv) {
+  const int64_t a = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (a > n) return;
+  orp[a] = rp[a];
+  if (a == n) return;
+  for (int64_t t = rp[a]; t < rp[a + 1]; ++t) {
+    oci[t] = ci[t];
+    ocv[t] = cv[t];
+  }
+}
+hipError_t launch_copy_csr(int64_t n, const int64_t* rp, const int32_t* ci, const float* cv,
+                           int64_t* orp, int32_t* oci, float* ocv, hipStream_t s) {
+  k_copy_csr<<<(unsigned)((n + 256) / 256), 256, 0, s>>>(n, rp, ci, cv, orp, oci, ocv);
+  return hipGetLastError();
+}
+
+__global__ void k_iota(int32_t* a, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) a[i] = (int32_t)i;
+}
+hipError_t launch_iota(int32_t* a, int64_t n, hipStream_t s) {
+  if (n == 0) return hipSuccess;
+  k_iota<<<(unsigned)((n + 255) / 256), 256, 0, s>>>(a, n);
+  return hipGetLastError();
+}
+
+}  // namespace pmmf

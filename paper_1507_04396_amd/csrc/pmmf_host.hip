@@ -1,0 +1,1098 @@
+// Host side of the pMMF library: the C ABI declared in include/pmmf.h.
+#include "pmmf.h"
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <memory>
+#include <mutex>
+#include <set>
+#include <string>
+#include <vector>
+
+#include "factor_kernels.h"
+#include "sweep_kernels.h"
+
+namespace {
+
+thread_local std::string g_err;
+
+struct Err {
+  int code;
+  std::string msg;
+};
+
+[[noreturn]] void raise(int code, const std::string& msg) { throw Err{code, msg}; }
+
+void hipchk(hipError_t e, const char* what) {
+  if (e != hipSuccess) {
+    if (e == hipErrorOutOfMemory) raise(MMF_ENOMEM, std::string(what) + ": out of device memory");
+    raise(MMF_EDEVICE, std::string(what) + ": " + hipGetErrorString(e));
+  }
+}
+#define HIPCHK(x) hipchk((x), #x)
+
+// Owned device buffer.
+struct DBuf {
+  void* p = nullptr;
+  size_t bytes = 0;
+  DBuf() = default;
+  DBuf(const DBuf&) = delete;
+  DBuf& operator=(const DBuf&) = delete;
+  ~DBuf() { release(); }
+  void release() {
+    if (p) (void)hipFree(p);
+    p = nullptr;
+    bytes = 0;
+  }
+  void ensure(size_t b) {
+    if (b <= bytes && p) return;
+    release();
+    if (b == 0) b = 16;
+    HIPCHK(hipMalloc(&p, b));
+    bytes = b;
+  }
+  template <class T> T* as() const { return reinterpret_cast<T*>(p); }
+  void swap_with(DBuf& o) {
+    std::swap(p, o.p);
+    std::swap(bytes, o.bytes);
+  }
+};
+
+// Host -> device copy on the stream; waits for it, since the host vector may be a temporary.
+template <class T>
+void upload(DBuf& d, const std::vector<T>& h, hipStream_t s) {
+  d.ensure(h.size() * sizeof(T));
+  if (h.empty()) return;
+  HIPCHK(hipMemcpyAsync(d.p, h.data(), h.size() * sizeof(T), hipMemcpyHostToDevice, s));
+  HIPCHK(hipStreamSynchronize(s));
+}
+
+int64_t read_i64(const int64_t* dptr, hipStream_t s) {
+  int64_t v = 0;
+  HIPCHK(hipMemcpyAsync(&v, dptr, sizeof(v), hipMemcpyDeviceToHost, s));
+  HIPCHK(hipStreamSynchronize(s));
+  return v;
+}
+
+constexpr int CMAX_LIMIT = 4096;   // largest cluster (dense c x c Gram, diagonal block, Q)
+
+}  // namespace
+
+struct StageDev {
+  int64_t size = 0, t = 0, rot_base = 0, nnz = 0;
+  int m = 0, cmax = 0, rmax = 0, lvl_stride = 0, depth_max = 0;
+  std::vector<int32_t> off_h, rcnt_h, roff_h;
+  std::vector<int64_t> gbase_h;
+  DBuf off, rcnt, roff, order, gbase, next, gid, cl_of, lvl_ptr, depth, sw_loc, sw_o, sw_idx;
+  double loss = 0.0;
+};
+
+struct mmf_plan {
+  int64_t n = 0, core = 0, R = 0;
+  int k = 2;
+  mmf_params prm{};
+  std::vector<std::unique_ptr<StageDev>> st;
+  DBuf rot_loc, rot_gid, rot_o, rot_ret, rot_margin, theta, rot_lit;
+  DBuf hdiag, hcore, core_ids, is_core;
+  DBuf hinv, chol_L, chol_X, status;
+  bool inv_ready = false;
+  DBuf ws[16];
+  mmf_info info{};
+  hipStream_t stream = nullptr;
+};
+
+namespace {
+
+hipStream_t as_stream(void* s) { return reinterpret_cast<hipStream_t>(s); }
+
+// ------------------------------------------------------------------------------------------
+// schedule (Alg. 1 stages, Alg. 2 rotation counts, seeded cluster sizes)
+struct SchedStage {
+  int64_t size, t;
+  std::vector<int32_t> sizes, rcnt;
+};
+
+std::vector<SchedStage> make_schedule(const mmf_params& p, int64_t n) {
+  std::vector<SchedStage> out;
+  int64_t s = n;
+  int stage = 0;
+  while (s > p.core_size) {
+    ++stage;
+    const int64_t t = std::min<int64_t>(s - p.core_size, (int64_t)std::floor(p.eta * (double)s));
+    if (t < 1) raise(MMF_EINVAL, "eta * |S| < 1: the schedule cannot reach the core");
+    SchedStage st;
+    st.size = s;
+    st.t = t;
+    if (p.cluster_min == 0 && p.cluster_max == 0) {
+      st.sizes.push_back((int32_t)s);
+    } else {
+      int64_t r = s;
+      uint64_t q = 0;
+      const int64_t lo = p.cluster_min, hi = p.cluster_max;
+      while (r > hi) {
+        int64_t c = lo + (int64_t)pmmf_mulhi(pmmf_hash4(p.seed, PMMF_TAG_CLUSTER_SIZE,
+                                                        (uint64_t)stage, q, 0),
+                                             (uint64_t)(hi - lo + 1));
+        c = std::min(c, r - lo);
+        if (p.flags & MMF_EVEN_CLUSTERS) c -= c % 2;
+        st.sizes.push_back((int32_t)c);
+        r -= c;
+        ++q;
+      }
+      st.sizes.push_back((int32_t)r);
+    }
+    // rotations per cluster: floor share plus leftovers by largest remainder (lower u on ties)
+    const size_t m = st.sizes.size();
+    std::vector<int64_t> base(m), rem(m);
+    int64_t sum = 0;
+    for (size_t u = 0; u < m; ++u) {
+      base[u] = (t * st.sizes[u]) / s;
+      rem[u] = (t * st.sizes[u]) % s;
+      sum += base[u];
+    }
+    std::vector<size_t> ord(m);
+    for (size_t u = 0; u < m; ++u) ord[u] = u;
+    std::stable_sort(ord.begin(), ord.end(), [&](size_t a, size_t b) { return rem[a] > rem[b]; });
+    for (int64_t q = 0; q < t - sum; ++q) base[ord[q]] += 1;
+    for (size_t u = 0; u < m; ++u) {
+      if (st.sizes[u] > CMAX_LIMIT)
+        raise(MMF_EINVAL, "cluster of " + std::to_string(st.sizes[u]) + " exceeds the limit " +
+                              std::to_string(CMAX_LIMIT) + " (set cluster bounds)");
+      if (base[u] > st.sizes[u] - (p.k - 1))
+        raise(MMF_EINVAL, "a cluster has fewer than k live indices at its last step");
+      st.rcnt.push_back((int32_t)base[u]);
+    }
+    out.push_back(std::move(st));
+    s -= t;
+  }
+  return out;
+}
+
+void validate(int64_t n, const mmf_params* p) {
+  if (!p) raise(MMF_EINVAL, "params is NULL");
+  if (n < 1 || n > (int64_t)INT32_MAX - 1) raise(MMF_EINVAL, "n out of range");
+  if (p->k != 2 && p->k != 3) raise(MMF_EINVAL, "k must be 2 or 3");
+  if (!(p->eta > 0.0 && p->eta <= 0.5)) raise(MMF_EINVAL, "eta must be in (0, 0.5]");
+  if (p->core_size < 1 || p->core_size > n) raise(MMF_EINVAL, "core_size must be in [1, n]");
+  const bool single = p->cluster_min == 0 && p->cluster_max == 0;
+  if (!single && (p->cluster_min < 2 || p->cluster_max < 2 * p->cluster_min))
+    raise(MMF_EINVAL, "cluster bounds need cluster_min >= 2 and cluster_max >= 2 cluster_min");
+  if (p->gram_mode != 0) raise(MMF_EINVAL, "gram_mode must be 0 (FP32 Gram)");
+}
+
+// sparse matrix in CSR
+struct Csr {
+  int64_t n = 0, nnz = 0;
+  DBuf rp, ci, cv;
+};
+
+void build_stage_geometry(StageDev& sd, const SchedStage& sc, int64_t rot_base, hipStream_t s) {
+  sd.size = sc.size;
+  sd.t = sc.t;
+  sd.m = (int)sc.sizes.size();
+  sd.rot_base = rot_base;
+  sd.off_h.assign(sd.m + 1, 0);
+  sd.roff_h.assign(sd.m + 1, 0);
+  sd.rcnt_h = sc.rcnt;
+  sd.gbase_h.assign(sd.m, 0);
+  int64_t gb = 0;
+  sd.cmax = 0;
+  sd.rmax = 0;
+  for (int u = 0; u < sd.m; ++u) {
+    sd.off_h[u + 1] = sd.off_h[u] + sc.sizes[u];
+    sd.roff_h[u + 1] = sd.roff_h[u] + sc.rcnt[u];
+    sd.gbase_h[u] = gb;
+    gb += (int64_t)sc.sizes[u] * sc.sizes[u];
+    sd.cmax = std::max(sd.cmax, sc.sizes[u]);
+    sd.rmax = std::max(sd.rmax, sc.rcnt[u]);
+  }
+  sd.lvl_stride = sd.rmax + 1;
+  std::vector<int32_t> order(sd.m);
+  for (int u = 0; u < sd.m; ++u) order[u] = u;
+  std::stable_sort(order.begin(), order.end(),
+                   [&](int a, int b) { return sc.sizes[a] > sc.sizes[b]; });
+  upload(sd.off, sd.off_h, s);
+  upload(sd.rcnt, sd.rcnt_h, s);
+  upload(sd.roff, sd.roff_h, s);
+  upload(sd.order, order, s);
+  upload(sd.gbase, sd.gbase_h, s);
+  sd.next.ensure(sd.size * sizeof(int32_t));
+  sd.gid.ensure(sd.size * sizeof(int32_t));
+  sd.cl_of.ensure(sd.size * sizeof(int32_t));
+  sd.lvl_ptr.ensure((size_t)sd.m * sd.lvl_stride * sizeof(int32_t));
+  sd.depth.ensure(sd.m * sizeof(int32_t));
+  sd.sw_idx.ensure(sd.t * sizeof(int32_t));
+  HIPCHK(pmmf::launch_fill_cluster_of(sd.off.as<int32_t>(), sd.m, (int)sd.size,
+                                      sd.cl_of.as<int32_t>(), s));
+}
+
+int round_cmax(int c) { return (c + 63) / 64 * 64; }
+
+pmmf::SweepStage sweep_view(const mmf_plan& h, const StageDev& sd) {
+  pmmf::SweepStage v;
+  v.m = sd.m;
+  v.k = h.k;
+  v.cmax = round_cmax(sd.cmax);
+  v.rmax = sd.rmax;
+  v.lvl_stride = sd.lvl_stride;
+  v.off = sd.off.as<int32_t>();
+  v.lvl_ptr = sd.lvl_ptr.as<int32_t>();
+  v.depth = sd.depth.as<int32_t>();
+  v.sw_loc = sd.sw_loc.as<int32_t>();
+  v.sw_o = sd.sw_o.as<float>();
+  v.next = sd.next.as<int32_t>();
+  v.gid = sd.gid.as<int32_t>();
+  return v;
+}
+
+// widest column tile whose LDS footprint allows two workgroups per CU (fallback: one)
+int pick_tile(const mmf_plan& h, int nv, int64_t nrhs) {
+  int cmax = 0, rmax = 0;
+  for (auto& sp : h.st) {
+    cmax = std::max(cmax, round_cmax(sp->cmax));
+    rmax = std::max(rmax, sp->rmax);
+  }
+  int wmax = 1;
+  while (wmax < nrhs && wmax < 32) wmax <<= 1;
+  for (size_t budget : {80u * 1024u, 160u * 1024u}) {
+    for (int W = wmax; W >= 1; W >>= 1)
+      if (pmmf::sweep_lds_bytes(h.k, W, nv, cmax, rmax) <= budget) return W;
+  }
+  raise(MMF_ECAPACITY, "clusters too large for the sweep's LDS tile");
+}
+
+}  // namespace
+
+// ------------------------------------------------------------------------------------------
+extern "C" const char* mmf_last_error(void) { return g_err.c_str(); }
+
+#define ABI_BEGIN try {
+#define ABI_END                                      \
+  }                                                  \
+  catch (const Err& e) {                             \
+    g_err = e.msg;                                   \
+    return e.code;                                   \
+  }                                                  \
+  catch (const std::exception& e) {                  \
+    g_err = e.what();                                \
+    return MMF_EDEVICE;                              \
+  }
+
+static std::mutex g_live_mu;
+static std::set<mmf_plan*> g_live;
+
+static void register_handle(mmf_plan* h) {
+  std::lock_guard<std::mutex> lk(g_live_mu);
+  g_live.insert(h);
+}
+
+static mmf_plan* checked(mmf_handle h) {
+  std::lock_guard<std::mutex> lk(g_live_mu);
+  if (!h || !g_live.count(h)) raise(MMF_ESTATE, "invalid or destroyed handle");
+  return h;
+}
+
+extern "C" int mmf_factor(int64_t n, int64_t nnz, const int64_t* d_rowptr, const int32_t* d_colind,
+                          const float* d_val, const mmf_params* p, void* stream, mmf_handle* out) {
+  ABI_BEGIN
+  g_err.clear();
+  if (!out) raise(MMF_EINVAL, "out is NULL");
+  *out = nullptr;
+  validate(n, p);
+  if (nnz < 0 || (nnz > 0 && (!d_rowptr || !d_colind || !d_val)) || !d_rowptr)
+    raise(MMF_EINVAL, "bad CSR arguments");
+  hipStream_t s = as_stream(stream);
+  auto h = std::make_unique<mmf_plan>();
+  h->n = n;
+  h->core = p->core_size;
+  h->k = p->k;
+  h->prm = *p;
+  h->stream = s;
+  h->R = n - p->core_size;
+  std::vector<SchedStage> sched = make_schedule(*p, n);
+
+  hipEvent_t ev0, ev1;
+  HIPCHK(hipEventCreate(&ev0));
+  HIPCHK(hipEventCreate(&ev1));
+  HIPCHK(hipEventRecord(ev0, s));
+
+  // input checks and ||A||_F^2, trace(A)
+  DBuf part, flags, dsum, scan_tmp;
+  part.ensure(2 * n * sizeof(double));
+  flags.ensure(sizeof(int32_t));
+  dsum.ensure(8 * sizeof(double));
+  HIPCHK(hipMemsetAsync(flags.p, 0, sizeof(int32_t), s));
+  HIPCHK(pmmf::launch_csr_stats(n, d_rowptr, d_colind, d_val,
+                                (p->flags & MMF_CHECK_SYMMETRY) ? 1 : 0, part.as<double>(),
+                                flags.as<int32_t>(), s));
+  HIPCHK(pmmf::launch_sum_double(part.as<double>(), n, dsum.as<double>() + 0, s));
+  HIPCHK(pmmf::launch_sum_double(part.as<double>() + n, n, dsum.as<double>() + 1, s));
+  int32_t fl = 0;
+  double stats_a[2] = {0, 0};
+  HIPCHK(hipMemcpyAsync(&fl, flags.p, sizeof(fl), hipMemcpyDeviceToHost, s));
+  HIPCHK(hipMemcpyAsync(stats_a, dsum.p, 2 * sizeof(double), hipMemcpyDeviceToHost, s));
+  HIPCHK(hipStreamSynchronize(s));
+  if (fl & 4) raise(MMF_EINVAL, "column index out of range");
+  if (fl & 8) raise(MMF_EINVAL, "column indices must be strictly ascending within each row");
+  if (fl & 1) raise(MMF_ENONFINITE, "matrix has NaN or Inf entries");
+  if (fl & 2) raise(MMF_ENOTSYM, "matrix is not exactly symmetric");
+
+  const int64_t R = h->R;
+  h->rot_loc.ensure(std::max<int64_t>(R, 1) * 3 * sizeof(int32_t));
+  h->rot_gid.ensure(std::max<int64_t>(R, 1) * 3 * sizeof(int32_t));
+  h->rot_o.ensure(std::max<int64_t>(R, 1) * 9 * sizeof(float));
+  h->rot_ret.ensure(std::max<int64_t>(R, 1) * sizeof(int32_t));
+  h->rot_margin.ensure(std::max<int64_t>(R, 1) * sizeof(float));
+  h->theta.ensure(std::max<int64_t>(R, 1) * sizeof(float));
+  h->rot_lit.ensure(std::max<int64_t>(R, 1) * sizeof(double));
+  h->hdiag.ensure(n * sizeof(float));
+  HIPCHK(hipMemsetAsync(h->hdiag.p, 0, n * sizeof(float), s));
+  HIPCHK(hipMemsetAsync(h->theta.p, 0, std::max<int64_t>(R, 1) * sizeof(float), s));
+
+  // working copy of the active matrix
+  Csr M, W, M2, Qr, Qt;
+  M.n = n;
+  M.nnz = nnz;
+  M.rp.ensure((n + 1) * sizeof(int64_t));
+  M.ci.ensure(std::max<int64_t>(nnz, 1) * sizeof(int32_t));
+  M.cv.ensure(std::max<int64_t>(nnz, 1) * sizeof(float));
+  HIPCHK(pmmf::launch_copy_csr(n, d_rowptr, d_colind, d_val, M.rp.as<int64_t>(),
+                               M.ci.as<int32_t>(), M.cv.as<float>(), s));
+
+  int64_t pool = 1;
+  for (auto& sc : sched) {
+    int64_t g = 0;
+    for (int32_t c : sc.sizes) g += (int64_t)c * c;
+    pool = std::max(pool, g);
+  }
+  DBuf G, D, Q, retflag, keep, scan, cnt, loss_row, overflow, gid_cur, tbase;
+  G.ensure(pool * sizeof(float));
+  D.ensure(pool * sizeof(float));
+  Q.ensure(pool * sizeof(float));
+  retflag.ensure(n);
+  keep.ensure((n + 1) * sizeof(int32_t));
+  scan.ensure((n + 2) * sizeof(int64_t));
+  cnt.ensure((n + 1) * sizeof(int32_t));
+  loss_row.ensure(n * sizeof(double));
+  overflow.ensure(2 * sizeof(int32_t));
+  scan_tmp.ensure(pmmf::scan_tmp_elems(n + 1) * sizeof(int64_t));
+  HIPCHK(hipMemsetAsync(overflow.p, 0, 2 * sizeof(int32_t), s));
+
+  int64_t rot_base = 0;
+  h->info.fro2_a = stats_a[0];
+  h->info.trace_a = stats_a[1];
+  std::vector<double> stage_loss_dev;
+  DBuf stage_loss;
+  stage_loss.ensure(std::max<size_t>(sched.size(), 1) * sizeof(double));
+
+  for (size_t pi = 0; pi < sched.size(); ++pi) {
+    const SchedStage& sc = sched[pi];
+    auto sdp = std::make_unique<StageDev>();
+    StageDev& sd = *sdp;
+    build_stage_geometry(sd, sc, rot_base, s);
+    sd.nnz = M.nnz;
+    const int S = (int)sd.size;
+    const int cm = round_cmax(sd.cmax);
+    if (pi == 0) HIPCHK(pmmf::launch_iota(sd.gid.as<int32_t>(), S, s));
+    else HIPCHK(hipMemcpyAsync(sd.gid.p, gid_cur.p, S * sizeof(int32_t), hipMemcpyDeviceToDevice, s));
+    HIPCHK(hipMemsetAsync(retflag.p, 0, S, s));
+
+    // cluster Grams, diagonal blocks, identity accumulators
+    HIPCHK(pmmf::launch_gram(S, M.rp.as<int64_t>(), M.ci.as<int32_t>(), M.cv.as<float>(),
+                             sd.off.as<int32_t>(), sd.cl_of.as<int32_t>(), sd.gbase.as<int64_t>(),
+                             G.as<float>(), D.as<float>(), Q.as<float>(), cm, s));
+    // greedy rotation search in every cluster
+    pmmf::FindArgs fa;
+    fa.p = (int)pi + 1;
+    fa.k = h->k;
+    fa.seed = p->seed;
+    fa.order = sd.order.as<int32_t>();
+    fa.off = sd.off.as<int32_t>();
+    fa.rcnt = sd.rcnt.as<int32_t>();
+    fa.roff = sd.roff.as<int32_t>();
+    fa.gbase = sd.gbase.as<int64_t>();
+    fa.G = G.as<float>();
+    fa.D = D.as<float>();
+    fa.Q = Q.as<float>();
+    fa.gid = sd.gid.as<int32_t>();
+    fa.rot0 = rot_base;
+    fa.rot_loc = h->rot_loc.as<int32_t>();
+    fa.rot_gid = h->rot_gid.as<int32_t>();
+    fa.rot_o = h->rot_o.as<float>();
+    fa.rot_ret = h->rot_ret.as<int32_t>();
+    fa.rot_margin = h->rot_margin.as<float>();
+    fa.theta = h->theta.as<float>();
+    fa.rot_lit = h->rot_lit.as<double>();
+    fa.hdiag = h->hdiag.as<float>();
+    fa.retflag = retflag.as<uint8_t>();
+    fa.err = overflow.as<int32_t>() + 1;
+    HIPCHK(pmmf::launch_find(fa, sd.m, cm, s));
+    // rotation levels and the sweep log
+    sd.sw_loc.ensure(sd.t * h->k * sizeof(int32_t));
+    sd.sw_o.ensure(sd.t * h->k * h->k * sizeof(float));
+    HIPCHK(pmmf::launch_levelize(sd.m, h->k, sd.off.as<int32_t>(), sd.rcnt.as<int32_t>(),
+                                 sd.roff.as<int32_t>(), rot_base, h->rot_loc.as<int32_t>(),
+                                 h->rot_o.as<float>(), sd.lvl_stride, sd.lvl_ptr.as<int32_t>(),
+                                 sd.depth.as<int32_t>(), sd.sw_loc.as<int32_t>(),
+                                 sd.sw_o.as<float>(), sd.sw_idx.as<int32_t>(), cm, s));
+    // survivors' positions in the next stage
+    HIPCHK(pmmf::launch_keep_flags(S, retflag.as<uint8_t>(), keep.as<int32_t>(), s));
+    HIPCHK(pmmf::launch_scan(keep.as<int32_t>(), scan.as<int64_t>(), S, scan_tmp.as<int64_t>(), s));
+    gid_cur.ensure(S * sizeof(int32_t));
+    DBuf gid_new;
+    gid_new.ensure(S * sizeof(int32_t));
+    HIPCHK(pmmf::launch_next_positions(S, retflag.as<uint8_t>(), scan.as<int64_t>(),
+                                       sd.gid.as<int32_t>(), sd.next.as<int32_t>(),
+                                       gid_new.as<int32_t>(), s));
+    const int64_t Snext = sd.size - sd.t;
+
+    // sparse Qbar and Qbar^T (the Gram pool is free now and receives the transposes)
+    {
+      std::vector<int64_t> tb(sd.m + 1, 0);
+      for (int u = 0; u < sd.m; ++u) {
+        const int64_t c = sd.off_h[u + 1] - sd.off_h[u];
+        const int64_t nt = (c + 31) / 32;
+        tb[u + 1] = tb[u] + nt * nt;
+      }
+      upload(tbase, tb, s);
+      HIPCHK(pmmf::launch_transpose_blocks(sd.m, sd.off.as<int32_t>(), sd.gbase.as<int64_t>(),
+                                           tbase.as<int64_t>(), tb[sd.m], Q.as<float>(),
+                                           G.as<float>(), s));
+    }
+    for (int which = 0; which < 2; ++which) {
+      Csr& Z = which == 0 ? Qr : Qt;
+      const float* pool_src = which == 0 ? Q.as<float>() : G.as<float>();
+      Z.n = S;
+      Z.rp.ensure((S + 1) * sizeof(int64_t));
+      HIPCHK(pmmf::launch_qbar_count(S, sd.off.as<int32_t>(), sd.cl_of.as<int32_t>(),
+                                     sd.gbase.as<int64_t>(), pool_src, cnt.as<int32_t>(), s));
+      HIPCHK(pmmf::launch_scan(cnt.as<int32_t>(), Z.rp.as<int64_t>(), S, scan_tmp.as<int64_t>(), s));
+      Z.nnz = read_i64(Z.rp.as<int64_t>() + S, s);
+      Z.ci.ensure(std::max<int64_t>(Z.nnz, 1) * sizeof(int32_t));
+      Z.cv.ensure(std::max<int64_t>(Z.nnz, 1) * sizeof(float));
+      HIPCHK(pmmf::launch_qbar_fill(S, sd.off.as<int32_t>(), sd.cl_of.as<int32_t>(),
+                                    sd.gbase.as<int64_t>(), pool_src, Z.rp.as<int64_t>(),
+                                    Z.ci.as<int32_t>(), Z.cv.as<float>(), s));
+    }
+    // W = M Qbar^T
+    W.n = S;
+    W.rp.ensure((S + 1) * sizeof(int64_t));
+    HIPCHK(pmmf::launch_right(S, 0, M.rp.as<int64_t>(), M.ci.as<int32_t>(), M.cv.as<float>(),
+                              sd.off.as<int32_t>(), sd.cl_of.as<int32_t>(), Qt.rp.as<int64_t>(),
+                              Qt.ci.as<int32_t>(), Qt.cv.as<float>(), cnt.as<int32_t>(), nullptr,
+                              nullptr, nullptr, cm, s));
+    HIPCHK(pmmf::launch_scan(cnt.as<int32_t>(), W.rp.as<int64_t>(), S, scan_tmp.as<int64_t>(), s));
+    W.nnz = read_i64(W.rp.as<int64_t>() + S, s);
+    W.ci.ensure(std::max<int64_t>(W.nnz, 1) * sizeof(int32_t));
+    W.cv.ensure(std::max<int64_t>(W.nnz, 1) * sizeof(float));
+    HIPCHK(pmmf::launch_right(S, 1, M.rp.as<int64_t>(), M.ci.as<int32_t>(), M.cv.as<float>(),
+                              sd.off.as<int32_t>(), sd.cl_of.as<int32_t>(), Qt.rp.as<int64_t>(),
+                              Qt.ci.as<int32_t>(), Qt.cv.as<float>(), nullptr, W.rp.as<int64_t>(),
+                              W.ci.as<int32_t>(), W.cv.as<float>(), cm, s));
+    // A_p = Qbar W, peeled to the survivors, plus the exact residual of the retired rows
+    M2.n = Snext;
+    M2.rp.ensure((Snext + 1) * sizeof(int64_t));
+    HIPCHK(pmmf::launch_left(S, 0, Qr.rp.as<int64_t>(), Qr.ci.as<int32_t>(), Qr.cv.as<float>(),
+                             W.rp.as<int64_t>(), W.ci.as<int32_t>(), W.cv.as<float>(),
+                             sd.off.as<int32_t>(), sd.cl_of.as<int32_t>(), sd.next.as<int32_t>(),
+                             cnt.as<int32_t>(), nullptr, nullptr, nullptr, nullptr,
+                             overflow.as<int32_t>(), cm, s));
+    HIPCHK(pmmf::launch_scan(cnt.as<int32_t>(), M2.rp.as<int64_t>(), Snext, scan_tmp.as<int64_t>(), s));
+    M2.nnz = read_i64(M2.rp.as<int64_t>() + Snext, s);
+    {
+      int32_t fl2[2] = {0, 0};
+      HIPCHK(hipMemcpy(fl2, overflow.p, 2 * sizeof(int32_t), hipMemcpyDeviceToHost));
+      if (fl2[1]) raise(MMF_EDEVICE, "greedy search found no partner in a cluster");
+      if (fl2[0]) raise(MMF_ECAPACITY, "a row of Qbar has more than 512 entries");
+    }
+    M2.ci.ensure(std::max<int64_t>(M2.nnz, 1) * sizeof(int32_t));
+    M2.cv.ensure(std::max<int64_t>(M2.nnz, 1) * sizeof(float));
+    HIPCHK(pmmf::launch_left(S, 1, Qr.rp.as<int64_t>(), Qr.ci.as<int32_t>(), Qr.cv.as<float>(),
+                             W.rp.as<int64_t>(), W.ci.as<int32_t>(), W.cv.as<float>(),
+                             sd.off.as<int32_t>(), sd.cl_of.as<int32_t>(), sd.next.as<int32_t>(),
+                             nullptr, M2.rp.as<int64_t>(), M2.ci.as<int32_t>(), M2.cv.as<float>(),
+                             loss_row.as<double>(), overflow.as<int32_t>(), cm, s));
+    HIPCHK(pmmf::launch_sum_double(loss_row.as<double>(), S, stage_loss.as<double>() + pi, s));
+    M.rp.swap_with(M2.rp);
+    M.ci.swap_with(M2.ci);
+    M.cv.swap_with(M2.cv);
+    std::swap(M.nnz, M2.nnz);
+    M.n = Snext;
+    gid_cur.swap_with(gid_new);
+    rot_base += sd.t;
+    h->st.push_back(std::move(sdp));
+  }
+
+  // core: the final active block, dense
+  const int64_t core = h->core;
+  h->hcore.ensure(std::max<int64_t>(core * core, 1) * sizeof(float));
+  HIPCHK(hipMemsetAsync(h->hcore.p, 0, core * core * sizeof(float), s));
+  HIPCHK(pmmf::launch_core_dense((int)core, M.rp.as<int64_t>(), M.ci.as<int32_t>(),
+                                 M.cv.as<float>(), h->hcore.as<float>(), s));
+  h->core_ids.ensure(std::max<int64_t>(core, 1) * sizeof(int32_t));
+  if (sched.empty()) HIPCHK(pmmf::launch_iota(h->core_ids.as<int32_t>(), core, s));
+  else HIPCHK(hipMemcpyAsync(h->core_ids.p, gid_cur.p, core * sizeof(int32_t),
+                             hipMemcpyDeviceToDevice, s));
+  // H statistics and the literal loss
+  HIPCHK(pmmf::launch_h_stats(n, h->hdiag.as<float>(), core, h->hcore.as<float>(),
+                              dsum.as<double>() + 2, s));
+  HIPCHK(pmmf::launch_sum_double(h->rot_lit.as<double>(), R, dsum.as<double>() + 4, s));
+  HIPCHK(hipEventRecord(ev1, s));
+  double hst[4] = {0, 0, 0, 0};
+  std::vector<double> sl(sched.size(), 0.0);
+  int32_t ovf = 0;
+  HIPCHK(hipMemcpyAsync(hst, dsum.as<double>() + 2, 3 * sizeof(double), hipMemcpyDeviceToHost, s));
+  if (!sched.empty())
+    HIPCHK(hipMemcpyAsync(sl.data(), stage_loss.p, sl.size() * sizeof(double),
+                          hipMemcpyDeviceToHost, s));
+  HIPCHK(hipMemcpyAsync(&ovf, overflow.p, sizeof(ovf), hipMemcpyDeviceToHost, s));
+  HIPCHK(hipStreamSynchronize(s));
+  if (ovf) raise(MMF_ECAPACITY, "a row of a stage rotation had more than 512 terms");
+  float ms = 0.f;
+  HIPCHK(hipEventElapsedTime(&ms, ev0, ev1));
+  (void)hipEventDestroy(ev0);
+  (void)hipEventDestroy(ev1);
+
+  // is_core flags for the sweeps
+  {
+    std::vector<int32_t> cid(core);
+    HIPCHK(hipMemcpy(cid.data(), h->core_ids.p, core * sizeof(int32_t), hipMemcpyDeviceToHost));
+    std::vector<uint8_t> flag(n, 0);
+    for (int32_t g : cid) flag[g] = 1;
+    upload(h->is_core, flag, s);
+    HIPCHK(hipStreamSynchronize(s));
+  }
+  mmf_info& inf = h->info;
+  inf.n = n;
+  inf.core_size = core;
+  inf.k = h->k;
+  inf.num_stages = (int32_t)h->st.size();
+  inf.num_rotations = R;
+  inf.max_clusters = 0;
+  inf.loss = 0.0;
+  for (size_t q = 0; q < sl.size(); ++q) {
+    h->st[q]->loss = sl[q];
+    inf.loss += sl[q];
+    inf.max_clusters = std::max<int64_t>(inf.max_clusters, h->st[q]->m);
+  }
+  inf.fro2_h = hst[0];
+  inf.trace_h = hst[1];
+  inf.loss_literal = hst[2];
+  inf.factor_ms = ms;
+  // stage depths for the stage info
+  for (auto& sp : h->st) {
+    std::vector<int32_t> dep(sp->m);
+    HIPCHK(hipMemcpy(dep.data(), sp->depth.p, sp->m * sizeof(int32_t), hipMemcpyDeviceToHost));
+    sp->depth_max = 0;
+    for (int32_t d : dep) sp->depth_max = std::max(sp->depth_max, d);
+  }
+  *out = h.release();
+  register_handle(*out);
+  return MMF_OK;
+  ABI_END
+}
+
+// ------------------------------------------------------------------------------------------
+namespace {
+
+float* wsbuf(mmf_plan& h, int slot, size_t floats) {
+  h.ws[slot].ensure(std::max<size_t>(floats, 1) * sizeof(float));
+  return h.ws[slot].as<float>();
+}
+
+void ensure_inverse(mmf_plan& h, hipStream_t s) {
+  if (h.inv_ready) return;
+  const int64_t c = h.core;
+  h.hinv.ensure(std::max<int64_t>(c * c, 1) * sizeof(float));
+  h.chol_L.ensure(std::max<int64_t>(c * c, 1) * sizeof(float));
+  h.chol_X.ensure(std::max<int64_t>(c * c, 1) * sizeof(float));
+  h.status.ensure(sizeof(int32_t));
+  HIPCHK(hipMemsetAsync(h.status.p, 0, sizeof(int32_t), s));
+  if (c > 0)
+    HIPCHK(hipMemcpyAsync(h.chol_L.p, h.hcore.p, c * c * sizeof(float), hipMemcpyDeviceToDevice, s));
+  HIPCHK(pmmf::launch_core_inverse((int)c, h.chol_L.as<float>(), h.chol_X.as<float>(),
+                                   h.hinv.as<float>(), h.n, h.hdiag.as<float>(),
+                                   h.is_core.as<uint8_t>(), h.status.as<int32_t>(), s));
+  int32_t st = 0;
+  HIPCHK(hipMemcpyAsync(&st, h.status.p, sizeof(st), hipMemcpyDeviceToHost, s));
+  HIPCHK(hipStreamSynchronize(s));
+  if (st & 2) raise(MMF_ESINGULAR, "H has a zero retired diagonal entry");
+  if (st & 1) raise(MMF_ESINGULAR, "the core of H is not positive definite");
+  h.inv_ready = true;
+}
+
+// Y = U^T op(H) U X with op = H (inverse = false) or H^{-1}
+void apply_impl(mmf_plan& h, const float* x, float* y, int64_t nrhs, int64_t ld, hipStream_t s,
+                bool inverse) {
+  if (nrhs < 0 || ld < nrhs || (!x && nrhs > 0) || (!y && nrhs > 0))
+    raise(MMF_EINVAL, "bad vector arguments");
+  if (nrhs == 0) return;
+  if (inverse) ensure_inverse(h, s);
+  const float* Hc = inverse ? h.hinv.as<float>() : h.hcore.as<float>();
+  const int P = (int)h.st.size();
+  const int64_t core = h.core;
+  if (P == 0) {
+    HIPCHK(pmmf::launch_gemm((int)core, (int)nrhs, (int)core, Hc, (int)core, 0, x, (int)ld, 0, y,
+                             (int)ld, 0.f, s));
+    return;
+  }
+  const int64_t s1 = h.st[0]->size - h.st[0]->t;
+  float* buf[2] = {wsbuf(h, 0, s1 * nrhs), wsbuf(h, 1, s1 * nrhs)};
+  const int W = pick_tile(h, 1, nrhs);
+  for (int p = 1; p <= P; ++p) {
+    const StageDev& sd = *h.st[p - 1];
+    pmmf::FwdIO io{};
+    io.src[0] = p == 1 ? x : buf[(p - 1) % 2];
+    io.ld_src = p == 1 ? ld : nrhs;
+    io.dst_c[0] = buf[p % 2];
+    io.ld_c = nrhs;
+    io.dst_nat[0] = y;
+    io.ld_nat = ld;
+    io.mode[0] = inverse ? 2 : 1;
+    io.hdiag = h.hdiag.as<float>();
+    io.nrhs = nrhs;
+    HIPCHK(pmmf::launch_sweep_fwd(sweep_view(h, sd), io, W, 1, s));
+  }
+  HIPCHK(pmmf::launch_gemm((int)core, (int)nrhs, (int)core, Hc, (int)core, 0, buf[P % 2],
+                           (int)nrhs, 0, buf[(P + 1) % 2], (int)nrhs, 0.f, s));
+  for (int p = P; p >= 1; --p) {
+    const StageDev& sd = *h.st[p - 1];
+    pmmf::RevIO io{};
+    io.src_c[0] = buf[(p + 1) % 2];
+    io.ld_c = nrhs;
+    io.src_nat[0] = y;
+    io.ld_nat = ld;
+    io.mode[0] = 0;
+    io.hdiag = h.hdiag.as<float>();
+    if (p == 1) {
+      io.dst_nat[0] = y;
+      io.ld_dnat = ld;
+    } else {
+      io.dst_c[0] = buf[p % 2];
+      io.ld_out = nrhs;
+    }
+    io.nrhs = nrhs;
+    HIPCHK(pmmf::launch_sweep_rev(sweep_view(h, sd), io, W, 1, false, s));
+  }
+}
+
+}  // namespace
+
+extern "C" int mmf_apply(mmf_handle hh, const float* d_x, float* d_y, int64_t nrhs, int64_t ld,
+                         void* stream) {
+  ABI_BEGIN
+  mmf_plan& h = *checked(hh);
+  apply_impl(h, d_x, d_y, nrhs, ld, as_stream(stream), false);
+  return MMF_OK;
+  ABI_END
+}
+
+extern "C" int mmf_apply_inverse(mmf_handle hh, const float* d_x, float* d_y, int64_t nrhs,
+                                 int64_t ld, void* stream) {
+  ABI_BEGIN
+  mmf_plan& h = *checked(hh);
+  apply_impl(h, d_x, d_y, nrhs, ld, as_stream(stream), true);
+  return MMF_OK;
+  ABI_END
+}
+
+extern "C" int mmf_backward(mmf_handle hh, const float* d_x, const float* d_ybar, float* d_xbar,
+                            float* d_hdiag_bar, float* d_hcore_bar, float* d_theta_bar,
+                            int64_t nrhs, int64_t ld, void* stream) {
+  ABI_BEGIN
+  mmf_plan& h = *checked(hh);
+  hipStream_t s = as_stream(stream);
+  if (nrhs < 1 || ld < nrhs || !d_x || !d_ybar) raise(MMF_EINVAL, "bad vector arguments");
+  if (d_theta_bar && h.k != 2) raise(MMF_EINVAL, "angle gradients exist only for k = 2");
+  const int P = (int)h.st.size();
+  const int64_t n = h.n, core = h.core;
+  const float* Hc = h.hcore.as<float>();
+  // forward sweeps of x and ybar together: a = U x, b = U ybar
+  float* a_nat = wsbuf(h, 2, n * nrhs);
+  float* b_nat = wsbuf(h, 3, n * nrhs);
+  const int64_t s1 = P > 0 ? h.st[0]->size - h.st[0]->t : core;
+  float* F[2][2] = {{wsbuf(h, 4, s1 * nrhs), wsbuf(h, 5, s1 * nrhs)},
+                    {wsbuf(h, 6, s1 * nrhs), wsbuf(h, 7, s1 * nrhs)}};  // F[vector][pingpong]
+  float* ga_core = wsbuf(h, 8, core * nrhs);
+  float* gb_core = wsbuf(h, 9, core * nrhs);
+  const float* a_core;
+  const float* b_core;
+  if (P == 0) {
+    a_core = d_x;
+    b_core = d_ybar;
+  }
+  const int W2 = pick_tile(h, 2, nrhs);
+  for (int p = 1; p <= P; ++p) {
+    const StageDev& sd = *h.st[p - 1];
+    pmmf::FwdIO io{};
+    io.src[0] = p == 1 ? d_x : F[0][(p - 1) % 2];
+    io.src[1] = p == 1 ? d_ybar : F[1][(p - 1) % 2];
+    io.ld_src = p == 1 ? ld : nrhs;
+    io.dst_c[0] = F[0][p % 2];
+    io.dst_c[1] = F[1][p % 2];
+    io.ld_c = nrhs;
+    io.dst_nat[0] = a_nat;
+    io.dst_nat[1] = b_nat;
+    io.ld_nat = nrhs;
+    io.mode[0] = io.mode[1] = 0;
+    io.hdiag = h.hdiag.as<float>();
+    io.nrhs = nrhs;
+    HIPCHK(pmmf::launch_sweep_fwd(sweep_view(h, sd), io, W2, 2, s));
+  }
+  int64_t lda_core = nrhs;
+  if (P > 0) {
+    a_core = F[0][P % 2];
+    b_core = F[1][P % 2];
+  } else {
+    lda_core = ld;
+  }
+  // H gradients: hdiag_bar on retired rows, hcore_bar = b_core a_core^T
+  if (d_hdiag_bar) {
+    if (P > 0)
+      HIPCHK(pmmf::launch_rowdot(n, a_nat, b_nat, nrhs, nrhs, h.is_core.as<uint8_t>(),
+                                 d_hdiag_bar, s));
+    else
+      HIPCHK(hipMemsetAsync(d_hdiag_bar, 0, n * sizeof(float), s));
+  }
+  if (d_hcore_bar)
+    HIPCHK(pmmf::launch_gemm((int)core, (int)core, (int)nrhs, b_core, (int)lda_core, 0, a_core,
+                             (int)lda_core, 1, d_hcore_bar, (int)core, 0.f, s));
+  // adjoint seeds on the core: g_a = H a, g_b = H^T b
+  HIPCHK(pmmf::launch_gemm((int)core, (int)nrhs, (int)core, Hc, (int)core, 0, a_core,
+                           (int)lda_core, 0, ga_core, (int)nrhs, 0.f, s));
+  HIPCHK(pmmf::launch_gemm((int)core, (int)nrhs, (int)core, Hc, (int)core, 1, b_core,
+                           (int)lda_core, 0, gb_core, (int)nrhs, 0.f, s));
+  if (P == 0) {
+    if (d_xbar)
+      HIPCHK(hipMemcpy2DAsync(d_xbar, ld * sizeof(float), gb_core, nrhs * sizeof(float),
+                              nrhs * sizeof(float), core, hipMemcpyDeviceToDevice, s));
+    return MMF_OK;
+  }
+  // reverse passes: A carries (z = U-states of ybar, g_a), B carries (z = states of x, g_b)
+  float* RA[2][2] = {{wsbuf(h, 10, s1 * nrhs), wsbuf(h, 11, s1 * nrhs)},
+                     {wsbuf(h, 12, s1 * nrhs), wsbuf(h, 13, s1 * nrhs)}};
+  float* RB[2][2] = {{wsbuf(h, 4, s1 * nrhs), wsbuf(h, 5, s1 * nrhs)},
+                     {wsbuf(h, 14, s1 * nrhs), wsbuf(h, 15, s1 * nrhs)}};
+  // RB[0] reuses the buffers of F[0]; the core states are copied first (below), so no buffer is
+  // read and written by the same sweep
+  const int ntiles = (int)((nrhs + W2 - 1) / W2);
+  int64_t tmax = 1;
+  for (auto& sp : h.st) tmax = std::max(tmax, sp->t);
+  DBuf pa_buf, pb_buf;
+  pa_buf.ensure((size_t)ntiles * tmax * sizeof(float));
+  pb_buf.ensure((size_t)ntiles * tmax * sizeof(float));
+  // copy of the core states so the ping-pong buffers are free for pass B
+  DBuf acopy, bcopy;
+  acopy.ensure(std::max<int64_t>(core * nrhs, 1) * sizeof(float));
+  bcopy.ensure(std::max<int64_t>(core * nrhs, 1) * sizeof(float));
+  HIPCHK(hipMemcpyAsync(acopy.p, a_core, core * nrhs * sizeof(float), hipMemcpyDeviceToDevice, s));
+  HIPCHK(hipMemcpyAsync(bcopy.p, b_core, core * nrhs * sizeof(float), hipMemcpyDeviceToDevice, s));
+  for (int p = P; p >= 1; --p) {
+    const StageDev& sd = *h.st[p - 1];
+    const pmmf::SweepStage v = sweep_view(h, sd);
+    for (int pass = 0; pass < 2; ++pass) {
+      float* (*Rb)[2] = pass == 0 ? RA : RB;
+      pmmf::RevIO io{};
+      if (p == P) {
+        io.src_c[0] = pass == 0 ? bcopy.as<float>() : acopy.as<float>();
+        io.src_c[1] = pass == 0 ? ga_core : gb_core;
+      } else {
+        io.src_c[0] = Rb[0][(p + 1) % 2];
+        io.src_c[1] = Rb[1][(p + 1) % 2];
+      }
+      io.ld_c = nrhs;
+      io.src_nat[0] = pass == 0 ? b_nat : a_nat;
+      io.src_nat[1] = pass == 0 ? a_nat : b_nat;
+      io.ld_nat = nrhs;
+      io.mode[0] = 0;
+      io.mode[1] = 1;
+      io.hdiag = h.hdiag.as<float>();
+      if (p == 1) {
+        io.dst_nat[0] = nullptr;
+        io.dst_nat[1] = pass == 1 ? d_xbar : nullptr;
+        io.ld_dnat = ld;
+      } else {
+        io.dst_c[0] = Rb[0][p % 2];
+        io.dst_c[1] = Rb[1][p % 2];
+        io.ld_out = nrhs;
+      }
+      io.nrhs = nrhs;
+      io.theta_part = pass == 0 ? pa_buf.as<float>() : pb_buf.as<float>();
+      io.theta_stride = sd.t;
+      HIPCHK(pmmf::launch_sweep_rev(v, io, W2, 2, h.k == 2, s));
+    }
+    if (d_theta_bar)
+      HIPCHK(pmmf::launch_theta_reduce((int)sd.t, ntiles, sd.t, pa_buf.as<float>(),
+                                       pb_buf.as<float>(), sd.sw_idx.as<int32_t>(), d_theta_bar,
+                                       s));
+  }
+  // keep the temporaries alive until the stream has consumed them
+  HIPCHK(hipStreamSynchronize(s));
+  return MMF_OK;
+  ABI_END
+}
+
+extern "C" int mmf_get_info(mmf_handle hh, mmf_info* out) {
+  ABI_BEGIN
+  mmf_plan& h = *checked(hh);
+  if (!out) raise(MMF_EINVAL, "out is NULL");
+  *out = h.info;
+  return MMF_OK;
+  ABI_END
+}
+
+extern "C" int mmf_get_stage_info(mmf_handle hh, int32_t stage, mmf_stage_info* out) {
+  ABI_BEGIN
+  mmf_plan& h = *checked(hh);
+  if (!out || stage < 0 || stage >= (int32_t)h.st.size()) raise(MMF_EINVAL, "bad stage");
+  const StageDev& sd = *h.st[stage];
+  out->size = sd.size;
+  out->rotations = sd.t;
+  out->clusters = sd.m;
+  out->nnz = sd.nnz;
+  out->max_cluster = sd.cmax;
+  out->max_depth = sd.depth_max;
+  out->pad = 0;
+  out->loss = sd.loss;
+  return MMF_OK;
+  ABI_END
+}
+
+extern "C" int mmf_export(mmf_handle hh, int32_t* rot_ids, float* rot_o, int32_t* rot_retired,
+                          float* rot_margin, float* hdiag, int32_t* core_ids, float* hcore) {
+  ABI_BEGIN
+  mmf_plan& h = *checked(hh);
+  HIPCHK(hipStreamSynchronize(h.stream));
+  const int64_t R = h.R;
+  const int k = h.k;
+  if (rot_ids || rot_o) {
+    std::vector<int32_t> ids(R * 3);
+    std::vector<float> o(R * 9);
+    if (R) {
+      HIPCHK(hipMemcpy(ids.data(), h.rot_gid.p, R * 3 * sizeof(int32_t), hipMemcpyDeviceToHost));
+      HIPCHK(hipMemcpy(o.data(), h.rot_o.p, R * 9 * sizeof(float), hipMemcpyDeviceToHost));
+    }
+    for (int64_t r = 0; r < R; ++r) {
+      for (int a = 0; a < k; ++a) {
+        if (rot_ids) rot_ids[r * k + a] = ids[r * 3 + a];
+        for (int b = 0; b < k; ++b)
+          if (rot_o) rot_o[(r * k + a) * k + b] = o[r * 9 + a * 3 + b];
+      }
+    }
+  }
+  if (rot_retired && R)
+    HIPCHK(hipMemcpy(rot_retired, h.rot_ret.p, R * sizeof(int32_t), hipMemcpyDeviceToHost));
+  if (rot_margin && R)
+    HIPCHK(hipMemcpy(rot_margin, h.rot_margin.p, R * sizeof(float), hipMemcpyDeviceToHost));
+  if (hdiag) HIPCHK(hipMemcpy(hdiag, h.hdiag.p, h.n * sizeof(float), hipMemcpyDeviceToHost));
+  if (core_ids && h.core)
+    HIPCHK(hipMemcpy(core_ids, h.core_ids.p, h.core * sizeof(int32_t), hipMemcpyDeviceToHost));
+  if (hcore && h.core)
+    HIPCHK(hipMemcpy(hcore, h.hcore.p, h.core * h.core * sizeof(float), hipMemcpyDeviceToHost));
+  return MMF_OK;
+  ABI_END
+}
+
+extern "C" int mmf_import(int64_t n, int32_t k, int64_t core_size, int32_t num_stages,
+                          const int64_t* stage_sizes, const int64_t* stage_clusters,
+                          const int64_t* cluster_sizes, const int32_t* rot_ids,
+                          const float* rot_o, const int32_t* rot_retired, const float* hdiag,
+                          const int32_t* core_ids, const float* hcore, void* stream,
+                          mmf_handle* out) {
+  ABI_BEGIN
+  g_err.clear();
+  if (!out) raise(MMF_EINVAL, "out is NULL");
+  *out = nullptr;
+  if (n < 1 || (k != 2 && k != 3) || core_size < 1 || core_size > n || num_stages < 0)
+    raise(MMF_EINVAL, "bad sizes");
+  if (num_stages > 0 && (!stage_sizes || !stage_clusters || !cluster_sizes || !rot_ids ||
+                         !rot_o || !rot_retired))
+    raise(MMF_EINVAL, "missing stage or rotation arrays");
+  if (!hdiag || !core_ids || !hcore) raise(MMF_EINVAL, "missing H arrays");
+  hipStream_t s = as_stream(stream);
+  auto h = std::make_unique<mmf_plan>();
+  h->n = n;
+  h->core = core_size;
+  h->k = k;
+  h->stream = s;
+  h->R = n - core_size;
+  h->prm.k = k;
+  h->prm.core_size = core_size;
+  const int64_t R = h->R;
+  std::vector<int32_t> loc(std::max<int64_t>(R, 1) * 3, -1), gidv(std::max<int64_t>(R, 1) * 3, -1),
+      ret(std::max<int64_t>(R, 1), 0);
+  std::vector<float> ob(std::max<int64_t>(R, 1) * 9, 0.f), th(std::max<int64_t>(R, 1), 0.f);
+  std::vector<int32_t> active(n);
+  for (int64_t i = 0; i < n; ++i) active[i] = (int32_t)i;
+  std::vector<int32_t> pos_of(n, -1);
+  int64_t rbase = 0, cbase = 0;
+  std::vector<uint8_t> retired(n, 0);
+  for (int32_t p = 0; p < num_stages; ++p) {
+    const int64_t S = stage_sizes[p];
+    const int64_t Snext = p + 1 < num_stages ? stage_sizes[p + 1] : core_size;
+    if (S != (int64_t)active.size() || Snext >= S) raise(MMF_EINVAL, "inconsistent stage sizes");
+    SchedStage sc;
+    sc.size = S;
+    sc.t = S - Snext;
+    const int64_t m = stage_clusters[p];
+    std::vector<int32_t> off(m + 1, 0);
+    for (int64_t u = 0; u < m; ++u) {
+      sc.sizes.push_back((int32_t)cluster_sizes[cbase + u]);
+      off[u + 1] = off[u] + (int32_t)cluster_sizes[cbase + u];
+    }
+    if (off[m] != S) raise(MMF_EINVAL, "cluster sizes do not add up to the stage size");
+    cbase += m;
+    for (int64_t q = 0; q < S; ++q) pos_of[active[q]] = (int32_t)q;
+    sc.rcnt.assign(m, 0);
+    int64_t last_u = 0;
+    for (int64_t r = rbase; r < rbase + sc.t; ++r) {
+      const int32_t q0 = pos_of[rot_ids[r * k]];
+      if (q0 < 0) raise(MMF_EINVAL, "rotation touches an inactive index");
+      const int64_t u = std::upper_bound(off.begin(), off.end(), q0) - off.begin() - 1;
+      if (u < last_u) raise(MMF_EINVAL, "rotations are not grouped by cluster");
+      last_u = u;
+      sc.rcnt[u] += 1;
+      for (int a = 0; a < k; ++a) {
+        const int32_t g = rot_ids[r * k + a];
+        const int32_t q = pos_of[g];
+        if (q < off[u] || q >= off[u + 1]) raise(MMF_EINVAL, "rotation crosses clusters");
+        loc[r * 3 + a] = q - off[u];
+        gidv[r * 3 + a] = g;
+        for (int b = 0; b < k; ++b) ob[r * 9 + a * 3 + b] = rot_o[(r * k + a) * k + b];
+      }
+      ret[r] = rot_retired[r];
+      if (pos_of[ret[r]] < 0 || retired[ret[r]]) raise(MMF_EINVAL, "bad retired index");
+      retired[ret[r]] = 1;
+      if (k == 2) th[r] = std::atan2(rot_o[(r * 2 + 1) * 2 + 0], rot_o[(r * 2 + 0) * 2 + 0]);
+    }
+    auto sdp = std::make_unique<StageDev>();
+    StageDev& sd = *sdp;
+    build_stage_geometry(sd, sc, rbase, s);
+    std::vector<int32_t> next(S), gid(S);
+    std::vector<int32_t> nact;
+    for (int64_t q = 0; q < S; ++q) {
+      const int32_t g = active[q];
+      gid[q] = g;
+      if (retired[g]) {
+        next[q] = -g - 1;
+      } else {
+        next[q] = (int32_t)nact.size();
+        nact.push_back(g);
+      }
+    }
+    if ((int64_t)nact.size() != Snext) raise(MMF_EINVAL, "retirements do not match stage sizes");
+    upload(sd.next, next, s);
+    upload(sd.gid, gid, s);
+    for (int64_t q = 0; q < S; ++q) pos_of[active[q]] = -1;
+    active.swap(nact);
+    rbase += sc.t;
+    h->st.push_back(std::move(sdp));
+  }
+  if (rbase != R) raise(MMF_EINVAL, "rotation count does not equal n - core_size");
+  upload(h->rot_loc, loc, s);
+  upload(h->rot_gid, gidv, s);
+  upload(h->rot_o, ob, s);
+  upload(h->rot_ret, ret, s);
+  upload(h->theta, th, s);
+  h->rot_margin.ensure(std::max<int64_t>(R, 1) * sizeof(float));
+  HIPCHK(hipMemsetAsync(h->rot_margin.p, 0, std::max<int64_t>(R, 1) * sizeof(float), s));
+  for (auto& sp : h->st) {
+    StageDev& sd = *sp;
+    sd.sw_loc.ensure(sd.t * k * sizeof(int32_t));
+    sd.sw_o.ensure(sd.t * k * k * sizeof(float));
+    HIPCHK(pmmf::launch_levelize(sd.m, k, sd.off.as<int32_t>(), sd.rcnt.as<int32_t>(),
+                                 sd.roff.as<int32_t>(), sd.rot_base, h->rot_loc.as<int32_t>(),
+                                 h->rot_o.as<float>(), sd.lvl_stride, sd.lvl_ptr.as<int32_t>(),
+                                 sd.depth.as<int32_t>(), sd.sw_loc.as<int32_t>(),
+                                 sd.sw_o.as<float>(), sd.sw_idx.as<int32_t>(),
+                                 round_cmax(sd.cmax), s));
+  }
+  std::vector<float> hd(hdiag, hdiag + n), hc(hcore, hcore + core_size * core_size);
+  std::vector<int32_t> cid(core_ids, core_ids + core_size);
+  std::vector<uint8_t> flag(n, 0);
+  for (int32_t g : cid) {
+    if (g < 0 || g >= n || flag[g]) raise(MMF_EINVAL, "bad core ids");
+    flag[g] = 1;
+  }
+  upload(h->hdiag, hd, s);
+  upload(h->hcore, hc, s);
+  upload(h->core_ids, cid, s);
+  upload(h->is_core, flag, s);
+  HIPCHK(hipStreamSynchronize(s));
+  for (auto& sp : h->st) {
+    std::vector<int32_t> dep(sp->m);
+    HIPCHK(hipMemcpy(dep.data(), sp->depth.p, sp->m * sizeof(int32_t), hipMemcpyDeviceToHost));
+    sp->depth_max = 0;
+    for (int32_t d : dep) sp->depth_max = std::max(sp->depth_max, d);
+  }
+  h->info.n = n;
+  h->info.core_size = core_size;
+  h->info.k = k;
+  h->info.num_stages = num_stages;
+  h->info.num_rotations = R;
+  *out = h.release();
+  register_handle(*out);
+  return MMF_OK;
+  ABI_END
+}
+
+extern "C" int mmf_param_ptrs(mmf_handle hh, float** theta, float** hdiag, float** hcore) {
+  ABI_BEGIN
+  mmf_plan& h = *checked(hh);
+  if (theta) *theta = h.k == 2 ? h.theta.as<float>() : nullptr;
+  if (hdiag) *hdiag = h.hdiag.as<float>();
+  if (hcore) *hcore = h.hcore.as<float>();
+  return MMF_OK;
+  ABI_END
+}
+
+extern "C" int mmf_sync_angles(mmf_handle hh, void* stream) {
+  ABI_BEGIN
+  mmf_plan& h = *checked(hh);
+  hipStream_t s = as_stream(stream);
+  h.inv_ready = false;
+  if (h.k != 2) return MMF_OK;
+  HIPCHK(pmmf::launch_sync_angles(h.R, h.theta.as<float>(), h.rot_o.as<float>(), s));
+  for (auto& sp : h.st)
+    HIPCHK(pmmf::launch_sync_sweep((int)sp->t, sp->sw_idx.as<int32_t>(), h.theta.as<float>(),
+                                   sp->sw_o.as<float>(), s));
+  return MMF_OK;
+  ABI_END
+}
+
+extern "C" int mmf_set_params(mmf_handle hh, const float* d_theta, const float* d_hdiag,
+                              const float* d_hcore, void* stream) {
+  ABI_BEGIN
+  mmf_plan& h = *checked(hh);
+  hipStream_t s = as_stream(stream);
+  if (d_theta && h.k != 2) raise(MMF_EINVAL, "angles exist only for k = 2");
+  h.inv_ready = false;
+  if (d_hdiag)
+    HIPCHK(hipMemcpyAsync(h.hdiag.p, d_hdiag, h.n * sizeof(float), hipMemcpyDeviceToDevice, s));
+  if (d_hcore && h.core)
+    HIPCHK(hipMemcpyAsync(h.hcore.p, d_hcore, h.core * h.core * sizeof(float),
+                          hipMemcpyDeviceToDevice, s));
+  if (d_theta && h.R) {
+    HIPCHK(hipMemcpyAsync(h.theta.p, d_theta, h.R * sizeof(float), hipMemcpyDeviceToDevice, s));
+    HIPCHK(pmmf::launch_sync_angles(h.R, h.theta.as<float>(), h.rot_o.as<float>(), s));
+    for (auto& sp : h.st)
+      HIPCHK(pmmf::launch_sync_sweep((int)sp->t, sp->sw_idx.as<int32_t>(), h.theta.as<float>(),
+                                     sp->sw_o.as<float>(), s));
+  }
+  return MMF_OK;
+  ABI_END
+}
+
+extern "C" int mmf_destroy(mmf_handle hh) {
+  ABI_BEGIN
+  checked(hh);
+  {
+    std::lock_guard<std::mutex> lk(g_live_mu);
+    g_live.erase(hh);
+  }
+  (void)hipStreamSynchronize(hh->stream);
+  delete hh;
+  return MMF_OK;
+  ABI_END
+}

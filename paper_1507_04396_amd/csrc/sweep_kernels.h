@@ -1,0 +1,71 @@
+// Matrix-free sweeps over the factorization's stages and the small dense core kernels.
+#pragma once
+
+#include "common.h"
+
+namespace pmmf {
+
+// One stage of the factorization as the sweeps see it.
+struct SweepStage {
+  int m;                     // clusters
+  int k;                     // rotation order
+  int cmax;                  // largest cluster
+  int rmax;                  // most rotations in one cluster
+  int lvl_stride;            // row stride of lvl_ptr
+  const int32_t* off;        // [m+1] cluster offsets (positions of S_{p-1})
+  const int32_t* lvl_ptr;    // [m][lvl_stride] stage-local index where each level starts
+  const int32_t* depth;      // [m] number of levels
+  const int32_t* sw_loc;     // [t][k] cluster-local ids, level order
+  const float* sw_o;         // [t][k*k] rotation blocks, level order
+  const int32_t* next;       // [S] next-stage position, or -(gid + 1) if the row retires here
+  const int32_t* gid;        // [S] global id of each position
+};
+
+struct FwdIO {
+  const float* src[2];       // compact rows of S_{p-1}
+  int64_t ld_src;
+  float* dst_c[2];           // compact rows of S_p
+  int64_t ld_c;
+  float* dst_nat[2];         // natural rows (retired rows of this stage)
+  int64_t ld_nat;
+  int mode[2];               // retired rows: 0 copy, 1 times hdiag, 2 divided by hdiag
+  const float* hdiag;
+  int64_t nrhs;
+};
+
+struct RevIO {
+  const float* src_c[2];     // compact rows of S_p (survivors)
+  int64_t ld_c;
+  const float* src_nat[2];   // natural rows (this stage's retired rows)
+  int64_t ld_nat;
+  int mode[2];               // retired rows on load: 0 copy, 1 times hdiag
+  const float* hdiag;
+  float* dst_c[2];           // compact rows of S_{p-1} (NULL: do not write)
+  int64_t ld_out;
+  float* dst_nat[2];         // if set: write natural rows instead (first stage)
+  int64_t ld_dnat;
+  int64_t nrhs;
+  float* theta_part;         // [ntiles][theta_stride] per-tile angle-gradient partials
+  int64_t theta_stride;
+};
+
+size_t sweep_lds_bytes(int k, int W, int nv, int cmax, int rmax);
+hipError_t launch_sweep_fwd(const SweepStage& st, const FwdIO& io, int W, int nv, hipStream_t s);
+hipError_t launch_sweep_rev(const SweepStage& st, const RevIO& io, int W, int nv, bool theta,
+                            hipStream_t s);
+hipError_t launch_gemm(int M, int N, int K, const float* A, int lda, int ta, const float* B,
+                       int ldb, int tb, float* C, int ldc, float beta, hipStream_t s);
+hipError_t launch_core_inverse(int n, float* work_L, float* work_X, float* out_inv,
+                               int64_t nfull, const float* hdiag, const uint8_t* is_core,
+                               int32_t* status, hipStream_t s);
+hipError_t launch_rowdot(int64_t n, const float* a, const float* b, int64_t ld, int64_t nrhs,
+                         const uint8_t* is_core, float* out, hipStream_t s);
+hipError_t launch_theta_reduce(int t, int ntiles, int64_t stride, const float* pa,
+                               const float* pb, const int32_t* sw_idx, float* out, hipStream_t s);
+hipError_t launch_gather_rows(int64_t rows, const float* src, int64_t lds, const int32_t* idx,
+                              float* dst, int64_t ldd, int64_t ncol, int scatter, hipStream_t s);
+hipError_t launch_sync_angles(int64_t R, const float* theta, float* rot_o, hipStream_t s);
+hipError_t launch_sync_sweep(int t, const int32_t* sw_idx, const float* theta, float* sw_o,
+                             hipStream_t s);
+
+}  // namespace pmmf

@@ -1,0 +1,459 @@
+// Matrix-free application of the factorization (Sec. 2.4) and its adjoint, gfx950.
+//
+// A block of vectors X [n][ld] goes through the stages one at a time.  In stage p a workgroup owns
+// one cluster and a tile of W columns: it loads the cluster's c_u rows of the tile into LDS,
+// applies the cluster's rotations level by level (rotations of one level touch disjoint rows, so
+// each level is one parallel step), and writes the rows back: survivors to the next stage's compact
+// buffer (ascending position order), retired rows to their natural place.  Every active row is
+// read and written once per stage.
+#include "sweep_kernels.h"
+
+namespace pmmf {
+
+// dynamic LDS of a sweep workgroup: tile[NV][cmax][W] floats, then the cluster's rotation ids
+// [rmax][K] and k x k blocks [rmax][K*K]
+
+__device__ inline int level_begin(const SweepStage& st, int u, int l) {
+  return st.lvl_ptr[(size_t)u * st.lvl_stride + l];
+}
+
+// Load the cluster's rotations (ids and k x k blocks) into LDS.
+template <int K>
+__device__ inline void load_rotations(const SweepStage& st, int rb, int r, int* rid, float* rob) {
+  for (int q = threadIdx.x; q < r * K; q += blockDim.x) rid[q] = st.sw_loc[(size_t)rb * K + q];
+  for (int q = threadIdx.x; q < r * K * K; q += blockDim.x)
+    rob[q] = st.sw_o[(size_t)rb * K * K + q];
+}
+
+// Apply one rotation (slot ids ids[], block o[]) to column w of every vector tile.
+template <int K, int W, int NV, bool TRANS>
+__device__ inline void rotate_cols(float* tile, int cstride, const int* ids, const float* o, int w) {
+#pragma unroll
+  for (int v = 0; v < NV; ++v) {
+    float* t = tile + (size_t)v * cstride;
+    float x[K];
+#pragma unroll
+    for (int a = 0; a < K; ++a) x[a] = t[ids[a] * W + w];
+#pragma unroll
+    for (int a = 0; a < K; ++a) {
+      float s = 0.f;
+#pragma unroll
+      for (int b = 0; b < K; ++b) s += (TRANS ? o[b * K + a] : o[a * K + b]) * x[b];
+      t[ids[a] * W + w] = s;
+    }
+  }
+}
+
+// ------------------------------------------------------------------------------------------
+// forward stage sweep: rows of S_{p-1} (compact, src) -> rotations in order -> survivors to
+// dst_c (compact S_p), retired rows to dst_nat[gid] times the vector's scale mode
+template <int K, int W, int NV>
+__global__ void __launch_bounds__(256) k_sweep_fwd(SweepStage st, FwdIO io) {
+  extern __shared__ float lds_f[];
+  const int u = blockIdx.x;
+  const int col0 = blockIdx.y * W;
+  const int o = st.off[u];
+  const int c = st.off[u + 1] - o;
+  const int cstride = st.cmax * W;
+  float* tile = lds_f;
+  int* rid = reinterpret_cast<int*>(tile + (size_t)NV * cstride);
+  const int rb = level_begin(st, u, 0);
+  const int depth = st.depth[u];
+  const int r = level_begin(st, u, depth) - rb;
+  float* rob = reinterpret_cast<float*>(rid + st.rmax * K);
+  load_rotations<K>(st, rb, r, rid, rob);
+  for (int q = threadIdx.x; q < c * W; q += blockDim.x) {
+    const int row = q / W, w = q % W;
+    const int col = col0 + w;
+#pragma unroll
+    for (int v = 0; v < NV; ++v) {
+      float val = 0.f;
+      if (col < io.nrhs) val = io.src[v][(size_t)(o + row) * io.ld_src + col];
+      tile[(size_t)v * cstride + row * W + w] = val;
+    }
+  }
+  __syncthreads();
+  for (int l = 0; l < depth; ++l) {
+    const int b0 = level_begin(st, u, l) - rb, b1 = level_begin(st, u, l + 1) - rb;
+    for (int q = threadIdx.x; q < (b1 - b0) * W; q += blockDim.x) {
+      const int rr = b0 + q / W, w = q % W;
+      rotate_cols<K, W, NV, false>(tile, cstride, rid + rr * K, rob + rr * K * K, w);
+    }
+    __syncthreads();
+  }
+  for (int q = threadIdx.x; q < c * W; q += blockDim.x) {
+    const int row = q / W, w = q % W;
+    const int col = col0 + w;
+    if (col >= io.nrhs) continue;
+    const int nx = st.next[o + row];
+#pragma unroll
+    for (int v = 0; v < NV; ++v) {
+      float val = tile[(size_t)v * cstride + row * W + w];
+      if (nx >= 0) {
+        io.dst_c[v][(size_t)nx * io.ld_c + col] = val;
+      } else {
+        const int g = -nx - 1;
+        if (io.mode[v] == 1) val *= io.hdiag[g];
+        else if (io.mode[v] == 2) val /= io.hdiag[g];
+        io.dst_nat[v][(size_t)g * io.ld_nat + col] = val;
+      }
+    }
+  }
+}
+
+// ------------------------------------------------------------------------------------------
+// reverse stage sweep: rows of S_{p-1}: survivors from src_c (compact S_p), retired rows from
+// src_nat[gid] (times hdiag if mode = 1) -> transposed rotations in reverse order -> dst_c
+// (compact S_{p-1}) or, when dst_nat is set, natural order (first stage).  With THETA, vector 0
+// is the state z and vector 1 the adjoint g, and before undoing rotation t the kernel adds
+// sum_w <g[T], J z[T]> (J = [[0, -1], [1, 0]]) to the tile's partial angle gradient.
+template <int K, int W, int NV, bool THETA>
+__global__ void __launch_bounds__(256) k_sweep_rev(SweepStage st, RevIO io) {
+  extern __shared__ float lds_f[];
+  const int u = blockIdx.x;
+  const int col0 = blockIdx.y * W;
+  const int o = st.off[u];
+  const int c = st.off[u + 1] - o;
+  const int cstride = st.cmax * W;
+  float* tile = lds_f;
+  int* rid = reinterpret_cast<int*>(tile + (size_t)NV * cstride);
+  const int rb = level_begin(st, u, 0);
+  const int depth = st.depth[u];
+  const int r = level_begin(st, u, depth) - rb;
+  float* rob = reinterpret_cast<float*>(rid + st.rmax * K);
+  load_rotations<K>(st, rb, r, rid, rob);
+  for (int q = threadIdx.x; q < c * W; q += blockDim.x) {
+    const int row = q / W, w = q % W;
+    const int col = col0 + w;
+    const int nx = st.next[o + row];
+#pragma unroll
+    for (int v = 0; v < NV; ++v) {
+      float val = 0.f;
+      if (col < io.nrhs) {
+        if (nx >= 0) {
+          val = io.src_c[v][(size_t)nx * io.ld_c + col];
+        } else {
+          const int g = -nx - 1;
+          val = io.src_nat[v][(size_t)g * io.ld_nat + col];
+          if (io.mode[v] == 1) val *= io.hdiag[g];
+        }
+      }
+      tile[(size_t)v * cstride + row * W + w] = val;
+    }
+  }
+  __syncthreads();
+  for (int l = depth - 1; l >= 0; --l) {
+    const int b0 = level_begin(st, u, l) - rb, b1 = level_begin(st, u, l + 1) - rb;
+    const int nwork = (b1 - b0) * W;
+    const int nround = (nwork + blockDim.x - 1) / blockDim.x * blockDim.x;
+    for (int q = threadIdx.x; q < nround; q += blockDim.x) {
+      const bool live = q < nwork;
+      const int rr = b0 + (live ? q / W : 0), w = q % W;
+      if constexpr (THETA) {
+        float part = 0.f;
+        if (live) {
+          const int* ids = rid + rr * K;
+          const float* z = tile;
+          const float* g = tile + cstride;
+          const float zi = z[ids[0] * W + w], zj = z[ids[1] * W + w];
+          const float gi = g[ids[0] * W + w], gj = g[ids[1] * W + w];
+          part = gj * zi - gi * zj;
+        }
+        // reduce over the W consecutive lanes holding one rotation's columns
+#pragma unroll
+        for (int ofs = W / 2; ofs > 0; ofs >>= 1) part += __shfl_xor(part, ofs, W);
+        if (live && w == 0)
+          io.theta_part[(size_t)blockIdx.y * io.theta_stride + (rr + rb)] = part;
+      }
+      if (live) rotate_cols<K, W, NV, true>(tile, cstride, rid + rr * K, rob + rr * K * K, w);
+    }
+    __syncthreads();
+  }
+  for (int q = threadIdx.x; q < c * W; q += blockDim.x) {
+    const int row = q / W, w = q % W;
+    const int col = col0 + w;
+    if (col >= io.nrhs) continue;
+#pragma unroll
+    for (int v = 0; v < NV; ++v) {
+      const float val = tile[(size_t)v * cstride + row * W + w];
+      if (io.dst_nat[v]) {
+        io.dst_nat[v][(size_t)st.gid[o + row] * io.ld_dnat + col] = val;
+      } else if (io.dst_c[v]) {
+        io.dst_c[v][(size_t)(o + row) * io.ld_out + col] = val;
+      }
+    }
+  }
+}
+
+size_t sweep_lds_bytes(int k, int W, int nv, int cmax, int rmax) {
+  return (size_t)nv * cmax * W * sizeof(float) + (size_t)rmax * k * sizeof(int) +
+         (size_t)rmax * k * k * sizeof(float);
+}
+
+template <int K, int W, int NV>
+static hipError_t fwd_dispatch(const SweepStage& st, const FwdIO& io, hipStream_t s) {
+  const size_t lds = sweep_lds_bytes(K, W, NV, st.cmax, st.rmax);
+  auto fn = k_sweep_fwd<K, W, NV>;
+  if (lds > 64 * 1024) {
+    hipError_t e = hipFuncSetAttribute((const void*)fn, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                       (int)lds);
+    if (e != hipSuccess) return e;
+  }
+  dim3 grid(st.m, (io.nrhs + W - 1) / W);
+  k_sweep_fwd<K, W, NV><<<grid, 256, lds, s>>>(st, io);
+  return hipGetLastError();
+}
+
+template <int K, int W, int NV, bool TH>
+static hipError_t rev_dispatch(const SweepStage& st, const RevIO& io, hipStream_t s) {
+  const size_t lds = sweep_lds_bytes(K, W, NV, st.cmax, st.rmax);
+  auto fn = k_sweep_rev<K, W, NV, TH>;
+  if (lds > 64 * 1024) {
+    hipError_t e = hipFuncSetAttribute((const void*)fn, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                       (int)lds);
+    if (e != hipSuccess) return e;
+  }
+  dim3 grid(st.m, (io.nrhs + W - 1) / W);
+  k_sweep_rev<K, W, NV, TH><<<grid, 256, lds, s>>>(st, io);
+  return hipGetLastError();
+}
+
+#define PMMF_W_SWITCH(W, CALL)                     \
+  switch (W) {                                     \
+    case 1: { constexpr int WW = 1; return CALL; } \
+    case 2: { constexpr int WW = 2; return CALL; } \
+    case 4: { constexpr int WW = 4; return CALL; } \
+    case 8: { constexpr int WW = 8; return CALL; } \
+    case 16: { constexpr int WW = 16; return CALL; } \
+    case 32: { constexpr int WW = 32; return CALL; } \
+    default: return hipErrorInvalidValue;         \
+  }
+
+hipError_t launch_sweep_fwd(const SweepStage& st, const FwdIO& io, int W, int nv, hipStream_t s) {
+  if (st.m == 0) return hipSuccess;
+  if (st.k == 2) {
+    if (nv == 1) { PMMF_W_SWITCH(W, (fwd_dispatch<2, WW, 1>(st, io, s))) }
+    PMMF_W_SWITCH(W, (fwd_dispatch<2, WW, 2>(st, io, s)))
+  }
+  if (nv == 1) { PMMF_W_SWITCH(W, (fwd_dispatch<3, WW, 1>(st, io, s))) }
+  PMMF_W_SWITCH(W, (fwd_dispatch<3, WW, 2>(st, io, s)))
+}
+
+hipError_t launch_sweep_rev(const SweepStage& st, const RevIO& io, int W, int nv, bool theta,
+                            hipStream_t s) {
+  if (st.m == 0) return hipSuccess;
+  if (st.k == 2) {
+    if (theta) { PMMF_W_SWITCH(W, (rev_dispatch<2, WW, 2, true>(st, io, s))) }
+    if (nv == 1) { PMMF_W_SWITCH(W, (rev_dispatch<2, WW, 1, false>(st, io, s))) }
+    PMMF_W_SWITCH(W, (rev_dispatch<2, WW, 2, false>(st, io, s)))
+  }
+  if (nv == 1) { PMMF_W_SWITCH(W, (rev_dispatch<3, WW, 1, false>(st, io, s))) }
+  PMMF_W_SWITCH(W, (rev_dispatch<3, WW, 2, false>(st, io, s)))
+}
+
+// ------------------------------------------------------------------------------------------
+// dense FP32 GEMM  C[M][N] = op(A)[M][K] * op(B)[K][N]  (row-major, op = transpose if flagged),
+// 64 x 64 output tiles, 16-deep K slices staged in LDS, 4 x 4 outputs per thread
+__global__ void __launch_bounds__(256) k_gemm(int M, int N, int K, const float* __restrict__ A,
+                                              int lda, int ta, const float* __restrict__ B,
+                                              int ldb, int tb, float* __restrict__ C, int ldc,
+                                              float beta) {
+  __shared__ float As[16][64 + 1];
+  __shared__ float Bs[16][64 + 1];
+  const int tx = threadIdx.x % 16, ty = threadIdx.x / 16;
+  const int m0 = blockIdx.y * 64, n0 = blockIdx.x * 64;
+  float acc[4][4] = {};
+  for (int k0 = 0; k0 < K; k0 += 16) {
+    for (int q = threadIdx.x; q < 16 * 64; q += 256) {
+      const int kk = q / 64, mm = q % 64;
+      const int gm = m0 + mm, gk = k0 + kk;
+      float va = 0.f;
+      if (gm < M && gk < K) va = ta ? A[(size_t)gk * lda + gm] : A[(size_t)gm * lda + gk];
+      As[kk][mm] = va;
+      const int gn = n0 + mm;
+      float vb = 0.f;
+      if (gn < N && gk < K) vb = tb ? B[(size_t)gn * ldb + gk] : B[(size_t)gk * ldb + gn];
+      Bs[kk][mm] = vb;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int kk = 0; kk < 16; ++kk) {
+      float a[4], b[4];
+#pragma unroll
+      for (int i = 0; i < 4; ++i) a[i] = As[kk][ty * 4 + i];
+#pragma unroll
+      for (int j = 0; j < 4; ++j) b[j] = Bs[kk][tx * 4 + j];
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) acc[i][j] += a[i] * b[j];
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const int gm = m0 + ty * 4 + i, gn = n0 + tx * 4 + j;
+      if (gm < M && gn < N) {
+        float* cp = C + (size_t)gm * ldc + gn;
+        *cp = beta == 0.f ? acc[i][j] : beta * *cp + acc[i][j];
+      }
+    }
+}
+
+hipError_t launch_gemm(int M, int N, int K, const float* A, int lda, int ta, const float* B,
+                       int ldb, int tb, float* C, int ldc, float beta, hipStream_t s) {
+  if (M == 0 || N == 0) return hipSuccess;
+  dim3 grid((N + 63) / 64, (M + 63) / 64);
+  k_gemm<<<grid, 256, 0, s>>>(M, N, K, A, lda, ta, B, ldb, tb, C, ldc, beta);
+  return hipGetLastError();
+}
+
+// ------------------------------------------------------------------------------------------
+// In-place Cholesky A = L L^T of a small SPD core (one workgroup, right-looking, lower triangle);
+// status[0] = 1 if a pivot is not positive.
+__global__ void __launch_bounds__(1024) k_cholesky(int n, float* __restrict__ A, int32_t* status) {
+  __shared__ float piv;
+  for (int j = 0; j < n; ++j) {
+    if (threadIdx.x == 0) {
+      const float d = A[(size_t)j * n + j];
+      if (!(d > 0.f)) { status[0] = 1; piv = 0.f; }
+      else { piv = sqrtf(d); A[(size_t)j * n + j] = piv; }
+    }
+    __syncthreads();
+    if (piv == 0.f) return;
+    for (int i = j + 1 + threadIdx.x; i < n; i += blockDim.x) A[(size_t)i * n + j] /= piv;
+    __syncthreads();
+    const int rem = n - j - 1;
+    // trailing update of the lower triangle: A[i][l] -= L[i][j] L[l][j], j < l <= i
+    for (int q = threadIdx.x; q < rem * rem; q += blockDim.x) {
+      const int i = j + 1 + q / rem, l = j + 1 + q % rem;
+      if (l <= i) A[(size_t)i * n + l] -= A[(size_t)i * n + j] * A[(size_t)l * n + j];
+    }
+    __syncthreads();
+  }
+}
+
+// X = L^{-1} (lower triangular), one column per thread by forward substitution.
+__global__ void k_tri_inverse(int n, const float* __restrict__ L, float* __restrict__ X) {
+  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= n) return;
+  for (int i = 0; i < j; ++i) X[(size_t)i * n + j] = 0.f;
+  for (int i = j; i < n; ++i) {
+    float s = (i == j) ? 1.f : 0.f;
+    for (int l = j; l < i; ++l) s -= L[(size_t)i * n + l] * X[(size_t)l * n + j];
+    X[(size_t)i * n + j] = s / L[(size_t)i * n + i];
+  }
+}
+
+__global__ void k_check_hdiag(int64_t n, const float* __restrict__ hdiag,
+                              const uint8_t* __restrict__ is_core, int32_t* status) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n && !is_core[i] && hdiag[i] == 0.f) atomicOr(status, 2);
+}
+
+hipError_t launch_core_inverse(int n, float* work_L, float* work_X, float* out_inv,
+                               int64_t nfull, const float* hdiag, const uint8_t* is_core,
+                               int32_t* status, hipStream_t s) {
+  k_check_hdiag<<<(unsigned)((nfull + 255) / 256), 256, 0, s>>>(nfull, hdiag, is_core, status);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess || n == 0) return e;
+  k_cholesky<<<1, 1024, 0, s>>>(n, work_L, status);
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  k_tri_inverse<<<(n + 63) / 64, 64, 0, s>>>(n, work_L, work_X);
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  // H^{-1} = L^{-T} L^{-1} = X^T X
+  return launch_gemm(n, n, n, work_X, n, 1, work_X, n, 0, out_inv, n, 0.f, s);
+}
+
+// ------------------------------------------------------------------------------------------
+// hdiag_bar[e] = sum_w b[e][w] a[e][w] on retired e (0 on the core); one wave per row
+__global__ void k_rowdot(int64_t n, const float* __restrict__ a, const float* __restrict__ b,
+                         int64_t ld, int64_t nrhs, const uint8_t* __restrict__ is_core,
+                         float* __restrict__ out) {
+  const int64_t row = (int64_t)blockIdx.x * (blockDim.x / PMMF_WAVE) + pmmf_wave();
+  if (row >= n) return;
+  float s = 0.f;
+  if (!is_core[row])
+    for (int64_t w = pmmf_lane(); w < nrhs; w += PMMF_WAVE) s += a[row * ld + w] * b[row * ld + w];
+  s = pmmf_wave_sum_float(s);
+  if (pmmf_lane() == 0) out[row] = s;
+}
+hipError_t launch_rowdot(int64_t n, const float* a, const float* b, int64_t ld, int64_t nrhs,
+                         const uint8_t* is_core, float* out, hipStream_t s) {
+  if (n == 0) return hipSuccess;
+  k_rowdot<<<(unsigned)((n + 3) / 4), 256, 0, s>>>(n, a, b, ld, nrhs, is_core, out);
+  return hipGetLastError();
+}
+
+// theta_bar[sw_idx[q]] = sum over column tiles of (partA + partB)[tile][q]
+__global__ void k_theta_reduce(int t, int ntiles, int64_t stride, const float* __restrict__ pa,
+                               const float* __restrict__ pb, const int32_t* __restrict__ sw_idx,
+                               float* __restrict__ out) {
+  const int q = blockIdx.x * blockDim.x + threadIdx.x;
+  if (q >= t) return;
+  float s = 0.f;
+  for (int y = 0; y < ntiles; ++y) s += pa[(size_t)y * stride + q] + pb[(size_t)y * stride + q];
+  out[sw_idx[q]] = s;
+}
+hipError_t launch_theta_reduce(int t, int ntiles, int64_t stride, const float* pa,
+                               const float* pb, const int32_t* sw_idx, float* out, hipStream_t s) {
+  if (t == 0) return hipSuccess;
+  k_theta_reduce<<<(t + 255) / 256, 256, 0, s>>>(t, ntiles, stride, pa, pb, sw_idx, out);
+  return hipGetLastError();
+}
+
+// core rows: compact buffer of the final active set -> natural rows of the core ids
+__global__ void k_gather_rows(int64_t rows, const float* __restrict__ src, int64_t lds,
+                              const int32_t* __restrict__ idx, float* __restrict__ dst,
+                              int64_t ldd, int64_t ncol, int scatter) {
+  const int64_t r = blockIdx.x;
+  const int64_t gi = idx[r];
+  for (int64_t w = threadIdx.x; w < ncol; w += blockDim.x) {
+    if (scatter) dst[gi * ldd + w] = src[r * lds + w];
+    else dst[r * ldd + w] = src[gi * lds + w];
+  }
+}
+hipError_t launch_gather_rows(int64_t rows, const float* src, int64_t lds, const int32_t* idx,
+                              float* dst, int64_t ldd, int64_t ncol, int scatter, hipStream_t s) {
+  if (rows == 0) return hipSuccess;
+  k_gather_rows<<<(unsigned)rows, 256, 0, s>>>(rows, src, lds, idx, dst, ldd, ncol, scatter);
+  return hipGetLastError();
+}
+
+// (cos, sin) of every Givens rotation from its angle, in the canonical and the sweep logs
+__global__ void k_sync_angles(int64_t R, const float* __restrict__ theta, float* __restrict__ rot_o) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= R) return;
+  float s, c;
+  sincosf(theta[i], &s, &c);
+  rot_o[i * 9 + 0] = c;
+  rot_o[i * 9 + 1] = -s;
+  rot_o[i * 9 + 3] = s;
+  rot_o[i * 9 + 4] = c;
+}
+__global__ void k_sync_sweep(int t, const int32_t* __restrict__ sw_idx,
+                             const float* __restrict__ theta, float* __restrict__ sw_o) {
+  const int q = blockIdx.x * blockDim.x + threadIdx.x;
+  if (q >= t) return;
+  float s, c;
+  sincosf(theta[sw_idx[q]], &s, &c);
+  sw_o[(size_t)q * 4 + 0] = c;
+  sw_o[(size_t)q * 4 + 1] = -s;
+  sw_o[(size_t)q * 4 + 2] = s;
+  sw_o[(size_t)q * 4 + 3] = c;
+}
+hipError_t launch_sync_angles(int64_t R, const float* theta, float* rot_o, hipStream_t s) {
+  if (R == 0) return hipSuccess;
+  k_sync_angles<<<(unsigned)((R + 255) / 256), 256, 0, s>>>(R, theta, rot_o);
+  return hipGetLastError();
+}
+hipError_t launch_sync_sweep(int t, const int32_t* sw_idx, const float* theta, float* sw_o,
+                             hipStream_t s) {
+  if (t == 0) return hipSuccess;
+  k_sync_sweep<<<(t + 255) / 256, 256, 0, s>>>(t, sw_idx, theta, sw_o);
+  return hipGetLastError();
+}
+
+}  // namespace pmmf

@@ -1,0 +1,321 @@
+"""Parity of the HIP path (through the C ABI) with the FP64 oracle.
+
+Decisions (tuples, retired indices, retirement order, core ids) are integers and must match the
+oracle exactly up to the first step whose oracle decision margin is below 1e-5 (relative): there
+both choices are correct, and later steps of that factorization are not comparable entry by entry.
+Floating point: loss to 1e-4 relative; applied vectors and H to 1e-5 relative (FP32 path vs FP64).
+"""
+import math
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+import oracle.pmmf_oracle as om
+import workloads
+from helpers import TIE, first_divergence, oracle_log, rel_err
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1507_04396_amd import _lib
+    _lib.load()  # fail loudly if the HIP library is missing
+
+
+def _say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+def _factor_both(A, params, name):
+    from paper_1507_04396_amd.api import Factorization
+    _say(f"[parity] {name}: oracle")
+    ref = oracle.factor(A, **params)
+    _say(f"[parity] {name}: gpu factor n={A.n} nnz={A.nnz} params={params}")
+    fac = Factorization.from_csr(A, **params)
+    return ref, fac
+
+
+def _check_factor(ref, fac, A, name, loss_rtol=1e-4):
+    inf = fac.info()
+    ex = fac.export()
+    R = len(ref.rotations)
+    assert inf["num_rotations"] == R
+    assert inf["num_stages"] == ref.num_stages
+    # properties that hold for any valid factorization
+    assert abs(inf["trace_h"] - inf["trace_a"]) <= 1e-5 * max(1.0, abs(inf["trace_a"]))
+    fro_gap = inf["fro2_a"] - inf["fro2_h"]
+    assert abs(fro_gap - inf["loss"]) <= 1e-4 * inf["fro2_a"] + 1e-4 * inf["loss"]
+    assert inf["loss_literal"] >= inf["loss"] * (1 - 1e-5)
+    k = fac.k
+    O = ex["rot_o"].astype(np.float64)
+    orth = np.abs(np.einsum("rij,rkj->rik", O, O) - np.eye(k)[None]).max() if R else 0.0
+    assert orth <= 1e-5
+    retired = ex["rot_retired"]
+    assert len(set(retired.tolist())) == R
+    assert sorted(set(retired.tolist()) | set(ex["core_ids"].tolist())) == list(range(A.n))
+    for t in range(R):
+        assert retired[t] in ex["rot_ids"][t]
+    # decisions: identical up to the first near-tie
+    t0 = first_divergence(ex, ref)
+    if t0 is not None:
+        m = ref.rotations[t0].margin
+        _say(f"[parity] {name}: first divergence at rotation {t0}/{R}, oracle margin {m:.3g}")
+        assert m <= TIE, f"decision differs at rotation {t0} with oracle margin {m}"
+    else:
+        _say(f"[parity] {name}: all {R} decisions identical")
+        np.testing.assert_array_equal(ex["core_ids"], ref.core_ids)
+        assert rel_err(ex["hdiag"], ref.hdiag) <= 1e-5
+        assert rel_err(ex["hcore"], ref.hcore) <= 1e-5
+        Oref = np.array([r.O for r in ref.rotations]).reshape(O.shape) if R else O
+        assert np.abs(O - Oref).max() <= 1e-4
+    lrel = abs(inf["loss"] - ref.loss) / max(ref.loss, 1e-300)
+    _say(f"[parity] {name}: loss gpu {inf['loss']:.10g} oracle {ref.loss:.10g} rel {lrel:.2e}")
+    if t0 is None:
+        assert lrel <= loss_rtol
+    return t0
+
+
+SMALL = [
+    ("knn2d_n512", lambda: workloads.make_matrix("knn2d_n512"),
+     workloads.WORKLOADS["knn2d_n512"]["params"]),
+    ("grid24x24_clusters", lambda: workloads.small_grid((24, 24), seed=3),
+     dict(k=2, eta=0.5, core=40, cluster=(32, 96), seed=5)),
+    ("knn2d_n700_k3_clusters", lambda: workloads.knn_points_matrix(700, 2, 8, 0.01, 4),
+     dict(k=3, eta=0.5, core=50, cluster=(40, 120), seed=1)),
+    ("knn3d_n1500_k3", lambda: workloads.knn_points_matrix(1500, 3, 10, 0.01, 6),
+     dict(k=3, eta=0.5, core=64, cluster=(64, 256), seed=2)),
+    ("random_sym_n300_eta03", lambda: workloads.random_symmetric(300, 0.03, 8, diag_shift=3.0),
+     dict(k=2, eta=0.3, core=20, cluster=(20, 60), seed=9)),
+    ("grid_ragged_n257", lambda: workloads.small_grid((1, 257), seed=4),
+     dict(k=2, eta=0.5, core=3, cluster=(5, 17), seed=4)),
+]
+
+
+@pytest.mark.parametrize("name,make,params", SMALL, ids=[c[0] for c in SMALL])
+def test_factor_matches_oracle_small(name, make, params):
+    A = make()
+    ref, fac = _factor_both(A, dict(params), name)
+    t0 = _check_factor(ref, fac, A, name)
+    if name == "knn2d_n512":
+        assert t0 is None, "the plain-MMF workload must match the oracle in every decision"
+
+
+def test_factor_is_deterministic():
+    from paper_1507_04396_amd.api import Factorization
+    A = workloads.small_grid((20, 30), seed=11)
+    prm = dict(k=2, eta=0.5, core=30, cluster=(24, 80), seed=7)
+    _say("[parity] determinism: two factorizations")
+    e1 = Factorization.from_csr(A, **prm).export()
+    e2 = Factorization.from_csr(A, **prm).export()
+    for key in e1:
+        assert np.array_equal(e1[key], e2[key]), key
+
+
+def test_core_equals_n_keeps_A():
+    from paper_1507_04396_amd.api import Factorization
+    A = workloads.random_symmetric(40, 0.2, 3)
+    _say("[parity] core == n")
+    fac = Factorization.from_csr(A, k=2, core=40)
+    ex = fac.export()
+    assert fac.info()["num_stages"] == 0
+    np.testing.assert_array_equal(ex["hcore"], A.to_dense().astype(np.float32))
+    x = torch.randn(40, 3, device="cuda")
+    y = fac.apply(x)
+    np.testing.assert_allclose(y.cpu().numpy(), A.to_dense() @ x.cpu().numpy().astype(np.float64),
+                               rtol=1e-5, atol=1e-5)
+
+
+def test_factor_grid2d_n65536_full_size():
+    """The 256 x 256 grid workload at full size, every decision checked against the oracle."""
+    A = workloads.make_matrix("grid2d_n65536")
+    params = dict(workloads.WORKLOADS["grid2d_n65536"]["params"])
+    ref, fac = _factor_both(A, params, "grid2d_n65536")
+    _check_factor(ref, fac, A, "grid2d_n65536")
+    inf = fac.info()
+    lrel = abs(inf["loss"] - ref.loss) / ref.loss
+    assert lrel <= 1e-3, "a near-tie divergence moved the loss by more than 1e-3"
+
+
+# --------------------------------------------------------------------------- apply / inverse
+
+def _import(ref):
+    from paper_1507_04396_amd.api import Factorization
+    lg = oracle_log(ref)
+    return Factorization.import_log(lg["n"], lg["k"], lg["core"], lg["stage_sizes"],
+                                    lg["stage_clusters"], lg["cluster_sizes"], lg["rot_ids"],
+                                    lg["rot_o"], lg["rot_retired"], lg["hdiag"], lg["core_ids"],
+                                    lg["hcore"])
+
+
+APPLY = [
+    ("grid20x20_k2", lambda: workloads.small_grid((20, 20), sigma=0.5, shift=0.3, seed=2),
+     dict(k=2, core=24, cluster=(16, 64), seed=3), [1, 7, 64, 100]),
+    ("knn2d_n600_k3", lambda: workloads.knn_points_matrix(600, 2, 8, 0.01, 5),
+     dict(k=3, core=40, cluster=(30, 90), seed=4), [5, 33]),
+    ("knn2d_n512_single", lambda: workloads.make_matrix("knn2d_n512"),
+     workloads.WORKLOADS["knn2d_n512"]["params"], [3, 256]),
+]
+
+
+@pytest.mark.parametrize("name,make,params,nrhs_list", APPLY, ids=[c[0] for c in APPLY])
+def test_apply_of_imported_oracle_factorization(name, make, params, nrhs_list):
+    A = make()
+    ref = oracle.factor(A, **params)
+    _say(f"[apply] {name}: import")
+    fac = _import(ref)
+    for nrhs in nrhs_list:
+        X = workloads.gaussian_block(A.n, nrhs, seed=nrhs)
+        _say(f"[apply] {name}: nrhs={nrhs}")
+        y = fac.apply(torch.from_numpy(X).cuda()).cpu().numpy()
+        yref = oracle.apply(ref, X.astype(np.float64))
+        assert rel_err(y, yref) <= 1e-5, (nrhs, rel_err(y, yref))
+
+
+def test_apply_with_padded_leading_dimension():
+    A = workloads.small_grid((12, 12), seed=1)
+    ref = oracle.factor(A, k=2, core=10, cluster=(8, 30), seed=1)
+    fac = _import(ref)
+    Xfull = torch.randn(A.n, 40, device="cuda")
+    X = Xfull[:, :13]
+    from paper_1507_04396_amd import _lib
+    import ctypes
+    Y = torch.full((A.n, 40), 7.0, device="cuda")
+    _say("[apply] padded ld")
+    _lib.check(_lib.load().mmf_apply(fac.handle, Xfull.data_ptr(), Y.data_ptr(), 13, 40,
+                                     ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)))
+    yref = oracle.apply(ref, X.cpu().numpy().astype(np.float64))
+    assert rel_err(Y[:, :13].cpu().numpy(), yref) <= 1e-5
+    assert torch.all(Y[:, 13:] == 7.0)
+
+
+def test_apply_inverse_of_imported_spd_factorization():
+    A = workloads.small_grid((16, 16), sigma=0.5, shift=0.5, seed=6)
+    ref = oracle.factor(A, k=2, core=32, cluster=(16, 48), seed=2)
+    fac = _import(ref)
+    X = workloads.gaussian_block(A.n, 9, seed=3)
+    _say("[apply] inverse")
+    y = fac.apply_inverse(torch.from_numpy(X).cuda()).cpu().numpy()
+    yref = oracle.apply_inverse(ref, X.astype(np.float64))
+    cond = np.linalg.cond(ref.hcore)
+    assert rel_err(y, yref) <= max(1e-5, 1e-7 * cond), (rel_err(y, yref), cond)
+    # A~^-1 A~ x = x through the GPU on both sides
+    z = fac.apply_inverse(fac.apply(torch.from_numpy(X).cuda())).cpu().numpy()
+    assert rel_err(z, X) <= max(1e-5, 1e-7 * cond)
+
+
+def test_apply_inverse_reports_singular_core():
+    A = workloads.small_grid((8, 8), seed=1)   # D - W is singular
+    ref = oracle.factor(A, k=2, core=8, cluster=(8, 24), seed=1)
+    lg = oracle_log(ref)
+    lg["hcore"][:] = 0.0
+    from paper_1507_04396_amd.api import Factorization, MMFError
+    fac = Factorization.import_log(lg["n"], lg["k"], lg["core"], lg["stage_sizes"],
+                                   lg["stage_clusters"], lg["cluster_sizes"], lg["rot_ids"],
+                                   lg["rot_o"], lg["rot_retired"], lg["hdiag"], lg["core_ids"],
+                                   lg["hcore"])
+    with pytest.raises(MMFError) as e:
+        fac.apply_inverse(torch.randn(A.n, 2, device="cuda"))
+    assert e.value.name == "MMF_ESINGULAR"
+
+
+# --------------------------------------------------------------------------- adjoint
+
+def _sub_instance():
+    """Leading 1,024 x 1,024 principal submatrix of the 256 x 256 grid Laplacian (4 grid rows)."""
+    A = workloads.make_matrix("grid2d_n65536").to_scipy()[:1024, :1024]
+    return workloads._csr_from_scipy(A)
+
+
+def test_backward_matches_oracle_adjoint_on_sub_instance():
+    A = _sub_instance()
+    ref = oracle.factor(A, k=2, eta=0.5, core=64, cluster=(256, 512), seed=0)
+    fac = _import(ref)
+    X = workloads.gaussian_block(A.n, 16, seed=1000)
+    Yb = workloads.gaussian_block(A.n, 16, seed=1001)
+    _say("[adjoint] gpu backward on the 1024-row sub-instance")
+    xb, hdb, hcb, thb = fac.backward(torch.from_numpy(X).cuda(), torch.from_numpy(Yb).cuda())
+    rx, rhd, rhc, rth = oracle.backward(ref, X.astype(np.float64), Yb.astype(np.float64))
+    assert rel_err(xb.cpu().numpy(), rx) <= 1e-5
+    assert rel_err(hdb.cpu().numpy(), rhd) <= 1e-5
+    assert rel_err(hcb.cpu().numpy(), rhc) <= 1e-5
+    assert rel_err(thb.cpu().numpy(), rth) <= 1e-4
+
+
+def test_backward_matches_fp64_finite_differences_on_sub_instance():
+    A = _sub_instance()
+    ref = oracle.factor(A, k=2, eta=0.5, core=64, cluster=(256, 512), seed=0)
+    fac = _import(ref)
+    rng = np.random.default_rng(0)
+    X = workloads.gaussian_block(A.n, 4, seed=7)
+    W = workloads.gaussian_block(A.n, 4, seed=8)
+    _say("[adjoint] FD check")
+    xb, hdb, hcb, thb = fac.backward(torch.from_numpy(X).cuda(), torch.from_numpy(W).cuda())
+    thb = thb.cpu().numpy()
+    th = om.angles(ref)
+    h = 1e-6
+
+    def obj(f):
+        return float((W.astype(np.float64) * oracle.apply(f, X.astype(np.float64))).sum())
+
+    for t in rng.choice(len(th), size=24, replace=False):
+        e = np.zeros_like(th)
+        e[t] = h
+        fd = (obj(om.with_angles(ref, th + e)) - obj(om.with_angles(ref, th - e))) / (2 * h)
+        assert abs(fd - thb[t]) <= 1e-3 * max(1.0, abs(fd)), (t, fd, thb[t])
+    d = rng.standard_normal(X.shape)
+    fd = obj_lin = float((W.astype(np.float64) * oracle.apply(ref, d)).sum())
+    assert abs(fd - float((xb.cpu().numpy() * d).sum())) <= 1e-4 * max(1.0, abs(obj_lin))
+
+
+def test_autograd_function_matches_backward():
+    from paper_1507_04396_amd.api import MMFApply
+    A = workloads.small_grid((10, 10), seed=2)
+    ref = oracle.factor(A, k=2, core=12, cluster=(8, 30), seed=3)
+    fac = _import(ref)
+    theta, hd, hc = fac.params()
+    theta.requires_grad_(True)
+    hd.requires_grad_(True)
+    hc.requires_grad_(True)
+    x = torch.randn(A.n, 5, device="cuda", requires_grad=True)
+    _say("[adjoint] autograd")
+    y = MMFApply.apply(x, theta, hd, hc, fac)
+    w = torch.randn_like(y)
+    (y * w).sum().backward()
+    rx, rhd, rhc, rth = oracle.backward(ref, x.detach().cpu().numpy().astype(np.float64),
+                                        w.cpu().numpy().astype(np.float64))
+    assert rel_err(theta.grad.cpu().numpy(), rth) <= 1e-4
+    assert rel_err(x.grad.cpu().numpy(), rx) <= 1e-5
+    assert rel_err(hc.grad.cpu().numpy(), rhc) <= 1e-5
+
+
+# --------------------------------------------------------------------------- errors
+
+def test_factor_reports_input_errors():
+    from paper_1507_04396_amd.api import Factorization, MMFError
+    a = np.diag(np.arange(1.0, 9.0))
+    a[0, 1] = 1.0
+    Ans = workloads.CSR(8, *_csr_arrays(a))
+    _say("[errors] not symmetric")
+    with pytest.raises(MMFError) as e:
+        Factorization.from_csr(Ans, k=2, core=2, check_symmetry=True)
+    assert e.value.name == "MMF_ENOTSYM"
+    b = np.diag(np.arange(1.0, 9.0))
+    b[3, 3] = np.nan
+    Anan = workloads.CSR(8, *_csr_arrays(b))
+    _say("[errors] NaN")
+    with pytest.raises(MMFError) as e:
+        Factorization.from_csr(Anan, k=2, core=2)
+    assert e.value.name == "MMF_ENONFINITE"
+
+
+def _csr_arrays(a):
+    import scipy.sparse as sp
+    m = sp.csr_matrix(a)
+    return m.indptr.astype(np.int64), m.indices.astype(np.int32), m.data.astype(np.float32)
