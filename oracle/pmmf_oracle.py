@@ -38,6 +38,11 @@ Readings of points the paper leaves open (each is also listed in the design note
   R12 Loss: the exact residual ||A - U^T H U||_F^2 equals 2 * sum_e m_e, where m_e is the squared
       mass of row e over the indices still active just after e retires; the literal per-retirement
       sum of 2 off^2_e is an upper bound and is reported beside it.
+  R13 Decision margins (not part of the factorization): the seed-partner score gap relative to
+      sqrt(G_ii) (the Cauchy-Schwarz bound of every score), the k = 2 angle-branch switch as
+      |G_jj - G_ii| / (|G_ii| + |G_jj| + 2|G_ij|), the k = 3 eigengap and trace gap, and the
+      elimination gap relative to max_t G_tt.  A margin below 1e-5 marks a step where two
+      choices are equally correct at working precision.
 """
 from __future__ import annotations
 
@@ -273,15 +278,20 @@ def factor(A, k: int = 2, eta: float = 0.5, core: int = 64, cluster=(0, 0), seed
                 order = cand[np.lexsort((cand, -score[cand]))]  # descending score, then lower j
                 partners = [int(j) for j in order[:kk - 1]]
                 T = [i] + partners
+                # decision margins (R13): each gap is measured against the scale at which the
+                # compared quantities are formed, so a small margin flags a numerical tie
                 margins = []
                 if order.size >= kk:
                     s_in, s_out = score[order[kk - 2]], score[order[kk - 1]]
-                    margins.append((s_in - s_out) / s_in if s_in > 0 else 0.0)
+                    bound = math.sqrt(G[i, i]) if G[i, i] > 0 else 0.0   # Cauchy-Schwarz
+                    margins.append((s_in - s_out) / bound if bound > 0 else 0.0)
                 # rotation that diagonalizes the k x k Gram block (R6)
                 gTT = G[np.ix_(T, T)]
                 if kk == 2:
-                    O, tau = rotation_k2(gTT)
-                    margins.append(tau)
+                    O, _ = rotation_k2(gTT)
+                    a_, b_, d_ = gTT[0, 0], gTT[0, 1], gTT[1, 1]
+                    den = abs(a_) + abs(d_) + 2.0 * abs(b_)
+                    margins.append(abs(d_ - a_) / den if (den > 0 and b_ != 0.0) else math.inf)
                 else:
                     O, tr_margin = rotation_k3(gTT)
                     margins.append(tr_margin)
@@ -298,7 +308,8 @@ def factor(A, k: int = 2, eta: float = 0.5, core: int = 64, cluster=(0, 0), seed
                     if off2[sl] <= off2[e_slot]:
                         e_slot = sl
                 srt = sorted(off2)
-                margins.append((srt[1] - srt[0]) / srt[1] if srt[1] > 0 else 0.0)
+                gscale = max(G[tt, tt] for tt in T)   # off^2 = G_tt - D_tt^2 is formed at this scale
+                margins.append((srt[1] - srt[0]) / gscale if gscale > 0 else 0.0)
                 e = T[e_slot]
                 active[e] = False
                 gid_e = int(S[off + e])
