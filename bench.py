@@ -1,0 +1,202 @@
+"""Benchmark of the pMMF hot path on one MI355X.
+
+A step is one pMMF factorization (mmf_factor: every stage's clustering, cluster Grams, greedy
+rotation search, two-sided rotation and peeling, and the core) of the n = 262,144 kNN Laplacian
+(3-point rotations, clusters of 512-2048, core 1,024).  The headline value is rotations per second
+= (n - core) / wall time per factorization, with the CSR already resident in HBM.
+
+Beside it the same JSON line reports the matrix-free apply and the adjoint (mmf_apply,
+mmf_backward) on the factorization of the 256 x 256 grid Laplacian with 256 right-hand sides, as
+algorithmic GB/s, the per-stage phase split, a roofline entry for the dominant kernel, and the FP64
+oracle timed on the host as a CPU baseline.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+
+
+def log(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+def device_csr(A, torch):
+    rp = torch.from_numpy(A.rowptr).cuda()
+    ci = torch.from_numpy(A.colind).cuda()
+    cv = torch.from_numpy(A.val).cuda()
+    return rp, ci, cv
+
+
+def sweep_rows(stages):
+    """sum over stages of |S_{p-1}| (rows each U-sweep reads and writes)."""
+    return sum(st["size"] for st in stages)
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default="knn3d_n262144")
+    ap.add_argument("--apply-workload", default="grid2d_n65536")
+    ap.add_argument("--nrhs", type=int, default=256)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-sample-n", type=int, default=32768)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "
+              "(the factorization shards by cluster, see the design notes)", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    import workloads
+    from paper_1507_04396_amd import _lib
+    from paper_1507_04396_amd.api import Factorization
+    _lib.load()
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+
+    # ----------------------------------------------------------------- factorization (headline)
+    wl = workloads.WORKLOADS[args.workload]
+    prm = dict(wl["params"])
+    log(f"[bench] generating {args.workload}")
+    A = workloads.make_matrix(args.workload)
+    rp, ci, cv = device_csr(A, torch)
+    torch.cuda.synchronize()
+    R = A.n - prm["core"]
+    for w in range(args.warmup):
+        log(f"[bench] warmup factor {w}")
+        Factorization.factor(rp, ci, cv, **prm).close()
+    torch.cuda.synchronize()
+    times = []
+    fac = None
+    for s in range(args.steps):
+        if fac is not None:
+            fac.close()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        fac = Factorization.factor(rp, ci, cv, **prm)
+        torch.cuda.synchronize()
+        times.append(time.perf_counter() - t0)
+        log(f"[bench] factor step {s}: {times[-1] * 1e3:.2f} ms")
+    info = fac.info()
+    stages = fac.stage_info()
+    ms_per_step = 1e3 * float(np.mean(times))
+    rot_per_s = R / (ms_per_step / 1e3)
+    find_ms = sum(st["find_ms"] for st in stages)
+    gram_ms = sum(st["gram_ms"] for st in stages)
+    rot_ms = sum(st["rotate_ms"] for st in stages)
+    fbytes = sum(st["find_bytes"] for st in stages)
+    fac.close()
+    del rp, ci, cv
+
+    # ----------------------------------------------------------------- apply / adjoint
+    log(f"[bench] factor {args.apply_workload} for apply/backward")
+    B = workloads.make_matrix(args.apply_workload)
+    bprm = dict(workloads.WORKLOADS[args.apply_workload]["params"])
+    fb = Factorization.from_csr(B, **bprm)
+    bstages = fb.stage_info()
+    X = torch.from_numpy(workloads.gaussian_block(B.n, args.nrhs, seed=1000)).cuda()
+    Yb = torch.from_numpy(workloads.gaussian_block(B.n, args.nrhs, seed=1001)).cuda()
+    Y = torch.empty_like(X)
+    fb.apply(X, out=Y)
+    fb.backward(X, Yb)
+    torch.cuda.synchronize()
+    nrep = max(3, args.steps)
+    st_ = torch.cuda.current_stream()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(st_)
+    for _ in range(nrep):
+        fb.apply(X, out=Y)
+    e1.record(st_)
+    torch.cuda.synchronize()
+    apply_ms = e0.elapsed_time(e1) / nrep
+    e0.record(st_)
+    for _ in range(nrep):
+        fb.backward(X, Yb)
+    e1.record(st_)
+    torch.cuda.synchronize()
+    back_ms = e0.elapsed_time(e1) / nrep
+    rows = sweep_rows(bstages)
+    nr, core, kk = args.nrhs, bprm["core"], bprm["k"]
+    Rb = B.n - core
+    log_bytes = Rb * (kk * 4 + kk * kk * 4)
+    usweep = 2 * 4 * nr * rows
+    apply_bytes = 2 * usweep + 2 * log_bytes + core * core * 4 + 2 * core * nr * 4
+    s1 = bstages[0]["size"]
+    back_bytes = (2 * usweep                                   # forward sweeps of x and ybar
+                  + 4 * 4 * nr * rows                          # reverse: read 4 vectors
+                  + 4 * 4 * nr * (rows - s1) + 4 * nr * s1     # reverse writes (xbar at stage 1)
+                  + 3 * log_bytes + 3 * core * core * 4 + Rb * 4 + B.n * 4)
+    apply_gbs = apply_bytes / (apply_ms * 1e-3) / 1e9
+    back_gbs = back_bytes / (back_ms * 1e-3) / 1e9
+    fb.close()
+
+    # ----------------------------------------------------------------- roofline (dominant kernel)
+    find_launches = len(stages)
+    find_gbs = fbytes / (find_ms * 1e-3) / 1e9
+    roofline = {"kernel": "k_find (greedy rotation search, one launch per stage)",
+                "bound": "hbm", "achieved": round(find_gbs, 2), "peak": HBM_PEAK_GBS,
+                "unit": "GB/s", "frac": round(find_gbs / HBM_PEAK_GBS, 5), "traffic": None,
+                "launches": find_launches,
+                "avg_launch_ms": round(find_ms / max(1, find_launches), 4),
+                "algorithmic_bytes_per_launch": int(fbytes / max(1, find_launches))}
+
+    # ----------------------------------------------------------------- CPU baseline (oracle)
+    cpu = None
+    if not args.no_cpu_baseline:
+        import oracle
+        n_s = args.cpu_sample_n
+        log(f"[bench] cpu baseline: FP64 oracle on the same generator at n={n_s}")
+        As = workloads.knn_points_matrix(n_s, wl.get("dim", 3), wl.get("knn", 10),
+                                         wl.get("sigma2", 0.01), 0)
+        t0 = time.perf_counter()
+        ref = oracle.factor(As, **prm)
+        dt = time.perf_counter() - t0
+        cpu = {"value": round(len(ref.rotations) / dt, 2), "unit": "rotations/s", "cores": 1,
+               "kind": "oracle",
+               "sample": f"FP64 oracle factorization of the same kNN generator at n={n_s} "
+                         f"(k={prm['k']}, clusters {prm['cluster']}, core {prm['core']}): "
+                         f"{len(ref.rotations)} rotations in {dt:.1f} s on one host thread"}
+
+    out = {
+        "metric": "rotations/sec + factor time at n=262k; apply+backward GB/s vs roofline",
+        "value": round(rot_per_s, 1), "unit": "rotations/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": round(ms_per_step, 3), "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": f"{args.workload}: pMMF factor of the kNN (k=10) normalized "
+                               f"Laplacian on {A.n} uniform points in [0,1]^3, "
+                               f"{prm['k']}-point rotations, clusters {prm['cluster'][0]}-"
+                               f"{prm['cluster'][1]}, eta {prm['eta']}, core {prm['core']}",
+                   "n": A.n, "nnz": A.nnz, "rotations": R},
+        "factor_ms": round(ms_per_step, 3),
+        "factor_device_ms": round(info["factor_ms"], 3),
+        "factor_phase_ms": {"gram": round(gram_ms, 3), "find": round(find_ms, 3),
+                            "rotate": round(rot_ms, 3)},
+        "factor_loss": info["loss"],
+        "apply": {"workload": f"{args.apply_workload} factorization, {args.nrhs} RHS",
+                  "ms": round(apply_ms, 4), "algorithmic_GBps": round(apply_gbs, 1),
+                  "frac_hbm": round(apply_gbs / HBM_PEAK_GBS, 4)},
+        "backward": {"workload": f"{args.apply_workload} factorization, {args.nrhs} RHS",
+                     "ms": round(back_ms, 4), "algorithmic_GBps": round(back_gbs, 1),
+                     "frac_hbm": round(back_gbs / HBM_PEAK_GBS, 4)},
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+        "stages": [{k2: (round(v, 4) if isinstance(v, float) else v) for k2, v in st.items()}
+                   for st in stages],
+    }
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

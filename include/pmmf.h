@@ -89,6 +89,13 @@ typedef struct {
   int32_t max_depth;     /* deepest chain of dependent rotations inside one cluster             */
   int32_t pad;
   double  loss;          /* residual contributed by this stage's retirements (FP64)             */
+  double  gram_ms;       /* device time of the cluster Gram / diagonal-block kernel             */
+  double  find_ms;       /* device time of the greedy rotation search (all clusters, one launch) */
+  double  rotate_ms;     /* device time of levelling, Qbar extraction and the two-sided rotation
+                            with peeling                                                         */
+  int64_t find_bytes;    /* algorithmic bytes of the greedy search: per rotation in a cluster of
+                            c, the seed's Gram row plus k rows of the Gram and of the diagonal
+                            block read and written, 4 c (1 + 4k)                                 */
 } mmf_stage_info;
 
 /*

@@ -28,7 +28,6 @@ struct FindArgs {
   float* rot_o;              // [R][9] k x k block (row-major, leading dim 3)
   int32_t* rot_ret;          // [R] retired global id
   float* rot_margin;         // [R] smallest relative decision margin
-  float* theta;              // [R] Givens angle (k = 2)
   double* rot_lit;           // [R] 2 off^2 of the retired index (literal loss term)
   float* hdiag;              // [n] retired diagonal of H
   uint8_t* retflag;          // [S] 1 if the position retires in this stage
@@ -43,11 +42,13 @@ hipError_t launch_fill_cluster_of(const int32_t* off, int m, int S, int32_t* cl_
 hipError_t launch_gram(int S, const int64_t* rp, const int32_t* ci, const float* cv,
                        const int32_t* off, const int32_t* cl_of, const int64_t* gbase, float* G,
                        float* D, float* Q, int cmax, hipStream_t s);
-hipError_t launch_find(const FindArgs& a, int m, int cmax, hipStream_t s);
+hipError_t launch_find(const FindArgs& a, int m, int cmax, int nt, hipStream_t s);
+size_t find_lds_bytes(int cmax);
 hipError_t launch_levelize(int m, int k, const int32_t* off, const int32_t* rcnt,
                            const int32_t* roff, int64_t rot0, const int32_t* rot_loc,
                            const float* rot_o, int lvl_stride, int32_t* lvl_ptr, int32_t* depth,
-                           int32_t* sw_loc, float* sw_o, int32_t* sw_idx, int cmax, hipStream_t s);
+                           int32_t* sw_loc, float* sw_o, int32_t* sw_idx, float* theta, int cmax,
+                           hipStream_t s);
 hipError_t launch_transpose_blocks(int m, const int32_t* off, const int64_t* gbase,
                                    const int64_t* tbase, int64_t ntiles, const float* src,
                                    float* dst, hipStream_t s);

@@ -112,71 +112,119 @@ __device__ inline void rot2(double a, double b, double d, double& c, double& s, 
 
 // 3x3: cyclic Jacobi eigendecomposition, eigenvectors in descending eigenvalue order as rows,
 // then the row permutation and signs maximizing trace(O) with O_rr >= 0 (lexicographically
-// smallest permutation on ties).
-__device__ inline void rot3(const double g[3][3], double O[3][3], double& trace_margin,
+// smallest permutation on ties).  Written with static indices only, so every array stays in
+// registers.
+__device__ inline void jacobi_pair(double (&A)[3][3], double (&V)[3][3], int p, int q, bool& rot) {
+  const double apq = A[p][q];
+  if (fabs(apq) <= 1e-18 * (fabs(A[p][p]) + fabs(A[q][q]))) {
+    A[p][q] = A[q][p] = 0.0;
+    return;
+  }
+  rot = true;
+  const double tau = (A[q][q] - A[p][p]) / (2.0 * apq);
+  const double sg = tau >= 0.0 ? 1.0 : -1.0;
+  const double t = sg / (fabs(tau) + sqrt(1.0 + tau * tau));
+  const double c = 1.0 / sqrt(1.0 + t * t);
+  const double s = t * c;
+  // A <- J^T A J with J = [[c, s], [-s, c]] on (p, q); V <- V J
+#pragma unroll
+  for (int r = 0; r < 3; ++r) {
+    const double arp = A[r][p], arq = A[r][q];
+    A[r][p] = c * arp - s * arq;
+    A[r][q] = s * arp + c * arq;
+  }
+#pragma unroll
+  for (int r = 0; r < 3; ++r) {
+    const double apr = A[p][r], aqr = A[q][r];
+    A[p][r] = c * apr - s * aqr;
+    A[q][r] = s * apr + c * aqr;
+  }
+  A[p][q] = A[q][p] = 0.0;
+#pragma unroll
+  for (int r = 0; r < 3; ++r) {
+    const double vrp = V[r][p], vrq = V[r][q];
+    V[r][p] = c * vrp - s * vrq;
+    V[r][q] = s * vrp + c * vrq;
+  }
+}
+
+__device__ inline void rot3(const double (&g)[3][3], double (&O)[3][3], double& trace_margin,
                             double& eig_margin) {
   double A[3][3], V[3][3];
+#pragma unroll
   for (int i = 0; i < 3; ++i)
+#pragma unroll
     for (int j = 0; j < 3; ++j) { A[i][j] = g[i][j]; V[i][j] = (i == j) ? 1.0 : 0.0; }
-  for (int sweep = 0; sweep < 16; ++sweep) {
-    const double offd = A[0][1] * A[0][1] + A[0][2] * A[0][2] + A[1][2] * A[1][2];
-    const double dg = A[0][0] * A[0][0] + A[1][1] * A[1][1] + A[2][2] * A[2][2];
-    if (offd <= 1e-36 * dg || offd == 0.0) break;
-    for (int pq = 0; pq < 3; ++pq) {
-      const int p = pq == 2 ? 1 : 0;
-      const int q = pq == 0 ? 1 : 2;
-      if (A[p][q] == 0.0) continue;
-      const double tau = (A[q][q] - A[p][p]) / (2.0 * A[p][q]);
-      const double sg = tau >= 0.0 ? 1.0 : -1.0;
-      const double t = sg / (fabs(tau) + hypot(1.0, tau));
-      const double c = 1.0 / sqrt(1.0 + t * t);
-      const double s = t * c;
-      // A <- J^T A J with J = [[c, s], [-s, c]] on (p, q); V <- V J
-      for (int r = 0; r < 3; ++r) {
-        const double arp = A[r][p], arq = A[r][q];
-        A[r][p] = c * arp - s * arq;
-        A[r][q] = s * arp + c * arq;
-      }
-      for (int r = 0; r < 3; ++r) {
-        const double apr = A[p][r], aqr = A[q][r];
-        A[p][r] = c * apr - s * aqr;
-        A[q][r] = s * apr + c * aqr;
-      }
-      A[p][q] = A[q][p] = 0.0;
-      for (int r = 0; r < 3; ++r) {
-        const double vrp = V[r][p], vrq = V[r][q];
-        V[r][p] = c * vrp - s * vrq;
-        V[r][q] = s * vrp + c * vrq;
-      }
-    }
+  for (int sweep = 0; sweep < 12; ++sweep) {
+    bool rot = false;
+    jacobi_pair(A, V, 0, 1, rot);
+    jacobi_pair(A, V, 0, 2, rot);
+    jacobi_pair(A, V, 1, 2, rot);
+    if (!rot) break;
   }
-  // descending eigenvalues
-  int idx[3] = {0, 1, 2};
-  double ev[3] = {A[0][0], A[1][1], A[2][2]};
-  for (int i = 0; i < 3; ++i)
-    for (int j = i + 1; j < 3; ++j)
-      if (ev[idx[j]] > ev[idx[i]]) { int t = idx[i]; idx[i] = idx[j]; idx[j] = t; }
-  double base[3][3];  // base[r] = eigenvector of the r-th largest eigenvalue
-  for (int r = 0; r < 3; ++r)
-    for (int j = 0; j < 3; ++j) base[r][j] = V[j][idx[r]];
-  const double emax = fmax(fabs(ev[idx[0]]), fabs(ev[idx[2]]));
-  const double gap = fmin(ev[idx[0]] - ev[idx[1]], ev[idx[1]] - ev[idx[2]]);
-  eig_margin = emax > 0.0 ? gap / emax : 0.0;
-  const int perms[6][3] = {{0, 1, 2}, {0, 2, 1}, {1, 0, 2}, {1, 2, 0}, {2, 0, 1}, {2, 1, 0}};
-  double tr[6];
+  // columns of V sorted by descending eigenvalue (three compare-swaps on scalars)
+  double e0 = A[0][0], e1 = A[1][1], e2 = A[2][2];
+  double b00 = V[0][0], b01 = V[1][0], b02 = V[2][0];   // b0 = eigenvector of e0 (column 0)
+  double b10 = V[0][1], b11 = V[1][1], b12 = V[2][1];
+  double b20 = V[0][2], b21 = V[1][2], b22 = V[2][2];
+#define PMMF_CSWAP(ex, ey, x0, x1, x2, y0, y1, y2)                              \
+  if (ey > ex) {                                                               \
+    double t_ = ex; ex = ey; ey = t_;                                          \
+    t_ = x0; x0 = y0; y0 = t_; t_ = x1; x1 = y1; y1 = t_; t_ = x2; x2 = y2; y2 = t_; \
+  }
+  PMMF_CSWAP(e0, e1, b00, b01, b02, b10, b11, b12)
+  PMMF_CSWAP(e0, e2, b00, b01, b02, b20, b21, b22)
+  PMMF_CSWAP(e1, e2, b10, b11, b12, b20, b21, b22)
+#undef PMMF_CSWAP
+  const double emax = fmax(fabs(e0), fabs(e2));
+  eig_margin = emax > 0.0 ? fmin(e0 - e1, e1 - e2) / emax : 0.0;
+  const double b[3][3] = {{b00, b01, b02}, {b10, b11, b12}, {b20, b21, b22}};
+  // traces of the six row permutations, in lexicographic order
+  const double tr0 = fabs(b00) + fabs(b11) + fabs(b22);  // (0,1,2)
+  const double tr1 = fabs(b00) + fabs(b21) + fabs(b12);  // (0,2,1)
+  const double tr2 = fabs(b10) + fabs(b01) + fabs(b22);  // (1,0,2)
+  const double tr3 = fabs(b10) + fabs(b21) + fabs(b02);  // (1,2,0)
+  const double tr4 = fabs(b20) + fabs(b01) + fabs(b12);  // (2,0,1)
+  const double tr5 = fabs(b20) + fabs(b11) + fabs(b02);  // (2,1,0)
   int best = 0;
-  for (int q = 0; q < 6; ++q) {
-    tr[q] = fabs(base[perms[q][0]][0]) + fabs(base[perms[q][1]][1]) + fabs(base[perms[q][2]][2]);
-    if (tr[q] > tr[best]) best = q;
+  double bt = tr0, second = -1.0;
+#define PMMF_PICK(trq, q)                        \
+  if (trq > bt) { second = bt; bt = trq; best = q; } \
+  else second = fmax(second, trq);
+  PMMF_PICK(tr1, 1)
+  PMMF_PICK(tr2, 2)
+  PMMF_PICK(tr3, 3)
+  PMMF_PICK(tr4, 4)
+  PMMF_PICK(tr5, 5)
+#undef PMMF_PICK
+  trace_margin = bt > 0.0 ? (bt - second) / bt : 0.0;
+  int p0, p1, p2;
+  switch (best) {
+    case 0: p0 = 0; p1 = 1; p2 = 2; break;
+    case 1: p0 = 0; p1 = 2; p2 = 1; break;
+    case 2: p0 = 1; p1 = 0; p2 = 2; break;
+    case 3: p0 = 1; p1 = 2; p2 = 0; break;
+    case 4: p0 = 2; p1 = 0; p2 = 1; break;
+    default: p0 = 2; p1 = 1; p2 = 0; break;
   }
-  double second = -1.0;
-  for (int q = 0; q < 6; ++q)
-    if (q != best) second = fmax(second, tr[q]);
-  trace_margin = tr[best] > 0.0 ? (tr[best] - second) / tr[best] : 0.0;
-  for (int r = 0; r < 3; ++r) {
-    const double* row = base[perms[best][r]];
-    const double sg = row[r] >= 0.0 ? 1.0 : -1.0;
-    for (int j = 0; j < 3; ++j) O[r][j] = sg * row[j];
+  // rows with static indices: select by comparing the permutation entries
+#pragma unroll
+  for (int j = 0; j < 3; ++j) {
+    const double r0 = p0 == 0 ? b[0][j] : (p0 == 1 ? b[1][j] : b[2][j]);
+    const double r1 = p1 == 0 ? b[0][j] : (p1 == 1 ? b[1][j] : b[2][j]);
+    const double r2 = p2 == 0 ? b[0][j] : (p2 == 1 ? b[1][j] : b[2][j]);
+    O[0][j] = r0;
+    O[1][j] = r1;
+    O[2][j] = r2;
+  }
+  const double s0 = O[0][0] >= 0.0 ? 1.0 : -1.0;
+  const double s1 = O[1][1] >= 0.0 ? 1.0 : -1.0;
+  const double s2 = O[2][2] >= 0.0 ? 1.0 : -1.0;
+#pragma unroll
+  for (int j = 0; j < 3; ++j) {
+    O[0][j] *= s0;
+    O[1][j] *= s1;
+    O[2][j] *= s2;
   }
 }
 
@@ -189,13 +237,19 @@ struct Cand {
 __device__ inline bool better(const Cand& a, const Cand& b) {
   return a.s > b.s || (a.s == b.s && a.j < b.j);
 }
-__device__ inline void merge2(Cand& b1, Cand& b2, const Cand& o1, const Cand& o2) {
-  if (better(o1, b1)) {
-    b2 = better(b1, o2) ? b1 : o2;
-    b1 = o1;
-  } else if (better(o1, b2)) {
-    b2 = o1;
-  }
+// top two of {b1, b2, o1, o2} (b1 before b2, o1 before o2), with scalar selects only
+__device__ inline void merge2(Cand& b1, Cand& b2, Cand o1, Cand o2) {
+  const bool o1_first = better(o1, b1);
+  const bool b1_beats_o2 = better(b1, o2);
+  const bool o1_beats_b2 = better(o1, b2);
+  const float n2s = o1_first ? (b1_beats_o2 ? b1.s : o2.s) : (o1_beats_b2 ? o1.s : b2.s);
+  const int n2j = o1_first ? (b1_beats_o2 ? b1.j : o2.j) : (o1_beats_b2 ? o1.j : b2.j);
+  const float n1s = o1_first ? o1.s : b1.s;
+  const int n1j = o1_first ? o1.j : b1.j;
+  b1.s = n1s;
+  b1.j = n1j;
+  b2.s = n2s;
+  b2.j = n2j;
 }
 
 // i-th set bit (0-based rank) of the active bitmask held in LDS; called by one whole wave.
@@ -228,17 +282,24 @@ __device__ inline int select_active(const uint32_t* mask, int nw, int rank) {
   return __shfl(found, src);
 }
 
-template <int NT>
+// The cluster's state lives in HBM as dense c x c arrays: G (Gram), D (diagonal block of the
+// active matrix) and Q (accumulated rotation).  Each thread owns the columns j = tid + q NT
+// (q < PER) and keeps its slice of the rows it needs in registers.  A step has three barriers:
+// after the partner argmax, after the serial FP64 rotation (which also picks the next seed), and
+// after the rotated rows are stored.
+template <int NT, int PER, int K>
 __global__ void __launch_bounds__(NT) k_find(FindArgs A, int cmax) {
   extern __shared__ float lds_f[];
   float* gdiag = lds_f;
   float* ddiag = gdiag + cmax;
   float* rowGi = ddiag + cmax;
   float* rowDi = rowGi + cmax;
-  uint32_t* mask = reinterpret_cast<uint32_t*>(rowDi + cmax);
-  __shared__ Cand red1[NT / PMMF_WAVE], red2[NT / PMMF_WAVE];
-  __shared__ int sh_i, sh_T[3], sh_kk, sh_bad;
-  __shared__ float sh_O[9];
+  int* lgid = reinterpret_cast<int*>(rowDi + cmax);
+  uint32_t* mask = reinterpret_cast<uint32_t*>(lgid + cmax);
+  constexpr int NW = NT / PMMF_WAVE;
+  __shared__ Cand red1[NW], red2[NW];
+  __shared__ int sh_i, sh_e;
+  __shared__ float sh_O[9], sh_gn[9], sh_dn[9];
 
   const int tid = threadIdx.x;
   const int u = A.order[blockIdx.x];
@@ -247,50 +308,54 @@ __global__ void __launch_bounds__(NT) k_find(FindArgs A, int cmax) {
   const int r = A.rcnt[u];
   const int rb = A.roff[u];
   const int nw = (c + 31) / 32;
-  float* G = A.G + A.gbase[u];
-  float* D = A.D + A.gbase[u];
-  float* Q = A.Q + A.gbase[u];
+  constexpr int kk = K;
+  float* __restrict__ G = A.G + A.gbase[u];
+  float* __restrict__ D = A.D + A.gbase[u];
+  float* __restrict__ Q = A.Q + A.gbase[u];
 
   for (int j = tid; j < c; j += NT) {
     gdiag[j] = G[(size_t)j * c + j];
     ddiag[j] = D[(size_t)j * c + j];
+    lgid[j] = A.gid[o + j];
   }
   for (int q = tid; q < nw; q += NT) {
     const int rem = c - q * 32;
     mask[q] = rem >= 32 ? 0xffffffffu : ((1u << rem) - 1u);
   }
   __syncthreads();
+  if (tid < PMMF_WAVE && r > 0) {  // first seed row, uniform over the active set
+    const uint64_t h = pmmf_hash4(A.seed, PMMF_TAG_SEED_ROW, (uint64_t)A.p, (uint64_t)u, 0);
+    const int i0 = select_active(mask, nw, (int)pmmf_mulhi(h, (uint64_t)c));
+    if (tid == 0) sh_i = i0;
+  }
+  __syncthreads();
 
   for (int s = 0; s < r; ++s) {
-    // seed row, uniform over the active set (ascending local order)
-    if (tid < PMMF_WAVE) {
-      const int live = c - s;
-      const uint64_t h = pmmf_hash4(A.seed, PMMF_TAG_SEED_ROW, (uint64_t)A.p, (uint64_t)u,
-                                    (uint64_t)s);
-      const int rank = (int)pmmf_mulhi(h, (uint64_t)live);
-      const int i = select_active(mask, nw, rank);
-      if (tid == 0) {
-        sh_i = i;
-        sh_kk = A.k;  // the host guarantees at least k live indices at every step
+    const int i = sh_i;
+    // the seed's rows of G and D; partner scores |G_ij| / sqrt(G_jj) over the active set,
+    // top (k - 1), lower j on ties
+    float gi[PER], di[PER];
+    Cand b1{-1.f, INT_MAX}, b2{-1.f, INT_MAX};
+#pragma unroll
+    for (int q = 0; q < PER; ++q) {
+      const int j = tid + q * NT;
+      gi[q] = 0.f;
+      di[q] = 0.f;
+      if (j < c) {
+        gi[q] = G[(size_t)i * c + j];
+        di[q] = D[(size_t)i * c + j];
       }
     }
-    __syncthreads();
-    const int i = sh_i;
-    const int kk = sh_kk;
-
-    // partner scores |G_ij| / sqrt(G_jj) over the active set, top (k - 1), lower j on ties
-    Cand b1{-1.f, INT_MAX}, b2{-1.f, INT_MAX};
-    {
-      const float* Gi = G + (size_t)i * c;
-      const float* Di = D + (size_t)i * c;
-      for (int j = tid; j < c; j += NT) {
-        const float g = Gi[j];
-        rowGi[j] = g;
-        rowDi[j] = Di[j];
+#pragma unroll
+    for (int q = 0; q < PER; ++q) {
+      const int j = tid + q * NT;
+      if (j < c) {
+        rowGi[j] = gi[q];
+        rowDi[j] = di[q];
         const bool act = (mask[j >> 5] >> (j & 31)) & 1u;
         if (act && j != i) {
           const float gd = gdiag[j];
-          float sc = gd > 0.f ? fabsf(g) / sqrtf(gd) : 0.f;
+          float sc = gd > 0.f ? fabsf(gi[q]) / sqrtf(gd) : 0.f;
           if (!(sc >= 0.f)) sc = 0.f;  // NaN from an overflowed Gram entry scores 0
           Cand cnd{sc, j};
           if (better(cnd, b1)) { b2 = b1; b1 = cnd; }
@@ -300,180 +365,245 @@ __global__ void __launch_bounds__(NT) k_find(FindArgs A, int cmax) {
     }
     for (int ofs = PMMF_WAVE / 2; ofs > 0; ofs >>= 1) {
       Cand o1{__shfl_xor(b1.s, ofs), __shfl_xor(b1.j, ofs)};
-      Cand o2{__shfl_xor(b2.s, ofs), __shfl_xor(b2.j, ofs)};
-      merge2(b1, b2, o1, o2);
+      if (kk == 3) {
+        Cand o2{__shfl_xor(b2.s, ofs), __shfl_xor(b2.j, ofs)};
+        merge2(b1, b2, o1, o2);
+      } else if (better(o1, b1)) {
+        b1 = o1;
+      }
     }
     if (pmmf_lane() == 0) { red1[pmmf_wave()] = b1; red2[pmmf_wave()] = b2; }
     __syncthreads();
-
-    if (tid == 0) {
-      Cand f1 = red1[0], f2 = red2[0];
-      for (int q = 1; q < NT / PMMF_WAVE; ++q) merge2(f1, f2, red1[q], red2[q]);
-      sh_bad = (f1.j >= c || (kk == 3 && f2.j >= c)) ? 1 : 0;
+    // every thread merges the per-wave winners (no second barrier)
+    Cand f1 = red1[0], f2 = red2[0];
+#pragma unroll
+    for (int q = 1; q < NW; ++q) {
+      if (kk == 3) merge2(f1, f2, red1[q], red2[q]);
+      else if (better(red1[q], f1)) f1 = red1[q];
     }
-    __syncthreads();
-    if (sh_bad) {  // no partner found: impossible with >= k live indices; report and stop
+    if (f1.j >= c || (kk == 3 && f2.j >= c)) {  // impossible with >= k live indices
       if (tid == 0) atomicOr(A.err, 1);
       return;
     }
-    if (tid == 0) {
-      Cand f1 = red1[0], f2 = red2[0];
-      for (int q = 1; q < NT / PMMF_WAVE; ++q) merge2(f1, f2, red1[q], red2[q]);
-      int T[3] = {i, f1.j, f2.j};
-      double margin = 1e300;
-      // k = 2: relative gap between the chosen partner and the runner-up
-      if (kk == 2 && f2.j != INT_MAX)
-        margin = fmin(margin, f1.s > 0.f ? (double)(f1.s - f2.s) / f1.s : 0.0);
-      double g[3][3], d[3][3], O[3][3];
-      for (int a = 0; a < kk; ++a)
-        for (int b = 0; b < kk; ++b) {
-          if (a == b) {
-            g[a][a] = gdiag[T[a]];
-            d[a][a] = ddiag[T[a]];
-          } else if (a == 0 || b == 0) {
-            const int other = a == 0 ? T[b] : T[a];
-            g[a][b] = rowGi[other];
-            d[a][b] = rowDi[other];
-          } else {
-            g[a][b] = G[(size_t)T[a] * c + T[b]];
-            d[a][b] = D[(size_t)T[a] * c + T[b]];
+    const int t0 = i, t1 = f1.j, t2 = kk == 3 ? f2.j : -1;
+
+    // partner rows of G and D, and rows T of Q
+    float g1[PER], g2[PER], d1[PER], d2[PER], q0[PER], q1[PER], q2[PER];
+#pragma unroll
+    for (int q = 0; q < PER; ++q) {
+      const int j = tid + q * NT;
+      g1[q] = g2[q] = d1[q] = d2[q] = q0[q] = q1[q] = q2[q] = 0.f;
+      if (j < c) {
+        g1[q] = G[(size_t)t1 * c + j];
+        d1[q] = D[(size_t)t1 * c + j];
+        q0[q] = Q[(size_t)t0 * c + j];
+        q1[q] = Q[(size_t)t1 * c + j];
+        if (kk == 3) {
+          g2[q] = G[(size_t)t2 * c + j];
+          d2[q] = D[(size_t)t2 * c + j];
+          q2[q] = Q[(size_t)t2 * c + j];
+        }
+      }
+    }
+
+    if (tid < PMMF_WAVE) {
+      if (tid == 0) {
+        double g[3][3] = {}, d[3][3] = {}, O[3][3] = {};
+        g[0][0] = gdiag[t0];
+        d[0][0] = ddiag[t0];
+        g[1][1] = gdiag[t1];
+        d[1][1] = ddiag[t1];
+        if (kk == 3) {
+          g[2][2] = gdiag[t2];
+          d[2][2] = ddiag[t2];
+        }
+        g[0][1] = g[1][0] = rowGi[t1];
+        d[0][1] = d[1][0] = rowDi[t1];
+        if (kk == 3) {
+          g[0][2] = g[2][0] = rowGi[t2];
+          d[0][2] = d[2][0] = rowDi[t2];
+          const double g12 = 0.5 * ((double)G[(size_t)t1 * c + t2] + (double)G[(size_t)t2 * c + t1]);
+          const double d12 = 0.5 * ((double)D[(size_t)t1 * c + t2] + (double)D[(size_t)t2 * c + t1]);
+          g[1][2] = g[2][1] = g12;
+          d[1][2] = d[2][1] = d12;
+        }
+        double margin = 3.0e38;
+        if (kk == 2) {
+          double cc, ss, ta;
+          rot2(g[0][0], g[0][1], g[1][1], cc, ss, ta);
+          O[0][0] = cc; O[0][1] = -ss; O[1][0] = ss; O[1][1] = cc;
+          margin = fmin(margin, ta);
+        } else {
+          double tm, em;
+          rot3(g, O, tm, em);
+          margin = fmin(margin, fmin(tm, em));
+        }
+        // rotated k x k blocks: O g O^T and O d O^T
+        double gn[3][3] = {}, dn[3][3] = {};
+#pragma unroll
+        for (int a = 0; a < kk; ++a)
+#pragma unroll
+          for (int b = 0; b < kk; ++b) {
+            double sg = 0.0, sd = 0.0;
+#pragma unroll
+            for (int x = 0; x < kk; ++x) {
+              double tg = 0.0, td = 0.0;
+#pragma unroll
+              for (int y = 0; y < kk; ++y) { tg += g[x][y] * O[b][y]; td += d[x][y] * O[b][y]; }
+              sg += O[a][x] * tg;
+              sd += O[a][x] * td;
+            }
+            gn[a][b] = sg;
+            dn[a][b] = sd;
           }
+        // eliminate the slot with the smallest off-diagonal norm (ties: later slot)
+        const double f0 = fmax(0.0, gn[0][0] - dn[0][0] * dn[0][0]);
+        const double f1v = fmax(0.0, gn[1][1] - dn[1][1] * dn[1][1]);
+        const double f2v = kk == 3 ? fmax(0.0, gn[2][2] - dn[2][2] * dn[2][2]) : 1e300;
+        int es = f1v <= f0 ? 1 : 0;
+        double fmin_ = es == 1 ? f1v : f0;
+        if (kk == 3 && f2v <= fmin_) { es = 2; fmin_ = f2v; }
+        {
+          // second smallest, for the (diagnostic) elimination margin
+          const double hi01 = fmax(f0, f1v), lo01 = fmin(f0, f1v);
+          const double lo2 = kk == 3 ? (f2v <= lo01 ? lo01 : fmin(hi01, f2v)) : hi01;
+          const double lo1 = fmin(lo01, f2v);
+          margin = fmin(margin, lo2 > 0.0 ? (lo2 - lo1) / lo2 : 0.0);
         }
-      if (kk == 3) {  // symmetrize the partner-partner entry
-        g[1][2] = g[2][1] = 0.5 * (g[1][2] + g[2][1]);
-        d[1][2] = d[2][1] = 0.5 * (d[1][2] + d[2][1]);
-      }
-      if (kk == 2) {
-        double cc, ss, ta;
-        rot2(g[0][0], g[0][1], g[1][1], cc, ss, ta);
-        O[0][0] = cc; O[0][1] = -ss; O[1][0] = ss; O[1][1] = cc;
-        margin = fmin(margin, ta);
-      } else {
-        double tm, em;
-        rot3(g, O, tm, em);
-        margin = fmin(margin, fmin(tm, em));
-      }
-      // rotated k x k blocks: O g O^T and O d O^T
-      double gn[3][3], dn[3][3];
-      for (int a = 0; a < kk; ++a)
-        for (int b = 0; b < kk; ++b) {
-          double sg = 0.0, sd = 0.0;
-          for (int x = 0; x < kk; ++x) {
-            double tg = 0.0, td = 0.0;
-            for (int y = 0; y < kk; ++y) { tg += g[x][y] * O[b][y]; td += d[x][y] * O[b][y]; }
-            sg += O[a][x] * tg;
-            sd += O[a][x] * td;
+        const int e = es == 0 ? t0 : (es == 1 ? t1 : t2);
+        const double dee = es == 0 ? dn[0][0] : (es == 1 ? dn[1][1] : dn[2][2]);
+        const double off2e = fmin_;
+        gdiag[t0] = (float)gn[0][0];
+        ddiag[t0] = (float)dn[0][0];
+        gdiag[t1] = (float)gn[1][1];
+        ddiag[t1] = (float)dn[1][1];
+        if (kk == 3) {
+          gdiag[t2] = (float)gn[2][2];
+          ddiag[t2] = (float)dn[2][2];
+        }
+        mask[e >> 5] &= ~(1u << (e & 31));
+        sh_e = e;
+#pragma unroll
+        for (int a = 0; a < 9; ++a) { sh_O[a] = 0.f; sh_gn[a] = 0.f; sh_dn[a] = 0.f; }
+#pragma unroll
+        for (int a = 0; a < kk; ++a)
+#pragma unroll
+          for (int b = 0; b < kk; ++b) {
+            sh_O[a * 3 + b] = (float)O[a][b];
+            sh_gn[a * 3 + b] = (float)gn[a][b];
+            sh_dn[a * 3 + b] = (float)dn[a][b];
           }
-          gn[a][b] = sg;
-          dn[a][b] = sd;
-        }
-      // eliminate the slot with the smallest off-diagonal norm (ties: later slot)
-      double off2[3];
-      int es = 0;
-      for (int a = 0; a < kk; ++a) {
-        off2[a] = fmax(0.0, gn[a][a] - dn[a][a] * dn[a][a]);
-        if (a > 0 && off2[a] <= off2[es]) es = a;
+        // rotation log (stores only: nothing on this lane waits for them)
+        const int64_t ridx = A.rot0 + rb + s;
+        A.rot_loc[ridx * 3 + 0] = t0;
+        A.rot_loc[ridx * 3 + 1] = t1;
+        A.rot_loc[ridx * 3 + 2] = kk == 3 ? t2 : -1;
+        A.rot_gid[ridx * 3 + 0] = lgid[t0];
+        A.rot_gid[ridx * 3 + 1] = lgid[t1];
+        A.rot_gid[ridx * 3 + 2] = kk == 3 ? lgid[t2] : -1;
+#pragma unroll
+        for (int a = 0; a < 9; ++a) A.rot_o[ridx * 9 + a] = sh_O[a];
+        A.rot_ret[ridx] = lgid[e];
+        A.rot_margin[ridx] = (float)margin;
+        A.rot_lit[ridx] = 2.0 * off2e;
+        A.hdiag[lgid[e]] = (float)dee;
+        A.retflag[o + e] = 1;
       }
-      {
-        double lo1 = 1e300, lo2 = 1e300;
-        for (int a = 0; a < kk; ++a) {
-          if (off2[a] < lo1) { lo2 = lo1; lo1 = off2[a]; }
-          else if (off2[a] < lo2) lo2 = off2[a];
-        }
-        margin = fmin(margin, lo2 > 0.0 ? (lo2 - lo1) / lo2 : 0.0);
+      // next seed row (the whole first wave), from the updated active set
+      if (s + 1 < r) {
+        const uint64_t h = pmmf_hash4(A.seed, PMMF_TAG_SEED_ROW, (uint64_t)A.p, (uint64_t)u,
+                                      (uint64_t)(s + 1));
+        const int nx = select_active(mask, nw, (int)pmmf_mulhi(h, (uint64_t)(c - s - 1)));
+        if (tid == 0) sh_i = nx;
       }
-      const int e = T[es];
-      // log
-      const int64_t ridx = A.rot0 + rb + s;
-      for (int a = 0; a < 3; ++a) {
-        A.rot_loc[ridx * 3 + a] = a < kk ? T[a] : -1;
-        A.rot_gid[ridx * 3 + a] = a < kk ? A.gid[o + T[a]] : -1;
-      }
-      for (int a = 0; a < 9; ++a) A.rot_o[ridx * 9 + a] = 0.f;
-      for (int a = 0; a < kk; ++a)
-        for (int b = 0; b < kk; ++b) A.rot_o[ridx * 9 + a * 3 + b] = (float)O[a][b];
-      A.rot_ret[ridx] = A.gid[o + e];
-      A.rot_margin[ridx] = (float)fmin(margin, 3.0e38);
-      A.rot_lit[ridx] = 2.0 * off2[es];
-      if (kk == 2) A.theta[ridx] = (float)atan2(O[1][0], O[0][0]);
-      A.hdiag[A.gid[o + e]] = (float)dn[es][es];
-      A.retflag[o + e] = 1;
-      for (int a = 0; a < kk; ++a) {
-        gdiag[T[a]] = (float)gn[a][a];
-        ddiag[T[a]] = (float)dn[a][a];
-        for (int b = 0; b < kk; ++b) {
-          G[(size_t)T[a] * c + T[b]] = (float)gn[a][b];
-          D[(size_t)T[a] * c + T[b]] = (float)dn[a][b];
-        }
-      }
-      mask[e >> 5] &= ~(1u << (e & 31));
-      for (int a = 0; a < 3; ++a) sh_T[a] = a < kk ? T[a] : -1;
-      for (int a = 0; a < kk; ++a)
-        for (int b = 0; b < kk; ++b) sh_O[a * 3 + b] = (float)O[a][b];
     }
     __syncthreads();
 
-    // G <- O G O^T, D <- O D O^T on rows/columns T (active columns only: retired columns are
-    // never read again), Q <- O Q on rows T (all columns)
-    {
-      const int t0 = sh_T[0], t1 = sh_T[1], t2 = sh_T[2];
-      float o_[9];
-      for (int a = 0; a < 9; ++a) o_[a] = sh_O[a];
-      for (int j = tid; j < c; j += NT) {
-        if (kk == 2) {
-          const float q0 = Q[(size_t)t0 * c + j], q1 = Q[(size_t)t1 * c + j];
-          Q[(size_t)t0 * c + j] = o_[0] * q0 + o_[1] * q1;
-          Q[(size_t)t1 * c + j] = o_[3] * q0 + o_[4] * q1;
-        } else {
-          const float q0 = Q[(size_t)t0 * c + j], q1 = Q[(size_t)t1 * c + j],
-                      q2 = Q[(size_t)t2 * c + j];
-          Q[(size_t)t0 * c + j] = o_[0] * q0 + o_[1] * q1 + o_[2] * q2;
-          Q[(size_t)t1 * c + j] = o_[3] * q0 + o_[4] * q1 + o_[5] * q2;
-          Q[(size_t)t2 * c + j] = o_[6] * q0 + o_[7] * q1 + o_[8] * q2;
+    // stores: G <- O G O^T and D <- O D O^T on rows/columns T (active columns only: retired
+    // columns are never read again); Q <- O Q on rows T (all columns)
+    float o_[9];
+#pragma unroll
+    for (int a = 0; a < 9; ++a) o_[a] = sh_O[a];
+    const int Tt[3] = {t0, t1, t2};
+    if (tid < kk * kk) {
+      const int a = tid / kk, b = tid % kk;
+      const int ta = a == 0 ? t0 : (a == 1 ? t1 : t2);
+      const int tb = b == 0 ? t0 : (b == 1 ? t1 : t2);
+      G[(size_t)ta * c + tb] = sh_gn[a * 3 + b];
+      D[(size_t)ta * c + tb] = sh_dn[a * 3 + b];
+    }
+#pragma unroll
+    for (int q = 0; q < PER; ++q) {
+      const int j = tid + q * NT;
+      if (j >= c) continue;
+      if (kk == 2) {
+        Q[(size_t)t0 * c + j] = o_[0] * q0[q] + o_[1] * q1[q];
+        Q[(size_t)t1 * c + j] = o_[3] * q0[q] + o_[4] * q1[q];
+      } else {
+        Q[(size_t)t0 * c + j] = o_[0] * q0[q] + o_[1] * q1[q] + o_[2] * q2[q];
+        Q[(size_t)t1 * c + j] = o_[3] * q0[q] + o_[4] * q1[q] + o_[5] * q2[q];
+        Q[(size_t)t2 * c + j] = o_[6] * q0[q] + o_[7] * q1[q] + o_[8] * q2[q];
+      }
+      const bool a_now = (mask[j >> 5] >> (j & 31)) & 1u;
+      if (!a_now || j == t0 || j == t1 || j == t2) continue;
+      const float gv[3] = {gi[q], g1[q], g2[q]};
+      const float dv[3] = {di[q], d1[q], d2[q]};
+#pragma unroll
+      for (int a = 0; a < K; ++a) {
+        float sg = 0.f, sd = 0.f;
+#pragma unroll
+        for (int b = 0; b < K; ++b) {
+          sg += o_[a * 3 + b] * gv[b];
+          sd += o_[a * 3 + b] * dv[b];
         }
-        const bool act = (mask[j >> 5] >> (j & 31)) & 1u;
-        if (!act || j == t0 || j == t1 || j == t2) continue;
-        float gv[3], dv[3], gn[3], dn[3];
-        gv[0] = rowGi[j];
-        dv[0] = rowDi[j];
-        gv[1] = G[(size_t)t1 * c + j];
-        dv[1] = D[(size_t)t1 * c + j];
-        if (kk == 3) {
-          gv[2] = G[(size_t)t2 * c + j];
-          dv[2] = D[(size_t)t2 * c + j];
-        }
-        for (int a = 0; a < kk; ++a) {
-          float sg = 0.f, sd = 0.f;
-          for (int b = 0; b < kk; ++b) {
-            sg += o_[a * 3 + b] * gv[b];
-            sd += o_[a * 3 + b] * dv[b];
-          }
-          gn[a] = sg;
-          dn[a] = sd;
-        }
-        const int Tt[3] = {t0, t1, t2};
-        for (int a = 0; a < kk; ++a) {
-          G[(size_t)Tt[a] * c + j] = gn[a];
-          D[(size_t)Tt[a] * c + j] = dn[a];
-          if (gn[a] != 0.f || gv[a] != 0.f) G[(size_t)j * c + Tt[a]] = gn[a];
-          if (dn[a] != 0.f || dv[a] != 0.f) D[(size_t)j * c + Tt[a]] = dn[a];
-        }
+        G[(size_t)Tt[a] * c + j] = sg;
+        D[(size_t)Tt[a] * c + j] = sd;
+        if (sg != 0.f || gv[a] != 0.f) G[(size_t)j * c + Tt[a]] = sg;
+        if (sd != 0.f || dv[a] != 0.f) D[(size_t)j * c + Tt[a]] = sd;
       }
     }
     __syncthreads();
   }
 }
 
-hipError_t launch_find(const FindArgs& a, int m, int cmax, hipStream_t s) {
-  if (m == 0) return hipSuccess;
-  const size_t lds = (size_t)cmax * 4 * sizeof(float) + (size_t)((cmax + 31) / 32) * 4;
+template <int NT, int PER, int K>
+static hipError_t find_launch(const FindArgs& a, int m, int cmax, size_t lds, hipStream_t s) {
   if (lds > 64 * 1024) {
-    hipError_t e = hipFuncSetAttribute((const void*)k_find<256>,
+    hipError_t e = hipFuncSetAttribute((const void*)&k_find<NT, PER, K>,
                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess) return e;
   }
-  k_find<256><<<m, 256, lds, s>>>(a, cmax);
+  k_find<NT, PER, K><<<m, NT, lds, s>>>(a, cmax);
   return hipGetLastError();
+}
+
+template <int NT, int PER>
+static hipError_t find_launch_k(const FindArgs& a, int m, int cmax, size_t lds, hipStream_t s) {
+  return a.k == 3 ? find_launch<NT, PER, 3>(a, m, cmax, lds, s)
+                  : find_launch<NT, PER, 2>(a, m, cmax, lds, s);
+}
+
+size_t find_lds_bytes(int cmax) {
+  return (size_t)cmax * 4 * sizeof(float) + (size_t)cmax * sizeof(int) +
+         (size_t)((cmax + 31) / 32) * 4;
+}
+
+hipError_t launch_find(const FindArgs& a, int m, int cmax, int nt, hipStream_t s) {
+  if (m == 0) return hipSuccess;
+  const size_t lds = find_lds_bytes(cmax);
+  if (nt == 512) {
+    if (cmax <= 512) return find_launch_k<512, 1>(a, m, cmax, lds, s);
+    if (cmax <= 1024) return find_launch_k<512, 2>(a, m, cmax, lds, s);
+    if (cmax <= 2048) return find_launch_k<512, 4>(a, m, cmax, lds, s);
+    if (cmax <= 4096) return find_launch_k<512, 8>(a, m, cmax, lds, s);
+  } else {
+    if (cmax <= 256) return find_launch_k<256, 1>(a, m, cmax, lds, s);
+    if (cmax <= 512) return find_launch_k<256, 2>(a, m, cmax, lds, s);
+    if (cmax <= 1024) return find_launch_k<256, 4>(a, m, cmax, lds, s);
+    if (cmax <= 2048) return find_launch_k<256, 8>(a, m, cmax, lds, s);
+    if (cmax <= 4096) return find_launch_k<256, 16>(a, m, cmax, lds, s);
+  }
+  return hipErrorInvalidValue;
 }
 
 // ------------------------------------------------------------------------------------------
@@ -485,7 +615,8 @@ __global__ void k_levelize(int k, const int32_t* __restrict__ off, const int32_t
                            const int32_t* __restrict__ rot_loc, const float* __restrict__ rot_o,
                            int lvl_stride, int32_t* __restrict__ lvl_ptr,
                            int32_t* __restrict__ depth_out, int32_t* __restrict__ sw_loc,
-                           float* __restrict__ sw_o, int32_t* __restrict__ sw_idx, int cmax) {
+                           float* __restrict__ sw_o, int32_t* __restrict__ sw_idx,
+                           float* __restrict__ theta, int cmax) {
   extern __shared__ int lds_i[];
   int* last = lds_i;          // [cmax]
   int* lvl = last + cmax;     // [cmax]
@@ -533,13 +664,18 @@ __global__ void k_levelize(int k, const int32_t* __restrict__ off, const int32_t
       for (int b = 0; b < k; ++b) sw_o[(size_t)pos * kk2 + a * k + b] = rot_o[ridx * 9 + a * 3 + b];
     sw_idx[pos] = (int32_t)ridx;
   }
+  if (k == 2)
+    for (int s = 0; s < r; ++s) {
+      const int64_t ridx = rot0 + rb + s;
+      theta[ridx] = (float)atan2((double)rot_o[ridx * 9 + 3], (double)rot_o[ridx * 9 + 0]);
+    }
 }
 
 hipError_t launch_levelize(int m, int k, const int32_t* off, const int32_t* rcnt,
                            const int32_t* roff, int64_t rot0, const int32_t* rot_loc,
                            const float* rot_o, int lvl_stride, int32_t* lvl_ptr, int32_t* depth,
-                           int32_t* sw_loc, float* sw_o, int32_t* sw_idx, int cmax,
-                           hipStream_t s) {
+                           int32_t* sw_loc, float* sw_o, int32_t* sw_idx, float* theta,
+                           int cmax, hipStream_t s) {
   if (m == 0) return hipSuccess;
   const size_t lds = (size_t)(3 * cmax + 2) * sizeof(int);
   if (lds > 64 * 1024) {
@@ -548,7 +684,7 @@ hipError_t launch_levelize(int m, int k, const int32_t* off, const int32_t* rcnt
     if (e != hipSuccess) return e;
   }
   k_levelize<<<m, 64, lds, s>>>(k, off, rcnt, roff, rot0, rot_loc, rot_o, lvl_stride, lvl_ptr,
-                                depth, sw_loc, sw_o, sw_idx, cmax);
+                                depth, sw_loc, sw_o, sw_idx, theta, cmax);
   return hipGetLastError();
 }
 

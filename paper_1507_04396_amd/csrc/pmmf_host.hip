@@ -3,6 +3,7 @@
 
 #include <algorithm>
 #include <cmath>
+#include <cstdlib>
 #include <cstring>
 #include <memory>
 #include <mutex>
@@ -86,6 +87,24 @@ struct StageDev {
   std::vector<int64_t> gbase_h;
   DBuf off, rcnt, roff, order, gbase, next, gid, cl_of, lvl_ptr, depth, sw_loc, sw_o, sw_idx;
   double loss = 0.0;
+  double gram_ms = 0.0, find_ms = 0.0, rotate_ms = 0.0;
+};
+
+// HIP events bracketing the phases of one stage
+struct PhaseEvents {
+  hipEvent_t e[4] = {nullptr, nullptr, nullptr, nullptr};
+  PhaseEvents() {
+    for (auto& x : e) HIPCHK(hipEventCreate(&x));
+  }
+  ~PhaseEvents() {
+    for (auto& x : e)
+      if (x) (void)hipEventDestroy(x);
+  }
+  double ms(int a, int b) const {
+    float v = 0.f;
+    HIPCHK(hipEventElapsedTime(&v, e[a], e[b]));
+    return v;
+  }
 };
 
 struct mmf_plan {
@@ -228,6 +247,15 @@ void build_stage_geometry(StageDev& sd, const SchedStage& sc, int64_t rot_base, 
 }
 
 int round_cmax(int c) { return (c + 63) / 64 * 64; }
+
+// workgroup size of the greedy search (PMMF_FIND_THREADS = 256 or 512; 256 by default)
+int find_threads() {
+  static int nt = [] {
+    const char* e = std::getenv("PMMF_FIND_THREADS");
+    return (e && std::atoi(e) == 512) ? 512 : 256;
+  }();
+  return nt;
+}
 
 pmmf::SweepStage sweep_view(const mmf_plan& h, const StageDev& sd) {
   pmmf::SweepStage v;
@@ -398,6 +426,8 @@ extern "C" int mmf_factor(int64_t n, int64_t nnz, const int64_t* d_rowptr, const
     else HIPCHK(hipMemcpyAsync(sd.gid.p, gid_cur.p, S * sizeof(int32_t), hipMemcpyDeviceToDevice, s));
     HIPCHK(hipMemsetAsync(retflag.p, 0, S, s));
 
+    PhaseEvents pev;
+    HIPCHK(hipEventRecord(pev.e[0], s));
     // cluster Grams, diagonal blocks, identity accumulators
     HIPCHK(pmmf::launch_gram(S, M.rp.as<int64_t>(), M.ci.as<int32_t>(), M.cv.as<float>(),
                              sd.off.as<int32_t>(), sd.cl_of.as<int32_t>(), sd.gbase.as<int64_t>(),
@@ -422,12 +452,13 @@ extern "C" int mmf_factor(int64_t n, int64_t nnz, const int64_t* d_rowptr, const
     fa.rot_o = h->rot_o.as<float>();
     fa.rot_ret = h->rot_ret.as<int32_t>();
     fa.rot_margin = h->rot_margin.as<float>();
-    fa.theta = h->theta.as<float>();
     fa.rot_lit = h->rot_lit.as<double>();
     fa.hdiag = h->hdiag.as<float>();
     fa.retflag = retflag.as<uint8_t>();
     fa.err = overflow.as<int32_t>() + 1;
-    HIPCHK(pmmf::launch_find(fa, sd.m, cm, s));
+    HIPCHK(hipEventRecord(pev.e[1], s));
+    HIPCHK(pmmf::launch_find(fa, sd.m, cm, find_threads(), s));
+    HIPCHK(hipEventRecord(pev.e[2], s));
     // rotation levels and the sweep log
     sd.sw_loc.ensure(sd.t * h->k * sizeof(int32_t));
     sd.sw_o.ensure(sd.t * h->k * h->k * sizeof(float));
@@ -435,7 +466,8 @@ extern "C" int mmf_factor(int64_t n, int64_t nnz, const int64_t* d_rowptr, const
                                  sd.roff.as<int32_t>(), rot_base, h->rot_loc.as<int32_t>(),
                                  h->rot_o.as<float>(), sd.lvl_stride, sd.lvl_ptr.as<int32_t>(),
                                  sd.depth.as<int32_t>(), sd.sw_loc.as<int32_t>(),
-                                 sd.sw_o.as<float>(), sd.sw_idx.as<int32_t>(), cm, s));
+                                 sd.sw_o.as<float>(), sd.sw_idx.as<int32_t>(),
+                                 h->theta.as<float>(), cm, s));
     // survivors' positions in the next stage
     HIPCHK(pmmf::launch_keep_flags(S, retflag.as<uint8_t>(), keep.as<int32_t>(), s));
     HIPCHK(pmmf::launch_scan(keep.as<int32_t>(), scan.as<int64_t>(), S, scan_tmp.as<int64_t>(), s));
@@ -513,7 +545,12 @@ extern "C" int mmf_factor(int64_t n, int64_t nnz, const int64_t* d_rowptr, const
                              sd.off.as<int32_t>(), sd.cl_of.as<int32_t>(), sd.next.as<int32_t>(),
                              nullptr, M2.rp.as<int64_t>(), M2.ci.as<int32_t>(), M2.cv.as<float>(),
                              loss_row.as<double>(), overflow.as<int32_t>(), cm, s));
+    HIPCHK(hipEventRecord(pev.e[3], s));
     HIPCHK(pmmf::launch_sum_double(loss_row.as<double>(), S, stage_loss.as<double>() + pi, s));
+    HIPCHK(hipEventSynchronize(pev.e[3]));
+    sd.gram_ms = pev.ms(0, 1);
+    sd.find_ms = pev.ms(1, 2);
+    sd.rotate_ms = pev.ms(2, 3);
     M.rp.swap_with(M2.rp);
     M.ci.swap_with(M2.ci);
     M.cv.swap_with(M2.cv);
@@ -855,6 +892,14 @@ extern "C" int mmf_get_stage_info(mmf_handle hh, int32_t stage, mmf_stage_info* 
   out->max_depth = sd.depth_max;
   out->pad = 0;
   out->loss = sd.loss;
+  out->gram_ms = sd.gram_ms;
+  out->find_ms = sd.find_ms;
+  out->rotate_ms = sd.rotate_ms;
+  out->find_bytes = 0;
+  for (int u = 0; u < sd.m; ++u) {
+    const int64_t c = sd.off_h[u + 1] - sd.off_h[u];
+    out->find_bytes += (int64_t)sd.rcnt_h[u] * 4 * c * (1 + 4 * h.k);
+  }
   return MMF_OK;
   ABI_END
 }
@@ -1006,7 +1051,7 @@ extern "C" int mmf_import(int64_t n, int32_t k, int64_t core_size, int32_t num_s
                                  h->rot_o.as<float>(), sd.lvl_stride, sd.lvl_ptr.as<int32_t>(),
                                  sd.depth.as<int32_t>(), sd.sw_loc.as<int32_t>(),
                                  sd.sw_o.as<float>(), sd.sw_idx.as<int32_t>(),
-                                 round_cmax(sd.cmax), s));
+                                 h->theta.as<float>(), round_cmax(sd.cmax), s));
   }
   std::vector<float> hd(hdiag, hdiag + n), hc(hcore, hcore + core_size * core_size);
   std::vector<int32_t> cid(core_ids, core_ids + core_size);

@@ -88,18 +88,12 @@ def knn_normalized_laplacian(points: np.ndarray, knn: int, sigma2: float) -> CSR
     n = points.shape[0]
     tree = scipy.spatial.cKDTree(points)
     dist, idx = tree.query(points, k=knn + 1)
-    rows, cols, d2 = [], [], []
-    for r in range(n):
-        for c in range(knn + 1):
-            j = int(idx[r, c])
-            if j == r:
-                continue
-            rows.append(r)
-            cols.append(j)
-            d2.append(float(dist[r, c]) ** 2)
-    rows = np.asarray(rows)
-    cols = np.asarray(cols)
-    w = np.exp(-np.asarray(d2) / sigma2)
+    rows = np.repeat(np.arange(n), knn + 1)
+    cols = idx.reshape(-1)
+    d2 = dist.reshape(-1).astype(np.float64) ** 2
+    keep = cols != rows
+    rows, cols, d2 = rows[keep], cols[keep], d2[keep]
+    w = np.exp(-d2 / sigma2)
     W = sp.coo_matrix((w, (rows, cols)), shape=(n, n)).tocsr()
     W = W.maximum(W.T)  # union symmetrization; both directions carry the same weight
     deg = np.asarray(W.sum(axis=1)).ravel()
