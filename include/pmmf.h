@@ -201,6 +201,33 @@ int mmf_sync_angles(mmf_handle h, void* stream);
 int mmf_set_params(mmf_handle h, const float* d_theta, const float* d_hdiag, const float* d_hcore,
                    void* stream);
 
+/* Result of mmf_pcg. */
+typedef struct {
+  int32_t iterations;        /* inner PCG iterations (all columns advance together)            */
+  int32_t refinements;       /* FP64 residual corrections performed                            */
+  int32_t converged;         /* columns with ||b_j - A x_j|| / ||b_j|| <= tol                  */
+  int32_t pad;
+  double  max_rel_residual;  /* max over columns of the FP64 relative residual at return        */
+  double  solve_ms;          /* device time of the solve                                       */
+} mmf_pcg_info;
+
+/*
+ * mmf_pcg — solve A X = B by conjugate gradients preconditioned with the factorization's inverse
+ * A~^{-1} = U^T H^{-1} U (Sec. 4: pMMF as a preconditioner), all columns in lockstep.  Inner
+ * iterations run in FP32 (CSR SpMM, mmf_apply_inverse, per-column dot products accumulated in FP64)
+ * on A d = r / ||r|| until every active column's residual drops by `inner_reduction`; an outer loop
+ * recomputes r = B - A X in FP64 and adds the correction to the FP64 solution, until
+ * ||b_j - A x_j|| / ||b_j|| <= tol for every column or max_iter inner iterations in total.
+ *   h       : factorization of (an approximation of) A, dimension n
+ *   A       : CSR (device), the matrix of the system (the one that was factored)
+ *   d_b     : [n][nrhs] float32 right-hand sides (device);  d_x : [n][nrhs] float64 solution (device)
+ * Synchronizes `stream` once per inner iteration.  Errors: MMF_EINVAL, MMF_ESTATE, MMF_ENOMEM,
+ * MMF_ESINGULAR (H not invertible), MMF_EDEVICE.
+ */
+int mmf_pcg(mmf_handle h, int64_t n, const int64_t* d_rowptr, const int32_t* d_colind,
+            const float* d_val, const float* d_b, double* d_x, int64_t nrhs, double tol,
+            int32_t max_iter, double inner_reduction, void* stream, mmf_pcg_info* out);
+
 /* Free the handle and all device memory it owns (synchronizes its stream). */
 int mmf_destroy(mmf_handle h);
 

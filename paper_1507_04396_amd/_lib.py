@@ -39,6 +39,12 @@ class mmf_info(ctypes.Structure):
                 ("trace_h", ctypes.c_double), ("factor_ms", ctypes.c_double)]
 
 
+class mmf_pcg_info(ctypes.Structure):
+    _fields_ = [("iterations", ctypes.c_int32), ("refinements", ctypes.c_int32),
+                ("converged", ctypes.c_int32), ("pad", ctypes.c_int32),
+                ("max_rel_residual", ctypes.c_double), ("solve_ms", ctypes.c_double)]
+
+
 class mmf_stage_info(ctypes.Structure):
     _fields_ = [("size", ctypes.c_int64), ("rotations", ctypes.c_int64),
                 ("clusters", ctypes.c_int64), ("nnz", ctypes.c_int64),
@@ -65,6 +71,8 @@ SIGNATURES = {
     "mmf_param_ptrs": [H, P, P, P],
     "mmf_sync_angles": [H, P],
     "mmf_set_params": [H, P, P, P, P],
+    "mmf_pcg": [H, I64, P, P, P, P, P, I64, ctypes.c_double, I32, ctypes.c_double, P,
+                ctypes.POINTER(mmf_pcg_info)],
     "mmf_destroy": [H],
     "mmf_last_error": [],
 }

@@ -183,6 +183,26 @@ class Factorization:
                                        _ptr(hcb), _ptr(thb), nrhs, ld, _stream(stream)))
         return xb, hdb, hcb, (thb[:R] if thb is not None else None)
 
+    def pcg(self, rowptr: torch.Tensor, colind: torch.Tensor, val: torch.Tensor,
+            b: torch.Tensor, tol: float = 1e-6, max_iter: int = 2000,
+            inner_reduction: float = 1e-3, stream=None):
+        """mmf_pcg: solve A X = B with the factorization's inverse as preconditioner.
+
+        Returns (X float64 [n][nrhs], info dict)."""
+        _require_device(rowptr, torch.int64, "rowptr")
+        _require_device(colind, torch.int32, "colind")
+        _require_device(val, torch.float32, "val")
+        b2 = b.contiguous()
+        if b2.dim() == 1:
+            b2 = b2[:, None]
+        _require_device(b2, torch.float32, "b")
+        x = torch.empty(b2.shape, dtype=torch.float64, device=b2.device)
+        inf = _lib.mmf_pcg_info()
+        check(_lib.load().mmf_pcg(self.handle, rowptr.numel() - 1, _ptr(rowptr), _ptr(colind),
+                                  _ptr(val), _ptr(b2), _ptr(x), b2.shape[1], tol, max_iter,
+                                  inner_reduction, _stream(stream), ctypes.byref(inf)))
+        return x, {f: getattr(inf, f) for f, _ in _lib.mmf_pcg_info._fields_ if f != "pad"}
+
     def set_params(self, theta=None, hdiag=None, hcore=None, stream=None) -> None:
         for t, nm in ((theta, "theta"), (hdiag, "hdiag"), (hcore, "hcore")):
             if t is not None:

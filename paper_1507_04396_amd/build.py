@@ -8,7 +8,7 @@ import sys
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
-SOURCES = ["pmmf_host.hip", "factor_kernels.hip", "sweep_kernels.hip"]
+SOURCES = ["pmmf_host.hip", "factor_kernels.hip", "sweep_kernels.hip", "pcg.hip"]
 LIB = os.path.join(HERE, "libpmmf.so")
 
 

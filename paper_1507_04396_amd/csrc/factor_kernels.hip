@@ -61,12 +61,42 @@ __global__ void __launch_bounds__(256) k_gram(int S, const int64_t* __restrict__
   const int la = a - o;
   for (int j = lane; j < c; j += PMMF_WAVE) acc[j] = 0.f;
   const int64_t a0 = rp[a], a1 = rp[a + 1];
-  for (int64_t kk = a0; kk < a1; ++kk) {
-    const int r = ci[kk];
-    const float war = cv[kk];
-    const int64_t lb = lower_bound_i32(ci, rp[r], rp[r + 1], o);
-    const int64_t ub = lower_bound_i32(ci, lb, rp[r + 1], o + c);
-    for (int64_t t = lb + lane; t < ub; t += PMMF_WAVE) acc[ci[t] - o] += war * cv[t];
+  for (int64_t kb = a0; kb < a1; kb += PMMF_WAVE) {
+    // each lane locates the cluster-u segment of one row r = ci[kb + lane]
+    const int nb = (int)min<int64_t>(PMMF_WAVE, a1 - kb);
+    int64_t lb = 0, ub = 0;
+    float w = 0.f;
+    if (lane < nb) {
+      const int r = ci[kb + lane];
+      w = cv[kb + lane];
+      const int64_t r1 = rp[r + 1];
+      lb = lower_bound_i32(ci, rp[r], r1, o);
+      ub = lower_bound_i32(ci, lb, r1, o + c);
+    }
+    // accumulate the segments in ascending r; the first 64 entries of four segments are
+    // loaded together so their latencies overlap (the summation order is unchanged)
+    for (int t = 0; t < nb; t += 4) {
+      int64_t sl[4], su[4];
+      float sw[4], pv[4];
+      int pc[4];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int tt = min(t + q, nb - 1);
+        sl[q] = __shfl(lb, tt);
+        su[q] = __shfl(ub, tt);
+        sw[q] = __shfl(w, tt);
+        if (t + q >= nb) su[q] = sl[q];
+        const int64_t e = sl[q] + lane;
+        pc[q] = e < su[q] ? ci[e] : 0;
+        pv[q] = e < su[q] ? cv[e] : 0.f;
+      }
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        if (sl[q] + lane < su[q]) acc[pc[q] - o] += sw[q] * pv[q];
+        for (int64_t e = sl[q] + PMMF_WAVE + lane; e < su[q]; e += PMMF_WAVE)
+          acc[ci[e] - o] += sw[q] * cv[e];
+      }
+    }
   }
   const size_t base = (size_t)gbase[u] + (size_t)la * c;
   for (int j = lane; j < c; j += PMMF_WAVE) {
@@ -618,57 +648,57 @@ __global__ void k_levelize(int k, const int32_t* __restrict__ off, const int32_t
                            float* __restrict__ sw_o, int32_t* __restrict__ sw_idx,
                            float* __restrict__ theta, int cmax) {
   extern __shared__ int lds_i[];
-  int* last = lds_i;          // [cmax]
-  int* lvl = last + cmax;     // [cmax]
-  int* start = lvl + cmax;    // [cmax + 2]
+  int* last = lds_i;            // [cmax]  latest level touching each index
+  int* lvl = last + cmax;       // [cmax]  level of each rotation, then its slot in level order
+  int* start = lvl + cmax;      // [cmax + 2]
+  int* ids = start + cmax + 2;  // [cmax][3] the cluster's rotation ids, staged from HBM
+  __shared__ int sh_depth;
   const int u = blockIdx.x;
   const int c = off[u + 1] - off[u];
   const int r = rcnt[u];
   const int rb = roff[u];
   for (int j = threadIdx.x; j < c; j += blockDim.x) last[j] = 0;
   for (int j = threadIdx.x; j < c + 2; j += blockDim.x) start[j] = 0;
+  for (int q = threadIdx.x; q < r * 3; q += blockDim.x) ids[q] = rot_loc[(rot0 + rb) * 3 + q];
   __syncthreads();
-  if (threadIdx.x != 0) return;
-  int depth = 0;
-  for (int s = 0; s < r; ++s) {
-    const int64_t ridx = rot0 + rb + s;
-    int L = 0;
-    for (int a = 0; a < 3; ++a) {
-      const int id = rot_loc[ridx * 3 + a];
-      if (id >= 0) L = max(L, last[id]);
+  if (threadIdx.x == 0) {
+    int depth = 0;
+    for (int s = 0; s < r; ++s) {
+      const int i0 = ids[s * 3], i1 = ids[s * 3 + 1], i2 = ids[s * 3 + 2];
+      int L = max(last[i0], last[i1]);
+      if (i2 >= 0) L = max(L, last[i2]);
+      L += 1;
+      last[i0] = L;
+      last[i1] = L;
+      if (i2 >= 0) last[i2] = L;
+      lvl[s] = L;
+      start[L] += 1;
+      depth = max(depth, L);
     }
-    L += 1;
-    for (int a = 0; a < 3; ++a) {
-      const int id = rot_loc[ridx * 3 + a];
-      if (id >= 0) last[id] = L;
+    int acc = 0;
+    for (int l = 1; l <= depth; ++l) {
+      const int cnt = start[l];
+      start[l] = acc;
+      lvl_ptr[(size_t)u * lvl_stride + (l - 1)] = rb + acc;
+      acc += cnt;
     }
-    lvl[s] = L;
-    start[L] += 1;
-    depth = max(depth, L);
+    lvl_ptr[(size_t)u * lvl_stride + depth] = rb + r;
+    depth_out[u] = depth;
+    for (int s = 0; s < r; ++s) lvl[s] = start[lvl[s]]++;   // slot of rotation s in level order
+    sh_depth = depth;
   }
-  int acc = 0;
-  for (int l = 1; l <= depth; ++l) {
-    const int cnt = start[l];
-    start[l] = acc;
-    lvl_ptr[(size_t)u * lvl_stride + (l - 1)] = rb + acc;
-    acc += cnt;
-  }
-  lvl_ptr[(size_t)u * lvl_stride + depth] = rb + r;
-  depth_out[u] = depth;
+  __syncthreads();
+  // write the sweep log in level order (all lanes)
   const int kk2 = k * k;
-  for (int s = 0; s < r; ++s) {
+  for (int s = threadIdx.x; s < r; s += blockDim.x) {
     const int64_t ridx = rot0 + rb + s;
-    const int pos = rb + start[lvl[s]]++;
-    for (int a = 0; a < k; ++a) sw_loc[(size_t)pos * k + a] = rot_loc[ridx * 3 + a];
+    const int pos = rb + lvl[s];
+    for (int a = 0; a < k; ++a) sw_loc[(size_t)pos * k + a] = ids[s * 3 + a];
     for (int a = 0; a < k; ++a)
       for (int b = 0; b < k; ++b) sw_o[(size_t)pos * kk2 + a * k + b] = rot_o[ridx * 9 + a * 3 + b];
     sw_idx[pos] = (int32_t)ridx;
+    if (k == 2) theta[ridx] = (float)atan2((double)rot_o[ridx * 9 + 3], (double)rot_o[ridx * 9 + 0]);
   }
-  if (k == 2)
-    for (int s = 0; s < r; ++s) {
-      const int64_t ridx = rot0 + rb + s;
-      theta[ridx] = (float)atan2((double)rot_o[ridx * 9 + 3], (double)rot_o[ridx * 9 + 0]);
-    }
 }
 
 hipError_t launch_levelize(int m, int k, const int32_t* off, const int32_t* rcnt,
@@ -677,7 +707,7 @@ hipError_t launch_levelize(int m, int k, const int32_t* off, const int32_t* rcnt
                            int32_t* sw_loc, float* sw_o, int32_t* sw_idx, float* theta,
                            int cmax, hipStream_t s) {
   if (m == 0) return hipSuccess;
-  const size_t lds = (size_t)(3 * cmax + 2) * sizeof(int);
+  const size_t lds = (size_t)(6 * cmax + 2) * sizeof(int);
   if (lds > 64 * 1024) {
     hipError_t e = hipFuncSetAttribute((const void*)k_levelize,
                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
@@ -819,15 +849,48 @@ __global__ void __launch_bounds__(256) k_right(int S, int fill, const int64_t* _
       if (n < PMMF_WAVE) break;
     }
     int bmin = INT_MAX, bmax = -1;
-    for (int64_t t = k; t < kend; ++t) {
-      const int y = ci[t];
-      const float mv = cv[t];
-      const int64_t q0 = qrp[y], q1 = qrp[y + 1];
-      for (int64_t e = q0 + lane; e < q1; e += PMMF_WAVE) {
-        const int b = qci[e] - ov;
-        acc[b] += mv * qcv[e];
-        bmin = min(bmin, b);
-        bmax = max(bmax, b);
+    for (int64_t kb = k; kb < kend; kb += PMMF_WAVE) {
+      // lane-parallel lookup of the Qbar^T rows of up to 64 entries y of the run
+      const int nb = (int)min<int64_t>(PMMF_WAVE, kend - kb);
+      int64_t q0 = 0, q1 = 0;
+      float mv = 0.f;
+      if (lane < nb) {
+        const int y = ci[kb + lane];
+        mv = cv[kb + lane];
+        q0 = qrp[y];
+        q1 = qrp[y + 1];
+      }
+      // expand them in ascending entry order, first chunks of four rows loaded together
+      for (int t = 0; t < nb; t += 4) {
+        int64_t sl[4], su[4];
+        float sw[4], pv[4];
+        int pc[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          const int tt = min(t + q, nb - 1);
+          sl[q] = __shfl(q0, tt);
+          su[q] = __shfl(q1, tt);
+          sw[q] = __shfl(mv, tt);
+          if (t + q >= nb) su[q] = sl[q];
+          const int64_t e = sl[q] + lane;
+          pc[q] = e < su[q] ? qci[e] : ov;
+          pv[q] = e < su[q] ? qcv[e] : 0.f;
+        }
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          if (sl[q] + lane < su[q]) {
+            const int b = pc[q] - ov;
+            acc[b] += sw[q] * pv[q];
+            bmin = min(bmin, b);
+            bmax = max(bmax, b);
+          }
+          for (int64_t e = sl[q] + PMMF_WAVE + lane; e < su[q]; e += PMMF_WAVE) {
+            const int b = qci[e] - ov;
+            acc[b] += sw[q] * qcv[e];
+            bmin = min(bmin, b);
+            bmax = max(bmax, b);
+          }
+        }
       }
     }
     bmin = pmmf_wave_min_int(bmin);
@@ -870,6 +933,7 @@ hipError_t launch_right(int S, int fill, const int64_t* rp, const int32_t* ci, c
 //     2 sum_{b survives} A_p[a,b]^2 + sum_{b retired, b != a} A_p[a,b]^2
 // to the exact residual (FP64), which totals 2 sum_e m_e over the stage's retirements.
 constexpr int LEFT_QMAX = 512;
+constexpr int LEFT_PER_LIST = 28;  // LDS bytes per list: cur, end (int64), next column, its cluster, weight
 
 __global__ void __launch_bounds__(256) k_left(int S, int fill, const int64_t* __restrict__ qrp,
                                               const int32_t* __restrict__ qci,
@@ -889,13 +953,14 @@ __global__ void __launch_bounds__(256) k_left(int S, int fill, const int64_t* __
   extern __shared__ float lds_f[];
   const int wpb = blockDim.x / PMMF_WAVE;
   const int w = pmmf_wave(), lane = pmmf_lane();
-  // per wave: acc[cmax] floats, then cur[QMAX], en[QMAX] (int64), qv[QMAX] (float)
   char* base = reinterpret_cast<char*>(lds_f) +
-               (size_t)w * ((size_t)cmax * 4 + (size_t)LEFT_QMAX * 20);
+               (size_t)w * ((size_t)cmax * 4 + (size_t)LEFT_QMAX * LEFT_PER_LIST);
   float* acc = reinterpret_cast<float*>(base);
   int64_t* cur = reinterpret_cast<int64_t*>(base + (size_t)cmax * 4);
   int64_t* en = cur + LEFT_QMAX;
-  float* qv = reinterpret_cast<float*>(en + LEFT_QMAX);
+  int* ncol = reinterpret_cast<int*>(en + LEFT_QMAX);   // column at cur, INT_MAX when done
+  int* ncl = ncol + LEFT_QMAX;                          // its cluster
+  float* qv = reinterpret_cast<float*>(ncl + LEFT_QMAX);
   const int a = blockIdx.x * wpb + w;
   if (a >= S) return;
   const int64_t q0 = qrp[a];
@@ -911,9 +976,13 @@ __global__ void __launch_bounds__(256) k_left(int S, int fill, const int64_t* __
   for (int j = lane; j < cmax; j += PMMF_WAVE) acc[j] = 0.f;
   for (int li = lane; li < nq; li += PMMF_WAVE) {
     const int x = qci[q0 + li];
-    cur[li] = wrp[x];
-    en[li] = wrp[x + 1];
+    const int64_t c0 = wrp[x], c1 = wrp[x + 1];
+    cur[li] = c0;
+    en[li] = c1;
     qv[li] = qcv[q0 + li];
+    const int col = c0 < c1 ? wci[c0] : INT_MAX;
+    ncol[li] = col;
+    ncl[li] = col < INT_MAX ? cl_of[col] : INT_MAX;
   }
   const int na = next[a];
   const bool surv = na >= 0;
@@ -921,14 +990,15 @@ __global__ void __launch_bounds__(256) k_left(int S, int fill, const int64_t* __
   double loss = 0.0;
   while (true) {
     int vmin = INT_MAX;
-    for (int li = lane; li < nq; li += PMMF_WAVE)
-      if (cur[li] < en[li]) vmin = min(vmin, cl_of[wci[cur[li]]]);
+    for (int li = lane; li < nq; li += PMMF_WAVE) vmin = min(vmin, ncl[li]);
     vmin = pmmf_wave_min_int(vmin);
     if (vmin == INT_MAX) break;
     const int ov = off[vmin];
     const int lim = off[vmin + 1];
     int bmin = INT_MAX, bmax = -1;
+    // lists with entries in this cluster, in ascending list order (deterministic sums)
     for (int li = 0; li < nq; ++li) {
+      if (ncl[li] != vmin) continue;
       int64_t cu = cur[li];
       const int64_t e = en[li];
       const float qq = qv[li];
@@ -936,18 +1006,31 @@ __global__ void __launch_bounds__(256) k_left(int S, int fill, const int64_t* __
         const int64_t idx = cu + lane;
         const int col = idx < e ? wci[idx] : INT_MAX;
         const bool in = col < lim;
-        const int n = __popcll(__ballot(in));
+        const float val = in ? wcv[idx] : 0.f;
+        const uint64_t bal = __ballot(in);
+        const int n = __popcll(bal);
         if (in) {
           const int b = col - ov;
-          acc[b] += qq * wcv[idx];
+          acc[b] += qq * val;
           bmin = min(bmin, b);
           bmax = max(bmax, b);
         }
         cu += n;
-        if (n < PMMF_WAVE) break;
+        if (n < PMMF_WAVE) {
+          // the first lane past the run holds the list's next column
+          const int nc = __shfl(col, n);
+          if (lane == 0) ncol[li] = nc;
+          break;
+        }
       }
-      if (lane == 0) cur[li] = cu;
+      if (cu >= e && lane == 0) ncol[li] = INT_MAX;
+      if (lane == 0) {
+        cur[li] = cu;
+        ncl[li] = -1;  // refreshed below, for all advanced lists at once
+      }
     }
+    for (int li = lane; li < nq; li += PMMF_WAVE)
+      if (ncl[li] == -1) ncl[li] = ncol[li] < INT_MAX ? cl_of[ncol[li]] : INT_MAX;
     bmin = pmmf_wave_min_int(bmin);
     bmax = pmmf_wave_max_int(bmax);
     for (int bb = bmin; bb <= bmax; bb += PMMF_WAVE) {
@@ -985,7 +1068,7 @@ hipError_t launch_left(int S, int fill, const int64_t* qrp, const int32_t* qci, 
                        int32_t* cnt, const int64_t* orp, int32_t* oci, float* ocv,
                        double* loss_row, int32_t* overflow, int cmax, hipStream_t s) {
   if (S == 0) return hipSuccess;
-  const size_t per_wave = (size_t)cmax * 4 + (size_t)LEFT_QMAX * 20;
+  const size_t per_wave = (size_t)cmax * 4 + (size_t)LEFT_QMAX * LEFT_PER_LIST;
   int wpb = 4;
   while (wpb > 1 && wpb * per_wave > 64 * 1024) wpb >>= 1;
   const size_t lds = wpb * per_wave;

@@ -295,6 +295,10 @@ int pick_tile(const mmf_plan& h, int nv, int64_t nrhs) {
 // ------------------------------------------------------------------------------------------
 extern "C" const char* mmf_last_error(void) { return g_err.c_str(); }
 
+namespace pmmf_host_detail {
+void set_error(const std::string& msg) { g_err = msg; }
+}
+
 #define ABI_BEGIN try {
 #define ABI_END                                      \
   }                                                  \
