@@ -88,6 +88,10 @@ struct StageDev {
   DBuf off, rcnt, roff, order, gbase, next, gid, cl_of, lvl_ptr, depth, sw_loc, sw_o, sw_idx;
   double loss = 0.0;
   double gram_ms = 0.0, find_ms = 0.0, rotate_ms = 0.0;
+  // sweep plan (built on first use): units of whole rotation components, and the clusters
+  // holding a component larger than a unit, which the level kernel handles
+  int nu = 0, nbig = 0, big_cmax = 0, big_rmax = 0;
+  DBuf u_row_ptr, u_rows, u_rot_ptr, u_rot_loc, u_rot_idx, big_list;
 };
 
 // HIP events bracketing the phases of one stage
@@ -116,6 +120,7 @@ struct mmf_plan {
   DBuf hdiag, hcore, core_ids, is_core;
   DBuf hinv, chol_L, chol_X, status;
   bool inv_ready = false;
+  bool units_ready = false;
   DBuf ws[16];
   mmf_info info{};
   hipStream_t stream = nullptr;
@@ -257,12 +262,13 @@ int find_threads() {
   return nt;
 }
 
+// level-kernel view of a stage restricted to its big clusters (those not split into units)
 pmmf::SweepStage sweep_view(const mmf_plan& h, const StageDev& sd) {
   pmmf::SweepStage v;
-  v.m = sd.m;
+  v.m = sd.nbig;
   v.k = h.k;
-  v.cmax = round_cmax(sd.cmax);
-  v.rmax = sd.rmax;
+  v.cmax = round_cmax(std::max(sd.big_cmax, 1));
+  v.rmax = std::max(sd.big_rmax, 1);
   v.lvl_stride = sd.lvl_stride;
   v.off = sd.off.as<int32_t>();
   v.lvl_ptr = sd.lvl_ptr.as<int32_t>();
@@ -271,15 +277,135 @@ pmmf::SweepStage sweep_view(const mmf_plan& h, const StageDev& sd) {
   v.sw_o = sd.sw_o.as<float>();
   v.next = sd.next.as<int32_t>();
   v.gid = sd.gid.as<int32_t>();
+  v.sw_idx = sd.sw_idx.as<int32_t>();
+  v.rot_base = sd.rot_base;
+  v.clist = sd.big_list.as<int32_t>();
   return v;
+}
+
+pmmf::UnitStage unit_view(const mmf_plan& h, const StageDev& sd) {
+  pmmf::UnitStage v;
+  v.nu = sd.nu;
+  v.k = h.k;
+  v.row_ptr = sd.u_row_ptr.as<int32_t>();
+  v.rows = sd.u_rows.as<int32_t>();
+  v.rot_ptr = sd.u_rot_ptr.as<int32_t>();
+  v.rot_loc = sd.u_rot_loc.as<int32_t>();
+  v.rot_idx = sd.u_rot_idx.as<int32_t>();
+  v.rot_o = h.rot_o.as<float>();
+  v.rot_base = sd.rot_base;
+  v.next = sd.next.as<int32_t>();
+  v.gid = sd.gid.as<int32_t>();
+  return v;
+}
+
+// Split every stage's clusters into units: connected components of the rotation graph packed up
+// to UNIT_MAX rows.  A cluster with a larger component stays whole for the level kernel.
+void ensure_units(mmf_plan& h, hipStream_t s) {
+  if (h.units_ready) return;
+  const int k = h.k;
+  for (auto& sp : h.st) {
+    StageDev& sd = *sp;
+    std::vector<int32_t> loc3(std::max<int64_t>(sd.t, 1) * 3);
+    if (sd.t)
+      HIPCHK(hipMemcpy(loc3.data(), h.rot_loc.as<int32_t>() + sd.rot_base * 3,
+                       sd.t * 3 * sizeof(int32_t), hipMemcpyDeviceToHost));
+    std::vector<int32_t> row_ptr{0}, rows, rot_ptr{0}, rot_loc, rot_idx, big;
+    sd.big_cmax = 0;
+    sd.big_rmax = 0;
+    std::vector<int> parent, cid, first, comp_rows_ptr, comp_rot_ptr, slot;
+    for (int u = 0; u < sd.m; ++u) {
+      const int o = sd.off_h[u], c = sd.off_h[u + 1] - o, r = sd.rcnt_h[u], rb = sd.roff_h[u];
+      parent.assign(c, 0);
+      for (int j = 0; j < c; ++j) parent[j] = j;
+      auto find = [&](int x) {
+        while (parent[x] != x) x = parent[x] = parent[parent[x]];
+        return x;
+      };
+      for (int q = 0; q < r; ++q)
+        for (int a = 1; a < k; ++a) {
+          const int x = find(loc3[(rb + q) * 3]), y = find(loc3[(rb + q) * 3 + a]);
+          if (x != y) parent[std::max(x, y)] = std::min(x, y);
+        }
+      // components numbered by their smallest row
+      cid.assign(c, -1);
+      int nc = 0;
+      std::vector<int> csize;
+      for (int j = 0; j < c; ++j) {
+        const int rt = find(j);
+        if (cid[rt] < 0) {
+          cid[rt] = nc++;
+          csize.push_back(0);
+        }
+        csize[cid[rt]] += 1;
+      }
+      int maxc = 0;
+      for (int z : csize) maxc = std::max(maxc, z);
+      if (maxc > pmmf::UNIT_MAX) {
+        big.push_back(u);
+        sd.big_cmax = std::max(sd.big_cmax, c);
+        sd.big_rmax = std::max(sd.big_rmax, r);
+        continue;
+      }
+      // rows and rotations grouped by component (ascending rows, rotations in order)
+      comp_rows_ptr.assign(nc + 1, 0);
+      comp_rot_ptr.assign(nc + 1, 0);
+      for (int j = 0; j < c; ++j) comp_rows_ptr[cid[find(j)] + 1] += 1;
+      for (int q = 0; q < r; ++q) comp_rot_ptr[cid[find(loc3[(rb + q) * 3])] + 1] += 1;
+      for (int z = 0; z < nc; ++z) {
+        comp_rows_ptr[z + 1] += comp_rows_ptr[z];
+        comp_rot_ptr[z + 1] += comp_rot_ptr[z];
+      }
+      std::vector<int> crow(c), crot(r);
+      {
+        std::vector<int> fill(comp_rows_ptr.begin(), comp_rows_ptr.end() - 1);
+        for (int j = 0; j < c; ++j) crow[fill[cid[find(j)]]++] = j;
+        std::vector<int> fr(comp_rot_ptr.begin(), comp_rot_ptr.end() - 1);
+        for (int q = 0; q < r; ++q) crot[fr[cid[find(loc3[(rb + q) * 3])]]++] = q;
+      }
+      slot.assign(c, -1);
+      int z = 0;
+      while (z < nc) {
+        // pack components z..z2-1 into one unit
+        int z2 = z, nrow = 0;
+        while (z2 < nc && nrow + (comp_rows_ptr[z2 + 1] - comp_rows_ptr[z2]) <= pmmf::UNIT_MAX) {
+          nrow += comp_rows_ptr[z2 + 1] - comp_rows_ptr[z2];
+          ++z2;
+        }
+        int li = 0;
+        for (int i = comp_rows_ptr[z]; i < comp_rows_ptr[z2]; ++i) {
+          slot[crow[i]] = li++;
+          rows.push_back(o + crow[i]);
+        }
+        for (int i = comp_rot_ptr[z]; i < comp_rot_ptr[z2]; ++i) {
+          const int q = crot[i];
+          for (int a = 0; a < k; ++a) rot_loc.push_back(slot[loc3[(rb + q) * 3 + a]]);
+          rot_idx.push_back((int32_t)(sd.rot_base + rb + q));
+        }
+        row_ptr.push_back((int32_t)rows.size());
+        rot_ptr.push_back((int32_t)rot_idx.size());
+        z = z2;
+      }
+    }
+    sd.nu = (int)row_ptr.size() - 1;
+    sd.nbig = (int)big.size();
+    upload(sd.u_row_ptr, row_ptr, s);
+    upload(sd.u_rows, rows, s);
+    upload(sd.u_rot_ptr, rot_ptr, s);
+    upload(sd.u_rot_loc, rot_loc, s);
+    upload(sd.u_rot_idx, rot_idx, s);
+    upload(sd.big_list, big, s);
+  }
+  h.units_ready = true;
 }
 
 // widest column tile whose LDS footprint allows two workgroups per CU (fallback: one)
 int pick_tile(const mmf_plan& h, int nv, int64_t nrhs) {
-  int cmax = 0, rmax = 0;
+  int cmax = 64, rmax = 1;
   for (auto& sp : h.st) {
-    cmax = std::max(cmax, round_cmax(sp->cmax));
-    rmax = std::max(rmax, sp->rmax);
+    if (!sp->nbig) continue;
+    cmax = std::max(cmax, round_cmax(sp->big_cmax));
+    rmax = std::max(rmax, sp->big_rmax);
   }
   int wmax = 1;
   while (wmax < nrhs && wmax < 32) wmax <<= 1;
@@ -670,6 +796,7 @@ void apply_impl(mmf_plan& h, const float* x, float* y, int64_t nrhs, int64_t ld,
     raise(MMF_EINVAL, "bad vector arguments");
   if (nrhs == 0) return;
   if (inverse) ensure_inverse(h, s);
+  ensure_units(h, s);
   const float* Hc = inverse ? h.hinv.as<float>() : h.hcore.as<float>();
   const int P = (int)h.st.size();
   const int64_t core = h.core;
@@ -693,6 +820,7 @@ void apply_impl(mmf_plan& h, const float* x, float* y, int64_t nrhs, int64_t ld,
     io.mode[0] = inverse ? 2 : 1;
     io.hdiag = h.hdiag.as<float>();
     io.nrhs = nrhs;
+    HIPCHK(pmmf::launch_unit_fwd(unit_view(h, sd), io, 1, s));
     HIPCHK(pmmf::launch_sweep_fwd(sweep_view(h, sd), io, W, 1, s));
   }
   HIPCHK(pmmf::launch_gemm((int)core, (int)nrhs, (int)core, Hc, (int)core, 0, buf[P % 2],
@@ -714,6 +842,7 @@ void apply_impl(mmf_plan& h, const float* x, float* y, int64_t nrhs, int64_t ld,
       io.ld_out = nrhs;
     }
     io.nrhs = nrhs;
+    HIPCHK(pmmf::launch_unit_rev(unit_view(h, sd), io, 1, false, s));
     HIPCHK(pmmf::launch_sweep_rev(sweep_view(h, sd), io, W, 1, false, s));
   }
 }
@@ -746,6 +875,7 @@ extern "C" int mmf_backward(mmf_handle hh, const float* d_x, const float* d_ybar
   hipStream_t s = as_stream(stream);
   if (nrhs < 1 || ld < nrhs || !d_x || !d_ybar) raise(MMF_EINVAL, "bad vector arguments");
   if (d_theta_bar && h.k != 2) raise(MMF_EINVAL, "angle gradients exist only for k = 2");
+  ensure_units(h, s);
   const int P = (int)h.st.size();
   const int64_t n = h.n, core = h.core;
   const float* Hc = h.hcore.as<float>();
@@ -779,6 +909,7 @@ extern "C" int mmf_backward(mmf_handle hh, const float* d_x, const float* d_ybar
     io.mode[0] = io.mode[1] = 0;
     io.hdiag = h.hdiag.as<float>();
     io.nrhs = nrhs;
+    HIPCHK(pmmf::launch_unit_fwd(unit_view(h, sd), io, 2, s));
     HIPCHK(pmmf::launch_sweep_fwd(sweep_view(h, sd), io, W2, 2, s));
   }
   int64_t lda_core = nrhs;
@@ -817,7 +948,7 @@ extern "C" int mmf_backward(mmf_handle hh, const float* d_x, const float* d_ybar
                      {wsbuf(h, 14, s1 * nrhs), wsbuf(h, 15, s1 * nrhs)}};
   // RB[0] reuses the buffers of F[0]; the core states are copied first (below), so no buffer is
   // read and written by the same sweep
-  const int ntiles = (int)((nrhs + W2 - 1) / W2);
+  const int ntiles = (int)std::max((nrhs + W2 - 1) / W2, (nrhs + 63) / 64);
   int64_t tmax = 1;
   for (auto& sp : h.st) tmax = std::max(tmax, sp->t);
   DBuf pa_buf, pb_buf;
@@ -861,12 +992,13 @@ extern "C" int mmf_backward(mmf_handle hh, const float* d_x, const float* d_ybar
       io.nrhs = nrhs;
       io.theta_part = pass == 0 ? pa_buf.as<float>() : pb_buf.as<float>();
       io.theta_stride = sd.t;
+      HIPCHK(hipMemsetAsync(io.theta_part, 0, (size_t)ntiles * sd.t * sizeof(float), s));
+      HIPCHK(pmmf::launch_unit_rev(unit_view(h, sd), io, 2, h.k == 2, s));
       HIPCHK(pmmf::launch_sweep_rev(v, io, W2, 2, h.k == 2, s));
     }
     if (d_theta_bar)
       HIPCHK(pmmf::launch_theta_reduce((int)sd.t, ntiles, sd.t, pa_buf.as<float>(),
-                                       pb_buf.as<float>(), sd.sw_idx.as<int32_t>(), d_theta_bar,
-                                       s));
+                                       pb_buf.as<float>(), sd.rot_base, d_theta_bar, s));
   }
   // keep the temporaries alive until the stream has consumed them
   HIPCHK(hipStreamSynchronize(s));

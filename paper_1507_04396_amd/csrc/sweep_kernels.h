@@ -19,6 +19,27 @@ struct SweepStage {
   const float* sw_o;         // [t][k*k] rotation blocks, level order
   const int32_t* next;       // [S] next-stage position, or -(gid + 1) if the row retires here
   const int32_t* gid;        // [S] global id of each position
+  const int32_t* sw_idx;     // [t] canonical index of each sweep-log rotation
+  int64_t rot_base;          // canonical index of the stage's first rotation
+  const int32_t* clist;      // clusters to process (NULL: all m); grid.x = number of entries
+};
+
+// The same stage split into "units": whole connected components of the rotation graph (rows
+// linked by a rotation), packed up to UNIT_MAX rows.  A unit's rotations touch only its rows, so a
+// wave applies them in order to a 64-column slice held in its own LDS, with no barrier.
+constexpr int UNIT_MAX = 32;
+struct UnitStage {
+  int nu;                    // units
+  int k;
+  const int32_t* row_ptr;    // [nu+1] into rows
+  const int32_t* rows;       // positions of S_{p-1}, unit by unit
+  const int32_t* rot_ptr;    // [nu+1] into rot_loc / rot_idx
+  const int32_t* rot_loc;    // [t][k] unit-local row of each slot
+  const int32_t* rot_idx;    // [t] canonical index (rotation block in rot_o, angle gradient)
+  const float* rot_o;        // canonical blocks [R][9], leading dimension 3
+  int64_t rot_base;          // canonical index of the stage's first rotation
+  const int32_t* next;
+  const int32_t* gid;
 };
 
 struct FwdIO {
@@ -50,6 +71,8 @@ struct RevIO {
 };
 
 size_t sweep_lds_bytes(int k, int W, int nv, int cmax, int rmax);
+hipError_t launch_unit_fwd(const UnitStage& st, const FwdIO& io, int nv, hipStream_t s);
+hipError_t launch_unit_rev(const UnitStage& st, const RevIO& io, int nv, bool theta, hipStream_t s);
 hipError_t launch_sweep_fwd(const SweepStage& st, const FwdIO& io, int W, int nv, hipStream_t s);
 hipError_t launch_sweep_rev(const SweepStage& st, const RevIO& io, int W, int nv, bool theta,
                             hipStream_t s);
@@ -61,7 +84,7 @@ hipError_t launch_core_inverse(int n, float* work_L, float* work_X, float* out_i
 hipError_t launch_rowdot(int64_t n, const float* a, const float* b, int64_t ld, int64_t nrhs,
                          const uint8_t* is_core, float* out, hipStream_t s);
 hipError_t launch_theta_reduce(int t, int ntiles, int64_t stride, const float* pa,
-                               const float* pb, const int32_t* sw_idx, float* out, hipStream_t s);
+                               const float* pb, int64_t rot_base, float* out, hipStream_t s);
 hipError_t launch_gather_rows(int64_t rows, const float* src, int64_t lds, const int32_t* idx,
                               float* dst, int64_t ldd, int64_t ncol, int scatter, hipStream_t s);
 hipError_t launch_sync_angles(int64_t R, const float* theta, float* rot_o, hipStream_t s);

@@ -50,7 +50,7 @@ __device__ inline void rotate_cols(float* tile, int cstride, const int* ids, con
 template <int K, int W, int NV>
 __global__ void __launch_bounds__(256) k_sweep_fwd(SweepStage st, FwdIO io) {
   extern __shared__ float lds_f[];
-  const int u = blockIdx.x;
+  const int u = st.clist ? st.clist[blockIdx.x] : blockIdx.x;
   const int col0 = blockIdx.y * W;
   const int o = st.off[u];
   const int c = st.off[u + 1] - o;
@@ -110,7 +110,7 @@ __global__ void __launch_bounds__(256) k_sweep_fwd(SweepStage st, FwdIO io) {
 template <int K, int W, int NV, bool THETA>
 __global__ void __launch_bounds__(256) k_sweep_rev(SweepStage st, RevIO io) {
   extern __shared__ float lds_f[];
-  const int u = blockIdx.x;
+  const int u = st.clist ? st.clist[blockIdx.x] : blockIdx.x;
   const int col0 = blockIdx.y * W;
   const int o = st.off[u];
   const int c = st.off[u + 1] - o;
@@ -163,7 +163,8 @@ __global__ void __launch_bounds__(256) k_sweep_rev(SweepStage st, RevIO io) {
 #pragma unroll
         for (int ofs = W / 2; ofs > 0; ofs >>= 1) part += __shfl_xor(part, ofs, W);
         if (live && w == 0)
-          io.theta_part[(size_t)blockIdx.y * io.theta_stride + (rr + rb)] = part;
+          io.theta_part[(size_t)blockIdx.y * io.theta_stride +
+                        (st.sw_idx[rr + rb] - st.rot_base)] = part;
       }
       if (live) rotate_cols<K, W, NV, true>(tile, cstride, rid + rr * K, rob + rr * K * K, w);
     }
@@ -199,7 +200,7 @@ static hipError_t fwd_dispatch(const SweepStage& st, const FwdIO& io, hipStream_
                                        (int)lds);
     if (e != hipSuccess) return e;
   }
-  dim3 grid(st.m, (io.nrhs + W - 1) / W);
+  dim3 grid(st.m, (io.nrhs + W - 1) / W);  // st.m = number of listed clusters
   k_sweep_fwd<K, W, NV><<<grid, 256, lds, s>>>(st, io);
   return hipGetLastError();
 }
@@ -387,21 +388,197 @@ hipError_t launch_rowdot(int64_t n, const float* a, const float* b, int64_t ld, 
   return hipGetLastError();
 }
 
-// theta_bar[sw_idx[q]] = sum over column tiles of (partA + partB)[tile][q]
+// theta_bar[rot_base + q] = sum over column tiles of (partA + partB)[tile][q]
 __global__ void k_theta_reduce(int t, int ntiles, int64_t stride, const float* __restrict__ pa,
-                               const float* __restrict__ pb, const int32_t* __restrict__ sw_idx,
+                               const float* __restrict__ pb, int64_t rot_base,
                                float* __restrict__ out) {
   const int q = blockIdx.x * blockDim.x + threadIdx.x;
   if (q >= t) return;
   float s = 0.f;
   for (int y = 0; y < ntiles; ++y) s += pa[(size_t)y * stride + q] + pb[(size_t)y * stride + q];
-  out[sw_idx[q]] = s;
+  out[rot_base + q] = s;
 }
 hipError_t launch_theta_reduce(int t, int ntiles, int64_t stride, const float* pa,
-                               const float* pb, const int32_t* sw_idx, float* out, hipStream_t s) {
+                               const float* pb, int64_t rot_base, float* out, hipStream_t s) {
   if (t == 0) return hipSuccess;
-  k_theta_reduce<<<(t + 255) / 256, 256, 0, s>>>(t, ntiles, stride, pa, pb, sw_idx, out);
+  k_theta_reduce<<<(t + 255) / 256, 256, 0, s>>>(t, ntiles, stride, pa, pb, rot_base, out);
   return hipGetLastError();
+}
+
+// ------------------------------------------------------------------------------------------
+// Unit sweeps: one wave per (unit, 64-column slice).  The unit's rows are loaded as 256-byte
+// row segments into the wave's LDS, its rotations are applied in order (MODE 0: O, forward) or in
+// reverse with transposed blocks (MODE 1; MODE 2 also adds the angle-gradient partial
+// sum_w <g[T], J z[T]> of each rotation before undoing it), and the rows are written back.
+template <int K, int NV, int MODE>
+__global__ void __launch_bounds__(256) k_unit_sweep(UnitStage st, FwdIO fio, RevIO rio) {
+  extern __shared__ float lds_f[];
+  constexpr int ROWF = NV * UNIT_MAX * PMMF_WAVE;
+  constexpr int PER_WAVE = ROWF + UNIT_MAX * (K + K * K);
+  const int wpb = blockDim.x / PMMF_WAVE;
+  const int w = pmmf_wave(), lane = pmmf_lane();
+  const int g = blockIdx.x * wpb + w;
+  if (g >= st.nu) return;
+  float* tile = lds_f + (size_t)w * PER_WAVE;
+  int* rloc = reinterpret_cast<int*>(tile + ROWF);
+  float* ro = reinterpret_cast<float*>(rloc + UNIT_MAX * K);
+  const int64_t col = (int64_t)blockIdx.y * PMMF_WAVE + lane;
+  const int64_t nrhs = MODE == 0 ? fio.nrhs : rio.nrhs;
+  const bool cok = col < nrhs;
+  const int r0 = st.row_ptr[g], ns = st.row_ptr[g + 1] - r0;
+  const int q0 = st.rot_ptr[g], nr = st.rot_ptr[g + 1] - q0;
+  for (int q = lane; q < nr * K; q += PMMF_WAVE) rloc[q] = st.rot_loc[(int64_t)q0 * K + q];
+  for (int q = lane; q < nr * K * K; q += PMMF_WAVE) {
+    const int rr = q / (K * K), ab = q % (K * K);
+    ro[q] = st.rot_o[(int64_t)st.rot_idx[q0 + rr] * 9 + (ab / K) * 3 + (ab % K)];
+  }
+  // the unit's row ids, next positions and retired scales, one lane per row (ns <= 32)
+  const int myrow = lane < ns ? st.rows[r0 + lane] : 0;
+  const int mynext = lane < ns ? st.next[myrow] : 0;
+  float myscale = 1.f;
+  if (MODE != 0 && lane < ns && mynext < 0 && rio.mode[0] + rio.mode[NV - 1] > 0)
+    myscale = rio.hdiag[-mynext - 1];
+  // load the rows, eight independent row segments in flight at a time
+  for (int i0 = 0; i0 < ns; i0 += 8) {
+    float vals[8][NV];
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+      const int i = min(i0 + q, ns - 1);
+      const int pos = __shfl(myrow, i);
+      const int nx = __shfl(mynext, i);
+      const float sc = __shfl(myscale, i);
+#pragma unroll
+      for (int v = 0; v < NV; ++v) {
+        float val = 0.f;
+        if (cok) {
+          if (MODE == 0) {
+            val = fio.src[v][(int64_t)pos * fio.ld_src + col];
+          } else if (nx >= 0) {
+            val = rio.src_c[v][(int64_t)nx * rio.ld_c + col];
+          } else {
+            val = rio.src_nat[v][(int64_t)(-nx - 1) * rio.ld_nat + col];
+            if (rio.mode[v] == 1) val *= sc;
+          }
+        }
+        vals[q][v] = val;
+      }
+    }
+#pragma unroll
+    for (int q = 0; q < 8; ++q)
+      if (i0 + q < ns)
+#pragma unroll
+        for (int v = 0; v < NV; ++v) tile[v * UNIT_MAX * PMMF_WAVE + (i0 + q) * PMMF_WAVE + lane] = vals[q][v];
+  }
+  if (MODE == 0) {
+    for (int q = 0; q < nr; ++q) {
+      const int* id = rloc + q * K;
+      const float* o = ro + q * K * K;
+#pragma unroll
+      for (int v = 0; v < NV; ++v) {
+        float* t = tile + v * UNIT_MAX * PMMF_WAVE;
+        float x[K];
+#pragma unroll
+        for (int a = 0; a < K; ++a) x[a] = t[id[a] * PMMF_WAVE + lane];
+#pragma unroll
+        for (int a = 0; a < K; ++a) {
+          float sacc = 0.f;
+#pragma unroll
+          for (int b = 0; b < K; ++b) sacc += o[a * K + b] * x[b];
+          t[id[a] * PMMF_WAVE + lane] = sacc;
+        }
+      }
+    }
+  } else {
+    for (int q = nr - 1; q >= 0; --q) {
+      const int* id = rloc + q * K;
+      const float* o = ro + q * K * K;
+      if (MODE == 2) {
+        const float* z = tile;
+        const float* gv = tile + UNIT_MAX * PMMF_WAVE;
+        float part = gv[id[1] * PMMF_WAVE + lane] * z[id[0] * PMMF_WAVE + lane] -
+                     gv[id[0] * PMMF_WAVE + lane] * z[id[1] * PMMF_WAVE + lane];
+        part = pmmf_wave_sum_float(part);
+        if (lane == 0)
+          rio.theta_part[(int64_t)blockIdx.y * rio.theta_stride +
+                         (st.rot_idx[q0 + q] - st.rot_base)] = part;
+      }
+#pragma unroll
+      for (int v = 0; v < NV; ++v) {
+        float* t = tile + v * UNIT_MAX * PMMF_WAVE;
+        float x[K];
+#pragma unroll
+        for (int a = 0; a < K; ++a) x[a] = t[id[a] * PMMF_WAVE + lane];
+#pragma unroll
+        for (int a = 0; a < K; ++a) {
+          float sacc = 0.f;
+#pragma unroll
+          for (int b = 0; b < K; ++b) sacc += o[b * K + a] * x[b];
+          t[id[a] * PMMF_WAVE + lane] = sacc;
+        }
+      }
+    }
+  }
+  // row data sits in lanes 0..ns-1, so every lane takes part in the shuffles below and only
+  // the stores are masked by the column bound
+  float myscale_out = 1.f;
+  if (MODE == 0 && lane < ns && mynext < 0 && fio.mode[0] + fio.mode[NV - 1] > 0)
+    myscale_out = fio.hdiag[-mynext - 1];
+  const int mygid = (MODE != 0 && lane < ns) ? st.gid[myrow] : 0;
+  for (int i = 0; i < ns; ++i) {
+    const int pos = __shfl(myrow, i);
+    const int nx = __shfl(mynext, i);
+    const float sc = __shfl(myscale_out, i);
+    const int gd = __shfl(mygid, i);
+    if (!cok) continue;
+#pragma unroll
+    for (int v = 0; v < NV; ++v) {
+      float val = tile[v * UNIT_MAX * PMMF_WAVE + i * PMMF_WAVE + lane];
+      if (MODE == 0) {
+        if (nx >= 0) {
+          fio.dst_c[v][(int64_t)nx * fio.ld_c + col] = val;
+        } else {
+          if (fio.mode[v] == 1) val *= sc;
+          else if (fio.mode[v] == 2) val /= sc;
+          fio.dst_nat[v][(int64_t)(-nx - 1) * fio.ld_nat + col] = val;
+        }
+      } else {
+        if (rio.dst_nat[v]) rio.dst_nat[v][(int64_t)gd * rio.ld_dnat + col] = val;
+        else if (rio.dst_c[v]) rio.dst_c[v][(int64_t)pos * rio.ld_out + col] = val;
+      }
+    }
+  }
+}
+
+template <int K, int NV, int MODE>
+static hipError_t unit_launch(const UnitStage& st, const FwdIO& fio, const RevIO& rio,
+                              hipStream_t s) {
+  if (st.nu == 0) return hipSuccess;
+  constexpr int WPB = 4;
+  const size_t lds = (size_t)WPB * (NV * UNIT_MAX * PMMF_WAVE + UNIT_MAX * (K + K * K)) * 4;
+  if (lds > 64 * 1024) {
+    hipError_t e = hipFuncSetAttribute((const void*)&k_unit_sweep<K, NV, MODE>,
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e != hipSuccess) return e;
+  }
+  const int64_t nrhs = MODE == 0 ? fio.nrhs : rio.nrhs;
+  dim3 grid((st.nu + WPB - 1) / WPB, (unsigned)((nrhs + PMMF_WAVE - 1) / PMMF_WAVE));
+  k_unit_sweep<K, NV, MODE><<<grid, WPB * PMMF_WAVE, lds, s>>>(st, fio, rio);
+  return hipGetLastError();
+}
+
+hipError_t launch_unit_fwd(const UnitStage& st, const FwdIO& io, int nv, hipStream_t s) {
+  RevIO none{};
+  if (st.k == 2) return nv == 1 ? unit_launch<2, 1, 0>(st, io, none, s) : unit_launch<2, 2, 0>(st, io, none, s);
+  return nv == 1 ? unit_launch<3, 1, 0>(st, io, none, s) : unit_launch<3, 2, 0>(st, io, none, s);
+}
+
+hipError_t launch_unit_rev(const UnitStage& st, const RevIO& io, int nv, bool theta, hipStream_t s) {
+  FwdIO none{};
+  if (st.k == 2) {
+    if (theta) return unit_launch<2, 2, 2>(st, none, io, s);
+    return nv == 1 ? unit_launch<2, 1, 1>(st, none, io, s) : unit_launch<2, 2, 1>(st, none, io, s);
+  }
+  return nv == 1 ? unit_launch<3, 1, 1>(st, none, io, s) : unit_launch<3, 2, 1>(st, none, io, s);
 }
 
 // core rows: compact buffer of the final active set -> natural rows of the core ids
