@@ -61,6 +61,29 @@ __device__ inline float pmmf_wave_sum_float(float v) {
   for (int o = PMMF_WAVE / 2; o > 0; o >>= 1) v += __shfl_xor(v, o);
   return v;
 }
+// Sum over the 64 lanes through DPP row shifts (inclusive sums inside each row of 16 lanes) and
+// the four row totals read back with readlane: no LDS traffic.  Every lane must be active; all
+// lanes receive the same result.
+template <int CTRL>
+__device__ inline float pmmf_dpp_row_shr(float v) {
+  return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), CTRL,
+                                                               0xf, 0xf, false));
+}
+__device__ inline float pmmf_wave_sum_dpp(float v) {
+  v += pmmf_dpp_row_shr<0x111>(v);
+  v += pmmf_dpp_row_shr<0x112>(v);
+  v += pmmf_dpp_row_shr<0x114>(v);
+  v += pmmf_dpp_row_shr<0x118>(v);
+  const int b = __builtin_bit_cast(int, v);
+  return (__builtin_bit_cast(float, __builtin_amdgcn_readlane(b, 15)) +
+          __builtin_bit_cast(float, __builtin_amdgcn_readlane(b, 31))) +
+         (__builtin_bit_cast(float, __builtin_amdgcn_readlane(b, 47)) +
+          __builtin_bit_cast(float, __builtin_amdgcn_readlane(b, 63)));
+}
+__device__ inline float pmmf_readlane_f(float v, int l) {
+  return __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, v), l));
+}
+
 // inclusive prefix sum over the lanes of a wave
 __device__ inline int pmmf_wave_incl_scan(int v) {
   const int lane = pmmf_lane();

@@ -91,7 +91,7 @@ struct StageDev {
   // sweep plan (built on first use): units of whole rotation components, and the clusters
   // holding a component larger than a unit, which the level kernel handles
   int nu = 0, nbig = 0, big_cmax = 0, big_rmax = 0;
-  DBuf u_row_ptr, u_rows, u_rot_ptr, u_rot_loc, u_rot_idx, big_list;
+  DBuf u_cnt, u_slot, u_rot, big_list;
 };
 
 // HIP events bracketing the phases of one stage
@@ -287,33 +287,31 @@ pmmf::UnitStage unit_view(const mmf_plan& h, const StageDev& sd) {
   pmmf::UnitStage v;
   v.nu = sd.nu;
   v.k = h.k;
-  v.row_ptr = sd.u_row_ptr.as<int32_t>();
-  v.rows = sd.u_rows.as<int32_t>();
-  v.rot_ptr = sd.u_rot_ptr.as<int32_t>();
-  v.rot_loc = sd.u_rot_loc.as<int32_t>();
-  v.rot_idx = sd.u_rot_idx.as<int32_t>();
+  v.cnt = sd.u_cnt.as<int2>();
+  v.slot = sd.u_slot.as<int4>();
+  v.rot = sd.u_rot.as<int2>();
   v.rot_o = h.rot_o.as<float>();
   v.rot_base = sd.rot_base;
-  v.next = sd.next.as<int32_t>();
-  v.gid = sd.gid.as<int32_t>();
   return v;
 }
 
-// Split every stage's clusters into units: connected components of the rotation graph packed up
-// to UNIT_MAX rows.  A cluster with a larger component stays whole for the level kernel.
 void ensure_units(mmf_plan& h, hipStream_t s) {
   if (h.units_ready) return;
   const int k = h.k;
+  constexpr int UM = pmmf::UNIT_MAX;
   for (auto& sp : h.st) {
     StageDev& sd = *sp;
     std::vector<int32_t> loc3(std::max<int64_t>(sd.t, 1) * 3);
+    std::vector<int32_t> nxt(std::max<int64_t>(sd.size, 1)), gidv(std::max<int64_t>(sd.size, 1));
     if (sd.t)
       HIPCHK(hipMemcpy(loc3.data(), h.rot_loc.as<int32_t>() + sd.rot_base * 3,
                        sd.t * 3 * sizeof(int32_t), hipMemcpyDeviceToHost));
-    std::vector<int32_t> row_ptr{0}, rows, rot_ptr{0}, rot_loc, rot_idx, big;
+    HIPCHK(hipMemcpy(nxt.data(), sd.next.p, sd.size * sizeof(int32_t), hipMemcpyDeviceToHost));
+    HIPCHK(hipMemcpy(gidv.data(), sd.gid.p, sd.size * sizeof(int32_t), hipMemcpyDeviceToHost));
+    std::vector<int32_t> ucnt, uslot, urot, big;
     sd.big_cmax = 0;
     sd.big_rmax = 0;
-    std::vector<int> parent, cid, first, comp_rows_ptr, comp_rot_ptr, slot;
+    std::vector<int> parent, cid, comp_rows_ptr, comp_rot_ptr, slot;
     for (int u = 0; u < sd.m; ++u) {
       const int o = sd.off_h[u], c = sd.off_h[u + 1] - o, r = sd.rcnt_h[u], rb = sd.roff_h[u];
       parent.assign(c, 0);
@@ -341,7 +339,7 @@ void ensure_units(mmf_plan& h, hipStream_t s) {
       }
       int maxc = 0;
       for (int z : csize) maxc = std::max(maxc, z);
-      if (maxc > pmmf::UNIT_MAX) {
+      if (maxc > UM) {
         big.push_back(u);
         sd.big_cmax = std::max(sd.big_cmax, c);
         sd.big_rmax = std::max(sd.big_rmax, r);
@@ -368,32 +366,42 @@ void ensure_units(mmf_plan& h, hipStream_t s) {
       while (z < nc) {
         // pack components z..z2-1 into one unit
         int z2 = z, nrow = 0;
-        while (z2 < nc && nrow + (comp_rows_ptr[z2 + 1] - comp_rows_ptr[z2]) <= pmmf::UNIT_MAX) {
+        while (z2 < nc && nrow + (comp_rows_ptr[z2 + 1] - comp_rows_ptr[z2]) <= UM) {
           nrow += comp_rows_ptr[z2 + 1] - comp_rows_ptr[z2];
           ++z2;
         }
+        const size_t sbase = uslot.size(), rbase = urot.size();
+        uslot.resize(sbase + 4 * UM, 0);
+        urot.resize(rbase + 2 * UM, 0);
         int li = 0;
         for (int i = comp_rows_ptr[z]; i < comp_rows_ptr[z2]; ++i) {
-          slot[crow[i]] = li++;
-          rows.push_back(o + crow[i]);
+          const int pos = o + crow[i];
+          slot[crow[i]] = li;
+          uslot[sbase + 4 * li + 0] = pos;
+          uslot[sbase + 4 * li + 1] = nxt[pos];
+          uslot[sbase + 4 * li + 2] = gidv[pos];
+          ++li;
         }
+        int nq = 0;
         for (int i = comp_rot_ptr[z]; i < comp_rot_ptr[z2]; ++i) {
           const int q = crot[i];
-          for (int a = 0; a < k; ++a) rot_loc.push_back(slot[loc3[(rb + q) * 3 + a]]);
-          rot_idx.push_back((int32_t)(sd.rot_base + rb + q));
+          if (nq >= UM) raise(MMF_EDEVICE, "unit with more rotations than slots");
+          int packed = 0;
+          for (int a = 0; a < k; ++a) packed |= slot[loc3[(rb + q) * 3 + a]] << (5 * a);
+          urot[rbase + 2 * nq + 0] = packed;
+          urot[rbase + 2 * nq + 1] = (int32_t)(sd.rot_base + rb + q);
+          ++nq;
         }
-        row_ptr.push_back((int32_t)rows.size());
-        rot_ptr.push_back((int32_t)rot_idx.size());
+        ucnt.push_back(li);
+        ucnt.push_back(nq);
         z = z2;
       }
     }
-    sd.nu = (int)row_ptr.size() - 1;
+    sd.nu = (int)(ucnt.size() / 2);
     sd.nbig = (int)big.size();
-    upload(sd.u_row_ptr, row_ptr, s);
-    upload(sd.u_rows, rows, s);
-    upload(sd.u_rot_ptr, rot_ptr, s);
-    upload(sd.u_rot_loc, rot_loc, s);
-    upload(sd.u_rot_idx, rot_idx, s);
+    upload(sd.u_cnt, ucnt, s);
+    upload(sd.u_slot, uslot, s);
+    upload(sd.u_rot, urot, s);
     upload(sd.big_list, big, s);
   }
   h.units_ready = true;

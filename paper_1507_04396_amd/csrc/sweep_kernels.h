@@ -25,21 +25,21 @@ struct SweepStage {
 };
 
 // The same stage split into "units": whole connected components of the rotation graph (rows
-// linked by a rotation), packed up to UNIT_MAX rows.  A unit's rotations touch only its rows, so a
-// wave applies them in order to a 64-column slice held in its own LDS, with no barrier.
+// linked by a rotation), packed up to UNIT_MAX rows.  A unit's rotations touch only its rows, so
+// one wave applies them in order to a 64-column slice held in its registers, with no barrier.
+// Every unit has UNIT_MAX row slots and UNIT_MAX rotation slots (a unit of c rows carries at most
+// c - 1 rotations, one retirement each), so a wave reads its whole description in one step.
 constexpr int UNIT_MAX = 32;
 struct UnitStage {
   int nu;                    // units
   int k;
-  const int32_t* row_ptr;    // [nu+1] into rows
-  const int32_t* rows;       // positions of S_{p-1}, unit by unit
-  const int32_t* rot_ptr;    // [nu+1] into rot_loc / rot_idx
-  const int32_t* rot_loc;    // [t][k] unit-local row of each slot
-  const int32_t* rot_idx;    // [t] canonical index (rotation block in rot_o, angle gradient)
+  const int2* cnt;           // [nu] {rows, rotations}
+  const int4* slot;          // [nu][UNIT_MAX] {position in S_{p-1}, next position or -(gid + 1),
+                             //                 gid, 0}
+  const int2* rot;           // [nu][UNIT_MAX] {unit-local slots, 5 bits each, slot a at bit 5a;
+                             //                 canonical rotation index}
   const float* rot_o;        // canonical blocks [R][9], leading dimension 3
   int64_t rot_base;          // canonical index of the stage's first rotation
-  const int32_t* next;
-  const int32_t* gid;
 };
 
 struct FwdIO {

@@ -253,60 +253,78 @@ hipError_t launch_sweep_rev(const SweepStage& st, const RevIO& io, int W, int nv
 }
 
 // ------------------------------------------------------------------------------------------
-// dense FP32 GEMM  C[M][N] = op(A)[M][K] * op(B)[K][N]  (row-major, op = transpose if flagged),
-// 64 x 64 output tiles, 16-deep K slices staged in LDS, 4 x 4 outputs per thread
+// dense FP32 GEMM  C[M][N] = op(A)[M][K] * op(B)[K][N] (+ beta C), row-major, op = transpose if
+// flagged.  32 x 32 output tile per workgroup, one 16 x 16 quarter per wave on
+// v_mfma_f32_16x16x4f32 (A operand: lane l holds A[l % 16][l / 16], B operand B[l / 16][l % 16],
+// result row 4 (l / 16) + r, column l % 16 in register r).  K advances in 128-deep slices staged
+// in LDS; the next slice is fetched into registers while the current one is multiplied.
+typedef float pmmf_f4 __attribute__((ext_vector_type(4)));
+constexpr int GEMM_T = 32, GEMM_K = 128, GEMM_PER = GEMM_T * GEMM_K / 256;
 __global__ void __launch_bounds__(256) k_gemm(int M, int N, int K, const float* __restrict__ A,
                                               int lda, int ta, const float* __restrict__ B,
                                               int ldb, int tb, float* __restrict__ C, int ldc,
                                               float beta) {
-  __shared__ float As[16][64 + 1];
-  __shared__ float Bs[16][64 + 1];
-  const int tx = threadIdx.x % 16, ty = threadIdx.x / 16;
-  const int m0 = blockIdx.y * 64, n0 = blockIdx.x * 64;
-  float acc[4][4] = {};
-  for (int k0 = 0; k0 < K; k0 += 16) {
-    for (int q = threadIdx.x; q < 16 * 64; q += 256) {
-      const int kk = q / 64, mm = q % 64;
-      const int gm = m0 + mm, gk = k0 + kk;
-      float va = 0.f;
-      if (gm < M && gk < K) va = ta ? A[(size_t)gk * lda + gm] : A[(size_t)gm * lda + gk];
-      As[kk][mm] = va;
-      const int gn = n0 + mm;
-      float vb = 0.f;
-      if (gn < N && gk < K) vb = tb ? B[(size_t)gn * ldb + gk] : B[(size_t)gk * ldb + gn];
-      Bs[kk][mm] = vb;
+  __shared__ float As[GEMM_T][GEMM_K + 1];
+  __shared__ float Bs[GEMM_K][GEMM_T + 1];
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  const int m0 = blockIdx.y * GEMM_T, n0 = blockIdx.x * GEMM_T;
+  const int wm = (w >> 1) * 16, wn = (w & 1) * 16;
+  float ra[GEMM_PER], rb[GEMM_PER];
+  auto a_index = [&](int q, int& m, int& k) {
+    if (ta) { k = q / GEMM_T; m = q % GEMM_T; } else { m = q / GEMM_K; k = q % GEMM_K; }
+  };
+  auto b_index = [&](int q, int& k, int& n) {
+    if (tb) { n = q / GEMM_K; k = q % GEMM_K; } else { k = q / GEMM_T; n = q % GEMM_T; }
+  };
+  auto fetch = [&](int k0) {
+#pragma unroll
+    for (int p = 0; p < GEMM_PER; ++p) {
+      const int q = tid + p * 256;
+      int m, k, n, kb;
+      a_index(q, m, k);
+      b_index(q, kb, n);
+      const int gm = m0 + m, gk = k0 + k, gn = n0 + n, gkb = k0 + kb;
+      ra[p] = (gm < M && gk < K) ? (ta ? A[(size_t)gk * lda + gm] : A[(size_t)gm * lda + gk]) : 0.f;
+      rb[p] = (gn < N && gkb < K) ? (tb ? B[(size_t)gn * ldb + gkb] : B[(size_t)gkb * ldb + gn])
+                                  : 0.f;
+    }
+  };
+  pmmf_f4 acc = {0.f, 0.f, 0.f, 0.f};
+  fetch(0);
+  for (int k0 = 0; k0 < K; k0 += GEMM_K) {
+#pragma unroll
+    for (int p = 0; p < GEMM_PER; ++p) {
+      const int q = tid + p * 256;
+      int m, k, n, kb;
+      a_index(q, m, k);
+      b_index(q, kb, n);
+      As[m][k] = ra[p];
+      Bs[kb][n] = rb[p];
     }
     __syncthreads();
-#pragma unroll
-    for (int kk = 0; kk < 16; ++kk) {
-      float a[4], b[4];
-#pragma unroll
-      for (int i = 0; i < 4; ++i) a[i] = As[kk][ty * 4 + i];
-#pragma unroll
-      for (int j = 0; j < 4; ++j) b[j] = Bs[kk][tx * 4 + j];
-#pragma unroll
-      for (int i = 0; i < 4; ++i)
-#pragma unroll
-        for (int j = 0; j < 4; ++j) acc[i][j] += a[i] * b[j];
+    if (k0 + GEMM_K < K) fetch(k0 + GEMM_K);
+#pragma unroll 8
+    for (int kk = 0; kk < GEMM_K; kk += 4) {
+      const float av = As[wm + (lane & 15)][kk + (lane >> 4)];
+      const float bv = Bs[kk + (lane >> 4)][wn + (lane & 15)];
+      acc = __builtin_amdgcn_mfma_f32_16x16x4f32(av, bv, acc, 0, 0, 0);
     }
     __syncthreads();
   }
 #pragma unroll
-  for (int i = 0; i < 4; ++i)
-#pragma unroll
-    for (int j = 0; j < 4; ++j) {
-      const int gm = m0 + ty * 4 + i, gn = n0 + tx * 4 + j;
-      if (gm < M && gn < N) {
-        float* cp = C + (size_t)gm * ldc + gn;
-        *cp = beta == 0.f ? acc[i][j] : beta * *cp + acc[i][j];
-      }
+  for (int r = 0; r < 4; ++r) {
+    const int gm = m0 + wm + 4 * (lane >> 4) + r, gn = n0 + wn + (lane & 15);
+    if (gm < M && gn < N) {
+      float* cp = C + (size_t)gm * ldc + gn;
+      *cp = beta == 0.f ? acc[r] : beta * *cp + acc[r];
     }
+  }
 }
 
 hipError_t launch_gemm(int M, int N, int K, const float* A, int lda, int ta, const float* B,
                        int ldb, int tb, float* C, int ldc, float beta, hipStream_t s) {
   if (M == 0 || N == 0) return hipSuccess;
-  dim3 grid((N + 63) / 64, (M + 63) / 64);
+  dim3 grid((N + GEMM_T - 1) / GEMM_T, (M + GEMM_T - 1) / GEMM_T);
   k_gemm<<<grid, 256, 0, s>>>(M, N, K, A, lda, ta, B, ldb, tb, C, ldc, beta);
   return hipGetLastError();
 }
@@ -406,139 +424,158 @@ hipError_t launch_theta_reduce(int t, int ntiles, int64_t stride, const float* p
 }
 
 // ------------------------------------------------------------------------------------------
-// Unit sweeps: one wave per (unit, 64-column slice).  The unit's rows are loaded as 256-byte
-// row segments into the wave's LDS, its rotations are applied in order (MODE 0: O, forward) or in
-// reverse with transposed blocks (MODE 1; MODE 2 also adds the angle-gradient partial
-// sum_w <g[T], J z[T]> of each rotation before undoing it), and the rows are written back.
+// Unit sweeps: one wave per (unit, 64-column slice), lane = column.  The unit's description (row
+// slots, rotation slots) is read in one step, every row segment is then requested at once into
+// registers and parked in the wave's own LDS tile, the rotations are applied in order (MODE 0: O,
+// forward) or in reverse with transposed blocks (MODE 1; MODE 2 also adds the angle-gradient
+// partial sum_w <g[T], J z[T]> of each rotation before undoing it, vector 0 = z, vector 1 = g),
+// and the rows are written back.  Rotation parameters live in the lane of their slot and are
+// broadcast with readlane; the tile is private to the wave, so no barrier is needed.
 template <int K, int NV, int MODE>
 __global__ void __launch_bounds__(256) k_unit_sweep(UnitStage st, FwdIO fio, RevIO rio) {
   extern __shared__ float lds_f[];
-  constexpr int ROWF = NV * UNIT_MAX * PMMF_WAVE;
-  constexpr int PER_WAVE = ROWF + UNIT_MAX * (K + K * K);
-  const int wpb = blockDim.x / PMMF_WAVE;
-  const int w = pmmf_wave(), lane = pmmf_lane();
-  const int g = blockIdx.x * wpb + w;
+  const int lane = pmmf_lane();
+  const int wv = __builtin_amdgcn_readfirstlane(pmmf_wave());
+  float* tile = lds_f + (size_t)wv * NV * UNIT_MAX * PMMF_WAVE;
+  const int g = blockIdx.x * (blockDim.x / PMMF_WAVE) + __builtin_amdgcn_readfirstlane(pmmf_wave());
   if (g >= st.nu) return;
-  float* tile = lds_f + (size_t)w * PER_WAVE;
-  int* rloc = reinterpret_cast<int*>(tile + ROWF);
-  float* ro = reinterpret_cast<float*>(rloc + UNIT_MAX * K);
   const int64_t col = (int64_t)blockIdx.y * PMMF_WAVE + lane;
   const int64_t nrhs = MODE == 0 ? fio.nrhs : rio.nrhs;
   const bool cok = col < nrhs;
-  const int r0 = st.row_ptr[g], ns = st.row_ptr[g + 1] - r0;
-  const int q0 = st.rot_ptr[g], nr = st.rot_ptr[g + 1] - q0;
-  for (int q = lane; q < nr * K; q += PMMF_WAVE) rloc[q] = st.rot_loc[(int64_t)q0 * K + q];
-  for (int q = lane; q < nr * K * K; q += PMMF_WAVE) {
-    const int rr = q / (K * K), ab = q % (K * K);
-    ro[q] = st.rot_o[(int64_t)st.rot_idx[q0 + rr] * 9 + (ab / K) * 3 + (ab % K)];
+  const int2 cnt = st.cnt[g];
+  const int ns = __builtin_amdgcn_readfirstlane(cnt.x);
+  const int nr = __builtin_amdgcn_readfirstlane(cnt.y);
+  int4 sl = make_int4(0, 0, 0, 0);
+  int2 rt = make_int2(0, 0);
+  if (lane < UNIT_MAX) {
+    sl = st.slot[(int64_t)g * UNIT_MAX + lane];
+    rt = st.rot[(int64_t)g * UNIT_MAX + lane];
   }
-  // the unit's row ids, next positions and retired scales, one lane per row (ns <= 32)
-  const int myrow = lane < ns ? st.rows[r0 + lane] : 0;
-  const int mynext = lane < ns ? st.next[myrow] : 0;
-  float myscale = 1.f;
-  if (MODE != 0 && lane < ns && mynext < 0 && rio.mode[0] + rio.mode[NV - 1] > 0)
-    myscale = rio.hdiag[-mynext - 1];
-  // load the rows, eight independent row segments in flight at a time
-  for (int i0 = 0; i0 < ns; i0 += 8) {
-    float vals[8][NV];
+  // this lane's rotation block (slot = lane) and retired-row scale (row slot = lane)
+  float om[K * K];
 #pragma unroll
-    for (int q = 0; q < 8; ++q) {
-      const int i = min(i0 + q, ns - 1);
-      const int pos = __shfl(myrow, i);
-      const int nx = __shfl(mynext, i);
-      const float sc = __shfl(myscale, i);
+  for (int ab = 0; ab < K * K; ++ab)
+    om[ab] = lane < nr ? st.rot_o[(int64_t)rt.y * 9 + (ab / K) * 3 + (ab % K)] : 0.f;
+  float sc = 1.f;
+  if (lane < ns && sl.y < 0) {
+    if (MODE == 0 && fio.mode[0] + fio.mode[NV - 1] > 0) sc = fio.hdiag[-sl.y - 1];
+    if (MODE != 0 && rio.mode[0] + rio.mode[NV - 1] > 0) sc = rio.hdiag[-sl.y - 1];
+  }
+  // requests for all rows, eight per uniform chunk; slots past ns repeat the last row and columns
+  // past nrhs read the last column, so every address is valid and only the stores are masked
+  const int64_t colc = cok ? col : nrhs - 1;
+  float x[NV][UNIT_MAX];
 #pragma unroll
-      for (int v = 0; v < NV; ++v) {
-        float val = 0.f;
-        if (cok) {
-          if (MODE == 0) {
-            val = fio.src[v][(int64_t)pos * fio.ld_src + col];
-          } else if (nx >= 0) {
-            val = rio.src_c[v][(int64_t)nx * rio.ld_c + col];
-          } else {
-            val = rio.src_nat[v][(int64_t)(-nx - 1) * rio.ld_nat + col];
-            if (rio.mode[v] == 1) val *= sc;
-          }
+  for (int c8 = 0; c8 < UNIT_MAX; c8 += 8) {
+    if (c8 < ns) {
+#pragma unroll
+      for (int i = c8; i < c8 + 8; ++i) {
+        const int li = min(i, ns - 1);
+        const int pos = __builtin_amdgcn_readlane(sl.x, li);
+        const int nx = __builtin_amdgcn_readlane(sl.y, li);
+#pragma unroll
+        for (int v = 0; v < NV; ++v) {
+          const float* src;
+          if (MODE == 0) src = fio.src[v] + (int64_t)pos * fio.ld_src;
+          else src = nx >= 0 ? rio.src_c[v] + (int64_t)nx * rio.ld_c
+                             : rio.src_nat[v] + (int64_t)(-nx - 1) * rio.ld_nat;
+          x[v][i] = src[colc];
         }
-        vals[q][v] = val;
       }
     }
-#pragma unroll
-    for (int q = 0; q < 8; ++q)
-      if (i0 + q < ns)
-#pragma unroll
-        for (int v = 0; v < NV; ++v) tile[v * UNIT_MAX * PMMF_WAVE + (i0 + q) * PMMF_WAVE + lane] = vals[q][v];
   }
+  if (MODE != 0 && rio.mode[0] + rio.mode[NV - 1] > 0) {
+#pragma unroll
+    for (int i = 0; i < UNIT_MAX; ++i) {
+      const float f = (i < ns && __builtin_amdgcn_readlane(sl.y, i) < 0) ? pmmf_readlane_f(sc, i)
+                                                                           : 1.f;
+#pragma unroll
+      for (int v = 0; v < NV; ++v)
+        if (rio.mode[v] == 1) x[v][i] *= f;
+    }
+  }
+#pragma unroll
+  for (int c8 = 0; c8 < UNIT_MAX; c8 += 8) {
+    if (c8 < ns) {
+#pragma unroll
+      for (int i = c8; i < c8 + 8; ++i)
+#pragma unroll
+        for (int v = 0; v < NV; ++v) tile[(v * UNIT_MAX + i) * PMMF_WAVE + lane] = x[v][i];
+    }
+  }
+  auto T = [&](int v, int i) -> float& { return tile[(v * UNIT_MAX + i) * PMMF_WAVE + lane]; };
   if (MODE == 0) {
     for (int q = 0; q < nr; ++q) {
-      const int* id = rloc + q * K;
-      const float* o = ro + q * K * K;
+      const int locs = __builtin_amdgcn_readlane(rt.x, q);
+      int id[K];
+      float o[K * K];
+#pragma unroll
+      for (int a = 0; a < K; ++a) id[a] = (locs >> (5 * a)) & 31;
+#pragma unroll
+      for (int ab = 0; ab < K * K; ++ab) o[ab] = pmmf_readlane_f(om[ab], q);
 #pragma unroll
       for (int v = 0; v < NV; ++v) {
-        float* t = tile + v * UNIT_MAX * PMMF_WAVE;
-        float x[K];
+        float y[K];
 #pragma unroll
-        for (int a = 0; a < K; ++a) x[a] = t[id[a] * PMMF_WAVE + lane];
+        for (int a = 0; a < K; ++a) y[a] = T(v, id[a]);
 #pragma unroll
         for (int a = 0; a < K; ++a) {
-          float sacc = 0.f;
+          float acc = 0.f;
 #pragma unroll
-          for (int b = 0; b < K; ++b) sacc += o[a * K + b] * x[b];
-          t[id[a] * PMMF_WAVE + lane] = sacc;
+          for (int b = 0; b < K; ++b) acc += o[a * K + b] * y[b];
+          T(v, id[a]) = acc;
         }
       }
     }
   } else {
     for (int q = nr - 1; q >= 0; --q) {
-      const int* id = rloc + q * K;
-      const float* o = ro + q * K * K;
-      if (MODE == 2) {
-        const float* z = tile;
-        const float* gv = tile + UNIT_MAX * PMMF_WAVE;
-        float part = gv[id[1] * PMMF_WAVE + lane] * z[id[0] * PMMF_WAVE + lane] -
-                     gv[id[0] * PMMF_WAVE + lane] * z[id[1] * PMMF_WAVE + lane];
-        part = pmmf_wave_sum_float(part);
+      const int locs = __builtin_amdgcn_readlane(rt.x, q);
+      int id[K];
+      float o[K * K];
+#pragma unroll
+      for (int a = 0; a < K; ++a) id[a] = (locs >> (5 * a)) & 31;
+#pragma unroll
+      for (int ab = 0; ab < K * K; ++ab) o[ab] = pmmf_readlane_f(om[ab], q);
+      if constexpr (MODE == 2 && NV == 2) {
+        // lanes past the last column hold a copy of it: they add nothing
+        float part = cok ? T(1, id[1]) * T(0, id[0]) - T(1, id[0]) * T(0, id[1]) : 0.f;
+        part = pmmf_wave_sum_dpp(part);
         if (lane == 0)
           rio.theta_part[(int64_t)blockIdx.y * rio.theta_stride +
-                         (st.rot_idx[q0 + q] - st.rot_base)] = part;
+                         (__builtin_amdgcn_readlane(rt.y, q) - st.rot_base)] = part;
       }
 #pragma unroll
       for (int v = 0; v < NV; ++v) {
-        float* t = tile + v * UNIT_MAX * PMMF_WAVE;
-        float x[K];
+        float y[K];
 #pragma unroll
-        for (int a = 0; a < K; ++a) x[a] = t[id[a] * PMMF_WAVE + lane];
+        for (int a = 0; a < K; ++a) y[a] = T(v, id[a]);
 #pragma unroll
         for (int a = 0; a < K; ++a) {
-          float sacc = 0.f;
+          float acc = 0.f;
 #pragma unroll
-          for (int b = 0; b < K; ++b) sacc += o[b * K + a] * x[b];
-          t[id[a] * PMMF_WAVE + lane] = sacc;
+          for (int b = 0; b < K; ++b) acc += o[b * K + a] * y[b];
+          T(v, id[a]) = acc;
         }
       }
     }
   }
-  // row data sits in lanes 0..ns-1, so every lane takes part in the shuffles below and only
-  // the stores are masked by the column bound
-  float myscale_out = 1.f;
-  if (MODE == 0 && lane < ns && mynext < 0 && fio.mode[0] + fio.mode[NV - 1] > 0)
-    myscale_out = fio.hdiag[-mynext - 1];
-  const int mygid = (MODE != 0 && lane < ns) ? st.gid[myrow] : 0;
-  for (int i = 0; i < ns; ++i) {
-    const int pos = __shfl(myrow, i);
-    const int nx = __shfl(mynext, i);
-    const float sc = __shfl(myscale_out, i);
-    const int gd = __shfl(mygid, i);
+#pragma unroll
+  for (int i = 0; i < UNIT_MAX; ++i) {
+    if (i >= ns) break;
+    const int pos = __builtin_amdgcn_readlane(sl.x, i);
+    const int nx = __builtin_amdgcn_readlane(sl.y, i);
+    const int gd = __builtin_amdgcn_readlane(sl.z, i);
+    const float f = pmmf_readlane_f(sc, i);
     if (!cok) continue;
 #pragma unroll
     for (int v = 0; v < NV; ++v) {
-      float val = tile[v * UNIT_MAX * PMMF_WAVE + i * PMMF_WAVE + lane];
+      float val = T(v, i);
       if (MODE == 0) {
         if (nx >= 0) {
           fio.dst_c[v][(int64_t)nx * fio.ld_c + col] = val;
         } else {
-          if (fio.mode[v] == 1) val *= sc;
-          else if (fio.mode[v] == 2) val /= sc;
+          if (fio.mode[v] == 1) val *= f;
+          else if (fio.mode[v] == 2) val /= f;
           fio.dst_nat[v][(int64_t)(-nx - 1) * fio.ld_nat + col] = val;
         }
       } else {
@@ -553,13 +590,8 @@ template <int K, int NV, int MODE>
 static hipError_t unit_launch(const UnitStage& st, const FwdIO& fio, const RevIO& rio,
                               hipStream_t s) {
   if (st.nu == 0) return hipSuccess;
-  constexpr int WPB = 4;
-  const size_t lds = (size_t)WPB * (NV * UNIT_MAX * PMMF_WAVE + UNIT_MAX * (K + K * K)) * 4;
-  if (lds > 64 * 1024) {
-    hipError_t e = hipFuncSetAttribute((const void*)&k_unit_sweep<K, NV, MODE>,
-                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-    if (e != hipSuccess) return e;
-  }
+  constexpr int WPB = 2;
+  const size_t lds = (size_t)WPB * NV * UNIT_MAX * PMMF_WAVE * sizeof(float);
   const int64_t nrhs = MODE == 0 ? fio.nrhs : rio.nrhs;
   dim3 grid((st.nu + WPB - 1) / WPB, (unsigned)((nrhs + PMMF_WAVE - 1) / PMMF_WAVE));
   k_unit_sweep<K, NV, MODE><<<grid, WPB * PMMF_WAVE, lds, s>>>(st, fio, rio);
