@@ -18,8 +18,7 @@ struct FindArgs {
   const int32_t* rcnt;       // [m] rotations of each cluster
   const int32_t* roff;       // [m+1] first stage-local rotation of each cluster
   const int64_t* gbase;      // [m] offset of each cluster's c x c blocks in the pools
-  float* G;                  // Gram pool
-  float* D;                  // diagonal-block pool
+  float2* GD;                // (Gram, diagonal block) pool, interleaved
   float* Q;                  // accumulated-rotation pool
   const int32_t* gid;        // [S] global id of each position
   int64_t rot0;              // global index of the stage's first rotation
@@ -40,8 +39,8 @@ struct FindArgs {
 namespace pmmf {
 hipError_t launch_fill_cluster_of(const int32_t* off, int m, int S, int32_t* cl_of, hipStream_t s);
 hipError_t launch_gram(int S, const int64_t* rp, const int32_t* ci, const float* cv,
-                       const int32_t* off, const int32_t* cl_of, const int64_t* gbase, float* G,
-                       float* D, float* Q, int cmax, hipStream_t s);
+                       const int32_t* off, const int32_t* cl_of, const int64_t* gbase,
+                       float2* GD, float* Q, int cmax, hipStream_t s);
 hipError_t launch_find(const FindArgs& a, int m, int cmax, int nt, hipStream_t s);
 size_t find_lds_bytes(int cmax);
 hipError_t launch_levelize(int m, int k, const int32_t* off, const int32_t* rcnt,

@@ -47,8 +47,8 @@ __global__ void __launch_bounds__(256) k_gram(int S, const int64_t* __restrict__
                                               const int32_t* __restrict__ off,
                                               const int32_t* __restrict__ cl_of,
                                               const int64_t* __restrict__ gbase,
-                                              float* __restrict__ G, float* __restrict__ D,
-                                              float* __restrict__ Q, int cmax) {
+                                              float2* __restrict__ GD, float* __restrict__ Q,
+                                              int cmax) {
   extern __shared__ float lds_f[];
   const int wpb = blockDim.x / PMMF_WAVE;
   const int w = pmmf_wave(), lane = pmmf_lane();
@@ -98,26 +98,29 @@ __global__ void __launch_bounds__(256) k_gram(int S, const int64_t* __restrict__
       }
     }
   }
+  // Gram halves of the interleaved (G, D) row, then the diagonal-block halves through the same
+  // accumulator (the two store passes write disjoint words)
   const size_t base = (size_t)gbase[u] + (size_t)la * c;
+  float* gd = reinterpret_cast<float*>(GD + base);
   for (int j = lane; j < c; j += PMMF_WAVE) {
-    G[base + j] = acc[j];
+    gd[2 * j] = acc[j];
     acc[j] = 0.f;
     Q[base + j] = (j == la) ? 1.f : 0.f;
   }
   const int64_t lb = lower_bound_i32(ci, a0, a1, o);
   const int64_t ub = lower_bound_i32(ci, lb, a1, o + c);
   for (int64_t t = lb + lane; t < ub; t += PMMF_WAVE) acc[ci[t] - o] = cv[t];
-  for (int j = lane; j < c; j += PMMF_WAVE) D[base + j] = acc[j];
+  for (int j = lane; j < c; j += PMMF_WAVE) gd[2 * j + 1] = acc[j];
 }
 
 hipError_t launch_gram(int S, const int64_t* rp, const int32_t* ci, const float* cv,
-                       const int32_t* off, const int32_t* cl_of, const int64_t* gbase, float* G,
-                       float* D, float* Q, int cmax, hipStream_t s) {
+                       const int32_t* off, const int32_t* cl_of, const int64_t* gbase,
+                       float2* GD, float* Q, int cmax, hipStream_t s) {
   if (S == 0) return hipSuccess;
   int wpb = 4;
   while (wpb > 1 && (size_t)wpb * cmax * 4 > 64 * 1024) wpb >>= 1;
   const size_t lds = (size_t)wpb * cmax * sizeof(float);
-  k_gram<<<(S + wpb - 1) / wpb, wpb * PMMF_WAVE, lds, s>>>(S, rp, ci, cv, off, cl_of, gbase, G, D,
+  k_gram<<<(S + wpb - 1) / wpb, wpb * PMMF_WAVE, lds, s>>>(S, rp, ci, cv, off, cl_of, gbase, GD,
                                                            Q, cmax);
   return hipGetLastError();
 }
@@ -312,23 +315,46 @@ __device__ inline int select_active(const uint32_t* mask, int nw, int rank) {
   return __shfl(found, src);
 }
 
-// The cluster's state lives in HBM as dense c x c arrays: G (Gram), D (diagonal block of the
-// active matrix) and Q (accumulated rotation).  Each thread owns the columns j = tid + q NT
-// (q < PER) and keeps its slice of the rows it needs in registers.  A step has three barriers:
-// after the partner argmax, after the serial FP64 rotation (which also picks the next seed), and
-// after the rotated rows are stored.
+// new value of slot a of a rotated (G, D) pair: sum_b O[a][b] v[b], in one fixed order so that
+// every thread that forms the same entry forms it bit-identically
+template <int K>
+__device__ inline float2 rot_entry(const float* o, int a, const float2* v) {
+  float sg = 0.f, sd = 0.f;
+#pragma unroll
+  for (int b = 0; b < K; ++b) {
+    sg = fmaf(o[a * 3 + b], v[b].x, sg);
+    sd = fmaf(o[a * 3 + b], v[b].y, sd);
+  }
+  return make_float2(sg, sd);
+}
+
+// The cluster's state lives in HBM as dense c x c arrays: GD (Gram and diagonal block of the
+// active matrix, interleaved so one 8-byte access moves both) and Q (accumulated rotation).
+// Each thread owns the columns j = tid + q NT (q < PER) and keeps its slice of the rows it needs
+// in registers.  A step has two barriers:
+//   A  after the partner argmax;
+//   B  after the serial FP64 rotation on lane 0 (wave 1 meanwhile picks the two candidates for
+//      the next seed from the active set before this step's retirement).
+// After B every thread knows O, the retired slot and the next seed i'.  It requests row i' of GD
+// before issuing this step's stores: entries of row i' outside the rotated columns T are not
+// touched by this step, and the entries at T are re-formed from the pre-rotation rows kept in
+// LDS (or, when i' is itself in T, the whole row is the one this thread just formed).  The next
+// step's scoring therefore needs no third barrier; barrier A of the next step orders this step's
+// stores before the partner rows are read.  The retirement is applied to the active mask one
+// step late (the scoring also skips the previous retiree explicitly), so wave 1 can read a mask
+// that nobody writes during the serial section.
 template <int NT, int PER, int K>
 __global__ void __launch_bounds__(NT) k_find(FindArgs A, int cmax) {
+  static_assert(NT >= 2 * PMMF_WAVE, "wave 1 selects the next seed");
   extern __shared__ float lds_f[];
   float* gdiag = lds_f;
   float* ddiag = gdiag + cmax;
-  float* rowGi = ddiag + cmax;
-  float* rowDi = rowGi + cmax;
-  int* lgid = reinterpret_cast<int*>(rowDi + cmax);
+  float2* rowbuf = reinterpret_cast<float2*>(ddiag + cmax);  // seed rows (2 parities), partners
+  int* lgid = reinterpret_cast<int*>(rowbuf + 4 * (size_t)cmax);
   uint32_t* mask = reinterpret_cast<uint32_t*>(lgid + cmax);
   constexpr int NW = NT / PMMF_WAVE;
   __shared__ Cand red1[NW], red2[NW];
-  __shared__ int sh_i, sh_e;
+  __shared__ int sh_i, sh_e, sh_c0, sh_c1;
   __shared__ float sh_O[9], sh_gn[9], sh_dn[9];
 
   const int tid = threadIdx.x;
@@ -339,13 +365,15 @@ __global__ void __launch_bounds__(NT) k_find(FindArgs A, int cmax) {
   const int rb = A.roff[u];
   const int nw = (c + 31) / 32;
   constexpr int kk = K;
-  float* __restrict__ G = A.G + A.gbase[u];
-  float* __restrict__ D = A.D + A.gbase[u];
+  float2* __restrict__ GD = A.GD + A.gbase[u];
   float* __restrict__ Q = A.Q + A.gbase[u];
+  float2* R1 = rowbuf + 2 * (size_t)cmax;
+  float2* R2 = rowbuf + 3 * (size_t)cmax;
 
   for (int j = tid; j < c; j += NT) {
-    gdiag[j] = G[(size_t)j * c + j];
-    ddiag[j] = D[(size_t)j * c + j];
+    const float2 dg = GD[(size_t)j * c + j];
+    gdiag[j] = dg.x;
+    ddiag[j] = dg.y;
     lgid[j] = A.gid[o + j];
   }
   for (int q = tid; q < nw; q += NT) {
@@ -359,33 +387,29 @@ __global__ void __launch_bounds__(NT) k_find(FindArgs A, int cmax) {
     if (tid == 0) sh_i = i0;
   }
   __syncthreads();
+  int i = r > 0 ? sh_i : 0;
+  int e_prev = -1;
+  float2 cur[PER];
+#pragma unroll
+  for (int q = 0; q < PER; ++q) {
+    const int j = tid + q * NT;
+    cur[q] = (r > 0 && j < c) ? GD[(size_t)i * c + j] : make_float2(0.f, 0.f);
+  }
 
   for (int s = 0; s < r; ++s) {
-    const int i = sh_i;
-    // the seed's rows of G and D; partner scores |G_ij| / sqrt(G_jj) over the active set,
-    // top (k - 1), lower j on ties
-    float gi[PER], di[PER];
+    float2* R0 = rowbuf + (size_t)(s & 1) * cmax;
+    // the seed's (G, D) row; partner scores |G_ij| / sqrt(G_jj) over the active set, top (k - 1),
+    // lower j on ties
     Cand b1{-1.f, INT_MAX}, b2{-1.f, INT_MAX};
 #pragma unroll
     for (int q = 0; q < PER; ++q) {
       const int j = tid + q * NT;
-      gi[q] = 0.f;
-      di[q] = 0.f;
       if (j < c) {
-        gi[q] = G[(size_t)i * c + j];
-        di[q] = D[(size_t)i * c + j];
-      }
-    }
-#pragma unroll
-    for (int q = 0; q < PER; ++q) {
-      const int j = tid + q * NT;
-      if (j < c) {
-        rowGi[j] = gi[q];
-        rowDi[j] = di[q];
-        const bool act = (mask[j >> 5] >> (j & 31)) & 1u;
+        R0[j] = cur[q];
+        const bool act = ((mask[j >> 5] >> (j & 31)) & 1u) && j != e_prev;
         if (act && j != i) {
           const float gd = gdiag[j];
-          float sc = gd > 0.f ? fabsf(gi[q]) / sqrtf(gd) : 0.f;
+          float sc = gd > 0.f ? fabsf(cur[q].x) / sqrtf(gd) : 0.f;
           if (!(sc >= 0.f)) sc = 0.f;  // NaN from an overflowed Gram entry scores 0
           Cand cnd{sc, j};
           if (better(cnd, b1)) { b2 = b1; b1 = cnd; }
@@ -403,8 +427,8 @@ __global__ void __launch_bounds__(NT) k_find(FindArgs A, int cmax) {
       }
     }
     if (pmmf_lane() == 0) { red1[pmmf_wave()] = b1; red2[pmmf_wave()] = b2; }
-    __syncthreads();
-    // every thread merges the per-wave winners (no second barrier)
+    __syncthreads();  // A
+    // every thread merges the per-wave winners
     Cand f1 = red1[0], f2 = red2[0];
 #pragma unroll
     for (int q = 1; q < NW; ++q) {
@@ -417,150 +441,181 @@ __global__ void __launch_bounds__(NT) k_find(FindArgs A, int cmax) {
     }
     const int t0 = i, t1 = f1.j, t2 = kk == 3 ? f2.j : -1;
 
-    // partner rows of G and D, and rows T of Q
-    float g1[PER], g2[PER], d1[PER], d2[PER], q0[PER], q1[PER], q2[PER];
+    // the (t1, t2) entries first (lane 0 needs them before anything else), then the partner rows
+    // of GD and rows T of Q
+    float2 x12 = make_float2(0.f, 0.f), x21 = make_float2(0.f, 0.f);
+    if (kk == 3 && tid < PMMF_WAVE) {
+      x12 = GD[(size_t)t1 * c + t2];
+      x21 = GD[(size_t)t2 * c + t1];
+    }
+    float2 p1[PER], p2[PER];
+    float q0[PER], q1[PER], q2[PER];
 #pragma unroll
     for (int q = 0; q < PER; ++q) {
       const int j = tid + q * NT;
-      g1[q] = g2[q] = d1[q] = d2[q] = q0[q] = q1[q] = q2[q] = 0.f;
+      p1[q] = p2[q] = make_float2(0.f, 0.f);
+      q0[q] = q1[q] = q2[q] = 0.f;
       if (j < c) {
-        g1[q] = G[(size_t)t1 * c + j];
-        d1[q] = D[(size_t)t1 * c + j];
+        p1[q] = GD[(size_t)t1 * c + j];
         q0[q] = Q[(size_t)t0 * c + j];
         q1[q] = Q[(size_t)t1 * c + j];
         if (kk == 3) {
-          g2[q] = G[(size_t)t2 * c + j];
-          d2[q] = D[(size_t)t2 * c + j];
+          p2[q] = GD[(size_t)t2 * c + j];
           q2[q] = Q[(size_t)t2 * c + j];
         }
       }
     }
 
-    if (tid < PMMF_WAVE) {
-      if (tid == 0) {
-        double g[3][3] = {}, d[3][3] = {}, O[3][3] = {};
-        g[0][0] = gdiag[t0];
-        d[0][0] = ddiag[t0];
-        g[1][1] = gdiag[t1];
-        d[1][1] = ddiag[t1];
-        if (kk == 3) {
-          g[2][2] = gdiag[t2];
-          d[2][2] = ddiag[t2];
-        }
-        g[0][1] = g[1][0] = rowGi[t1];
-        d[0][1] = d[1][0] = rowDi[t1];
-        if (kk == 3) {
-          g[0][2] = g[2][0] = rowGi[t2];
-          d[0][2] = d[2][0] = rowDi[t2];
-          const double g12 = 0.5 * ((double)G[(size_t)t1 * c + t2] + (double)G[(size_t)t2 * c + t1]);
-          const double d12 = 0.5 * ((double)D[(size_t)t1 * c + t2] + (double)D[(size_t)t2 * c + t1]);
-          g[1][2] = g[2][1] = g12;
-          d[1][2] = d[2][1] = d12;
-        }
-        double margin = 3.0e38;
-        if (kk == 2) {
-          double cc, ss, ta;
-          rot2(g[0][0], g[0][1], g[1][1], cc, ss, ta);
-          O[0][0] = cc; O[0][1] = -ss; O[1][0] = ss; O[1][1] = cc;
-          margin = fmin(margin, ta);
-        } else {
-          double tm, em;
-          rot3(g, O, tm, em);
-          margin = fmin(margin, fmin(tm, em));
-        }
-        // rotated k x k blocks: O g O^T and O d O^T
-        double gn[3][3] = {}, dn[3][3] = {};
-#pragma unroll
-        for (int a = 0; a < kk; ++a)
-#pragma unroll
-          for (int b = 0; b < kk; ++b) {
-            double sg = 0.0, sd = 0.0;
-#pragma unroll
-            for (int x = 0; x < kk; ++x) {
-              double tg = 0.0, td = 0.0;
-#pragma unroll
-              for (int y = 0; y < kk; ++y) { tg += g[x][y] * O[b][y]; td += d[x][y] * O[b][y]; }
-              sg += O[a][x] * tg;
-              sd += O[a][x] * td;
-            }
-            gn[a][b] = sg;
-            dn[a][b] = sd;
-          }
-        // eliminate the slot with the smallest off-diagonal norm (ties: later slot)
-        const double f0 = fmax(0.0, gn[0][0] - dn[0][0] * dn[0][0]);
-        const double f1v = fmax(0.0, gn[1][1] - dn[1][1] * dn[1][1]);
-        const double f2v = kk == 3 ? fmax(0.0, gn[2][2] - dn[2][2] * dn[2][2]) : 1e300;
-        int es = f1v <= f0 ? 1 : 0;
-        double fmin_ = es == 1 ? f1v : f0;
-        if (kk == 3 && f2v <= fmin_) { es = 2; fmin_ = f2v; }
-        {
-          // second smallest, for the (diagnostic) elimination margin
-          const double hi01 = fmax(f0, f1v), lo01 = fmin(f0, f1v);
-          const double lo2 = kk == 3 ? (f2v <= lo01 ? lo01 : fmin(hi01, f2v)) : hi01;
-          const double lo1 = fmin(lo01, f2v);
-          margin = fmin(margin, lo2 > 0.0 ? (lo2 - lo1) / lo2 : 0.0);
-        }
-        const int e = es == 0 ? t0 : (es == 1 ? t1 : t2);
-        const double dee = es == 0 ? dn[0][0] : (es == 1 ? dn[1][1] : dn[2][2]);
-        const double off2e = fmin_;
-        gdiag[t0] = (float)gn[0][0];
-        ddiag[t0] = (float)dn[0][0];
-        gdiag[t1] = (float)gn[1][1];
-        ddiag[t1] = (float)dn[1][1];
-        if (kk == 3) {
-          gdiag[t2] = (float)gn[2][2];
-          ddiag[t2] = (float)dn[2][2];
-        }
-        mask[e >> 5] &= ~(1u << (e & 31));
-        sh_e = e;
-#pragma unroll
-        for (int a = 0; a < 9; ++a) { sh_O[a] = 0.f; sh_gn[a] = 0.f; sh_dn[a] = 0.f; }
-#pragma unroll
-        for (int a = 0; a < kk; ++a)
-#pragma unroll
-          for (int b = 0; b < kk; ++b) {
-            sh_O[a * 3 + b] = (float)O[a][b];
-            sh_gn[a * 3 + b] = (float)gn[a][b];
-            sh_dn[a * 3 + b] = (float)dn[a][b];
-          }
-        // rotation log (stores only: nothing on this lane waits for them)
-        const int64_t ridx = A.rot0 + rb + s;
-        A.rot_loc[ridx * 3 + 0] = t0;
-        A.rot_loc[ridx * 3 + 1] = t1;
-        A.rot_loc[ridx * 3 + 2] = kk == 3 ? t2 : -1;
-        A.rot_gid[ridx * 3 + 0] = lgid[t0];
-        A.rot_gid[ridx * 3 + 1] = lgid[t1];
-        A.rot_gid[ridx * 3 + 2] = kk == 3 ? lgid[t2] : -1;
-#pragma unroll
-        for (int a = 0; a < 9; ++a) A.rot_o[ridx * 9 + a] = sh_O[a];
-        A.rot_ret[ridx] = lgid[e];
-        A.rot_margin[ridx] = (float)margin;
-        A.rot_lit[ridx] = 2.0 * off2e;
-        A.hdiag[lgid[e]] = (float)dee;
-        A.retflag[o + e] = 1;
+    if (tid == 0) {
+      double g[3][3] = {}, d[3][3] = {}, O[3][3] = {};
+      g[0][0] = gdiag[t0];
+      d[0][0] = ddiag[t0];
+      g[1][1] = gdiag[t1];
+      d[1][1] = ddiag[t1];
+      const float2 s01 = R0[t1];
+      g[0][1] = g[1][0] = s01.x;
+      d[0][1] = d[1][0] = s01.y;
+      if (kk == 3) {
+        g[2][2] = gdiag[t2];
+        d[2][2] = ddiag[t2];
+        const float2 s02 = R0[t2];
+        g[0][2] = g[2][0] = s02.x;
+        d[0][2] = d[2][0] = s02.y;
+        const double g12 = 0.5 * ((double)x12.x + (double)x21.x);
+        const double d12 = 0.5 * ((double)x12.y + (double)x21.y);
+        g[1][2] = g[2][1] = g12;
+        d[1][2] = d[2][1] = d12;
       }
-      // next seed row (the whole first wave), from the updated active set
-      if (s + 1 < r) {
-        const uint64_t h = pmmf_hash4(A.seed, PMMF_TAG_SEED_ROW, (uint64_t)A.p, (uint64_t)u,
-                                      (uint64_t)(s + 1));
-        const int nx = select_active(mask, nw, (int)pmmf_mulhi(h, (uint64_t)(c - s - 1)));
-        if (tid == 0) sh_i = nx;
+      double margin = 3.0e38;
+      if (kk == 2) {
+        double cc, ss, ta;
+        rot2(g[0][0], g[0][1], g[1][1], cc, ss, ta);
+        O[0][0] = cc; O[0][1] = -ss; O[1][0] = ss; O[1][1] = cc;
+        margin = fmin(margin, ta);
+      } else {
+        double tm, em;
+        rot3(g, O, tm, em);
+        margin = fmin(margin, fmin(tm, em));
+      }
+      // rotated k x k blocks: O g O^T and O d O^T
+      double gn[3][3] = {}, dn[3][3] = {};
+#pragma unroll
+      for (int a = 0; a < kk; ++a)
+#pragma unroll
+        for (int b = 0; b < kk; ++b) {
+          double sg = 0.0, sd = 0.0;
+#pragma unroll
+          for (int x = 0; x < kk; ++x) {
+            double tg = 0.0, td = 0.0;
+#pragma unroll
+            for (int y = 0; y < kk; ++y) { tg += g[x][y] * O[b][y]; td += d[x][y] * O[b][y]; }
+            sg += O[a][x] * tg;
+            sd += O[a][x] * td;
+          }
+          gn[a][b] = sg;
+          dn[a][b] = sd;
+        }
+      // eliminate the slot with the smallest off-diagonal norm (ties: later slot)
+      const double f0 = fmax(0.0, gn[0][0] - dn[0][0] * dn[0][0]);
+      const double f1v = fmax(0.0, gn[1][1] - dn[1][1] * dn[1][1]);
+      const double f2v = kk == 3 ? fmax(0.0, gn[2][2] - dn[2][2] * dn[2][2]) : 1e300;
+      int es = f1v <= f0 ? 1 : 0;
+      double fmin_ = es == 1 ? f1v : f0;
+      if (kk == 3 && f2v <= fmin_) { es = 2; fmin_ = f2v; }
+      {
+        // second smallest, for the (diagnostic) elimination margin
+        const double hi01 = fmax(f0, f1v), lo01 = fmin(f0, f1v);
+        const double lo2 = kk == 3 ? (f2v <= lo01 ? lo01 : fmin(hi01, f2v)) : hi01;
+        const double lo1 = fmin(lo01, f2v);
+        margin = fmin(margin, lo2 > 0.0 ? (lo2 - lo1) / lo2 : 0.0);
+      }
+      const int e = es == 0 ? t0 : (es == 1 ? t1 : t2);
+      const double dee = es == 0 ? dn[0][0] : (es == 1 ? dn[1][1] : dn[2][2]);
+      const double off2e = fmin_;
+      gdiag[t0] = (float)gn[0][0];
+      ddiag[t0] = (float)dn[0][0];
+      gdiag[t1] = (float)gn[1][1];
+      ddiag[t1] = (float)dn[1][1];
+      if (kk == 3) {
+        gdiag[t2] = (float)gn[2][2];
+        ddiag[t2] = (float)dn[2][2];
+      }
+      sh_e = e;
+#pragma unroll
+      for (int a = 0; a < 9; ++a) { sh_O[a] = 0.f; sh_gn[a] = 0.f; sh_dn[a] = 0.f; }
+#pragma unroll
+      for (int a = 0; a < kk; ++a)
+#pragma unroll
+        for (int b = 0; b < kk; ++b) {
+          sh_O[a * 3 + b] = (float)O[a][b];
+          sh_gn[a * 3 + b] = (float)gn[a][b];
+          sh_dn[a * 3 + b] = (float)dn[a][b];
+        }
+      // rotation log (stores only: nothing on this lane waits for them)
+      const int64_t ridx = A.rot0 + rb + s;
+      A.rot_loc[ridx * 3 + 0] = t0;
+      A.rot_loc[ridx * 3 + 1] = t1;
+      A.rot_loc[ridx * 3 + 2] = kk == 3 ? t2 : -1;
+      A.rot_gid[ridx * 3 + 0] = lgid[t0];
+      A.rot_gid[ridx * 3 + 1] = lgid[t1];
+      A.rot_gid[ridx * 3 + 2] = kk == 3 ? lgid[t2] : -1;
+#pragma unroll
+      for (int a = 0; a < 9; ++a) A.rot_o[ridx * 9 + a] = sh_O[a];
+      A.rot_ret[ridx] = lgid[e];
+      A.rot_margin[ridx] = (float)margin;
+      A.rot_lit[ridx] = 2.0 * off2e;
+      A.hdiag[lgid[e]] = (float)dee;
+      A.retflag[o + e] = 1;
+    } else if (tid >= PMMF_WAVE && tid < 2 * PMMF_WAVE && s + 1 < r) {
+      // next seed: the rank-th active index after this step's retirement is the rank-th one
+      // now if that lies below the retiree, else the (rank + 1)-th
+      const uint64_t h = pmmf_hash4(A.seed, PMMF_TAG_SEED_ROW, (uint64_t)A.p, (uint64_t)u,
+                                    (uint64_t)(s + 1));
+      const int rank = (int)pmmf_mulhi(h, (uint64_t)(c - s - 1));
+      const int c0 = select_active(mask, nw, rank);
+      const int c1 = select_active(mask, nw, rank + 1);
+      if (tid == PMMF_WAVE) { sh_c0 = c0; sh_c1 = c1; }
+    }
+    // pre-rotation partner rows, for re-forming the next seed row's entries at T
+#pragma unroll
+    for (int q = 0; q < PER; ++q) {
+      const int j = tid + q * NT;
+      if (j < c) {
+        R1[j] = p1[q];
+        if (kk == 3) R2[j] = p2[q];
       }
     }
-    __syncthreads();
+    __syncthreads();  // B
 
-    // stores: G <- O G O^T and D <- O D O^T on rows/columns T (active columns only: retired
-    // columns are never read again); Q <- O Q on rows T (all columns)
     float o_[9];
 #pragma unroll
     for (int a = 0; a < 9; ++a) o_[a] = sh_O[a];
+    const int e = sh_e;
+    const bool more = s + 1 < r;
+    const int nxt = more ? (sh_c0 < e ? sh_c0 : sh_c1) : -1;
+    const int aslot = nxt == t0 ? 0 : (nxt == t1 ? 1 : ((kk == 3 && nxt == t2) ? 2 : -1));
+    float2 nrow[PER];
+#pragma unroll
+    for (int q = 0; q < PER; ++q) {
+      const int j = tid + q * NT;
+      nrow[q] = make_float2(0.f, 0.f);
+      if (more && aslot < 0 && j < c) nrow[q] = GD[(size_t)nxt * c + j];
+    }
+    // pre-rotation values of rows T at column nxt (used when nxt is not in T)
+    float2 vn[3] = {make_float2(0.f, 0.f), make_float2(0.f, 0.f), make_float2(0.f, 0.f)};
+    if (more && aslot < 0) {
+      vn[0] = R0[nxt];
+      vn[1] = R1[nxt];
+      if (kk == 3) vn[2] = R2[nxt];
+    }
+    if (tid == 0) mask[e >> 5] &= ~(1u << (e & 31));
+
+    // stores: GD <- O GD O^T on rows/columns T (active columns only: retired columns are never
+    // read again); Q <- O Q on rows T (all columns)
     const int Tt[3] = {t0, t1, t2};
     if (tid < kk * kk) {
       const int a = tid / kk, b = tid % kk;
-      const int ta = a == 0 ? t0 : (a == 1 ? t1 : t2);
-      const int tb = b == 0 ? t0 : (b == 1 ? t1 : t2);
-      G[(size_t)ta * c + tb] = sh_gn[a * 3 + b];
-      D[(size_t)ta * c + tb] = sh_dn[a * 3 + b];
+      GD[(size_t)Tt[a] * c + Tt[b]] = make_float2(sh_gn[a * 3 + b], sh_dn[a * 3 + b]);
     }
 #pragma unroll
     for (int q = 0; q < PER; ++q) {
@@ -574,25 +629,31 @@ __global__ void __launch_bounds__(NT) k_find(FindArgs A, int cmax) {
         Q[(size_t)t1 * c + j] = o_[3] * q0[q] + o_[4] * q1[q] + o_[5] * q2[q];
         Q[(size_t)t2 * c + j] = o_[6] * q0[q] + o_[7] * q1[q] + o_[8] * q2[q];
       }
+      const int bj = j == t0 ? 0 : (j == t1 ? 1 : ((kk == 3 && j == t2) ? 2 : -1));
+      if (bj >= 0) {
+        // column j is in T: the next seed row's entry there
+        if (more) {
+          if (aslot >= 0) nrow[q] = make_float2(sh_gn[aslot * 3 + bj], sh_dn[aslot * 3 + bj]);
+          else nrow[q] = rot_entry<K>(o_, bj, vn);
+        }
+        continue;
+      }
       const bool a_now = (mask[j >> 5] >> (j & 31)) & 1u;
-      if (!a_now || j == t0 || j == t1 || j == t2) continue;
-      const float gv[3] = {gi[q], g1[q], g2[q]};
-      const float dv[3] = {di[q], d1[q], d2[q]};
+      if (!a_now) continue;
+      const float2 v[3] = {cur[q], p1[q], p2[q]};
 #pragma unroll
       for (int a = 0; a < K; ++a) {
-        float sg = 0.f, sd = 0.f;
-#pragma unroll
-        for (int b = 0; b < K; ++b) {
-          sg += o_[a * 3 + b] * gv[b];
-          sd += o_[a * 3 + b] * dv[b];
-        }
-        G[(size_t)Tt[a] * c + j] = sg;
-        D[(size_t)Tt[a] * c + j] = sd;
-        if (sg != 0.f || gv[a] != 0.f) G[(size_t)j * c + Tt[a]] = sg;
-        if (sd != 0.f || dv[a] != 0.f) D[(size_t)j * c + Tt[a]] = sd;
+        const float2 nv = rot_entry<K>(o_, a, v);
+        GD[(size_t)Tt[a] * c + j] = nv;
+        if (nv.x != 0.f || nv.y != 0.f || v[a].x != 0.f || v[a].y != 0.f)
+          GD[(size_t)j * c + Tt[a]] = nv;
+        if (a == aslot) nrow[q] = nv;
       }
     }
-    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < PER; ++q) cur[q] = nrow[q];
+    e_prev = e;
+    i = nxt;
   }
 }
 
@@ -614,8 +675,8 @@ static hipError_t find_launch_k(const FindArgs& a, int m, int cmax, size_t lds, 
 }
 
 size_t find_lds_bytes(int cmax) {
-  return (size_t)cmax * 4 * sizeof(float) + (size_t)cmax * sizeof(int) +
-         (size_t)((cmax + 31) / 32) * 4;
+  return (size_t)cmax * 2 * sizeof(float) + (size_t)cmax * 4 * sizeof(float2) +
+         (size_t)cmax * sizeof(int) + (size_t)((cmax + 31) / 32) * 4;
 }
 
 hipError_t launch_find(const FindArgs& a, int m, int cmax, int nt, hipStream_t s) {
@@ -625,13 +686,13 @@ hipError_t launch_find(const FindArgs& a, int m, int cmax, int nt, hipStream_t s
     if (cmax <= 512) return find_launch_k<512, 1>(a, m, cmax, lds, s);
     if (cmax <= 1024) return find_launch_k<512, 2>(a, m, cmax, lds, s);
     if (cmax <= 2048) return find_launch_k<512, 4>(a, m, cmax, lds, s);
-    if (cmax <= 4096) return find_launch_k<512, 8>(a, m, cmax, lds, s);
+    if (cmax <= 3072) return find_launch_k<512, 6>(a, m, cmax, lds, s);
   } else {
     if (cmax <= 256) return find_launch_k<256, 1>(a, m, cmax, lds, s);
     if (cmax <= 512) return find_launch_k<256, 2>(a, m, cmax, lds, s);
     if (cmax <= 1024) return find_launch_k<256, 4>(a, m, cmax, lds, s);
     if (cmax <= 2048) return find_launch_k<256, 8>(a, m, cmax, lds, s);
-    if (cmax <= 4096) return find_launch_k<256, 16>(a, m, cmax, lds, s);
+    if (cmax <= 3072) return find_launch_k<256, 12>(a, m, cmax, lds, s);
   }
   return hipErrorInvalidValue;
 }

@@ -76,7 +76,8 @@ int64_t read_i64(const int64_t* dptr, hipStream_t s) {
   return v;
 }
 
-constexpr int CMAX_LIMIT = 4096;   // largest cluster (dense c x c Gram, diagonal block, Q)
+constexpr int CMAX_LIMIT = 3072;   // largest cluster (dense c x c Gram, diagonal block, Q;
+                                    // the search keeps four of its rows in LDS)
 
 }  // namespace
 
@@ -532,9 +533,8 @@ extern "C" int mmf_factor(int64_t n, int64_t nnz, const int64_t* d_rowptr, const
     for (int32_t c : sc.sizes) g += (int64_t)c * c;
     pool = std::max(pool, g);
   }
-  DBuf G, D, Q, retflag, keep, scan, cnt, loss_row, overflow, gid_cur, tbase;
-  G.ensure(pool * sizeof(float));
-  D.ensure(pool * sizeof(float));
+  DBuf GD, Q, retflag, keep, scan, cnt, loss_row, overflow, gid_cur, tbase;
+  GD.ensure(pool * sizeof(float2));
   Q.ensure(pool * sizeof(float));
   retflag.ensure(n);
   keep.ensure((n + 1) * sizeof(int32_t));
@@ -569,7 +569,7 @@ extern "C" int mmf_factor(int64_t n, int64_t nnz, const int64_t* d_rowptr, const
     // cluster Grams, diagonal blocks, identity accumulators
     HIPCHK(pmmf::launch_gram(S, M.rp.as<int64_t>(), M.ci.as<int32_t>(), M.cv.as<float>(),
                              sd.off.as<int32_t>(), sd.cl_of.as<int32_t>(), sd.gbase.as<int64_t>(),
-                             G.as<float>(), D.as<float>(), Q.as<float>(), cm, s));
+                             GD.as<float2>(), Q.as<float>(), cm, s));
     // greedy rotation search in every cluster
     pmmf::FindArgs fa;
     fa.p = (int)pi + 1;
@@ -580,8 +580,7 @@ extern "C" int mmf_factor(int64_t n, int64_t nnz, const int64_t* d_rowptr, const
     fa.rcnt = sd.rcnt.as<int32_t>();
     fa.roff = sd.roff.as<int32_t>();
     fa.gbase = sd.gbase.as<int64_t>();
-    fa.G = G.as<float>();
-    fa.D = D.as<float>();
+    fa.GD = GD.as<float2>();
     fa.Q = Q.as<float>();
     fa.gid = sd.gid.as<int32_t>();
     fa.rot0 = rot_base;
@@ -628,11 +627,11 @@ extern "C" int mmf_factor(int64_t n, int64_t nnz, const int64_t* d_rowptr, const
       upload(tbase, tb, s);
       HIPCHK(pmmf::launch_transpose_blocks(sd.m, sd.off.as<int32_t>(), sd.gbase.as<int64_t>(),
                                            tbase.as<int64_t>(), tb[sd.m], Q.as<float>(),
-                                           G.as<float>(), s));
+                                           GD.as<float>(), s));
     }
     for (int which = 0; which < 2; ++which) {
       Csr& Z = which == 0 ? Qr : Qt;
-      const float* pool_src = which == 0 ? Q.as<float>() : G.as<float>();
+      const float* pool_src = which == 0 ? Q.as<float>() : GD.as<float>();
       Z.n = S;
       Z.rp.ensure((S + 1) * sizeof(int64_t));
       HIPCHK(pmmf::launch_qbar_count(S, sd.off.as<int32_t>(), sd.cl_of.as<int32_t>(),
