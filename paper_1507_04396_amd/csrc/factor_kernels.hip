@@ -1057,60 +1057,105 @@ __global__ void __launch_bounds__(256) k_left(int S, int fill, const int64_t* __
     const int ov = off[vmin];
     const int lim = off[vmin + 1];
     int bmin = INT_MAX, bmax = -1;
-    // lists with entries in this cluster, in ascending list order (deterministic sums)
-    for (int li = 0; li < nq; ++li) {
-      if (ncl[li] != vmin) continue;
-      int64_t cu = cur[li];
-      const int64_t e = en[li];
-      const float qq = qv[li];
-      while (cu < e) {
-        const int64_t idx = cu + lane;
-        const int col = idx < e ? wci[idx] : INT_MAX;
-        const bool in = col < lim;
-        const float val = in ? wcv[idx] : 0.f;
-        const uint64_t bal = __ballot(in);
-        const int n = __popcll(bal);
-        if (in) {
-          const int b = col - ov;
-          acc[b] += qq * val;
-          bmin = min(bmin, b);
-          bmax = max(bmax, b);
+    // lists with entries in this cluster, in ascending list order (deterministic sums); the
+    // first 64-entry chunk of up to eight of them is requested together
+    for (int g0 = 0; g0 < nq; g0 += PMMF_WAVE) {
+      uint64_t sel = __ballot(g0 + lane < nq && ncl[g0 + lane] == vmin);
+      while (sel) {
+        int ids[8];
+        int64_t cu[8], ee[8];
+        float qq[8], valv[8];
+        int colv[8];
+#pragma unroll
+        for (int b = 0; b < 8; ++b) {
+          ids[b] = -1;
+          if (sel) {
+            ids[b] = g0 + (__ffsll((unsigned long long)sel) - 1);
+            sel &= sel - 1;
+          }
+          cu[b] = ids[b] >= 0 ? cur[ids[b]] : 0;
+          ee[b] = ids[b] >= 0 ? en[ids[b]] : 0;
+          qq[b] = ids[b] >= 0 ? qv[ids[b]] : 0.f;
+          const int64_t idx = cu[b] + lane;
+          colv[b] = idx < ee[b] ? wci[idx] : INT_MAX;
+          valv[b] = idx < ee[b] ? wcv[idx] : 0.f;
         }
-        cu += n;
-        if (n < PMMF_WAVE) {
-          // the first lane past the run holds the list's next column
-          const int nc = __shfl(col, n);
-          if (lane == 0) ncol[li] = nc;
-          break;
+#pragma unroll
+        for (int b = 0; b < 8; ++b) {
+          if (ids[b] < 0) break;
+          int64_t c_ = cu[b];
+          const int64_t e_ = ee[b];
+          int col = colv[b];
+          float val = valv[b];
+          while (true) {
+            const bool in = col < lim;
+            const int n = __popcll(__ballot(in));
+            if (in) {
+              const int bb = col - ov;
+              acc[bb] += qq[b] * val;
+              bmin = min(bmin, bb);
+              bmax = max(bmax, bb);
+            }
+            c_ += n;
+            if (n < PMMF_WAVE) {
+              // the first lane past the run holds the list's next column
+              const int nc = __shfl(col, n);
+              if (lane == 0) ncol[ids[b]] = nc;
+              break;
+            }
+            if (c_ >= e_) {
+              if (lane == 0) ncol[ids[b]] = INT_MAX;
+              break;
+            }
+            const int64_t idx = c_ + lane;
+            col = idx < e_ ? wci[idx] : INT_MAX;
+            val = idx < e_ ? wcv[idx] : 0.f;
+          }
+          if (lane == 0) {
+            cur[ids[b]] = c_;
+            ncl[ids[b]] = -1;  // refreshed below, for all advanced lists at once
+          }
         }
-      }
-      if (cu >= e && lane == 0) ncol[li] = INT_MAX;
-      if (lane == 0) {
-        cur[li] = cu;
-        ncl[li] = -1;  // refreshed below, for all advanced lists at once
       }
     }
     for (int li = lane; li < nq; li += PMMF_WAVE)
       if (ncl[li] == -1) ncl[li] = ncol[li] < INT_MAX ? cl_of[ncol[li]] : INT_MAX;
     bmin = pmmf_wave_min_int(bmin);
     bmax = pmmf_wave_max_int(bmax);
-    for (int bb = bmin; bb <= bmax; bb += PMMF_WAVE) {
-      const int j = bb + lane;
-      float val = 0.f;
-      if (j <= bmax) { val = acc[j]; acc[j] = 0.f; }
-      const int colpos = ov + j;
-      if (surv) {
-        const bool keep = val != 0.f && next[colpos] >= 0;
-        const uint64_t b = __ballot(keep);
-        if (fill && keep) {
-          const int64_t pos = ocur + pmmf_lanes_below(b);
-          oci[pos] = next[colpos];
-          ocv[pos] = val;
+    // the cluster's accumulated run, eight 64-column chunks per round (their next positions are
+    // requested together, only where the value is nonzero)
+    for (int bb0 = bmin; bb0 <= bmax; bb0 += 8 * PMMF_WAVE) {
+      float vv[8];
+      int nxv[8];
+#pragma unroll
+      for (int t = 0; t < 8; ++t) {
+        const int j = bb0 + t * PMMF_WAVE + lane;
+        vv[t] = 0.f;
+        nxv[t] = -1;
+        if (j <= bmax) {
+          vv[t] = acc[j];
+          acc[j] = 0.f;
+          if (vv[t] != 0.f) nxv[t] = next[ov + j];
         }
-        ocur += __popcll(b);
-      } else if (fill && val != 0.f && colpos != a) {
-        const double v2 = (double)val * (double)val;
-        loss += next[colpos] >= 0 ? 2.0 * v2 : v2;
+      }
+#pragma unroll
+      for (int t = 0; t < 8; ++t) {
+        if (bb0 + t * PMMF_WAVE > bmax) break;
+        const int colpos = ov + bb0 + t * PMMF_WAVE + lane;
+        const float val = vv[t];
+        if (surv) {
+          const bool keep = val != 0.f && nxv[t] >= 0;
+          const uint64_t b = __ballot(keep);
+          if (fill && keep) {
+            const int64_t pos = ocur + pmmf_lanes_below(b);
+            oci[pos] = nxv[t];
+            ocv[pos] = val;
+          }
+          ocur += __popcll(b);
+        } else if (fill && val != 0.f && colpos != a) {
+          const double v2 = (double)val * (double)val;
+          loss += nxv[t] >= 0 ? 2.0 * v2 : v2;
+        }
       }
     }
   }
