@@ -7,8 +7,9 @@ rotation search, two-sided rotation and peeling, and the core) of the n = 262,14
 
 Beside it the same JSON line reports the matrix-free apply and the adjoint (mmf_apply,
 mmf_backward) on the factorization of the 256 x 256 grid Laplacian with 256 right-hand sides, as
-algorithmic GB/s, the per-stage phase split, a roofline entry for the dominant kernel, and the FP64
-oracle timed on the host as a CPU baseline.
+algorithmic GB/s, 50 steps of angle refinement on that factorization, the per-stage phase split,
+a roofline entry for the dominant kernel, and the FP64 oracle timed on the host as a CPU
+baseline.
 """
 from __future__ import annotations
 
@@ -50,6 +51,7 @@ def main():
     ap.add_argument("--workload", default="knn3d_n262144")
     ap.add_argument("--apply-workload", default="grid2d_n65536")
     ap.add_argument("--nrhs", type=int, default=256)
+    ap.add_argument("--refine-steps", type=int, default=50)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample-n", type=int, default=32768)
     args = ap.parse_args()
@@ -140,6 +142,26 @@ def main():
                   + 3 * log_bytes + 3 * core * core * 4 + Rb * 4 + B.n * 4)
     apply_gbs = apply_bytes / (apply_ms * 1e-3) / 1e9
     back_gbs = back_bytes / (back_ms * 1e-3) / 1e9
+    # ----------------------------------------------------------------- angle refinement
+    from paper_1507_04396_amd.refine import AngleRefiner
+    log(f"[bench] angle refinement on {args.apply_workload}: {args.refine_steps} Adam steps, "
+        f"{args.nrhs} probes")
+    rpB, ciB, cvB = device_csr(B, torch)
+    refiner = AngleRefiner(fb, rpB, ciB, cvB, lr=1e-3, optimizer="adam")
+    refiner.run(2, args.nrhs, seed=5)
+    torch.cuda.synchronize()
+    e0.record(st_)
+    hist = refiner.run(args.refine_steps, args.nrhs, seed=6)
+    e1.record(st_)
+    torch.cuda.synchronize()
+    refine_ms = e0.elapsed_time(e1) / max(1, args.refine_steps)
+    hist = hist.cpu().numpy()
+    refine = {"workload": f"{args.apply_workload} factorization, Hutchinson estimate of "
+                          f"||A - U^T H U||_F^2 with {args.nrhs} fresh N(0,1) probes per step, "
+                          f"Adam lr 1e-3 on theta and H",
+              "steps": args.refine_steps, "ms_per_step": round(refine_ms, 4),
+              "loss_first5": round(float(hist[:5].mean()), 4),
+              "loss_last5": round(float(hist[-5:].mean()), 4)}
     fb.close()
 
     # ----------------------------------------------------------------- roofline (dominant kernel)
@@ -190,6 +212,7 @@ def main():
         "backward": {"workload": f"{args.apply_workload} factorization, {args.nrhs} RHS",
                      "ms": round(back_ms, 4), "algorithmic_GBps": round(back_gbs, 1),
                      "frac_hbm": round(back_gbs / HBM_PEAK_GBS, 4)},
+        "refine": refine,
         "roofline": roofline,
         "cpu_baseline": cpu,
         "stages": [{k2: (round(v, 4) if isinstance(v, float) else v) for k2, v in st.items()}

@@ -228,6 +228,17 @@ int mmf_pcg(mmf_handle h, int64_t n, const int64_t* d_rowptr, const int32_t* d_c
             const float* d_val, const float* d_b, double* d_x, int64_t nrhs, double tol,
             int32_t max_iter, double inner_reduction, void* stream, mmf_pcg_info* out);
 
+/*
+ * mmf_spmm — Y = A X for a CSR matrix (device) and row-major [n][ld] blocks X, Y (device, no
+ * aliasing).  The product that the factorization approximates (Sec. 2.4 uses A~ v in its place);
+ * angle refinement contrasts it with mmf_apply on random probes, ||A x - A~ x||^2 being an
+ * unbiased estimate of the objective ||A - A~||_F^2 of Eq. 1 for x ~ N(0, I).
+ * One wave per row, one lane per column; each row's nonzeros are summed in ascending order.
+ * Asynchronous on `stream`.  Errors: MMF_EINVAL, MMF_EDEVICE.
+ */
+int mmf_spmm(int64_t n, const int64_t* d_rowptr, const int32_t* d_colind, const float* d_val,
+             const float* d_x, float* d_y, int64_t nrhs, int64_t ld, void* stream);
+
 /* Free the handle and all device memory it owns (synchronizes its stream). */
 int mmf_destroy(mmf_handle h);
 

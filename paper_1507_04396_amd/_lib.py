@@ -73,6 +73,7 @@ SIGNATURES = {
     "mmf_set_params": [H, P, P, P, P],
     "mmf_pcg": [H, I64, P, P, P, P, P, I64, ctypes.c_double, I32, ctypes.c_double, P,
                 ctypes.POINTER(mmf_pcg_info)],
+    "mmf_spmm": [I64, P, P, P, P, P, I64, I64, P],
     "mmf_destroy": [H],
     "mmf_last_error": [],
 }

@@ -235,7 +235,9 @@ class MMFApply(torch.autograd.Function):
     @staticmethod
     def backward(ctx, ybar):
         (x,) = ctx.saved_tensors
-        xb, hdb, hcb, thb = ctx.fac.backward(x.detach(), ybar.contiguous())
-        if x.dim() == 1:
+        need = ctx.needs_input_grad
+        want = tuple(nm for nm, w in zip(("x", "theta", "hdiag", "hcore"), need[:4]) if w)
+        xb, hdb, hcb, thb = ctx.fac.backward(x.detach(), ybar.contiguous(), want=want)
+        if xb is not None and x.dim() == 1:
             xb = xb[:, 0]
         return xb, thb, hdb, hcb, None

@@ -16,15 +16,27 @@ namespace pmmf {
 __global__ void k_spmm_f32(int64_t n, const int64_t* __restrict__ rp, const int32_t* __restrict__ ci,
                            const float* __restrict__ cv, const float* __restrict__ X,
                            float* __restrict__ Y, int64_t nrhs, int64_t ld) {
+  // one wave per row, lane = right-hand side; eight nonzeros per round so their rows of X are
+  // requested together (summed in ascending nonzero order)
   const int64_t row = (int64_t)blockIdx.x * (blockDim.x / PMMF_WAVE) + pmmf_wave();
   if (row >= n) return;
   const int lane = pmmf_lane();
   const int64_t b0 = rp[row], b1 = rp[row + 1];
   for (int64_t c0 = 0; c0 < nrhs; c0 += PMMF_WAVE) {
     const int64_t col = c0 + lane;
+    const int64_t colc = col < nrhs ? col : nrhs - 1;
     float acc = 0.f;
-    if (col < nrhs)
-      for (int64_t t = b0; t < b1; ++t) acc += cv[t] * X[(int64_t)ci[t] * ld + col];
+    for (int64_t t0 = b0; t0 < b1; t0 += 8) {
+      float w[8], xv[8];
+#pragma unroll
+      for (int q = 0; q < 8; ++q) {
+        const int64_t t = t0 + q < b1 ? t0 + q : b1 - 1;
+        w[q] = t0 + q < b1 ? cv[t] : 0.f;
+        xv[q] = X[(int64_t)ci[t] * ld + colc];
+      }
+#pragma unroll
+      for (int q = 0; q < 8; ++q) acc += w[q] * xv[q];
+    }
     if (col < nrhs) Y[row * ld + col] = acc;
   }
 }
@@ -292,4 +304,24 @@ extern "C" int mmf_pcg(mmf_handle h, int64_t n, const int64_t* d_rowptr, const i
     pmmf_host_detail::set_error(e.msg);
     return e.code;
   }
+}
+
+extern "C" int mmf_spmm(int64_t n, const int64_t* d_rowptr, const int32_t* d_colind,
+                        const float* d_val, const float* d_x, float* d_y, int64_t nrhs,
+                        int64_t ld, void* stream) {
+  if (n < 0 || nrhs < 0 || ld < nrhs || (n > 0 && (!d_rowptr || !d_colind || !d_val)) ||
+      (n > 0 && nrhs > 0 && (!d_x || !d_y)) || (d_x && d_x == d_y)) {
+    pmmf_host_detail::set_error("mmf_spmm: bad arguments");
+    return MMF_EINVAL;
+  }
+  if (n == 0 || nrhs == 0) return MMF_OK;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  const unsigned blocks = (unsigned)((n + 3) / 4);
+  pmmf::k_spmm_f32<<<blocks, 256, 0, s>>>(n, d_rowptr, d_colind, d_val, d_x, d_y, nrhs, ld);
+  const hipError_t e = hipGetLastError();
+  if (e != hipSuccess) {
+    pmmf_host_detail::set_error(std::string("mmf_spmm: ") + hipGetErrorString(e));
+    return MMF_EDEVICE;
+  }
+  return MMF_OK;
 }

@@ -34,3 +34,20 @@ def rel_err(a, b):
     b = np.asarray(b, dtype=np.float64)
     den = np.abs(b).max()
     return float(np.abs(a - b).max() / (den if den > 0 else 1.0))
+
+
+def grid_sub_instance():
+    """Leading 1,024 x 1,024 principal submatrix of the 256 x 256 grid Laplacian (4 grid rows)."""
+    import workloads
+    A = workloads.make_matrix("grid2d_n65536").to_scipy()[:1024, :1024]
+    return workloads._csr_from_scipy(A)
+
+
+def import_oracle(ref):
+    """Load an oracle factorization into the HIP library through mmf_import."""
+    from paper_1507_04396_amd.api import Factorization
+    lg = oracle_log(ref)
+    return Factorization.import_log(lg["n"], lg["k"], lg["core"], lg["stage_sizes"],
+                                    lg["stage_clusters"], lg["cluster_sizes"], lg["rot_ids"],
+                                    lg["rot_o"], lg["rot_retired"], lg["hdiag"], lg["core_ids"],
+                                    lg["hcore"])

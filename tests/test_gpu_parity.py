@@ -14,7 +14,7 @@ import pytest
 import oracle
 import oracle.pmmf_oracle as om
 import workloads
-from helpers import TIE, first_divergence, oracle_log, rel_err
+from helpers import TIE, first_divergence, grid_sub_instance, import_oracle, oracle_log, rel_err
 
 torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
@@ -144,12 +144,7 @@ def test_factor_grid2d_n65536_full_size():
 # --------------------------------------------------------------------------- apply / inverse
 
 def _import(ref):
-    from paper_1507_04396_amd.api import Factorization
-    lg = oracle_log(ref)
-    return Factorization.import_log(lg["n"], lg["k"], lg["core"], lg["stage_sizes"],
-                                    lg["stage_clusters"], lg["cluster_sizes"], lg["rot_ids"],
-                                    lg["rot_o"], lg["rot_retired"], lg["hdiag"], lg["core_ids"],
-                                    lg["hcore"])
+    return import_oracle(ref)
 
 
 APPLY = [
@@ -226,9 +221,7 @@ def test_apply_inverse_reports_singular_core():
 # --------------------------------------------------------------------------- adjoint
 
 def _sub_instance():
-    """Leading 1,024 x 1,024 principal submatrix of the 256 x 256 grid Laplacian (4 grid rows)."""
-    A = workloads.make_matrix("grid2d_n65536").to_scipy()[:1024, :1024]
-    return workloads._csr_from_scipy(A)
+    return grid_sub_instance()
 
 
 def test_backward_matches_oracle_adjoint_on_sub_instance():
