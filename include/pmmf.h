@@ -87,7 +87,8 @@ typedef struct {
   int64_t nnz;           /* nonzeros of the stage's active matrix A_{p-1}[S_{p-1}, S_{p-1}]     */
   int64_t max_cluster;   /* largest cluster of the stage                                        */
   int32_t max_depth;     /* deepest chain of dependent rotations inside one cluster             */
-  int32_t pad;
+  int32_t dense_gram;    /* 1 if the stage's Gram took the dense matrix-core form (fill >= 0.1,
+                            at most 16384 active rows), 0 for the sparse row-merge form        */
   double  loss;          /* residual contributed by this stage's retirements (FP64)             */
   double  gram_ms;       /* device time of the cluster Gram / diagonal-block kernel             */
   double  find_ms;       /* device time of the greedy rotation search (all clusters, one launch) */

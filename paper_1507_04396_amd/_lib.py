@@ -49,7 +49,7 @@ class mmf_stage_info(ctypes.Structure):
     _fields_ = [("size", ctypes.c_int64), ("rotations", ctypes.c_int64),
                 ("clusters", ctypes.c_int64), ("nnz", ctypes.c_int64),
                 ("max_cluster", ctypes.c_int64), ("max_depth", ctypes.c_int32),
-                ("pad", ctypes.c_int32), ("loss", ctypes.c_double),
+                ("dense_gram", ctypes.c_int32), ("loss", ctypes.c_double),
                 ("gram_ms", ctypes.c_double), ("find_ms", ctypes.c_double),
                 ("rotate_ms", ctypes.c_double), ("find_bytes", ctypes.c_int64)]
 

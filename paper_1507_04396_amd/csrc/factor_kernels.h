@@ -41,6 +41,9 @@ hipError_t launch_fill_cluster_of(const int32_t* off, int m, int S, int32_t* cl_
 hipError_t launch_gram(int S, const int64_t* rp, const int32_t* ci, const float* cv,
                        const int32_t* off, const int32_t* cl_of, const int64_t* gbase,
                        float2* GD, float* Q, int cmax, hipStream_t s);
+hipError_t launch_gram_dense(int S, const int64_t* rp, const int32_t* ci, const float* cv,
+                             float* dense, const int32_t* off, int m, const int64_t* gbase,
+                             float2* GD, float* Q, int cmax, hipStream_t s);
 hipError_t launch_find(const FindArgs& a, int m, int cmax, int nt, hipStream_t s);
 size_t find_lds_bytes(int cmax);
 hipError_t launch_levelize(int m, int k, const int32_t* off, const int32_t* rcnt,

@@ -93,8 +93,22 @@ __global__ void __launch_bounds__(256) k_gram(int S, const int64_t* __restrict__
 #pragma unroll
       for (int q = 0; q < 4; ++q) {
         if (sl[q] + lane < su[q]) acc[pc[q] - o] += sw[q] * pv[q];
-        for (int64_t e = sl[q] + PMMF_WAVE + lane; e < su[q]; e += PMMF_WAVE)
-          acc[ci[e] - o] += sw[q] * cv[e];
+        // the rest of the segment, eight 64-entry chunks requested at a time (entries of one
+        // segment hit distinct columns, so only the segment order fixes the sums)
+        for (int64_t e0 = sl[q] + PMMF_WAVE; e0 < su[q]; e0 += 8 * PMMF_WAVE) {
+          int cc[8];
+          float vv[8];
+#pragma unroll
+          for (int t = 0; t < 8; ++t) {
+            const int64_t e = e0 + t * PMMF_WAVE + lane;
+            const bool ok = e < su[q];
+            cc[t] = ok ? ci[e] : o;
+            vv[t] = ok ? cv[e] : 0.f;
+          }
+#pragma unroll
+          for (int t = 0; t < 8; ++t)
+            if (e0 + t * PMMF_WAVE + lane < su[q]) acc[cc[t] - o] += sw[q] * vv[t];
+        }
       }
     }
   }
@@ -111,6 +125,104 @@ __global__ void __launch_bounds__(256) k_gram(int S, const int64_t* __restrict__
   const int64_t ub = lower_bound_i32(ci, lb, a1, o + c);
   for (int64_t t = lb + lane; t < ub; t += PMMF_WAVE) acc[ci[t] - o] = cv[t];
   for (int j = lane; j < c; j += PMMF_WAVE) gd[2 * j + 1] = acc[j];
+}
+
+// ------------------------------------------------------------------------------------------
+// Dense form of the cluster Gram for dense active matrices (late stages).  The active matrix is
+// expanded to a row-major S x S array; cluster u's Gram G = A[:, B_u]^T A[:, B_u] is then a
+// product of two column slices, computed in 32 x 32 tiles on v_mfma_f32_16x16x4f32 (one 16 x 16
+// quarter per wave; A operand lane l holds (row l % 16, k = l / 16), B operand (k = l / 16,
+// column l % 16), result row 4 (l / 16) + r, column l % 16 in register r).  Only tiles with
+// ti <= tj are computed; each is stored at (ti, tj) and transposed at (tj, ti).  The diagonal
+// block D is read from the same array (row i of the block = row o + i of A), Q starts at I.
+__global__ void k_densify(int S, const int64_t* __restrict__ rp, const int32_t* __restrict__ ci,
+                          const float* __restrict__ cv, float* __restrict__ dense) {
+  const int row = blockIdx.x * (blockDim.x / PMMF_WAVE) + pmmf_wave();
+  if (row >= S) return;
+  for (int64_t t = rp[row] + pmmf_lane(); t < rp[row + 1]; t += PMMF_WAVE)
+    dense[(size_t)row * S + ci[t]] = cv[t];
+}
+
+typedef float pmmf_gf4 __attribute__((ext_vector_type(4)));
+constexpr int DG_T = 32, DG_K = 128, DG_PER = DG_T * DG_K / 256;
+__global__ void __launch_bounds__(256) k_gram_dense(int S, const float* __restrict__ dense,
+                                                    const int32_t* __restrict__ off,
+                                                    const int64_t* __restrict__ gbase,
+                                                    float2* __restrict__ GD, float* __restrict__ Q,
+                                                    int ntmax) {
+  __shared__ float As[DG_T][DG_K + 1];
+  __shared__ float Bs[DG_K][DG_T + 1];
+  const int u = blockIdx.y;
+  const int o = off[u], c = off[u + 1] - o;
+  const int nt = (c + DG_T - 1) / DG_T;
+  // upper-triangle tile (ti, tj), ti <= tj, from the linear block index
+  int t = blockIdx.x, ti = 0;
+  while (ti < ntmax && t >= ntmax - ti) { t -= ntmax - ti; ++ti; }
+  const int tj = ti + t;
+  if (ti >= nt || tj >= nt) return;
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  const int wm = (w >> 1) * 16, wn = (w & 1) * 16;
+  const int ca = o + ti * DG_T, cb = o + tj * DG_T;  // first columns of the two slices
+  const int lima = min(DG_T, c - ti * DG_T), limb = min(DG_T, c - tj * DG_T);
+  float ra[DG_PER], rb[DG_PER];
+  auto fetch = [&](int k0) {
+#pragma unroll
+    for (int p = 0; p < DG_PER; ++p) {
+      const int q = tid + p * 256;
+      const int k = q / DG_T, m = q % DG_T;
+      const bool okk = k0 + k < S;
+      const size_t rowoff = (size_t)(k0 + k) * S;
+      ra[p] = (okk && m < lima) ? dense[rowoff + ca + m] : 0.f;
+      rb[p] = (okk && m < limb) ? dense[rowoff + cb + m] : 0.f;
+    }
+  };
+  pmmf_gf4 acc = {0.f, 0.f, 0.f, 0.f};
+  fetch(0);
+  for (int k0 = 0; k0 < S; k0 += DG_K) {
+#pragma unroll
+    for (int p = 0; p < DG_PER; ++p) {
+      const int q = tid + p * 256;
+      const int k = q / DG_T, m = q % DG_T;
+      As[m][k] = ra[p];
+      Bs[k][m] = rb[p];
+    }
+    __syncthreads();
+    if (k0 + DG_K < S) fetch(k0 + DG_K);
+#pragma unroll 8
+    for (int kk = 0; kk < DG_K; kk += 4) {
+      const float av = As[wm + (lane & 15)][kk + (lane >> 4)];
+      const float bv = Bs[kk + (lane >> 4)][wn + (lane & 15)];
+      acc = __builtin_amdgcn_mfma_f32_16x16x4f32(av, bv, acc, 0, 0, 0);
+    }
+    __syncthreads();
+  }
+  const size_t base = (size_t)gbase[u];
+#pragma unroll
+  for (int r = 0; r < 4; ++r) {
+    const int i = ti * DG_T + wm + 4 * (lane >> 4) + r;
+    const int j = tj * DG_T + wn + (lane & 15);
+    if (i < c && j < c) {
+      GD[base + (size_t)i * c + j] = make_float2(acc[r], dense[(size_t)(o + i) * S + o + j]);
+      Q[base + (size_t)i * c + j] = i == j ? 1.f : 0.f;
+      if (ti != tj) {
+        GD[base + (size_t)j * c + i] = make_float2(acc[r], dense[(size_t)(o + j) * S + o + i]);
+        Q[base + (size_t)j * c + i] = 0.f;
+      }
+    }
+  }
+}
+
+hipError_t launch_gram_dense(int S, const int64_t* rp, const int32_t* ci, const float* cv,
+                             float* dense, const int32_t* off, int m, const int64_t* gbase,
+                             float2* GD, float* Q, int cmax, hipStream_t s) {
+  if (S == 0) return hipSuccess;
+  hipError_t e = hipMemsetAsync(dense, 0, (size_t)S * S * sizeof(float), s);
+  if (e != hipSuccess) return e;
+  k_densify<<<(S + 3) / 4, 256, 0, s>>>(S, rp, ci, cv, dense);
+  const int ntmax = (cmax + DG_T - 1) / DG_T;
+  dim3 grid((unsigned)(ntmax * (ntmax + 1) / 2), (unsigned)m);
+  k_gram_dense<<<grid, 256, 0, s>>>(S, dense, off, gbase, GD, Q, ntmax);
+  return hipGetLastError();
 }
 
 hipError_t launch_gram(int S, const int64_t* rp, const int32_t* ci, const float* cv,

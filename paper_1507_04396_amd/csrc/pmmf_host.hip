@@ -76,6 +76,9 @@ int64_t read_i64(const int64_t* dptr, hipStream_t s) {
   return v;
 }
 
+// active matrices with at most this many rows and at least this fill get the dense Gram
+constexpr int64_t DENSE_GRAM_MAX_ROWS = 16384;
+constexpr double DENSE_GRAM_MIN_FILL = 0.1;
 constexpr int CMAX_LIMIT = 3072;   // largest cluster (dense c x c Gram, diagonal block, Q;
                                     // the search keeps four of its rows in LDS)
 
@@ -89,6 +92,7 @@ struct StageDev {
   DBuf off, rcnt, roff, order, gbase, next, gid, cl_of, lvl_ptr, depth, sw_loc, sw_o, sw_idx;
   double loss = 0.0;
   double gram_ms = 0.0, find_ms = 0.0, rotate_ms = 0.0;
+  bool dense_gram = false;
   // sweep plan (built on first use): units of whole rotation components, and the clusters
   // holding a component larger than a unit, which the level kernel handles
   int nu = 0, nbig = 0, big_cmax = 0, big_rmax = 0;
@@ -533,7 +537,7 @@ extern "C" int mmf_factor(int64_t n, int64_t nnz, const int64_t* d_rowptr, const
     for (int32_t c : sc.sizes) g += (int64_t)c * c;
     pool = std::max(pool, g);
   }
-  DBuf GD, Q, retflag, keep, scan, cnt, loss_row, overflow, gid_cur, tbase;
+  DBuf GD, Q, retflag, keep, scan, cnt, loss_row, overflow, gid_cur, tbase, dense_buf;
   GD.ensure(pool * sizeof(float2));
   Q.ensure(pool * sizeof(float));
   retflag.ensure(n);
@@ -566,10 +570,22 @@ extern "C" int mmf_factor(int64_t n, int64_t nnz, const int64_t* d_rowptr, const
 
     PhaseEvents pev;
     HIPCHK(hipEventRecord(pev.e[0], s));
-    // cluster Grams, diagonal blocks, identity accumulators
-    HIPCHK(pmmf::launch_gram(S, M.rp.as<int64_t>(), M.ci.as<int32_t>(), M.cv.as<float>(),
-                             sd.off.as<int32_t>(), sd.cl_of.as<int32_t>(), sd.gbase.as<int64_t>(),
-                             GD.as<float2>(), Q.as<float>(), cm, s));
+    // cluster Grams, diagonal blocks, identity accumulators: sparse row merges, or dense column
+    // slices on the matrix cores once the active matrix is dense enough
+    const bool dense_gram = (int64_t)S <= DENSE_GRAM_MAX_ROWS &&
+                            (double)M.nnz >= DENSE_GRAM_MIN_FILL * (double)S * (double)S;
+    sd.dense_gram = dense_gram;
+    if (dense_gram) {
+      dense_buf.ensure((size_t)S * S * sizeof(float));
+      HIPCHK(pmmf::launch_gram_dense(S, M.rp.as<int64_t>(), M.ci.as<int32_t>(), M.cv.as<float>(),
+                                     dense_buf.as<float>(), sd.off.as<int32_t>(), sd.m,
+                                     sd.gbase.as<int64_t>(), GD.as<float2>(), Q.as<float>(),
+                                     sd.cmax, s));
+    } else {
+      HIPCHK(pmmf::launch_gram(S, M.rp.as<int64_t>(), M.ci.as<int32_t>(), M.cv.as<float>(),
+                               sd.off.as<int32_t>(), sd.cl_of.as<int32_t>(),
+                               sd.gbase.as<int64_t>(), GD.as<float2>(), Q.as<float>(), cm, s));
+    }
     // greedy rotation search in every cluster
     pmmf::FindArgs fa;
     fa.p = (int)pi + 1;
@@ -1033,7 +1049,7 @@ extern "C" int mmf_get_stage_info(mmf_handle hh, int32_t stage, mmf_stage_info* 
   out->nnz = sd.nnz;
   out->max_cluster = sd.cmax;
   out->max_depth = sd.depth_max;
-  out->pad = 0;
+  out->dense_gram = sd.dense_gram ? 1 : 0;
   out->loss = sd.loss;
   out->gram_ms = sd.gram_ms;
   out->find_ms = sd.find_ms;

@@ -143,6 +143,19 @@ def test_factor_grid2d_n65536_full_size():
 
 # --------------------------------------------------------------------------- apply / inverse
 
+def test_both_gram_forms_match_oracle():
+    """The sparse row-merge Gram (sparse early stages) and the dense matrix-core Gram (dense
+    later stages) within one factorization, against the oracle."""
+    # one cluster per stage: fill 0.9%, 5.9%, 32%, 76%, 96% over the five stages
+    A = workloads.knn_points_matrix(1500, 3, 10, 0.01, 2)
+    params = dict(k=3, eta=0.5, core=64, cluster=(0, 0), seed=0)
+    ref, fac = _factor_both(A, params, "knn3d_n1500 single cluster")
+    forms = [st["dense_gram"] for st in fac.stage_info()]
+    _say(f"[parity] dense gram by stage: {forms}")
+    assert forms == [0, 0, 1, 1, 1]
+    _check_factor(ref, fac, A, "knn3d_n1500 single cluster")
+
+
 def _import(ref):
     return import_oracle(ref)
 
