@@ -143,6 +143,25 @@ int mmf_backward(mmf_handle h, const float* d_x, const float* d_ybar, float* d_x
                  float* d_hdiag_bar, float* d_hcore_bar, float* d_theta_bar, int64_t nrhs,
                  int64_t ld, void* stream);
 
+/*
+ * Captured products (batching of Sec. 2.3 / Table 1's many small operations into one launch):
+ * mmf_graph_capture records one mmf_apply (inverse = 0) or mmf_apply_inverse (inverse = 1) from
+ * d_x to d_y ([n][ld], device, fixed for the graph's life) as a HIP graph.  It first runs the
+ * product eagerly on `stream` (so d_y holds the result and every size-dependent preparation is
+ * done) and synchronizes it; the graph contains kernel nodes only and owns its own workspace.
+ * mmf_graph_launch replays it on `stream` (asynchronous); it reads d_x and the handle's current
+ * rotations and H, and writes d_y.  A graph of the inverse is refused (MMF_ESTATE) once theta or H
+ * have changed (mmf_set_params, mmf_sync_angles), since it holds the core inverse of capture time.
+ * Launching after mmf_destroy of its factorization, or after mmf_graph_destroy, is MMF_ESTATE.
+ * mmf_graph_destroy waits for the device and frees the graph.  Errors: MMF_EINVAL, MMF_ESTATE,
+ * MMF_ESINGULAR (inverse), MMF_ENOMEM, MMF_EDEVICE.
+ */
+typedef struct mmf_graph_s* mmf_graph;
+int mmf_graph_capture(mmf_handle h, int32_t inverse, const float* d_x, float* d_y, int64_t nrhs,
+                      int64_t ld, void* stream, mmf_graph* out);
+int mmf_graph_launch(mmf_graph g, void* stream);
+int mmf_graph_destroy(mmf_graph g);
+
 /* Summary of a finished factorization (host struct).  Errors: MMF_ESTATE. */
 int mmf_get_info(mmf_handle h, mmf_info* out);
 
@@ -222,6 +241,7 @@ typedef struct {
  *   h       : factorization of (an approximation of) A, dimension n
  *   A       : CSR (device), the matrix of the system (the one that was factored)
  *   d_b     : [n][nrhs] float32 right-hand sides (device);  d_x : [n][nrhs] float64 solution (device)
+ * The preconditioner product is captured once per call as a graph (mmf_graph_capture) and replayed.
  * Synchronizes `stream` once per inner iteration.  Errors: MMF_EINVAL, MMF_ESTATE, MMF_ENOMEM,
  * MMF_ESINGULAR (H not invertible), MMF_EDEVICE.
  */

@@ -74,6 +74,9 @@ SIGNATURES = {
     "mmf_pcg": [H, I64, P, P, P, P, P, I64, ctypes.c_double, I32, ctypes.c_double, P,
                 ctypes.POINTER(mmf_pcg_info)],
     "mmf_spmm": [I64, P, P, P, P, P, I64, I64, P],
+    "mmf_graph_capture": [H, I32, P, P, I64, I64, P, ctypes.POINTER(H)],
+    "mmf_graph_launch": [H, P],
+    "mmf_graph_destroy": [H],
     "mmf_destroy": [H],
     "mmf_last_error": [],
 }

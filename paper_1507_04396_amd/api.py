@@ -203,6 +203,19 @@ class Factorization:
                                   inner_reduction, _stream(stream), ctypes.byref(inf)))
         return x, {f: getattr(inf, f) for f, _ in _lib.mmf_pcg_info._fields_ if f != "pad"}
 
+    def capture(self, x: torch.Tensor, y: torch.Tensor, inverse: bool = False,
+                stream=None) -> "ProductGraph":
+        """mmf_graph_capture: record y = A~ x (or A~^{-1} x) on these buffers as a HIP graph.
+        Runs the product once eagerly (y holds it on return)."""
+        x2, nrhs, ld = self._vec_args(x)
+        _require_device(y, torch.float32, "y")
+        if y.shape != x2.shape and not (y.dim() == 1 and x.dim() == 1):
+            raise ValueError("y must have the shape of x")
+        g = ctypes.c_void_p()
+        check(_lib.load().mmf_graph_capture(self.handle, 1 if inverse else 0, _ptr(x2), _ptr(y),
+                                            nrhs, ld, _stream(stream), ctypes.byref(g)))
+        return ProductGraph(g, self)
+
     def set_params(self, theta=None, hdiag=None, hcore=None, stream=None) -> None:
         for t, nm in ((theta, "theta"), (hdiag, "hdiag"), (hcore, "hcore")):
             if t is not None:
@@ -218,6 +231,30 @@ class Factorization:
         dev = "cuda"
         return (None if theta is None else torch.tensor(theta, dtype=torch.float32, device=dev),
                 torch.tensor(ex["hdiag"], device=dev), torch.tensor(ex["hcore"], device=dev))
+
+
+class ProductGraph:
+    """A captured mmf_apply / mmf_apply_inverse (mmf_graph_*); keeps its factorization alive."""
+
+    def __init__(self, g: ctypes.c_void_p, fac: Factorization):
+        self._g = g
+        self._fac = fac
+
+    def launch(self, stream=None) -> None:
+        if self._g is None:
+            raise MMFError(-7, "graph was closed")
+        check(_lib.load().mmf_graph_launch(self._g, _stream(stream)))
+
+    def close(self) -> None:
+        if self._g is not None and self._g.value:
+            check(_lib.load().mmf_graph_destroy(self._g))
+        self._g = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 class MMFApply(torch.autograd.Function):

@@ -220,6 +220,15 @@ extern "C" int mmf_pcg(mmf_handle h, int64_t n, const int64_t* d_rowptr, const i
       chk(hipGetLastError(), "kernels");
       chk(hipStreamSynchronize(s), "sync");
     }
+    // the preconditioner product R -> Z is captured once as a graph and replayed after that
+    struct GraphGuard {
+      mmf_graph g = nullptr;
+      ~GraphGuard() { if (g) (void)mmf_graph_destroy(g); }
+    } pre;
+    auto precondition = [&]() -> int {
+      if (!pre.g) return mmf_graph_capture(h, 1, R.as<float>(), Z.as<float>(), nrhs, ld, stream, &pre.g);
+      return mmf_graph_launch(pre.g, stream);
+    };
     std::vector<double> bn(nrhs), rn(nrhs), rzh(nrhs);
     chk(hipMemcpy(bn.data(), bb.p, nrhs * 8, hipMemcpyDeviceToHost), "copy");
     int total_it = 0, outer = 0;
@@ -248,7 +257,7 @@ extern "C" int mmf_pcg(mmf_handle h, int64_t n, const int64_t* d_rowptr, const i
       k_to_f32_scaled<<<ewb, 256, 0, s>>>(n, nrhs, ld, R64.as<double>(), scale.as<double>(),
                                           R.as<float>());
       chk(hipMemsetAsync(Dx.p, 0, N * 4, s), "memset");
-      rc = mmf_apply_inverse(h, R.as<float>(), Z.as<float>(), nrhs, ld, stream);
+      rc = precondition();
       if (rc != MMF_OK) return rc;
       chk(hipMemcpyAsync(P.p, Z.p, N * 4, hipMemcpyDeviceToDevice, s), "copy");
       coldot32(R.as<float>(), Z.as<float>(), rz.as<double>());
@@ -270,7 +279,7 @@ extern "C" int mmf_pcg(mmf_handle h, int64_t n, const int64_t* d_rowptr, const i
         for (int64_t j = 0; j < nrhs; ++j)
           if (act[j] && !(std::sqrt(rn[j]) <= inner_reduction)) inner_done = false;
         if (inner_done) break;
-        rc = mmf_apply_inverse(h, R.as<float>(), Z.as<float>(), nrhs, ld, stream);
+        rc = precondition();
         if (rc != MMF_OK) return rc;
         coldot32(R.as<float>(), Z.as<float>(), rz2.as<double>());
         k_cg_beta<<<(unsigned)((nrhs + 255) / 256), 256, 0, s>>>(nrhs, rz2.as<double>(),

@@ -126,6 +126,7 @@ struct mmf_plan {
   DBuf hinv, chol_L, chol_X, status;
   bool inv_ready = false;
   bool units_ready = false;
+  uint64_t version = 0;  // bumped whenever theta, H or the rotations change
   DBuf ws[16];
   mmf_info info{};
   hipStream_t stream = nullptr;
@@ -814,7 +815,7 @@ void ensure_inverse(mmf_plan& h, hipStream_t s) {
 
 // Y = U^T op(H) U X with op = H (inverse = false) or H^{-1}
 void apply_impl(mmf_plan& h, const float* x, float* y, int64_t nrhs, int64_t ld, hipStream_t s,
-                bool inverse) {
+                bool inverse, float* ws0 = nullptr, float* ws1 = nullptr) {
   if (nrhs < 0 || ld < nrhs || (!x && nrhs > 0) || (!y && nrhs > 0))
     raise(MMF_EINVAL, "bad vector arguments");
   if (nrhs == 0) return;
@@ -829,7 +830,7 @@ void apply_impl(mmf_plan& h, const float* x, float* y, int64_t nrhs, int64_t ld,
     return;
   }
   const int64_t s1 = h.st[0]->size - h.st[0]->t;
-  float* buf[2] = {wsbuf(h, 0, s1 * nrhs), wsbuf(h, 1, s1 * nrhs)};
+  float* buf[2] = {ws0 ? ws0 : wsbuf(h, 0, s1 * nrhs), ws1 ? ws1 : wsbuf(h, 1, s1 * nrhs)};
   const int W = pick_tile(h, 1, nrhs);
   for (int p = 1; p <= P; ++p) {
     const StageDev& sd = *h.st[p - 1];
@@ -886,6 +887,101 @@ extern "C" int mmf_apply_inverse(mmf_handle hh, const float* d_x, float* d_y, in
   ABI_BEGIN
   mmf_plan& h = *checked(hh);
   apply_impl(h, d_x, d_y, nrhs, ld, as_stream(stream), true);
+  return MMF_OK;
+  ABI_END
+}
+
+// ------------------------------------------------------------------------------------------
+// Captured products: one mmf_apply / mmf_apply_inverse on fixed buffers recorded as a HIP graph
+// (kernel nodes only: every size-dependent preparation runs in an eager call before capture).
+// The graph owns its ping-pong workspace, so later eager calls cannot move it.
+struct mmf_graph_s {
+  mmf_plan* h = nullptr;
+  bool inverse = false;
+  uint64_t version = 0;
+  hipGraph_t g = nullptr;
+  hipGraphExec_t ge = nullptr;
+  DBuf ws0, ws1;
+};
+static std::set<mmf_graph_s*> g_graphs;  // guarded by g_live_mu
+
+static void graph_free(mmf_graph_s* G) {
+  if (G->ge) (void)hipGraphExecDestroy(G->ge);
+  if (G->g) (void)hipGraphDestroy(G->g);
+  delete G;
+}
+
+extern "C" int mmf_graph_capture(mmf_handle hh, int32_t inverse, const float* d_x, float* d_y,
+                                 int64_t nrhs, int64_t ld, void* stream, mmf_graph* out) {
+  ABI_BEGIN
+  mmf_plan& h = *checked(hh);
+  if (!out || nrhs < 1 || ld < nrhs || !d_x || !d_y || d_x == d_y)
+    raise(MMF_EINVAL, "bad graph capture arguments");
+  hipStream_t s = as_stream(stream);
+  std::unique_ptr<mmf_graph_s, void (*)(mmf_graph_s*)> G(new mmf_graph_s, graph_free);
+  G->h = &h;
+  G->inverse = inverse != 0;
+  const int64_t s1 = h.st.empty() ? 0 : h.st[0]->size - h.st[0]->t;
+  G->ws0.ensure(std::max<int64_t>(s1 * nrhs, 1) * sizeof(float));
+  G->ws1.ensure(std::max<int64_t>(s1 * nrhs, 1) * sizeof(float));
+  // eager call: sweep units, core inverse and tile choice are prepared here, and y is produced
+  apply_impl(h, d_x, d_y, nrhs, ld, s, G->inverse, G->ws0.as<float>(), G->ws1.as<float>());
+  HIPCHK(hipStreamSynchronize(s));
+  G->version = h.version;
+  hipStream_t cs = nullptr;
+  HIPCHK(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking));
+  hipError_t ce = hipStreamBeginCapture(cs, hipStreamCaptureModeRelaxed);
+  if (ce != hipSuccess) {
+    (void)hipStreamDestroy(cs);
+    raise(MMF_EDEVICE, std::string("graph capture: ") + hipGetErrorString(ce));
+  }
+  try {
+    apply_impl(h, d_x, d_y, nrhs, ld, cs, G->inverse, G->ws0.as<float>(), G->ws1.as<float>());
+  } catch (...) {
+    hipGraph_t dead = nullptr;
+    (void)hipStreamEndCapture(cs, &dead);
+    if (dead) (void)hipGraphDestroy(dead);
+    (void)hipStreamDestroy(cs);
+    throw;
+  }
+  ce = hipStreamEndCapture(cs, &G->g);
+  (void)hipStreamDestroy(cs);
+  if (ce != hipSuccess) raise(MMF_EDEVICE, std::string("graph capture: ") + hipGetErrorString(ce));
+  HIPCHK(hipGraphInstantiate(&G->ge, G->g, nullptr, nullptr, 0));
+  {
+    std::lock_guard<std::mutex> lk(g_live_mu);
+    g_graphs.insert(G.get());
+  }
+  *out = G.release();
+  return MMF_OK;
+  ABI_END
+}
+
+extern "C" int mmf_graph_launch(mmf_graph gg, void* stream) {
+  ABI_BEGIN
+  mmf_graph_s* G = gg;
+  {
+    std::lock_guard<std::mutex> lk(g_live_mu);
+    if (!G || !g_graphs.count(G)) raise(MMF_ESTATE, "invalid or destroyed graph");
+    if (!g_live.count(G->h)) raise(MMF_ESTATE, "the graph's factorization was destroyed");
+    if (G->inverse && G->version != G->h->version)
+      raise(MMF_ESTATE, "parameters changed since the inverse graph was captured");
+  }
+  HIPCHK(hipGraphLaunch(G->ge, as_stream(stream)));
+  return MMF_OK;
+  ABI_END
+}
+
+extern "C" int mmf_graph_destroy(mmf_graph gg) {
+  ABI_BEGIN
+  mmf_graph_s* G = gg;
+  {
+    std::lock_guard<std::mutex> lk(g_live_mu);
+    if (!G || !g_graphs.count(G)) raise(MMF_ESTATE, "invalid or destroyed graph");
+    g_graphs.erase(G);
+  }
+  (void)hipDeviceSynchronize();  // no replay may still use the workspace
+  graph_free(G);
   return MMF_OK;
   ABI_END
 }
@@ -1256,6 +1352,7 @@ extern "C" int mmf_sync_angles(mmf_handle hh, void* stream) {
   mmf_plan& h = *checked(hh);
   hipStream_t s = as_stream(stream);
   h.inv_ready = false;
+  ++h.version;
   if (h.k != 2) return MMF_OK;
   HIPCHK(pmmf::launch_sync_angles(h.R, h.theta.as<float>(), h.rot_o.as<float>(), s));
   for (auto& sp : h.st)
@@ -1272,6 +1369,7 @@ extern "C" int mmf_set_params(mmf_handle hh, const float* d_theta, const float* 
   hipStream_t s = as_stream(stream);
   if (d_theta && h.k != 2) raise(MMF_EINVAL, "angles exist only for k = 2");
   h.inv_ready = false;
+  ++h.version;
   if (d_hdiag)
     HIPCHK(hipMemcpyAsync(h.hdiag.p, d_hdiag, h.n * sizeof(float), hipMemcpyDeviceToDevice, s));
   if (d_hcore && h.core)
