@@ -38,71 +38,33 @@ def device_csr(A, torch):
     return rp, ci, cv
 
 
+def measured_traffic(kernel, workload):
+    """HBM bytes per launch of `kernel` on `workload` from the committed counter summary
+    (profiles/<kernel>_<workload>_traffic.md), or None when there is none or the kernel's source
+    file changed since the counters were taken."""
+    import hashlib
+    import re
+    path = os.path.join(ROOT, "profiles", f"{kernel}_{workload}_traffic.md")
+    src = os.path.join(ROOT, "paper_1507_04396_amd", "csrc", "factor_kernels.hip")
+    if not os.path.exists(path):
+        return None
+    text = open(path).read()
+    m_sha = re.search(r"source_sha256\s*=\s*([0-9a-f]{64})", text)
+    m_b = re.search(r"traffic_bytes_per_launch\s*=\s*(\d+)", text)
+    if not (m_sha and m_b):
+        return None
+    if hashlib.sha256(open(src, "rb").read()).hexdigest() != m_sha.group(1):
+        return None
+    return int(m_b.group(1))
+
+
 def sweep_rows(stages):
     """sum over stages of |S_{p-1}| (rows each U-sweep reads and writes)."""
     return sum(st["size"] for st in stages)
 
 
-def main():
-    ap = argparse.ArgumentParser()
-    ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=3)
-    ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="knn3d_n262144")
-    ap.add_argument("--apply-workload", default="grid2d_n65536")
-    ap.add_argument("--nrhs", type=int, default=256)
-    ap.add_argument("--refine-steps", type=int, default=50)
-    ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-sample-n", type=int, default=32768)
-    args = ap.parse_args()
-    if args.gpus != 1:
-        print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "
-              "(the factorization shards by cluster, see the design notes)", file=sys.stderr)
-        sys.exit(2)
-
-    import torch
-
-    import workloads
-    from paper_1507_04396_amd import _lib
-    from paper_1507_04396_amd.api import Factorization
-    _lib.load()
-    assert torch.cuda.is_available(), "bench.py needs a GPU"
-
-    # ----------------------------------------------------------------- factorization (headline)
-    wl = workloads.WORKLOADS[args.workload]
-    prm = dict(wl["params"])
-    log(f"[bench] generating {args.workload}")
-    A = workloads.make_matrix(args.workload)
-    rp, ci, cv = device_csr(A, torch)
-    torch.cuda.synchronize()
-    R = A.n - prm["core"]
-    for w in range(args.warmup):
-        log(f"[bench] warmup factor {w}")
-        Factorization.factor(rp, ci, cv, **prm).close()
-    torch.cuda.synchronize()
-    times = []
-    fac = None
-    for s in range(args.steps):
-        if fac is not None:
-            fac.close()
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        fac = Factorization.factor(rp, ci, cv, **prm)
-        torch.cuda.synchronize()
-        times.append(time.perf_counter() - t0)
-        log(f"[bench] factor step {s}: {times[-1] * 1e3:.2f} ms")
-    info = fac.info()
-    stages = fac.stage_info()
-    ms_per_step = 1e3 * float(np.mean(times))
-    rot_per_s = R / (ms_per_step / 1e3)
-    find_ms = sum(st["find_ms"] for st in stages)
-    gram_ms = sum(st["gram_ms"] for st in stages)
-    rot_ms = sum(st["rotate_ms"] for st in stages)
-    fbytes = sum(st["find_bytes"] for st in stages)
-    fac.close()
-    del rp, ci, cv
-
-    # ----------------------------------------------------------------- apply / adjoint
+def measure_apply(args, torch, workloads, Factorization, log):
+    """Apply, adjoint and angle refinement on the apply workload's factorization."""
     log(f"[bench] factor {args.apply_workload} for apply/backward")
     B = workloads.make_matrix(args.apply_workload)
     bprm = dict(workloads.WORKLOADS[args.apply_workload]["params"])
@@ -163,16 +125,109 @@ def main():
               "loss_first5": round(float(hist[:5].mean()), 4),
               "loss_last5": round(float(hist[-5:].mean()), 4)}
     fb.close()
+    apply_res = {"workload": f"{args.apply_workload} factorization, {args.nrhs} RHS",
+                 "ms": round(apply_ms, 4), "algorithmic_GBps": round(apply_gbs, 1),
+                 "frac_hbm": round(apply_gbs / HBM_PEAK_GBS, 4)}
+    back_res = {"workload": f"{args.apply_workload} factorization, {args.nrhs} RHS",
+                "ms": round(back_ms, 4), "algorithmic_GBps": round(back_gbs, 1),
+                "frac_hbm": round(back_gbs / HBM_PEAK_GBS, 4)}
+    return apply_res, back_res, refine
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default="knn3d_n262144")
+    ap.add_argument("--apply-workload", default="grid2d_n65536")
+    ap.add_argument("--nrhs", type=int, default=256)
+    ap.add_argument("--refine-steps", type=int, default=50)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-sample-n", type=int, default=32768)
+    ap.add_argument("--factor-only", action="store_true",
+                    help="time the factorization and the copy reference only (counter runs)")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "
+              "(the factorization shards by cluster, see the design notes)", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    import workloads
+    from paper_1507_04396_amd import _lib
+    from paper_1507_04396_amd.api import Factorization
+    _lib.load()
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+
+    # ----------------------------------------------------------------- HBM reference: plain copy
+    copy_elems = 1 << 28                     # 1 GiB of float32 read, 1 GiB written
+    src = torch.ones(copy_elems, device="cuda")
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    torch.cuda.synchronize()
+    c0, c1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    c0.record()
+    for _ in range(5):
+        dst.copy_(src)
+    c1.record()
+    torch.cuda.synchronize()
+    copy_ms = c0.elapsed_time(c1) / 5
+    copy_gbs = 2 * 4 * copy_elems / (copy_ms * 1e-3) / 1e9
+    del src, dst
+
+    # ----------------------------------------------------------------- factorization (headline)
+    wl = workloads.WORKLOADS[args.workload]
+    prm = dict(wl["params"])
+    log(f"[bench] generating {args.workload}")
+    A = workloads.make_matrix(args.workload)
+    rp, ci, cv = device_csr(A, torch)
+    torch.cuda.synchronize()
+    R = A.n - prm["core"]
+    for w in range(args.warmup):
+        log(f"[bench] warmup factor {w}")
+        Factorization.factor(rp, ci, cv, **prm).close()
+    torch.cuda.synchronize()
+    times = []
+    fac = None
+    for s in range(args.steps):
+        if fac is not None:
+            fac.close()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        fac = Factorization.factor(rp, ci, cv, **prm)
+        torch.cuda.synchronize()
+        times.append(time.perf_counter() - t0)
+        log(f"[bench] factor step {s}: {times[-1] * 1e3:.2f} ms")
+    info = fac.info()
+    stages = fac.stage_info()
+    ms_per_step = 1e3 * float(np.mean(times))
+    rot_per_s = R / (ms_per_step / 1e3)
+    find_ms = sum(st["find_ms"] for st in stages)
+    gram_ms = sum(st["gram_ms"] for st in stages)
+    rot_ms = sum(st["rotate_ms"] for st in stages)
+    fbytes = sum(st["find_bytes"] for st in stages)
+    fac.close()
+    del rp, ci, cv
+
+    # ----------------------------------------------------------------- apply / adjoint
+    apply_res = back_res = refine = None
+    if not args.factor_only:
+        apply_res, back_res, refine = measure_apply(args, torch, workloads, Factorization, log)
 
     # ----------------------------------------------------------------- roofline (dominant kernel)
     find_launches = len(stages)
     find_gbs = fbytes / (find_ms * 1e-3) / 1e9
     roofline = {"kernel": "k_find (greedy rotation search, one launch per stage)",
                 "bound": "hbm", "achieved": round(find_gbs, 2), "peak": HBM_PEAK_GBS,
-                "unit": "GB/s", "frac": round(find_gbs / HBM_PEAK_GBS, 5), "traffic": None,
+                "unit": "GB/s", "frac": round(find_gbs / HBM_PEAK_GBS, 5),
+                "traffic": measured_traffic("k_find", "knn3d_n262144"),
                 "launches": find_launches,
                 "avg_launch_ms": round(find_ms / max(1, find_launches), 4),
-                "algorithmic_bytes_per_launch": int(fbytes / max(1, find_launches))}
+                "algorithmic_bytes_per_launch": int(fbytes / max(1, find_launches)),
+                "measured_copy_peak": round(copy_gbs, 1),
+                "frac_of_measured_copy": round(find_gbs / copy_gbs, 5)}
 
     # ----------------------------------------------------------------- CPU baseline (oracle)
     cpu = None
@@ -206,12 +261,10 @@ def main():
         "factor_phase_ms": {"gram": round(gram_ms, 3), "find": round(find_ms, 3),
                             "rotate": round(rot_ms, 3)},
         "factor_loss": info["loss"],
-        "apply": {"workload": f"{args.apply_workload} factorization, {args.nrhs} RHS",
-                  "ms": round(apply_ms, 4), "algorithmic_GBps": round(apply_gbs, 1),
-                  "frac_hbm": round(apply_gbs / HBM_PEAK_GBS, 4)},
-        "backward": {"workload": f"{args.apply_workload} factorization, {args.nrhs} RHS",
-                     "ms": round(back_ms, 4), "algorithmic_GBps": round(back_gbs, 1),
-                     "frac_hbm": round(back_gbs / HBM_PEAK_GBS, 4)},
+        "apply": apply_res,
+        "backward": back_res,
+        "hbm_copy": {"bytes": 8 * copy_elems, "ms": round(copy_ms, 4),
+                     "GBps": round(copy_gbs, 1), "kind": "1 GiB float32 device copy (torch)"},
         "refine": refine,
         "roofline": roofline,
         "cpu_baseline": cpu,
