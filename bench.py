@@ -145,6 +145,8 @@ def main():
     ap.add_argument("--refine-steps", type=int, default=50)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample-n", type=int, default=32768)
+    ap.add_argument("--gram-seeds", type=int, default=5,
+                    help="algorithm seeds for the FP32-vs-BF16 Gram comparison (0 = skip)")
     ap.add_argument("--factor-only", action="store_true",
                     help="time the factorization and the copy reference only (counter runs)")
     args = ap.parse_args()
@@ -209,6 +211,28 @@ def main():
     rot_ms = sum(st["rotate_ms"] for st in stages)
     fbytes = sum(st["find_bytes"] for st in stages)
     fac.close()
+
+    # ----------------------------------------------------------------- Gram forms over seeds
+    gram_forms = None
+    if args.gram_seeds > 0 and not args.factor_only:
+        gram_forms = {}
+        for mode, label in ((0, "fp32"), (1, "bf16_rescored")):
+            t_ms, losses = [], []
+            for sd in range(args.gram_seeds):
+                p2 = dict(prm)
+                p2["seed"] = sd
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                f2 = Factorization.factor(rp, ci, cv, gram_mode=mode, **p2)
+                torch.cuda.synchronize()
+                t_ms.append(1e3 * (time.perf_counter() - t0))
+                losses.append(f2.info()["loss"])
+                f2.close()
+            log(f"[bench] gram form {label}: {np.round(t_ms, 1)} ms, loss {np.round(losses, 2)}")
+            gram_forms[label] = {"seeds": args.gram_seeds,
+                                 "factor_ms_median": round(float(np.median(t_ms)), 3),
+                                 "loss_mean": round(float(np.mean(losses)), 4),
+                                 "loss_std": round(float(np.std(losses)), 4)}
     del rp, ci, cv
 
     # ----------------------------------------------------------------- apply / adjoint
@@ -266,6 +290,7 @@ def main():
         "hbm_copy": {"bytes": 8 * copy_elems, "ms": round(copy_ms, 4),
                      "GBps": round(copy_gbs, 1), "kind": "1 GiB float32 device copy (torch)"},
         "refine": refine,
+        "gram_forms": gram_forms,
         "roofline": roofline,
         "cpu_baseline": cpu,
         "stages": [{k2: (round(v, 4) if isinstance(v, float) else v) for k2, v in st.items()}

@@ -58,7 +58,10 @@ typedef struct {
   int32_t  cluster_min;  /* lo, hi: random uneven cluster sizes in [lo, hi], hi >= 2 lo >= 4;   */
   int32_t  cluster_max;  /* (0, 0) = one cluster per stage (plain MMF).  Sec. 2.1 clustering     */
   uint64_t seed;         /* drives the random seed rows (Alg. 2) and the cluster sizes          */
-  int32_t  gram_mode;    /* 0 = FP32 cluster Gram (the only mode this build provides)           */
+  int32_t  gram_mode;    /* 0 = FP32 cluster Gram; 1 = Gram of the BF16-rounded column slab on
+                            the matrix cores (FP32 accumulation) used to shortlist partners, the
+                            pick and G[T,T] then taken from exact FP32 dots of the slab columns,
+                            which every rotation right-rotates (Sec. 2.1 Gram, Alg. 2 scores)    */
   uint32_t flags;        /* MMF_* flags above                                                   */
 } mmf_params;
 
@@ -87,8 +90,9 @@ typedef struct {
   int64_t nnz;           /* nonzeros of the stage's active matrix A_{p-1}[S_{p-1}, S_{p-1}]     */
   int64_t max_cluster;   /* largest cluster of the stage                                        */
   int32_t max_depth;     /* deepest chain of dependent rotations inside one cluster             */
-  int32_t dense_gram;    /* 1 if the stage's Gram took the dense matrix-core form (fill >= 0.1,
-                            at most 16384 active rows), 0 for the sparse row-merge form        */
+  int32_t dense_gram;    /* 1 if the stage's Gram took a dense matrix-core form (FP32: fill >=
+                            0.1 and at most 16384 active rows; BF16 mode: always), 0 for the
+                            sparse row-merge form                                              */
   double  loss;          /* residual contributed by this stage's retirements (FP64)             */
   double  gram_ms;       /* device time of the cluster Gram / diagonal-block kernel             */
   double  find_ms;       /* device time of the greedy rotation search (all clusters, one launch) */
@@ -97,6 +101,9 @@ typedef struct {
   int64_t find_bytes;    /* algorithmic bytes of the greedy search: per rotation in a cluster of
                             c, the seed's Gram row plus k rows of the Gram and of the diagonal
                             block read and written, 4 c (1 + 4k)                                 */
+  int64_t bf16_long;     /* BF16 mode: steps with more than 64 shortlisted partners (rescored in
+                            several rounds)                                                      */
+  int64_t bf16_rescored; /* BF16 mode: candidates rescored with exact FP32 dots (all steps)       */
 } mmf_stage_info;
 
 /*

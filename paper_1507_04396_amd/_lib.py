@@ -51,7 +51,8 @@ class mmf_stage_info(ctypes.Structure):
                 ("max_cluster", ctypes.c_int64), ("max_depth", ctypes.c_int32),
                 ("dense_gram", ctypes.c_int32), ("loss", ctypes.c_double),
                 ("gram_ms", ctypes.c_double), ("find_ms", ctypes.c_double),
-                ("rotate_ms", ctypes.c_double), ("find_bytes", ctypes.c_int64)]
+                ("rotate_ms", ctypes.c_double), ("find_bytes", ctypes.c_int64),
+                ("bf16_long", ctypes.c_int64), ("bf16_rescored", ctypes.c_int64)]
 
 
 P = ctypes.c_void_p

@@ -46,7 +46,7 @@ class Factorization:
     @classmethod
     def factor(cls, rowptr: torch.Tensor, colind: torch.Tensor, val: torch.Tensor, *, k: int = 2,
                eta: float = 0.5, core: int = 64, cluster=(0, 0), seed: int = 0,
-               check_symmetry: bool = False, even_clusters: bool = False,
+               check_symmetry: bool = False, even_clusters: bool = False, gram_mode: int = 0,
                stream=None) -> "Factorization":
         """mmf_factor on a device CSR (int64 rowptr, int32 colind, float32 val)."""
         lib = _lib.load()
@@ -55,7 +55,7 @@ class Factorization:
         _require_device(val, torch.float32, "val")
         n = rowptr.numel() - 1
         prm = _lib.mmf_params(k=k, eta=eta, core_size=core, cluster_min=cluster[0],
-                              cluster_max=cluster[1], seed=seed, gram_mode=0,
+                              cluster_max=cluster[1], seed=seed, gram_mode=gram_mode,
                               flags=(_lib.MMF_CHECK_SYMMETRY if check_symmetry else 0)
                               | (_lib.MMF_EVEN_CLUSTERS if even_clusters else 0))
         h = ctypes.c_void_p()

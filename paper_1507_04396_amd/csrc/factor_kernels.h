@@ -31,6 +31,12 @@ struct FindArgs {
   float* hdiag;              // [n] retired diagonal of H
   uint8_t* retflag;          // [S] 1 if the position retires in this stage
   int32_t* err;              // set to 1 if a cluster finds no partner (never expected)
+  // BF16 form only: FP32 slabs (column-major, R_u rows per cluster) for exact rescoring, and
+  // counters {steps with more than one rescoring round, candidates rescored}
+  float* slab = nullptr;
+  const int64_t* slab_off = nullptr;
+  const int32_t* slab_rows = nullptr;
+  unsigned long long* sl_stats = nullptr;
 };
 
 }  // namespace pmmf
@@ -45,6 +51,16 @@ hipError_t launch_gram_dense(int S, const int64_t* rp, const int32_t* ci, const 
                              float* dense, const int32_t* off, int m, const int64_t* gbase,
                              float2* GD, float* Q, int cmax, hipStream_t s);
 hipError_t launch_find(const FindArgs& a, int m, int cmax, int nt, hipStream_t s);
+hipError_t launch_find_bf16(const FindArgs& a, int m, int cmax, hipStream_t s);
+hipError_t launch_slab_rows(int S, int m, const int64_t* rp, const int32_t* ci,
+                            const int32_t* cl_of, int64_t W, uint32_t* bm, int32_t* pre,
+                            int32_t* R, hipStream_t s);
+hipError_t launch_gram_bf16(int S, int m, const int64_t* rp, const int32_t* ci, const float* cv,
+                            const int32_t* off, const int32_t* cl_of, int64_t W,
+                            const uint32_t* bm, const int32_t* pre, const int64_t* slab_off,
+                            const int32_t* R, int64_t slab_elems, float* slab,
+                            unsigned short* slab_bf, const int64_t* gbase, float2* GD, float* Q,
+                            int cmax, hipStream_t s);
 size_t find_lds_bytes(int cmax);
 hipError_t launch_levelize(int m, int k, const int32_t* off, const int32_t* rcnt,
                            const int32_t* roff, int64_t rot0, const int32_t* rot_loc,

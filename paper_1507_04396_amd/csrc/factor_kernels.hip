@@ -225,6 +225,200 @@ hipError_t launch_gram_dense(int S, const int64_t* rp, const int32_t* ci, const 
   return hipGetLastError();
 }
 
+// ------------------------------------------------------------------------------------------
+// BF16 form of the cluster Gram.  Cluster u's slab is S_u = A[R_u, B_u] with R_u the positions
+// whose rows touch B_u (the union of the patterns of the rows of B_u, by symmetry); it is stored
+// column-major (column j of the cluster contiguous over the R_u rows, in ascending position
+// order), once in FP32 (kept for exact rescoring during the search and right-rotated with it) and
+// once rounded to BF16 (nearest even).  G~ = bf16(S)^T bf16(S) is formed on
+// v_mfma_f32_16x16x16bf16_1k with FP32 accumulation; its diagonal is then replaced by the exact
+// FP32 column norms.  R_u is found with one bitmap of positions per cluster and a popcount prefix.
+__device__ inline unsigned short pmmf_bf16_rne(float f) {
+  const uint32_t b = __builtin_bit_cast(uint32_t, f);
+  if ((b & 0x7f800000u) == 0x7f800000u) return (unsigned short)(b >> 16);  // inf / nan kept
+  return (unsigned short)((b + 0x7fffu + ((b >> 16) & 1u)) >> 16);
+}
+
+__global__ void k_slab_mark(int S, const int64_t* __restrict__ rp, const int32_t* __restrict__ ci,
+                            const int32_t* __restrict__ cl_of, int64_t W,
+                            uint32_t* __restrict__ bm) {
+  const int a = blockIdx.x * (blockDim.x / PMMF_WAVE) + pmmf_wave();
+  if (a >= S) return;
+  uint32_t* b = bm + (size_t)cl_of[a] * W;
+  for (int64_t t = rp[a] + pmmf_lane(); t < rp[a + 1]; t += PMMF_WAVE) {
+    const int r = ci[t];
+    atomicOr(b + (r >> 5), 1u << (r & 31));
+  }
+}
+
+// exclusive popcount prefix over each cluster's bitmap words; R[u] = the cluster's row count
+__global__ void __launch_bounds__(256) k_slab_prefix(int64_t W, const uint32_t* __restrict__ bm,
+                                                     int32_t* __restrict__ pre,
+                                                     int32_t* __restrict__ R) {
+  __shared__ int part[256];
+  const int u = blockIdx.x, tid = threadIdx.x;
+  const uint32_t* b = bm + (size_t)u * W;
+  int32_t* pr = pre + (size_t)u * W;
+  const int64_t per = (W + 255) / 256;
+  const int64_t w0 = tid * per, w1 = min<int64_t>(W, w0 + per);
+  int cnt = 0;
+  for (int64_t w = w0; w < w1; ++w) cnt += __popc(b[w]);
+  part[tid] = cnt;
+  __syncthreads();
+  for (int off = 1; off < 256; off <<= 1) {
+    const int v = tid >= off ? part[tid - off] : 0;
+    __syncthreads();
+    part[tid] += v;
+    __syncthreads();
+  }
+  int run = part[tid] - cnt;
+  for (int64_t w = w0; w < w1; ++w) {
+    pr[w] = run;
+    run += __popc(b[w]);
+  }
+  if (tid == 255) R[u] = part[255];
+}
+
+__global__ void k_slab_fill(int S, const int64_t* __restrict__ rp, const int32_t* __restrict__ ci,
+                            const float* __restrict__ cv, const int32_t* __restrict__ off,
+                            const int32_t* __restrict__ cl_of, int64_t W,
+                            const uint32_t* __restrict__ bm, const int32_t* __restrict__ pre,
+                            const int64_t* __restrict__ slab_off, const int32_t* __restrict__ R,
+                            float* __restrict__ slab, unsigned short* __restrict__ slab_bf) {
+  const int a = blockIdx.x * (blockDim.x / PMMF_WAVE) + pmmf_wave();
+  if (a >= S) return;
+  const int u = cl_of[a];
+  const int j = a - off[u];
+  const uint32_t* b = bm + (size_t)u * W;
+  const int32_t* pr = pre + (size_t)u * W;
+  const size_t col = (size_t)slab_off[u] + (size_t)j * R[u];
+  for (int64_t t = rp[a] + pmmf_lane(); t < rp[a + 1]; t += PMMF_WAVE) {
+    const int r = ci[t];
+    const int rho = pr[r >> 5] + __popc(b[r >> 5] & ((1u << (r & 31)) - 1u));
+    slab[col + rho] = cv[t];
+    slab_bf[col + rho] = pmmf_bf16_rne(cv[t]);
+  }
+}
+
+typedef short pmmf_s4 __attribute__((ext_vector_type(4)));
+constexpr int BG_T = 32, BG_K = 64;
+__global__ void __launch_bounds__(256) k_gram_bf16(const unsigned short* __restrict__ slab_bf,
+                                                   const int32_t* __restrict__ off,
+                                                   const int64_t* __restrict__ gbase,
+                                                   const int64_t* __restrict__ slab_off,
+                                                   const int32_t* __restrict__ R,
+                                                   float2* __restrict__ GD, float* __restrict__ Q,
+                                                   int ntmax) {
+  __shared__ unsigned short As[BG_T][BG_K + 4];
+  __shared__ unsigned short Bs[BG_T][BG_K + 4];
+  const int u = blockIdx.y;
+  const int o = off[u], c = off[u + 1] - o;
+  const int nt = (c + BG_T - 1) / BG_T;
+  int t = blockIdx.x, ti = 0;
+  while (ti < ntmax && t >= ntmax - ti) { t -= ntmax - ti; ++ti; }
+  const int tj = ti + t;
+  if (ti >= nt || tj >= nt) return;
+  const int Ru = R[u];
+  const unsigned short* Sb = slab_bf + slab_off[u];
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  const int wm = (w >> 1) * 16, wn = (w & 1) * 16;
+  pmmf_gf4 acc = {0.f, 0.f, 0.f, 0.f};
+  for (int k0 = 0; k0 < Ru; k0 += BG_K) {
+    // 32 columns x 64 rows of each slice: thread -> (column, 8 consecutive rows)
+    {
+      const int cc = tid >> 3, kk = (tid & 7) * 8;
+      const int ia = ti * BG_T + cc, ib = tj * BG_T + cc;
+#pragma unroll
+      for (int e = 0; e < 8; ++e) {
+        const int k = k0 + kk + e;
+        As[cc][kk + e] = (ia < c && k < Ru) ? Sb[(size_t)ia * Ru + k] : (unsigned short)0;
+        Bs[cc][kk + e] = (ib < c && k < Ru) ? Sb[(size_t)ib * Ru + k] : (unsigned short)0;
+      }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int kk = 0; kk < BG_K; kk += 16) {
+      pmmf_s4 av, bv;
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        av[e] = (short)As[wm + (lane & 15)][kk + 4 * (lane >> 4) + e];
+        bv[e] = (short)Bs[wn + (lane & 15)][kk + 4 * (lane >> 4) + e];
+      }
+      acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(av, bv, acc, 0, 0, 0);
+    }
+    __syncthreads();
+  }
+  const size_t base = (size_t)gbase[u];
+#pragma unroll
+  for (int r = 0; r < 4; ++r) {
+    const int i = ti * BG_T + wm + 4 * (lane >> 4) + r;
+    const int j = tj * BG_T + wn + (lane & 15);
+    if (i < c && j < c) {
+      GD[base + (size_t)i * c + j] = make_float2(acc[r], 0.f);
+      Q[base + (size_t)i * c + j] = i == j ? 1.f : 0.f;
+      if (ti != tj) {
+        GD[base + (size_t)j * c + i] = make_float2(acc[r], 0.f);
+        Q[base + (size_t)j * c + i] = 0.f;
+      }
+    }
+  }
+}
+
+// diagonal block D (row a's entries inside its cluster) into the second halves, and the exact
+// FP32 column norm ||S_j||^2 onto G~'s diagonal
+__global__ void k_slab_finish(int S, const int64_t* __restrict__ rp, const int32_t* __restrict__ ci,
+                              const float* __restrict__ cv, const int32_t* __restrict__ off,
+                              const int32_t* __restrict__ cl_of, const int64_t* __restrict__ gbase,
+                              const int64_t* __restrict__ slab_off, const int32_t* __restrict__ R,
+                              const float* __restrict__ slab, float2* __restrict__ GD) {
+  const int a = blockIdx.x * (blockDim.x / PMMF_WAVE) + pmmf_wave();
+  if (a >= S) return;
+  const int lane = pmmf_lane();
+  const int u = cl_of[a];
+  const int o = off[u], c = off[u + 1] - o, j = a - o;
+  float* gd = reinterpret_cast<float*>(GD + (size_t)gbase[u] + (size_t)j * c);
+  for (int64_t t = rp[a] + lane; t < rp[a + 1]; t += PMMF_WAVE) {
+    const int col = ci[t];
+    if (col >= o && col < o + c) gd[2 * (col - o) + 1] = cv[t];
+  }
+  const int Ru = R[u];
+  const float* col = slab + slab_off[u] + (size_t)j * Ru;
+  float acc = 0.f;
+  for (int rho = lane; rho < Ru; rho += PMMF_WAVE) acc += col[rho] * col[rho];
+  acc = pmmf_wave_sum_dpp(acc);
+  if (lane == 0) gd[2 * j] = acc;
+}
+
+hipError_t launch_slab_rows(int S, int m, const int64_t* rp, const int32_t* ci,
+                            const int32_t* cl_of, int64_t W, uint32_t* bm, int32_t* pre,
+                            int32_t* R, hipStream_t s) {
+  if (S == 0) return hipSuccess;
+  hipError_t e = hipMemsetAsync(bm, 0, (size_t)m * W * sizeof(uint32_t), s);
+  if (e != hipSuccess) return e;
+  k_slab_mark<<<(S + 3) / 4, 256, 0, s>>>(S, rp, ci, cl_of, W, bm);
+  k_slab_prefix<<<m, 256, 0, s>>>(W, bm, pre, R);
+  return hipGetLastError();
+}
+
+hipError_t launch_gram_bf16(int S, int m, const int64_t* rp, const int32_t* ci, const float* cv,
+                            const int32_t* off, const int32_t* cl_of, int64_t W,
+                            const uint32_t* bm, const int32_t* pre, const int64_t* slab_off,
+                            const int32_t* R, int64_t slab_elems, float* slab,
+                            unsigned short* slab_bf, const int64_t* gbase, float2* GD, float* Q,
+                            int cmax, hipStream_t s) {
+  if (S == 0) return hipSuccess;
+  hipError_t e = hipMemsetAsync(slab, 0, (size_t)slab_elems * sizeof(float), s);
+  if (e == hipSuccess) e = hipMemsetAsync(slab_bf, 0, (size_t)slab_elems * sizeof(unsigned short), s);
+  if (e != hipSuccess) return e;
+  k_slab_fill<<<(S + 3) / 4, 256, 0, s>>>(S, rp, ci, cv, off, cl_of, W, bm, pre, slab_off, R, slab,
+                                          slab_bf);
+  const int ntmax = (cmax + BG_T - 1) / BG_T;
+  dim3 grid((unsigned)(ntmax * (ntmax + 1) / 2), (unsigned)m);
+  k_gram_bf16<<<grid, 256, 0, s>>>(slab_bf, off, gbase, slab_off, R, GD, Q, ntmax);
+  k_slab_finish<<<(S + 3) / 4, 256, 0, s>>>(S, rp, ci, cv, off, cl_of, gbase, slab_off, R, slab, GD);
+  return hipGetLastError();
+}
+
 hipError_t launch_gram(int S, const int64_t* rp, const int32_t* ci, const float* cv,
                        const int32_t* off, const int32_t* cl_of, const int64_t* gbase,
                        float2* GD, float* Q, int cmax, hipStream_t s) {
@@ -784,6 +978,462 @@ template <int NT, int PER>
 static hipError_t find_launch_k(const FindArgs& a, int m, int cmax, size_t lds, hipStream_t s) {
   return a.k == 3 ? find_launch<NT, PER, 3>(a, m, cmax, lds, s)
                   : find_launch<NT, PER, 2>(a, m, cmax, lds, s);
+}
+
+// ------------------------------------------------------------------------------------------
+// Greedy search on the BF16 Gram (Alg. 2 with the scores shortlisted from G~ and decided exactly).
+// Same layout and step as k_find, with G~ in the first halves of the (G, D) pool; per step:
+//   1. approximate top-(k-1) scores from the seed's G~ row;
+//   2. shortlist, in ascending index order, every active j whose approximate score is within
+//      2 e of the (k-1)-th best, e = BF16_SAFETY (2^-7 + R 2^-24) sqrt(G_ii) bounding the score
+//      error (|G~_ij - G_ij| <= (2 u_bf16 + R u_f32) ||S_i|| ||S_j||, Cauchy-Schwarz);
+//   3. exact FP32 dots of the seed's slab column with each shortlisted column decide the pick
+//      (ties to the lower index), and the exact (t1, t2) dot completes G[T, T];
+//   4. rotation, elimination and updates as in k_find, with G~ updated like G and the slab
+//      columns T right-rotated (S[:, T] <- S[:, T] O^T) so later dots stay exact.
+// Every shortlisted candidate is rescored (in rounds of BF16_LIST), so the pick is the exact one;
+// steps whose shortlist needed more than one round are counted.
+constexpr float BF16_SAFETY = 2.f;
+constexpr int BF16_LIST = 64;
+
+__device__ inline float slab_dot(const float* __restrict__ a, const float* __restrict__ b, int R,
+                                 int lane) {
+  float acc = 0.f;
+  for (int r0 = 0; r0 < R; r0 += 4 * PMMF_WAVE) {
+    float x[4], y[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int r = r0 + q * PMMF_WAVE + lane;
+      x[q] = r < R ? a[r] : 0.f;
+      y[q] = r < R ? b[r] : 0.f;
+    }
+#pragma unroll
+    for (int q = 0; q < 4; ++q) acc = fmaf(x[q], y[q], acc);
+  }
+  return pmmf_wave_sum_dpp(acc);
+}
+
+template <int PER, int K>
+__global__ void __launch_bounds__(256) k_find_bf16(FindArgs A, int cmax) {
+  constexpr int NT = 256, NW = NT / PMMF_WAVE;
+  extern __shared__ float lds_f[];
+  float* gdiag = lds_f;
+  float* ddiag = gdiag + cmax;
+  float2* rowbuf = reinterpret_cast<float2*>(ddiag + cmax);
+  int* lgid = reinterpret_cast<int*>(rowbuf + 4 * (size_t)cmax);
+  uint32_t* mask = reinterpret_cast<uint32_t*>(lgid + cmax);
+  __shared__ Cand red1[NW], red2[NW];
+  __shared__ int sh_i, sh_e, sh_c0, sh_c1, sh_t1, sh_t2;
+  __shared__ float sh_O[9], sh_gn[9], sh_dn[9];
+  __shared__ int qcount[PER][NW];
+  __shared__ int list_j[BF16_LIST];
+  __shared__ float list_dot[BF16_LIST];
+
+  const int tid = threadIdx.x, lane = pmmf_lane(), wv = pmmf_wave();
+  const int u = A.order[blockIdx.x];
+  const int o = A.off[u];
+  const int c = A.off[u + 1] - o;
+  const int r = A.rcnt[u];
+  const int rb = A.roff[u];
+  const int nw = (c + 31) / 32;
+  constexpr int kk = K;
+  float2* __restrict__ GD = A.GD + A.gbase[u];
+  float* __restrict__ Q = A.Q + A.gbase[u];
+  const int Ru = A.slab_rows[u];
+  float* __restrict__ SL = A.slab + A.slab_off[u];
+  float2* R1 = rowbuf + 2 * (size_t)cmax;
+  float2* R2 = rowbuf + 3 * (size_t)cmax;
+  const float gamma = BF16_SAFETY * (0.0078125f + (float)Ru * 5.9604645e-8f);
+
+  for (int j = tid; j < c; j += NT) {
+    const float2 dg = GD[(size_t)j * c + j];
+    gdiag[j] = dg.x;
+    ddiag[j] = dg.y;
+    lgid[j] = A.gid[o + j];
+  }
+  for (int q = tid; q < nw; q += NT) {
+    const int rem = c - q * 32;
+    mask[q] = rem >= 32 ? 0xffffffffu : ((1u << rem) - 1u);
+  }
+  __syncthreads();
+  if (tid < PMMF_WAVE && r > 0) {
+    const uint64_t h = pmmf_hash4(A.seed, PMMF_TAG_SEED_ROW, (uint64_t)A.p, (uint64_t)u, 0);
+    const int i0 = select_active(mask, nw, (int)pmmf_mulhi(h, (uint64_t)c));
+    if (tid == 0) sh_i = i0;
+  }
+  __syncthreads();
+  int i = r > 0 ? sh_i : 0;
+  int e_prev = -1;
+  float2 cur[PER];
+#pragma unroll
+  for (int q = 0; q < PER; ++q) {
+    const int j = tid + q * NT;
+    cur[q] = (r > 0 && j < c) ? GD[(size_t)i * c + j] : make_float2(0.f, 0.f);
+  }
+  unsigned long long n_cut = 0, n_scored = 0;
+
+  for (int s = 0; s < r; ++s) {
+    float2* R0 = rowbuf + (size_t)(s & 1) * cmax;
+    // 1. approximate scores
+    float sc[PER];
+    Cand b1{-1.f, INT_MAX}, b2{-1.f, INT_MAX};
+#pragma unroll
+    for (int q = 0; q < PER; ++q) {
+      const int j = tid + q * NT;
+      sc[q] = -1.f;
+      if (j < c) {
+        R0[j] = cur[q];
+        const bool act = ((mask[j >> 5] >> (j & 31)) & 1u) && j != e_prev;
+        if (act && j != i) {
+          const float gd = gdiag[j];
+          float v = gd > 0.f ? fabsf(cur[q].x) / sqrtf(gd) : 0.f;
+          if (!(v >= 0.f)) v = 0.f;
+          sc[q] = v;
+          Cand cnd{v, j};
+          if (better(cnd, b1)) { b2 = b1; b1 = cnd; }
+          else if (better(cnd, b2)) b2 = cnd;
+        }
+      }
+    }
+    for (int ofs = PMMF_WAVE / 2; ofs > 0; ofs >>= 1) {
+      Cand o1{__shfl_xor(b1.s, ofs), __shfl_xor(b1.j, ofs)};
+      if (kk == 3) {
+        Cand o2{__shfl_xor(b2.s, ofs), __shfl_xor(b2.j, ofs)};
+        merge2(b1, b2, o1, o2);
+      } else if (better(o1, b1)) {
+        b1 = o1;
+      }
+    }
+    if (lane == 0) { red1[wv] = b1; red2[wv] = b2; }
+    __syncthreads();  // A
+    Cand f1 = red1[0], f2 = red2[0];
+#pragma unroll
+    for (int q = 1; q < NW; ++q) {
+      if (kk == 3) merge2(f1, f2, red1[q], red2[q]);
+      else if (better(red1[q], f1)) f1 = red1[q];
+    }
+    if (f1.j >= c || (kk == 3 && f2.j >= c)) {
+      if (tid == 0) atomicOr(A.err, 1);
+      return;
+    }
+    // 2. ordered shortlist: ballots per column slice, per-wave counts, offsets
+    const float thr = (kk == 3 ? f2.s : f1.s) - 2.f * gamma * sqrtf(fmaxf(gdiag[i], 0.f));
+    uint64_t ball[PER];
+#pragma unroll
+    for (int q = 0; q < PER; ++q) {
+      ball[q] = __ballot(sc[q] >= 0.f && sc[q] >= thr);
+      if (lane == 0) qcount[q][wv] = __popcll(ball[q]);
+    }
+    __syncthreads();  // A2
+    int total = 0, mypos[PER];
+#pragma unroll
+    for (int q = 0; q < PER; ++q) {
+      int before = 0;
+#pragma unroll
+      for (int w2 = 0; w2 < NW; ++w2) {
+        if (w2 == wv) before = total;
+        total += qcount[q][w2];
+      }
+      mypos[q] = ((ball[q] >> lane) & 1ull) ? before + pmmf_lanes_below(ball[q]) : -1;
+    }
+    // 3. exact dots of the seed column with the shortlisted columns, in rounds of BF16_LIST
+    //    candidates (ascending index), one wave per candidate
+    const float* si = SL + (size_t)i * Ru;
+    Cand x1{-1.f, INT_MAX}, x2{-1.f, INT_MAX};
+    float d1 = 0.f, d2 = 0.f;
+    for (int w0 = 0; w0 < total; w0 += BF16_LIST) {
+#pragma unroll
+      for (int q = 0; q < PER; ++q)
+        if (mypos[q] >= w0 && mypos[q] < w0 + BF16_LIST) list_j[mypos[q] - w0] = tid + q * NT;
+      const int nl = min(total - w0, BF16_LIST);
+      __syncthreads();  // A3
+      // four candidates per wave and pass: the seed column is read once for the four
+      for (int c4 = 4 * wv; c4 < nl; c4 += 4 * NW) {
+        const float* col[4];
+#pragma unroll
+        for (int e4 = 0; e4 < 4; ++e4)
+          col[e4] = SL + (size_t)list_j[min(c4 + e4, nl - 1)] * Ru;
+        float acc[4] = {0.f, 0.f, 0.f, 0.f};
+        for (int r0 = 0; r0 < Ru; r0 += 2 * PMMF_WAVE) {
+          float x[2], y[4][2];
+#pragma unroll
+          for (int h2 = 0; h2 < 2; ++h2) {
+            const int rr = r0 + h2 * PMMF_WAVE + lane;
+            x[h2] = rr < Ru ? si[rr] : 0.f;
+#pragma unroll
+            for (int e4 = 0; e4 < 4; ++e4) y[e4][h2] = rr < Ru ? col[e4][rr] : 0.f;
+          }
+#pragma unroll
+          for (int h2 = 0; h2 < 2; ++h2)
+#pragma unroll
+            for (int e4 = 0; e4 < 4; ++e4) acc[e4] = fmaf(x[h2], y[e4][h2], acc[e4]);
+        }
+#pragma unroll
+        for (int e4 = 0; e4 < 4; ++e4) {
+          const float d = pmmf_wave_sum_dpp(acc[e4]);
+          if (lane == 0 && c4 + e4 < nl) list_dot[c4 + e4] = d;
+        }
+      }
+      __syncthreads();  // A4
+      for (int ci = 0; ci < nl; ++ci) {
+        const int j = list_j[ci];
+        const float gd = gdiag[j];
+        float v = gd > 0.f ? fabsf(list_dot[ci]) / sqrtf(gd) : 0.f;
+        if (!(v >= 0.f)) v = 0.f;
+        const Cand cnd{v, j};
+        if (better(cnd, x1)) { x2 = x1; d2 = d1; x1 = cnd; d1 = list_dot[ci]; }
+        else if (better(cnd, x2)) { x2 = cnd; d2 = list_dot[ci]; }
+      }
+      if (w0 + BF16_LIST < total) __syncthreads();  // the next round reuses the list
+    }
+    if (x1.j >= c || (kk == 3 && x2.j >= c)) {
+      if (tid == 0) atomicOr(A.err, 1);
+      return;
+    }
+    if (tid == 0) {
+      n_cut += total > BF16_LIST ? 1 : 0;
+      n_scored += total;
+    }
+    const int t0 = i, t1 = x1.j, t2 = kk == 3 ? x2.j : -1;
+    // partner rows of G~ and D, and rows T of Q
+    float2 p1[PER], p2[PER];
+    float q0[PER], q1[PER], q2[PER];
+#pragma unroll
+    for (int q = 0; q < PER; ++q) {
+      const int j = tid + q * NT;
+      p1[q] = p2[q] = make_float2(0.f, 0.f);
+      q0[q] = q1[q] = q2[q] = 0.f;
+      if (j < c) {
+        p1[q] = GD[(size_t)t1 * c + j];
+        q0[q] = Q[(size_t)t0 * c + j];
+        q1[q] = Q[(size_t)t1 * c + j];
+        if (kk == 3) {
+          p2[q] = GD[(size_t)t2 * c + j];
+          q2[q] = Q[(size_t)t2 * c + j];
+        }
+      }
+    }
+    float g12 = 0.f;
+    if (kk == 3 && wv == 0) g12 = slab_dot(SL + (size_t)t1 * Ru, SL + (size_t)t2 * Ru, Ru, lane);
+    if (tid == 0) {
+      double g[3][3] = {}, d[3][3] = {}, O[3][3] = {};
+      g[0][0] = gdiag[t0];
+      d[0][0] = ddiag[t0];
+      g[1][1] = gdiag[t1];
+      d[1][1] = ddiag[t1];
+      g[0][1] = g[1][0] = d1;
+      d[0][1] = d[1][0] = R0[t1].y;
+      if (kk == 3) {
+        g[2][2] = gdiag[t2];
+        d[2][2] = ddiag[t2];
+        g[0][2] = g[2][0] = d2;
+        d[0][2] = d[2][0] = R0[t2].y;
+        g[1][2] = g[2][1] = g12;
+        const float2 a12 = GD[(size_t)t1 * c + t2], a21 = GD[(size_t)t2 * c + t1];
+        d[1][2] = d[2][1] = 0.5 * ((double)a12.y + (double)a21.y);
+      }
+      double margin = 3.0e38;
+      if (kk == 2) {
+        double cc, ss, ta;
+        rot2(g[0][0], g[0][1], g[1][1], cc, ss, ta);
+        O[0][0] = cc; O[0][1] = -ss; O[1][0] = ss; O[1][1] = cc;
+        margin = fmin(margin, ta);
+      } else {
+        double tm, em;
+        rot3(g, O, tm, em);
+        margin = fmin(margin, fmin(tm, em));
+      }
+      double gn[3][3] = {}, dn[3][3] = {};
+#pragma unroll
+      for (int a = 0; a < kk; ++a)
+#pragma unroll
+        for (int b = 0; b < kk; ++b) {
+          double sg = 0.0, sd = 0.0;
+#pragma unroll
+          for (int x = 0; x < kk; ++x) {
+            double tg = 0.0, td = 0.0;
+#pragma unroll
+            for (int y = 0; y < kk; ++y) { tg += g[x][y] * O[b][y]; td += d[x][y] * O[b][y]; }
+            sg += O[a][x] * tg;
+            sd += O[a][x] * td;
+          }
+          gn[a][b] = sg;
+          dn[a][b] = sd;
+        }
+      const double f0 = fmax(0.0, gn[0][0] - dn[0][0] * dn[0][0]);
+      const double f1v = fmax(0.0, gn[1][1] - dn[1][1] * dn[1][1]);
+      const double f2v = kk == 3 ? fmax(0.0, gn[2][2] - dn[2][2] * dn[2][2]) : 1e300;
+      int es = f1v <= f0 ? 1 : 0;
+      double fmin_ = es == 1 ? f1v : f0;
+      if (kk == 3 && f2v <= fmin_) { es = 2; fmin_ = f2v; }
+      {
+        const double hi01 = fmax(f0, f1v), lo01 = fmin(f0, f1v);
+        const double lo2 = kk == 3 ? (f2v <= lo01 ? lo01 : fmin(hi01, f2v)) : hi01;
+        const double lo1 = fmin(lo01, f2v);
+        margin = fmin(margin, lo2 > 0.0 ? (lo2 - lo1) / lo2 : 0.0);
+      }
+      const int e = es == 0 ? t0 : (es == 1 ? t1 : t2);
+      const double dee = es == 0 ? dn[0][0] : (es == 1 ? dn[1][1] : dn[2][2]);
+      gdiag[t0] = (float)gn[0][0];
+      ddiag[t0] = (float)dn[0][0];
+      gdiag[t1] = (float)gn[1][1];
+      ddiag[t1] = (float)dn[1][1];
+      if (kk == 3) {
+        gdiag[t2] = (float)gn[2][2];
+        ddiag[t2] = (float)dn[2][2];
+      }
+      sh_e = e;
+#pragma unroll
+      for (int a = 0; a < 9; ++a) { sh_O[a] = 0.f; sh_gn[a] = 0.f; sh_dn[a] = 0.f; }
+#pragma unroll
+      for (int a = 0; a < kk; ++a)
+#pragma unroll
+        for (int b = 0; b < kk; ++b) {
+          sh_O[a * 3 + b] = (float)O[a][b];
+          sh_gn[a * 3 + b] = (float)gn[a][b];
+          sh_dn[a * 3 + b] = (float)dn[a][b];
+        }
+      const int64_t ridx = A.rot0 + rb + s;
+      A.rot_loc[ridx * 3 + 0] = t0;
+      A.rot_loc[ridx * 3 + 1] = t1;
+      A.rot_loc[ridx * 3 + 2] = kk == 3 ? t2 : -1;
+      A.rot_gid[ridx * 3 + 0] = lgid[t0];
+      A.rot_gid[ridx * 3 + 1] = lgid[t1];
+      A.rot_gid[ridx * 3 + 2] = kk == 3 ? lgid[t2] : -1;
+#pragma unroll
+      for (int a = 0; a < 9; ++a) A.rot_o[ridx * 9 + a] = sh_O[a];
+      A.rot_ret[ridx] = lgid[e];
+      A.rot_margin[ridx] = (float)margin;
+      A.rot_lit[ridx] = 2.0 * fmin_;
+      A.hdiag[lgid[e]] = (float)dee;
+      A.retflag[o + e] = 1;
+    } else if (wv == 1 && s + 1 < r) {
+      const uint64_t h = pmmf_hash4(A.seed, PMMF_TAG_SEED_ROW, (uint64_t)A.p, (uint64_t)u,
+                                    (uint64_t)(s + 1));
+      const int rank = (int)pmmf_mulhi(h, (uint64_t)(c - s - 1));
+      const int c0 = select_active(mask, nw, rank);
+      const int c1 = select_active(mask, nw, rank + 1);
+      if (tid == PMMF_WAVE) { sh_c0 = c0; sh_c1 = c1; }
+    }
+#pragma unroll
+    for (int q = 0; q < PER; ++q) {
+      const int j = tid + q * NT;
+      if (j < c) {
+        R1[j] = p1[q];
+        if (kk == 3) R2[j] = p2[q];
+      }
+    }
+    __syncthreads();  // B
+
+    float o_[9];
+#pragma unroll
+    for (int a = 0; a < 9; ++a) o_[a] = sh_O[a];
+    const int e = sh_e;
+    const bool more = s + 1 < r;
+    const int nxt = more ? (sh_c0 < e ? sh_c0 : sh_c1) : -1;
+    const int aslot = nxt == t0 ? 0 : (nxt == t1 ? 1 : ((kk == 3 && nxt == t2) ? 2 : -1));
+    float2 nrow[PER];
+#pragma unroll
+    for (int q = 0; q < PER; ++q) {
+      const int j = tid + q * NT;
+      nrow[q] = make_float2(0.f, 0.f);
+      if (more && aslot < 0 && j < c) nrow[q] = GD[(size_t)nxt * c + j];
+    }
+    float2 vn[3] = {make_float2(0.f, 0.f), make_float2(0.f, 0.f), make_float2(0.f, 0.f)};
+    if (more && aslot < 0) {
+      vn[0] = R0[nxt];
+      vn[1] = R1[nxt];
+      if (kk == 3) vn[2] = R2[nxt];
+    }
+    if (tid == 0) mask[e >> 5] &= ~(1u << (e & 31));
+    const int Tt[3] = {t0, t1, t2};
+    if (tid < kk * kk) {
+      const int a = tid / kk, b = tid % kk;
+      GD[(size_t)Tt[a] * c + Tt[b]] = make_float2(sh_gn[a * 3 + b], sh_dn[a * 3 + b]);
+    }
+    // slab columns T right-rotated: S[:, T] <- S[:, T] O^T
+    for (int rr = tid; rr < Ru; rr += NT) {
+      float v[3] = {SL[(size_t)t0 * Ru + rr], SL[(size_t)t1 * Ru + rr],
+                    kk == 3 ? SL[(size_t)t2 * Ru + rr] : 0.f};
+#pragma unroll
+      for (int a = 0; a < K; ++a) {
+        float acc = 0.f;
+#pragma unroll
+        for (int b = 0; b < K; ++b) acc = fmaf(o_[a * 3 + b], v[b], acc);
+        SL[(size_t)Tt[a] * Ru + rr] = acc;
+      }
+    }
+#pragma unroll
+    for (int q = 0; q < PER; ++q) {
+      const int j = tid + q * NT;
+      if (j >= c) continue;
+      if (kk == 2) {
+        Q[(size_t)t0 * c + j] = o_[0] * q0[q] + o_[1] * q1[q];
+        Q[(size_t)t1 * c + j] = o_[3] * q0[q] + o_[4] * q1[q];
+      } else {
+        Q[(size_t)t0 * c + j] = o_[0] * q0[q] + o_[1] * q1[q] + o_[2] * q2[q];
+        Q[(size_t)t1 * c + j] = o_[3] * q0[q] + o_[4] * q1[q] + o_[5] * q2[q];
+        Q[(size_t)t2 * c + j] = o_[6] * q0[q] + o_[7] * q1[q] + o_[8] * q2[q];
+      }
+      const int bj = j == t0 ? 0 : (j == t1 ? 1 : ((kk == 3 && j == t2) ? 2 : -1));
+      if (bj >= 0) {
+        if (more) {
+          if (aslot >= 0) nrow[q] = make_float2(sh_gn[aslot * 3 + bj], sh_dn[aslot * 3 + bj]);
+          else nrow[q] = rot_entry<K>(o_, bj, vn);
+        }
+        continue;
+      }
+      const bool a_now = (mask[j >> 5] >> (j & 31)) & 1u;
+      if (!a_now) continue;
+      const float2 v[3] = {cur[q], p1[q], p2[q]};
+#pragma unroll
+      for (int a = 0; a < K; ++a) {
+        const float2 nv = rot_entry<K>(o_, a, v);
+        GD[(size_t)Tt[a] * c + j] = nv;
+        if (nv.x != 0.f || nv.y != 0.f || v[a].x != 0.f || v[a].y != 0.f)
+          GD[(size_t)j * c + Tt[a]] = nv;
+        if (a == aslot) nrow[q] = nv;
+      }
+    }
+#pragma unroll
+    for (int q = 0; q < PER; ++q) cur[q] = nrow[q];
+    e_prev = e;
+    i = nxt;
+  }
+  if (tid == 0 && r > 0) {
+    atomicAdd(A.sl_stats + 0, n_cut);
+    atomicAdd(A.sl_stats + 1, n_scored);
+  }
+}
+
+template <int PER, int K>
+static hipError_t find_bf16_launch(const FindArgs& a, int m, int cmax, size_t lds,
+                                   hipStream_t s) {
+  if (lds > 64 * 1024) {
+    hipError_t e = hipFuncSetAttribute((const void*)&k_find_bf16<PER, K>,
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e != hipSuccess) return e;
+  }
+  k_find_bf16<PER, K><<<m, 256, lds, s>>>(a, cmax);
+  return hipGetLastError();
+}
+
+template <int PER>
+static hipError_t find_bf16_launch_k(const FindArgs& a, int m, int cmax, size_t lds,
+                                     hipStream_t s) {
+  return a.k == 3 ? find_bf16_launch<PER, 3>(a, m, cmax, lds, s)
+                  : find_bf16_launch<PER, 2>(a, m, cmax, lds, s);
+}
+
+hipError_t launch_find_bf16(const FindArgs& a, int m, int cmax, hipStream_t s) {
+  if (m == 0) return hipSuccess;
+  const size_t lds = find_lds_bytes(cmax);
+  if (cmax <= 256) return find_bf16_launch_k<1>(a, m, cmax, lds, s);
+  if (cmax <= 512) return find_bf16_launch_k<2>(a, m, cmax, lds, s);
+  if (cmax <= 1024) return find_bf16_launch_k<4>(a, m, cmax, lds, s);
+  if (cmax <= 2048) return find_bf16_launch_k<8>(a, m, cmax, lds, s);
+  if (cmax <= 3072) return find_bf16_launch_k<12>(a, m, cmax, lds, s);
+  return hipErrorInvalidValue;
 }
 
 size_t find_lds_bytes(int cmax) {

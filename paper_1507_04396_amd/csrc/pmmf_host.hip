@@ -93,6 +93,7 @@ struct StageDev {
   double loss = 0.0;
   double gram_ms = 0.0, find_ms = 0.0, rotate_ms = 0.0;
   bool dense_gram = false;
+  int64_t bf16_long = 0, bf16_rescored = 0;  // BF16 form: long shortlists, candidates rescored
   // sweep plan (built on first use): units of whole rotation components, and the clusters
   // holding a component larger than a unit, which the level kernel handles
   int nu = 0, nbig = 0, big_cmax = 0, big_rmax = 0;
@@ -208,7 +209,8 @@ void validate(int64_t n, const mmf_params* p) {
   const bool single = p->cluster_min == 0 && p->cluster_max == 0;
   if (!single && (p->cluster_min < 2 || p->cluster_max < 2 * p->cluster_min))
     raise(MMF_EINVAL, "cluster bounds need cluster_min >= 2 and cluster_max >= 2 cluster_min");
-  if (p->gram_mode != 0) raise(MMF_EINVAL, "gram_mode must be 0 (FP32 Gram)");
+  if (p->gram_mode != 0 && p->gram_mode != 1)
+    raise(MMF_EINVAL, "gram_mode must be 0 (FP32 Gram) or 1 (BF16 Gram, FP32 rescoring)");
 }
 
 // sparse matrix in CSR
@@ -539,6 +541,8 @@ extern "C" int mmf_factor(int64_t n, int64_t nnz, const int64_t* d_rowptr, const
     pool = std::max(pool, g);
   }
   DBuf GD, Q, retflag, keep, scan, cnt, loss_row, overflow, gid_cur, tbase, dense_buf;
+  DBuf bf_bm, bf_pre, bf_R, bf_off, bf_slab, bf_slab16, bf_stats;  // BF16 form only
+  if (p->gram_mode == 1) bf_stats.ensure(2 * sizeof(unsigned long long));
   GD.ensure(pool * sizeof(float2));
   Q.ensure(pool * sizeof(float));
   retflag.ensure(n);
@@ -576,7 +580,35 @@ extern "C" int mmf_factor(int64_t n, int64_t nnz, const int64_t* d_rowptr, const
     const bool dense_gram = (int64_t)S <= DENSE_GRAM_MAX_ROWS &&
                             (double)M.nnz >= DENSE_GRAM_MIN_FILL * (double)S * (double)S;
     sd.dense_gram = dense_gram;
-    if (dense_gram) {
+    const bool bf16 = h->prm.gram_mode == 1;
+    if (bf16) {
+      // slab rows R_u, slab sizes (host), then FP32 + BF16 slabs, G~ on the matrix cores, D
+      // and the exact column norms
+      sd.dense_gram = true;
+      const int64_t W = (S + 31) / 32;
+      bf_bm.ensure((size_t)sd.m * W * sizeof(uint32_t));
+      bf_pre.ensure((size_t)sd.m * W * sizeof(int32_t));
+      bf_R.ensure((size_t)sd.m * sizeof(int32_t));
+      HIPCHK(pmmf::launch_slab_rows(S, sd.m, M.rp.as<int64_t>(), M.ci.as<int32_t>(),
+                                    sd.cl_of.as<int32_t>(), W, bf_bm.as<uint32_t>(),
+                                    bf_pre.as<int32_t>(), bf_R.as<int32_t>(), s));
+      std::vector<int32_t> Rh(sd.m);
+      HIPCHK(hipMemcpyAsync(Rh.data(), bf_R.p, sd.m * sizeof(int32_t), hipMemcpyDeviceToHost, s));
+      HIPCHK(hipStreamSynchronize(s));
+      std::vector<int64_t> soff(sd.m + 1, 0);
+      for (int u = 0; u < sd.m; ++u)
+        soff[u + 1] = soff[u] + (int64_t)Rh[u] * (sd.off_h[u + 1] - sd.off_h[u]);
+      upload(bf_off, soff, s);
+      bf_slab.ensure(std::max<int64_t>(soff[sd.m], 1) * sizeof(float));
+      bf_slab16.ensure(std::max<int64_t>(soff[sd.m], 1) * sizeof(uint16_t));
+      HIPCHK(pmmf::launch_gram_bf16(S, sd.m, M.rp.as<int64_t>(), M.ci.as<int32_t>(),
+                                    M.cv.as<float>(), sd.off.as<int32_t>(),
+                                    sd.cl_of.as<int32_t>(), W, bf_bm.as<uint32_t>(),
+                                    bf_pre.as<int32_t>(), bf_off.as<int64_t>(),
+                                    bf_R.as<int32_t>(), soff[sd.m], bf_slab.as<float>(),
+                                    bf_slab16.as<unsigned short>(), sd.gbase.as<int64_t>(),
+                                    GD.as<float2>(), Q.as<float>(), sd.cmax, s));
+    } else if (dense_gram) {
       dense_buf.ensure((size_t)S * S * sizeof(float));
       HIPCHK(pmmf::launch_gram_dense(S, M.rp.as<int64_t>(), M.ci.as<int32_t>(), M.cv.as<float>(),
                                      dense_buf.as<float>(), sd.off.as<int32_t>(), sd.m,
@@ -611,7 +643,21 @@ extern "C" int mmf_factor(int64_t n, int64_t nnz, const int64_t* d_rowptr, const
     fa.retflag = retflag.as<uint8_t>();
     fa.err = overflow.as<int32_t>() + 1;
     HIPCHK(hipEventRecord(pev.e[1], s));
-    HIPCHK(pmmf::launch_find(fa, sd.m, cm, find_threads(), s));
+    if (bf16) {
+      HIPCHK(hipMemsetAsync(bf_stats.p, 0, 2 * sizeof(unsigned long long), s));
+      fa.slab = bf_slab.as<float>();
+      fa.slab_off = bf_off.as<int64_t>();
+      fa.slab_rows = bf_R.as<int32_t>();
+      fa.sl_stats = bf_stats.as<unsigned long long>();
+      HIPCHK(pmmf::launch_find_bf16(fa, sd.m, cm, s));
+      unsigned long long st2[2];
+      HIPCHK(hipMemcpyAsync(st2, bf_stats.p, sizeof(st2), hipMemcpyDeviceToHost, s));
+      HIPCHK(hipStreamSynchronize(s));
+      sd.bf16_long = (int64_t)st2[0];
+      sd.bf16_rescored = (int64_t)st2[1];
+    } else {
+      HIPCHK(pmmf::launch_find(fa, sd.m, cm, find_threads(), s));
+    }
     HIPCHK(hipEventRecord(pev.e[2], s));
     // rotation levels and the sweep log
     sd.sw_loc.ensure(sd.t * h->k * sizeof(int32_t));
@@ -1155,6 +1201,8 @@ extern "C" int mmf_get_stage_info(mmf_handle hh, int32_t stage, mmf_stage_info* 
     const int64_t c = sd.off_h[u + 1] - sd.off_h[u];
     out->find_bytes += (int64_t)sd.rcnt_h[u] * 4 * c * (1 + 4 * h.k);
   }
+  out->bf16_long = sd.bf16_long;
+  out->bf16_rescored = sd.bf16_rescored;
   return MMF_OK;
   ABI_END
 }

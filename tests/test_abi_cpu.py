@@ -53,7 +53,7 @@ def _factor(lib, n=10, nnz=0, **kw):
 
 @pytest.mark.parametrize("kw", [dict(k=4), dict(eta=0.0), dict(eta=0.7), dict(core_size=0),
                                 dict(core_size=11), dict(cluster_min=4, cluster_max=6),
-                                dict(cluster_min=1, cluster_max=8), dict(gram_mode=1)])
+                                dict(cluster_min=1, cluster_max=8), dict(gram_mode=2)])
 def test_factor_rejects_bad_params(lib, kw):
     from paper_1507_04396_amd import _lib
     assert _factor(lib, **kw) == -1
