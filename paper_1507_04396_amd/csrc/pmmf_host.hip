@@ -1,8 +1,12 @@
 // Host side of the pMMF library: the C ABI declared in include/pmmf.h.
 #include "pmmf.h"
 
+#include <sys/stat.h>
+
 #include <algorithm>
 #include <cmath>
+#include <cstdio>
+#include <map>
 #include <cstdlib>
 #include <cstring>
 #include <memory>
@@ -117,6 +121,12 @@ struct PhaseEvents {
   }
 };
 
+// launch configuration of the sweeps (chosen by the autotuner)
+struct SweepCfg {
+  int wpb = 2;  // units (waves) per workgroup of the unit sweep
+  int W = 0;    // column tile of the level sweep
+};
+
 struct mmf_plan {
   int64_t n = 0, core = 0, R = 0;
   int k = 2;
@@ -128,6 +138,7 @@ struct mmf_plan {
   bool inv_ready = false;
   bool units_ready = false;
   uint64_t version = 0;  // bumped whenever theta, H or the rotations change
+  std::map<std::pair<std::string, int64_t>, SweepCfg> tune;  // (product, width) -> config
   DBuf ws[16];
   mmf_info info{};
   hipStream_t stream = nullptr;
@@ -860,13 +871,162 @@ void ensure_inverse(mmf_plan& h, hipStream_t s) {
 }
 
 // Y = U^T op(H) U X with op = H (inverse = false) or H^{-1}
-void apply_impl(mmf_plan& h, const float* x, float* y, int64_t nrhs, int64_t ld, hipStream_t s,
-                bool inverse, float* ws0 = nullptr, float* ws1 = nullptr) {
-  if (nrhs < 0 || ld < nrhs || (!x && nrhs > 0) || (!y && nrhs > 0))
-    raise(MMF_EINVAL, "bad vector arguments");
-  if (nrhs == 0) return;
-  if (inverse) ensure_inverse(h, s);
-  ensure_units(h, s);
+// ------------------------------------------------------------------------------------------
+// Sweep autotuner.  The first product (or adjoint) of a handle with a given column count times each
+// candidate configuration of the sweep kernels on the caller's own buffers (the products are
+// idempotent) and keeps the fastest: waves per workgroup of the unit sweep (1, 2, 4) and, when
+// some cluster needs the level kernel, its column tile (widest that fits, half, quarter).  Results
+// persist in a small JSON file (PMMF_TUNE_CACHE, default $HOME/.cache/pmmf_tune.json), keyed by
+// device, rotation order, size, core, vectors per sweep, column count and the sweep plan's shape,
+// so later processes reuse them.  PMMF_AUTOTUNE=0 keeps the default configuration.
+struct TuneCache {
+  std::mutex mu;
+  bool loaded = false;
+  std::string path;
+  std::map<std::string, std::pair<SweepCfg, double>> entries;
+};
+TuneCache g_tune;
+
+bool autotune_enabled() {
+  const char* e = std::getenv("PMMF_AUTOTUNE");
+  return !(e && std::strcmp(e, "0") == 0);
+}
+
+std::string tune_path() {
+  const char* e = std::getenv("PMMF_TUNE_CACHE");
+  if (e && *e) return e;
+  const char* home = std::getenv("HOME");
+  return std::string(home && *home ? home : "/tmp") + "/.cache/pmmf_tune.json";
+}
+
+// one entry per line:  "key": {"wpb": 2, "W": 16, "ms": 0.123},
+void tune_load_locked() {
+  g_tune.path = tune_path();
+  g_tune.loaded = true;
+  FILE* f = std::fopen(g_tune.path.c_str(), "r");
+  if (!f) return;
+  char line[1024];
+  while (std::fgets(line, sizeof line, f)) {
+    const char* q0 = std::strchr(line, '"');
+    const char* q1 = q0 ? std::strchr(q0 + 1, '"') : nullptr;
+    const char* br = q1 ? std::strchr(q1, '{') : nullptr;
+    if (!br) continue;
+    SweepCfg c;
+    double ms = 0.0;
+    if (std::sscanf(br, "{\"wpb\": %d, \"W\": %d, \"ms\": %lf}", &c.wpb, &c.W, &ms) == 3)
+      g_tune.entries[std::string(q0 + 1, q1)] = {c, ms};
+  }
+  std::fclose(f);
+}
+
+void tune_save_locked() {
+  const std::string& path = g_tune.path;
+  const size_t slash = path.rfind('/');
+  if (slash != std::string::npos) {
+    const std::string dir = path.substr(0, slash);
+    for (size_t k = 1; k <= dir.size(); ++k)  // mkdir -p, one level at a time
+      if (k == dir.size() || dir[k] == '/') (void)mkdir(dir.substr(0, k).c_str(), 0755);
+  }
+  const std::string tmp = path + ".tmp";
+  FILE* f = std::fopen(tmp.c_str(), "w");
+  if (!f) return;
+  std::fprintf(f, "{\n");
+  size_t k = 0;
+  for (const auto& kv : g_tune.entries) {
+    std::fprintf(f, "  \"%s\": {\"wpb\": %d, \"W\": %d, \"ms\": %.6f}%s\n", kv.first.c_str(),
+                 kv.second.first.wpb, kv.second.first.W, kv.second.second,
+                 ++k < g_tune.entries.size() ? "," : "");
+  }
+  std::fprintf(f, "}\n");
+  std::fclose(f);
+  (void)std::rename(tmp.c_str(), path.c_str());
+}
+
+std::string tune_key(const mmf_plan& h, const char* what, int nv, int64_t nrhs) {
+  int dev = 0;
+  hipDeviceProp_t prop{};
+  if (hipGetDevice(&dev) != hipSuccess || hipGetDeviceProperties(&prop, dev) != hipSuccess)
+    std::strcpy(prop.gcnArchName, "unknown");
+  int64_t nu = 0, nbig = 0;
+  for (const auto& sp : h.st) {
+    nu += sp->nu;
+    nbig += sp->nbig;
+  }
+  std::string arch = prop.gcnArchName;
+  for (char& ch : arch)
+    if (ch == '"' || ch == '\\') ch = '_';
+  char buf[512];
+  std::snprintf(buf, sizeof buf, "%s|%s|k%d|n%lld|core%lld|nv%d|cols%lld|units%lld|big%lld",
+                arch.c_str(), what, h.k, (long long)h.n, (long long)h.core, nv, (long long)nrhs,
+                (long long)nu, (long long)nbig);
+  return buf;
+}
+
+// the configuration for (what, nv, nrhs): from the handle, the cache file, or by timing `run`
+template <class Run>
+SweepCfg sweep_config(mmf_plan& h, const char* what, int nv, int64_t nrhs, hipStream_t s,
+                      Run run) {
+  const auto hk = std::make_pair(std::string(what) + std::to_string(nv), nrhs);
+  auto it = h.tune.find(hk);
+  if (it != h.tune.end()) return it->second;
+  SweepCfg def;
+  def.W = pick_tile(h, nv, nrhs);
+  hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
+  if (!autotune_enabled() || hipStreamIsCapturing(s, &cap) != hipSuccess ||
+      cap != hipStreamCaptureStatusNone) {
+    return def;
+  }
+  const std::string key = tune_key(h, what, nv, nrhs);
+  {
+    std::lock_guard<std::mutex> lk(g_tune.mu);
+    if (!g_tune.loaded || g_tune.path != tune_path()) {
+      g_tune.entries.clear();
+      tune_load_locked();
+    }
+    auto f = g_tune.entries.find(key);
+    if (f != g_tune.entries.end()) {
+      h.tune[hk] = f->second.first;
+      return f->second.first;
+    }
+  }
+  bool big = false;
+  for (const auto& sp : h.st) big = big || sp->nbig > 0;
+  std::vector<int> Ws{def.W};
+  if (big)
+    for (int w = def.W / 2; w >= std::max(1, def.W / 4); w /= 2) Ws.push_back(w);
+  hipEvent_t e0, e1;
+  HIPCHK(hipEventCreate(&e0));
+  HIPCHK(hipEventCreate(&e1));
+  SweepCfg best = def;
+  double best_ms = 1e300;
+  for (int wpb : {1, 2, 4})
+    for (int W : Ws) {
+      SweepCfg c{wpb, W};
+      run(c);  // warm
+      HIPCHK(hipEventRecord(e0, s));
+      for (int r = 0; r < 3; ++r) run(c);
+      HIPCHK(hipEventRecord(e1, s));
+      HIPCHK(hipEventSynchronize(e1));
+      float ms = 0.f;
+      HIPCHK(hipEventElapsedTime(&ms, e0, e1));
+      if (ms / 3.0 < best_ms) {
+        best_ms = ms / 3.0;
+        best = c;
+      }
+    }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  h.tune[hk] = best;
+  {
+    std::lock_guard<std::mutex> lk(g_tune.mu);
+    g_tune.entries[key] = {best, best_ms};
+    tune_save_locked();
+  }
+  return best;
+}
+
+void apply_body(mmf_plan& h, const float* x, float* y, int64_t nrhs, int64_t ld, hipStream_t s,
+                bool inverse, float* ws0, float* ws1, const SweepCfg& cfg) {
   const float* Hc = inverse ? h.hinv.as<float>() : h.hcore.as<float>();
   const int P = (int)h.st.size();
   const int64_t core = h.core;
@@ -877,7 +1037,7 @@ void apply_impl(mmf_plan& h, const float* x, float* y, int64_t nrhs, int64_t ld,
   }
   const int64_t s1 = h.st[0]->size - h.st[0]->t;
   float* buf[2] = {ws0 ? ws0 : wsbuf(h, 0, s1 * nrhs), ws1 ? ws1 : wsbuf(h, 1, s1 * nrhs)};
-  const int W = pick_tile(h, 1, nrhs);
+  const int W = cfg.W;
   for (int p = 1; p <= P; ++p) {
     const StageDev& sd = *h.st[p - 1];
     pmmf::FwdIO io{};
@@ -890,7 +1050,7 @@ void apply_impl(mmf_plan& h, const float* x, float* y, int64_t nrhs, int64_t ld,
     io.mode[0] = inverse ? 2 : 1;
     io.hdiag = h.hdiag.as<float>();
     io.nrhs = nrhs;
-    HIPCHK(pmmf::launch_unit_fwd(unit_view(h, sd), io, 1, s));
+    HIPCHK(pmmf::launch_unit_fwd(unit_view(h, sd), io, 1, cfg.wpb, s));
     HIPCHK(pmmf::launch_sweep_fwd(sweep_view(h, sd), io, W, 1, s));
   }
   HIPCHK(pmmf::launch_gemm((int)core, (int)nrhs, (int)core, Hc, (int)core, 0, buf[P % 2],
@@ -912,9 +1072,22 @@ void apply_impl(mmf_plan& h, const float* x, float* y, int64_t nrhs, int64_t ld,
       io.ld_out = nrhs;
     }
     io.nrhs = nrhs;
-    HIPCHK(pmmf::launch_unit_rev(unit_view(h, sd), io, 1, false, s));
+    HIPCHK(pmmf::launch_unit_rev(unit_view(h, sd), io, 1, false, cfg.wpb, s));
     HIPCHK(pmmf::launch_sweep_rev(sweep_view(h, sd), io, W, 1, false, s));
   }
+}
+
+void apply_impl(mmf_plan& h, const float* x, float* y, int64_t nrhs, int64_t ld, hipStream_t s,
+                bool inverse, float* ws0 = nullptr, float* ws1 = nullptr) {
+  if (nrhs < 0 || ld < nrhs || (!x && nrhs > 0) || (!y && nrhs > 0))
+    raise(MMF_EINVAL, "bad vector arguments");
+  if (nrhs == 0) return;
+  if (inverse) ensure_inverse(h, s);
+  ensure_units(h, s);
+  const SweepCfg cfg = sweep_config(h, "apply", 1, nrhs, s, [&](const SweepCfg& c) {
+    apply_body(h, x, y, nrhs, ld, s, inverse, ws0, ws1, c);
+  });
+  apply_body(h, x, y, nrhs, ld, s, inverse, ws0, ws1, cfg);
 }
 
 }  // namespace
@@ -1032,15 +1205,9 @@ extern "C" int mmf_graph_destroy(mmf_graph gg) {
   ABI_END
 }
 
-extern "C" int mmf_backward(mmf_handle hh, const float* d_x, const float* d_ybar, float* d_xbar,
-                            float* d_hdiag_bar, float* d_hcore_bar, float* d_theta_bar,
-                            int64_t nrhs, int64_t ld, void* stream) {
-  ABI_BEGIN
-  mmf_plan& h = *checked(hh);
-  hipStream_t s = as_stream(stream);
-  if (nrhs < 1 || ld < nrhs || !d_x || !d_ybar) raise(MMF_EINVAL, "bad vector arguments");
-  if (d_theta_bar && h.k != 2) raise(MMF_EINVAL, "angle gradients exist only for k = 2");
-  ensure_units(h, s);
+void backward_body(mmf_plan& h, const float* d_x, const float* d_ybar, float* d_xbar,
+                   float* d_hdiag_bar, float* d_hcore_bar, float* d_theta_bar, int64_t nrhs,
+                   int64_t ld, hipStream_t s, const SweepCfg& cfg) {
   const int P = (int)h.st.size();
   const int64_t n = h.n, core = h.core;
   const float* Hc = h.hcore.as<float>();
@@ -1058,7 +1225,7 @@ extern "C" int mmf_backward(mmf_handle hh, const float* d_x, const float* d_ybar
     a_core = d_x;
     b_core = d_ybar;
   }
-  const int W2 = pick_tile(h, 2, nrhs);
+  const int W2 = cfg.W;
   for (int p = 1; p <= P; ++p) {
     const StageDev& sd = *h.st[p - 1];
     pmmf::FwdIO io{};
@@ -1074,7 +1241,7 @@ extern "C" int mmf_backward(mmf_handle hh, const float* d_x, const float* d_ybar
     io.mode[0] = io.mode[1] = 0;
     io.hdiag = h.hdiag.as<float>();
     io.nrhs = nrhs;
-    HIPCHK(pmmf::launch_unit_fwd(unit_view(h, sd), io, 2, s));
+    HIPCHK(pmmf::launch_unit_fwd(unit_view(h, sd), io, 2, cfg.wpb, s));
     HIPCHK(pmmf::launch_sweep_fwd(sweep_view(h, sd), io, W2, 2, s));
   }
   int64_t lda_core = nrhs;
@@ -1104,7 +1271,7 @@ extern "C" int mmf_backward(mmf_handle hh, const float* d_x, const float* d_ybar
     if (d_xbar)
       HIPCHK(hipMemcpy2DAsync(d_xbar, ld * sizeof(float), gb_core, nrhs * sizeof(float),
                               nrhs * sizeof(float), core, hipMemcpyDeviceToDevice, s));
-    return MMF_OK;
+    return;
   }
   // reverse passes: A carries (z = U-states of ybar, g_a), B carries (z = states of x, g_b)
   float* RA[2][2] = {{wsbuf(h, 10, s1 * nrhs), wsbuf(h, 11, s1 * nrhs)},
@@ -1158,7 +1325,7 @@ extern "C" int mmf_backward(mmf_handle hh, const float* d_x, const float* d_ybar
       io.theta_part = pass == 0 ? pa_buf.as<float>() : pb_buf.as<float>();
       io.theta_stride = sd.t;
       HIPCHK(hipMemsetAsync(io.theta_part, 0, (size_t)ntiles * sd.t * sizeof(float), s));
-      HIPCHK(pmmf::launch_unit_rev(unit_view(h, sd), io, 2, h.k == 2, s));
+      HIPCHK(pmmf::launch_unit_rev(unit_view(h, sd), io, 2, h.k == 2, cfg.wpb, s));
       HIPCHK(pmmf::launch_sweep_rev(v, io, W2, 2, h.k == 2, s));
     }
     if (d_theta_bar)
@@ -1167,6 +1334,21 @@ extern "C" int mmf_backward(mmf_handle hh, const float* d_x, const float* d_ybar
   }
   // keep the temporaries alive until the stream has consumed them
   HIPCHK(hipStreamSynchronize(s));
+}
+
+extern "C" int mmf_backward(mmf_handle hh, const float* d_x, const float* d_ybar, float* d_xbar,
+                            float* d_hdiag_bar, float* d_hcore_bar, float* d_theta_bar,
+                            int64_t nrhs, int64_t ld, void* stream) {
+  ABI_BEGIN
+  mmf_plan& h = *checked(hh);
+  hipStream_t s = as_stream(stream);
+  if (nrhs < 1 || ld < nrhs || !d_x || !d_ybar) raise(MMF_EINVAL, "bad vector arguments");
+  if (d_theta_bar && h.k != 2) raise(MMF_EINVAL, "angle gradients exist only for k = 2");
+  ensure_units(h, s);
+  const SweepCfg cfg = sweep_config(h, "adjoint", 2, nrhs, s, [&](const SweepCfg& c) {
+    backward_body(h, d_x, d_ybar, d_xbar, d_hdiag_bar, d_hcore_bar, d_theta_bar, nrhs, ld, s, c);
+  });
+  backward_body(h, d_x, d_ybar, d_xbar, d_hdiag_bar, d_hcore_bar, d_theta_bar, nrhs, ld, s, cfg);
   return MMF_OK;
   ABI_END
 }

@@ -71,8 +71,10 @@ struct RevIO {
 };
 
 size_t sweep_lds_bytes(int k, int W, int nv, int cmax, int rmax);
-hipError_t launch_unit_fwd(const UnitStage& st, const FwdIO& io, int nv, hipStream_t s);
-hipError_t launch_unit_rev(const UnitStage& st, const RevIO& io, int nv, bool theta, hipStream_t s);
+// wpb: waves (units) per workgroup, 1, 2 or 4
+hipError_t launch_unit_fwd(const UnitStage& st, const FwdIO& io, int nv, int wpb, hipStream_t s);
+hipError_t launch_unit_rev(const UnitStage& st, const RevIO& io, int nv, bool theta, int wpb,
+                           hipStream_t s);
 hipError_t launch_sweep_fwd(const SweepStage& st, const FwdIO& io, int W, int nv, hipStream_t s);
 hipError_t launch_sweep_rev(const SweepStage& st, const RevIO& io, int W, int nv, bool theta,
                             hipStream_t s);

@@ -587,30 +587,36 @@ __global__ void __launch_bounds__(256) k_unit_sweep(UnitStage st, FwdIO fio, Rev
 }
 
 template <int K, int NV, int MODE>
-static hipError_t unit_launch(const UnitStage& st, const FwdIO& fio, const RevIO& rio,
+static hipError_t unit_launch(const UnitStage& st, const FwdIO& fio, const RevIO& rio, int wpb,
                               hipStream_t s) {
   if (st.nu == 0) return hipSuccess;
-  constexpr int WPB = 2;
-  const size_t lds = (size_t)WPB * NV * UNIT_MAX * PMMF_WAVE * sizeof(float);
+  if (wpb != 1 && wpb != 2 && wpb != 4) return hipErrorInvalidValue;
+  const size_t lds = (size_t)wpb * NV * UNIT_MAX * PMMF_WAVE * sizeof(float);
   const int64_t nrhs = MODE == 0 ? fio.nrhs : rio.nrhs;
-  dim3 grid((st.nu + WPB - 1) / WPB, (unsigned)((nrhs + PMMF_WAVE - 1) / PMMF_WAVE));
-  k_unit_sweep<K, NV, MODE><<<grid, WPB * PMMF_WAVE, lds, s>>>(st, fio, rio);
+  dim3 grid((st.nu + wpb - 1) / wpb, (unsigned)((nrhs + PMMF_WAVE - 1) / PMMF_WAVE));
+  k_unit_sweep<K, NV, MODE><<<grid, wpb * PMMF_WAVE, lds, s>>>(st, fio, rio);
   return hipGetLastError();
 }
 
-hipError_t launch_unit_fwd(const UnitStage& st, const FwdIO& io, int nv, hipStream_t s) {
+hipError_t launch_unit_fwd(const UnitStage& st, const FwdIO& io, int nv, int wpb, hipStream_t s) {
   RevIO none{};
-  if (st.k == 2) return nv == 1 ? unit_launch<2, 1, 0>(st, io, none, s) : unit_launch<2, 2, 0>(st, io, none, s);
-  return nv == 1 ? unit_launch<3, 1, 0>(st, io, none, s) : unit_launch<3, 2, 0>(st, io, none, s);
+  if (st.k == 2)
+    return nv == 1 ? unit_launch<2, 1, 0>(st, io, none, wpb, s)
+                   : unit_launch<2, 2, 0>(st, io, none, wpb, s);
+  return nv == 1 ? unit_launch<3, 1, 0>(st, io, none, wpb, s)
+                 : unit_launch<3, 2, 0>(st, io, none, wpb, s);
 }
 
-hipError_t launch_unit_rev(const UnitStage& st, const RevIO& io, int nv, bool theta, hipStream_t s) {
+hipError_t launch_unit_rev(const UnitStage& st, const RevIO& io, int nv, bool theta, int wpb,
+                           hipStream_t s) {
   FwdIO none{};
   if (st.k == 2) {
-    if (theta) return unit_launch<2, 2, 2>(st, none, io, s);
-    return nv == 1 ? unit_launch<2, 1, 1>(st, none, io, s) : unit_launch<2, 2, 1>(st, none, io, s);
+    if (theta) return unit_launch<2, 2, 2>(st, none, io, wpb, s);
+    return nv == 1 ? unit_launch<2, 1, 1>(st, none, io, wpb, s)
+                   : unit_launch<2, 2, 1>(st, none, io, wpb, s);
   }
-  return nv == 1 ? unit_launch<3, 1, 1>(st, none, io, s) : unit_launch<3, 2, 1>(st, none, io, s);
+  return nv == 1 ? unit_launch<3, 1, 1>(st, none, io, wpb, s)
+                 : unit_launch<3, 2, 1>(st, none, io, wpb, s);
 }
 
 // core rows: compact buffer of the final active set -> natural rows of the core ids
