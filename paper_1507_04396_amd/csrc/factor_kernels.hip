@@ -453,6 +453,22 @@ __device__ inline void rot2(double a, double b, double d, double& c, double& s, 
 // then the row permutation and signs maximizing trace(O) with O_rr >= 0 (lexicographically
 // smallest permutation on ties).  Written with static indices only, so every array stays in
 // registers.
+// reciprocal and reciprocal square root: hardware estimates refined by two Newton steps each
+// (within an ulp or two; the rotation is converged to the same fixed point either way)
+__device__ inline double nr_rcp(double x) {
+  double y = __builtin_amdgcn_rcp(x);
+  double e = fma(-x, y, 1.0);
+  y = fma(y, e, y);
+  e = fma(-x, y, 1.0);
+  return fma(y, e, y);
+}
+__device__ inline double nr_rsq(double x) {
+  double y = __builtin_amdgcn_rsq(x);
+  const double h = 0.5 * x;
+  y = y * fma(-h * y, y, 1.5);
+  return y * fma(-h * y, y, 1.5);
+}
+
 __device__ inline void jacobi_pair(double (&A)[3][3], double (&V)[3][3], int p, int q, bool& rot) {
   const double apq = A[p][q];
   if (fabs(apq) <= 1e-18 * (fabs(A[p][p]) + fabs(A[q][q]))) {
@@ -460,10 +476,11 @@ __device__ inline void jacobi_pair(double (&A)[3][3], double (&V)[3][3], int p, 
     return;
   }
   rot = true;
-  const double tau = (A[q][q] - A[p][p]) / (2.0 * apq);
+  const double tau = (A[q][q] - A[p][p]) * nr_rcp(2.0 * apq);
   const double sg = tau >= 0.0 ? 1.0 : -1.0;
-  const double t = sg / (fabs(tau) + sqrt(1.0 + tau * tau));
-  const double c = 1.0 / sqrt(1.0 + t * t);
+  const double r1 = fma(tau, tau, 1.0);
+  const double t = sg * nr_rcp(fabs(tau) + r1 * nr_rsq(r1));
+  const double c = nr_rsq(fma(t, t, 1.0));
   const double s = t * c;
   // A <- J^T A J with J = [[c, s], [-s, c]] on (p, q); V <- V J
 #pragma unroll
