@@ -80,10 +80,18 @@ hipError_t launch_right(int S, int fill, const int64_t* rp, const int32_t* ci, c
                         const int32_t* qci, const float* qcv, int32_t* cnt, const int64_t* orp,
                         int32_t* oci, float* ocv, int cmax, hipStream_t s);
 hipError_t launch_left(int S, int fill, const int64_t* qrp, const int32_t* qci, const float* qcv,
-                       const int64_t* wrp, const int32_t* wci, const float* wcv,
+                       const int64_t* wrp, const int32_t* wcnt, const int32_t* wci,
+                       const float* wcv,
                        const int32_t* off, const int32_t* cl_of, const int32_t* next,
                        int32_t* cnt, const int64_t* orp, int32_t* oci, float* ocv,
                        double* loss_row, int32_t* overflow, int cmax, hipStream_t s);
+hipError_t launch_bound_right(int S, const int64_t* rp, const int32_t* ci, const int64_t* qrp,
+                              int64_t cap, int32_t* ub, hipStream_t s);
+hipError_t launch_bound_left(int S, const int64_t* qrp, const int32_t* qci, const int32_t* wcnt,
+                             const int32_t* next, int64_t cap, int32_t* ub, hipStream_t s);
+hipError_t launch_compact_rows(int64_t n, const int64_t* sb, const int32_t* cnt,
+                               const int32_t* sci, const float* scv, const int64_t* rp,
+                               int32_t* ci, float* cv, hipStream_t s);
 hipError_t launch_next_positions(int S, const uint8_t* retflag, const int64_t* scan,
                                  const int32_t* gid, int32_t* next, int32_t* gid_new,
                                  hipStream_t s);

@@ -1749,7 +1749,7 @@ __global__ void __launch_bounds__(256) k_right(int S, int fill, const int64_t* _
     }
     k = kend;
   }
-  if (!fill && lane == 0) cnt[x] = (int32_t)cur;
+  if (lane == 0) cnt[x] = (int32_t)(fill ? cur - orp[x] : cur);
 }
 
 hipError_t launch_right(int S, int fill, const int64_t* rp, const int32_t* ci, const float* cv,
@@ -1779,6 +1779,7 @@ __global__ void __launch_bounds__(256) k_left(int S, int fill, const int64_t* __
                                               const int32_t* __restrict__ qci,
                                               const float* __restrict__ qcv,
                                               const int64_t* __restrict__ wrp,
+                                              const int32_t* __restrict__ wcnt,
                                               const int32_t* __restrict__ wci,
                                               const float* __restrict__ wcv,
                                               const int32_t* __restrict__ off,
@@ -1808,7 +1809,7 @@ __global__ void __launch_bounds__(256) k_left(int S, int fill, const int64_t* __
   if (nq > LEFT_QMAX) {
     if (lane == 0) {
       atomicOr(overflow, 1);
-      if (!fill && next[a] >= 0) cnt[next[a]] = 0;
+      if (next[a] >= 0) cnt[next[a]] = 0;
       if (fill) loss_row[a] = 0.0;
     }
     return;
@@ -1816,7 +1817,7 @@ __global__ void __launch_bounds__(256) k_left(int S, int fill, const int64_t* __
   for (int j = lane; j < cmax; j += PMMF_WAVE) acc[j] = 0.f;
   for (int li = lane; li < nq; li += PMMF_WAVE) {
     const int x = qci[q0 + li];
-    const int64_t c0 = wrp[x], c1 = wrp[x + 1];
+    const int64_t c0 = wrp[x], c1 = wcnt ? c0 + wcnt[x] : wrp[x + 1];
     cur[li] = c0;
     en[li] = c1;
     qv[li] = qcv[q0 + li];
@@ -1944,11 +1945,78 @@ __global__ void __launch_bounds__(256) k_left(int S, int fill, const int64_t* __
   } else if (fill && lane == 0) {
     loss_row[a] = 0.0;
   }
-  if (!fill && lane == 0 && surv) cnt[na] = (int32_t)ocur;
+  if (lane == 0 && surv) cnt[na] = (int32_t)(fill ? ocur - orp[na] : ocur);
+}
+
+// Row capacities for writing a product straight into staging storage (no counting pass): a row
+// of W = M Qbar^T has at most sum_y nnz(Qbar^T_y) entries over its entries y, and a row of
+// A_p = Qbar W at most sum_x nnz(W_x) over the entries x of its Qbar row; both at most `cap`.
+__global__ void k_bound_right(int S, const int64_t* __restrict__ rp, const int32_t* __restrict__ ci,
+                              const int64_t* __restrict__ qrp, int64_t cap,
+                              int32_t* __restrict__ ub) {
+  const int x = blockIdx.x * (blockDim.x / PMMF_WAVE) + pmmf_wave();
+  if (x >= S) return;
+  int64_t acc = 0;
+  for (int64_t t = rp[x] + pmmf_lane(); t < rp[x + 1]; t += PMMF_WAVE) {
+    const int y = ci[t];
+    acc += qrp[y + 1] - qrp[y];
+  }
+  for (int o = PMMF_WAVE / 2; o > 0; o >>= 1) acc += __shfl_xor(acc, o);
+  if (pmmf_lane() == 0) ub[x] = (int32_t)min<int64_t>(acc, cap);
+}
+
+__global__ void k_bound_left(int S, const int64_t* __restrict__ qrp, const int32_t* __restrict__ qci,
+                             const int32_t* __restrict__ wcnt, const int32_t* __restrict__ next,
+                             int64_t cap, int32_t* __restrict__ ub) {
+  const int a = blockIdx.x * (blockDim.x / PMMF_WAVE) + pmmf_wave();
+  if (a >= S) return;
+  const int na = next[a];
+  if (na < 0) return;
+  int64_t acc = 0;
+  for (int64_t t = qrp[a] + pmmf_lane(); t < qrp[a + 1]; t += PMMF_WAVE) acc += wcnt[qci[t]];
+  for (int o = PMMF_WAVE / 2; o > 0; o >>= 1) acc += __shfl_xor(acc, o);
+  if (pmmf_lane() == 0) ub[na] = (int32_t)min<int64_t>(acc, cap);
+}
+
+// staging rows (start sb[r], cnt[r] entries) -> compact CSR rows at rp[r]
+__global__ void k_compact_rows(int64_t n, const int64_t* __restrict__ sb,
+                               const int32_t* __restrict__ cnt, const int32_t* __restrict__ sci,
+                               const float* __restrict__ scv, const int64_t* __restrict__ rp,
+                               int32_t* __restrict__ ci, float* __restrict__ cv) {
+  const int64_t r = (int64_t)blockIdx.x * (blockDim.x / PMMF_WAVE) + pmmf_wave();
+  if (r >= n) return;
+  const int64_t src = sb[r], dst = rp[r];
+  for (int t = pmmf_lane(); t < cnt[r]; t += PMMF_WAVE) {
+    ci[dst + t] = sci[src + t];
+    cv[dst + t] = scv[src + t];
+  }
+}
+
+hipError_t launch_bound_right(int S, const int64_t* rp, const int32_t* ci, const int64_t* qrp,
+                              int64_t cap, int32_t* ub, hipStream_t s) {
+  if (S == 0) return hipSuccess;
+  k_bound_right<<<(S + 3) / 4, 256, 0, s>>>(S, rp, ci, qrp, cap, ub);
+  return hipGetLastError();
+}
+
+hipError_t launch_bound_left(int S, const int64_t* qrp, const int32_t* qci, const int32_t* wcnt,
+                             const int32_t* next, int64_t cap, int32_t* ub, hipStream_t s) {
+  if (S == 0) return hipSuccess;
+  k_bound_left<<<(S + 3) / 4, 256, 0, s>>>(S, qrp, qci, wcnt, next, cap, ub);
+  return hipGetLastError();
+}
+
+hipError_t launch_compact_rows(int64_t n, const int64_t* sb, const int32_t* cnt,
+                               const int32_t* sci, const float* scv, const int64_t* rp,
+                               int32_t* ci, float* cv, hipStream_t s) {
+  if (n == 0) return hipSuccess;
+  k_compact_rows<<<(unsigned)((n + 3) / 4), 256, 0, s>>>(n, sb, cnt, sci, scv, rp, ci, cv);
+  return hipGetLastError();
 }
 
 hipError_t launch_left(int S, int fill, const int64_t* qrp, const int32_t* qci, const float* qcv,
-                       const int64_t* wrp, const int32_t* wci, const float* wcv,
+                       const int64_t* wrp, const int32_t* wcnt, const int32_t* wci,
+                       const float* wcv,
                        const int32_t* off, const int32_t* cl_of, const int32_t* next,
                        int32_t* cnt, const int64_t* orp, int32_t* oci, float* ocv,
                        double* loss_row, int32_t* overflow, int cmax, hipStream_t s) {
@@ -1962,7 +2030,7 @@ hipError_t launch_left(int S, int fill, const int64_t* qrp, const int32_t* qci, 
                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess) return e;
   }
-  k_left<<<(S + wpb - 1) / wpb, wpb * PMMF_WAVE, lds, s>>>(S, fill, qrp, qci, qcv, wrp, wci, wcv,
+  k_left<<<(S + wpb - 1) / wpb, wpb * PMMF_WAVE, lds, s>>>(S, fill, qrp, qci, qcv, wrp, wcnt, wci, wcv,
                                                            off, cl_of, next, cnt, orp, oci, ocv,
                                                            loss_row, overflow, cmax);
   return hipGetLastError();

@@ -553,6 +553,7 @@ extern "C" int mmf_factor(int64_t n, int64_t nnz, const int64_t* d_rowptr, const
   }
   DBuf GD, Q, retflag, keep, scan, cnt, loss_row, overflow, gid_cur, tbase, dense_buf;
   DBuf bf_bm, bf_pre, bf_R, bf_off, bf_slab, bf_slab16, bf_stats;  // BF16 form only
+  DBuf wstart, wcnt, abase, stage_ci, stage_cv;  // staging rows of the two products
   if (p->gram_mode == 1) bf_stats.ensure(2 * sizeof(unsigned long long));
   GD.ensure(pool * sizeof(float2));
   Q.ensure(pool * sizeof(float));
@@ -718,44 +719,53 @@ extern "C" int mmf_factor(int64_t n, int64_t nnz, const int64_t* d_rowptr, const
                                     sd.gbase.as<int64_t>(), pool_src, Z.rp.as<int64_t>(),
                                     Z.ci.as<int32_t>(), Z.cv.as<float>(), s));
     }
-    // W = M Qbar^T
+    // W = M Qbar^T, written once into staging rows sized by a capacity bound (row x of W keeps
+    // its entries at [wstart[x], wstart[x] + wcnt[x]); k_left reads it in that form)
+    HIPCHK(pmmf::launch_bound_right(S, M.rp.as<int64_t>(), M.ci.as<int32_t>(), Qt.rp.as<int64_t>(),
+                                    S, cnt.as<int32_t>(), s));
+    wstart.ensure((S + 1) * sizeof(int64_t));
+    HIPCHK(pmmf::launch_scan(cnt.as<int32_t>(), wstart.as<int64_t>(), S, scan_tmp.as<int64_t>(), s));
+    const int64_t wcap = read_i64(wstart.as<int64_t>() + S, s);
     W.n = S;
-    W.rp.ensure((S + 1) * sizeof(int64_t));
-    HIPCHK(pmmf::launch_right(S, 0, M.rp.as<int64_t>(), M.ci.as<int32_t>(), M.cv.as<float>(),
-                              sd.off.as<int32_t>(), sd.cl_of.as<int32_t>(), Qt.rp.as<int64_t>(),
-                              Qt.ci.as<int32_t>(), Qt.cv.as<float>(), cnt.as<int32_t>(), nullptr,
-                              nullptr, nullptr, cm, s));
-    HIPCHK(pmmf::launch_scan(cnt.as<int32_t>(), W.rp.as<int64_t>(), S, scan_tmp.as<int64_t>(), s));
-    W.nnz = read_i64(W.rp.as<int64_t>() + S, s);
-    W.ci.ensure(std::max<int64_t>(W.nnz, 1) * sizeof(int32_t));
-    W.cv.ensure(std::max<int64_t>(W.nnz, 1) * sizeof(float));
+    W.ci.ensure(std::max<int64_t>(wcap, 1) * sizeof(int32_t));
+    W.cv.ensure(std::max<int64_t>(wcap, 1) * sizeof(float));
+    wcnt.ensure(S * sizeof(int32_t));
     HIPCHK(pmmf::launch_right(S, 1, M.rp.as<int64_t>(), M.ci.as<int32_t>(), M.cv.as<float>(),
                               sd.off.as<int32_t>(), sd.cl_of.as<int32_t>(), Qt.rp.as<int64_t>(),
-                              Qt.ci.as<int32_t>(), Qt.cv.as<float>(), nullptr, W.rp.as<int64_t>(),
-                              W.ci.as<int32_t>(), W.cv.as<float>(), cm, s));
-    // A_p = Qbar W, peeled to the survivors, plus the exact residual of the retired rows
-    M2.n = Snext;
-    M2.rp.ensure((Snext + 1) * sizeof(int64_t));
-    HIPCHK(pmmf::launch_left(S, 0, Qr.rp.as<int64_t>(), Qr.ci.as<int32_t>(), Qr.cv.as<float>(),
-                             W.rp.as<int64_t>(), W.ci.as<int32_t>(), W.cv.as<float>(),
-                             sd.off.as<int32_t>(), sd.cl_of.as<int32_t>(), sd.next.as<int32_t>(),
-                             cnt.as<int32_t>(), nullptr, nullptr, nullptr, nullptr,
+                              Qt.ci.as<int32_t>(), Qt.cv.as<float>(), wcnt.as<int32_t>(),
+                              wstart.as<int64_t>(), W.ci.as<int32_t>(), W.cv.as<float>(), cm, s));
+    // A_p = Qbar W, peeled to the survivors, plus the exact residual of the retired rows: written
+    // into staging rows, then compacted into the next stage's CSR
+    HIPCHK(pmmf::launch_bound_left(S, Qr.rp.as<int64_t>(), Qr.ci.as<int32_t>(), wcnt.as<int32_t>(),
+                                   sd.next.as<int32_t>(), Snext, cnt.as<int32_t>(), s));
+    abase.ensure((Snext + 1) * sizeof(int64_t));
+    HIPCHK(pmmf::launch_scan(cnt.as<int32_t>(), abase.as<int64_t>(), Snext, scan_tmp.as<int64_t>(), s));
+    const int64_t acap = read_i64(abase.as<int64_t>() + Snext, s);
+    stage_ci.ensure(std::max<int64_t>(acap, 1) * sizeof(int32_t));
+    stage_cv.ensure(std::max<int64_t>(acap, 1) * sizeof(float));
+    HIPCHK(pmmf::launch_left(S, 1, Qr.rp.as<int64_t>(), Qr.ci.as<int32_t>(), Qr.cv.as<float>(),
+                             wstart.as<int64_t>(), wcnt.as<int32_t>(), W.ci.as<int32_t>(),
+                             W.cv.as<float>(), sd.off.as<int32_t>(), sd.cl_of.as<int32_t>(),
+                             sd.next.as<int32_t>(), cnt.as<int32_t>(), abase.as<int64_t>(),
+                             stage_ci.as<int32_t>(), stage_cv.as<float>(), loss_row.as<double>(),
                              overflow.as<int32_t>(), cm, s));
-    HIPCHK(pmmf::launch_scan(cnt.as<int32_t>(), M2.rp.as<int64_t>(), Snext, scan_tmp.as<int64_t>(), s));
-    M2.nnz = read_i64(M2.rp.as<int64_t>() + Snext, s);
     {
       int32_t fl2[2] = {0, 0};
-      HIPCHK(hipMemcpy(fl2, overflow.p, 2 * sizeof(int32_t), hipMemcpyDeviceToHost));
+      HIPCHK(hipMemcpyAsync(fl2, overflow.p, 2 * sizeof(int32_t), hipMemcpyDeviceToHost, s));
+      HIPCHK(hipStreamSynchronize(s));
       if (fl2[1]) raise(MMF_EDEVICE, "greedy search found no partner in a cluster");
       if (fl2[0]) raise(MMF_ECAPACITY, "a row of Qbar has more than 512 entries");
     }
+    M2.n = Snext;
+    M2.rp.ensure((Snext + 1) * sizeof(int64_t));
+    HIPCHK(pmmf::launch_scan(cnt.as<int32_t>(), M2.rp.as<int64_t>(), Snext, scan_tmp.as<int64_t>(), s));
+    M2.nnz = read_i64(M2.rp.as<int64_t>() + Snext, s);
     M2.ci.ensure(std::max<int64_t>(M2.nnz, 1) * sizeof(int32_t));
     M2.cv.ensure(std::max<int64_t>(M2.nnz, 1) * sizeof(float));
-    HIPCHK(pmmf::launch_left(S, 1, Qr.rp.as<int64_t>(), Qr.ci.as<int32_t>(), Qr.cv.as<float>(),
-                             W.rp.as<int64_t>(), W.ci.as<int32_t>(), W.cv.as<float>(),
-                             sd.off.as<int32_t>(), sd.cl_of.as<int32_t>(), sd.next.as<int32_t>(),
-                             nullptr, M2.rp.as<int64_t>(), M2.ci.as<int32_t>(), M2.cv.as<float>(),
-                             loss_row.as<double>(), overflow.as<int32_t>(), cm, s));
+    HIPCHK(pmmf::launch_compact_rows(Snext, abase.as<int64_t>(), cnt.as<int32_t>(),
+                                     stage_ci.as<int32_t>(), stage_cv.as<float>(),
+                                     M2.rp.as<int64_t>(), M2.ci.as<int32_t>(), M2.cv.as<float>(),
+                                     s));
     HIPCHK(hipEventRecord(pev.e[3], s));
     HIPCHK(pmmf::launch_sum_double(loss_row.as<double>(), S, stage_loss.as<double>() + pi, s));
     HIPCHK(hipEventSynchronize(pev.e[3]));
