@@ -19,7 +19,6 @@ struct FindArgs {
   const int32_t* roff;       // [m+1] first stage-local rotation of each cluster
   const int64_t* gbase;      // [m] offset of each cluster's c x c blocks in the pools
   float2* GD;                // (Gram, diagonal block) pool, interleaved
-  float* Q;                  // accumulated-rotation pool
   const int32_t* gid;        // [S] global id of each position
   int64_t rot0;              // global index of the stage's first rotation
   int32_t* rot_loc;          // [R][3] cluster-local ids, slot order
@@ -46,10 +45,10 @@ namespace pmmf {
 hipError_t launch_fill_cluster_of(const int32_t* off, int m, int S, int32_t* cl_of, hipStream_t s);
 hipError_t launch_gram(int S, const int64_t* rp, const int32_t* ci, const float* cv,
                        const int32_t* off, const int32_t* cl_of, const int64_t* gbase,
-                       float2* GD, float* Q, int cmax, hipStream_t s);
+                       float2* GD, int cmax, hipStream_t s);
 hipError_t launch_gram_dense(int S, const int64_t* rp, const int32_t* ci, const float* cv,
                              float* dense, const int32_t* off, int m, const int64_t* gbase,
-                             float2* GD, float* Q, int cmax, hipStream_t s);
+                             float2* GD, int cmax, hipStream_t s);
 hipError_t launch_find(const FindArgs& a, int m, int cmax, int nt, hipStream_t s);
 hipError_t launch_find_bf16(const FindArgs& a, int m, int cmax, hipStream_t s);
 hipError_t launch_slab_rows(int S, int m, const int64_t* rp, const int32_t* ci,
@@ -59,7 +58,7 @@ hipError_t launch_gram_bf16(int S, int m, const int64_t* rp, const int32_t* ci, 
                             const int32_t* off, const int32_t* cl_of, int64_t W,
                             const uint32_t* bm, const int32_t* pre, const int64_t* slab_off,
                             const int32_t* R, int64_t slab_elems, float* slab,
-                            unsigned short* slab_bf, const int64_t* gbase, float2* GD, float* Q,
+                            unsigned short* slab_bf, const int64_t* gbase, float2* GD,
                             int cmax, hipStream_t s);
 size_t find_lds_bytes(int cmax);
 hipError_t launch_levelize(int m, int k, const int32_t* off, const int32_t* rcnt,
@@ -67,6 +66,10 @@ hipError_t launch_levelize(int m, int k, const int32_t* off, const int32_t* rcnt
                            const float* rot_o, int lvl_stride, int32_t* lvl_ptr, int32_t* depth,
                            int32_t* sw_loc, float* sw_o, int32_t* sw_idx, float* theta, int cmax,
                            hipStream_t s);
+hipError_t launch_build_q(int m, int k, const int32_t* off, const int64_t* gbase,
+                          const int32_t* lvl_ptr, int lvl_stride, const int32_t* depth,
+                          const int32_t* sw_loc, const float* sw_o, float* Q, int cmax,
+                          hipStream_t s);
 hipError_t launch_transpose_blocks(int m, const int32_t* off, const int64_t* gbase,
                                    const int64_t* tbase, int64_t ntiles, const float* src,
                                    float* dst, hipStream_t s);

@@ -47,8 +47,7 @@ __global__ void __launch_bounds__(256) k_gram(int S, const int64_t* __restrict__
                                               const int32_t* __restrict__ off,
                                               const int32_t* __restrict__ cl_of,
                                               const int64_t* __restrict__ gbase,
-                                              float2* __restrict__ GD, float* __restrict__ Q,
-                                              int cmax) {
+                                              float2* __restrict__ GD, int cmax) {
   extern __shared__ float lds_f[];
   const int wpb = blockDim.x / PMMF_WAVE;
   const int w = pmmf_wave(), lane = pmmf_lane();
@@ -119,7 +118,6 @@ __global__ void __launch_bounds__(256) k_gram(int S, const int64_t* __restrict__
   for (int j = lane; j < c; j += PMMF_WAVE) {
     gd[2 * j] = acc[j];
     acc[j] = 0.f;
-    Q[base + j] = (j == la) ? 1.f : 0.f;
   }
   const int64_t lb = lower_bound_i32(ci, a0, a1, o);
   const int64_t ub = lower_bound_i32(ci, lb, a1, o + c);
@@ -148,8 +146,7 @@ constexpr int DG_T = 32, DG_K = 128, DG_PER = DG_T * DG_K / 256;
 __global__ void __launch_bounds__(256) k_gram_dense(int S, const float* __restrict__ dense,
                                                     const int32_t* __restrict__ off,
                                                     const int64_t* __restrict__ gbase,
-                                                    float2* __restrict__ GD, float* __restrict__ Q,
-                                                    int ntmax) {
+                                                    float2* __restrict__ GD, int ntmax) {
   __shared__ float As[DG_T][DG_K + 1];
   __shared__ float Bs[DG_K][DG_T + 1];
   const int u = blockIdx.y;
@@ -203,25 +200,22 @@ __global__ void __launch_bounds__(256) k_gram_dense(int S, const float* __restri
     const int j = tj * DG_T + wn + (lane & 15);
     if (i < c && j < c) {
       GD[base + (size_t)i * c + j] = make_float2(acc[r], dense[(size_t)(o + i) * S + o + j]);
-      Q[base + (size_t)i * c + j] = i == j ? 1.f : 0.f;
-      if (ti != tj) {
+      if (ti != tj)
         GD[base + (size_t)j * c + i] = make_float2(acc[r], dense[(size_t)(o + j) * S + o + i]);
-        Q[base + (size_t)j * c + i] = 0.f;
-      }
     }
   }
 }
 
 hipError_t launch_gram_dense(int S, const int64_t* rp, const int32_t* ci, const float* cv,
                              float* dense, const int32_t* off, int m, const int64_t* gbase,
-                             float2* GD, float* Q, int cmax, hipStream_t s) {
+                             float2* GD, int cmax, hipStream_t s) {
   if (S == 0) return hipSuccess;
   hipError_t e = hipMemsetAsync(dense, 0, (size_t)S * S * sizeof(float), s);
   if (e != hipSuccess) return e;
   k_densify<<<(S + 3) / 4, 256, 0, s>>>(S, rp, ci, cv, dense);
   const int ntmax = (cmax + DG_T - 1) / DG_T;
   dim3 grid((unsigned)(ntmax * (ntmax + 1) / 2), (unsigned)m);
-  k_gram_dense<<<grid, 256, 0, s>>>(S, dense, off, gbase, GD, Q, ntmax);
+  k_gram_dense<<<grid, 256, 0, s>>>(S, dense, off, gbase, GD, ntmax);
   return hipGetLastError();
 }
 
@@ -307,8 +301,7 @@ __global__ void __launch_bounds__(256) k_gram_bf16(const unsigned short* __restr
                                                    const int64_t* __restrict__ gbase,
                                                    const int64_t* __restrict__ slab_off,
                                                    const int32_t* __restrict__ R,
-                                                   float2* __restrict__ GD, float* __restrict__ Q,
-                                                   int ntmax) {
+                                                   float2* __restrict__ GD, int ntmax) {
   __shared__ unsigned short As[BG_T][BG_K + 4];
   __shared__ unsigned short Bs[BG_T][BG_K + 4];
   const int u = blockIdx.y;
@@ -355,11 +348,7 @@ __global__ void __launch_bounds__(256) k_gram_bf16(const unsigned short* __restr
     const int j = tj * BG_T + wn + (lane & 15);
     if (i < c && j < c) {
       GD[base + (size_t)i * c + j] = make_float2(acc[r], 0.f);
-      Q[base + (size_t)i * c + j] = i == j ? 1.f : 0.f;
-      if (ti != tj) {
-        GD[base + (size_t)j * c + i] = make_float2(acc[r], 0.f);
-        Q[base + (size_t)j * c + i] = 0.f;
-      }
+      if (ti != tj) GD[base + (size_t)j * c + i] = make_float2(acc[r], 0.f);
     }
   }
 }
@@ -404,7 +393,7 @@ hipError_t launch_gram_bf16(int S, int m, const int64_t* rp, const int32_t* ci, 
                             const int32_t* off, const int32_t* cl_of, int64_t W,
                             const uint32_t* bm, const int32_t* pre, const int64_t* slab_off,
                             const int32_t* R, int64_t slab_elems, float* slab,
-                            unsigned short* slab_bf, const int64_t* gbase, float2* GD, float* Q,
+                            unsigned short* slab_bf, const int64_t* gbase, float2* GD,
                             int cmax, hipStream_t s) {
   if (S == 0) return hipSuccess;
   hipError_t e = hipMemsetAsync(slab, 0, (size_t)slab_elems * sizeof(float), s);
@@ -414,20 +403,20 @@ hipError_t launch_gram_bf16(int S, int m, const int64_t* rp, const int32_t* ci, 
                                           slab_bf);
   const int ntmax = (cmax + BG_T - 1) / BG_T;
   dim3 grid((unsigned)(ntmax * (ntmax + 1) / 2), (unsigned)m);
-  k_gram_bf16<<<grid, 256, 0, s>>>(slab_bf, off, gbase, slab_off, R, GD, Q, ntmax);
+  k_gram_bf16<<<grid, 256, 0, s>>>(slab_bf, off, gbase, slab_off, R, GD, ntmax);
   k_slab_finish<<<(S + 3) / 4, 256, 0, s>>>(S, rp, ci, cv, off, cl_of, gbase, slab_off, R, slab, GD);
   return hipGetLastError();
 }
 
 hipError_t launch_gram(int S, const int64_t* rp, const int32_t* ci, const float* cv,
                        const int32_t* off, const int32_t* cl_of, const int64_t* gbase,
-                       float2* GD, float* Q, int cmax, hipStream_t s) {
+                       float2* GD, int cmax, hipStream_t s) {
   if (S == 0) return hipSuccess;
   int wpb = 4;
   while (wpb > 1 && (size_t)wpb * cmax * 4 > 64 * 1024) wpb >>= 1;
   const size_t lds = (size_t)wpb * cmax * sizeof(float);
   k_gram<<<(S + wpb - 1) / wpb, wpb * PMMF_WAVE, lds, s>>>(S, rp, ci, cv, off, cl_of, gbase, GD,
-                                                           Q, cmax);
+                                                           cmax);
   return hipGetLastError();
 }
 
@@ -651,8 +640,9 @@ __device__ inline float2 rot_entry(const float* o, int a, const float2* v) {
   return make_float2(sg, sd);
 }
 
-// The cluster's state lives in HBM as dense c x c arrays: GD (Gram and diagonal block of the
-// active matrix, interleaved so one 8-byte access moves both) and Q (accumulated rotation).
+// The cluster's state lives in HBM as a dense c x c array GD (Gram and diagonal block of the
+// active matrix, interleaved so one 8-byte access moves both); the accumulated rotation Qbar is
+// rebuilt from the log afterwards (k_build_q).
 // Each thread owns the columns j = tid + q NT (q < PER) and keeps its slice of the rows it needs
 // in registers.  A step has two barriers:
 //   A  after the partner argmax;
@@ -689,7 +679,6 @@ __global__ void __launch_bounds__(NT) k_find(FindArgs A, int cmax) {
   const int nw = (c + 31) / 32;
   constexpr int kk = K;
   float2* __restrict__ GD = A.GD + A.gbase[u];
-  float* __restrict__ Q = A.Q + A.gbase[u];
   float2* R1 = rowbuf + 2 * (size_t)cmax;
   float2* R2 = rowbuf + 3 * (size_t)cmax;
 
@@ -772,20 +761,13 @@ __global__ void __launch_bounds__(NT) k_find(FindArgs A, int cmax) {
       x21 = GD[(size_t)t2 * c + t1];
     }
     float2 p1[PER], p2[PER];
-    float q0[PER], q1[PER], q2[PER];
 #pragma unroll
     for (int q = 0; q < PER; ++q) {
       const int j = tid + q * NT;
       p1[q] = p2[q] = make_float2(0.f, 0.f);
-      q0[q] = q1[q] = q2[q] = 0.f;
       if (j < c) {
         p1[q] = GD[(size_t)t1 * c + j];
-        q0[q] = Q[(size_t)t0 * c + j];
-        q1[q] = Q[(size_t)t1 * c + j];
-        if (kk == 3) {
-          p2[q] = GD[(size_t)t2 * c + j];
-          q2[q] = Q[(size_t)t2 * c + j];
-        }
+        if (kk == 3) p2[q] = GD[(size_t)t2 * c + j];
       }
     }
 
@@ -934,7 +916,7 @@ __global__ void __launch_bounds__(NT) k_find(FindArgs A, int cmax) {
     if (tid == 0) mask[e >> 5] &= ~(1u << (e & 31));
 
     // stores: GD <- O GD O^T on rows/columns T (active columns only: retired columns are never
-    // read again); Q <- O Q on rows T (all columns)
+    // read again)
     const int Tt[3] = {t0, t1, t2};
     if (tid < kk * kk) {
       const int a = tid / kk, b = tid % kk;
@@ -944,14 +926,6 @@ __global__ void __launch_bounds__(NT) k_find(FindArgs A, int cmax) {
     for (int q = 0; q < PER; ++q) {
       const int j = tid + q * NT;
       if (j >= c) continue;
-      if (kk == 2) {
-        Q[(size_t)t0 * c + j] = o_[0] * q0[q] + o_[1] * q1[q];
-        Q[(size_t)t1 * c + j] = o_[3] * q0[q] + o_[4] * q1[q];
-      } else {
-        Q[(size_t)t0 * c + j] = o_[0] * q0[q] + o_[1] * q1[q] + o_[2] * q2[q];
-        Q[(size_t)t1 * c + j] = o_[3] * q0[q] + o_[4] * q1[q] + o_[5] * q2[q];
-        Q[(size_t)t2 * c + j] = o_[6] * q0[q] + o_[7] * q1[q] + o_[8] * q2[q];
-      }
       const int bj = j == t0 ? 0 : (j == t1 ? 1 : ((kk == 3 && j == t2) ? 2 : -1));
       if (bj >= 0) {
         // column j is in T: the next seed row's entry there
@@ -1055,7 +1029,6 @@ __global__ void __launch_bounds__(256) k_find_bf16(FindArgs A, int cmax) {
   const int nw = (c + 31) / 32;
   constexpr int kk = K;
   float2* __restrict__ GD = A.GD + A.gbase[u];
-  float* __restrict__ Q = A.Q + A.gbase[u];
   const int Ru = A.slab_rows[u];
   float* __restrict__ SL = A.slab + A.slab_off[u];
   float2* R1 = rowbuf + 2 * (size_t)cmax;
@@ -1212,22 +1185,15 @@ __global__ void __launch_bounds__(256) k_find_bf16(FindArgs A, int cmax) {
       n_scored += total;
     }
     const int t0 = i, t1 = x1.j, t2 = kk == 3 ? x2.j : -1;
-    // partner rows of G~ and D, and rows T of Q
+    // partner rows of G~ and D
     float2 p1[PER], p2[PER];
-    float q0[PER], q1[PER], q2[PER];
 #pragma unroll
     for (int q = 0; q < PER; ++q) {
       const int j = tid + q * NT;
       p1[q] = p2[q] = make_float2(0.f, 0.f);
-      q0[q] = q1[q] = q2[q] = 0.f;
       if (j < c) {
         p1[q] = GD[(size_t)t1 * c + j];
-        q0[q] = Q[(size_t)t0 * c + j];
-        q1[q] = Q[(size_t)t1 * c + j];
-        if (kk == 3) {
-          p2[q] = GD[(size_t)t2 * c + j];
-          q2[q] = Q[(size_t)t2 * c + j];
-        }
+        if (kk == 3) p2[q] = GD[(size_t)t2 * c + j];
       }
     }
     float g12 = 0.f;
@@ -1384,14 +1350,6 @@ __global__ void __launch_bounds__(256) k_find_bf16(FindArgs A, int cmax) {
     for (int q = 0; q < PER; ++q) {
       const int j = tid + q * NT;
       if (j >= c) continue;
-      if (kk == 2) {
-        Q[(size_t)t0 * c + j] = o_[0] * q0[q] + o_[1] * q1[q];
-        Q[(size_t)t1 * c + j] = o_[3] * q0[q] + o_[4] * q1[q];
-      } else {
-        Q[(size_t)t0 * c + j] = o_[0] * q0[q] + o_[1] * q1[q] + o_[2] * q2[q];
-        Q[(size_t)t1 * c + j] = o_[3] * q0[q] + o_[4] * q1[q] + o_[5] * q2[q];
-        Q[(size_t)t2 * c + j] = o_[6] * q0[q] + o_[7] * q1[q] + o_[8] * q2[q];
-      }
       const int bj = j == t0 ? 0 : (j == t1 ? 1 : ((kk == 3 && j == t2) ? 2 : -1));
       if (bj >= 0) {
         if (more) {
@@ -1474,6 +1432,87 @@ hipError_t launch_find(const FindArgs& a, int m, int cmax, int nt, hipStream_t s
     if (cmax <= 3072) return find_launch_k<256, 12>(a, m, cmax, lds, s);
   }
   return hipErrorInvalidValue;
+}
+
+// ------------------------------------------------------------------------------------------
+// Dense accumulated rotation of each cluster, Qbar_u = O_r ... O_1 (row-major c x c in the pool),
+// rebuilt from the stage's sweep log: one workgroup per (cluster, 8-column slice) holds the slice
+// of the identity in LDS and applies the rotations level by level (a level's rotations touch
+// disjoint rows); x[T] <- O x[T] on each column of the slice.
+constexpr int BQ_W = 8;
+template <int K>
+__global__ void __launch_bounds__(256) k_build_q(const int32_t* __restrict__ off,
+                                                 const int64_t* __restrict__ gbase,
+                                                 const int32_t* __restrict__ lvl_ptr,
+                                                 int lvl_stride, const int32_t* __restrict__ depth,
+                                                 const int32_t* __restrict__ sw_loc,
+                                                 const float* __restrict__ sw_o,
+                                                 float* __restrict__ Q) {
+  extern __shared__ float tile[];  // [c][BQ_W]
+  const int u = blockIdx.y;
+  const int c = off[u + 1] - off[u];
+  const int col0 = blockIdx.x * BQ_W;
+  if (col0 >= c) return;
+  const int tid = threadIdx.x;
+  for (int q = tid; q < c * BQ_W; q += blockDim.x) {
+    const int row = q / BQ_W, w = q % BQ_W;
+    tile[q] = row == col0 + w ? 1.f : 0.f;
+  }
+  __syncthreads();
+  const int* lp = lvl_ptr + (size_t)u * lvl_stride;
+  const int dep = depth[u];
+  for (int l = 0; l < dep; ++l) {
+    const int r0 = lp[l], r1 = lp[l + 1];
+    for (int q = tid; q < (r1 - r0) * BQ_W; q += blockDim.x) {
+      const int rr = r0 + q / BQ_W, w = q % BQ_W;
+      int id[K];
+      float x[K];
+#pragma unroll
+      for (int a = 0; a < K; ++a) {
+        id[a] = sw_loc[(size_t)rr * K + a];
+        x[a] = tile[id[a] * BQ_W + w];
+      }
+      const float* o = sw_o + (size_t)rr * K * K;
+#pragma unroll
+      for (int a = 0; a < K; ++a) {
+        float acc = 0.f;
+#pragma unroll
+        for (int b = 0; b < K; ++b) acc = fmaf(o[a * K + b], x[b], acc);
+        tile[id[a] * BQ_W + w] = acc;
+      }
+    }
+    __syncthreads();
+  }
+  float* Qu = Q + gbase[u];
+  for (int q = tid; q < c * BQ_W; q += blockDim.x) {
+    const int row = q / BQ_W, w = q % BQ_W;
+    if (col0 + w < c) Qu[(size_t)row * c + col0 + w] = tile[q];
+  }
+}
+
+hipError_t launch_build_q(int m, int k, const int32_t* off, const int64_t* gbase,
+                          const int32_t* lvl_ptr, int lvl_stride, const int32_t* depth,
+                          const int32_t* sw_loc, const float* sw_o, float* Q, int cmax,
+                          hipStream_t s) {
+  if (m == 0) return hipSuccess;
+  const size_t lds = (size_t)cmax * BQ_W * sizeof(float);
+  dim3 grid((unsigned)((cmax + BQ_W - 1) / BQ_W), (unsigned)m);
+  if (k == 3) {
+    if (lds > 64 * 1024) {
+      hipError_t e = hipFuncSetAttribute((const void*)&k_build_q<3>,
+                                         hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+      if (e != hipSuccess) return e;
+    }
+    k_build_q<3><<<grid, 256, lds, s>>>(off, gbase, lvl_ptr, lvl_stride, depth, sw_loc, sw_o, Q);
+  } else {
+    if (lds > 64 * 1024) {
+      hipError_t e = hipFuncSetAttribute((const void*)&k_build_q<2>,
+                                         hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+      if (e != hipSuccess) return e;
+    }
+    k_build_q<2><<<grid, 256, lds, s>>>(off, gbase, lvl_ptr, lvl_stride, depth, sw_loc, sw_o, Q);
+  }
+  return hipGetLastError();
 }
 
 // ------------------------------------------------------------------------------------------

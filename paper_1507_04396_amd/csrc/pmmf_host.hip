@@ -619,17 +619,16 @@ extern "C" int mmf_factor(int64_t n, int64_t nnz, const int64_t* d_rowptr, const
                                     bf_pre.as<int32_t>(), bf_off.as<int64_t>(),
                                     bf_R.as<int32_t>(), soff[sd.m], bf_slab.as<float>(),
                                     bf_slab16.as<unsigned short>(), sd.gbase.as<int64_t>(),
-                                    GD.as<float2>(), Q.as<float>(), sd.cmax, s));
+                                    GD.as<float2>(), sd.cmax, s));
     } else if (dense_gram) {
       dense_buf.ensure((size_t)S * S * sizeof(float));
       HIPCHK(pmmf::launch_gram_dense(S, M.rp.as<int64_t>(), M.ci.as<int32_t>(), M.cv.as<float>(),
                                      dense_buf.as<float>(), sd.off.as<int32_t>(), sd.m,
-                                     sd.gbase.as<int64_t>(), GD.as<float2>(), Q.as<float>(),
-                                     sd.cmax, s));
+                                     sd.gbase.as<int64_t>(), GD.as<float2>(), sd.cmax, s));
     } else {
       HIPCHK(pmmf::launch_gram(S, M.rp.as<int64_t>(), M.ci.as<int32_t>(), M.cv.as<float>(),
                                sd.off.as<int32_t>(), sd.cl_of.as<int32_t>(),
-                               sd.gbase.as<int64_t>(), GD.as<float2>(), Q.as<float>(), cm, s));
+                               sd.gbase.as<int64_t>(), GD.as<float2>(), cm, s));
     }
     // greedy rotation search in every cluster
     pmmf::FindArgs fa;
@@ -642,7 +641,6 @@ extern "C" int mmf_factor(int64_t n, int64_t nnz, const int64_t* d_rowptr, const
     fa.roff = sd.roff.as<int32_t>();
     fa.gbase = sd.gbase.as<int64_t>();
     fa.GD = GD.as<float2>();
-    fa.Q = Q.as<float>();
     fa.gid = sd.gid.as<int32_t>();
     fa.rot0 = rot_base;
     fa.rot_loc = h->rot_loc.as<int32_t>();
@@ -680,6 +678,11 @@ extern "C" int mmf_factor(int64_t n, int64_t nnz, const int64_t* d_rowptr, const
                                  sd.depth.as<int32_t>(), sd.sw_loc.as<int32_t>(),
                                  sd.sw_o.as<float>(), sd.sw_idx.as<int32_t>(),
                                  h->theta.as<float>(), cm, s));
+    // the clusters' accumulated rotations, rebuilt from the sweep log
+    HIPCHK(pmmf::launch_build_q(sd.m, h->k, sd.off.as<int32_t>(), sd.gbase.as<int64_t>(),
+                                sd.lvl_ptr.as<int32_t>(), sd.lvl_stride, sd.depth.as<int32_t>(),
+                                sd.sw_loc.as<int32_t>(), sd.sw_o.as<float>(), Q.as<float>(),
+                                sd.cmax, s));
     // survivors' positions in the next stage
     HIPCHK(pmmf::launch_keep_flags(S, retflag.as<uint8_t>(), keep.as<int32_t>(), s));
     HIPCHK(pmmf::launch_scan(keep.as<int32_t>(), scan.as<int64_t>(), S, scan_tmp.as<int64_t>(), s));
