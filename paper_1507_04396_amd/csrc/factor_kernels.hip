@@ -41,12 +41,55 @@ __device__ inline int64_t lower_bound_i32(const int32_t* __restrict__ a, int64_t
 // i.e. the inner products of column a with the cluster's columns over all active rows r (M is
 // symmetric, so column a's entries are row a's).  The row is accumulated in LDS in ascending r
 // (deterministic) and written densely, which also clears the previous stage's contents.
+// Run table of the active matrix: for every row, the maximal runs of columns in one cluster
+// (clusters are contiguous position ranges and columns ascend, so a row meets each cluster in at
+// most one run), as (cluster, first entry) pairs in ascending cluster order.
+__global__ void k_runs(int S, int fill, const int64_t* __restrict__ rp,
+                       const int32_t* __restrict__ ci, const int32_t* __restrict__ cl_of,
+                       int32_t* __restrict__ nruns, const int64_t* __restrict__ run_ptr,
+                       int32_t* __restrict__ run_cl, int64_t* __restrict__ run_start) {
+  const int r = blockIdx.x * (blockDim.x / PMMF_WAVE) + pmmf_wave();
+  if (r >= S) return;
+  const int lane = pmmf_lane();
+  const int64_t r0 = rp[r], r1 = rp[r + 1];
+  int64_t out = fill ? run_ptr[r] : 0;
+  int prev = -1;  // cluster of the entry before the current chunk
+  for (int64_t t0 = r0; t0 < r1; t0 += PMMF_WAVE) {
+    const int64_t t = t0 + lane;
+    const int cl = t < r1 ? cl_of[ci[t]] : INT_MAX;
+    int left = __shfl_up(cl, 1);
+    if (lane == 0) left = prev;
+    const bool head = t < r1 && cl != left;
+    const uint64_t b = __ballot(head);
+    if (fill && head) {
+      const int64_t pos = out + pmmf_lanes_below(b);
+      run_cl[pos] = cl;
+      run_start[pos] = t;
+    }
+    out += __popcll(b);
+    prev = __shfl(cl, PMMF_WAVE - 1);
+  }
+  if (!fill && lane == 0) nruns[r] = (int32_t)out;
+}
+
+hipError_t launch_runs(int S, int fill, const int64_t* rp, const int32_t* ci,
+                       const int32_t* cl_of, int32_t* nruns, const int64_t* run_ptr,
+                       int32_t* run_cl, int64_t* run_start, hipStream_t s) {
+  if (S == 0) return hipSuccess;
+  k_runs<<<(S + 3) / 4, 256, 0, s>>>(S, fill, rp, ci, cl_of, nruns, run_ptr, run_cl, run_start);
+  return hipGetLastError();
+}
+
+constexpr int GRAM_SEGS = 8;  // segments whose first chunks are requested together
 __global__ void __launch_bounds__(256) k_gram(int S, const int64_t* __restrict__ rp,
                                               const int32_t* __restrict__ ci,
                                               const float* __restrict__ cv,
                                               const int32_t* __restrict__ off,
                                               const int32_t* __restrict__ cl_of,
                                               const int64_t* __restrict__ gbase,
+                                              const int64_t* __restrict__ run_ptr,
+                                              const int32_t* __restrict__ run_cl,
+                                              const int64_t* __restrict__ run_start,
                                               float2* __restrict__ GD, int cmax) {
   extern __shared__ float lds_f[];
   const int wpb = blockDim.x / PMMF_WAVE;
@@ -66,20 +109,29 @@ __global__ void __launch_bounds__(256) k_gram(int S, const int64_t* __restrict__
     int64_t lb = 0, ub = 0;
     float w = 0.f;
     if (lane < nb) {
+      // row r's run of columns in cluster u, from its run table (clusters ascending)
       const int r = ci[kb + lane];
       w = cv[kb + lane];
-      const int64_t r1 = rp[r + 1];
-      lb = lower_bound_i32(ci, rp[r], r1, o);
-      ub = lower_bound_i32(ci, lb, r1, o + c);
+      int64_t lo = run_ptr[r], hi = run_ptr[r + 1];
+      const int64_t re = hi;
+      while (lo < hi) {
+        const int64_t mid = (lo + hi) >> 1;
+        if (run_cl[mid] < u) lo = mid + 1;
+        else hi = mid;
+      }
+      if (lo < re && run_cl[lo] == u) {
+        lb = run_start[lo];
+        ub = lo + 1 < re ? run_start[lo + 1] : rp[r + 1];
+      }
     }
     // accumulate the segments in ascending r; the first 64 entries of four segments are
     // loaded together so their latencies overlap (the summation order is unchanged)
-    for (int t = 0; t < nb; t += 4) {
-      int64_t sl[4], su[4];
-      float sw[4], pv[4];
-      int pc[4];
+    for (int t = 0; t < nb; t += GRAM_SEGS) {
+      int64_t sl[GRAM_SEGS], su[GRAM_SEGS];
+      float sw[GRAM_SEGS], pv[GRAM_SEGS];
+      int pc[GRAM_SEGS];
 #pragma unroll
-      for (int q = 0; q < 4; ++q) {
+      for (int q = 0; q < GRAM_SEGS; ++q) {
         const int tt = min(t + q, nb - 1);
         sl[q] = __shfl(lb, tt);
         su[q] = __shfl(ub, tt);
@@ -90,7 +142,7 @@ __global__ void __launch_bounds__(256) k_gram(int S, const int64_t* __restrict__
         pv[q] = e < su[q] ? cv[e] : 0.f;
       }
 #pragma unroll
-      for (int q = 0; q < 4; ++q) {
+      for (int q = 0; q < GRAM_SEGS; ++q) {
         if (sl[q] + lane < su[q]) acc[pc[q] - o] += sw[q] * pv[q];
         // the rest of the segment, eight 64-entry chunks requested at a time (entries of one
         // segment hit distinct columns, so only the segment order fixes the sums)
@@ -410,12 +462,14 @@ hipError_t launch_gram_bf16(int S, int m, const int64_t* rp, const int32_t* ci, 
 
 hipError_t launch_gram(int S, const int64_t* rp, const int32_t* ci, const float* cv,
                        const int32_t* off, const int32_t* cl_of, const int64_t* gbase,
+                       const int64_t* run_ptr, const int32_t* run_cl, const int64_t* run_start,
                        float2* GD, int cmax, hipStream_t s) {
   if (S == 0) return hipSuccess;
   int wpb = 4;
   while (wpb > 1 && (size_t)wpb * cmax * 4 > 64 * 1024) wpb >>= 1;
   const size_t lds = (size_t)wpb * cmax * sizeof(float);
-  k_gram<<<(S + wpb - 1) / wpb, wpb * PMMF_WAVE, lds, s>>>(S, rp, ci, cv, off, cl_of, gbase, GD,
+  k_gram<<<(S + wpb - 1) / wpb, wpb * PMMF_WAVE, lds, s>>>(S, rp, ci, cv, off, cl_of, gbase,
+                                                           run_ptr, run_cl, run_start, GD,
                                                            cmax);
   return hipGetLastError();
 }

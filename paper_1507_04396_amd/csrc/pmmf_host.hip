@@ -556,6 +556,7 @@ extern "C" int mmf_factor(int64_t n, int64_t nnz, const int64_t* d_rowptr, const
   DBuf GD, Q, retflag, keep, scan, cnt, loss_row, overflow, gid_cur, tbase, dense_buf;
   DBuf bf_bm, bf_pre, bf_R, bf_off, bf_slab, bf_slab16, bf_stats;  // BF16 form only
   DBuf wstart, wcnt, abase, stage_ci, stage_cv;  // staging rows of the two products
+  DBuf run_ptr, run_cl, run_start;                 // run table of the active matrix
   if (p->gram_mode == 1) bf_stats.ensure(2 * sizeof(unsigned long long));
   GD.ensure(pool * sizeof(float2));
   Q.ensure(pool * sizeof(float));
@@ -628,9 +629,24 @@ extern "C" int mmf_factor(int64_t n, int64_t nnz, const int64_t* d_rowptr, const
                                      dense_buf.as<float>(), sd.off.as<int32_t>(), sd.m,
                                      sd.gbase.as<int64_t>(), GD.as<float2>(), sd.cmax, s));
     } else {
+      // run table of the active matrix (each row's column runs per cluster), then the Grams
+      HIPCHK(pmmf::launch_runs(S, 0, M.rp.as<int64_t>(), M.ci.as<int32_t>(),
+                               sd.cl_of.as<int32_t>(), cnt.as<int32_t>(), nullptr, nullptr,
+                               nullptr, s));
+      run_ptr.ensure((S + 1) * sizeof(int64_t));
+      HIPCHK(pmmf::launch_scan(cnt.as<int32_t>(), run_ptr.as<int64_t>(), S,
+                               scan_tmp.as<int64_t>(), s));
+      const int64_t nrun = read_i64(run_ptr.as<int64_t>() + S, s);
+      run_cl.ensure(std::max<int64_t>(nrun, 1) * sizeof(int32_t));
+      run_start.ensure(std::max<int64_t>(nrun, 1) * sizeof(int64_t));
+      HIPCHK(pmmf::launch_runs(S, 1, M.rp.as<int64_t>(), M.ci.as<int32_t>(),
+                               sd.cl_of.as<int32_t>(), nullptr, run_ptr.as<int64_t>(),
+                               run_cl.as<int32_t>(), run_start.as<int64_t>(), s));
       HIPCHK(pmmf::launch_gram(S, M.rp.as<int64_t>(), M.ci.as<int32_t>(), M.cv.as<float>(),
                                sd.off.as<int32_t>(), sd.cl_of.as<int32_t>(),
-                               sd.gbase.as<int64_t>(), GD.as<float2>(), cm, s));
+                               sd.gbase.as<int64_t>(), run_ptr.as<int64_t>(),
+                               run_cl.as<int32_t>(), run_start.as<int64_t>(), GD.as<float2>(),
+                               cm, s));
     }
     // greedy rotation search in every cluster
     pmmf::FindArgs fa;
