@@ -137,6 +137,16 @@ int mmf_apply_inverse(mmf_handle h, const float* d_x, float* d_y, int64_t nrhs, 
                       void* stream);
 
 /*
+ * mmf_apply_inverse_sqrt — Y = U^T H^{-1/2} U X = A~^{-1/2} X (the xi = 1/2 power of Sec. 4's
+ * preconditioner A~^{-xi}, as used for split-symmetric preconditioning): reciprocal square roots
+ * of the retired diagonal, and V diag(lambda^{-1/2}) V^T for the core from its FP64 symmetric
+ * eigendecomposition (rocSOLVER dsyevd on first use, kept until the parameters change).
+ * Errors as mmf_apply, plus MMF_ESINGULAR (a retired entry <= 0 or a core eigenvalue <= 0).
+ */
+int mmf_apply_inverse_sqrt(mmf_handle h, const float* d_x, float* d_y, int64_t nrhs, int64_t ld,
+                           void* stream);
+
+/*
  * mmf_backward — adjoint of Y = U^T H U X (from Eq. 1; the paper has no gradient) given Ybar:
  *   d_xbar      [n][ld]         = U^T H^T U Ybar
  *   d_hdiag_bar [n]             : sum over columns of (U Ybar)_e (U X)_e on retired e (0 on core)
@@ -152,13 +162,14 @@ int mmf_backward(mmf_handle h, const float* d_x, const float* d_ybar, float* d_x
 
 /*
  * Captured products (batching of Sec. 2.3 / Table 1's many small operations into one launch):
- * mmf_graph_capture records one mmf_apply (inverse = 0) or mmf_apply_inverse (inverse = 1) from
+ * mmf_graph_capture records one mmf_apply (inverse = 0), mmf_apply_inverse (inverse = 1) or
+ * mmf_apply_inverse_sqrt (inverse = 2) from
  * d_x to d_y ([n][ld], device, fixed for the graph's life) as a HIP graph.  It first runs the
  * product eagerly on `stream` (so d_y holds the result and every size-dependent preparation is
  * done) and synchronizes it; the graph contains kernel nodes only and owns its own workspace.
  * mmf_graph_launch replays it on `stream` (asynchronous); it reads d_x and the handle's current
- * rotations and H, and writes d_y.  A graph of the inverse is refused (MMF_ESTATE) once theta or H
- * have changed (mmf_set_params, mmf_sync_angles), since it holds the core inverse of capture time.
+ * rotations and H, and writes d_y.  A graph of an inverse is refused (MMF_ESTATE) once theta or H
+ * have changed (mmf_set_params, mmf_sync_angles), since it holds the core factor of capture time.
  * Launching after mmf_destroy of its factorization, or after mmf_graph_destroy, is MMF_ESTATE.
  * mmf_graph_destroy waits for the device and frees the graph.  Errors: MMF_EINVAL, MMF_ESTATE,
  * MMF_ESINGULAR (inverse), MMF_ENOMEM, MMF_EDEVICE.

@@ -20,6 +20,7 @@ from .pmmf_oracle import (  # noqa: F401
     apply_Ut,
     apply,
     apply_inverse,
+    apply_inverse_sqrt,
     backward,
     dense_U,
     dense_reconstruction,

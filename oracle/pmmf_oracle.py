@@ -416,6 +416,31 @@ def apply_inverse(fac: Factorization, X: np.ndarray) -> np.ndarray:
     return Y[:, 0] if squeeze else Y
 
 
+def apply_inverse_sqrt(fac: Factorization, X: np.ndarray) -> np.ndarray:
+    """A~^{-1/2} X = U^T H^{-1/2} U X (Sec. 4, the xi = 1/2 power used for split-symmetric
+    preconditioning): U is orthogonal, so A~^{-1/2} = U^T H^{-1/2} U with H^{-1/2} the retired
+    diagonal to the power -1/2 and the core's inverse square root V diag(lambda^{-1/2}) V^T from
+    LAPACK's symmetric eigendecomposition.  Requires H positive definite."""
+    X = np.asarray(X, dtype=np.float64)
+    squeeze = X.ndim == 1
+    X2 = X[:, None] if squeeze else X
+    Z = apply_U(fac, X2)
+    W = np.zeros_like(Z)
+    core = fac.core_ids
+    mask = np.ones(fac.n, dtype=bool)
+    mask[core] = False
+    if np.any(fac.hdiag[mask] <= 0.0):
+        raise ValueError("H has a retired diagonal entry that is not positive")
+    W[mask] = Z[mask] / np.sqrt(fac.hdiag[mask, None])
+    if len(core):
+        lam, V = np.linalg.eigh(0.5 * (fac.hcore + fac.hcore.T))
+        if np.any(lam <= 0.0):
+            raise ValueError("the core of H is not positive definite")
+        W[core] = (V * (1.0 / np.sqrt(lam))) @ (V.T @ Z[core])
+    Y = apply_Ut(fac, W)
+    return Y[:, 0] if squeeze else Y
+
+
 def dense_U(fac: Factorization) -> np.ndarray:
     return apply_U(fac, np.eye(fac.n))
 

@@ -64,6 +64,7 @@ SIGNATURES = {
     "mmf_factor": [I64, I64, P, P, P, ctypes.POINTER(mmf_params), P, ctypes.POINTER(H)],
     "mmf_apply": [H, P, P, I64, I64, P],
     "mmf_apply_inverse": [H, P, P, I64, I64, P],
+    "mmf_apply_inverse_sqrt": [H, P, P, I64, I64, P],
     "mmf_backward": [H, P, P, P, P, P, P, I64, I64, P],
     "mmf_get_info": [H, ctypes.POINTER(mmf_info)],
     "mmf_get_stage_info": [H, I32, ctypes.POINTER(mmf_stage_info)],

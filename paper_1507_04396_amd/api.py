@@ -153,12 +153,15 @@ class Factorization:
         return x, x.shape[1], x.stride(0)
 
     def apply(self, x: torch.Tensor, out: Optional[torch.Tensor] = None, stream=None,
-              inverse: bool = False) -> torch.Tensor:
-        """Y = U^T H U X (or U^T H^-1 U X), X row-major [n][nrhs]."""
+              inverse=False) -> torch.Tensor:
+        """Y = U^T H U X, U^T H^-1 U X (inverse=True) or U^T H^-1/2 U X (inverse="sqrt");
+        X row-major [n][nrhs]."""
         squeeze = x.dim() == 1
         x2, nrhs, ld = self._vec_args(x.contiguous())
         y = torch.empty_like(x2) if out is None else out
-        fn = _lib.load().mmf_apply_inverse if inverse else _lib.load().mmf_apply
+        lib = _lib.load()
+        fn = (lib.mmf_apply_inverse_sqrt if inverse == "sqrt"
+              else lib.mmf_apply_inverse if inverse else lib.mmf_apply)
         check(fn(self.handle, _ptr(x2), _ptr(y), nrhs, ld, _stream(stream)))
         return y[:, 0] if squeeze else y
 
@@ -212,7 +215,8 @@ class Factorization:
         if y.shape != x2.shape and not (y.dim() == 1 and x.dim() == 1):
             raise ValueError("y must have the shape of x")
         g = ctypes.c_void_p()
-        check(_lib.load().mmf_graph_capture(self.handle, 1 if inverse else 0, _ptr(x2), _ptr(y),
+        which = 2 if inverse == "sqrt" else (1 if inverse else 0)
+        check(_lib.load().mmf_graph_capture(self.handle, which, _ptr(x2), _ptr(y),
                                             nrhs, ld, _stream(stream), ctypes.byref(g)))
         return ProductGraph(g, self)
 

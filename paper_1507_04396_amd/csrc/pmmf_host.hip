@@ -15,6 +15,9 @@
 #include <string>
 #include <vector>
 
+#include <rocblas/rocblas.h>
+#include <rocsolver/rocsolver.h>
+
 #include "factor_kernels.h"
 #include "sweep_kernels.h"
 
@@ -135,7 +138,9 @@ struct mmf_plan {
   DBuf rot_loc, rot_gid, rot_o, rot_ret, rot_margin, theta, rot_lit;
   DBuf hdiag, hcore, core_ids, is_core;
   DBuf hinv, chol_L, chol_X, status;
+  DBuf hisqrt, eig_A, eig_D, eig_E, eig_info;  // H_core^{-1/2} and its eigendecomposition
   bool inv_ready = false;
+  bool isqrt_ready = false;
   bool units_ready = false;
   uint64_t version = 0;  // bumped whenever theta, H or the rotations change
   std::map<std::pair<std::string, int64_t>, SweepCfg> tune;  // (product, width) -> config
@@ -901,7 +906,53 @@ void ensure_inverse(mmf_plan& h, hipStream_t s) {
   h.inv_ready = true;
 }
 
-// Y = U^T op(H) U X with op = H (inverse = false) or H^{-1}
+// H^{-1/2} for Y = U^T H^{-1/2} U X: positive retired diagonal (checked), and the core's inverse
+// square root from an FP64 symmetric eigendecomposition (LAPACK syevd through rocSOLVER, once per
+// handle and parameter set)
+std::mutex g_rb_mu;
+rocblas_handle g_rb = nullptr;
+
+void ensure_inverse_sqrt(mmf_plan& h, hipStream_t s) {
+  if (h.isqrt_ready) return;
+  const int64_t c = h.core;
+  h.hisqrt.ensure(std::max<int64_t>(c * c, 1) * sizeof(float));
+  h.status.ensure(sizeof(int32_t));
+  HIPCHK(hipMemsetAsync(h.status.p, 0, sizeof(int32_t), s));
+  HIPCHK(pmmf::launch_check_hdiag_pos(h.n, h.hdiag.as<float>(), h.is_core.as<uint8_t>(),
+                                      h.status.as<int32_t>(), s));
+  if (c > 0) {
+    h.eig_A.ensure(c * c * sizeof(double));
+    h.eig_D.ensure(c * sizeof(double));
+    h.eig_E.ensure(c * sizeof(double));
+    h.eig_info.ensure(sizeof(rocblas_int));
+    HIPCHK(pmmf::launch_f32_to_f64(c * c, h.hcore.as<float>(), h.eig_A.as<double>(), s));
+    std::lock_guard<std::mutex> lk(g_rb_mu);
+    if (!g_rb && rocblas_create_handle(&g_rb) != rocblas_status_success)
+      raise(MMF_EDEVICE, "rocblas_create_handle failed");
+    if (rocblas_set_stream(g_rb, s) != rocblas_status_success)
+      raise(MMF_EDEVICE, "rocblas_set_stream failed");
+    // the core is symmetric, so its row-major array is also its column-major array
+    const rocblas_status st = rocsolver_dsyevd(g_rb, rocblas_evect_original, rocblas_fill_upper,
+                                               (rocblas_int)c, h.eig_A.as<double>(),
+                                               (rocblas_int)c, h.eig_D.as<double>(),
+                                               h.eig_E.as<double>(),
+                                               h.eig_info.as<rocblas_int>());
+    if (st != rocblas_status_success) raise(MMF_EDEVICE, "rocsolver_dsyevd failed");
+    HIPCHK(pmmf::launch_isqrt_assemble((int)c, h.eig_A.as<double>(), h.eig_D.as<double>(),
+                                       h.hisqrt.as<float>(), h.status.as<int32_t>(), s));
+  }
+  int32_t st = 0;
+  rocblas_int info = 0;
+  HIPCHK(hipMemcpyAsync(&st, h.status.p, sizeof(st), hipMemcpyDeviceToHost, s));
+  if (c > 0) HIPCHK(hipMemcpyAsync(&info, h.eig_info.p, sizeof(info), hipMemcpyDeviceToHost, s));
+  HIPCHK(hipStreamSynchronize(s));
+  if (info != 0) raise(MMF_EDEVICE, "the core eigendecomposition did not converge");
+  if (st & 4) raise(MMF_ESINGULAR, "H has a retired diagonal entry that is not positive");
+  if (st & 8) raise(MMF_ESINGULAR, "the core of H is not positive definite");
+  h.isqrt_ready = true;
+}
+
+// Y = U^T op(H) U X with op = H (which = 0), H^{-1} (1) or H^{-1/2} (2)
 // ------------------------------------------------------------------------------------------
 // Sweep autotuner.  The first product (or adjoint) of a handle with a given column count times each
 // candidate configuration of the sweep kernels on the caller's own buffers (the products are
@@ -1057,8 +1108,9 @@ SweepCfg sweep_config(mmf_plan& h, const char* what, int nv, int64_t nrhs, hipSt
 }
 
 void apply_body(mmf_plan& h, const float* x, float* y, int64_t nrhs, int64_t ld, hipStream_t s,
-                bool inverse, float* ws0, float* ws1, const SweepCfg& cfg) {
-  const float* Hc = inverse ? h.hinv.as<float>() : h.hcore.as<float>();
+                int which, float* ws0, float* ws1, const SweepCfg& cfg) {
+  const float* Hc = which == 2 ? h.hisqrt.as<float>()
+                               : (which == 1 ? h.hinv.as<float>() : h.hcore.as<float>());
   const int P = (int)h.st.size();
   const int64_t core = h.core;
   if (P == 0) {
@@ -1078,7 +1130,7 @@ void apply_body(mmf_plan& h, const float* x, float* y, int64_t nrhs, int64_t ld,
     io.ld_c = nrhs;
     io.dst_nat[0] = y;
     io.ld_nat = ld;
-    io.mode[0] = inverse ? 2 : 1;
+    io.mode[0] = which == 2 ? 3 : (which == 1 ? 2 : 1);
     io.hdiag = h.hdiag.as<float>();
     io.nrhs = nrhs;
     HIPCHK(pmmf::launch_unit_fwd(unit_view(h, sd), io, 1, cfg.wpb, s));
@@ -1109,16 +1161,17 @@ void apply_body(mmf_plan& h, const float* x, float* y, int64_t nrhs, int64_t ld,
 }
 
 void apply_impl(mmf_plan& h, const float* x, float* y, int64_t nrhs, int64_t ld, hipStream_t s,
-                bool inverse, float* ws0 = nullptr, float* ws1 = nullptr) {
+                int which, float* ws0 = nullptr, float* ws1 = nullptr) {
   if (nrhs < 0 || ld < nrhs || (!x && nrhs > 0) || (!y && nrhs > 0))
     raise(MMF_EINVAL, "bad vector arguments");
   if (nrhs == 0) return;
-  if (inverse) ensure_inverse(h, s);
+  if (which == 1) ensure_inverse(h, s);
+  if (which == 2) ensure_inverse_sqrt(h, s);
   ensure_units(h, s);
   const SweepCfg cfg = sweep_config(h, "apply", 1, nrhs, s, [&](const SweepCfg& c) {
-    apply_body(h, x, y, nrhs, ld, s, inverse, ws0, ws1, c);
+    apply_body(h, x, y, nrhs, ld, s, which, ws0, ws1, c);
   });
-  apply_body(h, x, y, nrhs, ld, s, inverse, ws0, ws1, cfg);
+  apply_body(h, x, y, nrhs, ld, s, which, ws0, ws1, cfg);
 }
 
 }  // namespace
@@ -1127,7 +1180,7 @@ extern "C" int mmf_apply(mmf_handle hh, const float* d_x, float* d_y, int64_t nr
                          void* stream) {
   ABI_BEGIN
   mmf_plan& h = *checked(hh);
-  apply_impl(h, d_x, d_y, nrhs, ld, as_stream(stream), false);
+  apply_impl(h, d_x, d_y, nrhs, ld, as_stream(stream), 0);
   return MMF_OK;
   ABI_END
 }
@@ -1136,7 +1189,16 @@ extern "C" int mmf_apply_inverse(mmf_handle hh, const float* d_x, float* d_y, in
                                  int64_t ld, void* stream) {
   ABI_BEGIN
   mmf_plan& h = *checked(hh);
-  apply_impl(h, d_x, d_y, nrhs, ld, as_stream(stream), true);
+  apply_impl(h, d_x, d_y, nrhs, ld, as_stream(stream), 1);
+  return MMF_OK;
+  ABI_END
+}
+
+extern "C" int mmf_apply_inverse_sqrt(mmf_handle hh, const float* d_x, float* d_y, int64_t nrhs,
+                                      int64_t ld, void* stream) {
+  ABI_BEGIN
+  mmf_plan& h = *checked(hh);
+  apply_impl(h, d_x, d_y, nrhs, ld, as_stream(stream), 2);
   return MMF_OK;
   ABI_END
 }
@@ -1147,7 +1209,7 @@ extern "C" int mmf_apply_inverse(mmf_handle hh, const float* d_x, float* d_y, in
 // The graph owns its ping-pong workspace, so later eager calls cannot move it.
 struct mmf_graph_s {
   mmf_plan* h = nullptr;
-  bool inverse = false;
+  int which = 0;  // 0 A~, 1 A~^{-1}, 2 A~^{-1/2}
   uint64_t version = 0;
   hipGraph_t g = nullptr;
   hipGraphExec_t ge = nullptr;
@@ -1165,17 +1227,17 @@ extern "C" int mmf_graph_capture(mmf_handle hh, int32_t inverse, const float* d_
                                  int64_t nrhs, int64_t ld, void* stream, mmf_graph* out) {
   ABI_BEGIN
   mmf_plan& h = *checked(hh);
-  if (!out || nrhs < 1 || ld < nrhs || !d_x || !d_y || d_x == d_y)
+  if (!out || nrhs < 1 || ld < nrhs || !d_x || !d_y || d_x == d_y || inverse < 0 || inverse > 2)
     raise(MMF_EINVAL, "bad graph capture arguments");
   hipStream_t s = as_stream(stream);
   std::unique_ptr<mmf_graph_s, void (*)(mmf_graph_s*)> G(new mmf_graph_s, graph_free);
   G->h = &h;
-  G->inverse = inverse != 0;
+  G->which = inverse;
   const int64_t s1 = h.st.empty() ? 0 : h.st[0]->size - h.st[0]->t;
   G->ws0.ensure(std::max<int64_t>(s1 * nrhs, 1) * sizeof(float));
   G->ws1.ensure(std::max<int64_t>(s1 * nrhs, 1) * sizeof(float));
   // eager call: sweep units, core inverse and tile choice are prepared here, and y is produced
-  apply_impl(h, d_x, d_y, nrhs, ld, s, G->inverse, G->ws0.as<float>(), G->ws1.as<float>());
+  apply_impl(h, d_x, d_y, nrhs, ld, s, G->which, G->ws0.as<float>(), G->ws1.as<float>());
   HIPCHK(hipStreamSynchronize(s));
   G->version = h.version;
   hipStream_t cs = nullptr;
@@ -1186,7 +1248,7 @@ extern "C" int mmf_graph_capture(mmf_handle hh, int32_t inverse, const float* d_
     raise(MMF_EDEVICE, std::string("graph capture: ") + hipGetErrorString(ce));
   }
   try {
-    apply_impl(h, d_x, d_y, nrhs, ld, cs, G->inverse, G->ws0.as<float>(), G->ws1.as<float>());
+    apply_impl(h, d_x, d_y, nrhs, ld, cs, G->which, G->ws0.as<float>(), G->ws1.as<float>());
   } catch (...) {
     hipGraph_t dead = nullptr;
     (void)hipStreamEndCapture(cs, &dead);
@@ -1214,7 +1276,7 @@ extern "C" int mmf_graph_launch(mmf_graph gg, void* stream) {
     std::lock_guard<std::mutex> lk(g_live_mu);
     if (!G || !g_graphs.count(G)) raise(MMF_ESTATE, "invalid or destroyed graph");
     if (!g_live.count(G->h)) raise(MMF_ESTATE, "the graph's factorization was destroyed");
-    if (G->inverse && G->version != G->h->version)
+    if (G->which != 0 && G->version != G->h->version)
       raise(MMF_ESTATE, "parameters changed since the inverse graph was captured");
   }
   HIPCHK(hipGraphLaunch(G->ge, as_stream(stream)));
@@ -1613,6 +1675,7 @@ extern "C" int mmf_sync_angles(mmf_handle hh, void* stream) {
   mmf_plan& h = *checked(hh);
   hipStream_t s = as_stream(stream);
   h.inv_ready = false;
+  h.isqrt_ready = false;
   ++h.version;
   if (h.k != 2) return MMF_OK;
   HIPCHK(pmmf::launch_sync_angles(h.R, h.theta.as<float>(), h.rot_o.as<float>(), s));
@@ -1630,6 +1693,7 @@ extern "C" int mmf_set_params(mmf_handle hh, const float* d_theta, const float* 
   hipStream_t s = as_stream(stream);
   if (d_theta && h.k != 2) raise(MMF_EINVAL, "angles exist only for k = 2");
   h.inv_ready = false;
+  h.isqrt_ready = false;
   ++h.version;
   if (d_hdiag)
     HIPCHK(hipMemcpyAsync(h.hdiag.p, d_hdiag, h.n * sizeof(float), hipMemcpyDeviceToDevice, s));

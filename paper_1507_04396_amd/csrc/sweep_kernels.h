@@ -49,7 +49,8 @@ struct FwdIO {
   int64_t ld_c;
   float* dst_nat[2];         // natural rows (retired rows of this stage)
   int64_t ld_nat;
-  int mode[2];               // retired rows: 0 copy, 1 times hdiag, 2 divided by hdiag
+  int mode[2];               // retired rows: 0 copy, 1 times hdiag, 2 divided by hdiag,
+                             // 3 divided by sqrt(hdiag)
   const float* hdiag;
   int64_t nrhs;
 };
@@ -83,6 +84,11 @@ hipError_t launch_gemm(int M, int N, int K, const float* A, int lda, int ta, con
 hipError_t launch_core_inverse(int n, float* work_L, float* work_X, float* out_inv,
                                int64_t nfull, const float* hdiag, const uint8_t* is_core,
                                int32_t* status, hipStream_t s);
+hipError_t launch_check_hdiag_pos(int64_t n, const float* hdiag, const uint8_t* is_core,
+                                  int32_t* status, hipStream_t s);
+hipError_t launch_f32_to_f64(int64_t n, const float* a, double* b, hipStream_t s);
+hipError_t launch_isqrt_assemble(int n, const double* V, const double* lam, float* out,
+                                 int32_t* status, hipStream_t s);
 hipError_t launch_rowdot(int64_t n, const float* a, const float* b, int64_t ld, int64_t nrhs,
                          const uint8_t* is_core, float* out, hipStream_t s);
 hipError_t launch_theta_reduce(int t, int ntiles, int64_t stride, const float* pa,

@@ -95,6 +95,7 @@ __global__ void __launch_bounds__(256) k_sweep_fwd(SweepStage st, FwdIO io) {
         const int g = -nx - 1;
         if (io.mode[v] == 1) val *= io.hdiag[g];
         else if (io.mode[v] == 2) val /= io.hdiag[g];
+        else if (io.mode[v] == 3) val /= sqrtf(io.hdiag[g]);
         io.dst_nat[v][(size_t)g * io.ld_nat + col] = val;
       }
     }
@@ -387,6 +388,59 @@ hipError_t launch_core_inverse(int n, float* work_L, float* work_X, float* out_i
 }
 
 // ------------------------------------------------------------------------------------------
+// H^{-1/2}: the retired diagonal must be positive, and the core's inverse square root is
+// V diag(lambda^{-1/2}) V^T from its FP64 eigendecomposition (eigenvectors in the columns of V,
+// column-major as LAPACK leaves them); status bit 4: a retired entry <= 0, bit 8: an eigenvalue
+// <= 0 (the core is not positive definite).
+__global__ void k_check_hdiag_pos(int64_t n, const float* __restrict__ hdiag,
+                                  const uint8_t* __restrict__ is_core, int32_t* status) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n && !is_core[i] && !(hdiag[i] > 0.f)) atomicOr(status, 4);
+}
+
+__global__ void k_f32_to_f64(int64_t n, const float* __restrict__ a, double* __restrict__ b) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) b[i] = a[i];
+}
+
+__global__ void k_isqrt_assemble(int n, const double* __restrict__ V, const double* __restrict__ lam,
+                                 float* __restrict__ out, int32_t* status) {
+  // out[i][j] = sum_k V[k*n + i] lam_k^{-1/2} V[k*n + j]  (V column-major: column k at k*n)
+  const int i = blockIdx.y, j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= n) return;
+  double acc = 0.0;
+  for (int k = 0; k < n; ++k) {
+    const double l = lam[k];
+    if (!(l > 0.0)) {
+      if (i == 0 && j == 0) atomicOr(status, 8);
+      continue;
+    }
+    acc += V[(size_t)k * n + i] * V[(size_t)k * n + j] / sqrt(l);
+  }
+  out[(size_t)i * n + j] = (float)acc;
+}
+
+hipError_t launch_check_hdiag_pos(int64_t n, const float* hdiag, const uint8_t* is_core,
+                                  int32_t* status, hipStream_t s) {
+  k_check_hdiag_pos<<<(unsigned)((n + 255) / 256), 256, 0, s>>>(n, hdiag, is_core, status);
+  return hipGetLastError();
+}
+
+hipError_t launch_f32_to_f64(int64_t n, const float* a, double* b, hipStream_t s) {
+  if (n == 0) return hipSuccess;
+  k_f32_to_f64<<<(unsigned)((n + 255) / 256), 256, 0, s>>>(n, a, b);
+  return hipGetLastError();
+}
+
+hipError_t launch_isqrt_assemble(int n, const double* V, const double* lam, float* out,
+                                 int32_t* status, hipStream_t s) {
+  if (n == 0) return hipSuccess;
+  dim3 grid((unsigned)((n + 255) / 256), (unsigned)n);
+  k_isqrt_assemble<<<grid, 256, 0, s>>>(n, V, lam, out, status);
+  return hipGetLastError();
+}
+
+// ------------------------------------------------------------------------------------------
 // hdiag_bar[e] = sum_w b[e][w] a[e][w] on retired e (0 on the core); one wave per row
 __global__ void k_rowdot(int64_t n, const float* __restrict__ a, const float* __restrict__ b,
                          int64_t ld, int64_t nrhs, const uint8_t* __restrict__ is_core,
@@ -576,6 +630,7 @@ __global__ void __launch_bounds__(256) k_unit_sweep(UnitStage st, FwdIO fio, Rev
         } else {
           if (fio.mode[v] == 1) val *= f;
           else if (fio.mode[v] == 2) val /= f;
+          else if (fio.mode[v] == 3) val /= sqrtf(f);
           fio.dst_nat[v][(int64_t)(-nx - 1) * fio.ld_nat + col] = val;
         }
       } else {

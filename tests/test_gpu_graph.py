@@ -37,7 +37,7 @@ CASES = [
 
 
 @pytest.mark.parametrize("name,make,params,nrhs", CASES, ids=[c[0] for c in CASES])
-@pytest.mark.parametrize("inverse", [False, True])
+@pytest.mark.parametrize("inverse", [False, True, "sqrt"])
 def test_graph_replays_match_eager(name, make, params, nrhs, inverse):
     A = make()
     ref = oracle.factor(A, **params)

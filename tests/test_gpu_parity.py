@@ -216,6 +216,32 @@ def test_apply_inverse_of_imported_spd_factorization():
     assert rel_err(z, X) <= max(1e-5, 1e-7 * cond)
 
 
+def test_apply_inverse_sqrt_matches_oracle_and_splits_symmetrically():
+    """A~^{-1/2} (Sec. 4, xi = 1/2): against the oracle, its square against A~^{-1}, and the
+    split-symmetric operator A~^{-1/2} A A~^{-1/2} is symmetric."""
+    from paper_1507_04396_amd.refine import spmm
+    A = workloads.small_grid((16, 16), sigma=0.5, shift=0.5, seed=6)
+    ref = oracle.factor(A, k=2, core=32, cluster=(16, 48), seed=2)
+    fac = _import(ref)
+    X = workloads.gaussian_block(A.n, 9, seed=3)
+    Xd = torch.from_numpy(X).cuda()
+    _say("[apply] inverse square root")
+    y = fac.apply(Xd, inverse="sqrt").cpu().numpy()
+    yref = oracle.apply_inverse_sqrt(ref, X.astype(np.float64))
+    cond = np.linalg.cond(ref.hcore)
+    tol = max(1e-5, 1e-7 * np.sqrt(cond))
+    assert rel_err(y, yref) <= tol, (rel_err(y, yref), cond)
+    z = fac.apply(fac.apply(Xd, inverse="sqrt"), inverse="sqrt").cpu().numpy()
+    assert rel_err(z, fac.apply_inverse(Xd).cpu().numpy()) <= max(1e-5, 1e-7 * cond)
+    rp, ci, cv = (torch.from_numpy(A.rowptr).cuda(), torch.from_numpy(A.colind).cuda(),
+                  torch.from_numpy(A.val).cuda())
+    B = lambda V: fac.apply(spmm(rp, ci, cv, fac.apply(V, inverse="sqrt")), inverse="sqrt")  # noqa
+    Yd = torch.from_numpy(workloads.gaussian_block(A.n, 9, seed=4)).cuda()
+    lhs = (B(Xd) * Yd).sum(0).double()
+    rhs = (Xd * B(Yd)).sum(0).double()
+    assert torch.allclose(lhs, rhs, rtol=1e-4, atol=1e-3)
+
+
 def test_apply_inverse_reports_singular_core():
     A = workloads.small_grid((8, 8), seed=1)   # D - W is singular
     ref = oracle.factor(A, k=2, core=8, cluster=(8, 24), seed=1)
@@ -228,6 +254,9 @@ def test_apply_inverse_reports_singular_core():
                                    lg["hcore"])
     with pytest.raises(MMFError) as e:
         fac.apply_inverse(torch.randn(A.n, 2, device="cuda"))
+    assert e.value.name == "MMF_ESINGULAR"
+    with pytest.raises(MMFError) as e:
+        fac.apply(torch.randn(A.n, 2, device="cuda"), inverse="sqrt")
     assert e.value.name == "MMF_ESINGULAR"
 
 

@@ -379,6 +379,30 @@ def test_apply_is_symmetric_and_inverse_inverts():
                                rtol=1e-9, atol=1e-11)
 
 
+def test_inverse_square_root_pins():
+    """A~^{-1/2} (Sec. 4, xi = 1/2) against independent routes: its square is the Cholesky-based
+    A~^{-1}, it is symmetric, A~^{-1/2} A~ A~^{-1/2} = I, and it equals SciPy's inverse of the
+    dense matrix square root of A~ rebuilt from the log."""
+    import scipy.linalg as sla
+    A = workloads.small_grid((7, 9), sigma=0.7, shift=0.5, seed=12)   # SPD
+    fac = oracle.factor(A, k=2, core=9, cluster=(6, 20), seed=1)
+    rng = np.random.default_rng(8)
+    Xb = rng.standard_normal((fac.n, 4))
+    S = lambda Z: oracle.apply_inverse_sqrt(fac, Z)  # noqa: E731
+    np.testing.assert_allclose(S(S(Xb)), oracle.apply_inverse(fac, Xb), rtol=1e-9, atol=1e-11)
+    x, y = rng.standard_normal(fac.n), rng.standard_normal(fac.n)
+    assert abs(x @ S(y) - y @ S(x)) <= 1e-12 * np.abs(x).sum() * np.abs(y).max()
+    np.testing.assert_allclose(S(oracle.apply(fac, S(Xb))), Xb, atol=1e-10)
+    U = _dense_U_from_log(fac)
+    Atil = U.T @ _dense_H(fac) @ U
+    ref = np.linalg.solve(np.real(sla.sqrtm(Atil)), Xb)
+    np.testing.assert_allclose(S(Xb), ref, rtol=1e-8, atol=1e-10)
+    # an indefinite H is refused
+    bad = om.with_angles(fac, om.angles(fac), hcore=-np.eye(len(fac.core_ids)))
+    with pytest.raises(ValueError):
+        oracle.apply_inverse_sqrt(bad, Xb)
+
+
 # --------------------------------------------------------------------------- adjoint
 
 def _objective(fac, X, W):
