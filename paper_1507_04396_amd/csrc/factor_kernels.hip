@@ -627,6 +627,124 @@ __device__ inline void rot3(const double (&g)[3][3], double (&O)[3][3], double& 
   }
 }
 
+// FP32 form of the same eigendecomposition (used by k_find): the rotation is stored and applied
+// in FP32, so FP32 eigenvectors are as accurate as its use; the rotated block is then formed in
+// FP64 from exactly this rotation.  Off-diagonal pairs are rotated as 2-vectors, so their
+// rounding is relative to their own size and the sweeps reach the threshold quadratically.
+__device__ inline void jacobi_pair_f(float (&A)[3][3], float (&V)[3][3], int p, int q, bool& rot) {
+  const float apq = A[p][q];
+  if (fabsf(apq) <= 1e-8f * (fabsf(A[p][p]) + fabsf(A[q][q]))) {
+    A[p][q] = A[q][p] = 0.f;
+    return;
+  }
+  rot = true;
+  const float tau = (A[q][q] - A[p][p]) * __builtin_amdgcn_rcpf(2.f * apq);
+  const float sg = tau >= 0.f ? 1.f : -1.f;
+  const float r1 = fmaf(tau, tau, 1.f);
+  const float t = sg * __builtin_amdgcn_rcpf(fabsf(tau) + r1 * __builtin_amdgcn_rsqf(r1));
+  const float c = __builtin_amdgcn_rsqf(fmaf(t, t, 1.f));
+  const float s = t * c;
+#pragma unroll
+  for (int r = 0; r < 3; ++r) {
+    const float arp = A[r][p], arq = A[r][q];
+    A[r][p] = c * arp - s * arq;
+    A[r][q] = s * arp + c * arq;
+  }
+#pragma unroll
+  for (int r = 0; r < 3; ++r) {
+    const float apr = A[p][r], aqr = A[q][r];
+    A[p][r] = c * apr - s * aqr;
+    A[q][r] = s * apr + c * aqr;
+  }
+  A[p][q] = A[q][p] = 0.f;
+#pragma unroll
+  for (int r = 0; r < 3; ++r) {
+    const float vrp = V[r][p], vrq = V[r][q];
+    V[r][p] = c * vrp - s * vrq;
+    V[r][q] = s * vrp + c * vrq;
+  }
+}
+
+__device__ inline void rot3f(const double (&g)[3][3], double (&O)[3][3], double& trace_margin,
+                             double& eig_margin) {
+  float A[3][3], V[3][3];
+#pragma unroll
+  for (int i = 0; i < 3; ++i)
+#pragma unroll
+    for (int j = 0; j < 3; ++j) { A[i][j] = (float)g[i][j]; V[i][j] = (i == j) ? 1.f : 0.f; }
+  for (int sweep = 0; sweep < 12; ++sweep) {
+    bool rot = false;
+    jacobi_pair_f(A, V, 0, 1, rot);
+    jacobi_pair_f(A, V, 0, 2, rot);
+    jacobi_pair_f(A, V, 1, 2, rot);
+    if (!rot) break;
+  }
+  // columns of V sorted by descending eigenvalue (three compare-swaps on scalars)
+  float e0 = A[0][0], e1 = A[1][1], e2 = A[2][2];
+  float b00 = V[0][0], b01 = V[1][0], b02 = V[2][0];   // b0 = eigenvector of e0 (column 0)
+  float b10 = V[0][1], b11 = V[1][1], b12 = V[2][1];
+  float b20 = V[0][2], b21 = V[1][2], b22 = V[2][2];
+#define PMMF_CSWAPF(ex, ey, x0, x1, x2, y0, y1, y2)                              \
+  if (ey > ex) {                                                               \
+    float t_ = ex; ex = ey; ey = t_;                                          \
+    t_ = x0; x0 = y0; y0 = t_; t_ = x1; x1 = y1; y1 = t_; t_ = x2; x2 = y2; y2 = t_; \
+  }
+  PMMF_CSWAPF(e0, e1, b00, b01, b02, b10, b11, b12)
+  PMMF_CSWAPF(e0, e2, b00, b01, b02, b20, b21, b22)
+  PMMF_CSWAPF(e1, e2, b10, b11, b12, b20, b21, b22)
+#undef PMMF_CSWAPF
+  const double emax = fmax(fabs((double)e0), fabs((double)e2));
+  eig_margin = emax > 0.0 ? fmin((double)e0 - e1, (double)e1 - e2) / emax : 0.0;
+  const float b[3][3] = {{b00, b01, b02}, {b10, b11, b12}, {b20, b21, b22}};
+  // traces of the six row permutations, in lexicographic order
+  const float tr0 = fabsf(b00) + fabsf(b11) + fabsf(b22);  // (0,1,2)
+  const float tr1 = fabsf(b00) + fabsf(b21) + fabsf(b12);  // (0,2,1)
+  const float tr2 = fabsf(b10) + fabsf(b01) + fabsf(b22);  // (1,0,2)
+  const float tr3 = fabsf(b10) + fabsf(b21) + fabsf(b02);  // (1,2,0)
+  const float tr4 = fabsf(b20) + fabsf(b01) + fabsf(b12);  // (2,0,1)
+  const float tr5 = fabsf(b20) + fabsf(b11) + fabsf(b02);  // (2,1,0)
+  int best = 0;
+  float bt = tr0, second = -1.f;
+#define PMMF_PICKF(trq, q)                        \
+  if (trq > bt) { second = bt; bt = trq; best = q; } \
+  else second = fmaxf(second, trq);
+  PMMF_PICKF(tr1, 1)
+  PMMF_PICKF(tr2, 2)
+  PMMF_PICKF(tr3, 3)
+  PMMF_PICKF(tr4, 4)
+  PMMF_PICKF(tr5, 5)
+#undef PMMF_PICKF
+  trace_margin = bt > 0.f ? ((double)bt - second) / bt : 0.0;
+  int p0, p1, p2;
+  switch (best) {
+    case 0: p0 = 0; p1 = 1; p2 = 2; break;
+    case 1: p0 = 0; p1 = 2; p2 = 1; break;
+    case 2: p0 = 1; p1 = 0; p2 = 2; break;
+    case 3: p0 = 1; p1 = 2; p2 = 0; break;
+    case 4: p0 = 2; p1 = 0; p2 = 1; break;
+    default: p0 = 2; p1 = 1; p2 = 0; break;
+  }
+  // rows with static indices: select by comparing the permutation entries
+#pragma unroll
+  for (int j = 0; j < 3; ++j) {
+    const float r0 = p0 == 0 ? b[0][j] : (p0 == 1 ? b[1][j] : b[2][j]);
+    const float r1 = p1 == 0 ? b[0][j] : (p1 == 1 ? b[1][j] : b[2][j]);
+    const float r2 = p2 == 0 ? b[0][j] : (p2 == 1 ? b[1][j] : b[2][j]);
+    O[0][j] = r0;
+    O[1][j] = r1;
+    O[2][j] = r2;
+  }
+  const double s0 = O[0][0] >= 0.0 ? 1.0 : -1.0;
+  const double s1 = O[1][1] >= 0.0 ? 1.0 : -1.0;
+  const double s2 = O[2][2] >= 0.0 ? 1.0 : -1.0;
+#pragma unroll
+  for (int j = 0; j < 3; ++j) {
+    O[0][j] *= s0;
+    O[1][j] *= s1;
+    O[2][j] *= s2;
+  }
+}
+
 // ------------------------------------------------------------------------------------------
 // Randomized greedy rotation search inside one cluster (Alg. 2), one workgroup per cluster.
 struct Cand {
@@ -853,7 +971,7 @@ __global__ void __launch_bounds__(NT) k_find(FindArgs A, int cmax) {
         margin = fmin(margin, ta);
       } else {
         double tm, em;
-        rot3(g, O, tm, em);
+        rot3f(g, O, tm, em);
         margin = fmin(margin, fmin(tm, em));
       }
       // rotated k x k blocks: O g O^T and O d O^T
