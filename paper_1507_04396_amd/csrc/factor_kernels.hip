@@ -747,6 +747,14 @@ __device__ inline void rot3f(const double (&g)[3][3], double (&O)[3][3], double&
 
 // ------------------------------------------------------------------------------------------
 // Randomized greedy rotation search inside one cluster (Alg. 2), one workgroup per cluster.
+__device__ inline int slot_of(int j, int t0, int t1, int t2) {
+  return j == t0 ? 0 : (j == t1 ? 1 : (j == t2 ? 2 : -1));
+}
+// by value: a select between references would put the operands in memory
+template <typename T>
+__device__ inline T pick3(int a, T x0, T x1, T x2) {
+  return a == 0 ? x0 : (a == 1 ? x1 : x2);
+}
 struct Cand {
   float s;
   int j;
@@ -797,6 +805,53 @@ __device__ inline int select_active(const uint32_t* mask, int nw, int rank) {
   uint64_t b = __ballot(found >= 0);
   const int src = __ffsll((unsigned long long)b) - 1;
   return __shfl(found, src);
+}
+
+// Top-2 (k = 3) or top-1 (k = 2) candidate of a wave through DPP row shifts (inclusive inside
+// each row of 16 lanes, disjoint sets at every step) and the four row results read back with
+// readlane.  Every lane must be active; all lanes return the same result.
+template <int CTRL>
+__device__ inline Cand dpp_cand(Cand v) {
+  Cand o;
+  o.s = __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(__builtin_bit_cast(int, -1.f),
+                                                              __builtin_bit_cast(int, v.s), CTRL,
+                                                              0xf, 0xf, false));
+  o.j = __builtin_amdgcn_update_dpp(INT_MAX, v.j, CTRL, 0xf, 0xf, false);
+  return o;
+}
+template <int K, int CTRL>
+__device__ inline void top_step(Cand& b1, Cand& b2) {
+  const Cand o1 = dpp_cand<CTRL>(b1);
+  if (K == 3) {
+    const Cand o2 = dpp_cand<CTRL>(b2);
+    merge2(b1, b2, o1, o2);
+  } else {
+    const bool t = better(o1, b1);
+    b1.s = t ? o1.s : b1.s;
+    b1.j = t ? o1.j : b1.j;
+  }
+}
+__device__ inline Cand readlane_cand(Cand v, int l) {
+  return Cand{pmmf_readlane_f(v.s, l), __builtin_amdgcn_readlane(v.j, l)};
+}
+template <int K>
+__device__ inline void wave_top(Cand& b1, Cand& b2) {
+  top_step<K, 0x111>(b1, b2);
+  top_step<K, 0x112>(b1, b2);
+  top_step<K, 0x114>(b1, b2);
+  top_step<K, 0x118>(b1, b2);
+  Cand r1 = readlane_cand(b1, 15), r2 = readlane_cand(b2, 15);
+#pragma unroll
+  for (int rr = 1; rr < 4; ++rr) {
+    const Cand o1 = readlane_cand(b1, 16 * rr + 15);
+    if (K == 3) {
+      merge2(r1, r2, o1, readlane_cand(b2, 16 * rr + 15));
+    } else if (better(o1, r1)) {
+      r1 = o1;
+    }
+  }
+  b1 = r1;
+  b2 = r2;
 }
 
 // new value of slot a of a rotated (G, D) pair: sum_b O[a][b] v[b], in one fixed order so that
@@ -873,15 +928,28 @@ __global__ void __launch_bounds__(NT) k_find(FindArgs A, int cmax) {
   __syncthreads();
   int i = r > 0 ? sh_i : 0;
   int e_prev = -1;
+  // column stores of the previous step, issued during this step's rotation (see below): their
+  // values, which of them are real, the T they belong to and that step's retiree, whose column
+  // is dead and takes the lanes with nothing to store
+  float2 cst[3][PER];
+  uint64_t cmask = 0;
+  int tq0 = -1, tq1 = -1, tq2 = -1, edead = -1;
+  int jl[PER];  // this thread's columns, clamped into the cluster for address forming
   float2 cur[PER];
 #pragma unroll
   for (int q = 0; q < PER; ++q) {
     const int j = tid + q * NT;
+    jl[q] = min(j, c - 1);
     cur[q] = (r > 0 && j < c) ? GD[(size_t)i * c + j] : make_float2(0.f, 0.f);
+#pragma unroll
+    for (int a = 0; a < 3; ++a) cst[a][q] = make_float2(0.f, 0.f);
   }
 
-  for (int s = 0; s < r; ++s) {
-    float2* R0 = rowbuf + (size_t)(s & 1) * cmax;
+  // scoring of a step's seed row (held in cur): written to R0 of that step's parity, partner
+  // scores reduced per wave.  Called at the end of the previous step, so the wait for the seed
+  // row's load is counted against the stores issued after it rather than a full drain.
+  auto score_seed = [&](int sn) {
+    float2* R0s = rowbuf + (size_t)(sn & 1) * cmax;
     // the seed's (G, D) row; partner scores |G_ij| / sqrt(G_jj) over the active set, top (k - 1),
     // lower j on ties
     Cand b1{-1.f, INT_MAX}, b2{-1.f, INT_MAX};
@@ -889,7 +957,7 @@ __global__ void __launch_bounds__(NT) k_find(FindArgs A, int cmax) {
     for (int q = 0; q < PER; ++q) {
       const int j = tid + q * NT;
       if (j < c) {
-        R0[j] = cur[q];
+        R0s[j] = cur[q];
         const bool act = ((mask[j >> 5] >> (j & 31)) & 1u) && j != e_prev;
         if (act && j != i) {
           const float gd = gdiag[j];
@@ -901,16 +969,12 @@ __global__ void __launch_bounds__(NT) k_find(FindArgs A, int cmax) {
         }
       }
     }
-    for (int ofs = PMMF_WAVE / 2; ofs > 0; ofs >>= 1) {
-      Cand o1{__shfl_xor(b1.s, ofs), __shfl_xor(b1.j, ofs)};
-      if (kk == 3) {
-        Cand o2{__shfl_xor(b2.s, ofs), __shfl_xor(b2.j, ofs)};
-        merge2(b1, b2, o1, o2);
-      } else if (better(o1, b1)) {
-        b1 = o1;
-      }
-    }
+    wave_top<K>(b1, b2);
     if (pmmf_lane() == 0) { red1[pmmf_wave()] = b1; red2[pmmf_wave()] = b2; }
+  };
+  if (r > 0) score_seed(0);
+  for (int s = 0; s < r; ++s) {
+    float2* R0 = rowbuf + (size_t)(s & 1) * cmax;
     __syncthreads();  // A
     // every thread merges the per-wave winners
     Cand f1 = red1[0], f2 = red2[0];
@@ -925,8 +989,12 @@ __global__ void __launch_bounds__(NT) k_find(FindArgs A, int cmax) {
     }
     const int t0 = i, t1 = f1.j, t2 = kk == 3 ? f2.j : -1;
 
+    // The previous step's column stores (entries (j, T_{s-1}) of rows outside T_{s-1}) may still
+    // be in flight: such an entry is read at its transpose (T_{s-1}[b], j), stored with the rows
+    // T_{s-1} before barrier A and equal to it.  Everything older was stored before barrier B of
+    // the previous step.
+    const int st1 = slot_of(t1, tq0, tq1, tq2), st2 = kk == 3 ? slot_of(t2, tq0, tq1, tq2) : -1;
     // the (t1, t2) entries first (lane 0 needs them before anything else), then the partner rows
-    // of GD and rows T of Q
     float2 x12 = make_float2(0.f, 0.f), x21 = make_float2(0.f, 0.f);
     if (kk == 3 && tid < PMMF_WAVE) {
       x12 = GD[(size_t)t1 * c + t2];
@@ -936,12 +1004,29 @@ __global__ void __launch_bounds__(NT) k_find(FindArgs A, int cmax) {
 #pragma unroll
     for (int q = 0; q < PER; ++q) {
       const int j = tid + q * NT;
-      p1[q] = p2[q] = make_float2(0.f, 0.f);
-      if (j < c) {
-        p1[q] = GD[(size_t)t1 * c + j];
-        if (kk == 3) p2[q] = GD[(size_t)t2 * c + j];
-      }
+      const int sj = slot_of(j, tq0, tq1, tq2);
+      const uint32_t jq = (uint32_t)jl[q];
+      p1[q] = GD[(sj >= 0 && st1 < 0) ? (uint32_t)(j * c + t1) : (uint32_t)(t1 * c) + jq];
+      p2[q] = kk == 3 ? GD[(sj >= 0 && st2 < 0) ? (uint32_t)(j * c + t2) : (uint32_t)(t2 * c) + jq]
+                      : make_float2(0.f, 0.f);
     }
+    // the previous step's column stores, after this step's loads (wave 0 issues its share after
+    // lane 0's rotation); a lane with no real entry writes into the dead row of that step's
+    // retiree, contiguous across the wave.  Branch-free, so a wait for the loads above does not
+    // wait for these stores.
+    auto column_stores = [&]() {
+#pragma unroll
+      for (int q = 0; q < PER; ++q) {
+        const int j = tid + q * NT;
+#pragma unroll
+        for (int a = 0; a < K; ++a) {
+          const int ta = a == 0 ? tq0 : (a == 1 ? tq1 : tq2);
+          const bool real = (cmask >> (a * PER + q)) & 1ull;
+          GD[real ? (uint32_t)(j * c + ta) : (uint32_t)(edead * c + jl[q])] = cst[a][q];
+        }
+      }
+    };
+    if (s > 0 && pmmf_wave() != 0) column_stores();
 
     if (tid == 0) {
       double g[3][3] = {}, d[3][3] = {}, O[3][3] = {};
@@ -958,8 +1043,11 @@ __global__ void __launch_bounds__(NT) k_find(FindArgs A, int cmax) {
         const float2 s02 = R0[t2];
         g[0][2] = g[2][0] = s02.x;
         d[0][2] = d[2][0] = s02.y;
-        const double g12 = 0.5 * ((double)x12.x + (double)x21.x);
-        const double d12 = 0.5 * ((double)x12.y + (double)x21.y);
+        // an entry whose column is in T_{s-1} and row is not may be stale: take its transpose
+        const bool fresh12 = st1 >= 0 || st2 < 0, fresh21 = st2 >= 0 || st1 < 0;
+        const float2 y12 = fresh12 ? x12 : x21, y21 = fresh21 ? x21 : x12;
+        const double g12 = 0.5 * ((double)y12.x + (double)y21.x);
+        const double d12 = 0.5 * ((double)y12.y + (double)y21.y);
         g[1][2] = g[2][1] = g12;
         d[1][2] = d[2][1] = d12;
       }
@@ -1062,6 +1150,7 @@ __global__ void __launch_bounds__(NT) k_find(FindArgs A, int cmax) {
         if (kk == 3) R2[j] = p2[q];
       }
     }
+    if (s > 0 && pmmf_wave() == 0) column_stores();
     __syncthreads();  // B
 
     float o_[9];
@@ -1071,13 +1160,15 @@ __global__ void __launch_bounds__(NT) k_find(FindArgs A, int cmax) {
     const bool more = s + 1 < r;
     const int nxt = more ? (sh_c0 < e ? sh_c0 : sh_c1) : -1;
     const int aslot = nxt == t0 ? 0 : (nxt == t1 ? 1 : ((kk == 3 && nxt == t2) ? 2 : -1));
-    float2 nrow[PER];
-#pragma unroll
-    for (int q = 0; q < PER; ++q) {
-      const int j = tid + q * NT;
-      nrow[q] = make_float2(0.f, 0.f);
-      if (more && aslot < 0 && j < c) nrow[q] = GD[(size_t)nxt * c + j];
+    const int Tt[3] = {t0, t1, t2};
+    if (tid < kk * kk) {
+      const int a = tid / kk, b = tid % kk;
+      GD[(size_t)Tt[a] * c + Tt[b]] = make_float2(sh_gn[a * 3 + b], sh_dn[a * 3 + b]);
     }
+    float2 nrow[PER];
+    const uint32_t nb = (uint32_t)((more && aslot < 0 ? nxt : 0) * c);
+#pragma unroll
+    for (int q = 0; q < PER; ++q) nrow[q] = GD[nb + (uint32_t)jl[q]];
     // pre-rotation values of rows T at column nxt (used when nxt is not in T)
     float2 vn[3] = {make_float2(0.f, 0.f), make_float2(0.f, 0.f), make_float2(0.f, 0.f)};
     if (more && aslot < 0) {
@@ -1087,42 +1178,46 @@ __global__ void __launch_bounds__(NT) k_find(FindArgs A, int cmax) {
     }
     if (tid == 0) mask[e >> 5] &= ~(1u << (e & 31));
 
-    // stores: GD <- O GD O^T on rows/columns T (active columns only: retired columns are never
-    // read again)
-    const int Tt[3] = {t0, t1, t2};
-    if (tid < kk * kk) {
-      const int a = tid / kk, b = tid % kk;
-      GD[(size_t)Tt[a] * c + Tt[b]] = make_float2(sh_gn[a * 3 + b], sh_dn[a * 3 + b]);
-    }
+    // stores: GD <- O GD O^T on rows T now (the k x k block above; a column in T or beyond the
+    // cluster writes into the dead column of this step's retiree, and a retired column's entry
+    // is dead too), columns T during the next step's rotation
+    cmask = 0;
 #pragma unroll
     for (int q = 0; q < PER; ++q) {
       const int j = tid + q * NT;
-      if (j >= c) continue;
-      const int bj = j == t0 ? 0 : (j == t1 ? 1 : ((kk == 3 && j == t2) ? 2 : -1));
-      if (bj >= 0) {
-        // column j is in T: the next seed row's entry there
-        if (more) {
-          if (aslot >= 0) nrow[q] = make_float2(sh_gn[aslot * 3 + bj], sh_dn[aslot * 3 + bj]);
-          else nrow[q] = rot_entry<K>(o_, bj, vn);
-        }
-        continue;
-      }
-      const bool a_now = (mask[j >> 5] >> (j & 31)) & 1u;
-      if (!a_now) continue;
+      const int bj = slot_of(j, t0, t1, t2);
+      const bool in = j < c && bj < 0;
+      const bool a_now = in && ((mask[j >> 5] >> (j & 31)) & 1u);
       const float2 v[3] = {cur[q], p1[q], p2[q]};
+      float2 nv[3] = {make_float2(0.f, 0.f), make_float2(0.f, 0.f), make_float2(0.f, 0.f)};
 #pragma unroll
       for (int a = 0; a < K; ++a) {
-        const float2 nv = rot_entry<K>(o_, a, v);
-        GD[(size_t)Tt[a] * c + j] = nv;
-        if (nv.x != 0.f || nv.y != 0.f || v[a].x != 0.f || v[a].y != 0.f)
-          GD[(size_t)j * c + Tt[a]] = nv;
-        if (a == aslot) nrow[q] = nv;
+        nv[a] = rot_entry<K>(o_, a, v);
+        GD[(uint32_t)(Tt[a] * c) + (uint32_t)(in ? j : e)] = nv[a];
+        cst[a][q] = nv[a];
+        const uint32_t m = __float_as_uint(nv[a].x) | __float_as_uint(nv[a].y) |
+                           __float_as_uint(v[a].x) | __float_as_uint(v[a].y);
+        cmask |= (uint64_t)(a_now && (m << 1) != 0u) << (a * PER + q);
+      }
+      // the next seed row at column j
+      if (more) {
+        if (bj >= 0) {
+          nrow[q] = aslot >= 0 ? make_float2(sh_gn[aslot * 3 + bj], sh_dn[aslot * 3 + bj])
+                               : rot_entry<K>(o_, bj, vn);
+        } else if (aslot >= 0) {
+          nrow[q] = pick3(aslot, nv[0], nv[1], nv[2]);
+        }
       }
     }
+    tq0 = t0;
+    tq1 = t1;
+    tq2 = t2;
+    edead = e;
 #pragma unroll
     for (int q = 0; q < PER; ++q) cur[q] = nrow[q];
     e_prev = e;
     i = nxt;
+    if (more) score_seed(s + 1);
   }
 }
 
