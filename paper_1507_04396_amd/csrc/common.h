@@ -94,6 +94,33 @@ __device__ inline int pmmf_wave_incl_scan(int v) {
   return v;
 }
 
+// inclusive prefix sum over the lanes of a wave through DPP (row shifts inside rows of 16, then
+// the row totals broadcast into the following rows): no LDS traffic.  Every lane must be active.
+__device__ inline int pmmf_wave_incl_scan_dpp(int v) {
+  v += __builtin_amdgcn_update_dpp(0, v, 0x111, 0xf, 0xf, false);  // row_shr:1
+  v += __builtin_amdgcn_update_dpp(0, v, 0x112, 0xf, 0xf, false);  // row_shr:2
+  v += __builtin_amdgcn_update_dpp(0, v, 0x114, 0xf, 0xf, false);  // row_shr:4
+  v += __builtin_amdgcn_update_dpp(0, v, 0x118, 0xf, 0xf, false);  // row_shr:8
+  v += __builtin_amdgcn_update_dpp(0, v, 0x142, 0xa, 0xf, false);  // row_bcast:15 -> rows 1, 3
+  v += __builtin_amdgcn_update_dpp(0, v, 0x143, 0xc, 0xf, false);  // row_bcast:31 -> rows 2, 3
+  return v;
+}
+
+// position of the n-th (0-based) set bit of m, n < popcount(m): binary search on popcounts
+__device__ inline int pmmf_nth_bit(uint32_t m, int n) {
+  int pos = 0;
+#pragma unroll
+  for (int w = 16; w > 0; w >>= 1) {
+    const uint32_t lo = m & ((1u << w) - 1u);
+    const int pc = __popc(lo);
+    const bool up = n >= pc;
+    n -= up ? pc : 0;
+    m = up ? (m >> w) : lo;
+    pos += up ? w : 0;
+  }
+  return pos;
+}
+
 // Number of set bits of a 64-bit ballot below this lane.
 __device__ inline int pmmf_lanes_below(uint64_t mask) {
   const int lane = pmmf_lane();

@@ -747,6 +747,38 @@ __device__ inline void rot3f(const double (&g)[3][3], double (&O)[3][3], double&
 
 // ------------------------------------------------------------------------------------------
 // Randomized greedy rotation search inside one cluster (Alg. 2), one workgroup per cluster.
+// rank-th, (rank+1)-th and (rank+2)-th set bits of the active bitmask in LDS (-1 where absent);
+// called by one whole wave
+__device__ inline void select_active3(const uint32_t* mask, int nw, int rank, int (&out)[3]) {
+  const int lane = pmmf_lane();
+  const int wpl = (nw + PMMF_WAVE - 1) / PMMF_WAVE;
+  const int w0 = lane * wpl;
+  int cnt = 0;
+  for (int t = 0; t < wpl; ++t) {
+    const int wi = w0 + t;
+    if (wi < nw) cnt += __popc(mask[wi]);
+  }
+  const int incl = pmmf_wave_incl_scan_dpp(cnt);
+  int base = incl - cnt;
+  int f[3] = {-1, -1, -1};
+  for (int t = 0; t < wpl; ++t) {
+    const int wi = w0 + t;
+    const uint32_t m = wi < nw ? mask[wi] : 0u;
+    const int pc = __popc(m);
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+      const int want = rank + d - base;
+      if (want >= 0 && want < pc) f[d] = wi * 32 + pmmf_nth_bit(m, want);
+    }
+    base += pc;
+  }
+#pragma unroll
+  for (int d = 0; d < 3; ++d) {
+    const uint64_t bb = __ballot(f[d] >= 0);
+    out[d] = bb ? __shfl(f[d], __ffsll((unsigned long long)bb) - 1) : -1;
+  }
+}
+
 __device__ inline int slot_of(int j, int t0, int t1, int t2) {
   return j == t0 ? 0 : (j == t1 ? 1 : (j == t2 ? 2 : -1));
 }
@@ -892,9 +924,10 @@ __global__ void __launch_bounds__(NT) k_find(FindArgs A, int cmax) {
   float2* rowbuf = reinterpret_cast<float2*>(ddiag + cmax);  // seed rows (2 parities), partners
   int* lgid = reinterpret_cast<int*>(rowbuf + 4 * (size_t)cmax);
   uint32_t* mask = reinterpret_cast<uint32_t*>(lgid + cmax);
+  float* gsq = reinterpret_cast<float*>(mask + (cmax + 31) / 32);  // sqrt(G_jj), for the scores
   constexpr int NW = NT / PMMF_WAVE;
   __shared__ Cand red1[NW], red2[NW];
-  __shared__ int sh_i, sh_e, sh_c0, sh_c1;
+  __shared__ int sh_i, sh_e, sh_c0, sh_c1, sh_k[3];
   __shared__ float sh_O[9], sh_gn[9], sh_dn[9];
 
   const int tid = threadIdx.x;
@@ -912,6 +945,7 @@ __global__ void __launch_bounds__(NT) k_find(FindArgs A, int cmax) {
   for (int j = tid; j < c; j += NT) {
     const float2 dg = GD[(size_t)j * c + j];
     gdiag[j] = dg.x;
+    gsq[j] = sqrtf(dg.x);
     ddiag[j] = dg.y;
     lgid[j] = A.gid[o + j];
   }
@@ -924,6 +958,13 @@ __global__ void __launch_bounds__(NT) k_find(FindArgs A, int cmax) {
     const uint64_t h = pmmf_hash4(A.seed, PMMF_TAG_SEED_ROW, (uint64_t)A.p, (uint64_t)u, 0);
     const int i0 = select_active(mask, nw, (int)pmmf_mulhi(h, (uint64_t)c));
     if (tid == 0) sh_i = i0;
+    if (r > 1) {  // the two candidates for the second seed (see the next-seed rule below)
+      const uint64_t h1 = pmmf_hash4(A.seed, PMMF_TAG_SEED_ROW, (uint64_t)A.p, (uint64_t)u, 1);
+      const int rank1 = (int)pmmf_mulhi(h1, (uint64_t)(c - 1));
+      const int c0 = select_active(mask, nw, rank1);
+      const int c1 = select_active(mask, nw, rank1 + 1);
+      if (tid == 0) { sh_c0 = c0; sh_c1 = c1; }
+    }
   }
   __syncthreads();
   int i = r > 0 ? sh_i : 0;
@@ -935,6 +976,9 @@ __global__ void __launch_bounds__(NT) k_find(FindArgs A, int cmax) {
   uint64_t cmask = 0;
   int tq0 = -1, tq1 = -1, tq2 = -1, edead = -1;
   int jl[PER];  // this thread's columns, clamped into the cluster for address forming
+  // candidates for the next seed (their rows are loaded during this step's rotation)
+  int cc0 = r > 1 ? sh_c0 : 0, cc1 = r > 1 ? sh_c1 : 0;
+  float2 c0r[PER], c1r[PER];
   float2 cur[PER];
 #pragma unroll
   for (int q = 0; q < PER; ++q) {
@@ -960,8 +1004,8 @@ __global__ void __launch_bounds__(NT) k_find(FindArgs A, int cmax) {
         R0s[j] = cur[q];
         const bool act = ((mask[j >> 5] >> (j & 31)) & 1u) && j != e_prev;
         if (act && j != i) {
-          const float gd = gdiag[j];
-          float sc = gd > 0.f ? fabsf(cur[q].x) / sqrtf(gd) : 0.f;
+          const float gq = gsq[j];  // > 0 exactly when G_jj > 0
+          float sc = gq > 0.f ? fabsf(cur[q].x) / gq : 0.f;
           if (!(sc >= 0.f)) sc = 0.f;  // NaN from an overflowed Gram entry scores 0
           Cand cnd{sc, j};
           if (better(cnd, b1)) { b2 = b1; b1 = cnd; }
@@ -1027,6 +1071,22 @@ __global__ void __launch_bounds__(NT) k_find(FindArgs A, int cmax) {
       }
     };
     if (s > 0 && pmmf_wave() != 0) column_stores();
+    // the rows of the two candidates for the next seed, read the same way (their entries at T
+    // are re-formed after this step's rotation); issued after the stores, as nothing before
+    // barrier B needs them
+    // (k = 2 only: with k = 3 the extra loads delay the lane-0 entries more than the prefetch
+    // saves after barrier B)
+    if constexpr (K == 2) {
+      const int sc0 = slot_of(cc0, tq0, tq1, tq2), sc1 = slot_of(cc1, tq0, tq1, tq2);
+#pragma unroll
+      for (int q = 0; q < PER; ++q) {
+        const int j = tid + q * NT;
+        const int sj = slot_of(j, tq0, tq1, tq2);
+        const uint32_t jq = (uint32_t)jl[q];
+        c0r[q] = GD[(sj >= 0 && sc0 < 0) ? (uint32_t)(j * c + cc0) : (uint32_t)(cc0 * c) + jq];
+        c1r[q] = GD[(sj >= 0 && sc1 < 0) ? (uint32_t)(j * c + cc1) : (uint32_t)(cc1 * c) + jq];
+      }
+    }
 
     if (tid == 0) {
       double g[3][3] = {}, d[3][3] = {}, O[3][3] = {};
@@ -1101,9 +1161,12 @@ __global__ void __launch_bounds__(NT) k_find(FindArgs A, int cmax) {
       ddiag[t0] = (float)dn[0][0];
       gdiag[t1] = (float)gn[1][1];
       ddiag[t1] = (float)dn[1][1];
+      gsq[t0] = sqrtf((float)gn[0][0]);
+      gsq[t1] = sqrtf((float)gn[1][1]);
       if (kk == 3) {
         gdiag[t2] = (float)gn[2][2];
         ddiag[t2] = (float)dn[2][2];
+        gsq[t2] = sqrtf((float)gn[2][2]);
       }
       sh_e = e;
 #pragma unroll
@@ -1131,15 +1194,16 @@ __global__ void __launch_bounds__(NT) k_find(FindArgs A, int cmax) {
       A.rot_lit[ridx] = 2.0 * off2e;
       A.hdiag[lgid[e]] = (float)dee;
       A.retflag[o + e] = 1;
-    } else if (tid >= PMMF_WAVE && tid < 2 * PMMF_WAVE && s + 1 < r) {
-      // next seed: the rank-th active index after this step's retirement is the rank-th one
-      // now if that lies below the retiree, else the (rank + 1)-th
+    } else if (tid >= PMMF_WAVE && tid < 2 * PMMF_WAVE && s + 2 < r) {
+      // next-seed rule: the rank-th active index after a retirement e is the rank-th one before
+      // it if that lies below e, else the (rank + 1)-th.  The seed of step s+2 is picked after
+      // two more retirements (e_s, e_{s+1}), so the (rank + m)-th indices, m < 3, are taken now;
+      // after this step the two candidates for it follow, after the next step the seed.
       const uint64_t h = pmmf_hash4(A.seed, PMMF_TAG_SEED_ROW, (uint64_t)A.p, (uint64_t)u,
-                                    (uint64_t)(s + 1));
-      const int rank = (int)pmmf_mulhi(h, (uint64_t)(c - s - 1));
-      const int c0 = select_active(mask, nw, rank);
-      const int c1 = select_active(mask, nw, rank + 1);
-      if (tid == PMMF_WAVE) { sh_c0 = c0; sh_c1 = c1; }
+                                    (uint64_t)(s + 2));
+      int k3[3];
+      select_active3(mask, nw, (int)pmmf_mulhi(h, (uint64_t)(c - s - 2)), k3);
+      if (tid == PMMF_WAVE) { sh_k[0] = k3[0]; sh_k[1] = k3[1]; sh_k[2] = k3[2]; }
     }
     // pre-rotation partner rows, for re-forming the next seed row's entries at T
 #pragma unroll
@@ -1158,7 +1222,7 @@ __global__ void __launch_bounds__(NT) k_find(FindArgs A, int cmax) {
     for (int a = 0; a < 9; ++a) o_[a] = sh_O[a];
     const int e = sh_e;
     const bool more = s + 1 < r;
-    const int nxt = more ? (sh_c0 < e ? sh_c0 : sh_c1) : -1;
+    const int nxt = more ? (cc0 < e ? cc0 : cc1) : -1;
     const int aslot = nxt == t0 ? 0 : (nxt == t1 ? 1 : ((kk == 3 && nxt == t2) ? 2 : -1));
     const int Tt[3] = {t0, t1, t2};
     if (tid < kk * kk) {
@@ -1166,9 +1230,19 @@ __global__ void __launch_bounds__(NT) k_find(FindArgs A, int cmax) {
       GD[(size_t)Tt[a] * c + Tt[b]] = make_float2(sh_gn[a * 3 + b], sh_dn[a * 3 + b]);
     }
     float2 nrow[PER];
-    const uint32_t nb = (uint32_t)((more && aslot < 0 ? nxt : 0) * c);
+    if constexpr (K == 2) {
 #pragma unroll
-    for (int q = 0; q < PER; ++q) nrow[q] = GD[nb + (uint32_t)jl[q]];
+      for (int q = 0; q < PER; ++q) nrow[q] = nxt == cc0 ? c0r[q] : c1r[q];
+    } else {
+      const uint32_t nb = (uint32_t)((more && aslot < 0 ? nxt : 0) * c);
+#pragma unroll
+      for (int q = 0; q < PER; ++q) nrow[q] = GD[nb + (uint32_t)jl[q]];
+    }
+    if (s + 2 < r) {  // candidates for the seed of step s+2
+      const int k0 = sh_k[0], k1 = sh_k[1], k2 = sh_k[2];
+      cc0 = k0 < e ? k0 : k1;
+      cc1 = k1 < e ? k1 : k2;
+    }
     // pre-rotation values of rows T at column nxt (used when nxt is not in T)
     float2 vn[3] = {make_float2(0.f, 0.f), make_float2(0.f, 0.f), make_float2(0.f, 0.f)};
     if (more && aslot < 0) {
@@ -1222,7 +1296,8 @@ __global__ void __launch_bounds__(NT) k_find(FindArgs A, int cmax) {
 }
 
 template <int NT, int PER, int K>
-static hipError_t find_launch(const FindArgs& a, int m, int cmax, size_t lds, hipStream_t s) {
+static hipError_t find_launch(const FindArgs& a, int m, int cmax, size_t lds0, hipStream_t s) {
+  const size_t lds = lds0 + (size_t)cmax * sizeof(float);  // + sqrt(G_jj)
   if (lds > 64 * 1024) {
     hipError_t e = hipFuncSetAttribute((const void*)&k_find<NT, PER, K>,
                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
