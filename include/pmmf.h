@@ -281,6 +281,18 @@ int mmf_spmm(int64_t n, const int64_t* d_rowptr, const int32_t* d_colind, const 
 /* Free the handle and all device memory it owns (synchronizes its stream). */
 int mmf_destroy(mmf_handle h);
 
+/* Device memory of every later allocation of the library (handles, workspaces, PCG buffers):
+ *   alloc(bytes, stream, ctx) returns device memory for use on `stream` (NULL on failure, reported
+ *   as MMF_ENOMEM); release(ptr, stream, ctx) takes back a block with the stream it was allocated
+ *   for.  The library waits for the device before it releases a block (as hipFree does), so an
+ *   allocator that reuses memory in stream order (e.g. a caching allocator) never hands out memory
+ *   still in use on another stream.  Blocks keep the allocator that produced them: a later call
+ *   does not change how existing blocks are released.  Both NULL restores hipMalloc/hipFree.
+ *   Process-wide; set it before creating handles that should use it.
+ *   Errors: MMF_EINVAL when exactly one of alloc and release is NULL. */
+int mmf_set_allocator(void* (*alloc)(size_t bytes, void* stream, void* ctx),
+                      void (*release)(void* ptr, void* stream, void* ctx), void* ctx);
+
 /* Thread-local text of the last error reported on this thread ("" if none). */
 const char* mmf_last_error(void);
 

@@ -59,6 +59,9 @@ P = ctypes.c_void_p
 I64 = ctypes.c_int64
 I32 = ctypes.c_int32
 H = ctypes.c_void_p
+# mmf_set_allocator callbacks: alloc(bytes, stream, ctx) -> ptr, release(ptr, stream, ctx)
+ALLOC_FN = ctypes.CFUNCTYPE(ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p, ctypes.c_void_p)
+RELEASE_FN = ctypes.CFUNCTYPE(None, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p)
 
 SIGNATURES = {
     "mmf_factor": [I64, I64, P, P, P, ctypes.POINTER(mmf_params), P, ctypes.POINTER(H)],
@@ -80,6 +83,7 @@ SIGNATURES = {
     "mmf_graph_launch": [H, P],
     "mmf_graph_destroy": [H],
     "mmf_destroy": [H],
+    "mmf_set_allocator": [ALLOC_FN, RELEASE_FN, P],
     "mmf_last_error": [],
 }
 

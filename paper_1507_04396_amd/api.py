@@ -15,6 +15,33 @@ from . import _lib
 from ._lib import MMFError, check  # noqa: F401
 
 
+# every callback pair ever installed stays referenced: blocks remember the release function that
+# belongs to them, so it must outlive them even after the allocator is switched back
+_ALLOCATORS = []
+
+
+def use_torch_allocator(enable: bool = True) -> None:
+    """Route the library's later device allocations through torch's caching allocator
+    (mmf_set_allocator); ``enable=False`` restores hipMalloc/hipFree for later allocations."""
+    lib = _lib.load()
+    if not enable:
+        check(lib.mmf_set_allocator(_lib.ALLOC_FN(), _lib.RELEASE_FN(), None))
+        return
+
+    def alloc(nbytes, stream, ctx):
+        try:
+            return torch.cuda.caching_allocator_alloc(int(nbytes), stream=int(stream or 0))
+        except Exception:  # reported by the library as MMF_ENOMEM
+            return None
+
+    def release(ptr, stream, ctx):
+        torch.cuda.caching_allocator_delete(int(ptr))
+
+    pair = (_lib.ALLOC_FN(alloc), _lib.RELEASE_FN(release))
+    _ALLOCATORS.append(pair)
+    check(lib.mmf_set_allocator(pair[0], pair[1], None))
+
+
 def _stream(stream=None) -> ctypes.c_void_p:
     s = stream if stream is not None else torch.cuda.current_stream()
     return ctypes.c_void_p(s.cuda_stream)

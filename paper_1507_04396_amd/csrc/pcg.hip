@@ -8,6 +8,7 @@
 #include <vector>
 
 #include "common.h"
+#include "dev_alloc.h"
 #include "pmmf.h"
 
 namespace pmmf {
@@ -147,12 +148,11 @@ namespace {
 
 struct Buf {
   void* p = nullptr;
-  explicit Buf(size_t bytes) {
-    if (hipMalloc(&p, std::max<size_t>(bytes, 16)) != hipSuccess) p = nullptr;
-  }
-  ~Buf() {
-    if (p) (void)hipFree(p);
-  }
+  pmmf_alloc::How how;
+  explicit Buf(size_t bytes) { p = pmmf_alloc::alloc(std::max<size_t>(bytes, 16), &how); }
+  ~Buf() { pmmf_alloc::release(p, how); }
+  Buf(const Buf&) = delete;
+  Buf& operator=(const Buf&) = delete;
   template <class T> T* as() const { return reinterpret_cast<T*>(p); }
 };
 
@@ -185,6 +185,7 @@ extern "C" int mmf_pcg(mmf_handle h, int64_t n, const int64_t* d_rowptr, const i
     if (rc != MMF_OK) return rc;
     if (inf.n != n) throw PcgErr{MMF_EINVAL, "the factorization has another dimension"};
     hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    pmmf_alloc::StreamScope alloc_scope(stream);
     const int64_t ld = nrhs, N = n * nrhs;
     hipEvent_t e0, e1;
     chk(hipEventCreate(&e0), "event");

@@ -18,8 +18,60 @@
 #include <rocblas/rocblas.h>
 #include <rocsolver/rocsolver.h>
 
+#include "dev_alloc.h"
 #include "factor_kernels.h"
 #include "sweep_kernels.h"
+
+namespace pmmf_alloc {
+namespace {
+std::mutex g_mu;
+void* (*g_alloc)(size_t, void*, void*) = nullptr;
+void (*g_release)(void*, void*, void*) = nullptr;
+void* g_ctx = nullptr;
+thread_local void* g_stream = nullptr;
+}  // namespace
+
+void* alloc(size_t bytes, How* how) {
+  void* (*a)(size_t, void*, void*);
+  void (*r)(void*, void*, void*);
+  void* ctx;
+  {
+    std::lock_guard<std::mutex> lk(g_mu);
+    a = g_alloc;
+    r = g_release;
+    ctx = g_ctx;
+  }
+  if (a) {
+    how->release = r;
+    how->ctx = ctx;
+    how->stream = g_stream;
+    return a(bytes, g_stream, ctx);
+  }
+  *how = How{};
+  void* p = nullptr;
+  return hipMalloc(&p, bytes) == hipSuccess ? p : nullptr;
+}
+
+void release(void* p, const How& how) {
+  if (!p) return;
+  if (how.release) {
+    (void)hipDeviceSynchronize();
+    how.release(p, how.stream, how.ctx);
+  } else {
+    (void)hipFree(p);
+  }
+}
+
+StreamScope::StreamScope(void* stream) : prev(g_stream) { g_stream = stream; }
+StreamScope::~StreamScope() { g_stream = prev; }
+
+void set(void* (*a)(size_t, void*, void*), void (*r)(void*, void*, void*), void* ctx) {
+  std::lock_guard<std::mutex> lk(g_mu);
+  g_alloc = a;
+  g_release = r;
+  g_ctx = ctx;
+}
+}  // namespace pmmf_alloc
 
 namespace {
 
@@ -44,12 +96,13 @@ void hipchk(hipError_t e, const char* what) {
 struct DBuf {
   void* p = nullptr;
   size_t bytes = 0;
+  pmmf_alloc::How how;  // the allocator that produced p
   DBuf() = default;
   DBuf(const DBuf&) = delete;
   DBuf& operator=(const DBuf&) = delete;
   ~DBuf() { release(); }
   void release() {
-    if (p) (void)hipFree(p);
+    if (p) pmmf_alloc::release(p, how);
     p = nullptr;
     bytes = 0;
   }
@@ -57,13 +110,15 @@ struct DBuf {
     if (b <= bytes && p) return;
     release();
     if (b == 0) b = 16;
-    HIPCHK(hipMalloc(&p, b));
+    p = pmmf_alloc::alloc(b, &how);
+    if (!p) raise(MMF_ENOMEM, "device allocation of " + std::to_string(b) + " bytes failed");
     bytes = b;
   }
   template <class T> T* as() const { return reinterpret_cast<T*>(p); }
   void swap_with(DBuf& o) {
     std::swap(p, o.p);
     std::swap(bytes, o.bytes);
+    std::swap(how, o.how);
   }
 };
 
@@ -455,6 +510,17 @@ int pick_tile(const mmf_plan& h, int nv, int64_t nrhs) {
 // ------------------------------------------------------------------------------------------
 extern "C" const char* mmf_last_error(void) { return g_err.c_str(); }
 
+extern "C" int mmf_set_allocator(void* (*alloc)(size_t, void*, void*),
+                                 void (*release)(void*, void*, void*), void* ctx) {
+  g_err.clear();
+  if ((alloc == nullptr) != (release == nullptr)) {
+    g_err = "mmf_set_allocator: alloc and release must both be set or both be NULL";
+    return MMF_EINVAL;
+  }
+  pmmf_alloc::set(alloc, release, ctx);
+  return MMF_OK;
+}
+
 namespace pmmf_host_detail {
 void set_error(const std::string& msg) { g_err = msg; }
 }
@@ -494,6 +560,7 @@ extern "C" int mmf_factor(int64_t n, int64_t nnz, const int64_t* d_rowptr, const
   validate(n, p);
   if (nnz < 0 || (nnz > 0 && (!d_rowptr || !d_colind || !d_val)) || !d_rowptr)
     raise(MMF_EINVAL, "bad CSR arguments");
+  pmmf_alloc::StreamScope alloc_scope(stream);
   hipStream_t s = as_stream(stream);
   auto h = std::make_unique<mmf_plan>();
   h->n = n;
@@ -1180,6 +1247,7 @@ extern "C" int mmf_apply(mmf_handle hh, const float* d_x, float* d_y, int64_t nr
                          void* stream) {
   ABI_BEGIN
   mmf_plan& h = *checked(hh);
+  pmmf_alloc::StreamScope alloc_scope(stream);
   apply_impl(h, d_x, d_y, nrhs, ld, as_stream(stream), 0);
   return MMF_OK;
   ABI_END
@@ -1189,6 +1257,7 @@ extern "C" int mmf_apply_inverse(mmf_handle hh, const float* d_x, float* d_y, in
                                  int64_t ld, void* stream) {
   ABI_BEGIN
   mmf_plan& h = *checked(hh);
+  pmmf_alloc::StreamScope alloc_scope(stream);
   apply_impl(h, d_x, d_y, nrhs, ld, as_stream(stream), 1);
   return MMF_OK;
   ABI_END
@@ -1198,6 +1267,7 @@ extern "C" int mmf_apply_inverse_sqrt(mmf_handle hh, const float* d_x, float* d_
                                       int64_t ld, void* stream) {
   ABI_BEGIN
   mmf_plan& h = *checked(hh);
+  pmmf_alloc::StreamScope alloc_scope(stream);
   apply_impl(h, d_x, d_y, nrhs, ld, as_stream(stream), 2);
   return MMF_OK;
   ABI_END
@@ -1229,6 +1299,7 @@ extern "C" int mmf_graph_capture(mmf_handle hh, int32_t inverse, const float* d_
   mmf_plan& h = *checked(hh);
   if (!out || nrhs < 1 || ld < nrhs || !d_x || !d_y || d_x == d_y || inverse < 0 || inverse > 2)
     raise(MMF_EINVAL, "bad graph capture arguments");
+  pmmf_alloc::StreamScope alloc_scope(stream);
   hipStream_t s = as_stream(stream);
   std::unique_ptr<mmf_graph_s, void (*)(mmf_graph_s*)> G(new mmf_graph_s, graph_free);
   G->h = &h;
@@ -1434,6 +1505,7 @@ extern "C" int mmf_backward(mmf_handle hh, const float* d_x, const float* d_ybar
                             int64_t nrhs, int64_t ld, void* stream) {
   ABI_BEGIN
   mmf_plan& h = *checked(hh);
+  pmmf_alloc::StreamScope alloc_scope(stream);
   hipStream_t s = as_stream(stream);
   if (nrhs < 1 || ld < nrhs || !d_x || !d_ybar) raise(MMF_EINVAL, "bad vector arguments");
   if (d_theta_bar && h.k != 2) raise(MMF_EINVAL, "angle gradients exist only for k = 2");
@@ -1533,6 +1605,7 @@ extern "C" int mmf_import(int64_t n, int32_t k, int64_t core_size, int32_t num_s
                          !rot_o || !rot_retired))
     raise(MMF_EINVAL, "missing stage or rotation arrays");
   if (!hdiag || !core_ids || !hcore) raise(MMF_EINVAL, "missing H arrays");
+  pmmf_alloc::StreamScope alloc_scope(stream);
   hipStream_t s = as_stream(stream);
   auto h = std::make_unique<mmf_plan>();
   h->n = n;
@@ -1673,6 +1746,7 @@ extern "C" int mmf_param_ptrs(mmf_handle hh, float** theta, float** hdiag, float
 extern "C" int mmf_sync_angles(mmf_handle hh, void* stream) {
   ABI_BEGIN
   mmf_plan& h = *checked(hh);
+  pmmf_alloc::StreamScope alloc_scope(stream);
   hipStream_t s = as_stream(stream);
   h.inv_ready = false;
   h.isqrt_ready = false;
@@ -1690,6 +1764,7 @@ extern "C" int mmf_set_params(mmf_handle hh, const float* d_theta, const float* 
                               const float* d_hcore, void* stream) {
   ABI_BEGIN
   mmf_plan& h = *checked(hh);
+  pmmf_alloc::StreamScope alloc_scope(stream);
   hipStream_t s = as_stream(stream);
   if (d_theta && h.k != 2) raise(MMF_EINVAL, "angles exist only for k = 2");
   h.inv_ready = false;

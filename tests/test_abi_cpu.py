@@ -72,3 +72,11 @@ def test_handle_errors(lib):
     assert lib.mmf_get_info(None, ctypes.byref(inf)) == -7
     assert lib.mmf_destroy(None) == -7
     assert lib.mmf_apply(ctypes.c_void_p(12345), None, None, 1, 1, None) == -7
+
+
+def test_set_allocator_needs_both_functions_or_neither(lib):
+    from paper_1507_04396_amd import _lib
+    alloc = _lib.ALLOC_FN(lambda nbytes, stream, ctx: None)
+    assert lib.mmf_set_allocator(alloc, _lib.RELEASE_FN(), None) == -1
+    assert lib.mmf_last_error()
+    assert lib.mmf_set_allocator(_lib.ALLOC_FN(), _lib.RELEASE_FN(), None) == 0
