@@ -633,15 +633,18 @@ __device__ inline void rot3(const double (&g)[3][3], double (&O)[3][3], double& 
 // rounding is relative to their own size and the sweeps reach the threshold quadratically.
 __device__ inline void jacobi_pair_f(float (&A)[3][3], float (&V)[3][3], int p, int q, bool& rot) {
   const float apq = A[p][q];
-  if (fabsf(apq) <= 1e-8f * (fabsf(A[p][p]) + fabsf(A[q][q]))) {
+  // converged once the pivot is below FP32 resolution of the diagonal pair
+  if (fabsf(apq) <= 1e-7f * (fabsf(A[p][p]) + fabsf(A[q][q]))) {
     A[p][q] = A[q][p] = 0.f;
     return;
   }
   rot = true;
-  const float tau = (A[q][q] - A[p][p]) * __builtin_amdgcn_rcpf(2.f * apq);
-  const float sg = tau >= 0.f ? 1.f : -1.f;
-  const float r1 = fmaf(tau, tau, 1.f);
-  const float t = sg * __builtin_amdgcn_rcpf(fabsf(tau) + r1 * __builtin_amdgcn_rsqf(r1));
+  // t = tan(theta) = apq / (d + sign(d) sqrt(d^2 + apq^2)), d = (aqq - app) / 2 (the smaller
+  // root of t^2 + 2 (d / apq) t - 1 = 0)
+  const float d = 0.5f * (A[q][q] - A[p][p]);
+  const float h2 = fmaf(d, d, apq * apq);
+  const float den = fabsf(d) + h2 * __builtin_amdgcn_rsqf(h2);
+  const float t = (d >= 0.f ? apq : -apq) * __builtin_amdgcn_rcpf(den);
   const float c = __builtin_amdgcn_rsqf(fmaf(t, t, 1.f));
   const float s = t * c;
 #pragma unroll
@@ -1194,7 +1197,8 @@ __global__ void __launch_bounds__(NT) k_find(FindArgs A, int cmax) {
       A.rot_lit[ridx] = 2.0 * off2e;
       A.hdiag[lgid[e]] = (float)dee;
       A.retflag[o + e] = 1;
-    } else if (tid >= PMMF_WAVE && tid < 2 * PMMF_WAVE && s + 2 < r) {
+    }
+    if (tid >= PMMF_WAVE && tid < 2 * PMMF_WAVE && s + 2 < r) {
       // next-seed rule: the rank-th active index after a retirement e is the rank-th one before
       // it if that lies below e, else the (rank + 1)-th.  The seed of step s+2 is picked after
       // two more retirements (e_s, e_{s+1}), so the (rank + m)-th indices, m < 3, are taken now;
