@@ -482,3 +482,4 @@ def test_backward_matches_torch_autograd_fp64():
     np.testing.assert_allclose(xbar, xt.grad.numpy(), rtol=1e-10, atol=1e-10)
     np.testing.assert_allclose(hdbar[mask.numpy()], hd.grad.numpy()[mask.numpy()], atol=1e-10)
     np.testing.assert_allclose(hcbar, hc.grad.numpy(), atol=1e-10)
+

@@ -191,6 +191,18 @@ def gaussian_block(n: int, ncols: int, seed: int) -> np.ndarray:
     return rng.standard_normal((n, ncols)).astype(np.float32)
 
 
+def rbf_kernel_matrix(n: int, dim: int, gamma: float, seed: int) -> CSR:
+    """Dense Gaussian kernel matrix exp(-gamma |x_i - x_j|^2) on ``n`` Morton-sorted uniform points
+    in [0,1]^dim, stored as CSR with every entry (the kernel-matrix workload of the compression
+    curve)."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    pts = rng.random((n, dim))
+    pts = pts[morton_order(pts)]
+    d2 = ((pts[:, None, :] - pts[None, :, :]) ** 2).sum(-1)
+    k = np.exp(-gamma * d2)
+    return csr_from_dense(0.5 * (k + k.T))
+
+
 def random_symmetric(n: int, density: float, seed: int, diag_shift: float = 0.0) -> CSR:
     """Random sparse symmetric matrix with N(0,1) entries (edge and special-case tests)."""
     rng = np.random.Generator(np.random.PCG64(seed))
