@@ -22,6 +22,10 @@ from .pmmf_oracle import (  # noqa: F401
     apply_inverse,
     apply_inverse_sqrt,
     backward,
+    rot3_generators,
+    rot3_param_matrix,
+    rot3_param_jacobian,
+    with_params3,
     dense_U,
     dense_reconstruction,
 )

@@ -43,6 +43,10 @@ Readings of points the paper leaves open (each is also listed in the design note
       |G_jj - G_ii| / (|G_ii| + |G_jj| + 2|G_ij|), the k = 3 eigengap and trace gap, and the
       elimination gap relative to max_t G_tt.  A margin below 1e-5 marks a step where two
       choices are equally correct at working precision.
+  R15 Angles of a 3-point rotation (the paper parametrizes only Givens rotations by an angle):
+      O(w) = expm(w_0 G_01 + w_1 G_02 + w_2 G_12) O0, with O0 the rotation the search found and
+      G_pq = E_qp - E_pq the generator of the (p, q) plane in slot order (G_01 extends the Givens
+      J = [[0, -1], [1, 0]]); w = 0 at the start.
 """
 from __future__ import annotations
 
@@ -458,7 +462,61 @@ def dense_reconstruction(fac: Factorization) -> np.ndarray:
 
 # --------------------------------------------------------------------------- adjoint
 
-def backward(fac: Factorization, X: np.ndarray, Ybar: np.ndarray):
+def rot3_generators():
+    """G_01, G_02, G_12 (R15): G_pq = E_qp - E_pq, the generator of rotations in the (p, q)
+    plane of a 3-point rotation's slots."""
+    gens = []
+    for p, q in ((0, 1), (0, 2), (1, 2)):
+        G = np.zeros((3, 3))
+        G[q, p], G[p, q] = 1.0, -1.0
+        gens.append(G)
+    return gens
+
+
+def rot3_param_matrix(w) -> np.ndarray:
+    """W(w) = w_0 G_01 + w_1 G_02 + w_2 G_12 (skew-symmetric)."""
+    return sum(wm * G for wm, G in zip(w, rot3_generators()))
+
+
+def rot3_param_jacobian(w) -> np.ndarray:
+    """3x3 matrix B(w) with  d expm(W(w)) = W(B(w) dw) expm(W(w)): the left-trivialized
+    derivative of the matrix exponential, dexp_W(X) = sum_{k>=0} ad_W^k(X) / (k+1)! with
+    ad_W(X) = W X - X W, applied to each generator and read back in the generator basis."""
+    W = rot3_param_matrix(w)
+    gens = rot3_generators()
+    B = np.zeros((3, 3))
+    for m, G in enumerate(gens):
+        term, total = G.copy(), G.copy()
+        for k in range(1, 40):
+            term = (W @ term - term @ W) / (k + 1)
+            total = total + term
+            if np.abs(term).max() < 1e-18:
+                break
+        # coordinates of the skew matrix `total` in (G_01, G_02, G_12): entries (1,0), (2,0), (2,1)
+        B[:, m] = [total[1, 0], total[2, 0], total[2, 1]]
+    return B
+
+
+def with_params3(fac: Factorization, theta, hdiag=None, hcore=None) -> Factorization:
+    """Copy of a k = 3 factorization with O_t = expm(W(theta_t)) O_t (R15): ``fac`` holds the
+    rotations at theta = 0.  Steps with 2 indices use theta_t[0] as their Givens angle offset in
+    the (0, 1) plane."""
+    import scipy.linalg
+    theta = np.asarray(theta, dtype=np.float64)
+    rots = []
+    for r, w in zip(fac.rotations, theta):
+        if len(r.ids) == 2:
+            c, sn = math.cos(w[0]), math.sin(w[0])
+            O = np.array([[c, -sn], [sn, c]]) @ r.O
+        else:
+            O = scipy.linalg.expm(rot3_param_matrix(w)) @ r.O
+        rots.append(dataclasses.replace(r, O=O))
+    return dataclasses.replace(fac, rotations=rots,
+                               hdiag=fac.hdiag if hdiag is None else hdiag,
+                               hcore=fac.hcore if hcore is None else hcore)
+
+
+def backward(fac: Factorization, X: np.ndarray, Ybar: np.ndarray, theta=None):
     """Adjoint of Y = U^T H U X with respect to X, H and the Givens angles.
 
     The angle of rotation t is theta_t with O_t = [[cos, -sin], [sin, cos]], so
@@ -466,7 +524,12 @@ def backward(fac: Factorization, X: np.ndarray, Ybar: np.ndarray):
     adjoint states g_a = (Q_T..Q_{t+1})^T H a and g_b = (Q_T..Q_{t+1})^T H^T b, the angle
     gradient is  sum_rhs <g_a[T], J zy_t[T]> + <g_b[T], J zx_t[T]>,  where zx_t and zy_t are x and
     ybar after rotations 1..t.  States are recovered by undoing rotations, not stored.
-    Returns (xbar, hdiag_bar, hcore_bar, theta_bar); theta_bar is None for k = 3.
+    For k = 3 (R15) the plane generators G_01, G_02, G_12 take J's place, giving the derivatives
+    l_t along exp(eps G_m) O_t; the gradient in the parameters w_t of O_t = expm(W(w_t)) O0_t is
+    the chain rule through the derivative of the matrix exponential (``rot3_param_jacobian``),
+    which is the identity at w = 0.  ``theta`` are the current parameters (k = 3: [R][3]; None
+    means zero).
+    Returns (xbar, hdiag_bar, hcore_bar, theta_bar); theta_bar is [R] for k = 2, [R][3] for k = 3.
     """
     X = np.asarray(X, dtype=np.float64)
     Yb = np.asarray(Ybar, dtype=np.float64)
@@ -483,13 +546,24 @@ def backward(fac: Factorization, X: np.ndarray, Ybar: np.ndarray):
     ga = _apply_H(fac, a)
     gb = _apply_H(dataclasses.replace(fac, hcore=fac.hcore.T), b)
     zx, zy = a.copy(), b.copy()
-    theta_bar = np.zeros(len(fac.rotations)) if fac.k == 2 else None
+    R = len(fac.rotations)
+    theta_bar = np.zeros(R) if fac.k == 2 else np.zeros((R, 3))
     J = np.array([[0.0, -1.0], [1.0, 0.0]])
-    for t in range(len(fac.rotations) - 1, -1, -1):
+    gens = rot3_generators()
+    for t in range(R - 1, -1, -1):
         r = fac.rotations[t]
         ids = r.ids
-        if theta_bar is not None and len(ids) == 2:
-            theta_bar[t] = float((ga[ids] * (J @ zy[ids])).sum() + (gb[ids] * (J @ zx[ids])).sum())
+        if len(ids) == 2:
+            lt = float((ga[ids] * (J @ zy[ids])).sum() + (gb[ids] * (J @ zx[ids])).sum())
+            if fac.k == 2:
+                theta_bar[t] = lt
+            else:  # a 2-point step inside a k = 3 factorization: its (0, 1) plane only
+                theta_bar[t, 0] = lt
+        else:
+            l3 = np.array([float((ga[ids] * (G @ zy[ids])).sum() + (gb[ids] * (G @ zx[ids])).sum())
+                           for G in gens])
+            w = np.zeros(3) if theta is None else np.asarray(theta, dtype=np.float64)[t]
+            theta_bar[t] = rot3_param_jacobian(w).T @ l3
         Ot = r.O.T
         zx[ids] = Ot @ zx[ids]
         zy[ids] = Ot @ zy[ids]

@@ -446,6 +446,45 @@ def test_backward_matches_central_finite_differences():
     assert abs(fd - float((xbar * d).sum())) <= 1e-10 * max(1.0, abs(fd))
 
 
+@pytest.mark.parametrize("scale", [0.0, 0.3])
+def test_backward_k3_angle_gradient_matches_central_finite_differences(scale):
+    # R15: 3-point rotations O_t(w) = expm(W(w_t)) O0_t; the gradient in w at w = 0 and at a
+    # random w (where the derivative of the exponential map is not the identity)
+    A = workloads.small_grid((5, 6), seed=13)
+    fac0 = oracle.factor(A, k=3, core=6, cluster=(4, 10), seed=2)
+    rng = np.random.default_rng(7)
+    R = len(fac0.rotations)
+    w0 = scale * rng.standard_normal((R, 3))
+    X = rng.standard_normal((fac0.n, 3))
+    W = rng.standard_normal((fac0.n, 3))
+    fac = om.with_params3(fac0, w0)
+    _, _, _, thbar = oracle.backward(fac, X, W, theta=w0)
+    assert thbar.shape == (R, 3)
+    h = 1e-6
+    for t in range(R):
+        for m in range(3):
+            e = np.zeros_like(w0)
+            e[t, m] = h
+            fd = (_objective(om.with_params3(fac0, w0 + e), X, W)
+                  - _objective(om.with_params3(fac0, w0 - e), X, W)) / (2 * h)
+            assert abs(fd - thbar[t, m]) <= 1e-6 * max(1.0, abs(fd)), (t, m, fd, thbar[t, m])
+
+
+def test_rot3_parametrization_pins():
+    # G_01 is the Givens generator in slots (0, 1); W(w) is skew; expm(W) is a rotation; B(0) = I
+    G = om.rot3_generators()
+    assert np.array_equal(G[0][:2, :2], np.array([[0.0, -1.0], [1.0, 0.0]]))
+    w = np.array([0.4, -1.1, 0.7])
+    Wm = om.rot3_param_matrix(w)
+    assert np.array_equal(Wm, -Wm.T)
+    import scipy.linalg
+    Q = scipy.linalg.expm(Wm)
+    assert np.allclose(Q @ Q.T, np.eye(3), atol=1e-14) and abs(np.linalg.det(Q) - 1) < 1e-14
+    assert np.array_equal(om.rot3_param_jacobian(np.zeros(3)), np.eye(3))
+    # a rotation about a single plane: the exponential map is linear along it (B w = w)
+    assert np.allclose(om.rot3_param_jacobian(np.array([0.0, 0.9, 0.0])) @ [0, 1, 0], [0, 1, 0])
+
+
 def test_backward_matches_torch_autograd_fp64():
     torch = pytest.importorskip("torch")
     A = workloads.small_grid((6, 6), seed=14)
