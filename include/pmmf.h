@@ -151,8 +151,9 @@ int mmf_apply_inverse_sqrt(mmf_handle h, const float* d_x, float* d_y, int64_t n
  *   d_xbar      [n][ld]         = U^T H^T U Ybar
  *   d_hdiag_bar [n]             : sum over columns of (U Ybar)_e (U X)_e on retired e (0 on core)
  *   d_hcore_bar [core][core]    : (U Ybar)_core (U X)_core^T, row-major
- *   d_theta_bar [num_rotations] : d<Ybar, Y>/d theta_t for the Givens angle of rotation t, in the
- *                                 order of mmf_export (k = 2 only; pass NULL for k = 3)
+ *   d_theta_bar                 : d<Ybar, Y>/d theta in the layout of mmf_param_ptrs, in the
+ *                                 order of mmf_export: [num_rotations] Givens angles (k = 2) or
+ *                                 [num_rotations][3] angles of the 3-point rotations (k = 3)
  * Any of the four outputs may be NULL to skip it.  Stage states are recomputed by undoing
  * rotations, not stored.  Asynchronous.  Errors: MMF_ESTATE, MMF_EINVAL, MMF_ENOMEM, MMF_EDEVICE.
  */
@@ -219,22 +220,28 @@ int mmf_import(int64_t n, int32_t k, int64_t core_size, int32_t num_stages,
 
 /*
  * mmf_param_ptrs — device pointers to the handle-owned parameters used by apply and backward:
- *   theta [num_rotations] Givens angles (k = 2; NULL for k = 3), hdiag [n], hcore [core][core].
+ *   theta   k = 2: [num_rotations] Givens angles, O_t = [[cos, -sin], [sin, cos]];
+ *           k = 3: [num_rotations][3] angles w_t with O_t = expm(w_0 G_01 + w_1 G_02 + w_2 G_12) O0_t,
+ *           G_pq = E_qp - E_pq the generator of the (p, q) plane of the rotation's slots and O0_t
+ *           the rotation the search found (w = 0 after mmf_factor and mmf_import; the paper
+ *           gives angles only for Givens rotations, this extends them to its k-point rotations);
+ *   hdiag [n], hcore [core][core].
  * They may be updated in place (e.g. by an optimizer); after changing theta call
  * mmf_sync_angles so the rotations use the new angles.  Errors: MMF_ESTATE.
  */
 int mmf_param_ptrs(mmf_handle h, float** theta, float** hdiag, float** hcore);
 
-/* Recompute the stored (cos, sin) of every Givens rotation from theta, on `stream`.  Also drops
- * the cached core factor used by mmf_apply_inverse.  Errors: MMF_ESTATE, MMF_EDEVICE. */
+/* Recompute every rotation from theta (k = 2: (cos, sin); k = 3: expm(W(w_t)) O0_t by Rodrigues'
+ * formula in FP64), on `stream`.  Also drops the cached core factor used by mmf_apply_inverse.
+ * Errors: MMF_ESTATE, MMF_EDEVICE. */
 int mmf_sync_angles(mmf_handle h, void* stream);
 
 /*
  * mmf_set_params — copy new parameters from caller device buffers into the handle, on `stream`:
- *   d_theta [num_rotations] (k = 2 only), d_hdiag [n], d_hcore [core][core]; any may be NULL.
+ *   d_theta (layout of mmf_param_ptrs), d_hdiag [n], d_hcore [core][core]; any may be NULL.
  * Recomputes the rotations from theta when it is given and drops the cached core factor.
  * Used by gradient refinement of the angles (the parameters of y = U^T H U x).
- * Errors: MMF_ESTATE, MMF_EINVAL (theta for k = 3), MMF_EDEVICE.
+ * Errors: MMF_ESTATE, MMF_EDEVICE.
  */
 int mmf_set_params(mmf_handle h, const float* d_theta, const float* d_hdiag, const float* d_hcore,
                    void* stream);

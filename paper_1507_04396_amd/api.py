@@ -68,6 +68,7 @@ class Factorization:
         self.n = n
         self.k = k
         self.core = core
+        self._theta3 = None  # k = 3: the angles last handed to set_params (zero until then)
 
     # ------------------------------------------------------------------ construction
     @classmethod
@@ -208,10 +209,13 @@ class Factorization:
         xb = torch.empty_like(x2) if "x" in want else None
         hdb = torch.empty(self.n, device=dev) if "hdiag" in want else None
         hcb = torch.empty(self.core, self.core, device=dev) if "hcore" in want else None
-        thb = torch.empty(max(R, 1), device=dev) if ("theta" in want and self.k == 2) else None
+        na = 3 if self.k == 3 else 1  # angles per rotation
+        thb = torch.empty(max(R, 1) * na, device=dev) if "theta" in want else None
         check(_lib.load().mmf_backward(self.handle, _ptr(x2), _ptr(yb), _ptr(xb), _ptr(hdb),
                                        _ptr(hcb), _ptr(thb), nrhs, ld, _stream(stream)))
-        return xb, hdb, hcb, (thb[:R] if thb is not None else None)
+        if thb is not None:
+            thb = thb[:R] if na == 1 else thb[:3 * R].view(R, 3)
+        return xb, hdb, hcb, thb
 
     def pcg(self, rowptr: torch.Tensor, colind: torch.Tensor, val: torch.Tensor,
             b: torch.Tensor, tol: float = 1e-6, max_iter: int = 2000,
@@ -253,15 +257,23 @@ class Factorization:
                 _require_device(t, torch.float32, nm)
         check(_lib.load().mmf_set_params(self.handle, _ptr(theta), _ptr(hdiag), _ptr(hcore),
                                          _stream(stream)))
+        if theta is not None and self.k == 3:
+            self._theta3 = theta.detach().clone().reshape(-1, 3)
 
     def params(self):
-        """Copies of (theta, hdiag, hcore) as device tensors."""
+        """Copies of (theta, hdiag, hcore) as device tensors: theta is [R] Givens angles (k = 2) or
+        [R][3] angles of the 3-point rotations about the rotations as found (k = 3)."""
         ex = self.export()
-        o = ex["rot_o"]
-        theta = np.arctan2(o[:, 1, 0], o[:, 0, 0]) if self.k == 2 else None
         dev = "cuda"
-        return (None if theta is None else torch.tensor(theta, dtype=torch.float32, device=dev),
-                torch.tensor(ex["hdiag"], device=dev), torch.tensor(ex["hcore"], device=dev))
+        if self.k == 2:
+            o = ex["rot_o"]
+            theta = torch.tensor(np.arctan2(o[:, 1, 0], o[:, 0, 0]), dtype=torch.float32,
+                                 device=dev)
+        elif self._theta3 is not None:
+            theta = self._theta3.clone()
+        else:
+            theta = torch.zeros(self.n - self.core, 3, dtype=torch.float32, device=dev)
+        return theta, torch.tensor(ex["hdiag"], device=dev), torch.tensor(ex["hcore"], device=dev)
 
 
 class ProductGraph:

@@ -191,6 +191,7 @@ struct mmf_plan {
   mmf_params prm{};
   std::vector<std::unique_ptr<StageDev>> st;
   DBuf rot_loc, rot_gid, rot_o, rot_ret, rot_margin, theta, rot_lit;
+  DBuf rot_o0;  // k = 3: the rotations as found (angles w = 0), O_t = expm(W(w_t)) O0_t
   DBuf hdiag, hcore, core_ids, is_core;
   DBuf hinv, chol_L, chol_X, status;
   DBuf hisqrt, eig_A, eig_D, eig_E, eig_info;  // H_core^{-1/2} and its eigendecomposition
@@ -549,6 +550,33 @@ static mmf_plan* checked(mmf_handle h) {
   std::lock_guard<std::mutex> lk(g_live_mu);
   if (!h || !g_live.count(h)) raise(MMF_ESTATE, "invalid or destroyed handle");
   return h;
+}
+
+// k = 3: three angles per rotation, all zero, about the rotations as found
+static void init_params3(mmf_plan& h, hipStream_t s) {
+  if (h.k != 3) return;
+  const int64_t R = std::max<int64_t>(h.R, 1);
+  h.theta.ensure(R * 3 * sizeof(float));
+  HIPCHK(hipMemsetAsync(h.theta.p, 0, R * 3 * sizeof(float), s));
+  h.rot_o0.ensure(R * 9 * sizeof(float));
+  HIPCHK(hipMemcpyAsync(h.rot_o0.p, h.rot_o.p, R * 9 * sizeof(float), hipMemcpyDeviceToDevice, s));
+  HIPCHK(hipStreamSynchronize(s));
+}
+
+// rotations (canonical and sweep-log copies) from the current angles
+static void sync_rotations(mmf_plan& h, hipStream_t s) {
+  if (h.k == 2) {
+    HIPCHK(pmmf::launch_sync_angles(h.R, h.theta.as<float>(), h.rot_o.as<float>(), s));
+    for (auto& sp : h.st)
+      HIPCHK(pmmf::launch_sync_sweep((int)sp->t, sp->sw_idx.as<int32_t>(), h.theta.as<float>(),
+                                     sp->sw_o.as<float>(), s));
+  } else {
+    HIPCHK(pmmf::launch_sync_rot3(h.R, h.theta.as<float>(), h.rot_o0.as<float>(),
+                                  h.rot_o.as<float>(), s));
+    for (auto& sp : h.st)
+      HIPCHK(pmmf::launch_sync_sweep3((int)sp->t, sp->sw_idx.as<int32_t>(), h.rot_o.as<float>(),
+                                      sp->sw_o.as<float>(), s));
+  }
 }
 
 extern "C" int mmf_factor(int64_t n, int64_t nnz, const int64_t* d_rowptr, const int32_t* d_colind,
@@ -938,6 +966,7 @@ extern "C" int mmf_factor(int64_t n, int64_t nnz, const int64_t* d_rowptr, const
     sp->depth_max = 0;
     for (int32_t d : dep) sp->depth_max = std::max(sp->depth_max, d);
   }
+  init_params3(*h, s);
   *out = h.release();
   register_handle(*out);
   return MMF_OK;
@@ -1447,9 +1476,12 @@ void backward_body(mmf_plan& h, const float* d_x, const float* d_ybar, float* d_
   const int ntiles = (int)std::max((nrhs + W2 - 1) / W2, (nrhs + 63) / 64);
   int64_t tmax = 1;
   for (auto& sp : h.st) tmax = std::max(tmax, sp->t);
+  // angle partials per rotation: one (k = 2) or one per plane of its slots (k = 3)
+  const int NP = h.k == 3 ? 3 : 1;
+  const bool want_theta = h.k == 2 || d_theta_bar;
   DBuf pa_buf, pb_buf;
-  pa_buf.ensure((size_t)ntiles * tmax * sizeof(float));
-  pb_buf.ensure((size_t)ntiles * tmax * sizeof(float));
+  pa_buf.ensure((size_t)ntiles * tmax * NP * sizeof(float));
+  pb_buf.ensure((size_t)ntiles * tmax * NP * sizeof(float));
   // copy of the core states so the ping-pong buffers are free for pass B
   DBuf acopy, bcopy;
   acopy.ensure(std::max<int64_t>(core * nrhs, 1) * sizeof(float));
@@ -1487,15 +1519,19 @@ void backward_body(mmf_plan& h, const float* d_x, const float* d_ybar, float* d_
       }
       io.nrhs = nrhs;
       io.theta_part = pass == 0 ? pa_buf.as<float>() : pb_buf.as<float>();
-      io.theta_stride = sd.t;
-      HIPCHK(hipMemsetAsync(io.theta_part, 0, (size_t)ntiles * sd.t * sizeof(float), s));
-      HIPCHK(pmmf::launch_unit_rev(unit_view(h, sd), io, 2, h.k == 2, cfg.wpb, s));
-      HIPCHK(pmmf::launch_sweep_rev(v, io, W2, 2, h.k == 2, s));
+      io.theta_stride = sd.t * NP;
+      if (want_theta)
+        HIPCHK(hipMemsetAsync(io.theta_part, 0, (size_t)ntiles * sd.t * NP * sizeof(float), s));
+      HIPCHK(pmmf::launch_unit_rev(unit_view(h, sd), io, 2, want_theta, cfg.wpb, s));
+      HIPCHK(pmmf::launch_sweep_rev(v, io, W2, 2, want_theta, s));
     }
     if (d_theta_bar)
-      HIPCHK(pmmf::launch_theta_reduce((int)sd.t, ntiles, sd.t, pa_buf.as<float>(),
-                                       pb_buf.as<float>(), sd.rot_base, d_theta_bar, s));
+      HIPCHK(pmmf::launch_theta_reduce((int)(sd.t * NP), ntiles, sd.t * NP, pa_buf.as<float>(),
+                                       pb_buf.as<float>(), sd.rot_base * NP, d_theta_bar, s));
   }
+  // k = 3: plane derivatives -> derivatives in the angles (derivative of the exponential map)
+  if (d_theta_bar && h.k == 3)
+    HIPCHK(pmmf::launch_theta3_chain(h.R, h.theta.as<float>(), d_theta_bar, s));
   // keep the temporaries alive until the stream has consumed them
   HIPCHK(hipStreamSynchronize(s));
 }
@@ -1508,7 +1544,6 @@ extern "C" int mmf_backward(mmf_handle hh, const float* d_x, const float* d_ybar
   pmmf_alloc::StreamScope alloc_scope(stream);
   hipStream_t s = as_stream(stream);
   if (nrhs < 1 || ld < nrhs || !d_x || !d_ybar) raise(MMF_EINVAL, "bad vector arguments");
-  if (d_theta_bar && h.k != 2) raise(MMF_EINVAL, "angle gradients exist only for k = 2");
   ensure_units(h, s);
   const SweepCfg cfg = sweep_config(h, "adjoint", 2, nrhs, s, [&](const SweepCfg& c) {
     backward_body(h, d_x, d_ybar, d_xbar, d_hdiag_bar, d_hcore_bar, d_theta_bar, nrhs, ld, s, c);
@@ -1727,6 +1762,7 @@ extern "C" int mmf_import(int64_t n, int32_t k, int64_t core_size, int32_t num_s
   h->info.k = k;
   h->info.num_stages = num_stages;
   h->info.num_rotations = R;
+  init_params3(*h, s);
   *out = h.release();
   register_handle(*out);
   return MMF_OK;
@@ -1736,7 +1772,7 @@ extern "C" int mmf_import(int64_t n, int32_t k, int64_t core_size, int32_t num_s
 extern "C" int mmf_param_ptrs(mmf_handle hh, float** theta, float** hdiag, float** hcore) {
   ABI_BEGIN
   mmf_plan& h = *checked(hh);
-  if (theta) *theta = h.k == 2 ? h.theta.as<float>() : nullptr;
+  if (theta) *theta = h.theta.as<float>();
   if (hdiag) *hdiag = h.hdiag.as<float>();
   if (hcore) *hcore = h.hcore.as<float>();
   return MMF_OK;
@@ -1751,11 +1787,7 @@ extern "C" int mmf_sync_angles(mmf_handle hh, void* stream) {
   h.inv_ready = false;
   h.isqrt_ready = false;
   ++h.version;
-  if (h.k != 2) return MMF_OK;
-  HIPCHK(pmmf::launch_sync_angles(h.R, h.theta.as<float>(), h.rot_o.as<float>(), s));
-  for (auto& sp : h.st)
-    HIPCHK(pmmf::launch_sync_sweep((int)sp->t, sp->sw_idx.as<int32_t>(), h.theta.as<float>(),
-                                   sp->sw_o.as<float>(), s));
+  sync_rotations(h, s);
   return MMF_OK;
   ABI_END
 }
@@ -1766,7 +1798,6 @@ extern "C" int mmf_set_params(mmf_handle hh, const float* d_theta, const float* 
   mmf_plan& h = *checked(hh);
   pmmf_alloc::StreamScope alloc_scope(stream);
   hipStream_t s = as_stream(stream);
-  if (d_theta && h.k != 2) raise(MMF_EINVAL, "angles exist only for k = 2");
   h.inv_ready = false;
   h.isqrt_ready = false;
   ++h.version;
@@ -1776,11 +1807,9 @@ extern "C" int mmf_set_params(mmf_handle hh, const float* d_theta, const float* 
     HIPCHK(hipMemcpyAsync(h.hcore.p, d_hcore, h.core * h.core * sizeof(float),
                           hipMemcpyDeviceToDevice, s));
   if (d_theta && h.R) {
-    HIPCHK(hipMemcpyAsync(h.theta.p, d_theta, h.R * sizeof(float), hipMemcpyDeviceToDevice, s));
-    HIPCHK(pmmf::launch_sync_angles(h.R, h.theta.as<float>(), h.rot_o.as<float>(), s));
-    for (auto& sp : h.st)
-      HIPCHK(pmmf::launch_sync_sweep((int)sp->t, sp->sw_idx.as<int32_t>(), h.theta.as<float>(),
-                                     sp->sw_o.as<float>(), s));
+    const int64_t na = h.R * (h.k == 3 ? 3 : 1);
+    HIPCHK(hipMemcpyAsync(h.theta.p, d_theta, na * sizeof(float), hipMemcpyDeviceToDevice, s));
+    sync_rotations(h, s);
   }
   return MMF_OK;
   ABI_END

@@ -98,5 +98,11 @@ hipError_t launch_gather_rows(int64_t rows, const float* src, int64_t lds, const
 hipError_t launch_sync_angles(int64_t R, const float* theta, float* rot_o, hipStream_t s);
 hipError_t launch_sync_sweep(int t, const int32_t* sw_idx, const float* theta, float* sw_o,
                              hipStream_t s);
+// 3-point rotations: O_t = expm(W(w_t)) O0_t, sweep-log copies, and the chain rule of d/dw
+hipError_t launch_sync_rot3(int64_t R, const float* theta, const float* o0, float* rot_o,
+                            hipStream_t s);
+hipError_t launch_sync_sweep3(int t, const int32_t* sw_idx, const float* rot_o, float* sw_o,
+                              hipStream_t s);
+hipError_t launch_theta3_chain(int64_t R, const float* theta, float* g, hipStream_t s);
 
 }  // namespace pmmf

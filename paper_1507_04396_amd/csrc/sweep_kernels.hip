@@ -151,21 +151,27 @@ __global__ void __launch_bounds__(256) k_sweep_rev(SweepStage st, RevIO io) {
       const bool live = q < nwork;
       const int rr = b0 + (live ? q / W : 0), w = q % W;
       if constexpr (THETA) {
-        float part = 0.f;
-        if (live) {
-          const int* ids = rid + rr * K;
-          const float* z = tile;
-          const float* g = tile + cstride;
-          const float zi = z[ids[0] * W + w], zj = z[ids[1] * W + w];
-          const float gi = g[ids[0] * W + w], gj = g[ids[1] * W + w];
-          part = gj * zi - gi * zj;
-        }
-        // reduce over the W consecutive lanes holding one rotation's columns
+        // k = 3: one partial per plane (0,1), (0,2), (1,2) of the slots
+        constexpr int NP = K == 3 ? 3 : 1;
 #pragma unroll
-        for (int ofs = W / 2; ofs > 0; ofs >>= 1) part += __shfl_xor(part, ofs, W);
-        if (live && w == 0)
-          io.theta_part[(size_t)blockIdx.y * io.theta_stride +
-                        (st.sw_idx[rr + rb] - st.rot_base)] = part;
+        for (int m = 0; m < NP; ++m) {
+          const int pp = m == 2 ? 1 : 0, qq = m == 0 ? 1 : 2;
+          float part = 0.f;
+          if (live) {
+            const int* ids = rid + rr * K;
+            const float* z = tile;
+            const float* g = tile + cstride;
+            const float zi = z[ids[pp] * W + w], zj = z[ids[qq] * W + w];
+            const float gi = g[ids[pp] * W + w], gj = g[ids[qq] * W + w];
+            part = gj * zi - gi * zj;
+          }
+          // reduce over the W consecutive lanes holding one rotation's columns
+#pragma unroll
+          for (int ofs = W / 2; ofs > 0; ofs >>= 1) part += __shfl_xor(part, ofs, W);
+          if (live && w == 0)
+            io.theta_part[(size_t)blockIdx.y * io.theta_stride +
+                          (size_t)(st.sw_idx[rr + rb] - st.rot_base) * NP + m] = part;
+        }
       }
       if (live) rotate_cols<K, W, NV, true>(tile, cstride, rid + rr * K, rob + rr * K * K, w);
     }
@@ -249,6 +255,7 @@ hipError_t launch_sweep_rev(const SweepStage& st, const RevIO& io, int W, int nv
     if (nv == 1) { PMMF_W_SWITCH(W, (rev_dispatch<2, WW, 1, false>(st, io, s))) }
     PMMF_W_SWITCH(W, (rev_dispatch<2, WW, 2, false>(st, io, s)))
   }
+  if (theta) { PMMF_W_SWITCH(W, (rev_dispatch<3, WW, 2, true>(st, io, s))) }
   if (nv == 1) { PMMF_W_SWITCH(W, (rev_dispatch<3, WW, 1, false>(st, io, s))) }
   PMMF_W_SWITCH(W, (rev_dispatch<3, WW, 2, false>(st, io, s)))
 }
@@ -591,12 +598,18 @@ __global__ void __launch_bounds__(256) k_unit_sweep(UnitStage st, FwdIO fio, Rev
 #pragma unroll
       for (int ab = 0; ab < K * K; ++ab) o[ab] = pmmf_readlane_f(om[ab], q);
       if constexpr (MODE == 2 && NV == 2) {
-        // lanes past the last column hold a copy of it: they add nothing
-        float part = cok ? T(1, id[1]) * T(0, id[0]) - T(1, id[0]) * T(0, id[1]) : 0.f;
-        part = pmmf_wave_sum_dpp(part);
-        if (lane == 0)
-          rio.theta_part[(int64_t)blockIdx.y * rio.theta_stride +
-                         (__builtin_amdgcn_readlane(rt.y, q) - st.rot_base)] = part;
+        // lanes past the last column hold a copy of it: they add nothing.  k = 3: one partial
+        // per plane (0,1), (0,2), (1,2) of the slots, <g, G_pq z> = g_q z_p - g_p z_q
+        constexpr int NP = K == 3 ? 3 : 1;
+        const int64_t at = (int64_t)blockIdx.y * rio.theta_stride +
+                           (int64_t)(__builtin_amdgcn_readlane(rt.y, q) - st.rot_base) * NP;
+#pragma unroll
+        for (int m = 0; m < NP; ++m) {
+          const int pp = m == 2 ? 1 : 0, qq = m == 0 ? 1 : 2;
+          float part = cok ? T(1, id[qq]) * T(0, id[pp]) - T(1, id[pp]) * T(0, id[qq]) : 0.f;
+          part = pmmf_wave_sum_dpp(part);
+          if (lane == 0) rio.theta_part[at + m] = part;
+        }
       }
 #pragma unroll
       for (int v = 0; v < NV; ++v) {
@@ -670,6 +683,7 @@ hipError_t launch_unit_rev(const UnitStage& st, const RevIO& io, int nv, bool th
     return nv == 1 ? unit_launch<2, 1, 1>(st, none, io, wpb, s)
                    : unit_launch<2, 2, 1>(st, none, io, wpb, s);
   }
+  if (theta) return unit_launch<3, 2, 2>(st, none, io, wpb, s);
   return nv == 1 ? unit_launch<3, 1, 1>(st, none, io, wpb, s)
                  : unit_launch<3, 2, 1>(st, none, io, wpb, s);
 }
@@ -723,6 +737,120 @@ hipError_t launch_sync_sweep(int t, const int32_t* sw_idx, const float* theta, f
                              hipStream_t s) {
   if (t == 0) return hipSuccess;
   k_sync_sweep<<<(t + 255) / 256, 256, 0, s>>>(t, sw_idx, theta, sw_o);
+  return hipGetLastError();
+}
+
+// ------------------------------------------------------------------------------------------
+// Angles of 3-point rotations: O_t = expm(W(w_t)) O0_t with W(w) = w_0 G_01 + w_1 G_02 + w_2 G_12
+// and G_pq = E_qp - E_pq.  In axis form W(w) = hat(v), v = (w_2, -w_1, w_0) (hat(v) x = v x x), so
+// expm follows Rodrigues' formula and the derivative of the exponential map is the left Jacobian
+// J(v) = I + (1 - cos f)/f^2 hat(v) + (f - sin f)/f^3 hat(v)^2, f = |v|:
+//     d expm(hat(v)) = hat(J(v) dv) expm(hat(v)).
+// Both evaluated in FP64 (series near f = 0).
+__device__ inline void so3_coeffs(double f2, double& a, double& b, double& c) {
+  // a = sin f / f, b = (1 - cos f) / f^2, c = (f - sin f) / f^3
+  if (f2 < 1e-8) {
+    a = 1.0 - f2 / 6.0;
+    b = 0.5 - f2 / 24.0;
+    c = 1.0 / 6.0 - f2 / 120.0;
+  } else {
+    const double f = sqrt(f2);
+    a = sin(f) / f;
+    b = (1.0 - cos(f)) / f2;
+    c = (f - sin(f)) / (f2 * f);
+  }
+}
+
+__device__ inline void hat3(const double (&v)[3], double (&K)[3][3]) {
+  K[0][0] = 0.0;   K[0][1] = -v[2]; K[0][2] = v[1];
+  K[1][0] = v[2];  K[1][1] = 0.0;   K[1][2] = -v[0];
+  K[2][0] = -v[1]; K[2][1] = v[0];  K[2][2] = 0.0;
+}
+
+// O_t = expm(W(w_t)) O0_t for every rotation (rot_o row-major [R][9])
+__global__ void k_sync_rot3(int64_t R, const float* __restrict__ theta,
+                            const float* __restrict__ o0, float* __restrict__ rot_o) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= R) return;
+  const double v[3] = {theta[3 * t + 2], -(double)theta[3 * t + 1], theta[3 * t + 0]};
+  double K[3][3], E[3][3], a, b, c;
+  hat3(v, K);
+  so3_coeffs(v[0] * v[0] + v[1] * v[1] + v[2] * v[2], a, b, c);
+#pragma unroll
+  for (int i = 0; i < 3; ++i)
+#pragma unroll
+    for (int j = 0; j < 3; ++j) {
+      double k2 = 0.0;
+#pragma unroll
+      for (int m = 0; m < 3; ++m) k2 += K[i][m] * K[m][j];
+      E[i][j] = (i == j ? 1.0 : 0.0) + a * K[i][j] + b * k2;
+    }
+#pragma unroll
+  for (int i = 0; i < 3; ++i)
+#pragma unroll
+    for (int j = 0; j < 3; ++j) {
+      double acc = 0.0;
+#pragma unroll
+      for (int m = 0; m < 3; ++m) acc += E[i][m] * (double)o0[t * 9 + m * 3 + j];
+      rot_o[t * 9 + i * 3 + j] = (float)acc;
+    }
+}
+
+// sweep-log blocks (k x k = 3 x 3 per entry) from the canonical blocks
+__global__ void k_sync_sweep3(int t, const int32_t* __restrict__ sw_idx,
+                              const float* __restrict__ rot_o, float* __restrict__ sw_o) {
+  const int q = blockIdx.x * blockDim.x + threadIdx.x;
+  if (q >= t) return;
+  const int64_t r = sw_idx[q];
+#pragma unroll
+  for (int ab = 0; ab < 9; ++ab) sw_o[(size_t)q * 9 + ab] = rot_o[r * 9 + ab];
+}
+
+// d/dw from the plane derivatives l (along exp(eps G_m) O_t): with P the map w -> v above (a
+// signed permutation), dO = hat(J(v) P dw) O, so d/dw = P^T J(v)^T P l
+__global__ void k_theta3_chain(int64_t R, const float* __restrict__ theta, float* __restrict__ g) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= R) return;
+  const double v[3] = {theta[3 * t + 2], -(double)theta[3 * t + 1], theta[3 * t + 0]};
+  double K[3][3], a, b, c;
+  hat3(v, K);
+  so3_coeffs(v[0] * v[0] + v[1] * v[1] + v[2] * v[2], a, b, c);
+  // P l in axis form
+  const double pl[3] = {g[3 * t + 2], -(double)g[3 * t + 1], g[3 * t + 0]};
+  double y[3];
+#pragma unroll
+  for (int j = 0; j < 3; ++j) {  // y = J^T (P l), J = I + b K + c K^2
+    double acc = pl[j];
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+      double k2 = 0.0;
+#pragma unroll
+      for (int m = 0; m < 3; ++m) k2 += K[i][m] * K[m][j];
+      acc += (b * K[i][j] + c * k2) * pl[i];
+    }
+    y[j] = acc;
+  }
+  // P^T y: w_0 <- v_z, w_1 <- -v_y, w_2 <- v_x
+  g[3 * t + 0] = (float)y[2];
+  g[3 * t + 1] = (float)-y[1];
+  g[3 * t + 2] = (float)y[0];
+}
+
+hipError_t launch_sync_rot3(int64_t R, const float* theta, const float* o0, float* rot_o,
+                            hipStream_t s) {
+  if (R == 0) return hipSuccess;
+  k_sync_rot3<<<(unsigned)((R + 255) / 256), 256, 0, s>>>(R, theta, o0, rot_o);
+  return hipGetLastError();
+}
+hipError_t launch_sync_sweep3(int t, const int32_t* sw_idx, const float* rot_o, float* sw_o,
+                              hipStream_t s) {
+  if (t == 0) return hipSuccess;
+  k_sync_sweep3<<<(t + 255) / 256, 256, 0, s>>>(t, sw_idx, rot_o, sw_o);
+  return hipGetLastError();
+}
+hipError_t launch_theta3_chain(int64_t R, const float* theta, float* g, hipStream_t s) {
+  if (R == 0) return hipSuccess;
+  k_theta3_chain<<<(unsigned)((R + 255) / 256), 256, 0, s>>>(R, theta, g);
   return hipGetLastError();
 }
 

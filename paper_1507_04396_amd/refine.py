@@ -1,12 +1,12 @@
-"""Gradient refinement of a factorization's Givens angles and H.
+"""Gradient refinement of a factorization's rotation angles and H.
 
 Eq. 1 measures a factorization by ||A - A~||_F^2 with A~ = U^T H U.  For probes x ~ N(0, I),
 E ||A x - A~ x||^2 = ||A - A~||_F^2, so the mean over N probes of ||A x_r - A~ x_r||^2 is an
 unbiased (Hutchinson) estimate of that objective.  Its gradient in the angles theta and in H comes
 from mmf_backward (through MMFApply), A x from mmf_spmm, and the step from a torch optimizer.
-Every step hands the new theta to the library, which re-derives each rotation's (cos, sin)
-(mmf_set_params) before the next product.  Givens rotations (k = 2) only: a 3-point rotation has
-no angle parametrisation here.
+Every step hands the new theta to the library, which re-derives each rotation (mmf_set_params)
+before the next product: a Givens angle gives (cos, sin); the three angles w of a 3-point rotation
+give expm(w_0 G_01 + w_1 G_02 + w_2 G_12) O0, O0 being the rotation the search found.
 """
 from __future__ import annotations
 
@@ -41,7 +41,7 @@ def spmm(rowptr: torch.Tensor, colind: torch.Tensor, val: torch.Tensor, x: torch
 class AngleRefiner:
     """Minimises the probe estimate of ||A - U(theta)^T H U(theta)||_F^2 over theta (and H).
 
-    fac: a k = 2 Factorization of A; (rowptr, colind, val): A in device CSR.  optimizer is
+    fac: a Factorization of A (k = 2 or 3); (rowptr, colind, val): A in device CSR.  optimizer is
     "adam" (torch.optim.Adam) or "sgd" (torch.optim.SGD); refine_h also moves H's retired
     diagonal and core.  The handle's parameters follow the refined values after every step.
     """
@@ -49,8 +49,6 @@ class AngleRefiner:
     def __init__(self, fac: Factorization, rowptr: torch.Tensor, colind: torch.Tensor,
                  val: torch.Tensor, lr: float = 1e-3, optimizer: str = "adam",
                  refine_h: bool = True):
-        if fac.k != 2:
-            raise ValueError("angle refinement needs Givens rotations (k = 2)")
         self.fac = fac
         self.A = (rowptr, colind, val)
         theta, hdiag, hcore = fac.params()
