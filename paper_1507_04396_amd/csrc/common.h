@@ -41,6 +41,14 @@ constexpr uint64_t PMMF_TAG_CLUSTER_SIZE = 2;
 __device__ inline int pmmf_lane() { return threadIdx.x & (PMMF_WAVE - 1); }
 __device__ inline int pmmf_wave() { return threadIdx.x / PMMF_WAVE; }
 
+// Workgroups of a launch are dispatched round robin over the eight XCDs, each with its own L2:
+// workgroup b runs on XCD b % 8.  This renumbering gives each XCD one contiguous range of the
+// n workgroups' work, taken in dispatch order, so that neighbouring work items share an L2.
+__device__ inline int pmmf_xcd_block(int b, int n) {
+  const int x = b & 7, i = b >> 3, q = n >> 3, r = n & 7;
+  return x * q + min(x, r) + i;
+}
+
 __device__ inline int pmmf_wave_sum_int(int v) {
   for (int o = PMMF_WAVE / 2; o > 0; o >>= 1) v += __shfl_xor(v, o);
   return v;

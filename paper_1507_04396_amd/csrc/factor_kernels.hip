@@ -80,7 +80,14 @@ hipError_t launch_runs(int S, int fill, const int64_t* rp, const int32_t* ci,
   return hipGetLastError();
 }
 
-constexpr int GRAM_SEGS = 8;  // segments whose first chunks are requested together
+// One 64-entry chunk of a row segment: entries [off, off + rem) of the segment that starts at ci/cv
+// index base, scaled by w.  All fields are wave-uniform (scalar registers).
+struct GramChunk {
+  int64_t base;
+  int off, rem;
+  float w;
+};
+constexpr int GRAM_ITEM = 4;  // chunks whose loads are requested together
 __global__ void __launch_bounds__(256) k_gram(int S, const int64_t* __restrict__ rp,
                                               const int32_t* __restrict__ ci,
                                               const float* __restrict__ cv,
@@ -94,7 +101,10 @@ __global__ void __launch_bounds__(256) k_gram(int S, const int64_t* __restrict__
   extern __shared__ float lds_f[];
   const int wpb = blockDim.x / PMMF_WAVE;
   const int w = pmmf_wave(), lane = pmmf_lane();
-  float* acc = lds_f + (size_t)w * cmax;
+  // cmax accumulator slots, then one spare slot per lane that takes the zero contributions of
+  // lanes past a segment's end (so every lane adds unconditionally and no two lanes of one
+  // chunk touch the same slot)
+  float* acc = lds_f + (size_t)w * (cmax + PMMF_WAVE);
   const int a = blockIdx.x * wpb + w;
   if (a >= S) return;
   const int u = cl_of[a];
@@ -102,16 +112,18 @@ __global__ void __launch_bounds__(256) k_gram(int S, const int64_t* __restrict__
   const int c = off[u + 1] - o;
   const int la = a - o;
   for (int j = lane; j < c; j += PMMF_WAVE) acc[j] = 0.f;
+  const int spare = cmax + lane;
   const int64_t a0 = rp[a], a1 = rp[a + 1];
   for (int64_t kb = a0; kb < a1; kb += PMMF_WAVE) {
     // each lane locates the cluster-u segment of one row r = ci[kb + lane]
     const int nb = (int)min<int64_t>(PMMF_WAVE, a1 - kb);
-    int64_t lb = 0, ub = 0;
-    float w = 0.f;
+    int64_t lb = 0;
+    int len = 0;
+    float wr = 0.f;
     if (lane < nb) {
       // row r's run of columns in cluster u, from its run table (clusters ascending)
       const int r = ci[kb + lane];
-      w = cv[kb + lane];
+      wr = cv[kb + lane];
       int64_t lo = run_ptr[r], hi = run_ptr[r + 1];
       const int64_t re = hi;
       while (lo < hi) {
@@ -121,46 +133,74 @@ __global__ void __launch_bounds__(256) k_gram(int S, const int64_t* __restrict__
       }
       if (lo < re && run_cl[lo] == u) {
         lb = run_start[lo];
-        ub = lo + 1 < re ? run_start[lo + 1] : rp[r + 1];
+        len = (int)((lo + 1 < re ? run_start[lo + 1] : rp[r + 1]) - lb);
       }
     }
-    // accumulate the segments in ascending r; the first 64 entries of four segments are
-    // loaded together so their latencies overlap (the summation order is unchanged)
-    for (int t = 0; t < nb; t += GRAM_SEGS) {
-      int64_t sl[GRAM_SEGS], su[GRAM_SEGS];
-      float sw[GRAM_SEGS], pv[GRAM_SEGS];
-      int pc[GRAM_SEGS];
+    // Walk the chunks of the non-empty segments in ascending r with a wave-uniform cursor; the
+    // loads of the next GRAM_ITEM chunks are requested before the current ones are added.  The
+    // entries of one segment hit distinct columns, so each column still sums in ascending r.
+    uint64_t left = __ballot(len > 0);
+    bool live = false;  // a segment is under the cursor
+    int qn = 0, qoff = 0;
+    int64_t qb = 0;
+    float qw = 0.f;
+    auto next_seg = [&]() {
+      live = left != 0;
+      const int l = live ? (int)__builtin_ctzll(left) : 0;
+      left &= left - 1;
+      qn = __builtin_amdgcn_readlane(len, l);
+      qb = ((int64_t)__builtin_amdgcn_readlane((int)(lb >> 32), l) << 32) |
+           (uint32_t)__builtin_amdgcn_readlane((int)lb, l);
+      qw = pmmf_readlane_f(wr, l);
+      qoff = 0;
+    };
+    next_seg();
+    // an exhausted cursor yields empty chunks at the last segment's start (a valid address)
+    auto take = [&](GramChunk& g) {
+      g.base = qb;
+      g.off = live ? qoff : 0;
+      g.rem = live ? qn - qoff : 0;
+      g.w = qw;
+      qoff += PMMF_WAVE;
+      if (live && qoff >= qn) next_seg();
+    };
+    auto load = [&](const GramChunk* g, int* col, float* val) {
 #pragma unroll
-      for (int q = 0; q < GRAM_SEGS; ++q) {
-        const int tt = min(t + q, nb - 1);
-        sl[q] = __shfl(lb, tt);
-        su[q] = __shfl(ub, tt);
-        sw[q] = __shfl(w, tt);
-        if (t + q >= nb) su[q] = sl[q];
-        const int64_t e = sl[q] + lane;
-        pc[q] = e < su[q] ? ci[e] : 0;
-        pv[q] = e < su[q] ? cv[e] : 0.f;
+      for (int t = 0; t < GRAM_ITEM; ++t) {
+        // lanes past the end re-read an entry of the segment (an address inside it)
+        const uint32_t eb = 4u * (uint32_t)(g[t].off + min(lane, max(g[t].rem - 1, 0)));
+        col[t] = *reinterpret_cast<const int32_t*>(reinterpret_cast<const char*>(ci + g[t].base) + eb);
+        val[t] = *reinterpret_cast<const float*>(reinterpret_cast<const char*>(cv + g[t].base) + eb);
       }
+    };
+    auto add = [&](const GramChunk* g, const int* col, const float* val) {
 #pragma unroll
-      for (int q = 0; q < GRAM_SEGS; ++q) {
-        if (sl[q] + lane < su[q]) acc[pc[q] - o] += sw[q] * pv[q];
-        // the rest of the segment, eight 64-entry chunks requested at a time (entries of one
-        // segment hit distinct columns, so only the segment order fixes the sums)
-        for (int64_t e0 = sl[q] + PMMF_WAVE; e0 < su[q]; e0 += 8 * PMMF_WAVE) {
-          int cc[8];
-          float vv[8];
-#pragma unroll
-          for (int t = 0; t < 8; ++t) {
-            const int64_t e = e0 + t * PMMF_WAVE + lane;
-            const bool ok = e < su[q];
-            cc[t] = ok ? ci[e] : o;
-            vv[t] = ok ? cv[e] : 0.f;
-          }
-#pragma unroll
-          for (int t = 0; t < 8; ++t)
-            if (e0 + t * PMMF_WAVE + lane < su[q]) acc[cc[t] - o] += sw[q] * vv[t];
-        }
+      for (int t = 0; t < GRAM_ITEM; ++t) {
+        const bool ok = lane < g[t].rem;
+        acc[ok ? col[t] - o : spare] += ok ? g[t].w * val[t] : 0.f;
       }
+    };
+    // two register sets in turn, so that no loaded value is copied (a copy waits for its load)
+    GramChunk g0[GRAM_ITEM], g1[GRAM_ITEM];
+    int c0[GRAM_ITEM], c1[GRAM_ITEM];
+    float v0[GRAM_ITEM], v1[GRAM_ITEM];
+    // a fixed, even number of GRAM_ITEM-chunk items (the last ones may be empty): no exit test
+    // sits between a load and the add that uses it
+    const int nch = __builtin_amdgcn_readlane(pmmf_wave_incl_scan_dpp((len + PMMF_WAVE - 1) >> 6),
+                                              PMMF_WAVE - 1);
+    const int pairs = (nch + 2 * GRAM_ITEM - 1) / (2 * GRAM_ITEM);
+#pragma unroll
+    for (int t = 0; t < GRAM_ITEM; ++t) take(g0[t]);
+    load(g0, c0, v0);
+    for (int it = 0; it < pairs; ++it) {
+#pragma unroll
+      for (int t = 0; t < GRAM_ITEM; ++t) take(g1[t]);
+      load(g1, c1, v1);
+      add(g0, c0, v0);
+#pragma unroll
+      for (int t = 0; t < GRAM_ITEM; ++t) take(g0[t]);
+      load(g0, c0, v0);
+      add(g1, c1, v1);
     }
   }
   // Gram halves of the interleaved (G, D) row, then the diagonal-block halves through the same
@@ -466,8 +506,8 @@ hipError_t launch_gram(int S, const int64_t* rp, const int32_t* ci, const float*
                        float2* GD, int cmax, hipStream_t s) {
   if (S == 0) return hipSuccess;
   int wpb = 4;
-  while (wpb > 1 && (size_t)wpb * cmax * 4 > 64 * 1024) wpb >>= 1;
-  const size_t lds = (size_t)wpb * cmax * sizeof(float);
+  while (wpb > 1 && (size_t)wpb * (cmax + PMMF_WAVE) * 4 > 64 * 1024) wpb >>= 1;
+  const size_t lds = (size_t)wpb * (cmax + PMMF_WAVE) * sizeof(float);
   k_gram<<<(S + wpb - 1) / wpb, wpb * PMMF_WAVE, lds, s>>>(S, rp, ci, cv, off, cl_of, gbase,
                                                            run_ptr, run_cl, run_start, GD,
                                                            cmax);
@@ -2055,7 +2095,7 @@ __global__ void __launch_bounds__(256) k_right(int S, int fill, const int64_t* _
   const int wpb = blockDim.x / PMMF_WAVE;
   const int w = pmmf_wave(), lane = pmmf_lane();
   float* acc = lds_f + (size_t)w * cmax;
-  const int x = blockIdx.x * wpb + w;
+  const int x = pmmf_xcd_block(blockIdx.x, gridDim.x) * wpb + w;
   if (x >= S) return;
   for (int j = lane; j < cmax; j += PMMF_WAVE) acc[j] = 0.f;
   const int64_t end = rp[x + 1];
@@ -2157,9 +2197,13 @@ hipError_t launch_right(int S, int fill, const int64_t* rp, const int32_t* ci, c
 // surviving columns, renumbered to the next stage's positions; a retired row contributes
 //     2 sum_{b survives} A_p[a,b]^2 + sum_{b retired, b != a} A_p[a,b]^2
 // to the exact residual (FP64), which totals 2 sum_e m_e over the stage's retirements.
+// Rows of up to LEFT_QSMALL lists run in a launch with a small list area (more waves per CU);
+// the few longer rows, up to LEFT_QMAX lists, in a second launch.
 constexpr int LEFT_QMAX = 512;
+constexpr int LEFT_QSMALL = 64;
 constexpr int LEFT_PER_LIST = 28;  // LDS bytes per list: cur, end (int64), next column, its cluster, weight
 
+template <int QCAP>
 __global__ void __launch_bounds__(256) k_left(int S, int fill, const int64_t* __restrict__ qrp,
                                               const int32_t* __restrict__ qci,
                                               const float* __restrict__ qcv,
@@ -2180,17 +2224,20 @@ __global__ void __launch_bounds__(256) k_left(int S, int fill, const int64_t* __
   const int wpb = blockDim.x / PMMF_WAVE;
   const int w = pmmf_wave(), lane = pmmf_lane();
   char* base = reinterpret_cast<char*>(lds_f) +
-               (size_t)w * ((size_t)cmax * 4 + (size_t)LEFT_QMAX * LEFT_PER_LIST);
+               (size_t)w * ((size_t)cmax * 4 + (size_t)QCAP * LEFT_PER_LIST);
   float* acc = reinterpret_cast<float*>(base);
   int64_t* cur = reinterpret_cast<int64_t*>(base + (size_t)cmax * 4);
-  int64_t* en = cur + LEFT_QMAX;
-  int* ncol = reinterpret_cast<int*>(en + LEFT_QMAX);   // column at cur, INT_MAX when done
-  int* ncl = ncol + LEFT_QMAX;                          // its cluster
-  float* qv = reinterpret_cast<float*>(ncl + LEFT_QMAX);
-  const int a = blockIdx.x * wpb + w;
+  int64_t* en = cur + QCAP;
+  int* ncol = reinterpret_cast<int*>(en + QCAP);   // column at cur, INT_MAX when done
+  int* ncl = ncol + QCAP;                          // its cluster
+  float* qv = reinterpret_cast<float*>(ncl + QCAP);
+  // a cluster's positions read the same rows of W: keep them on one XCD
+  const int a = pmmf_xcd_block(blockIdx.x, gridDim.x) * wpb + w;
   if (a >= S) return;
   const int64_t q0 = qrp[a];
   const int nq = (int)(qrp[a + 1] - q0);
+  // each row belongs to exactly one of the two launches
+  if (QCAP == LEFT_QSMALL ? nq > LEFT_QSMALL : nq <= LEFT_QSMALL) return;
   if (nq > LEFT_QMAX) {
     if (lane == 0) {
       atomicOr(overflow, 1);
@@ -2406,19 +2453,24 @@ hipError_t launch_left(int S, int fill, const int64_t* qrp, const int32_t* qci, 
                        int32_t* cnt, const int64_t* orp, int32_t* oci, float* ocv,
                        double* loss_row, int32_t* overflow, int cmax, hipStream_t s) {
   if (S == 0) return hipSuccess;
-  const size_t per_wave = (size_t)cmax * 4 + (size_t)LEFT_QMAX * LEFT_PER_LIST;
-  int wpb = 4;
-  while (wpb > 1 && wpb * per_wave > 64 * 1024) wpb >>= 1;
-  const size_t lds = wpb * per_wave;
-  if (lds > 64 * 1024) {
-    hipError_t e = hipFuncSetAttribute((const void*)k_left,
-                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-    if (e != hipSuccess) return e;
-  }
-  k_left<<<(S + wpb - 1) / wpb, wpb * PMMF_WAVE, lds, s>>>(S, fill, qrp, qci, qcv, wrp, wcnt, wci, wcv,
-                                                           off, cl_of, next, cnt, orp, oci, ocv,
-                                                           loss_row, overflow, cmax);
-  return hipGetLastError();
+  auto go = [&](auto kern, int qcap) -> hipError_t {
+    const size_t per_wave = (size_t)cmax * 4 + (size_t)qcap * LEFT_PER_LIST;
+    int wpb = 4;
+    while (wpb > 1 && wpb * per_wave > 64 * 1024) wpb >>= 1;
+    const size_t lds = wpb * per_wave;
+    if (lds > 64 * 1024) {
+      hipError_t e = hipFuncSetAttribute((const void*)kern,
+                                         hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+      if (e != hipSuccess) return e;
+    }
+    kern<<<(S + wpb - 1) / wpb, wpb * PMMF_WAVE, lds, s>>>(S, fill, qrp, qci, qcv, wrp, wcnt, wci,
+                                                           wcv, off, cl_of, next, cnt, orp, oci,
+                                                           ocv, loss_row, overflow, cmax);
+    return hipGetLastError();
+  };
+  hipError_t e = go(k_left<LEFT_QSMALL>, LEFT_QSMALL);
+  if (e == hipSuccess) e = go(k_left<LEFT_QMAX>, LEFT_QMAX);
+  return e;
 }
 
 // ------------------------------------------------------------------------------------------
