@@ -294,11 +294,19 @@ int mmf_destroy(mmf_handle h);
  *   for.  The library waits for the device before it releases a block (as hipFree does), so an
  *   allocator that reuses memory in stream order (e.g. a caching allocator) never hands out memory
  *   still in use on another stream.  Blocks keep the allocator that produced them: a later call
- *   does not change how existing blocks are released.  Both NULL restores hipMalloc/hipFree.
+ *   does not change how existing blocks are released.  Both NULL restores the default allocator
+ *   (hipMalloc with released blocks kept for reuse, see mmf_trim).
  *   Process-wide; set it before creating handles that should use it.
  *   Errors: MMF_EINVAL when exactly one of alloc and release is NULL. */
 int mmf_set_allocator(void* (*alloc)(size_t bytes, void* stream, void* ctx),
                       void (*release)(void* ptr, void* stream, void* ctx), void* ctx);
+
+/* Free the device blocks that the default allocator keeps for reuse (waits for the device).
+ * Without a caller's allocator the library allocates with hipMalloc and keeps each released
+ * block, up to 64 GiB per process: a later allocation of at most its size (and at least half of
+ * it) on the same device takes it back, at once on the stream that released it, on another stream
+ * after a device synchronization.  Handles and buffers in use are not affected.  Always MMF_OK. */
+int mmf_trim(void);
 
 /* Thread-local text of the last error reported on this thread ("" if none). */
 const char* mmf_last_error(void);

@@ -84,6 +84,7 @@ SIGNATURES = {
     "mmf_graph_destroy": [H],
     "mmf_destroy": [H],
     "mmf_set_allocator": [ALLOC_FN, RELEASE_FN, P],
+    "mmf_trim": [],
     "mmf_last_error": [],
 }
 

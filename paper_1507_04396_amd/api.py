@@ -22,7 +22,8 @@ _ALLOCATORS = []
 
 def use_torch_allocator(enable: bool = True) -> None:
     """Route the library's later device allocations through torch's caching allocator
-    (mmf_set_allocator); ``enable=False`` restores hipMalloc/hipFree for later allocations."""
+    (mmf_set_allocator); ``enable=False`` restores the library's default allocator for later
+    allocations."""
     lib = _lib.load()
     if not enable:
         check(lib.mmf_set_allocator(_lib.ALLOC_FN(), _lib.RELEASE_FN(), None))
@@ -40,6 +41,11 @@ def use_torch_allocator(enable: bool = True) -> None:
     pair = (_lib.ALLOC_FN(alloc), _lib.RELEASE_FN(release))
     _ALLOCATORS.append(pair)
     check(lib.mmf_set_allocator(pair[0], pair[1], None))
+
+
+def trim_device_cache() -> None:
+    """Free the device blocks that the library's default allocator keeps for reuse (mmf_trim)."""
+    check(_lib.load().mmf_trim())
 
 
 def _stream(stream=None) -> ctypes.c_void_p:

@@ -29,6 +29,100 @@ void* (*g_alloc)(size_t, void*, void*) = nullptr;
 void (*g_release)(void*, void*, void*) = nullptr;
 void* g_ctx = nullptr;
 thread_local void* g_stream = nullptr;
+
+// Blocks of the default allocator.  A released block is kept for reuse: at once by later
+// allocations on the stream it was released on (stream order keeps them behind the work that
+// used it), by other streams only after the device has been synchronized since its release.
+struct Block {
+  void* p;
+  size_t bytes;
+  int dev;
+  void* stream;  // stream of the releasing call
+  bool idle;     // the device has been synchronized since the release
+};
+struct Live {
+  size_t bytes;
+  int dev;
+};
+std::vector<Block> g_kept;               // released blocks, oldest first
+std::map<void*, Live> g_out;            // blocks handed out by the default allocator
+size_t g_kept_bytes = 0;
+constexpr size_t kKeepMax = 64ull << 30;  // at most this much is kept for reuse
+
+// best-fitting kept block for `bytes` on `dev` (sizes up to twice the request), or -1
+int fit(size_t bytes, int dev, void* stream, bool usable_only) {
+  int best = -1;
+  for (int i = 0; i < (int)g_kept.size(); ++i) {
+    const Block& b = g_kept[i];
+    if (b.dev != dev || b.bytes < bytes || b.bytes > 2 * bytes) continue;
+    if (usable_only && !b.idle && b.stream != stream) continue;
+    if (best < 0 || b.bytes < g_kept[best].bytes) best = i;
+  }
+  return best;
+}
+
+// frees every kept block (after waiting for the device); g_mu must not be held
+void drop_kept() {
+  std::vector<Block> all;
+  {
+    std::lock_guard<std::mutex> lk(g_mu);
+    all.swap(g_kept);
+    g_kept_bytes = 0;
+  }
+  for (const Block& b : all) (void)hipFree(b.p);
+}
+
+void* default_alloc(size_t bytes) {
+  int dev = 0;
+  (void)hipGetDevice(&dev);
+  void* const stream = g_stream;
+  for (int pass = 0; pass < 2; ++pass) {
+    {
+      std::lock_guard<std::mutex> lk(g_mu);
+      int i = fit(bytes, dev, stream, true);
+      if (i >= 0) {
+        const Block b = g_kept[i];
+        g_kept.erase(g_kept.begin() + i);
+        g_kept_bytes -= b.bytes;
+        g_out[b.p] = Live{b.bytes, dev};
+        return b.p;
+      }
+      if (pass == 1 || fit(bytes, dev, stream, false) < 0) break;
+    }
+    // a kept block would fit once the work that used it has finished
+    (void)hipDeviceSynchronize();
+    std::lock_guard<std::mutex> lk(g_mu);
+    for (Block& b : g_kept) b.idle = true;
+  }
+  void* p = nullptr;
+  if (hipMalloc(&p, bytes) != hipSuccess) {
+    (void)hipGetLastError();
+    drop_kept();
+    p = nullptr;
+    if (hipMalloc(&p, bytes) != hipSuccess) return nullptr;
+  }
+  std::lock_guard<std::mutex> lk(g_mu);
+  g_out[p] = Live{bytes, dev};
+  return p;
+}
+
+void default_release(void* p) {
+  std::vector<void*> drop;
+  {
+    std::lock_guard<std::mutex> lk(g_mu);
+    auto it = g_out.find(p);
+    if (it == g_out.end()) return;
+    g_kept.push_back(Block{p, it->second.bytes, it->second.dev, g_stream, false});
+    g_kept_bytes += it->second.bytes;
+    g_out.erase(it);
+    while (g_kept_bytes > kKeepMax && !g_kept.empty()) {
+      drop.push_back(g_kept.front().p);
+      g_kept_bytes -= g_kept.front().bytes;
+      g_kept.erase(g_kept.begin());
+    }
+  }
+  for (void* q : drop) (void)hipFree(q);  // hipFree waits for the device
+}
 }  // namespace
 
 void* alloc(size_t bytes, How* how) {
@@ -48,8 +142,7 @@ void* alloc(size_t bytes, How* how) {
     return a(bytes, g_stream, ctx);
   }
   *how = How{};
-  void* p = nullptr;
-  return hipMalloc(&p, bytes) == hipSuccess ? p : nullptr;
+  return default_alloc(bytes);
 }
 
 void release(void* p, const How& how) {
@@ -58,9 +151,11 @@ void release(void* p, const How& how) {
     (void)hipDeviceSynchronize();
     how.release(p, how.stream, how.ctx);
   } else {
-    (void)hipFree(p);
+    default_release(p);
   }
 }
+
+void trim() { drop_kept(); }
 
 StreamScope::StreamScope(void* stream) : prev(g_stream) { g_stream = stream; }
 StreamScope::~StreamScope() { g_stream = prev; }
@@ -519,6 +614,12 @@ extern "C" int mmf_set_allocator(void* (*alloc)(size_t, void*, void*),
     return MMF_EINVAL;
   }
   pmmf_alloc::set(alloc, release, ctx);
+  return MMF_OK;
+}
+
+extern "C" int mmf_trim(void) {
+  g_err.clear();
+  pmmf_alloc::trim();
   return MMF_OK;
 }
 

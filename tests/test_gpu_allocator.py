@@ -61,3 +61,35 @@ def test_torch_allocator_same_results_and_all_memory_returned():
     _say(f"[alloc] handle held {held} bytes of torch memory; after destroy "
          f"{torch.cuda.memory_allocated() - base}")
     assert torch.cuda.memory_allocated() == base
+
+
+def test_kept_blocks_reused_on_same_and_other_stream():
+    """The default allocator keeps released blocks: a second factorization on the same stream, one
+    on another stream, and one after mmf_trim all reproduce the first bit for bit."""
+    from paper_1507_04396_amd.api import Factorization, trim_device_cache
+    A = workloads.knn_points_matrix(700, 2, 8, 0.01, 6)
+    params = dict(k=2, core=40, cluster=(32, 128), seed=2)
+    _say("[alloc] first factorization (fresh blocks)")
+    f = Factorization.from_csr(A, **params)
+    ref = f.export()
+    f.close()
+    _say("[alloc] second factorization, same stream (kept blocks)")
+    f = Factorization.from_csr(A, **params)
+    for key, want in ref.items():
+        assert np.array_equal(f.export()[key], want), key
+    f.close()
+    side = torch.cuda.Stream()
+    _say("[alloc] factorization on another stream (kept blocks after a device sync)")
+    with torch.cuda.stream(side):
+        f = Factorization.from_csr(A, **params)
+        got = f.export()
+    side.synchronize()
+    for key, want in ref.items():
+        assert np.array_equal(got[key], want), key
+    f.close()
+    _say("[alloc] trim, then a factorization on fresh blocks")
+    trim_device_cache()
+    f = Factorization.from_csr(A, **params)
+    for key, want in ref.items():
+        assert np.array_equal(f.export()[key], want), key
+    f.close()
