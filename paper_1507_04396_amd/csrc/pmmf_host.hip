@@ -226,10 +226,52 @@ void upload(DBuf& d, const std::vector<T>& h, hipStream_t s) {
   HIPCHK(hipStreamSynchronize(s));
 }
 
+// Host -> device copies that do not wait: the data is copied into a pinned staging area of the
+// calling thread, which is reused once the stream its copies were queued on has been waited for
+// (staging_synced, called after each such wait) or by waiting for it when the area is full.
+struct Staging {
+  char* buf = nullptr;
+  size_t cap = 0, used = 0;
+  hipStream_t stream = nullptr;  // stream of the copies not known to be complete (used > 0)
+  ~Staging() {
+    if (buf) (void)hipHostFree(buf);
+  }
+};
+thread_local Staging g_staging;
+
+void staging_synced(hipStream_t s) {
+  if (g_staging.stream == s) g_staging.used = 0;
+}
+
+template <class T>
+void upload_async(DBuf& d, const std::vector<T>& h, hipStream_t s) {
+  d.ensure(h.size() * sizeof(T));
+  if (h.empty()) return;
+  Staging& g = g_staging;
+  const size_t b = h.size() * sizeof(T);
+  if (g.used > 0 && (g.stream != s || g.used + b > g.cap)) {
+    HIPCHK(hipStreamSynchronize(g.stream));
+    g.used = 0;
+  }
+  if (b > g.cap) {
+    if (g.buf) HIPCHK(hipHostFree(g.buf));
+    g.buf = nullptr;
+    g.cap = 0;
+    const size_t cap = std::max<size_t>(b, 64 * 1024);
+    HIPCHK(hipHostMalloc((void**)&g.buf, cap, hipHostMallocDefault));
+    g.cap = cap;
+  }
+  std::memcpy(g.buf + g.used, h.data(), b);
+  HIPCHK(hipMemcpyAsync(d.p, g.buf + g.used, b, hipMemcpyHostToDevice, s));
+  g.used = (g.used + b + 255) & ~(size_t)255;
+  g.stream = s;
+}
+
 int64_t read_i64(const int64_t* dptr, hipStream_t s) {
   int64_t v = 0;
   HIPCHK(hipMemcpyAsync(&v, dptr, sizeof(v), hipMemcpyDeviceToHost, s));
   HIPCHK(hipStreamSynchronize(s));
+  staging_synced(s);
   return v;
 }
 
@@ -411,11 +453,11 @@ void build_stage_geometry(StageDev& sd, const SchedStage& sc, int64_t rot_base, 
   for (int u = 0; u < sd.m; ++u) order[u] = u;
   std::stable_sort(order.begin(), order.end(),
                    [&](int a, int b) { return sc.sizes[a] > sc.sizes[b]; });
-  upload(sd.off, sd.off_h, s);
-  upload(sd.rcnt, sd.rcnt_h, s);
-  upload(sd.roff, sd.roff_h, s);
-  upload(sd.order, order, s);
-  upload(sd.gbase, sd.gbase_h, s);
+  upload_async(sd.off, sd.off_h, s);
+  upload_async(sd.rcnt, sd.rcnt_h, s);
+  upload_async(sd.roff, sd.roff_h, s);
+  upload_async(sd.order, order, s);
+  upload_async(sd.gbase, sd.gbase_h, s);
   sd.next.ensure(sd.size * sizeof(int32_t));
   sd.gid.ensure(sd.size * sizeof(int32_t));
   sd.cl_of.ensure(sd.size * sizeof(int32_t));
@@ -777,6 +819,7 @@ extern "C" int mmf_factor(int64_t n, int64_t nnz, const int64_t* d_rowptr, const
   DBuf stage_loss;
   stage_loss.ensure(std::max<size_t>(sched.size(), 1) * sizeof(double));
 
+  std::vector<std::unique_ptr<PhaseEvents>> stage_events;
   for (size_t pi = 0; pi < sched.size(); ++pi) {
     const SchedStage& sc = sched[pi];
     auto sdp = std::make_unique<StageDev>();
@@ -789,7 +832,9 @@ extern "C" int mmf_factor(int64_t n, int64_t nnz, const int64_t* d_rowptr, const
     else HIPCHK(hipMemcpyAsync(sd.gid.p, gid_cur.p, S * sizeof(int32_t), hipMemcpyDeviceToDevice, s));
     HIPCHK(hipMemsetAsync(retflag.p, 0, S, s));
 
-    PhaseEvents pev;
+    // phase timings, read once the factorization has finished
+    stage_events.push_back(std::make_unique<PhaseEvents>());
+    PhaseEvents& pev = *stage_events.back();
     HIPCHK(hipEventRecord(pev.e[0], s));
     // cluster Grams, diagonal blocks, identity accumulators: sparse row merges, or dense column
     // slices on the matrix cores once the active matrix is dense enough
@@ -837,7 +882,8 @@ extern "C" int mmf_factor(int64_t n, int64_t nnz, const int64_t* d_rowptr, const
       run_ptr.ensure((S + 1) * sizeof(int64_t));
       HIPCHK(pmmf::launch_scan(cnt.as<int32_t>(), run_ptr.as<int64_t>(), S,
                                scan_tmp.as<int64_t>(), s));
-      const int64_t nrun = read_i64(run_ptr.as<int64_t>() + S, s);
+      // a run holds at least one entry, and a row meets each cluster in at most one run
+      const int64_t nrun = std::min<int64_t>(M.nnz, (int64_t)S * sd.m);
       run_cl.ensure(std::max<int64_t>(nrun, 1) * sizeof(int32_t));
       run_start.ensure(std::max<int64_t>(nrun, 1) * sizeof(int64_t));
       HIPCHK(pmmf::launch_runs(S, 1, M.rp.as<int64_t>(), M.ci.as<int32_t>(),
@@ -921,7 +967,7 @@ extern "C" int mmf_factor(int64_t n, int64_t nnz, const int64_t* d_rowptr, const
         const int64_t nt = (c + 31) / 32;
         tb[u + 1] = tb[u] + nt * nt;
       }
-      upload(tbase, tb, s);
+      upload_async(tbase, tb, s);
       HIPCHK(pmmf::launch_transpose_blocks(sd.m, sd.off.as<int32_t>(), sd.gbase.as<int64_t>(),
                                            tbase.as<int64_t>(), tb[sd.m], Q.as<float>(),
                                            GD.as<float>(), s));
@@ -934,7 +980,8 @@ extern "C" int mmf_factor(int64_t n, int64_t nnz, const int64_t* d_rowptr, const
       HIPCHK(pmmf::launch_qbar_count(S, sd.off.as<int32_t>(), sd.cl_of.as<int32_t>(),
                                      sd.gbase.as<int64_t>(), pool_src, cnt.as<int32_t>(), s));
       HIPCHK(pmmf::launch_scan(cnt.as<int32_t>(), Z.rp.as<int64_t>(), S, scan_tmp.as<int64_t>(), s));
-      Z.nnz = read_i64(Z.rp.as<int64_t>() + S, s);
+      // Qbar^T has the entries of Qbar
+      Z.nnz = which == 0 ? read_i64(Z.rp.as<int64_t>() + S, s) : Qr.nnz;
       Z.ci.ensure(std::max<int64_t>(Z.nnz, 1) * sizeof(int32_t));
       Z.cv.ensure(std::max<int64_t>(Z.nnz, 1) * sizeof(float));
       HIPCHK(pmmf::launch_qbar_fill(S, sd.off.as<int32_t>(), sd.cl_of.as<int32_t>(),
@@ -971,17 +1018,22 @@ extern "C" int mmf_factor(int64_t n, int64_t nnz, const int64_t* d_rowptr, const
                              sd.next.as<int32_t>(), cnt.as<int32_t>(), abase.as<int64_t>(),
                              stage_ci.as<int32_t>(), stage_cv.as<float>(), loss_row.as<double>(),
                              overflow.as<int32_t>(), cm, s));
-    {
-      int32_t fl2[2] = {0, 0};
-      HIPCHK(hipMemcpyAsync(fl2, overflow.p, 2 * sizeof(int32_t), hipMemcpyDeviceToHost, s));
-      HIPCHK(hipStreamSynchronize(s));
-      if (fl2[1]) raise(MMF_EDEVICE, "greedy search found no partner in a cluster");
-      if (fl2[0]) raise(MMF_ECAPACITY, "a row of Qbar has more than 512 entries");
-    }
     M2.n = Snext;
     M2.rp.ensure((Snext + 1) * sizeof(int64_t));
     HIPCHK(pmmf::launch_scan(cnt.as<int32_t>(), M2.rp.as<int64_t>(), Snext, scan_tmp.as<int64_t>(), s));
-    M2.nnz = read_i64(M2.rp.as<int64_t>() + Snext, s);
+    {
+      // the error flags and the next active matrix's entry count, in one wait
+      int32_t fl2[2] = {0, 0};
+      int64_t nnz2 = 0;
+      HIPCHK(hipMemcpyAsync(fl2, overflow.p, 2 * sizeof(int32_t), hipMemcpyDeviceToHost, s));
+      HIPCHK(hipMemcpyAsync(&nnz2, M2.rp.as<int64_t>() + Snext, sizeof(int64_t),
+                            hipMemcpyDeviceToHost, s));
+      HIPCHK(hipStreamSynchronize(s));
+      staging_synced(s);
+      if (fl2[1]) raise(MMF_EDEVICE, "greedy search found no partner in a cluster");
+      if (fl2[0]) raise(MMF_ECAPACITY, "a row of Qbar has more than 512 entries");
+      M2.nnz = nnz2;
+    }
     M2.ci.ensure(std::max<int64_t>(M2.nnz, 1) * sizeof(int32_t));
     M2.cv.ensure(std::max<int64_t>(M2.nnz, 1) * sizeof(float));
     HIPCHK(pmmf::launch_compact_rows(Snext, abase.as<int64_t>(), cnt.as<int32_t>(),
@@ -990,10 +1042,6 @@ extern "C" int mmf_factor(int64_t n, int64_t nnz, const int64_t* d_rowptr, const
                                      s));
     HIPCHK(hipEventRecord(pev.e[3], s));
     HIPCHK(pmmf::launch_sum_double(loss_row.as<double>(), S, stage_loss.as<double>() + pi, s));
-    HIPCHK(hipEventSynchronize(pev.e[3]));
-    sd.gram_ms = pev.ms(0, 1);
-    sd.find_ms = pev.ms(1, 2);
-    sd.rotate_ms = pev.ms(2, 3);
     M.rp.swap_with(M2.rp);
     M.ci.swap_with(M2.ci);
     M.cv.swap_with(M2.cv);
@@ -1028,7 +1076,15 @@ extern "C" int mmf_factor(int64_t n, int64_t nnz, const int64_t* d_rowptr, const
                           hipMemcpyDeviceToHost, s));
   HIPCHK(hipMemcpyAsync(&ovf, overflow.p, sizeof(ovf), hipMemcpyDeviceToHost, s));
   HIPCHK(hipStreamSynchronize(s));
+  staging_synced(s);
   if (ovf) raise(MMF_ECAPACITY, "a row of a stage rotation had more than 512 terms");
+  for (size_t pi = 0; pi < stage_events.size(); ++pi) {
+    StageDev& sd = *h->st[pi];
+    const PhaseEvents& pev = *stage_events[pi];
+    sd.gram_ms = pev.ms(0, 1);
+    sd.find_ms = pev.ms(1, 2);
+    sd.rotate_ms = pev.ms(2, 3);
+  }
   float ms = 0.f;
   HIPCHK(hipEventElapsedTime(&ms, ev0, ev1));
   (void)hipEventDestroy(ev0);
