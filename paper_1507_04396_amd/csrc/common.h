@@ -114,6 +114,18 @@ __device__ inline int pmmf_wave_incl_scan_dpp(int v) {
   return v;
 }
 
+// inclusive maximum over the lanes of a wave through DPP, for values >= -1 (-1 is the identity);
+// same shifts and broadcasts as the prefix sum above.  Every lane must be active.
+__device__ inline int pmmf_wave_incl_max_dpp(int v) {
+  v = max(v, __builtin_amdgcn_update_dpp(-1, v, 0x111, 0xf, 0xf, false));  // row_shr:1
+  v = max(v, __builtin_amdgcn_update_dpp(-1, v, 0x112, 0xf, 0xf, false));  // row_shr:2
+  v = max(v, __builtin_amdgcn_update_dpp(-1, v, 0x114, 0xf, 0xf, false));  // row_shr:4
+  v = max(v, __builtin_amdgcn_update_dpp(-1, v, 0x118, 0xf, 0xf, false));  // row_shr:8
+  v = max(v, __builtin_amdgcn_update_dpp(-1, v, 0x142, 0xa, 0xf, false));  // row_bcast:15
+  v = max(v, __builtin_amdgcn_update_dpp(-1, v, 0x143, 0xc, 0xf, false));  // row_bcast:31
+  return v;
+}
+
 // position of the n-th (0-based) set bit of m, n < popcount(m): binary search on popcounts
 __device__ inline int pmmf_nth_bit(uint32_t m, int n) {
   int pos = 0;

@@ -2078,7 +2078,10 @@ hipError_t launch_qbar_fill(int S, const int32_t* off, const int32_t* cl_of,
 // Right rotation W = M Qbar^T (the column half of [[A_p]]_{u,v} = Qbar_u [[A_{p-1}]]_{u,v}
 // Qbar_v^T in Alg. 1).  One wave per row x; the row's entries are grouped into runs of one
 // cluster v, and each run is expanded through Qbar_v^T in a dense LDS accumulator of c_v slots,
-// summing in ascending entry order (deterministic).  fill = 0 counts, fill = 1 writes.
+// list by list in ascending entry order (lanes of one chunk that meet at a column from different
+// lists are combined by the LDS atomic add, in the hardware's fixed lane order).  fill = 0 counts,
+// fill = 1 writes.
+constexpr int RIGHT_CH = 2;  // flat 64-entry chunks whose loads are requested together
 __global__ void __launch_bounds__(256) k_right(int S, int fill, const int64_t* __restrict__ rp,
                                                const int32_t* __restrict__ ci,
                                                const float* __restrict__ cv,
@@ -2094,7 +2097,9 @@ __global__ void __launch_bounds__(256) k_right(int S, int fill, const int64_t* _
   extern __shared__ float lds_f[];
   const int wpb = blockDim.x / PMMF_WAVE;
   const int w = pmmf_wave(), lane = pmmf_lane();
-  float* acc = lds_f + (size_t)w * cmax;
+  // cmax accumulator slots, then the list heads of RIGHT_CH flat chunks
+  float* acc = lds_f + (size_t)w * (cmax + RIGHT_CH * PMMF_WAVE);
+  int* head = reinterpret_cast<int*>(acc + cmax);
   const int x = pmmf_xcd_block(blockIdx.x, gridDim.x) * wpb + w;
   if (x >= S) return;
   for (int j = lane; j < cmax; j += PMMF_WAVE) acc[j] = 0.f;
@@ -2117,41 +2122,56 @@ __global__ void __launch_bounds__(256) k_right(int S, int fill, const int64_t* _
     for (int64_t kb = k; kb < kend; kb += PMMF_WAVE) {
       // lane-parallel lookup of the Qbar^T rows of up to 64 entries y of the run
       const int nb = (int)min<int64_t>(PMMF_WAVE, kend - kb);
-      int64_t q0 = 0, q1 = 0;
+      int64_t q0 = 0;
+      int len = 0;
       float mv = 0.f;
       if (lane < nb) {
         const int y = ci[kb + lane];
         mv = cv[kb + lane];
         q0 = qrp[y];
-        q1 = qrp[y + 1];
+        len = (int)(qrp[y + 1] - q0);
       }
-      // expand them in ascending entry order, first chunks of four rows loaded together
-      for (int t = 0; t < nb; t += 4) {
-        int64_t sl[4], su[4];
-        float sw[4], pv[4];
-        int pc[4];
+      // The lists, in entry order, form one flat sequence of T entries (a list of ~10-20 entries
+      // would leave most of a 64-lane chunk idle); flat position f of list l is entry
+      // q0_l + f - P_l.  Lanes of one chunk may hit the same column from different lists, hence
+      // the LDS atomic add.
+      const int incl = pmmf_wave_incl_scan_dpp(len);
+      const int P = incl - len;
+      const int T = __builtin_amdgcn_readlane(incl, PMMF_WAVE - 1);
+      const int64_t lbase = q0 - P;
+      int carry = -1;  // list of the last flat position so far
+      for (int f0 = 0; f0 < T; f0 += RIGHT_CH * PMMF_WAVE) {
+        int cc[RIGHT_CH];
+        float vv[RIGHT_CH];
+        bool ok[RIGHT_CH];
 #pragma unroll
-        for (int q = 0; q < 4; ++q) {
-          const int tt = min(t + q, nb - 1);
-          sl[q] = __shfl(q0, tt);
-          su[q] = __shfl(q1, tt);
-          sw[q] = __shfl(mv, tt);
-          if (t + q >= nb) su[q] = sl[q];
-          const int64_t e = sl[q] + lane;
-          pc[q] = e < su[q] ? qci[e] : ov;
-          pv[q] = e < su[q] ? qcv[e] : 0.f;
+        for (int h = 0; h < RIGHT_CH; ++h) {
+          // the list of each flat position: list l marks its start, a running maximum fills in.
+          // The marks cross lanes through LDS, so they are atomic accesses ordered by a
+          // wavefront fence (plain accesses would let each lane see only its own writes).
+          int* hd = head + h * PMMF_WAVE;
+          __hip_atomic_store(hd + lane, -1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT);
+          const int rel = P - (f0 + h * PMMF_WAVE);
+          if (len > 0 && rel >= 0 && rel < PMMF_WAVE)
+            __hip_atomic_store(hd + rel, lane, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT);
+          __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+          __builtin_amdgcn_wave_barrier();
+          const int mark = __hip_atomic_load(hd + lane, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT);
+          int l = max(pmmf_wave_incl_max_dpp(mark), carry);
+          carry = __builtin_amdgcn_readlane(l, PMMF_WAVE - 1);
+          l = max(l, 0);
+          const int f = f0 + h * PMMF_WAVE + lane;
+          ok[h] = f < T;
+          const int64_t e = __shfl(lbase, l) + f;
+          vv[h] = __shfl(mv, l);
+          cc[h] = ok[h] ? qci[e] : ov;
+          vv[h] = ok[h] ? vv[h] * qcv[e] : 0.f;
         }
 #pragma unroll
-        for (int q = 0; q < 4; ++q) {
-          if (sl[q] + lane < su[q]) {
-            const int b = pc[q] - ov;
-            acc[b] += sw[q] * pv[q];
-            bmin = min(bmin, b);
-            bmax = max(bmax, b);
-          }
-          for (int64_t e = sl[q] + PMMF_WAVE + lane; e < su[q]; e += PMMF_WAVE) {
-            const int b = qci[e] - ov;
-            acc[b] += sw[q] * qcv[e];
+        for (int h = 0; h < RIGHT_CH; ++h) {
+          if (ok[h]) {
+            const int b = cc[h] - ov;
+            __hip_atomic_fetch_add(acc + b, vv[h], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
             bmin = min(bmin, b);
             bmax = max(bmax, b);
           }
@@ -2183,8 +2203,8 @@ hipError_t launch_right(int S, int fill, const int64_t* rp, const int32_t* ci, c
                         int32_t* oci, float* ocv, int cmax, hipStream_t s) {
   if (S == 0) return hipSuccess;
   int wpb = 4;
-  while (wpb > 1 && (size_t)wpb * cmax * 4 > 64 * 1024) wpb >>= 1;
-  const size_t lds = (size_t)wpb * cmax * sizeof(float);
+  while (wpb > 1 && (size_t)wpb * (cmax + RIGHT_CH * PMMF_WAVE) * 4 > 64 * 1024) wpb >>= 1;
+  const size_t lds = (size_t)wpb * (cmax + RIGHT_CH * PMMF_WAVE) * sizeof(float);
   k_right<<<(S + wpb - 1) / wpb, wpb * PMMF_WAVE, lds, s>>>(S, fill, rp, ci, cv, off, cl_of, qrp,
                                                             qci, qcv, cnt, orp, oci, ocv, cmax);
   return hipGetLastError();
