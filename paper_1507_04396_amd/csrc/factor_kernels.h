@@ -74,9 +74,6 @@ hipError_t launch_build_q(int m, int k, const int32_t* off, const int64_t* gbase
                           const int32_t* lvl_ptr, int lvl_stride, const int32_t* depth,
                           const int32_t* sw_loc, const float* sw_o, float* Q, int cmax,
                           hipStream_t s);
-hipError_t launch_transpose_blocks(int m, const int32_t* off, const int64_t* gbase,
-                                   const int64_t* tbase, int64_t ntiles, const float* src,
-                                   float* dst, hipStream_t s);
 hipError_t launch_qbar_count(int S, const int32_t* off, const int32_t* cl_of,
                              const int64_t* gbase, const float* Q, int32_t* cnt, hipStream_t s);
 hipError_t launch_qbar_fill(int S, const int32_t* off, const int32_t* cl_of,
@@ -104,6 +101,11 @@ hipError_t launch_next_positions(int S, const uint8_t* retflag, const int64_t* s
                                  hipStream_t s);
 hipError_t launch_keep_flags(int S, const uint8_t* retflag, int32_t* keep, hipStream_t s);
 hipError_t launch_scan(const int32_t* in, int64_t* out, int64_t n, int64_t* tmp, hipStream_t s);
+// CSR transpose of an n x n matrix (rows of the result in arbitrary entry order): cnt (n ints) and
+// cursor (n int64) are scratch, tmp as for launch_scan; trp receives n + 1 row pointers
+hipError_t launch_csr_transpose(int n, int64_t nnz, const int64_t* rp, const int32_t* ci,
+                                const float* cv, int32_t* cnt, int64_t* trp, int64_t* tmp,
+                                int64_t* cursor, int32_t* tci, float* tcv, hipStream_t s);
 int64_t scan_tmp_elems(int64_t n);
 hipError_t launch_sum_double(const double* in, int64_t n, double* out, hipStream_t s);
 hipError_t launch_csr_stats(int64_t n, const int64_t* rp, const int32_t* ci, const float* cv,

@@ -1983,46 +1983,6 @@ hipError_t launch_levelize(int m, int k, const int32_t* off, const int32_t* rcnt
   return hipGetLastError();
 }
 
-// ------------------------------------------------------------------------------------------
-// Dense transpose of every cluster's c x c block (src -> dst, same pool layout), 32 x 32 tiles
-// through LDS so both sides are coalesced.  grid.x = tile index over all clusters.
-__global__ void k_transpose_blocks(int m, const int32_t* __restrict__ off,
-                                   const int64_t* __restrict__ gbase,
-                                   const int64_t* __restrict__ tbase,
-                                   const float* __restrict__ src, float* __restrict__ dst) {
-  __shared__ float tile[32][33];
-  // find the cluster owning this tile (tbase = prefix of tiles per cluster)
-  const int64_t t = blockIdx.x;
-  int lo = 0, hi = m - 1;
-  while (lo < hi) {
-    const int mid = (lo + hi + 1) >> 1;
-    if (tbase[mid] <= t) lo = mid; else hi = mid - 1;
-  }
-  const int u = lo;
-  const int c = off[u + 1] - off[u];
-  const int nt = (c + 31) / 32;
-  const int64_t lt = t - tbase[u];
-  const int tr = (int)(lt / nt), tc = (int)(lt % nt);
-  const float* S = src + gbase[u];
-  float* Dd = dst + gbase[u];
-  const int x = threadIdx.x & 31, y0 = threadIdx.x >> 5;
-  for (int y = y0; y < 32; y += blockDim.x / 32) {
-    const int r = tr * 32 + y, cc = tc * 32 + x;
-    tile[y][x] = (r < c && cc < c) ? S[(size_t)r * c + cc] : 0.f;
-  }
-  __syncthreads();
-  for (int y = y0; y < 32; y += blockDim.x / 32) {
-    const int r = tc * 32 + y, cc = tr * 32 + x;
-    if (r < c && cc < c) Dd[(size_t)r * c + cc] = tile[x][y];
-  }
-}
-hipError_t launch_transpose_blocks(int m, const int32_t* off, const int64_t* gbase,
-                                   const int64_t* tbase, int64_t ntiles, const float* src,
-                                   float* dst, hipStream_t s) {
-  if (ntiles == 0) return hipSuccess;
-  k_transpose_blocks<<<(unsigned)ntiles, 256, 0, s>>>(m, off, gbase, tbase, src, dst);
-  return hipGetLastError();
-}
 
 // ------------------------------------------------------------------------------------------
 // Sparse rows of Qbar from the dense per-cluster accumulators (rows of Qbar^T from their
@@ -2057,6 +2017,45 @@ __global__ void k_qbar(int S, int fill, const int32_t* __restrict__ off,
     total += __popcll(b);
   }
   if (!fill && lane == 0) cnt[a] = total;
+}
+
+// Transpose of a CSR matrix (n x n): column counts, then each entry placed at its column's next
+// free slot.  Entries of one output row land in arbitrary order, which is enough for Qbar^T: its
+// rows are only expanded as whole lists whose entries hit distinct columns.
+__global__ void k_csr_col_count(int64_t nnz, const int32_t* __restrict__ ci,
+                                int32_t* __restrict__ cnt) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t < nnz) atomicAdd(cnt + ci[t], 1);
+}
+
+__global__ void k_csr_transpose_fill(int n, const int64_t* __restrict__ rp,
+                                     const int32_t* __restrict__ ci, const float* __restrict__ cv,
+                                     unsigned long long* __restrict__ cursor,
+                                     int32_t* __restrict__ tci, float* __restrict__ tcv) {
+  const int a = blockIdx.x * (blockDim.x / PMMF_WAVE) + pmmf_wave();
+  if (a >= n) return;
+  for (int64_t t = rp[a] + pmmf_lane(); t < rp[a + 1]; t += PMMF_WAVE) {
+    const int64_t pos = (int64_t)atomicAdd(cursor + ci[t], 1ull);
+    tci[pos] = a;
+    tcv[pos] = cv[t];
+  }
+}
+
+hipError_t launch_csr_transpose(int n, int64_t nnz, const int64_t* rp, const int32_t* ci,
+                                const float* cv, int32_t* cnt, int64_t* trp, int64_t* tmp,
+                                int64_t* cursor, int32_t* tci, float* tcv, hipStream_t s) {
+  if (n == 0) return hipSuccess;
+  hipError_t e = hipMemsetAsync(cnt, 0, (size_t)n * sizeof(int32_t), s);
+  if (e != hipSuccess) return e;
+  if (nnz > 0) k_csr_col_count<<<(unsigned)((nnz + 255) / 256), 256, 0, s>>>(nnz, ci, cnt);
+  e = launch_scan(cnt, trp, n, tmp, s);
+  if (e != hipSuccess) return e;
+  e = hipMemcpyAsync(cursor, trp, (size_t)n * sizeof(int64_t), hipMemcpyDeviceToDevice, s);
+  if (e != hipSuccess) return e;
+  k_csr_transpose_fill<<<(n + 3) / 4, 256, 0, s>>>(n, rp, ci, cv,
+                                                   reinterpret_cast<unsigned long long*>(cursor),
+                                                   tci, tcv);
+  return hipGetLastError();
 }
 
 hipError_t launch_qbar_count(int S, const int32_t* off, const int32_t* cl_of,

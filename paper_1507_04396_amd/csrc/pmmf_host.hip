@@ -796,9 +796,10 @@ extern "C" int mmf_factor(int64_t n, int64_t nnz, const int64_t* d_rowptr, const
     for (int32_t c : sc.sizes) g += (int64_t)c * c;
     pool = std::max(pool, g);
   }
-  DBuf GD, Q, retflag, keep, scan, cnt, loss_row, overflow, gid_cur, tbase, dense_buf;
+  DBuf GD, Q, retflag, keep, scan, cnt, loss_row, overflow, gid_cur, dense_buf;
   DBuf bf_bm, bf_pre, bf_R, bf_off, bf_slab, bf_slab16, bf_stats;  // BF16 form only
   DBuf wstart, wcnt, abase, stage_ci, stage_cv;  // staging rows of the two products
+  DBuf tcur;                                     // column cursors of the Qbar transpose
   DBuf run_ptr, run_cl, run_start;                 // run table of the active matrix
   if (p->gram_mode == 1) bf_stats.ensure(2 * sizeof(unsigned long long));
   GD.ensure(pool * sizeof(float2));
@@ -959,35 +960,28 @@ extern "C" int mmf_factor(int64_t n, int64_t nnz, const int64_t* d_rowptr, const
                                        gid_new.as<int32_t>(), s));
     const int64_t Snext = sd.size - sd.t;
 
-    // sparse Qbar and Qbar^T (the Gram pool is free now and receives the transposes)
-    {
-      std::vector<int64_t> tb(sd.m + 1, 0);
-      for (int u = 0; u < sd.m; ++u) {
-        const int64_t c = sd.off_h[u + 1] - sd.off_h[u];
-        const int64_t nt = (c + 31) / 32;
-        tb[u + 1] = tb[u] + nt * nt;
-      }
-      upload_async(tbase, tb, s);
-      HIPCHK(pmmf::launch_transpose_blocks(sd.m, sd.off.as<int32_t>(), sd.gbase.as<int64_t>(),
-                                           tbase.as<int64_t>(), tb[sd.m], Q.as<float>(),
-                                           GD.as<float>(), s));
-    }
-    for (int which = 0; which < 2; ++which) {
-      Csr& Z = which == 0 ? Qr : Qt;
-      const float* pool_src = which == 0 ? Q.as<float>() : GD.as<float>();
-      Z.n = S;
-      Z.rp.ensure((S + 1) * sizeof(int64_t));
-      HIPCHK(pmmf::launch_qbar_count(S, sd.off.as<int32_t>(), sd.cl_of.as<int32_t>(),
-                                     sd.gbase.as<int64_t>(), pool_src, cnt.as<int32_t>(), s));
-      HIPCHK(pmmf::launch_scan(cnt.as<int32_t>(), Z.rp.as<int64_t>(), S, scan_tmp.as<int64_t>(), s));
-      // Qbar^T has the entries of Qbar
-      Z.nnz = which == 0 ? read_i64(Z.rp.as<int64_t>() + S, s) : Qr.nnz;
-      Z.ci.ensure(std::max<int64_t>(Z.nnz, 1) * sizeof(int32_t));
-      Z.cv.ensure(std::max<int64_t>(Z.nnz, 1) * sizeof(float));
-      HIPCHK(pmmf::launch_qbar_fill(S, sd.off.as<int32_t>(), sd.cl_of.as<int32_t>(),
-                                    sd.gbase.as<int64_t>(), pool_src, Z.rp.as<int64_t>(),
-                                    Z.ci.as<int32_t>(), Z.cv.as<float>(), s));
-    }
+    // sparse Qbar from the dense per-cluster accumulators, then its transpose
+    Qr.n = S;
+    Qr.rp.ensure((S + 1) * sizeof(int64_t));
+    HIPCHK(pmmf::launch_qbar_count(S, sd.off.as<int32_t>(), sd.cl_of.as<int32_t>(),
+                                   sd.gbase.as<int64_t>(), Q.as<float>(), cnt.as<int32_t>(), s));
+    HIPCHK(pmmf::launch_scan(cnt.as<int32_t>(), Qr.rp.as<int64_t>(), S, scan_tmp.as<int64_t>(), s));
+    Qr.nnz = read_i64(Qr.rp.as<int64_t>() + S, s);
+    Qr.ci.ensure(std::max<int64_t>(Qr.nnz, 1) * sizeof(int32_t));
+    Qr.cv.ensure(std::max<int64_t>(Qr.nnz, 1) * sizeof(float));
+    HIPCHK(pmmf::launch_qbar_fill(S, sd.off.as<int32_t>(), sd.cl_of.as<int32_t>(),
+                                  sd.gbase.as<int64_t>(), Q.as<float>(), Qr.rp.as<int64_t>(),
+                                  Qr.ci.as<int32_t>(), Qr.cv.as<float>(), s));
+    Qt.n = S;
+    Qt.nnz = Qr.nnz;
+    Qt.rp.ensure((S + 1) * sizeof(int64_t));
+    Qt.ci.ensure(std::max<int64_t>(Qt.nnz, 1) * sizeof(int32_t));
+    Qt.cv.ensure(std::max<int64_t>(Qt.nnz, 1) * sizeof(float));
+    tcur.ensure(std::max<int64_t>(S, 1) * sizeof(int64_t));
+    HIPCHK(pmmf::launch_csr_transpose(S, Qr.nnz, Qr.rp.as<int64_t>(), Qr.ci.as<int32_t>(),
+                                      Qr.cv.as<float>(), cnt.as<int32_t>(), Qt.rp.as<int64_t>(),
+                                      scan_tmp.as<int64_t>(), tcur.as<int64_t>(),
+                                      Qt.ci.as<int32_t>(), Qt.cv.as<float>(), s));
     // W = M Qbar^T, written once into staging rows sized by a capacity bound (row x of W keeps
     // its entries at [wstart[x], wstart[x] + wcnt[x]); k_left reads it in that form)
     HIPCHK(pmmf::launch_bound_right(S, M.rp.as<int64_t>(), M.ci.as<int32_t>(), Qt.rp.as<int64_t>(),
