@@ -43,10 +43,11 @@ struct FindArgs {
 // launchers (factor_kernels.hip)
 namespace pmmf {
 hipError_t launch_fill_cluster_of(const int32_t* off, int m, int S, int32_t* cl_of, hipStream_t s);
-hipError_t launch_gram(int S, const int64_t* rp, const int32_t* ci, const float* cv,
-                       const int32_t* off, const int32_t* cl_of, const int64_t* gbase,
-                       const int64_t* run_ptr, const int32_t* run_cl, const int64_t* run_start,
-                       float2* GD, int cmax, hipStream_t s);
+// sparse Gram of the active matrix (rp_nnz entries)
+hipError_t launch_gram(int S, int64_t rp_nnz, const int64_t* rp, const int32_t* ci,
+                       const float* cv, const int32_t* off, const int32_t* cl_of,
+                       const int64_t* gbase, const int64_t* run_ptr, const int32_t* run_cl,
+                       const int64_t* run_start, float2* GD, int cmax, hipStream_t s);
 hipError_t launch_runs(int S, int fill, const int64_t* rp, const int32_t* ci,
                        const int32_t* cl_of, int32_t* nruns, const int64_t* run_ptr,
                        int32_t* run_cl, int64_t* run_start, hipStream_t s);

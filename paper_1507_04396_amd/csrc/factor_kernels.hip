@@ -80,14 +80,23 @@ hipError_t launch_runs(int S, int fill, const int64_t* rp, const int32_t* ci,
   return hipGetLastError();
 }
 
-// One 64-entry chunk of a row segment: entries [off, off + rem) of the segment that starts at ci/cv
-// index base, scaled by w.  All fields are wave-uniform (scalar registers).
+// Up to GRAM_ITEM consecutive 64-entry chunks of one row segment: entries from off on (rem of
+// them left in the segment) of the segment that starts at ci/cv index base, scaled by w.  All
+// fields are wave-uniform (scalar registers).
+struct GramItem {
+  int64_t base;
+  int off, rem;
+  float w;
+};
+// One 64-entry chunk of a row segment (entries [off, off + rem) of the segment at base), for
+// stages with short segments, where items of one segment would leave most of their chunks empty.
 struct GramChunk {
   int64_t base;
   int off, rem;
   float w;
 };
 constexpr int GRAM_ITEM = 4;  // chunks whose loads are requested together
+template <bool SEGMENT_ITEMS>
 __global__ void __launch_bounds__(256) k_gram(int S, const int64_t* __restrict__ rp,
                                               const int32_t* __restrict__ ci,
                                               const float* __restrict__ cv,
@@ -136,71 +145,142 @@ __global__ void __launch_bounds__(256) k_gram(int S, const int64_t* __restrict__
         len = (int)((lo + 1 < re ? run_start[lo + 1] : rp[r + 1]) - lb);
       }
     }
-    // Walk the chunks of the non-empty segments in ascending r with a wave-uniform cursor; the
-    // loads of the next GRAM_ITEM chunks are requested before the current ones are added.  The
-    // entries of one segment hit distinct columns, so each column still sums in ascending r.
-    uint64_t left = __ballot(len > 0);
-    bool live = false;  // a segment is under the cursor
-    int qn = 0, qoff = 0;
-    int64_t qb = 0;
-    float qw = 0.f;
-    auto next_seg = [&]() {
-      live = left != 0;
-      const int l = live ? (int)__builtin_ctzll(left) : 0;
-      left &= left - 1;
-      qn = __builtin_amdgcn_readlane(len, l);
-      qb = ((int64_t)__builtin_amdgcn_readlane((int)(lb >> 32), l) << 32) |
-           (uint32_t)__builtin_amdgcn_readlane((int)lb, l);
-      qw = pmmf_readlane_f(wr, l);
-      qoff = 0;
-    };
-    next_seg();
-    // an exhausted cursor yields empty chunks at the last segment's start (a valid address)
-    auto take = [&](GramChunk& g) {
-      g.base = qb;
-      g.off = live ? qoff : 0;
-      g.rem = live ? qn - qoff : 0;
-      g.w = qw;
-      qoff += PMMF_WAVE;
-      if (live && qoff >= qn) next_seg();
-    };
-    auto load = [&](const GramChunk* g, int* col, float* val) {
-#pragma unroll
-      for (int t = 0; t < GRAM_ITEM; ++t) {
-        // lanes past the end re-read an entry of the segment (an address inside it)
-        const uint32_t eb = 4u * (uint32_t)(g[t].off + min(lane, max(g[t].rem - 1, 0)));
-        col[t] = *reinterpret_cast<const int32_t*>(reinterpret_cast<const char*>(ci + g[t].base) + eb);
-        val[t] = *reinterpret_cast<const float*>(reinterpret_cast<const char*>(cv + g[t].base) + eb);
+    if constexpr (SEGMENT_ITEMS) {
+      // Walk the non-empty segments in ascending r with a wave-uniform cursor, in items of up to
+      // GRAM_ITEM consecutive chunks of one segment (the scalar work is per item); the loads of
+      // the next item are requested before the current one is added.  The entries of one segment
+      // hit distinct columns, so each column still sums in ascending r.
+      uint64_t left = __ballot(len > 0);
+      bool live = false;  // a segment is under the cursor
+      int qn = 0, qoff = 0;
+      int64_t qb = 0;
+      float qw = 0.f;
+      auto next_seg = [&]() {
+        live = left != 0;
+        const int l = live ? (int)__builtin_ctzll(left) : 0;
+        left &= left - 1;
+        qn = __builtin_amdgcn_readlane(len, l);
+        qb = ((int64_t)__builtin_amdgcn_readlane((int)(lb >> 32), l) << 32) |
+             (uint32_t)__builtin_amdgcn_readlane((int)lb, l);
+        qw = pmmf_readlane_f(wr, l);
+        qoff = 0;
+      };
+      next_seg();
+      // an exhausted cursor yields empty items at the last segment's start (a valid address)
+      auto take = [&](GramItem& g) {
+        g.base = qb;
+        g.off = live ? qoff : 0;
+        g.rem = live ? qn - qoff : 0;
+        g.w = qw;
+        qoff += GRAM_ITEM * PMMF_WAVE;
+        if (live && qoff >= qn) next_seg();
+      };
+      auto load = [&](const GramItem& g, int* col, float* val) {
+        const char* cp = reinterpret_cast<const char*>(ci + g.base);
+        const char* vp = reinterpret_cast<const char*>(cv + g.base);
+        const int last = max(g.rem - 1, 0);
+  #pragma unroll
+        for (int t = 0; t < GRAM_ITEM; ++t) {
+          // lanes past the end re-read the segment's last entry (an address inside it)
+          const uint32_t eb = 4u * (uint32_t)(g.off + min(lane + t * PMMF_WAVE, last));
+          col[t] = *reinterpret_cast<const int32_t*>(cp + eb);
+          val[t] = *reinterpret_cast<const float*>(vp + eb);
+        }
+      };
+      auto add = [&](const GramItem& g, const int* col, const float* val) {
+  #pragma unroll
+        for (int t = 0; t < GRAM_ITEM; ++t) {
+          const bool ok = lane + t * PMMF_WAVE < g.rem;
+          acc[ok ? col[t] - o : spare] += ok ? g.w * val[t] : 0.f;
+        }
+      };
+      // two register sets in turn, so that no loaded value is copied (a copy waits for its load)
+      GramItem g0, g1;
+      int c0[GRAM_ITEM], c1[GRAM_ITEM];
+      float v0[GRAM_ITEM], v1[GRAM_ITEM];
+      // a fixed, even number of items (the last ones may be empty): no exit test sits between a
+      // load and the add that uses it
+      const int nit = __builtin_amdgcn_readlane(
+          pmmf_wave_incl_scan_dpp((len + GRAM_ITEM * PMMF_WAVE - 1) / (GRAM_ITEM * PMMF_WAVE)),
+          PMMF_WAVE - 1);
+      const int pairs = (nit + 1) / 2;
+      take(g0);
+      load(g0, c0, v0);
+      for (int it = 0; it < pairs; ++it) {
+        take(g1);
+        load(g1, c1, v1);
+        add(g0, c0, v0);
+        take(g0);
+        load(g0, c0, v0);
+        add(g1, c1, v1);
       }
-    };
-    auto add = [&](const GramChunk* g, const int* col, const float* val) {
-#pragma unroll
-      for (int t = 0; t < GRAM_ITEM; ++t) {
-        const bool ok = lane < g[t].rem;
-        acc[ok ? col[t] - o : spare] += ok ? g[t].w * val[t] : 0.f;
-      }
-    };
-    // two register sets in turn, so that no loaded value is copied (a copy waits for its load)
-    GramChunk g0[GRAM_ITEM], g1[GRAM_ITEM];
-    int c0[GRAM_ITEM], c1[GRAM_ITEM];
-    float v0[GRAM_ITEM], v1[GRAM_ITEM];
-    // a fixed, even number of GRAM_ITEM-chunk items (the last ones may be empty): no exit test
-    // sits between a load and the add that uses it
-    const int nch = __builtin_amdgcn_readlane(pmmf_wave_incl_scan_dpp((len + PMMF_WAVE - 1) >> 6),
-                                              PMMF_WAVE - 1);
-    const int pairs = (nch + 2 * GRAM_ITEM - 1) / (2 * GRAM_ITEM);
-#pragma unroll
-    for (int t = 0; t < GRAM_ITEM; ++t) take(g0[t]);
-    load(g0, c0, v0);
-    for (int it = 0; it < pairs; ++it) {
-#pragma unroll
-      for (int t = 0; t < GRAM_ITEM; ++t) take(g1[t]);
-      load(g1, c1, v1);
-      add(g0, c0, v0);
-#pragma unroll
+    } else {
+      // Walk the chunks of the non-empty segments in ascending r with a wave-uniform cursor; the
+      // loads of the next GRAM_ITEM chunks are requested before the current ones are added.  The
+      // entries of one segment hit distinct columns, so each column still sums in ascending r.
+      uint64_t left = __ballot(len > 0);
+      bool live = false;  // a segment is under the cursor
+      int qn = 0, qoff = 0;
+      int64_t qb = 0;
+      float qw = 0.f;
+      auto next_seg = [&]() {
+        live = left != 0;
+        const int l = live ? (int)__builtin_ctzll(left) : 0;
+        left &= left - 1;
+        qn = __builtin_amdgcn_readlane(len, l);
+        qb = ((int64_t)__builtin_amdgcn_readlane((int)(lb >> 32), l) << 32) |
+             (uint32_t)__builtin_amdgcn_readlane((int)lb, l);
+        qw = pmmf_readlane_f(wr, l);
+        qoff = 0;
+      };
+      next_seg();
+      // an exhausted cursor yields empty chunks at the last segment's start (a valid address)
+      auto take = [&](GramChunk& g) {
+        g.base = qb;
+        g.off = live ? qoff : 0;
+        g.rem = live ? qn - qoff : 0;
+        g.w = qw;
+        qoff += PMMF_WAVE;
+        if (live && qoff >= qn) next_seg();
+      };
+      auto load = [&](const GramChunk* g, int* col, float* val) {
+  #pragma unroll
+        for (int t = 0; t < GRAM_ITEM; ++t) {
+          // lanes past the end re-read an entry of the segment (an address inside it)
+          const uint32_t eb = 4u * (uint32_t)(g[t].off + min(lane, max(g[t].rem - 1, 0)));
+          col[t] = *reinterpret_cast<const int32_t*>(reinterpret_cast<const char*>(ci + g[t].base) + eb);
+          val[t] = *reinterpret_cast<const float*>(reinterpret_cast<const char*>(cv + g[t].base) + eb);
+        }
+      };
+      auto add = [&](const GramChunk* g, const int* col, const float* val) {
+  #pragma unroll
+        for (int t = 0; t < GRAM_ITEM; ++t) {
+          const bool ok = lane < g[t].rem;
+          acc[ok ? col[t] - o : spare] += ok ? g[t].w * val[t] : 0.f;
+        }
+      };
+      // two register sets in turn, so that no loaded value is copied (a copy waits for its load)
+      GramChunk g0[GRAM_ITEM], g1[GRAM_ITEM];
+      int c0[GRAM_ITEM], c1[GRAM_ITEM];
+      float v0[GRAM_ITEM], v1[GRAM_ITEM];
+      // a fixed, even number of GRAM_ITEM-chunk items (the last ones may be empty): no exit test
+      // sits between a load and the add that uses it
+      const int nch = __builtin_amdgcn_readlane(pmmf_wave_incl_scan_dpp((len + PMMF_WAVE - 1) >> 6),
+                                                PMMF_WAVE - 1);
+      const int pairs = (nch + 2 * GRAM_ITEM - 1) / (2 * GRAM_ITEM);
+  #pragma unroll
       for (int t = 0; t < GRAM_ITEM; ++t) take(g0[t]);
       load(g0, c0, v0);
-      add(g1, c1, v1);
+      for (int it = 0; it < pairs; ++it) {
+  #pragma unroll
+        for (int t = 0; t < GRAM_ITEM; ++t) take(g1[t]);
+        load(g1, c1, v1);
+        add(g0, c0, v0);
+  #pragma unroll
+        for (int t = 0; t < GRAM_ITEM; ++t) take(g0[t]);
+        load(g0, c0, v0);
+        add(g1, c1, v1);
+      }
     }
   }
   // Gram halves of the interleaved (G, D) row, then the diagonal-block halves through the same
@@ -500,17 +580,19 @@ hipError_t launch_gram_bf16(int S, int m, const int64_t* rp, const int32_t* ci, 
   return hipGetLastError();
 }
 
-hipError_t launch_gram(int S, const int64_t* rp, const int32_t* ci, const float* cv,
-                       const int32_t* off, const int32_t* cl_of, const int64_t* gbase,
-                       const int64_t* run_ptr, const int32_t* run_cl, const int64_t* run_start,
-                       float2* GD, int cmax, hipStream_t s) {
+hipError_t launch_gram(int S, int64_t rp_nnz, const int64_t* rp, const int32_t* ci,
+                       const float* cv, const int32_t* off, const int32_t* cl_of,
+                       const int64_t* gbase, const int64_t* run_ptr, const int32_t* run_cl,
+                       const int64_t* run_start, float2* GD, int cmax, hipStream_t s) {
   if (S == 0) return hipSuccess;
   int wpb = 4;
   while (wpb > 1 && (size_t)wpb * (cmax + PMMF_WAVE) * 4 > 64 * 1024) wpb >>= 1;
   const size_t lds = (size_t)wpb * (cmax + PMMF_WAVE) * sizeof(float);
-  k_gram<<<(S + wpb - 1) / wpb, wpb * PMMF_WAVE, lds, s>>>(S, rp, ci, cv, off, cl_of, gbase,
-                                                           run_ptr, run_cl, run_start, GD,
-                                                           cmax);
+  // items of one segment once rows are long (their segments then span several chunks)
+  const int64_t nnz = rp_nnz;
+  auto kern = nnz >= 128 * (int64_t)S ? k_gram<true> : k_gram<false>;
+  kern<<<(S + wpb - 1) / wpb, wpb * PMMF_WAVE, lds, s>>>(S, rp, ci, cv, off, cl_of, gbase, run_ptr,
+                                                         run_cl, run_start, GD, cmax);
   return hipGetLastError();
 }
 

@@ -890,7 +890,7 @@ extern "C" int mmf_factor(int64_t n, int64_t nnz, const int64_t* d_rowptr, const
       HIPCHK(pmmf::launch_runs(S, 1, M.rp.as<int64_t>(), M.ci.as<int32_t>(),
                                sd.cl_of.as<int32_t>(), nullptr, run_ptr.as<int64_t>(),
                                run_cl.as<int32_t>(), run_start.as<int64_t>(), s));
-      HIPCHK(pmmf::launch_gram(S, M.rp.as<int64_t>(), M.ci.as<int32_t>(), M.cv.as<float>(),
+      HIPCHK(pmmf::launch_gram(S, M.nnz, M.rp.as<int64_t>(), M.ci.as<int32_t>(), M.cv.as<float>(),
                                sd.off.as<int32_t>(), sd.cl_of.as<int32_t>(),
                                sd.gbase.as<int64_t>(), run_ptr.as<int64_t>(),
                                run_cl.as<int32_t>(), run_start.as<int64_t>(), GD.as<float2>(),
