@@ -80,13 +80,19 @@ hipError_t launch_qbar_count(int S, const int32_t* off, const int32_t* cl_of,
 hipError_t launch_qbar_fill(int S, const int32_t* off, const int32_t* cl_of,
                             const int64_t* gbase, const float* Q, const int64_t* rp, int32_t* ci,
                             float* cv, hipStream_t s);
+// W = M Qbar^T; with fill = 1 it also records where each run of row x (the runs of the run table
+// run_ptr of M) starts in W's staging row: wrs[run_ptr[x] + r]
 hipError_t launch_right(int S, int fill, const int64_t* rp, const int32_t* ci, const float* cv,
                         const int32_t* off, const int32_t* cl_of, const int64_t* qrp,
                         const int32_t* qci, const float* qcv, int32_t* cnt, const int64_t* orp,
-                        int32_t* oci, float* ocv, int cmax, hipStream_t s);
+                        int32_t* oci, float* ocv, const int64_t* run_ptr, int64_t* wrs,
+                        int cmax, hipStream_t s);
+// A_p = Qbar W with peeling; W's rows are runs as recorded by launch_right (run table run_ptr,
+// run_cl of M, starts wrs)
 hipError_t launch_left(int S, int fill, const int64_t* qrp, const int32_t* qci, const float* qcv,
                        const int64_t* wrp, const int32_t* wcnt, const int32_t* wci,
-                       const float* wcv,
+                       const float* wcv, const int64_t* run_ptr, const int32_t* run_cl,
+                       const int64_t* wrs,
                        const int32_t* off, const int32_t* cl_of, const int32_t* next,
                        int32_t* cnt, const int64_t* orp, int32_t* oci, float* ocv,
                        double* loss_row, int32_t* overflow, int cmax, hipStream_t s);

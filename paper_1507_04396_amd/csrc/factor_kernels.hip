@@ -2174,7 +2174,9 @@ __global__ void __launch_bounds__(256) k_right(int S, int fill, const int64_t* _
                                                int32_t* __restrict__ cnt,
                                                const int64_t* __restrict__ orp,
                                                int32_t* __restrict__ oci,
-                                               float* __restrict__ ocv, int cmax) {
+                                               float* __restrict__ ocv,
+                                               const int64_t* __restrict__ run_ptr,
+                                               int64_t* __restrict__ wrs, int cmax) {
   extern __shared__ float lds_f[];
   const int wpb = blockDim.x / PMMF_WAVE;
   const int w = pmmf_wave(), lane = pmmf_lane();
@@ -2187,6 +2189,7 @@ __global__ void __launch_bounds__(256) k_right(int S, int fill, const int64_t* _
   const int64_t end = rp[x + 1];
   int64_t k = rp[x];
   int64_t cur = fill ? orp[x] : 0;
+  int64_t rr = fill ? run_ptr[x] : 0;  // run index in the run table of M
   while (k < end) {
     const int v = cl_of[ci[k]];
     const int ov = off[v];
@@ -2199,6 +2202,9 @@ __global__ void __launch_bounds__(256) k_right(int S, int fill, const int64_t* _
       kend += n;
       if (n < PMMF_WAVE) break;
     }
+    // W's entries of this run (cluster v) start here
+    if (fill && lane == 0) wrs[rr] = cur;
+    ++rr;
     int bmin = INT_MAX, bmax = -1;
     for (int64_t kb = k; kb < kend; kb += PMMF_WAVE) {
       // lane-parallel lookup of the Qbar^T rows of up to 64 entries y of the run
@@ -2281,13 +2287,15 @@ __global__ void __launch_bounds__(256) k_right(int S, int fill, const int64_t* _
 hipError_t launch_right(int S, int fill, const int64_t* rp, const int32_t* ci, const float* cv,
                         const int32_t* off, const int32_t* cl_of, const int64_t* qrp,
                         const int32_t* qci, const float* qcv, int32_t* cnt, const int64_t* orp,
-                        int32_t* oci, float* ocv, int cmax, hipStream_t s) {
+                        int32_t* oci, float* ocv, const int64_t* run_ptr, int64_t* wrs,
+                        int cmax, hipStream_t s) {
   if (S == 0) return hipSuccess;
   int wpb = 4;
   while (wpb > 1 && (size_t)wpb * (cmax + RIGHT_CH * PMMF_WAVE) * 4 > 64 * 1024) wpb >>= 1;
   const size_t lds = (size_t)wpb * (cmax + RIGHT_CH * PMMF_WAVE) * sizeof(float);
   k_right<<<(S + wpb - 1) / wpb, wpb * PMMF_WAVE, lds, s>>>(S, fill, rp, ci, cv, off, cl_of, qrp,
-                                                            qci, qcv, cnt, orp, oci, ocv, cmax);
+                                                            qci, qcv, cnt, orp, oci, ocv, run_ptr,
+                                                            wrs, cmax);
   return hipGetLastError();
 }
 
@@ -2298,8 +2306,8 @@ hipError_t launch_right(int S, int fill, const int64_t* rp, const int32_t* ci, c
 // surviving columns, renumbered to the next stage's positions; a retired row contributes
 //     2 sum_{b survives} A_p[a,b]^2 + sum_{b retired, b != a} A_p[a,b]^2
 // to the exact residual (FP64), which totals 2 sum_e m_e over the stage's retirements.
-// Rows of up to LEFT_QSMALL lists run in a launch with a small list area (more waves per CU);
-// the few longer rows, up to LEFT_QMAX lists, in a second launch.
+// Rows of up to LEFT_QSMALL lists run in k_left_seg; this kernel takes the few longer rows, up to
+// LEFT_QMAX lists, with the lists' positions in an LDS list area.
 constexpr int LEFT_QMAX = 512;
 constexpr int LEFT_QSMALL = 64;
 constexpr int LEFT_PER_LIST = 28;  // LDS bytes per list: cur, end (int64), next column, its cluster, weight
@@ -2481,6 +2489,194 @@ __global__ void __launch_bounds__(256) k_left(int S, int fill, const int64_t* __
   if (lane == 0 && surv) cnt[na] = (int32_t)(fill ? ocur - orp[na] : ocur);
 }
 
+// Left rotation for rows with at most 64 lists (nearly all rows): one list per lane, its position
+// kept in registers as an index into its row's run table (W's rows have the runs of M's rows, one
+// per cluster, in ascending cluster order, with their starts in W recorded by k_right).  Each
+// round takes the smallest cluster v among the lists' current runs and walks the runs of v of the
+// lists that have one, in list order, with a wave-uniform cursor in items of up to GRAM_ITEM
+// consecutive 64-entry chunks of one run (the loads of the next item requested before the
+// current one is added); a run's entries hit distinct columns, so every column sums in list
+// order, as in k_left.  The cluster's accumulated run is then emitted as in k_left.
+__global__ void __launch_bounds__(256) k_left_seg(int S, int fill, const int64_t* __restrict__ qrp,
+                                                  const int32_t* __restrict__ qci,
+                                                  const float* __restrict__ qcv,
+                                                  const int64_t* __restrict__ wrp,
+                                                  const int32_t* __restrict__ wcnt,
+                                                  const int32_t* __restrict__ wci,
+                                                  const float* __restrict__ wcv,
+                                                  const int64_t* __restrict__ run_ptr,
+                                                  const int32_t* __restrict__ run_cl,
+                                                  const int64_t* __restrict__ wrs,
+                                                  const int32_t* __restrict__ off,
+                                                  const int32_t* __restrict__ next,
+                                                  int32_t* __restrict__ cnt,
+                                                  const int64_t* __restrict__ orp,
+                                                  int32_t* __restrict__ oci,
+                                                  float* __restrict__ ocv,
+                                                  double* __restrict__ loss_row, int cmax) {
+  extern __shared__ float lds_f[];
+  const int wpb = blockDim.x / PMMF_WAVE;
+  const int w = pmmf_wave(), lane = pmmf_lane();
+  // cmax accumulator slots, then one spare slot per lane for the zero contributions of lanes past
+  // a run's end
+  float* acc = lds_f + (size_t)w * (cmax + PMMF_WAVE);
+  const int spare = cmax + lane;
+  // a cluster's positions read the same rows of W: keep them on one XCD
+  const int a = pmmf_xcd_block(blockIdx.x, gridDim.x) * wpb + w;
+  if (a >= S) return;
+  const int64_t q0 = qrp[a];
+  const int nq = (int)(qrp[a + 1] - q0);
+  if (nq > PMMF_WAVE) return;  // longer rows: k_left
+  for (int j = lane; j < cmax; j += PMMF_WAVE) acc[j] = 0.f;
+  // this lane's list: row x of W, weight Qbar[a, x], current run ri of [ri, r1), its cluster and
+  // entries [rs, re)
+  int64_t ri = 0, r1 = 0, rs = 0, re = 0, wend = 0;
+  int cl = INT_MAX;
+  float qv = 0.f;
+  if (lane < nq) {
+    const int x = qci[q0 + lane];
+    qv = qcv[q0 + lane];
+    ri = run_ptr[x];
+    r1 = run_ptr[x + 1];
+    wend = wcnt ? wrp[x] + wcnt[x] : wrp[x + 1];
+    if (ri < r1) {
+      cl = run_cl[ri];
+      rs = wrs[ri];
+      re = ri + 1 < r1 ? wrs[ri + 1] : wend;
+    }
+  }
+  const int na = next[a];
+  const bool surv = na >= 0;
+  int64_t ocur = (fill && surv) ? orp[na] : 0;
+  double loss = 0.0;
+  while (true) {
+    const int vmin = pmmf_wave_min_int(cl);
+    if (vmin == INT_MAX) break;
+    const int ov = off[vmin];
+    const bool part = cl == vmin;
+    const int len = part ? (int)(re - rs) : 0;
+    int bmin = INT_MAX, bmax = -1;
+    {
+      uint64_t left = __ballot(len > 0);
+      bool live = false;
+      int qn = 0, qoff = 0;
+      int64_t qb = 0;
+      float qw = 0.f;
+      auto next_run = [&]() {
+        live = left != 0;
+        const int l = live ? (int)__builtin_ctzll(left) : 0;
+        left &= left - 1;
+        qn = __builtin_amdgcn_readlane(len, l);
+        qb = ((int64_t)__builtin_amdgcn_readlane((int)(rs >> 32), l) << 32) |
+             (uint32_t)__builtin_amdgcn_readlane((int)rs, l);
+        qw = pmmf_readlane_f(qv, l);
+        qoff = 0;
+      };
+      next_run();
+      // an exhausted cursor yields empty items at the last run's start (a valid address)
+      auto take = [&](GramItem& g) {
+        g.base = qb;
+        g.off = live ? qoff : 0;
+        g.rem = live ? qn - qoff : 0;
+        g.w = qw;
+        qoff += GRAM_ITEM * PMMF_WAVE;
+        if (live && qoff >= qn) next_run();
+      };
+      auto load = [&](const GramItem& g, int* col, float* val) {
+        const char* cp = reinterpret_cast<const char*>(wci + g.base);
+        const char* vp = reinterpret_cast<const char*>(wcv + g.base);
+        const int last = max(g.rem - 1, 0);
+#pragma unroll
+        for (int t = 0; t < GRAM_ITEM; ++t) {
+          const uint32_t eb = 4u * (uint32_t)(g.off + min(lane + t * PMMF_WAVE, last));
+          col[t] = *reinterpret_cast<const int32_t*>(cp + eb);
+          val[t] = *reinterpret_cast<const float*>(vp + eb);
+        }
+      };
+      auto add = [&](const GramItem& g, const int* col, const float* val) {
+#pragma unroll
+        for (int t = 0; t < GRAM_ITEM; ++t) {
+          const bool ok = lane + t * PMMF_WAVE < g.rem;
+          const int b = col[t] - ov;
+          acc[ok ? b : spare] += ok ? g.w * val[t] : 0.f;
+          bmin = ok ? min(bmin, b) : bmin;
+          bmax = ok ? max(bmax, b) : bmax;
+        }
+      };
+      GramItem g0, g1;
+      int c0[GRAM_ITEM], c1[GRAM_ITEM];
+      float v0[GRAM_ITEM], v1[GRAM_ITEM];
+      // a fixed, even number of items: no exit test sits between a load and its add
+      const int nit = __builtin_amdgcn_readlane(
+          pmmf_wave_incl_scan_dpp((len + GRAM_ITEM * PMMF_WAVE - 1) / (GRAM_ITEM * PMMF_WAVE)),
+          PMMF_WAVE - 1);
+      const int pairs = (nit + 1) / 2;
+      take(g0);
+      load(g0, c0, v0);
+      for (int it = 0; it < pairs; ++it) {
+        take(g1);
+        load(g1, c1, v1);
+        add(g0, c0, v0);
+        take(g0);
+        load(g0, c0, v0);
+        add(g1, c1, v1);
+      }
+    }
+    // the participating lists move to their next run
+    if (part) {
+      ++ri;
+      cl = ri < r1 ? run_cl[ri] : INT_MAX;
+      rs = re;
+      re = ri + 1 < r1 ? wrs[ri + 1] : wend;
+    }
+    bmin = pmmf_wave_min_int(bmin);
+    bmax = pmmf_wave_max_int(bmax);
+    // the cluster's accumulated run, eight 64-column chunks per round (their next positions are
+    // requested together, only where the value is nonzero)
+    for (int bb0 = bmin; bb0 <= bmax; bb0 += 8 * PMMF_WAVE) {
+      float vv[8];
+      int nxv[8];
+#pragma unroll
+      for (int t = 0; t < 8; ++t) {
+        const int j = bb0 + t * PMMF_WAVE + lane;
+        vv[t] = 0.f;
+        nxv[t] = -1;
+        if (j <= bmax) {
+          vv[t] = acc[j];
+          acc[j] = 0.f;
+          if (vv[t] != 0.f) nxv[t] = next[ov + j];
+        }
+      }
+#pragma unroll
+      for (int t = 0; t < 8; ++t) {
+        if (bb0 + t * PMMF_WAVE > bmax) break;
+        const int colpos = ov + bb0 + t * PMMF_WAVE + lane;
+        const float val = vv[t];
+        if (surv) {
+          const bool keep = val != 0.f && nxv[t] >= 0;
+          const uint64_t b = __ballot(keep);
+          if (fill && keep) {
+            const int64_t pos = ocur + pmmf_lanes_below(b);
+            oci[pos] = nxv[t];
+            ocv[pos] = val;
+          }
+          ocur += __popcll(b);
+        } else if (fill && val != 0.f && colpos != a) {
+          const double v2 = (double)val * (double)val;
+          loss += nxv[t] >= 0 ? 2.0 * v2 : v2;
+        }
+      }
+    }
+  }
+  if (fill && !surv) {
+    loss = pmmf_wave_sum_double(loss);
+    if (lane == 0) loss_row[a] = loss;
+  } else if (fill && lane == 0) {
+    loss_row[a] = 0.0;
+  }
+  if (lane == 0 && surv) cnt[na] = (int32_t)(fill ? ocur - orp[na] : ocur);
+}
+
 // Row capacities for writing a product straight into staging storage (no counting pass): a row
 // of W = M Qbar^T has at most sum_y nnz(Qbar^T_y) entries over its entries y, and a row of
 // A_p = Qbar W at most sum_x nnz(W_x) over the entries x of its Qbar row; both at most `cap`.
@@ -2549,7 +2745,8 @@ hipError_t launch_compact_rows(int64_t n, const int64_t* sb, const int32_t* cnt,
 
 hipError_t launch_left(int S, int fill, const int64_t* qrp, const int32_t* qci, const float* qcv,
                        const int64_t* wrp, const int32_t* wcnt, const int32_t* wci,
-                       const float* wcv,
+                       const float* wcv, const int64_t* run_ptr, const int32_t* run_cl,
+                       const int64_t* wrs,
                        const int32_t* off, const int32_t* cl_of, const int32_t* next,
                        int32_t* cnt, const int64_t* orp, int32_t* oci, float* ocv,
                        double* loss_row, int32_t* overflow, int cmax, hipStream_t s) {
@@ -2569,9 +2766,17 @@ hipError_t launch_left(int S, int fill, const int64_t* qrp, const int32_t* qci, 
                                                            ocv, loss_row, overflow, cmax);
     return hipGetLastError();
   };
-  hipError_t e = go(k_left<LEFT_QSMALL>, LEFT_QSMALL);
-  if (e == hipSuccess) e = go(k_left<LEFT_QMAX>, LEFT_QMAX);
-  return e;
+  {
+    const size_t per_wave = ((size_t)cmax + PMMF_WAVE) * 4;
+    int wpb = 4;
+    while (wpb > 1 && wpb * per_wave > 64 * 1024) wpb >>= 1;
+    k_left_seg<<<(S + wpb - 1) / wpb, wpb * PMMF_WAVE, wpb * per_wave, s>>>(
+        S, fill, qrp, qci, qcv, wrp, wcnt, wci, wcv, run_ptr, run_cl, wrs, off, next, cnt, orp,
+        oci, ocv, loss_row, cmax);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
+  return go(k_left<LEFT_QMAX>, LEFT_QMAX);
 }
 
 // ------------------------------------------------------------------------------------------

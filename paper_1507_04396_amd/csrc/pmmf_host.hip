@@ -800,7 +800,7 @@ extern "C" int mmf_factor(int64_t n, int64_t nnz, const int64_t* d_rowptr, const
   DBuf bf_bm, bf_pre, bf_R, bf_off, bf_slab, bf_slab16, bf_stats;  // BF16 form only
   DBuf wstart, wcnt, abase, stage_ci, stage_cv;  // staging rows of the two products
   DBuf tcur;                                     // column cursors of the Qbar transpose
-  DBuf run_ptr, run_cl, run_start;                 // run table of the active matrix
+  DBuf run_ptr, run_cl, run_start, wrs;            // run table of the active matrix, run starts in W
   if (p->gram_mode == 1) bf_stats.ensure(2 * sizeof(unsigned long long));
   GD.ensure(pool * sizeof(float2));
   Q.ensure(pool * sizeof(float));
@@ -843,6 +843,24 @@ extern "C" int mmf_factor(int64_t n, int64_t nnz, const int64_t* d_rowptr, const
                             (double)M.nnz >= DENSE_GRAM_MIN_FILL * (double)S * (double)S;
     sd.dense_gram = dense_gram;
     const bool bf16 = h->prm.gram_mode == 1;
+    // run table of the active matrix (each row's column runs per cluster): read by the sparse
+    // Gram and, through the runs' starts in W, by the left rotation
+    {
+      HIPCHK(pmmf::launch_runs(S, 0, M.rp.as<int64_t>(), M.ci.as<int32_t>(),
+                               sd.cl_of.as<int32_t>(), cnt.as<int32_t>(), nullptr, nullptr,
+                               nullptr, s));
+      run_ptr.ensure((S + 1) * sizeof(int64_t));
+      HIPCHK(pmmf::launch_scan(cnt.as<int32_t>(), run_ptr.as<int64_t>(), S,
+                               scan_tmp.as<int64_t>(), s));
+      // a run holds at least one entry, and a row meets each cluster in at most one run
+      const int64_t nrun = std::min<int64_t>(M.nnz, (int64_t)S * sd.m);
+      run_cl.ensure(std::max<int64_t>(nrun, 1) * sizeof(int32_t));
+      run_start.ensure(std::max<int64_t>(nrun, 1) * sizeof(int64_t));
+      wrs.ensure(std::max<int64_t>(nrun, 1) * sizeof(int64_t));
+      HIPCHK(pmmf::launch_runs(S, 1, M.rp.as<int64_t>(), M.ci.as<int32_t>(),
+                               sd.cl_of.as<int32_t>(), nullptr, run_ptr.as<int64_t>(),
+                               run_cl.as<int32_t>(), run_start.as<int64_t>(), s));
+    }
     if (bf16) {
       // slab rows R_u, slab sizes (host), then FP32 + BF16 slabs, G~ on the matrix cores, D
       // and the exact column norms
@@ -876,20 +894,6 @@ extern "C" int mmf_factor(int64_t n, int64_t nnz, const int64_t* d_rowptr, const
                                      dense_buf.as<float>(), sd.off.as<int32_t>(), sd.m,
                                      sd.gbase.as<int64_t>(), GD.as<float2>(), sd.cmax, s));
     } else {
-      // run table of the active matrix (each row's column runs per cluster), then the Grams
-      HIPCHK(pmmf::launch_runs(S, 0, M.rp.as<int64_t>(), M.ci.as<int32_t>(),
-                               sd.cl_of.as<int32_t>(), cnt.as<int32_t>(), nullptr, nullptr,
-                               nullptr, s));
-      run_ptr.ensure((S + 1) * sizeof(int64_t));
-      HIPCHK(pmmf::launch_scan(cnt.as<int32_t>(), run_ptr.as<int64_t>(), S,
-                               scan_tmp.as<int64_t>(), s));
-      // a run holds at least one entry, and a row meets each cluster in at most one run
-      const int64_t nrun = std::min<int64_t>(M.nnz, (int64_t)S * sd.m);
-      run_cl.ensure(std::max<int64_t>(nrun, 1) * sizeof(int32_t));
-      run_start.ensure(std::max<int64_t>(nrun, 1) * sizeof(int64_t));
-      HIPCHK(pmmf::launch_runs(S, 1, M.rp.as<int64_t>(), M.ci.as<int32_t>(),
-                               sd.cl_of.as<int32_t>(), nullptr, run_ptr.as<int64_t>(),
-                               run_cl.as<int32_t>(), run_start.as<int64_t>(), s));
       HIPCHK(pmmf::launch_gram(S, M.nnz, M.rp.as<int64_t>(), M.ci.as<int32_t>(), M.cv.as<float>(),
                                sd.off.as<int32_t>(), sd.cl_of.as<int32_t>(),
                                sd.gbase.as<int64_t>(), run_ptr.as<int64_t>(),
@@ -996,7 +1000,8 @@ extern "C" int mmf_factor(int64_t n, int64_t nnz, const int64_t* d_rowptr, const
     HIPCHK(pmmf::launch_right(S, 1, M.rp.as<int64_t>(), M.ci.as<int32_t>(), M.cv.as<float>(),
                               sd.off.as<int32_t>(), sd.cl_of.as<int32_t>(), Qt.rp.as<int64_t>(),
                               Qt.ci.as<int32_t>(), Qt.cv.as<float>(), wcnt.as<int32_t>(),
-                              wstart.as<int64_t>(), W.ci.as<int32_t>(), W.cv.as<float>(), cm, s));
+                              wstart.as<int64_t>(), W.ci.as<int32_t>(), W.cv.as<float>(),
+                              run_ptr.as<int64_t>(), wrs.as<int64_t>(), cm, s));
     // A_p = Qbar W, peeled to the survivors, plus the exact residual of the retired rows: written
     // into staging rows, then compacted into the next stage's CSR
     HIPCHK(pmmf::launch_bound_left(S, Qr.rp.as<int64_t>(), Qr.ci.as<int32_t>(), wcnt.as<int32_t>(),
@@ -1008,7 +1013,8 @@ extern "C" int mmf_factor(int64_t n, int64_t nnz, const int64_t* d_rowptr, const
     stage_cv.ensure(std::max<int64_t>(acap, 1) * sizeof(float));
     HIPCHK(pmmf::launch_left(S, 1, Qr.rp.as<int64_t>(), Qr.ci.as<int32_t>(), Qr.cv.as<float>(),
                              wstart.as<int64_t>(), wcnt.as<int32_t>(), W.ci.as<int32_t>(),
-                             W.cv.as<float>(), sd.off.as<int32_t>(), sd.cl_of.as<int32_t>(),
+                             W.cv.as<float>(), run_ptr.as<int64_t>(), run_cl.as<int32_t>(),
+                             wrs.as<int64_t>(), sd.off.as<int32_t>(), sd.cl_of.as<int32_t>(),
                              sd.next.as<int32_t>(), cnt.as<int32_t>(), abase.as<int64_t>(),
                              stage_ci.as<int32_t>(), stage_cv.as<float>(), loss_row.as<double>(),
                              overflow.as<int32_t>(), cm, s));
