@@ -12,6 +12,8 @@ from .pmmf_oracle import (  # noqa: F401
     mulhi,
     stage_schedule,
     cluster_sizes,
+    boundary_cuts,
+    cut_cluster_sizes,
     allocate_rotations,
     rotation_k2,
     rotation_k3,

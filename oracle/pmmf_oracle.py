@@ -47,6 +47,12 @@ Readings of points the paper leaves open (each is also listed in the design note
       O(w) = expm(w_0 G_01 + w_1 G_02 + w_2 G_12) O0, with O0 the rotation the search found and
       G_pq = E_qp - E_pq the generator of the (p, q) plane in slot order (G_01 extends the Givens
       J = [[0, -1], [1, 0]]); w = 0 at the start.
+  R16 A data-driven clustering (optional, Alg. 1 "cluster"): clusters stay contiguous chunks of
+      the active list, with sizes in [lo, hi], but their boundaries are chosen to cut the fewest
+      entries of the active matrix: boundary b (between positions b-1 and b) cuts the entries
+      (i, j), i < j, with i < b <= j, and the chosen boundaries minimize the total count.  Among
+      optimal partitions the one whose cluster sizes, read from the last cluster backwards, are
+      lexicographically largest is taken.  A stage with at most hi active indices is one cluster.
 """
 from __future__ import annotations
 
@@ -125,6 +131,54 @@ def cluster_sizes(total: int, lo: int, hi: int, seed: int, p: int, even: bool = 
         q += 1
     sizes.append(r)
     return sizes
+
+
+def boundary_cuts(M) -> np.ndarray:
+    """w[b] for b = 0..S: the number of entries (i, j), i < j, of the symmetric active matrix M
+    with i < b <= j, i.e. the entries a cluster boundary at b separates (R16).  w[0] = w[S] = 0."""
+    M = sp.csr_matrix(M)
+    S = M.shape[0]
+    coo = M.tocoo()
+    upper = coo.row < coo.col
+    w = np.zeros(S + 1, dtype=np.int64)
+    for i, j in zip(coo.row[upper], coo.col[upper]):
+        w[i + 1:j + 1] += 1
+    return w
+
+
+def cut_cluster_sizes(M, lo: int, hi: int) -> List[int]:
+    """Contiguous cluster sizes in [lo, hi] whose boundaries cut the fewest entries of M (R16).
+
+    f[b] is the least total cut of a partition of positions [0, b) into clusters, counting the
+    boundary at b itself (for b < S); the last cluster of an optimal partition of [0, b) starts at
+    the smallest optimal predecessor, which makes the sizes read backwards lexicographically
+    largest."""
+    S = sp.csr_matrix(M).shape[0]
+    if lo == 0 and hi == 0:
+        return [S]
+    if lo < 2 or hi < 2 * lo:
+        raise ValueError("cluster bounds need lo >= 2 and hi >= 2*lo")
+    if S <= hi:
+        return [S]
+    w = boundary_cuts(M)
+    INF = None
+    f: List[Optional[int]] = [INF] * (S + 1)
+    back = [-1] * (S + 1)
+    f[0] = 0
+    for b in range(lo, S + 1):
+        best, arg = INF, -1
+        for prev in range(max(0, b - hi), b - lo + 1):   # ascending: ties keep the smallest
+            if f[prev] is not INF and (best is INF or f[prev] < best):
+                best, arg = f[prev], prev
+        if best is not INF:
+            f[b] = best + (int(w[b]) if b < S else 0)
+            back[b] = arg
+    sizes = []
+    b = S
+    while b > 0:
+        sizes.append(b - back[b])
+        b = back[b]
+    return sizes[::-1]
 
 
 def allocate_rotations(t: int, sizes: List[int]) -> List[int]:
@@ -228,7 +282,7 @@ def _as_csr64(A) -> sp.csr_matrix:
 
 
 def factor(A, k: int = 2, eta: float = 0.5, core: int = 64, cluster=(0, 0), seed: int = 0,
-           even_clusters: bool = False,
+           even_clusters: bool = False, cut_clusters: bool = False,
            on_step: Optional[Callable[[dict], None]] = None) -> Factorization:
     """pMMF factorization A ~ U^T H U (Eq. 1 / Eq. 4) by Algorithm 1 with Algorithm 2 inside.
 
@@ -253,7 +307,12 @@ def factor(A, k: int = 2, eta: float = 0.5, core: int = 64, cluster=(0, 0), seed
 
     for p, (size, t) in enumerate(schedule, start=1):
         assert size == len(S)
-        sizes = cluster_sizes(size, lo, hi, seed, p, even=even_clusters)
+        if cut_clusters:                 # R16
+            if even_clusters:
+                raise ValueError("even and cut clusters exclude each other")
+            sizes = cut_cluster_sizes(M, lo, hi)
+        else:
+            sizes = cluster_sizes(size, lo, hi, seed, p, even=even_clusters)
         r_u = allocate_rotations(t, sizes)
         offsets = np.concatenate([[0], np.cumsum(sizes)]).astype(np.int64)
         nnz_start = M.nnz
