@@ -47,6 +47,11 @@ enum {
 /* flags */
 #define MMF_CHECK_SYMMETRY   0x1u  /* verify A == A^T on the device before factoring            */
 #define MMF_EVEN_CLUSTERS    0x2u  /* round every cluster size but the last down to even (tests) */
+#define MMF_CUT_CLUSTERS     0x4u  /* data-driven clustering (Alg. 1 "cluster"): contiguous clusters
+                                      with sizes in [cluster_min, cluster_max] whose boundaries
+                                      separate the fewest entries of the stage's active matrix,
+                                      chosen at the start of each stage; excludes
+                                      MMF_EVEN_CLUSTERS                                          */
 
 /* Factorization parameters (Sec. 2, Alg. 1 and Alg. 2). */
 typedef struct {

@@ -14,6 +14,7 @@ ERRORS = {
 }
 MMF_CHECK_SYMMETRY = 0x1
 MMF_EVEN_CLUSTERS = 0x2
+MMF_CUT_CLUSTERS = 0x4
 
 
 class MMFError(RuntimeError):

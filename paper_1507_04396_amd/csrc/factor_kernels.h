@@ -108,6 +108,10 @@ hipError_t launch_next_positions(int S, const uint8_t* retflag, const int64_t* s
                                  hipStream_t s);
 hipError_t launch_keep_flags(int S, const uint8_t* retflag, int32_t* keep, hipStream_t s);
 hipError_t launch_scan(const int32_t* in, int64_t* out, int64_t n, int64_t* tmp, hipStream_t s);
+// boundary cut counts of the active matrix (data-driven clustering): d (S + 2 ints) is scratch,
+// w (S + 2 int64) receives at w[b + 1] the number of entries (i, j), i < j, with i < b <= j
+hipError_t launch_cut_counts(int S, const int64_t* rp, const int32_t* ci, int32_t* d, int64_t* w,
+                             int64_t* tmp, hipStream_t s);
 // CSR transpose of an n x n matrix (rows of the result in arbitrary entry order): cnt (n ints) and
 // cursor (n int64) are scratch, tmp as for launch_scan; trp receives n + 1 row pointers
 hipError_t launch_csr_transpose(int n, int64_t nnz, const int64_t* rp, const int32_t* ci,

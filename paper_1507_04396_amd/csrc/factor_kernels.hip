@@ -2140,6 +2140,35 @@ hipError_t launch_csr_transpose(int n, int64_t nnz, const int64_t* rp, const int
   return hipGetLastError();
 }
 
+// Boundary cut counts of the active matrix for the data-driven clustering: boundary b (between
+// positions b-1 and b) separates the entries (i, j), i < j, with i < b <= j.  Each such entry adds
+// +1 at i + 1 and -1 at j + 1 of a difference array whose prefix sums are the counts (integer
+// atomics: the counts are exact, whatever the order).
+__global__ void k_cut_marks(int S, const int64_t* __restrict__ rp, const int32_t* __restrict__ ci,
+                            int32_t* __restrict__ d) {
+  const int i = blockIdx.x * (blockDim.x / PMMF_WAVE) + pmmf_wave();
+  if (i >= S) return;
+  int n = 0;
+  for (int64_t t = rp[i] + pmmf_lane(); t < rp[i + 1]; t += PMMF_WAVE) {
+    const int j = ci[t];
+    const bool up = j > i;
+    n += __popcll(__ballot(up));
+    if (up) atomicAdd(d + j + 1, -1);
+  }
+  if (pmmf_lane() == 0 && n > 0) atomicAdd(d + i + 1, n);
+}
+
+hipError_t launch_cut_counts(int S, const int64_t* rp, const int32_t* ci, int32_t* d, int64_t* w,
+                             int64_t* tmp, hipStream_t s) {
+  hipError_t e = hipMemsetAsync(d, 0, (size_t)(S + 2) * sizeof(int32_t), s);
+  if (e != hipSuccess) return e;
+  if (S > 0) k_cut_marks<<<(S + 3) / 4, 256, 0, s>>>(S, rp, ci, d);
+  e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  // exclusive scan over S + 1 slots: w[b + 1] = d[0] + ... + d[b], the count at boundary b
+  return launch_scan(d, w, S + 1, tmp, s);
+}
+
 hipError_t launch_qbar_count(int S, const int32_t* off, const int32_t* cl_of,
                              const int64_t* gbase, const float* Q, int32_t* cnt, hipStream_t s) {
   if (S == 0) return hipSuccess;

@@ -353,10 +353,74 @@ struct SchedStage {
   std::vector<int32_t> sizes, rcnt;
 };
 
+// rotations per cluster: floor share plus leftovers by largest remainder (lower u on ties)
+void allocate_stage_rotations(SchedStage& st, const mmf_params& p) {
+  const int64_t s = st.size, t = st.t;
+  const size_t m = st.sizes.size();
+  std::vector<int64_t> base(m), rem(m);
+  int64_t sum = 0;
+  for (size_t u = 0; u < m; ++u) {
+    base[u] = (t * st.sizes[u]) / s;
+    rem[u] = (t * st.sizes[u]) % s;
+    sum += base[u];
+  }
+  std::vector<size_t> ord(m);
+  for (size_t u = 0; u < m; ++u) ord[u] = u;
+  std::stable_sort(ord.begin(), ord.end(), [&](size_t a, size_t b) { return rem[a] > rem[b]; });
+  for (int64_t q = 0; q < t - sum; ++q) base[ord[q]] += 1;
+  st.rcnt.clear();
+  for (size_t u = 0; u < m; ++u) {
+    if (st.sizes[u] > CMAX_LIMIT)
+      raise(MMF_EINVAL, "cluster of " + std::to_string(st.sizes[u]) + " exceeds the limit " +
+                            std::to_string(CMAX_LIMIT) + " (set cluster bounds)");
+    if (base[u] > st.sizes[u] - (p.k - 1))
+      raise(MMF_EINVAL, "a cluster has fewer than k live indices at its last step");
+    st.rcnt.push_back((int32_t)base[u]);
+  }
+}
+
+// Data-driven cluster sizes (MMF_CUT_CLUSTERS): contiguous clusters with sizes in [lo, hi] whose
+// boundaries separate the fewest entries of the active matrix; w[b] is the count at boundary b
+// (b = 0..S).  f(b) = least total count of a partition of [0, b) into clusters (counting b itself
+// when b < S) = w(b) + min f(b') over b' in [b - hi, b - lo]; the window minimum comes from a
+// monotone deque, which keeps the smallest b' among equal minima, so the sizes read backwards are
+// the lexicographically largest optimal ones.  O(S).
+std::vector<int32_t> cut_cluster_sizes(const std::vector<int64_t>& w, int64_t S, int64_t lo,
+                                       int64_t hi) {
+  if (S <= hi) return {(int32_t)S};
+  const int64_t INF = INT64_MAX;
+  std::vector<int64_t> f(S + 1, INF), back(S + 1, -1);
+  f[0] = 0;
+  std::vector<int64_t> dq(S + 1);
+  size_t head = 0, tail = 0;  // candidates b' in ascending order, f non-decreasing
+  for (int64_t b = lo; b <= S; ++b) {
+    const int64_t add = b - lo;  // enters the window
+    if (f[add] != INF) {
+      while (tail > head && f[dq[tail - 1]] > f[add]) --tail;
+      dq[tail++] = add;
+    }
+    while (tail > head && dq[head] < b - hi) ++head;  // leaves the window
+    if (tail > head) {
+      f[b] = f[dq[head]] + (b < S ? w[b] : 0);
+      back[b] = dq[head];
+    }
+  }
+  if (f[S] == INF) raise(MMF_EINVAL, "the active set cannot be split into clusters of [lo, hi]");
+  std::vector<int32_t> sizes;
+  for (int64_t b = S; b > 0; b = back[b]) sizes.push_back((int32_t)(b - back[b]));
+  std::reverse(sizes.begin(), sizes.end());
+  return sizes;
+}
+
 std::vector<SchedStage> make_schedule(const mmf_params& p, int64_t n) {
   std::vector<SchedStage> out;
   int64_t s = n;
   int stage = 0;
+  const bool cut = (p.flags & MMF_CUT_CLUSTERS) != 0;
+  if (cut && (p.flags & MMF_EVEN_CLUSTERS))
+    raise(MMF_EINVAL, "MMF_CUT_CLUSTERS and MMF_EVEN_CLUSTERS exclude each other");
+  if (cut && p.cluster_max > CMAX_LIMIT)
+    raise(MMF_EINVAL, "cluster_max exceeds the limit " + std::to_string(CMAX_LIMIT));
   while (s > p.core_size) {
     ++stage;
     const int64_t t = std::min<int64_t>(s - p.core_size, (int64_t)std::floor(p.eta * (double)s));
@@ -365,6 +429,10 @@ std::vector<SchedStage> make_schedule(const mmf_params& p, int64_t n) {
     st.size = s;
     st.t = t;
     if (p.cluster_min == 0 && p.cluster_max == 0) {
+      st.sizes.push_back((int32_t)s);
+    } else if (cut && s > p.cluster_max) {
+      // sizes chosen at the start of the stage from the active matrix
+    } else if (cut) {
       st.sizes.push_back((int32_t)s);
     } else {
       int64_t r = s;
@@ -382,27 +450,7 @@ std::vector<SchedStage> make_schedule(const mmf_params& p, int64_t n) {
       }
       st.sizes.push_back((int32_t)r);
     }
-    // rotations per cluster: floor share plus leftovers by largest remainder (lower u on ties)
-    const size_t m = st.sizes.size();
-    std::vector<int64_t> base(m), rem(m);
-    int64_t sum = 0;
-    for (size_t u = 0; u < m; ++u) {
-      base[u] = (t * st.sizes[u]) / s;
-      rem[u] = (t * st.sizes[u]) % s;
-      sum += base[u];
-    }
-    std::vector<size_t> ord(m);
-    for (size_t u = 0; u < m; ++u) ord[u] = u;
-    std::stable_sort(ord.begin(), ord.end(), [&](size_t a, size_t b) { return rem[a] > rem[b]; });
-    for (int64_t q = 0; q < t - sum; ++q) base[ord[q]] += 1;
-    for (size_t u = 0; u < m; ++u) {
-      if (st.sizes[u] > CMAX_LIMIT)
-        raise(MMF_EINVAL, "cluster of " + std::to_string(st.sizes[u]) + " exceeds the limit " +
-                              std::to_string(CMAX_LIMIT) + " (set cluster bounds)");
-      if (base[u] > st.sizes[u] - (p.k - 1))
-        raise(MMF_EINVAL, "a cluster has fewer than k live indices at its last step");
-      st.rcnt.push_back((int32_t)base[u]);
-    }
+    if (!st.sizes.empty()) allocate_stage_rotations(st, p);
     out.push_back(std::move(st));
     s -= t;
   }
@@ -794,6 +842,8 @@ extern "C" int mmf_factor(int64_t n, int64_t nnz, const int64_t* d_rowptr, const
   for (auto& sc : sched) {
     int64_t g = 0;
     for (int32_t c : sc.sizes) g += (int64_t)c * c;
+    // sizes chosen during the factorization: every cluster has at most cluster_max positions
+    if (sc.sizes.empty()) g = sc.size * std::min<int64_t>(sc.size, p->cluster_max);
     pool = std::max(pool, g);
   }
   DBuf GD, Q, retflag, keep, scan, cnt, loss_row, overflow, gid_cur, dense_buf;
@@ -821,8 +871,26 @@ extern "C" int mmf_factor(int64_t n, int64_t nnz, const int64_t* d_rowptr, const
   stage_loss.ensure(std::max<size_t>(sched.size(), 1) * sizeof(double));
 
   std::vector<std::unique_ptr<PhaseEvents>> stage_events;
+  DBuf cut_d, cut_w;  // boundary cut counts (data-driven clustering)
   for (size_t pi = 0; pi < sched.size(); ++pi) {
-    const SchedStage& sc = sched[pi];
+    SchedStage& sc = sched[pi];
+    if (sc.sizes.empty()) {
+      // data-driven clustering of this stage's active matrix (MMF_CUT_CLUSTERS)
+      const int64_t S0 = sc.size;
+      cut_d.ensure((S0 + 2) * sizeof(int32_t));
+      cut_w.ensure((S0 + 2) * sizeof(int64_t));
+      HIPCHK(pmmf::launch_cut_counts((int)S0, M.rp.as<int64_t>(), M.ci.as<int32_t>(),
+                                     cut_d.as<int32_t>(), cut_w.as<int64_t>(),
+                                     scan_tmp.as<int64_t>(), s));
+      std::vector<int64_t> wb(S0 + 2);
+      HIPCHK(hipMemcpyAsync(wb.data(), cut_w.p, (S0 + 2) * sizeof(int64_t), hipMemcpyDeviceToHost,
+                            s));
+      HIPCHK(hipStreamSynchronize(s));
+      staging_synced(s);
+      std::vector<int64_t> w(wb.begin() + 1, wb.end());  // w[b] = count at boundary b
+      sc.sizes = cut_cluster_sizes(w, S0, p->cluster_min, p->cluster_max);
+      allocate_stage_rotations(sc, *p);
+    }
     auto sdp = std::make_unique<StageDev>();
     StageDev& sd = *sdp;
     build_stage_geometry(sd, sc, rot_base, s);
