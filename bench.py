@@ -233,6 +233,28 @@ def main():
                                  "factor_ms_median": round(float(np.median(t_ms)), 3),
                                  "loss_mean": round(float(np.mean(losses)), 4),
                                  "loss_std": round(float(np.std(losses)), 4)}
+    # ----------------------------------------------------------------- clustering forms
+    # the seeded contiguous clusters (the FP32 Gram form above) against the data-driven
+    # clusters that cut the fewest active-matrix entries, over the same algorithm seeds
+    clustering = None
+    if gram_forms is not None:
+        t_ms, losses = [], []
+        for sd in range(args.gram_seeds):
+            p2 = dict(prm)
+            p2["seed"] = sd
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            f2 = Factorization.factor(rp, ci, cv, cut_clusters=True, **p2)
+            torch.cuda.synchronize()
+            t_ms.append(1e3 * (time.perf_counter() - t0))
+            losses.append(f2.info()["loss"])
+            f2.close()
+        log(f"[bench] cut clusters: {np.round(t_ms, 1)} ms, loss {np.round(losses, 2)}")
+        clustering = {"seeded": gram_forms["fp32"],
+                      "cut": {"seeds": args.gram_seeds,
+                              "factor_ms_median": round(float(np.median(t_ms)), 3),
+                              "loss_mean": round(float(np.mean(losses)), 4),
+                              "loss_std": round(float(np.std(losses)), 4)}}
     del rp, ci, cv
 
     # ----------------------------------------------------------------- apply / adjoint
@@ -291,6 +313,7 @@ def main():
                      "GBps": round(copy_gbs, 1), "kind": "1 GiB float32 device copy (torch)"},
         "refine": refine,
         "gram_forms": gram_forms,
+        "clustering": clustering,
         "roofline": roofline,
         "cpu_baseline": cpu,
         "stages": [{k2: (round(v, 4) if isinstance(v, float) else v) for k2, v in st.items()}

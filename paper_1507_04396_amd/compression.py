@@ -36,9 +36,11 @@ def best_rank_error2(lam_sorted: np.ndarray, rank: int) -> float:
     return float(np.dot(tail, tail))
 
 
-def compression_curve(csr, cores, *, k=2, eta=0.5, cluster=(0, 0), seed=0, lam=None):
+def compression_curve(csr, cores, *, k=2, eta=0.5, cluster=(0, 0), seed=0, lam=None,
+                      cut_clusters=False):
     """One record per core size: relative errors of pMMF and of the best rank-delta approximation
-    and their ratio, with the factorization time."""
+    and their ratio, with the factorization time.  ``cut_clusters`` selects the data-driven
+    clustering (boundaries that separate the fewest active-matrix entries)."""
     from .api import Factorization
     if lam is None:
         lam = eigenvalues_fp64(csr)
@@ -46,7 +48,7 @@ def compression_curve(csr, cores, *, k=2, eta=0.5, cluster=(0, 0), seed=0, lam=N
     out = []
     for core in cores:
         f = Factorization.from_csr(csr, k=k, eta=eta, core=int(core), cluster=tuple(cluster),
-                                   seed=seed)
+                                   seed=seed, cut_clusters=cut_clusters)
         inf = f.info()
         f.close()
         err2 = max(float(inf["loss"]), 0.0)
@@ -81,12 +83,16 @@ def main(argv=None):
     ap.add_argument("--k", type=int, default=2)
     ap.add_argument("--cluster", default="512,2048")
     ap.add_argument("--seed", type=int, default=0)
+    ap.add_argument("--cut-clusters", action="store_true",
+                    help="data-driven clusters (fewest separated entries) instead of seeded sizes")
     a = ap.parse_args(argv)
     csr = _matrix(a.workload, a.n, 0)
     cores = [int(c) for c in a.cores.split(",")]
     lo, hi = (int(v) for v in a.cluster.split(","))
-    for rec in compression_curve(csr, cores, k=a.k, cluster=(lo, hi), seed=a.seed):
-        rec.update(workload=a.workload, n=len(csr.rowptr) - 1, k=a.k, cluster=[lo, hi])
+    for rec in compression_curve(csr, cores, k=a.k, cluster=(lo, hi), seed=a.seed,
+                                 cut_clusters=a.cut_clusters):
+        rec.update(workload=a.workload, n=len(csr.rowptr) - 1, k=a.k, cluster=[lo, hi],
+                   clustering="cut" if a.cut_clusters else "seeded")
         print(json.dumps(rec), flush=True)
 
 
