@@ -917,7 +917,8 @@ struct Cand {
   int j;
 };
 __device__ inline bool better(const Cand& a, const Cand& b) {
-  return a.s > b.s || (a.s == b.s && a.j < b.j);
+  // bitwise, not short-circuit: straight-line compares and selects, no branches
+  return (a.s > b.s) | ((a.s == b.s) & (a.j < b.j));
 }
 // top two of {b1, b2, o1, o2} (b1 before b2, o1 before o2), with scalar selects only
 __device__ inline void merge2(Cand& b1, Cand& b2, Cand o1, Cand o2) {
