@@ -2339,7 +2339,7 @@ hipError_t launch_right(int S, int fill, const int64_t* rp, const int32_t* ci, c
 // Rows of up to LEFT_QSMALL lists run in k_left_seg; this kernel takes the few longer rows, up to
 // LEFT_QMAX lists, with the lists' positions in an LDS list area.
 constexpr int LEFT_QMAX = 512;
-constexpr int LEFT_QSMALL = 64;
+constexpr int LEFT_QSMALL = 2 * PMMF_WAVE;
 constexpr int LEFT_PER_LIST = 28;  // LDS bytes per list: cur, end (int64), next column, its cluster, weight
 
 template <int QCAP>
@@ -2519,9 +2519,10 @@ __global__ void __launch_bounds__(256) k_left(int S, int fill, const int64_t* __
   if (lane == 0 && surv) cnt[na] = (int32_t)(fill ? ocur - orp[na] : ocur);
 }
 
-// Left rotation for rows with at most 64 lists (nearly all rows): one list per lane, its position
-// kept in registers as an index into its row's run table (W's rows have the runs of M's rows, one
-// per cluster, in ascending cluster order, with their starts in W recorded by k_right).  Each
+// Left rotation for rows with at most 128 lists (nearly all rows): two lists per lane (lists l and
+// l + 64), each list's position kept in registers as an index into its row's run table (W's rows
+// have the runs of M's rows, one per cluster, in ascending cluster order, with their starts in W
+// recorded by k_right).  Each
 // round takes the smallest cluster v among the lists' current runs and walks the runs of v of the
 // lists that have one, in list order, with a wave-uniform cursor in items of up to GRAM_ITEM
 // consecutive 64-entry chunks of one run (the loads of the next item requested before the
@@ -2556,23 +2557,28 @@ __global__ void __launch_bounds__(256) k_left_seg(int S, int fill, const int64_t
   if (a >= S) return;
   const int64_t q0 = qrp[a];
   const int nq = (int)(qrp[a + 1] - q0);
-  if (nq > PMMF_WAVE) return;  // longer rows: k_left
+  constexpr int NS = 2;            // list slots per lane
+  if (nq > NS * PMMF_WAVE) return;  // longer rows: k_left
   for (int j = lane; j < cmax; j += PMMF_WAVE) acc[j] = 0.f;
-  // this lane's list: row x of W, weight Qbar[a, x], current run ri of [ri, r1), its cluster and
-  // entries [rs, re)
-  int64_t ri = 0, r1 = 0, rs = 0, re = 0, wend = 0;
-  int cl = INT_MAX;
-  float qv = 0.f;
-  if (lane < nq) {
-    const int x = qci[q0 + lane];
-    qv = qcv[q0 + lane];
-    ri = run_ptr[x];
-    r1 = run_ptr[x + 1];
-    wend = wcnt ? wrp[x] + wcnt[x] : wrp[x + 1];
-    if (ri < r1) {
-      cl = run_cl[ri];
-      rs = wrs[ri];
-      re = ri + 1 < r1 ? wrs[ri + 1] : wend;
+  // this lane's lists h = 0, 1 (list lane + 64 h): row x of W, weight Qbar[a, x], current run ri
+  // of [ri, r1), its cluster and entries [rs, re)
+  int64_t ri[2] = {0, 0}, r1[2] = {0, 0}, rs[2] = {0, 0}, re[2] = {0, 0}, wend[2] = {0, 0};
+  int cl[2] = {INT_MAX, INT_MAX};
+  float qv[2] = {0.f, 0.f};
+#pragma unroll
+  for (int h = 0; h < NS; ++h) {
+    const int li = lane + h * PMMF_WAVE;
+    if (li < nq) {
+      const int x = qci[q0 + li];
+      qv[h] = qcv[q0 + li];
+      ri[h] = run_ptr[x];
+      r1[h] = run_ptr[x + 1];
+      wend[h] = wcnt ? wrp[x] + wcnt[x] : wrp[x + 1];
+      if (ri[h] < r1[h]) {
+        cl[h] = run_cl[ri[h]];
+        rs[h] = wrs[ri[h]];
+        re[h] = ri[h] + 1 < r1[h] ? wrs[ri[h] + 1] : wend[h];
+      }
     }
   }
   const int na = next[a];
@@ -2580,26 +2586,36 @@ __global__ void __launch_bounds__(256) k_left_seg(int S, int fill, const int64_t
   int64_t ocur = (fill && surv) ? orp[na] : 0;
   double loss = 0.0;
   while (true) {
-    const int vmin = pmmf_wave_min_int(cl);
+    const int vmin = pmmf_wave_min_int(NS == 2 ? min(cl[0], cl[1]) : cl[0]);
     if (vmin == INT_MAX) break;
     const int ov = off[vmin];
-    const bool part = cl == vmin;
-    const int len = part ? (int)(re - rs) : 0;
+    const bool part0 = cl[0] == vmin, part1 = NS == 2 && cl[1] == vmin;
+    const int len0 = part0 ? (int)(re[0] - rs[0]) : 0;
+    const int len1 = part1 ? (int)(re[1] - rs[1]) : 0;
     int bmin = INT_MAX, bmax = -1;
     {
-      uint64_t left = __ballot(len > 0);
+      // participating runs in list order: lists 0..63 (h = 0), then 64..127 (h = 1)
+      uint64_t left0 = __ballot(len0 > 0), left1 = NS == 2 ? __ballot(len1 > 0) : 0;
       bool live = false;
       int qn = 0, qoff = 0;
       int64_t qb = 0;
       float qw = 0.f;
       auto next_run = [&]() {
-        live = left != 0;
-        const int l = live ? (int)__builtin_ctzll(left) : 0;
-        left &= left - 1;
-        qn = __builtin_amdgcn_readlane(len, l);
-        qb = ((int64_t)__builtin_amdgcn_readlane((int)(rs >> 32), l) << 32) |
-             (uint32_t)__builtin_amdgcn_readlane((int)rs, l);
-        qw = pmmf_readlane_f(qv, l);
+        const bool h1 = left0 == 0;
+        const uint64_t m = h1 ? left1 : left0;
+        live = m != 0;
+        const int l = live ? (int)__builtin_ctzll(m) : 0;
+        if (h1) left1 &= left1 - 1;
+        else left0 &= left0 - 1;
+        const int n0 = __builtin_amdgcn_readlane(len0, l), n1 = __builtin_amdgcn_readlane(len1, l);
+        const int64_t b0 = ((int64_t)__builtin_amdgcn_readlane((int)(rs[0] >> 32), l) << 32) |
+                           (uint32_t)__builtin_amdgcn_readlane((int)rs[0], l);
+        const int64_t b1 = ((int64_t)__builtin_amdgcn_readlane((int)(rs[1] >> 32), l) << 32) |
+                           (uint32_t)__builtin_amdgcn_readlane((int)rs[1], l);
+        const float w0 = pmmf_readlane_f(qv[0], l), w1 = pmmf_readlane_f(qv[1], l);
+        qn = h1 ? n1 : n0;
+        qb = h1 ? b1 : b0;
+        qw = h1 ? w1 : w0;
         qoff = 0;
       };
       next_run();
@@ -2637,9 +2653,9 @@ __global__ void __launch_bounds__(256) k_left_seg(int S, int fill, const int64_t
       int c0[GRAM_ITEM], c1[GRAM_ITEM];
       float v0[GRAM_ITEM], v1[GRAM_ITEM];
       // a fixed, even number of items: no exit test sits between a load and its add
+      constexpr int IE = GRAM_ITEM * PMMF_WAVE;
       const int nit = __builtin_amdgcn_readlane(
-          pmmf_wave_incl_scan_dpp((len + GRAM_ITEM * PMMF_WAVE - 1) / (GRAM_ITEM * PMMF_WAVE)),
-          PMMF_WAVE - 1);
+          pmmf_wave_incl_scan_dpp((len0 + IE - 1) / IE + (len1 + IE - 1) / IE), PMMF_WAVE - 1);
       const int pairs = (nit + 1) / 2;
       take(g0);
       load(g0, c0, v0);
@@ -2653,11 +2669,14 @@ __global__ void __launch_bounds__(256) k_left_seg(int S, int fill, const int64_t
       }
     }
     // the participating lists move to their next run
-    if (part) {
-      ++ri;
-      cl = ri < r1 ? run_cl[ri] : INT_MAX;
-      rs = re;
-      re = ri + 1 < r1 ? wrs[ri + 1] : wend;
+#pragma unroll
+    for (int h = 0; h < NS; ++h) {
+      if (cl[h] == vmin) {
+        ++ri[h];
+        cl[h] = ri[h] < r1[h] ? run_cl[ri[h]] : INT_MAX;
+        rs[h] = re[h];
+        re[h] = ri[h] + 1 < r1[h] ? wrs[ri[h] + 1] : wend[h];
+      }
     }
     bmin = pmmf_wave_min_int(bmin);
     bmax = pmmf_wave_max_int(bmax);
@@ -2800,7 +2819,8 @@ hipError_t launch_left(int S, int fill, const int64_t* qrp, const int32_t* qci, 
     const size_t per_wave = ((size_t)cmax + PMMF_WAVE) * 4;
     int wpb = 4;
     while (wpb > 1 && wpb * per_wave > 64 * 1024) wpb >>= 1;
-    k_left_seg<<<(S + wpb - 1) / wpb, wpb * PMMF_WAVE, wpb * per_wave, s>>>(
+    const unsigned grid = (unsigned)((S + wpb - 1) / wpb);
+    k_left_seg<<<grid, wpb * PMMF_WAVE, wpb * per_wave, s>>>(
         S, fill, qrp, qci, qcv, wrp, wcnt, wci, wcv, run_ptr, run_cl, wrs, off, next, cnt, orp,
         oci, ocv, loss_row, cmax);
     hipError_t e = hipGetLastError();
