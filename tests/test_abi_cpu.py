@@ -80,3 +80,16 @@ def test_set_allocator_needs_both_functions_or_neither(lib):
     assert lib.mmf_set_allocator(alloc, _lib.RELEASE_FN(), None) == -1
     assert lib.mmf_last_error()
     assert lib.mmf_set_allocator(_lib.ALLOC_FN(), _lib.RELEASE_FN(), None) == 0
+
+
+def test_trim_with_nothing_kept_is_ok(lib):
+    # no block has been released in this process: nothing to free, no device call
+    assert lib.mmf_trim() == 0
+    assert lib.mmf_last_error() in (b"", None)
+
+
+def test_cut_clusters_flag_excludes_even_clusters(lib):
+    from paper_1507_04396_amd import _lib
+    flags = _lib.MMF_EVEN_CLUSTERS | _lib.MMF_CUT_CLUSTERS
+    assert _factor(lib, n=32, core_size=4, cluster_min=4, cluster_max=8, flags=flags) == -1
+    assert b"exclude" in lib.mmf_last_error()
