@@ -2009,7 +2009,68 @@ __global__ void k_levelize(int k, const int32_t* __restrict__ off, const int32_t
   for (int j = threadIdx.x; j < c + 2; j += blockDim.x) start[j] = 0;
   for (int q = threadIdx.x; q < r * 3; q += blockDim.x) ids[q] = rot_loc[(rot0 + rb) * 3 + q];
   __syncthreads();
-  if (threadIdx.x == 0) {
+  // Wave 0 walks the rotations with wave-uniform control flow: a chunk of 64 rotations' indices is
+  // held one per lane and read back by readlane, and the per-level counts and next free slots
+  // live in one register indexed by level (lane l holds level l), so only the latest-level table
+  // goes through LDS.  Clusters whose depth reaches 64 levels are redone by the serial walk below.
+  bool fast = false;
+  if (threadIdx.x < PMMF_WAVE) {
+    const int lane = pmmf_lane();
+    int cnt_v = 0, depth = 0;
+    for (int s0 = 0; s0 < r; s0 += PMMF_WAVE) {
+      const int sl = min(s0 + lane, r - 1);
+      const int c0 = ids[sl * 3], c1 = ids[sl * 3 + 1], c2 = ids[sl * 3 + 2];
+      const int n = min(PMMF_WAVE, r - s0);
+      int lv = 0;
+      for (int t = 0; t < n; ++t) {
+        const int i0 = __builtin_amdgcn_readlane(c0, t), i1 = __builtin_amdgcn_readlane(c1, t),
+                  i2 = __builtin_amdgcn_readlane(c2, t);
+        int L = max(last[i0], last[i1]);
+        if (i2 >= 0) L = max(L, last[i2]);
+        L += 1;
+        // every lane writes the same value at the same address, so each lane reads back its own
+        // writes (no lane depends on another lane's LDS write)
+        last[i0] = L;
+        last[i1] = L;
+        if (i2 >= 0) last[i2] = L;
+        cnt_v += lane == L ? 1 : 0;
+        lv = lane == t ? L : lv;
+        depth = max(depth, L);
+      }
+      if (lane < n) lvl[s0 + lane] = lv;
+    }
+    fast = depth < PMMF_WAVE;
+    if (fast) {
+      // exclusive prefix of the level counts (levels 1..depth in lanes 1..depth)
+      const int incl = pmmf_wave_incl_scan_dpp(cnt_v);
+      int start_v = incl - cnt_v;
+      if (lane >= 1 && lane <= depth) lvl_ptr[(size_t)u * lvl_stride + (lane - 1)] = rb + start_v;
+      if (lane == 0) {
+        lvl_ptr[(size_t)u * lvl_stride + depth] = rb + r;
+        depth_out[u] = depth;
+        sh_depth = depth;
+      }
+      // slot of each rotation in level order (rotation order inside a level)
+      for (int s0 = 0; s0 < r; s0 += PMMF_WAVE) {
+        const int n = min(PMMF_WAVE, r - s0);
+        const int lvv = lane < n ? lvl[s0 + lane] : 0;
+        int slot = 0;
+        for (int t = 0; t < n; ++t) {
+          const int L = __builtin_amdgcn_readlane(lvv, t);
+          const int sl = __builtin_amdgcn_readlane(start_v, L);
+          start_v += lane == L ? 1 : 0;
+          slot = lane == t ? sl : slot;
+        }
+        if (lane < n) lvl[s0 + lane] = slot;
+      }
+    } else {
+      for (int j = lane; j < c; j += PMMF_WAVE) last[j] = 0;
+    }
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) sh_depth = fast ? sh_depth : -1;
+  __syncthreads();
+  if (sh_depth < 0 && threadIdx.x == 0) {
     int depth = 0;
     for (int s = 0; s < r; ++s) {
       const int i0 = ids[s * 3], i1 = ids[s * 3 + 1], i2 = ids[s * 3 + 2];
