@@ -17,6 +17,15 @@ from .pmmf_oracle import (  # noqa: F401
     allocate_rotations,
     rotation_k2,
     rotation_k3,
+    TIE,
+    KAPPA,
+    TINY32,
+    U32,
+    score_error,
+    near_tie,
+    partner_decision,
+    rotation_decision,
+    elimination_decision,
     factor,
     apply_U,
     apply_Ut,

@@ -38,11 +38,17 @@ Readings of points the paper leaves open (each is also listed in the design note
   R12 Loss: the exact residual ||A - U^T H U||_F^2 equals 2 * sum_e m_e, where m_e is the squared
       mass of row e over the indices still active just after e retires; the literal per-retirement
       sum of 2 off^2_e is an upper bound and is reported beside it.
-  R13 Decision margins (not part of the factorization): the seed-partner score gap relative to
-      sqrt(G_ii) (the Cauchy-Schwarz bound of every score), the k = 2 angle-branch switch as
-      |G_jj - G_ii| / (|G_ii| + |G_jj| + 2|G_ij|), the k = 3 eigengap and trace gap, and the
-      elimination gap relative to max_t G_tt.  A margin below 1e-5 marks a step where two
-      choices are equally correct at working precision.
+  R13 Decision margins (not part of the factorization), each a gap relative to the values it
+      separates: partners (s_q - s_{q+1}) / s_q below each chosen rank q of the sorted scores;
+      the rotation |tau| at the k = 2 root switch, the relative gap of the two best traces for
+      k = 3, and for both the relative eigengap of G[T,T]; the elimination
+      (off2_(2) - off2_(1)) / off2_(2).  A decision is a near-tie, where every choice is correct,
+      if its margin is at most TIE = 1e-5 or if its absolute gap is within the FP32 error bounds
+      of the two values compared: a method that stores the matrix, the Gram, the diagonal block
+      and the rotations in FP32 cannot order values closer than that.  The bounds come from a
+      first-order running error analysis of such a method (see KAPPA below), carried beside the
+      FP64 values.  Replay adopts another implementation's choice at a near-tie and reports any
+      other adopted choice as a divergence.
   R15 Angles of a 3-point rotation (the paper parametrizes only Givens rotations by an angle):
       O(w) = expm(w_0 G_01 + w_1 G_02 + w_2 G_12) O0, with O0 the rotation the search found and
       G_pq = E_qp - E_pq the generator of the (p, q) plane in slot order (G_01 extends the Givens
@@ -195,12 +201,13 @@ def allocate_rotations(t: int, sizes: List[int]) -> List[int]:
 
 # --------------------------------------------------------------------------- rotations (R6)
 
-def rotation_k2(g: np.ndarray):
+def rotation_k2(g: np.ndarray, other_root: bool = False):
     """2x2 rotation O = [[c, -s], [s, c]] with O g O^T diagonal and |theta| <= pi/4.
 
     The symmetric Schur decomposition of a 2x2 block (Golub & Van Loan, Alg. 8.4.1), with the
     smaller-magnitude root of t^2 + 2 tau t - 1 = 0.  Returns (O, |tau|); |tau| -> 0 is where the
-    choice of root switches sign.
+    choice of root switches sign.  ``other_root`` takes the other root t' = -1/t (|theta| >= pi/4),
+    which diagonalizes g as well; replay adopts it where |tau| is a near-tie.
     """
     a, b, d = float(g[0, 0]), float(g[0, 1]), float(g[1, 1])
     if b == 0.0:
@@ -208,17 +215,31 @@ def rotation_k2(g: np.ndarray):
     tau = (d - a) / (2.0 * b)
     sgn = 1.0 if tau >= 0.0 else -1.0
     t = sgn / (abs(tau) + math.hypot(1.0, tau))
+    if other_root:
+        t = -1.0 / t
     c = 1.0 / math.sqrt(1.0 + t * t)
     s = t * c
     return np.array([[c, -s], [s, c]]), abs(tau)
 
 
-def rotation_k3(g: np.ndarray):
+def _relative_eigengap(lam_desc: np.ndarray) -> float:
+    """Smallest gap between consecutive eigenvalues over the largest magnitude (0 if g = 0)."""
+    scale = float(np.abs(lam_desc).max())
+    if scale == 0.0:
+        return 0.0
+    return float(min(lam_desc[r] - lam_desc[r + 1] for r in range(len(lam_desc) - 1))) / scale
+
+
+def rotation_k3(g: np.ndarray, prefer: Optional[np.ndarray] = None,
+                with_trace_margin: bool = False):
     """k x k orthogonal O whose rows are eigenvectors of g, arranged closest to the identity.
 
     Rows are eigenvectors in descending eigenvalue order (LAPACK), then permuted and signed to
     maximize trace(O) with nonnegative diagonal; ties go to the lexicographically smallest
-    permutation.  Returns (O, relative margin between the best and second-best trace).
+    permutation.  Returns (O, margin) with margin the smaller of the relative gap between the best
+    and second-best trace and the relative eigengap (an eigenvector is determined only when its
+    eigenvalue is simple).  ``prefer`` (replay at a near-tie only): among the permuted and signed
+    arrangements take the one closest to ``prefer`` instead of the largest trace.
     """
     kk = g.shape[0]
     w, v = np.linalg.eigh(g)
@@ -229,12 +250,113 @@ def rotation_k3(g: np.ndarray):
     best = max(tr for tr, _ in traces)
     perm = min(pm for tr, pm in traces if tr == best)
     others = sorted((tr for tr, pm in traces if pm != perm), reverse=True)
-    margin = (best - others[0]) / best if best > 0 else 0.0
-    O = np.empty((kk, kk))
-    for r in range(kk):
-        row = base[perm[r]]
-        O[r] = row if row[r] >= 0.0 else -row
-    return O, margin
+    trace_margin = (best - others[0]) / best if best > 0 else 0.0
+    margin = min(trace_margin, _relative_eigengap(w[::-1]))
+
+    def arrange(pm):
+        O = np.empty((kk, kk))
+        for r in range(kk):
+            row = base[pm[r]]
+            O[r] = row if row[r] >= 0.0 else -row
+        return O
+
+    if prefer is not None:
+        perm = min(itertools.permutations(range(kk)),
+                   key=lambda pm: (float(np.abs(arrange(pm) - prefer).max()), pm))
+    if with_trace_margin:
+        return arrange(perm), margin, trace_margin, best
+    return arrange(perm), margin
+
+
+def _nearest_orthogonal(O: np.ndarray) -> np.ndarray:
+    """Orthogonal polar factor of O (closest orthogonal matrix in the Frobenius norm)."""
+    u, _, vt = np.linalg.svd(np.asarray(O, dtype=np.float64))
+    return u @ vt
+
+
+# --------------------------------------------------------------------------- decision margins
+
+TIE = 1e-5  # a decision whose margin (R13) is at most this is a near-tie: every choice is correct
+# FP32 error bounds of the compared values (R13), by a first-order running error analysis of an
+# FP32 implementation of the same steps.  A stage starts from running magnitudes: the same
+# computation carried out on absolute values (|A| for the input, |Qbar| for each stage's two-sided
+# rotation, |slab|^T |slab| for a Gram), and a Gram or diagonal-block entry starts within KAPPA
+# U32 of its magnitude.  Each rotation then forms rows and columns T again from k terms with a
+# rounded O: the new error is |O| times the old one, plus (k + 1) U32 |O| |G| for the rounding, plus
+# |dO| |G| where dO bounds how far the eigenvectors of an FP32 G[T,T] lie from the exact ones.
+U32 = 2.0 ** -24
+KAPPA = 16.0
+# FP32 keeps nothing below its smallest normal number 2^-126 (GPU code flushes subnormals), so a
+# stored value errs by at least that much
+TINY32 = 2.0 ** -126
+
+
+def near_tie(rel: float, gap: float, err: float) -> bool:
+    """R13: relative margin at most TIE, or an absolute gap within ``err``, the sum of the FP32
+    error bounds of the two values compared."""
+    return rel <= TIE or gap <= err
+
+
+def score_error(g_ij: float, err_ij: float, g_jj: float, err_jj: float) -> float:
+    """FP32 error bound of the score |G_ij| / sqrt(G_jj) from the error bounds of its two Gram
+    entries (first-order perturbation of the quotient)."""
+    if g_jj <= 0.0:
+        return err_ij
+    sc = abs(g_ij) / math.sqrt(g_jj)
+    return err_ij / math.sqrt(g_jj) + sc * err_jj / (2.0 * g_jj)
+
+
+def partner_decision(scores_desc: np.ndarray, kk: int, err_desc: np.ndarray):
+    """R13 for the partner choice: (margin, tie).  The margin is the smallest relative gap
+    (s_q - s_{q+1}) / s_q below a chosen rank q of the sorted scores (it fixes both the set and the
+    slot order; 0 where the compared scores are zero, inf where no further candidate exists);
+    the choice is a near-tie if some such gap is a near-tie, ``err_desc`` being the scores' FP32
+    error bounds in the same order."""
+    m, tie = math.inf, False
+    for q in range(kk - 1):
+        if q + 1 >= len(scores_desc):
+            break
+        hi, lo = float(scores_desc[q]), float(scores_desc[q + 1])
+        rel = (hi - lo) / hi if hi > 0 else 0.0
+        m = min(m, rel)
+        tie = tie or near_tie(rel, hi - lo, float(err_desc[q]) + float(err_desc[q + 1]))
+    return m, tie
+
+
+def elimination_decision(off2, err):
+    """R13 for the elimination: (off2_(2) - off2_(1)) / off2_(2) over the two smallest values;
+    ``err`` are the FP32 error bounds of off2_t = G_tt - D_tt^2 in slot order."""
+    order = sorted(range(len(off2)), key=lambda t: float(off2[t]))
+    v1, v2 = float(off2[order[0]]), float(off2[order[1]])
+    rel = (v2 - v1) / v2 if v2 > 0 else 0.0
+    return rel, near_tie(rel, v2 - v1, float(err[order[0]]) + float(err[order[1]]))
+
+
+def rotation_decision(gTT: np.ndarray, errTT: np.ndarray):
+    """R13 for the rotation: (margin, tie, relative eigengap, eigenvector error bound).
+
+    G[T,T] known to within ``errTT`` entrywise errs by at most E = ||errTT||_F in the 2-norm,
+    which moves each eigenvalue by at most E (Weyl) and each eigenvector by at most E / gap
+    (Davis-Kahan).  k = 2: the root switch |tau|, fixed by the sign of G_jj - G_ii (a near-tie
+    within the error bounds of the two diagonal entries), and the eigengap (a near-tie within
+    2E).  k = 3: the relative gap of the two best traces (each trace moves by at most 3 E / gap)
+    and the eigengap."""
+    lam = np.linalg.eigvalsh(gTT)[::-1]
+    scale = float(np.abs(lam).max())
+    eig = _relative_eigengap(lam)
+    gap_abs = eig * scale
+    E = float(np.sqrt((np.asarray(errTT) ** 2).sum()))
+    tie_eig = near_tie(eig, gap_abs, 2.0 * E)
+    vec_err = E / gap_abs if gap_abs > 0 else math.inf
+    if gTT.shape[0] == 2:
+        _, tau = rotation_k2(gTT)
+        a, d = float(gTT[0, 0]), float(gTT[1, 1])
+        err_ad = float(errTT[0, 0]) + float(errTT[1, 1])
+        tie_root = near_tie(tau, abs(d - a), err_ad) if gTT[0, 1] != 0.0 else False
+        return min(tau, eig), tie_root or tie_eig, eig, vec_err
+    _, m, tr, best = rotation_k3(gTT, with_trace_margin=True)   # m = min(trace margin, eigengap)
+    tie_tr = near_tie(tr, tr * best, 2.0 * 3.0 * vec_err)
+    return m, tie_tr or tie_eig, eig, vec_err
 
 
 # --------------------------------------------------------------------------- factorization
@@ -248,7 +370,12 @@ class Rotation:
     O: np.ndarray            # k x k block: x[ids] <- O @ x[ids]
     retired: int             # global index eliminated after this rotation
     seed_pos: int            # local position of the seed row inside the cluster
-    margin: float            # smallest relative decision margin of the step (R13 in the notes)
+    margin: float            # smallest decision margin of the step (R13)
+    margins: tuple = ()      # (partner, rotation, elimination) relative margins (R13)
+    eig_gap: float = math.inf  # relative eigengap of G[T,T] (sets how well O is determined)
+    o_err: float = 0.0       # bound on how far an FP32 G[T,T] moves the rows of O (R13)
+    near_ties: tuple = ()    # (partner, rotation, elimination): near-tie under R13
+    adopted: tuple = ()      # replay: decisions taken from the replayed log instead of the rule
 
 
 @dataclasses.dataclass
@@ -263,6 +390,8 @@ class Factorization:
     loss: float              # exact residual 2 * sum_e m_e
     loss_literal: float      # sum of 2 * off^2 at retirement (upper bound)
     retired_order: np.ndarray  # global ids in retirement order (stage, cluster, step)
+    divergences: list = dataclasses.field(default_factory=list)
+    # replay: (rotation index, decision, margin) for every adopted decision whose margin > TIE
 
     @property
     def num_stages(self) -> int:
@@ -281,13 +410,221 @@ def _as_csr64(A) -> sp.csr_matrix:
     return m
 
 
+def _search_cluster(slab, D, gids, r_u, k, seed, p, u, replay=None, on_step=None, ctx=None,
+                    slab_abs=None, D_abs=None):
+    """Algorithm 2 on one cluster: r_u greedy steps on its Gram and diagonal block.
+
+    ``slab`` is the column slab M[S_{p-1}, B_u] (sparse), ``D`` the diagonal block, ``gids`` the
+    global ids of the cluster's columns.  ``replay`` (ids [r_u][k], retired [r_u], O [r_u][k][k]:
+    another implementation's log of this cluster, global ids) makes the step take that log's choice
+    wherever it differs from the rule's; every such decision is reported with its margin (R13).
+    ``slab_abs`` and ``D_abs`` are the running magnitudes of the slab and the block (R13): they
+    set the initial FP32 error bounds of the Gram and the block, which are carried through the
+    rotations beside them, only to bound the error of each compared value.
+    Returns the rotations, the accumulated Q_u (sparse), the retired local positions in step order,
+    their H entries and the literal loss terms."""
+
+    def gram(sl):                                        # local Gram, Sec. 2.1
+        if sl.nnz >= 0.1 * sl.shape[0] * sl.shape[1]:    # (filled-in late stages: BLAS product)
+            dense = sl.toarray()
+            return dense.T @ dense
+        return (sl.T @ sl).toarray()
+
+    def dense(x):
+        return x.toarray() if sp.issparse(x) else np.array(x, dtype=np.float64)
+
+    G = gram(slab)
+    D = dense(D)
+    # FP32 error bounds of the Gram and the diagonal block (R13)
+    ErrG = KAPPA * U32 * gram(abs(slab) if slab_abs is None else slab_abs) + TINY32
+    ErrD = KAPPA * U32 * (np.abs(D) if D_abs is None else dense(D_abs)) + TINY32
+    c = G.shape[0]
+    Qu = np.eye(c)
+    active = np.ones(c, dtype=bool)                      # I = [c]
+    rots, retired, hd, literal = [], [], [], []
+    for s in range(r_u):
+        live = np.flatnonzero(active)
+        i = int(live[mulhi(chain_hash(seed, TAG_SEED_ROW, p, u, s), live.size)])
+        kk = k if live.size >= k else 2
+        # normalized inner products with the seed column, in absolute value (R2)
+        gdiag = np.diag(G)
+        score = np.zeros(c)
+        pos = gdiag > 0.0
+        score[pos] = np.abs(G[i, pos]) / np.sqrt(gdiag[pos])
+        cand = live[live != i]
+        order = cand[np.lexsort((cand, -score[cand]))]  # descending score, then lower j
+        T = [i] + [int(j) for j in order[:kk - 1]]
+
+        def err(j):                                      # FP32 error bound of score j (R13)
+            return score_error(G[i, j], ErrG[i, j], G[j, j], ErrG[j, j])
+
+        score_err = np.array([err(j) for j in order[:kk]])
+        m_part, tie_part = partner_decision(score[order[:kk]], kk, score_err)
+        adopted = []
+        rp_s = replay is not None and bool(replay["use"][s])
+        if rp_s:
+            g_ids = np.minimum(np.searchsorted(gids, replay["ids"][s][:kk]), c - 1)
+            g_T = [int(x) for x in g_ids]
+            if not np.array_equal(gids[g_ids], replay["ids"][s][:kk]):
+                adopted.append(("partners", False, m_part))   # not a tuple of this cluster
+            elif g_T != T:
+                # the other log's tuple is correct if its seed is this seed and each of its
+                # partners scores within the tie margin of the same rank's best score
+                valid = g_T[0] == i and len(set(g_T)) == kk and all(active[j] for j in g_T)
+                ok = valid and all(
+                    near_tie(abs(score[g_T[q + 1]] - score[order[q]]) / score[order[q]]
+                             if score[order[q]] > 0 else 0.0,
+                             abs(score[g_T[q + 1]] - score[order[q]]),
+                             err(g_T[q + 1]) + err(order[q]))
+                    for q in range(kk - 1))
+                adopted.append(("partners", ok, m_part))
+                if valid:
+                    T = g_T
+        # rotation that diagonalizes the k x k Gram block (R6)
+        gTT = G[np.ix_(T, T)]
+        O = rotation_k2(gTT)[0] if kk == 2 else rotation_k3(gTT)[0]
+        m_rot, tie_rot, eig_gap, vec_err = rotation_decision(gTT, ErrG[np.ix_(T, T)])
+        if rp_s:
+            g_O = np.asarray(replay["O"][s][:kk, :kk], dtype=np.float64)
+            alt = O
+            if np.abs(O - g_O).max() > 1e-3:
+                if kk == 2:
+                    alt = rotation_k2(gTT, other_root=True)[0]
+                else:
+                    alt = rotation_k3(gTT, prefer=g_O)[0]
+            # a different root / arrangement of the eigenvectors is a decision (R6, R13)
+            if np.abs(alt - g_O).max() < np.abs(O - g_O).max():
+                adopted.append(("rotation", tie_rot, m_rot))
+                O = alt
+                if tie_rot and np.abs(O - g_O).max() > 1e-3:
+                    O = _nearest_orthogonal(g_O)      # a multiple eigenvalue: any basis is right
+        # G <- O G O^T and the same for the diagonal block and the accumulated Q (Alg. 2), with
+        # the error bounds carried beside them (R13): |O| err + dO |X| + (k + 1) u |O| |X|
+        Oabs = np.abs(O)
+        dO = min(vec_err, 2.0)
+        for X, Err in ((G, ErrG), (D, ErrD)):
+            Xa = np.abs(X[T, :])
+            Err[T, :] = (Oabs @ Err[T, :] + dO * Xa.sum(axis=0)[None, :]
+                         + (kk + 1) * U32 * (Oabs @ Xa) + TINY32)
+            X[T, :] = O @ X[T, :]
+            Xa = np.abs(X[:, T])
+            Err[:, T] = (Err[:, T] @ Oabs.T + dO * Xa.sum(axis=1)[:, None]
+                         + (kk + 1) * U32 * (Xa @ Oabs.T) + TINY32)
+            X[:, T] = X[:, T] @ O.T
+        Qu[T, :] = O @ Qu[T, :]
+        # eliminate the slot with the smallest off-diagonal norm, ties to the later (R5)
+        off2 = [max(0.0, G[tt, tt] - D[tt, tt] ** 2) for tt in T]
+        e_slot = 0
+        for sl in range(1, kk):
+            if off2[sl] <= off2[e_slot]:
+                e_slot = sl
+        off2_err = [ErrG[tt, tt] + 2.0 * abs(D[tt, tt]) * ErrD[tt, tt] for tt in T]
+        m_elim, tie_elim = elimination_decision(off2, off2_err)
+        if rp_s:
+            g_e = int(np.searchsorted(gids, replay["retired"][s]))
+            if g_e != T[e_slot] and g_e in T:
+                adopted.append(("elimination", tie_elim, m_elim))
+                e_slot = T.index(g_e)
+            elif g_e != T[e_slot]:
+                adopted.append(("elimination", False, m_elim))
+        e = T[e_slot]
+        active[e] = False
+        retired.append(e)
+        hd.append(float(D[e, e]))
+        literal.append(2.0 * off2[e_slot])
+        rots.append(Rotation(stage=p, cluster=u, step=s, ids=gids[np.asarray(T)].copy(),
+                             O=O.copy(), retired=int(gids[e]), seed_pos=i,
+                             margin=float(min(m_part, m_rot, m_elim)),
+                             margins=(m_part, m_rot, m_elim), eig_gap=eig_gap, o_err=vec_err,
+                             near_ties=(tie_part, tie_rot, tie_elim), adopted=tuple(adopted)))
+        if on_step is not None:
+            on_step(dict(stage=p, cluster=u, step=s, G=G, D=D, T=list(T), O=O, e=e,
+                         active=active.copy(), ranked=[int(j) for j in order[:kk]],
+                         score_err=score_err, off2_err=off2_err, **(ctx or {})))
+    Qs = sp.csr_matrix(Qu)
+    Qs.eliminate_zeros()
+    return dict(rots=rots, Q=Qs, retired=retired, hd=hd, literal=literal)
+
+
+# state of the stage being computed, read by the per-cluster tasks (a forked worker inherits it)
+_STAGE: dict = {}
+
+
+def _stage_map(fn, items, workers: int):
+    """[fn(x) for x in items], in ``workers`` forked processes when workers > 1."""
+    if workers <= 1 or len(items) <= 1:
+        return [fn(x) for x in items]
+    import concurrent.futures
+    import multiprocessing
+    with concurrent.futures.ProcessPoolExecutor(
+            max_workers=min(workers, len(items)),
+            mp_context=multiprocessing.get_context("fork")) as pool:
+        return list(pool.map(fn, items))
+
+
+def _cluster_task(u: int):
+    """Algorithm 2 on cluster u of the current stage."""
+    st = _STAGE
+    off, c = int(st["offsets"][u]), int(st["sizes"][u])
+    rp = None
+    if st["replay"] is not None:
+        r0 = st["r_base"] + sum(st["r_u"][:u])
+        r1 = r0 + st["r_u"][u]
+        use = st["replay"].get("rot_use")
+        rp = dict(ids=st["replay"]["rot_ids"][r0:r1], retired=st["replay"]["rot_retired"][r0:r1],
+                  O=st["replay"]["rot_o"][r0:r1],
+                  use=np.ones(r1 - r0, dtype=bool) if use is None else use[r0:r1])
+    ctx = dict(offset=off, S=st["S"]) if st["on_step"] is not None else None
+    return _search_cluster(st["Mc"][:, off:off + c],           # rows: all of S_{p-1} (R4)
+                           st["M"][off:off + c, off:off + c],  # [[A]]_{u,u}
+                           st["S"][off:off + c].copy(), st["r_u"][u], st["k"], st["seed"],
+                           st["p"], u, rp, st["on_step"], ctx,
+                           st["Mabs_c"][:, off:off + c], st["Mabs"][off:off + c, off:off + c])
+
+
+def _rotate_rows_task(u: int):
+    """Block rows B_u of A_p = Qbar A_{p-1} Qbar^T, Q_u [[A_{p-1}]]_{u,:} Qbar^T (Alg. 1), then
+    their part of the exact loss (R12) and of the peeled matrix: the rows of B_u that survive,
+    restricted to the surviving columns."""
+    st = _STAGE
+    off, c = int(st["offsets"][u]), int(st["sizes"][u])
+    QM_u = (st["Q"][u] @ st["M"][off:off + c]).tocsr()
+    rows = (QM_u @ st["QbarT"]).tocsr()
+    rows.eliminate_zeros()
+    keep, R = st["keep"], st["R"]
+    local_keep = keep[off:off + c]
+    mine = R[(R >= off) & (R < off + c)] - off             # this block's retired rows
+    MR = rows[mine]
+    m_rs = MR[:, st["Sv"]]
+    m_rr = MR[:, R].tocoo()
+    m_rr_off = m_rr.data[mine[m_rr.row] + off != R[m_rr.col]]   # only e' != e enters
+    stats = dict(sq_rs=float((m_rs.data ** 2).sum()), sq_rr=float((m_rr_off ** 2).sum()),
+                 diag_R=np.asarray(rows[mine, mine + off]).ravel() if mine.size else np.zeros(0),
+                 qm_row_nnz_max=int(np.diff(QM_u.indptr).max()) if QM_u.nnz else 0,
+                 row_nnz_max=int(np.diff(rows.indptr).max()) if rows.nnz else 0,
+                 fro2=float((rows.data ** 2).sum()), mine=mine + off)
+    # running magnitudes of the same rows (R13): |Q_u| |A_{p-1}|_mag[B_u, :] |Qbar|^T
+    mag = ((abs(st["Q"][u]) @ st["Mabs"][off:off + c]) @ st["QbarT_abs"]).tocsr()
+    surv = np.flatnonzero(local_keep)
+    return stats, rows[surv][:, st["Sv"]].tocsr(), mag[surv][:, st["Sv"]].tocsr()
+
+
 def factor(A, k: int = 2, eta: float = 0.5, core: int = 64, cluster=(0, 0), seed: int = 0,
            even_clusters: bool = False, cut_clusters: bool = False,
-           on_step: Optional[Callable[[dict], None]] = None) -> Factorization:
+           on_step: Optional[Callable[[dict], None]] = None, replay: Optional[dict] = None,
+           workers: int = 1) -> Factorization:
     """pMMF factorization A ~ U^T H U (Eq. 1 / Eq. 4) by Algorithm 1 with Algorithm 2 inside.
 
     ``A`` is symmetric (a CSR from ``workloads``, a SciPy sparse matrix or a dense array).
     ``on_step`` (tests only) receives the cluster's state after every rotation.
+    ``replay`` (tests only): a rotation log of another implementation in (stage, cluster, step)
+    order, a dict with ``rot_ids`` [R][k] and ``rot_retired`` [R] (global ids) and ``rot_o``
+    [R][k][k], optionally ``rot_use`` [R] (False: that step follows the rule); where the log's
+    choice differs from the rule's, the step takes it and records the decision with its margin,
+    and ``Factorization.divergences`` lists those that are not near-ties (R13).
+    ``workers`` > 1 runs the clusters of a stage (their searches, and their block rows of the
+    two-sided rotation) in that many forked processes: clusters are independent (Sec. 2.3), and
+    the result does not depend on it.
     """
     if k not in (2, 3):
         raise ValueError("k must be 2 or 3")
@@ -295,9 +632,12 @@ def factor(A, k: int = 2, eta: float = 0.5, core: int = 64, cluster=(0, 0), seed
     n = M.shape[0]
     if (abs(M - M.T) > 0).nnz:
         raise ValueError("matrix is not symmetric")
+    if on_step is not None:
+        workers = 1
     lo, hi = cluster
     schedule = stage_schedule(n, core, eta)
     S = np.arange(n)                    # global ids of the active positions, ascending
+    Mabs = abs(M)                       # running magnitude of the active matrix (R13)
     hdiag = np.zeros(n)
     rotations: List[Rotation] = []
     stages = []
@@ -317,112 +657,61 @@ def factor(A, k: int = 2, eta: float = 0.5, core: int = 64, cluster=(0, 0), seed
         offsets = np.concatenate([[0], np.cumsum(sizes)]).astype(np.int64)
         nnz_start = M.nnz
         fro_start = math.sqrt((M.data ** 2).sum())
-        q_blocks = []
+        _STAGE.clear()
+        _STAGE.update(M=M, Mc=M.tocsc(), Mabs=Mabs, Mabs_c=Mabs.tocsc(), S=S, offsets=offsets,
+                      sizes=sizes, r_u=r_u, k=k,
+                      seed=seed, p=p, replay=replay, r_base=len(rotations), on_step=on_step)
+        results = _stage_map(_cluster_task, list(range(len(sizes))), workers)
         retired_pos = []                # compact positions retired in this stage, in order
-        Mc = M.tocsc()
-
-        for u, c in enumerate(sizes):
+        for u, res in enumerate(results):
             off = int(offsets[u])
-            slab = Mc[:, off:off + c]                            # rows: all of S_{p-1} (R4)
-            G = (slab.T @ slab).toarray()                        # local Gram, Sec. 2.1
-            D = M[off:off + c, off:off + c].toarray()            # diagonal block [[A]]_{u,u}
-            Qu = np.eye(c)
-            active = np.ones(c, dtype=bool)                      # I = [c]
-            for s in range(r_u[u]):
-                live = np.flatnonzero(active)
-                i = int(live[mulhi(chain_hash(seed, TAG_SEED_ROW, p, u, s), live.size)])
-                kk = k if live.size >= k else 2
-                # normalized inner products with the seed column, in absolute value (R2)
-                gdiag = np.diag(G)
-                score = np.zeros(c)
-                pos = gdiag > 0.0
-                score[pos] = np.abs(G[i, pos]) / np.sqrt(gdiag[pos])
-                cand = live[live != i]
-                order = cand[np.lexsort((cand, -score[cand]))]  # descending score, then lower j
-                partners = [int(j) for j in order[:kk - 1]]
-                T = [i] + partners
-                # decision margins (R13): each gap is measured against the scale at which the
-                # compared quantities are formed, so a small margin flags a numerical tie
-                margins = []
-                if order.size >= kk:
-                    s_in, s_out = score[order[kk - 2]], score[order[kk - 1]]
-                    bound = math.sqrt(G[i, i]) if G[i, i] > 0 else 0.0   # Cauchy-Schwarz
-                    margins.append((s_in - s_out) / bound if bound > 0 else 0.0)
-                # rotation that diagonalizes the k x k Gram block (R6)
-                gTT = G[np.ix_(T, T)]
-                if kk == 2:
-                    O, _ = rotation_k2(gTT)
-                    a_, b_, d_ = gTT[0, 0], gTT[0, 1], gTT[1, 1]
-                    den = abs(a_) + abs(d_) + 2.0 * abs(b_)
-                    margins.append(abs(d_ - a_) / den if (den > 0 and b_ != 0.0) else math.inf)
-                else:
-                    O, tr_margin = rotation_k3(gTT)
-                    margins.append(tr_margin)
-                # G <- O G O^T and the same for the diagonal block and the accumulated Q (Alg. 2)
-                G[T, :] = O @ G[T, :]
-                G[:, T] = G[:, T] @ O.T
-                D[T, :] = O @ D[T, :]
-                D[:, T] = D[:, T] @ O.T
-                Qu[T, :] = O @ Qu[T, :]
-                # eliminate the slot with the smallest off-diagonal norm, ties to the later (R5)
-                off2 = [max(0.0, G[tt, tt] - D[tt, tt] ** 2) for tt in T]
-                e_slot = 0
-                for sl in range(1, kk):
-                    if off2[sl] <= off2[e_slot]:
-                        e_slot = sl
-                srt = sorted(off2)
-                gscale = max(G[tt, tt] for tt in T)   # off^2 = G_tt - D_tt^2 is formed at this scale
-                margins.append((srt[1] - srt[0]) / gscale if gscale > 0 else 0.0)
-                e = T[e_slot]
-                active[e] = False
+            for rot, e, h, lit in zip(res["rots"], res["retired"], res["hd"], res["literal"]):
                 gid_e = int(S[off + e])
-                hdiag[gid_e] = D[e, e]
-                loss_literal += 2.0 * off2[e_slot]
+                hdiag[gid_e] = h
+                loss_literal += lit
                 retired_pos.append(off + e)
                 retired_order.append(gid_e)
-                rotations.append(Rotation(stage=p, cluster=u, step=s,
-                                          ids=S[off + np.asarray(T)].copy(), O=O.copy(),
-                                          retired=gid_e, seed_pos=i,
-                                          margin=float(min(margins))))
-                if on_step is not None:
-                    on_step(dict(stage=p, cluster=u, step=s, G=G, D=D, T=list(T), O=O,
-                                 e=e, active=active.copy(), offset=off, S=S.copy()))
-            q_blocks.append(Qu)
+                rotations.append(rot)
 
-        # rotate the whole (blocked) matrix from both sides with the stage's rotations (Alg. 1)
-        Qbar = sp.block_diag([sp.csr_matrix(q) for q in q_blocks], format="csr")
-        row_nnz_max = int(np.diff(M.indptr).max()) if M.nnz else 0
-        QM = (Qbar @ M).tocsr()
-        M = (QM @ Qbar.T).tocsr()
-        qm_row_nnz_max = int(np.diff(QM.indptr).max()) if QM.nnz else 0
-        M.eliminate_zeros()
-        fro_end = math.sqrt((M.data ** 2).sum())
-        # exact loss of this stage's retirements (R12) and peeling of the retired rows/columns
+        # rotate the whole (blocked) matrix from both sides with the stage's rotations (Alg. 1):
+        # block rows [[A_p]]_{u,:} = Q_u [[A_{p-1}]]_{u,:} Qbar^T with Qbar = diag(Q_1, ..., Q_m);
+        # then the exact loss of this stage's retirements (R12) and the peeling of their rows and
+        # columns
         R = np.asarray(retired_pos, dtype=np.int64)
         keep = np.ones(size, dtype=bool)
         keep[R] = False
         Sv = np.flatnonzero(keep)
-        MR = M[R]
-        m_rs = MR[:, Sv]
-        m_rr = MR[:, R].tolil()
-        m_rr.setdiag(0.0)                       # only e' != e enters the residual
-        m_rr = m_rr.tocsr()
-        stage_loss = 2.0 * float((m_rs.data ** 2).sum()) + float((m_rr.data ** 2).sum())
+        Q = [res["Q"] for res in results]
+        QbarT = sp.block_diag(Q, format="csr").T.tocsr()
+        _STAGE.update(Q=Q, QbarT=QbarT, QbarT_abs=abs(QbarT), keep=keep, R=R, Sv=Sv)
+        blocks = _stage_map(_rotate_rows_task, list(range(len(sizes))), workers)
+        _STAGE.clear()
+        row_nnz_max = int(np.diff(M.indptr).max()) if M.nnz else 0
+        stage_loss = sum(2.0 * st["sq_rs"] + st["sq_rr"] for st, _, _ in blocks)
         loss += stage_loss
-        hdiag_check = float(np.max(np.abs(M.diagonal()[R] - hdiag[S[R]]))) if R.size else 0.0
+        fro_end = math.sqrt(sum(st["fro2"] for st, _, _ in blocks))
+        diag_R = np.zeros(size)
+        for st, _, _ in blocks:
+            diag_R[st["mine"]] = st["diag_R"]
+        hdiag_check = float(np.max(np.abs(diag_R[R] - hdiag[S[R]]))) if R.size else 0.0
         stages.append(dict(stage=p, size=size, rotations=t, cluster_sizes=sizes,
                            cluster_rotations=r_u, offsets=offsets, active=S.copy(),
                            retired=S[R].copy(), nnz_start=nnz_start, fro_start=fro_start,
-                           row_nnz_max=row_nnz_max, qm_row_nnz_max=qm_row_nnz_max,
-                           full_row_nnz_max=int(np.diff(M.indptr).max()) if M.nnz else 0,
+                           row_nnz_max=row_nnz_max,
+                           qm_row_nnz_max=max(st["qm_row_nnz_max"] for st, _, _ in blocks),
+                           full_row_nnz_max=max(st["row_nnz_max"] for st, _, _ in blocks),
                            fro_end=fro_end, loss=stage_loss, hdiag_check=hdiag_check))
-        M = M[Sv][:, Sv].tocsr()
+        M = sp.vstack([blk for _, blk, _ in blocks], format="csr")
+        Mabs = sp.vstack([mag for _, _, mag in blocks], format="csr")
         S = S[Sv]
 
+    divergences = [(t, what, m) for t, r in enumerate(rotations)
+                   for what, ok, m in r.adopted if not ok]
     hcore = M.toarray()
     return Factorization(n=n, k=k, rotations=rotations, stages=stages, hdiag=hdiag,
                          core_ids=S.copy(), hcore=hcore, loss=loss, loss_literal=loss_literal,
-                         retired_order=np.asarray(retired_order, dtype=np.int64))
+                         retired_order=np.asarray(retired_order, dtype=np.int64),
+                         divergences=divergences)
 
 
 # --------------------------------------------------------------------------- matrix-free use

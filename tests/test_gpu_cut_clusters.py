@@ -8,6 +8,7 @@ import pytest
 
 import oracle
 import workloads
+from helpers import check_factor_parity
 
 torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
@@ -39,15 +40,12 @@ CASES = [
 @pytest.mark.parametrize("name,make,params", CASES, ids=[c[0] for c in CASES])
 def test_cut_clusters_match_oracle(name, make, params):
     from paper_1507_04396_amd.api import Factorization
-    from test_gpu_parity import _check_factor
     A = make()
-    _say(f"[cut] {name}: oracle")
-    ref = oracle.factor(A, cut_clusters=True, **params)
     _say(f"[cut] {name}: gpu factor n={A.n} params={params}")
     fac = Factorization.from_csr(A, cut_clusters=True, **params)
+    ref = check_factor_parity(A, dict(params, cut_clusters=True), fac, name, say=_say)
     st = fac.stage_info()
     assert [s["clusters"] for s in st] == [len(s["cluster_sizes"]) for s in ref.stages]
-    _check_factor(ref, fac, A, name)
     seeded = oracle.factor(A, **params)
     _say(f"[cut] {name}: loss cut {ref.loss:.6g}, seeded {seeded.loss:.6g}")
 
