@@ -669,13 +669,10 @@ __device__ inline void jacobi_pair(double (&A)[3][3], double (&V)[3][3], int p, 
   }
 }
 
-__device__ inline void rot3(const double (&g)[3][3], double (&O)[3][3], double& trace_margin,
-                            double& eig_margin) {
-  double A[3][3], V[3][3];
-#pragma unroll
-  for (int i = 0; i < 3; ++i)
-#pragma unroll
-    for (int j = 0; j < 3; ++j) { A[i][j] = g[i][j]; V[i][j] = (i == j) ? 1.0 : 0.0; }
+// FP64 cyclic Jacobi sweeps on A (accumulated into V, A = V^T g V on entry), then the arrangement
+// of the eigenvectors described above.
+__device__ inline void rot3_finish(double (&A)[3][3], double (&V)[3][3], double (&O)[3][3],
+                                   double& trace_margin, double& eig_margin) {
   for (int sweep = 0; sweep < 12; ++sweep) {
     bool rot = false;
     jacobi_pair(A, V, 0, 1, rot);
@@ -749,10 +746,19 @@ __device__ inline void rot3(const double (&g)[3][3], double (&O)[3][3], double& 
   }
 }
 
-// FP32 form of the same eigendecomposition (used by k_find): the rotation is stored and applied
-// in FP32, so FP32 eigenvectors are as accurate as its use; the rotated block is then formed in
-// FP64 from exactly this rotation.  Off-diagonal pairs are rotated as 2-vectors, so their
-// rounding is relative to their own size and the sweeps reach the threshold quadratically.
+__device__ inline void rot3(const double (&g)[3][3], double (&O)[3][3], double& trace_margin,
+                            double& eig_margin) {
+  double A[3][3], V[3][3];
+#pragma unroll
+  for (int i = 0; i < 3; ++i)
+#pragma unroll
+    for (int j = 0; j < 3; ++j) { A[i][j] = g[i][j]; V[i][j] = (i == j) ? 1.0 : 0.0; }
+  rot3_finish(A, V, O, trace_margin, eig_margin);
+}
+
+// FP32 cyclic Jacobi sweeps: the start of the FP64 eigendecomposition in k_find.  Off-diagonal
+// pairs are rotated as 2-vectors, so their rounding is relative to their own size and the sweeps
+// reach the FP32 threshold quadratically.
 __device__ inline void jacobi_pair_f(float (&A)[3][3], float (&V)[3][3], int p, int q, bool& rot) {
   const float apq = A[p][q];
   // converged once the pivot is below FP32 resolution of the diagonal pair
@@ -790,84 +796,56 @@ __device__ inline void jacobi_pair_f(float (&A)[3][3], float (&V)[3][3], int p, 
   }
 }
 
-__device__ inline void rot3f(const double (&g)[3][3], double (&O)[3][3], double& trace_margin,
-                             double& eig_margin) {
-  float A[3][3], V[3][3];
+// The same FP64 eigendecomposition as rot3, started from FP32 sweeps: eigenvectors from FP32
+// cyclic Jacobi, made orthonormal in FP64 by one Newton-Schulz step (V <- V (3I - V^T V) / 2, which
+// squares the departure from orthogonality), then V^T g V formed in FP64 and finished by FP64
+// Jacobi sweeps, which from off-diagonal entries at FP32 resolution converge in one or two
+// sweeps instead of the four or five a start from the identity takes.
+__device__ inline void rot3_polished(const double (&g)[3][3], double (&O)[3][3],
+                                     double& trace_margin, double& eig_margin) {
+  float Af[3][3], Vf[3][3];
 #pragma unroll
   for (int i = 0; i < 3; ++i)
 #pragma unroll
-    for (int j = 0; j < 3; ++j) { A[i][j] = (float)g[i][j]; V[i][j] = (i == j) ? 1.f : 0.f; }
+    for (int j = 0; j < 3; ++j) { Af[i][j] = (float)g[i][j]; Vf[i][j] = (i == j) ? 1.f : 0.f; }
   for (int sweep = 0; sweep < 12; ++sweep) {
     bool rot = false;
-    jacobi_pair_f(A, V, 0, 1, rot);
-    jacobi_pair_f(A, V, 0, 2, rot);
-    jacobi_pair_f(A, V, 1, 2, rot);
+    jacobi_pair_f(Af, Vf, 0, 1, rot);
+    jacobi_pair_f(Af, Vf, 0, 2, rot);
+    jacobi_pair_f(Af, Vf, 1, 2, rot);
     if (!rot) break;
   }
-  // columns of V sorted by descending eigenvalue (three compare-swaps on scalars)
-  float e0 = A[0][0], e1 = A[1][1], e2 = A[2][2];
-  float b00 = V[0][0], b01 = V[1][0], b02 = V[2][0];   // b0 = eigenvector of e0 (column 0)
-  float b10 = V[0][1], b11 = V[1][1], b12 = V[2][1];
-  float b20 = V[0][2], b21 = V[1][2], b22 = V[2][2];
-#define PMMF_CSWAPF(ex, ey, x0, x1, x2, y0, y1, y2)                              \
-  if (ey > ex) {                                                               \
-    float t_ = ex; ex = ey; ey = t_;                                          \
-    t_ = x0; x0 = y0; y0 = t_; t_ = x1; x1 = y1; y1 = t_; t_ = x2; x2 = y2; y2 = t_; \
-  }
-  PMMF_CSWAPF(e0, e1, b00, b01, b02, b10, b11, b12)
-  PMMF_CSWAPF(e0, e2, b00, b01, b02, b20, b21, b22)
-  PMMF_CSWAPF(e1, e2, b10, b11, b12, b20, b21, b22)
-#undef PMMF_CSWAPF
-  const double emax = fmax(fabs((double)e0), fabs((double)e2));
-  eig_margin = emax > 0.0 ? fmin((double)e0 - e1, (double)e1 - e2) / emax : 0.0;
-  const float b[3][3] = {{b00, b01, b02}, {b10, b11, b12}, {b20, b21, b22}};
-  // traces of the six row permutations, in lexicographic order
-  const float tr0 = fabsf(b00) + fabsf(b11) + fabsf(b22);  // (0,1,2)
-  const float tr1 = fabsf(b00) + fabsf(b21) + fabsf(b12);  // (0,2,1)
-  const float tr2 = fabsf(b10) + fabsf(b01) + fabsf(b22);  // (1,0,2)
-  const float tr3 = fabsf(b10) + fabsf(b21) + fabsf(b02);  // (1,2,0)
-  const float tr4 = fabsf(b20) + fabsf(b01) + fabsf(b12);  // (2,0,1)
-  const float tr5 = fabsf(b20) + fabsf(b11) + fabsf(b02);  // (2,1,0)
-  int best = 0;
-  float bt = tr0, second = -1.f;
-#define PMMF_PICKF(trq, q)                        \
-  if (trq > bt) { second = bt; bt = trq; best = q; } \
-  else second = fmaxf(second, trq);
-  PMMF_PICKF(tr1, 1)
-  PMMF_PICKF(tr2, 2)
-  PMMF_PICKF(tr3, 3)
-  PMMF_PICKF(tr4, 4)
-  PMMF_PICKF(tr5, 5)
-#undef PMMF_PICKF
-  trace_margin = bt > 0.f ? ((double)bt - second) / bt : 0.0;
-  int p0, p1, p2;
-  switch (best) {
-    case 0: p0 = 0; p1 = 1; p2 = 2; break;
-    case 1: p0 = 0; p1 = 2; p2 = 1; break;
-    case 2: p0 = 1; p1 = 0; p2 = 2; break;
-    case 3: p0 = 1; p1 = 2; p2 = 0; break;
-    case 4: p0 = 2; p1 = 0; p2 = 1; break;
-    default: p0 = 2; p1 = 1; p2 = 0; break;
-  }
-  // rows with static indices: select by comparing the permutation entries
+  double V0[3][3], P[3][3], V[3][3], W[3][3], A[3][3];
 #pragma unroll
-  for (int j = 0; j < 3; ++j) {
-    const float r0 = p0 == 0 ? b[0][j] : (p0 == 1 ? b[1][j] : b[2][j]);
-    const float r1 = p1 == 0 ? b[0][j] : (p1 == 1 ? b[1][j] : b[2][j]);
-    const float r2 = p2 == 0 ? b[0][j] : (p2 == 1 ? b[1][j] : b[2][j]);
-    O[0][j] = r0;
-    O[1][j] = r1;
-    O[2][j] = r2;
-  }
-  const double s0 = O[0][0] >= 0.0 ? 1.0 : -1.0;
-  const double s1 = O[1][1] >= 0.0 ? 1.0 : -1.0;
-  const double s2 = O[2][2] >= 0.0 ? 1.0 : -1.0;
+  for (int i = 0; i < 3; ++i)
 #pragma unroll
-  for (int j = 0; j < 3; ++j) {
-    O[0][j] *= s0;
-    O[1][j] *= s1;
-    O[2][j] *= s2;
-  }
+    for (int j = 0; j < 3; ++j) V0[i][j] = (double)Vf[i][j];
+  // P = (3I - V0^T V0) / 2, V = V0 P
+#pragma unroll
+  for (int i = 0; i < 3; ++i)
+#pragma unroll
+    for (int j = 0; j < 3; ++j) {
+      const double vtv = V0[0][i] * V0[0][j] + V0[1][i] * V0[1][j] + V0[2][i] * V0[2][j];
+      P[i][j] = (i == j ? 1.5 : 0.0) - 0.5 * vtv;
+    }
+#pragma unroll
+  for (int i = 0; i < 3; ++i)
+#pragma unroll
+    for (int j = 0; j < 3; ++j) V[i][j] = V0[i][0] * P[0][j] + V0[i][1] * P[1][j] + V0[i][2] * P[2][j];
+  // A = V^T g V
+#pragma unroll
+  for (int i = 0; i < 3; ++i)
+#pragma unroll
+    for (int j = 0; j < 3; ++j) W[i][j] = g[i][0] * V[0][j] + g[i][1] * V[1][j] + g[i][2] * V[2][j];
+#pragma unroll
+  for (int i = 0; i < 3; ++i)
+#pragma unroll
+    for (int j = 0; j < 3; ++j) A[i][j] = V[0][i] * W[0][j] + V[1][i] * W[1][j] + V[2][i] * W[2][j];
+#pragma unroll
+  for (int i = 0; i < 3; ++i)
+#pragma unroll
+    for (int j = 0; j < i; ++j) A[i][j] = A[j][i] = 0.5 * (A[i][j] + A[j][i]);
+  rot3_finish(A, V, O, trace_margin, eig_margin);
 }
 
 // ------------------------------------------------------------------------------------------
@@ -1245,7 +1223,7 @@ __global__ void __launch_bounds__(NT) k_find(FindArgs A, int cmax) {
         margin = fmin(margin, ta);
       } else {
         double tm, em;
-        rot3f(g, O, tm, em);
+        rot3_polished(g, O, tm, em);
         margin = fmin(margin, fmin(tm, em));
       }
       // rotated k x k blocks: O g O^T and O d O^T
