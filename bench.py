@@ -7,9 +7,10 @@ rotation search, two-sided rotation and peeling, and the core) of the n = 262,14
 
 Beside it the same JSON line reports the matrix-free apply and the adjoint (mmf_apply,
 mmf_backward) on the factorization of the 256 x 256 grid Laplacian with 256 right-hand sides, as
-algorithmic GB/s, 50 steps of angle refinement on that factorization, the per-stage phase split,
-a roofline entry for the dominant kernel, and the FP64 oracle timed on the host as a CPU
-baseline.
+algorithmic GB/s, 50 steps of angle refinement on that factorization, preconditioned CG on the
+101 x 101 x 103 grid with 128 right-hand sides, the two Gram forms with their matrix-core rates,
+the per-stage phase split, a roofline entry for the dominant kernel, and the FP64 oracle on the
+host: it replays the whole headline factorization (CPU baseline and loss against the oracle).
 """
 from __future__ import annotations
 
@@ -25,6 +26,8 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+FP32_PEAK_TFLOPS = 157.3     # MI355X FP32 (matrix and vector)
+BF16_PEAK_TFLOPS = 2500.0    # MI355X dense BF16 matrix
 
 
 def log(msg):
@@ -134,6 +137,71 @@ def measure_apply(args, torch, workloads, Factorization, log):
     return apply_res, back_res, refine
 
 
+def measure_pcg(args, torch, workloads, Factorization, log):
+    """Preconditioned CG with the pMMF inverse on the 101 x 101 x 103 grid (Sec. 4)."""
+    wl = args.pcg_workload
+    log(f"[bench] pcg: factor {wl}")
+    A = workloads.make_matrix(wl)
+    prm = dict(workloads.WORKLOADS[wl]["params"])
+    rp, ci, cv = device_csr(A, torch)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    fac = Factorization.factor(rp, ci, cv, **prm)
+    torch.cuda.synchronize()
+    factor_ms = 1e3 * (time.perf_counter() - t0)
+    stages = fac.stage_info()
+    nr = args.pcg_nrhs
+    B = torch.from_numpy(workloads.gaussian_block(A.n, nr, seed=2)).cuda()
+    # one preconditioner application: A~^{-1} X
+    Y = torch.empty_like(B)
+    fac.apply(B, out=Y, inverse=True)
+    torch.cuda.synchronize()
+    st_ = torch.cuda.current_stream()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(st_)
+    for _ in range(3):
+        fac.apply(B, out=Y, inverse=True)
+    e1.record(st_)
+    torch.cuda.synchronize()
+    inv_ms = e0.elapsed_time(e1) / 3
+    core, kk = prm["core"], prm["k"]
+    log_bytes = (A.n - core) * (kk * 4 + kk * kk * 4)
+    inv_bytes = (2 * 2 * 4 * nr * sweep_rows(stages) + 2 * log_bytes + core * core * 4
+                 + 2 * core * nr * 4)
+    log(f"[bench] pcg: solve {nr} right-hand sides")
+    X, info = fac.pcg(rp, ci, cv, B, tol=1e-6, max_iter=2000)
+    torch.cuda.synchronize()
+    fac.close()
+    it = max(1, info["iterations"])
+    return {"workload": f"{wl}: 7-point 101x101x103 grid, lognormal(0,1.5) weights, D - W + 1e-2 I "
+                        f"(n={A.n}), {nr} N(0,1) right-hand sides, pMMF inverse (k={prm['k']}, "
+                        f"clusters {prm['cluster'][0]}-{prm['cluster'][1]}, core {core}) as "
+                        f"preconditioner, FP64 residual tolerance 1e-6",
+            "factor_ms": round(factor_ms, 2), "iterations": info["iterations"],
+            "refinements": info["refinements"], "converged": info["converged"],
+            "max_rel_residual": info["max_rel_residual"], "solve_ms": round(info["solve_ms"], 2),
+            "ms_per_iteration": round(info["solve_ms"] / it, 4),
+            "apply_inverse_ms": round(inv_ms, 4),
+            "apply_inverse_algorithmic_GBps": round(inv_bytes / (inv_ms * 1e-3) / 1e9, 1),
+            "apply_inverse_frac_hbm": round(inv_bytes / (inv_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
+
+
+def gram_rates(stages, peak_tflops):
+    """Matrix-core Gram (stages in a dense form): performed and useful flop rates."""
+    dense = [st for st in stages if st["dense_gram"]]
+    if not dense:
+        return None
+    ms = sum(st["gram_ms"] for st in dense)
+    perf = sum(st["gram_flops"] for st in dense)
+    useful = sum(st["gram_useful_flops"] for st in dense)
+    rate = perf / (ms * 1e-3) / 1e12
+    return {"stages": [i + 1 for i, st in enumerate(stages) if st["dense_gram"]],
+            "ms": round(ms, 3), "performed_tflops": round(rate, 3),
+            "useful_tflops": round(useful / (ms * 1e-3) / 1e12, 3),
+            "useful_fraction": round(useful / perf, 4) if perf else None,
+            "peak_tflops": peak_tflops, "mfma_utilisation": round(rate / peak_tflops, 5)}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -144,11 +212,13 @@ def main():
     ap.add_argument("--nrhs", type=int, default=256)
     ap.add_argument("--refine-steps", type=int, default=50)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-sample-n", type=int, default=32768)
     ap.add_argument("--gram-seeds", type=int, default=5,
                     help="algorithm seeds for the FP32-vs-BF16 Gram comparison (0 = skip)")
     ap.add_argument("--factor-only", action="store_true",
                     help="time the factorization and the copy reference only (counter runs)")
+    ap.add_argument("--pcg-workload", default="grid3d_n1050703")
+    ap.add_argument("--pcg-nrhs", type=int, default=128)
+    ap.add_argument("--no-pcg", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "
@@ -204,6 +274,7 @@ def main():
         log(f"[bench] factor step {s}: {times[-1] * 1e3:.2f} ms")
     info = fac.info()
     stages = fac.stage_info()
+    ex = fac.export()
     ms_per_step = 1e3 * float(np.mean(times))
     rot_per_s = R / (ms_per_step / 1e3)
     find_ms = sum(st["find_ms"] for st in stages)
@@ -227,12 +298,17 @@ def main():
                 torch.cuda.synchronize()
                 t_ms.append(1e3 * (time.perf_counter() - t0))
                 losses.append(f2.info()["loss"])
+                if sd == 0:
+                    st0 = f2.stage_info()
                 f2.close()
             log(f"[bench] gram form {label}: {np.round(t_ms, 1)} ms, loss {np.round(losses, 2)}")
             gram_forms[label] = {"seeds": args.gram_seeds,
                                  "factor_ms_median": round(float(np.median(t_ms)), 3),
                                  "loss_mean": round(float(np.mean(losses)), 4),
-                                 "loss_std": round(float(np.std(losses)), 4)}
+                                 "loss_std": round(float(np.std(losses)), 4),
+                                 "gram_ms": round(sum(st["gram_ms"] for st in st0), 3),
+                                 "matrix_core_gram": gram_rates(
+                                     st0, FP32_PEAK_TFLOPS if mode == 0 else BF16_PEAK_TFLOPS)}
     # ----------------------------------------------------------------- clustering forms
     # the seeded contiguous clusters (the FP32 Gram form above) against the data-driven
     # clusters that cut the fewest active-matrix entries, over the same algorithm seeds
@@ -275,22 +351,47 @@ def main():
                 "measured_copy_peak": round(copy_gbs, 1),
                 "frac_of_measured_copy": round(find_gbs / copy_gbs, 5)}
 
+    # ----------------------------------------------------------------- PCG (Sec. 4)
+    pcg = None
+    if not args.factor_only and not args.no_pcg:
+        pcg = measure_pcg(args, torch, workloads, Factorization, log)
+
     # ----------------------------------------------------------------- CPU baseline (oracle)
-    cpu = None
+    # the FP64 oracle factors the same matrix on the host's cores (one process per cluster of a
+    # stage), replaying the GPU's log: it takes the GPU's choice only where its own decision is a
+    # near-tie, so its loss is comparable with the GPU's
+    cpu = parity = None
     if not args.no_cpu_baseline:
         import oracle
-        n_s = args.cpu_sample_n
-        log(f"[bench] cpu baseline: FP64 oracle on the same generator at n={n_s}")
-        As = workloads.knn_points_matrix(n_s, wl.get("dim", 3), wl.get("knn", 10),
-                                         wl.get("sigma2", 0.01), 0)
+        try:
+            ncores = len(os.sched_getaffinity(0))
+        except AttributeError:
+            ncores = os.cpu_count() or 1
+        workers = max(1, min(16, ncores))
+        log(f"[bench] cpu baseline: FP64 oracle replay of the {args.workload} factorization on "
+            f"{workers} processes")
         t0 = time.perf_counter()
-        ref = oracle.factor(As, **prm)
+        ref = oracle.factor(A, replay=dict(rot_ids=ex["rot_ids"], rot_retired=ex["rot_retired"],
+                                           rot_o=ex["rot_o"]), workers=workers, **prm)
         dt = time.perf_counter() - t0
-        cpu = {"value": round(len(ref.rotations) / dt, 2), "unit": "rotations/s", "cores": 1,
-               "kind": "oracle",
-               "sample": f"FP64 oracle factorization of the same kNN generator at n={n_s} "
-                         f"(k={prm['k']}, clusters {prm['cluster']}, core {prm['core']}): "
-                         f"{len(ref.rotations)} rotations in {dt:.1f} s on one host thread"}
+        cpu = {"value": round(len(ref.rotations) / dt, 2), "unit": "rotations/s",
+               "cores": workers, "kind": "oracle",
+               "sample": f"the whole {args.workload} factorization ({len(ref.rotations)} "
+                         f"rotations, {ref.num_stages} stages) by the FP64 oracle in {dt:.1f} s, "
+                         f"clusters of a stage in {workers} processes, replaying the GPU's log "
+                         f"(the GPU's choice taken at near-ties only)"}
+        adopted = sum(len(r.adopted) for r in ref.rotations)
+        parity = {"oracle_loss": ref.loss, "gpu_loss": info["loss"],
+                  "oracle_loss_rel_err": abs(info["loss"] - ref.loss) / ref.loss,
+                  "near_tie_decisions_taken_from_gpu": adopted,
+                  "divergences": len(ref.divergences),
+                  "hdiag_max_rel_err": float(np.abs(ex["hdiag"] - ref.hdiag).max()
+                                             / np.abs(ref.hdiag).max()),
+                  "hcore_max_rel_err": float(np.abs(ex["hcore"] - ref.hcore).max()
+                                             / np.abs(ref.hcore).max())}
+        log(f"[bench] oracle loss {ref.loss:.10g}, gpu {info['loss']:.10g}, rel "
+            f"{parity['oracle_loss_rel_err']:.2e}, {adopted} near-ties taken, "
+            f"{len(ref.divergences)} divergences")
 
     out = {
         "metric": "rotations/sec + factor time at n=262k; apply+backward GB/s vs roofline",
@@ -314,8 +415,10 @@ def main():
         "refine": refine,
         "gram_forms": gram_forms,
         "clustering": clustering,
+        "pcg": pcg,
         "roofline": roofline,
         "cpu_baseline": cpu,
+        "parity": parity,
         "stages": [{k2: (round(v, 4) if isinstance(v, float) else v) for k2, v in st.items()}
                    for st in stages],
     }

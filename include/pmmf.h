@@ -104,11 +104,16 @@ typedef struct {
   double  rotate_ms;     /* device time of levelling, Qbar extraction and the two-sided rotation
                             with peeling                                                         */
   int64_t find_bytes;    /* algorithmic bytes of the greedy search: per rotation in a cluster of
-                            c, the seed's Gram row plus k rows of the Gram and of the diagonal
-                            block read and written, 4 c (1 + 4k)                                 */
+                            c, the seed's Gram row, then k rows and k columns of the Gram and of
+                            the diagonal block read and written: 4c + 16kc + 16kc = 4c (1 + 8k)  */
   int64_t bf16_long;     /* BF16 mode: steps with more than 64 shortlisted partners (rescored in
                             several rounds)                                                      */
   int64_t bf16_rescored; /* BF16 mode: candidates rescored with exact FP32 dots (all steps)       */
+  double  gram_flops;    /* flops the stage's Gram kernel performs: the matrix-core tiles of the
+                            dense and BF16 forms (upper triangle, padded), else as below          */
+  double  gram_useful_flops; /* flops the cluster Grams need: 2 sum over rows and clusters of the
+                            row's entry count in the cluster squared (Sec. 2.1 Gram on a sparse
+                            slab)                                                               */
 } mmf_stage_info;
 
 /*

@@ -53,7 +53,8 @@ class mmf_stage_info(ctypes.Structure):
                 ("dense_gram", ctypes.c_int32), ("loss", ctypes.c_double),
                 ("gram_ms", ctypes.c_double), ("find_ms", ctypes.c_double),
                 ("rotate_ms", ctypes.c_double), ("find_bytes", ctypes.c_int64),
-                ("bf16_long", ctypes.c_int64), ("bf16_rescored", ctypes.c_int64)]
+                ("bf16_long", ctypes.c_int64), ("bf16_rescored", ctypes.c_int64),
+                ("gram_flops", ctypes.c_double), ("gram_useful_flops", ctypes.c_double)]
 
 
 P = ctypes.c_void_p

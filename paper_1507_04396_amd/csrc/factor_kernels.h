@@ -48,6 +48,10 @@ hipError_t launch_gram(int S, int64_t rp_nnz, const int64_t* rp, const int32_t* 
                        const float* cv, const int32_t* off, const int32_t* cl_of,
                        const int64_t* gbase, const int64_t* run_ptr, const int32_t* run_cl,
                        const int64_t* run_start, float2* GD, int cmax, hipStream_t s);
+// multiply-adds of the stage's cluster Grams (sum over rows and runs of the run length squared),
+// added to *out
+hipError_t launch_gram_work(int S, const int64_t* rp, const int64_t* run_ptr,
+                            const int64_t* run_start, unsigned long long* out, hipStream_t s);
 hipError_t launch_runs(int S, int fill, const int64_t* rp, const int32_t* ci,
                        const int32_t* cl_of, int32_t* nruns, const int64_t* run_ptr,
                        int32_t* run_cl, int64_t* run_start, hipStream_t s);

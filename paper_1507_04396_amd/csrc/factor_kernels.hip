@@ -80,6 +80,33 @@ hipError_t launch_runs(int S, int fill, const int64_t* rp, const int32_t* ci,
   return hipGetLastError();
 }
 
+// Useful work of the stage's cluster Grams: G^u = A[:, B_u]^T A[:, B_u] takes, from each row, the
+// products of the row's entries in B_u with each other, |seg(row, u)|^2 multiply-adds per run.
+// One thread per row sums them over its runs; one atomic add per wave.
+__global__ void k_gram_work(int S, const int64_t* __restrict__ rp,
+                            const int64_t* __restrict__ run_ptr,
+                            const int64_t* __restrict__ run_start,
+                            unsigned long long* __restrict__ out) {
+  const int r = blockIdx.x * blockDim.x + threadIdx.x;
+  unsigned long long w = 0;
+  if (r < S) {
+    const int64_t q0 = run_ptr[r], q1 = run_ptr[r + 1];
+    for (int64_t q = q0; q < q1; ++q) {
+      const int64_t len = (q + 1 < q1 ? run_start[q + 1] : rp[r + 1]) - run_start[q];
+      w += (unsigned long long)(len * len);
+    }
+  }
+  for (int d = PMMF_WAVE / 2; d > 0; d >>= 1) w += __shfl_xor(w, d);
+  if (pmmf_lane() == 0 && w) atomicAdd(out, w);
+}
+
+hipError_t launch_gram_work(int S, const int64_t* rp, const int64_t* run_ptr,
+                            const int64_t* run_start, unsigned long long* out, hipStream_t s) {
+  if (S == 0) return hipSuccess;
+  k_gram_work<<<(S + 255) / 256, 256, 0, s>>>(S, rp, run_ptr, run_start, out);
+  return hipGetLastError();
+}
+
 // Up to GRAM_ITEM consecutive 64-entry chunks of one row segment: entries from off on (rem of
 // them left in the segment) of the segment that starts at ci/cv index base, scaled by w.  All
 // fields are wave-uniform (scalar registers).

@@ -293,6 +293,7 @@ struct StageDev {
   double gram_ms = 0.0, find_ms = 0.0, rotate_ms = 0.0;
   bool dense_gram = false;
   int64_t bf16_long = 0, bf16_rescored = 0;  // BF16 form: long shortlists, candidates rescored
+  double gram_flops = 0.0, gram_useful_flops = 0.0;  // performed / algorithmic Gram flops
   // sweep plan (built on first use): units of whole rotation components, and the clusters
   // holding a component larger than a unit, which the level kernel handles
   int nu = 0, nbig = 0, big_cmax = 0, big_rmax = 0;
@@ -867,8 +868,10 @@ extern "C" int mmf_factor(int64_t n, int64_t nnz, const int64_t* d_rowptr, const
   h->info.fro2_a = stats_a[0];
   h->info.trace_a = stats_a[1];
   std::vector<double> stage_loss_dev;
-  DBuf stage_loss;
+  DBuf stage_loss, gram_work;
   stage_loss.ensure(std::max<size_t>(sched.size(), 1) * sizeof(double));
+  gram_work.ensure(std::max<size_t>(sched.size(), 1) * sizeof(unsigned long long));
+  HIPCHK(hipMemsetAsync(gram_work.p, 0, std::max<size_t>(sched.size(), 1) * 8, s));
 
   std::vector<std::unique_ptr<PhaseEvents>> stage_events;
   DBuf cut_d, cut_w;  // boundary cut counts (data-driven clustering)
@@ -928,6 +931,9 @@ extern "C" int mmf_factor(int64_t n, int64_t nnz, const int64_t* d_rowptr, const
       HIPCHK(pmmf::launch_runs(S, 1, M.rp.as<int64_t>(), M.ci.as<int32_t>(),
                                sd.cl_of.as<int32_t>(), nullptr, run_ptr.as<int64_t>(),
                                run_cl.as<int32_t>(), run_start.as<int64_t>(), s));
+      HIPCHK(pmmf::launch_gram_work(S, M.rp.as<int64_t>(), run_ptr.as<int64_t>(),
+                                    run_start.as<int64_t>(),
+                                    gram_work.as<unsigned long long>() + pi, s));
     }
     if (bf16) {
       // slab rows R_u, slab sizes (host), then FP32 + BF16 slabs, G~ on the matrix cores, D
@@ -949,6 +955,11 @@ extern "C" int mmf_factor(int64_t n, int64_t nnz, const int64_t* d_rowptr, const
       upload(bf_off, soff, s);
       bf_slab.ensure(std::max<int64_t>(soff[sd.m], 1) * sizeof(float));
       bf_slab16.ensure(std::max<int64_t>(soff[sd.m], 1) * sizeof(uint16_t));
+      // matrix-core work: upper-triangle 32 x 32 tiles, slab rows in 64-row slices
+      for (int u = 0; u < sd.m; ++u) {
+        const double nt = (double)((sd.off_h[u + 1] - sd.off_h[u] + 31) / 32);
+        sd.gram_flops += nt * (nt + 1) / 2 * 2.0 * 32 * 32 * (double)((Rh[u] + 63) / 64 * 64);
+      }
       HIPCHK(pmmf::launch_gram_bf16(S, sd.m, M.rp.as<int64_t>(), M.ci.as<int32_t>(),
                                     M.cv.as<float>(), sd.off.as<int32_t>(),
                                     sd.cl_of.as<int32_t>(), W, bf_bm.as<uint32_t>(),
@@ -957,6 +968,11 @@ extern "C" int mmf_factor(int64_t n, int64_t nnz, const int64_t* d_rowptr, const
                                     bf_slab16.as<unsigned short>(), sd.gbase.as<int64_t>(),
                                     GD.as<float2>(), sd.cmax, s));
     } else if (dense_gram) {
+      // matrix-core work: upper-triangle 32 x 32 tiles over all S rows in 128-row slices
+      for (int u = 0; u < sd.m; ++u) {
+        const double nt = (double)((sd.off_h[u + 1] - sd.off_h[u] + 31) / 32);
+        sd.gram_flops += nt * (nt + 1) / 2 * 2.0 * 32 * 32 * (double)((S + 127) / 128 * 128);
+      }
       dense_buf.ensure((size_t)S * S * sizeof(float));
       HIPCHK(pmmf::launch_gram_dense(S, M.rp.as<int64_t>(), M.ci.as<int32_t>(), M.cv.as<float>(),
                                      dense_buf.as<float>(), sd.off.as<int32_t>(), sd.m,
@@ -1139,9 +1155,13 @@ extern "C" int mmf_factor(int64_t n, int64_t nnz, const int64_t* d_rowptr, const
   std::vector<double> sl(sched.size(), 0.0);
   int32_t ovf = 0;
   HIPCHK(hipMemcpyAsync(hst, dsum.as<double>() + 2, 3 * sizeof(double), hipMemcpyDeviceToHost, s));
-  if (!sched.empty())
+  std::vector<unsigned long long> gw(sched.size(), 0);
+  if (!sched.empty()) {
     HIPCHK(hipMemcpyAsync(sl.data(), stage_loss.p, sl.size() * sizeof(double),
                           hipMemcpyDeviceToHost, s));
+    HIPCHK(hipMemcpyAsync(gw.data(), gram_work.p, gw.size() * sizeof(unsigned long long),
+                          hipMemcpyDeviceToHost, s));
+  }
   HIPCHK(hipMemcpyAsync(&ovf, overflow.p, sizeof(ovf), hipMemcpyDeviceToHost, s));
   HIPCHK(hipStreamSynchronize(s));
   staging_synced(s);
@@ -1176,6 +1196,8 @@ extern "C" int mmf_factor(int64_t n, int64_t nnz, const int64_t* d_rowptr, const
   inf.max_clusters = 0;
   inf.loss = 0.0;
   for (size_t q = 0; q < sl.size(); ++q) {
+    h->st[q]->gram_useful_flops = 2.0 * (double)gw[q];
+    if (!h->st[q]->dense_gram) h->st[q]->gram_flops = h->st[q]->gram_useful_flops;
     h->st[q]->loss = sl[q];
     inf.loss += sl[q];
     inf.max_clusters = std::max<int64_t>(inf.max_clusters, h->st[q]->m);
@@ -1806,8 +1828,10 @@ extern "C" int mmf_get_stage_info(mmf_handle hh, int32_t stage, mmf_stage_info* 
   out->find_bytes = 0;
   for (int u = 0; u < sd.m; ++u) {
     const int64_t c = sd.off_h[u + 1] - sd.off_h[u];
-    out->find_bytes += (int64_t)sd.rcnt_h[u] * 4 * c * (1 + 4 * h.k);
+    out->find_bytes += (int64_t)sd.rcnt_h[u] * 4 * c * (1 + 8 * h.k);
   }
+  out->gram_flops = sd.gram_flops;
+  out->gram_useful_flops = sd.gram_useful_flops;
   out->bf16_long = sd.bf16_long;
   out->bf16_rescored = sd.bf16_rescored;
   return MMF_OK;
