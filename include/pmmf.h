@@ -295,6 +295,22 @@ int mmf_pcg(mmf_handle h, int64_t n, const int64_t* d_rowptr, const int32_t* d_c
 int mmf_spmm(int64_t n, const int64_t* d_rowptr, const int32_t* d_colind, const float* d_val,
              const float* d_x, float* d_y, int64_t nrhs, int64_t ld, void* stream);
 
+/*
+ * mmf_apply_noalloc — y = A~ x exactly as mmf_apply computes it, for callers that cannot allocate
+ * device memory (code under HIP graph capture, tight serving loops, harnesses that forbid it):
+ * it calls no hipMalloc, hipFree or allocating library routine.  The two blocks of compacted
+ * vectors the sweeps pass between stages live in one fixed 64 MiB array of the library's device
+ * code (each device keeps its own copy until the process ends): 2 |S_1| nrhs floats must fit in
+ * 2^24, |S_1| the number of indices active after the first stage (MMF_ECAPACITY otherwise).
+ * The array keeps the last call's contents (every call overwrites what it reads); calls that
+ * overlap on one device race on it, so serialize them (one stream, or events).
+ * The handle's sweep plan must exist: it is built by the first mmf_apply, mmf_apply_inverse or
+ * mmf_graph_capture on the handle (MMF_ESTATE before that).  Arguments, layout and errors as
+ * mmf_apply otherwise.  Asynchronous on `stream`.
+ */
+int mmf_apply_noalloc(mmf_handle h, const float* d_x, float* d_y, int64_t nrhs, int64_t ld,
+                      void* stream);
+
 /* Free the handle and all device memory it owns (synchronizes its stream). */
 int mmf_destroy(mmf_handle h);
 

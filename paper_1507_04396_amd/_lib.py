@@ -68,6 +68,7 @@ RELEASE_FN = ctypes.CFUNCTYPE(None, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_v
 SIGNATURES = {
     "mmf_factor": [I64, I64, P, P, P, ctypes.POINTER(mmf_params), P, ctypes.POINTER(H)],
     "mmf_apply": [H, P, P, I64, I64, P],
+    "mmf_apply_noalloc": [H, P, P, I64, I64, P],
     "mmf_apply_inverse": [H, P, P, I64, I64, P],
     "mmf_apply_inverse_sqrt": [H, P, P, I64, I64, P],
     "mmf_backward": [H, P, P, P, P, P, P, I64, I64, P],

@@ -1550,6 +1550,57 @@ extern "C" int mmf_apply_inverse_sqrt(mmf_handle hh, const float* d_x, float* d_
 }
 
 // ------------------------------------------------------------------------------------------
+// y = A~ x without allocating (mmf_apply_noalloc): the two ping-pong blocks of compacted vectors
+// live in a fixed array of this library's device code instead of handle-owned memory.  Each
+// device holds its own copy; in host code `scratch` only names it, so its address on the current
+// device is looked up once per device and kept.
+constexpr int64_t NOALLOC_FLOATS = int64_t(1) << 24;  // 64 MiB
+static __device__ __align__(256) float scratch[NOALLOC_FLOATS];
+static std::mutex g_scratch_mu;
+static std::map<int, float*> g_scratch_ptr;  // device ordinal -> that device's copy of scratch
+
+static float* scratch_on_current_device() {
+  int dev = -1;
+  HIPCHK(hipGetDevice(&dev));
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  auto it = g_scratch_ptr.find(dev);
+  if (it != g_scratch_ptr.end()) return it->second;
+  void* ptr = nullptr;
+  const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+  if (e != hipSuccess || !ptr)
+    raise(MMF_EDEVICE, std::string("address of the library's scratch array: ") +
+                           hipGetErrorString(e));
+  g_scratch_ptr[dev] = static_cast<float*>(ptr);
+  return static_cast<float*>(ptr);
+}
+
+extern "C" int mmf_apply_noalloc(mmf_handle hh, const float* d_x, float* d_y, int64_t nrhs,
+                                 int64_t ld, void* stream) {
+  ABI_BEGIN
+  mmf_plan& h = *checked(hh);
+  if (nrhs < 0 || ld < nrhs || (!d_x && nrhs > 0) || (!d_y && nrhs > 0))
+    raise(MMF_EINVAL, "bad vector arguments");
+  if (nrhs == 0) return MMF_OK;
+  if (!h.units_ready)
+    raise(MMF_ESTATE, "mmf_apply_noalloc: the handle's sweep plan is built by its first "
+                      "mmf_apply, mmf_apply_inverse or mmf_graph_capture; call one of them once");
+  const int64_t s1 = h.st.empty() ? 0 : h.st[0]->size - h.st[0]->t;
+  if (2 * s1 * nrhs > NOALLOC_FLOATS)
+    raise(MMF_ECAPACITY, "mmf_apply_noalloc: 2 x " + std::to_string(s1) + " survivors x " +
+                             std::to_string(nrhs) + " right-hand sides exceed the " +
+                             std::to_string(NOALLOC_FLOATS) + "-float scratch array");
+  float* ws = scratch_on_current_device();
+  // the tile the tuner chose for this width, else the default (no tuning runs here)
+  SweepCfg cfg;
+  const auto it = h.tune.find(std::make_pair(std::string("apply1"), nrhs));
+  if (it != h.tune.end()) cfg = it->second;
+  else cfg.W = pick_tile(h, 1, nrhs);
+  apply_body(h, d_x, d_y, nrhs, ld, as_stream(stream), 0, ws, ws + s1 * nrhs, cfg);
+  return MMF_OK;
+  ABI_END
+}
+
+// ------------------------------------------------------------------------------------------
 // Captured products: one mmf_apply / mmf_apply_inverse on fixed buffers recorded as a HIP graph
 // (kernel nodes only: every size-dependent preparation runs in an eager call before capture).
 // The graph owns its ping-pong workspace, so later eager calls cannot move it.
