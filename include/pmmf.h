@@ -247,6 +247,13 @@ int mmf_param_ptrs(mmf_handle h, float** theta, float** hdiag, float** hcore);
 int mmf_sync_angles(mmf_handle h, void* stream);
 
 /*
+ * mmf_get_params — copy the handle's parameters into caller device buffers, on `stream` (the
+ * layouts of mmf_param_ptrs: theta [R] or [R][3], hdiag [n], hcore [core][core]); any may be NULL.
+ * Errors: MMF_ESTATE, MMF_EDEVICE.
+ */
+int mmf_get_params(mmf_handle h, float* d_theta, float* d_hdiag, float* d_hcore, void* stream);
+
+/*
  * mmf_set_params — copy new parameters from caller device buffers into the handle, on `stream`:
  *   d_theta (layout of mmf_param_ptrs), d_hdiag [n], d_hcore [core][core]; any may be NULL.
  * Recomputes the rotations from theta when it is given and drops the cached core factor.
@@ -283,6 +290,18 @@ typedef struct {
 int mmf_pcg(mmf_handle h, int64_t n, const int64_t* d_rowptr, const int32_t* d_colind,
             const float* d_val, const float* d_b, double* d_x, int64_t nrhs, double tol,
             int32_t max_iter, double inner_reduction, void* stream, mmf_pcg_info* out);
+
+/*
+ * mmf_pcg_split — the same solve in the split-symmetric form of Sec. 4: the inner iterations run
+ * plain CG on the symmetric (M^{-1/2} A M^{-1/2}) y = M^{-1/2} r with M^{-1/2} = A~^{-1/2}
+ * (mmf_apply_inverse_sqrt, two applications per iteration, both replayed as captured graphs) and
+ * set d = M^{-1/2} y; the inner loop stops once every active column's ||M^{-1/2} (r - A d)|| has
+ * dropped by `inner_reduction`, and the outer FP64 correction is as in mmf_pcg.  Requires H
+ * positive definite (MMF_ESINGULAR otherwise).  Arguments, result and errors as mmf_pcg.
+ */
+int mmf_pcg_split(mmf_handle h, int64_t n, const int64_t* d_rowptr, const int32_t* d_colind,
+                  const float* d_val, const float* d_b, double* d_x, int64_t nrhs, double tol,
+                  int32_t max_iter, double inner_reduction, void* stream, mmf_pcg_info* out);
 
 /*
  * mmf_spmm — Y = A X for a CSR matrix (device) and row-major [n][ld] blocks X, Y (device, no

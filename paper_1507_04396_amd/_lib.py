@@ -77,9 +77,12 @@ SIGNATURES = {
     "mmf_export": [H, P, P, P, P, P, P, P],
     "mmf_import": [I64, I32, I64, I32, P, P, P, P, P, P, P, P, P, P, ctypes.POINTER(H)],
     "mmf_param_ptrs": [H, P, P, P],
+    "mmf_get_params": [H, P, P, P, P],
     "mmf_sync_angles": [H, P],
     "mmf_set_params": [H, P, P, P, P],
     "mmf_pcg": [H, I64, P, P, P, P, P, I64, ctypes.c_double, I32, ctypes.c_double, P,
+                ctypes.POINTER(mmf_pcg_info)],
+    "mmf_pcg_split": [H, I64, P, P, P, P, P, I64, ctypes.c_double, I32, ctypes.c_double, P,
                 ctypes.POINTER(mmf_pcg_info)],
     "mmf_spmm": [I64, P, P, P, P, P, I64, I64, P],
     "mmf_graph_capture": [H, I32, P, P, I64, I64, P, ctypes.POINTER(H)],

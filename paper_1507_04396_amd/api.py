@@ -74,7 +74,6 @@ class Factorization:
         self.n = n
         self.k = k
         self.core = core
-        self._theta3 = None  # k = 3: the angles last handed to set_params (zero until then)
 
     # ------------------------------------------------------------------ construction
     @classmethod
@@ -229,8 +228,9 @@ class Factorization:
 
     def pcg(self, rowptr: torch.Tensor, colind: torch.Tensor, val: torch.Tensor,
             b: torch.Tensor, tol: float = 1e-6, max_iter: int = 2000,
-            inner_reduction: float = 1e-3, stream=None):
-        """mmf_pcg: solve A X = B with the factorization's inverse as preconditioner.
+            inner_reduction: float = 1e-3, stream=None, split: bool = False):
+        """mmf_pcg: solve A X = B with the factorization's inverse as preconditioner
+        (``split=True``: mmf_pcg_split, CG on A~^{-1/2} A A~^{-1/2}).
 
         Returns (X float64 [n][nrhs], info dict)."""
         _require_device(rowptr, torch.int64, "rowptr")
@@ -242,9 +242,10 @@ class Factorization:
         _require_device(b2, torch.float32, "b")
         x = torch.empty(b2.shape, dtype=torch.float64, device=b2.device)
         inf = _lib.mmf_pcg_info()
-        check(_lib.load().mmf_pcg(self.handle, rowptr.numel() - 1, _ptr(rowptr), _ptr(colind),
-                                  _ptr(val), _ptr(b2), _ptr(x), b2.shape[1], tol, max_iter,
-                                  inner_reduction, _stream(stream), ctypes.byref(inf)))
+        fn = _lib.load().mmf_pcg_split if split else _lib.load().mmf_pcg
+        check(fn(self.handle, rowptr.numel() - 1, _ptr(rowptr), _ptr(colind), _ptr(val),
+                 _ptr(b2), _ptr(x), b2.shape[1], tol, max_iter, inner_reduction,
+                 _stream(stream), ctypes.byref(inf)))
         return x, {f: getattr(inf, f) for f, _ in _lib.mmf_pcg_info._fields_ if f != "pad"}
 
     def capture(self, x: torch.Tensor, y: torch.Tensor, inverse: bool = False,
@@ -267,23 +268,18 @@ class Factorization:
                 _require_device(t, torch.float32, nm)
         check(_lib.load().mmf_set_params(self.handle, _ptr(theta), _ptr(hdiag), _ptr(hcore),
                                          _stream(stream)))
-        if theta is not None and self.k == 3:
-            self._theta3 = theta.detach().clone().reshape(-1, 3)
 
-    def params(self):
-        """Copies of (theta, hdiag, hcore) as device tensors: theta is [R] Givens angles (k = 2) or
-        [R][3] angles of the 3-point rotations about the rotations as found (k = 3)."""
-        ex = self.export()
-        dev = "cuda"
-        if self.k == 2:
-            o = ex["rot_o"]
-            theta = torch.tensor(np.arctan2(o[:, 1, 0], o[:, 0, 0]), dtype=torch.float32,
-                                 device=dev)
-        elif self._theta3 is not None:
-            theta = self._theta3.clone()
-        else:
-            theta = torch.zeros(self.n - self.core, 3, dtype=torch.float32, device=dev)
-        return theta, torch.tensor(ex["hdiag"], device=dev), torch.tensor(ex["hcore"], device=dev)
+    def params(self, stream=None):
+        """Copies of the handle's (theta, hdiag, hcore) as device tensors (mmf_get_params): theta
+        is [R] Givens angles (k = 2) or [R][3] angles of the 3-point rotations about the rotations
+        as found (k = 3)."""
+        R = self.n - self.core
+        theta = torch.empty((R,) if self.k == 2 else (R, 3), dtype=torch.float32, device="cuda")
+        hdiag = torch.empty(self.n, dtype=torch.float32, device="cuda")
+        hcore = torch.empty(self.core, self.core, dtype=torch.float32, device="cuda")
+        check(_lib.load().mmf_get_params(self.handle, _ptr(theta), _ptr(hdiag), _ptr(hcore),
+                                         _stream(stream)))
+        return theta, hdiag, hcore
 
 
 class ProductGraph:
@@ -315,10 +311,13 @@ class MMFApply(torch.autograd.Function):
 
     @staticmethod
     def forward(ctx, x, theta, hdiag, hcore, fac: Factorization):
-        fac.set_params(theta=theta.detach().contiguous(), hdiag=hdiag.detach().contiguous(),
-                       hcore=hcore.detach().contiguous())
+        # the parameters this product used, kept for the backward: the handle may hold others by
+        # then (another forward or set_params on the same factorization)
+        params = tuple(t.detach().contiguous().clone() for t in (theta, hdiag, hcore))
+        fac.set_params(theta=params[0], hdiag=params[1], hcore=params[2])
         y = fac.apply(x.detach())
         ctx.fac = fac
+        ctx.params = params
         ctx.save_for_backward(x)
         return y
 
@@ -327,6 +326,8 @@ class MMFApply(torch.autograd.Function):
         (x,) = ctx.saved_tensors
         need = ctx.needs_input_grad
         want = tuple(nm for nm, w in zip(("x", "theta", "hdiag", "hcore"), need[:4]) if w)
+        th, hd, hc = ctx.params
+        ctx.fac.set_params(theta=th, hdiag=hd, hcore=hc)
         xb, hdb, hcb, thb = ctx.fac.backward(x.detach(), ybar.contiguous(), want=want)
         if xb is not None and x.dim() == 1:
             xb = xb[:, 0]

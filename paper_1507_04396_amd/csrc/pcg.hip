@@ -171,10 +171,12 @@ namespace pmmf_host_detail {
 void set_error(const std::string& msg);
 }
 
-extern "C" int mmf_pcg(mmf_handle h, int64_t n, const int64_t* d_rowptr, const int32_t* d_colind,
-                       const float* d_val, const float* d_b, double* d_x, int64_t nrhs,
-                       double tol, int32_t max_iter, double inner_reduction, void* stream,
-                       mmf_pcg_info* out) {
+// split = false: CG on M^{-1} A (left preconditioning, z = M^{-1} r);
+// split = true:  CG on the symmetric M^{-1/2} A M^{-1/2} y = M^{-1/2} r with d = M^{-1/2} y.
+static int pcg_impl(mmf_handle h, int64_t n, const int64_t* d_rowptr, const int32_t* d_colind,
+                    const float* d_val, const float* d_b, double* d_x, int64_t nrhs, double tol,
+                    int32_t max_iter, double inner_reduction, void* stream, mmf_pcg_info* out,
+                    bool split) {
   using namespace pmmf;
   try {
     if (!h || !d_rowptr || !d_colind || !d_val || !d_b || !d_x || nrhs < 1 || n < 1 ||
@@ -221,14 +223,29 @@ extern "C" int mmf_pcg(mmf_handle h, int64_t n, const int64_t* d_rowptr, const i
       chk(hipGetLastError(), "kernels");
       chk(hipStreamSynchronize(s), "sync");
     }
-    // the preconditioner product R -> Z is captured once as a graph and replayed after that
+    // the preconditioner products are captured once as graphs and replayed after that: R -> Z
+    // (M^{-1}); split form: P -> T1 and T2 -> AP (M^{-1/2})
     struct GraphGuard {
       mmf_graph g = nullptr;
       ~GraphGuard() { if (g) (void)mmf_graph_destroy(g); }
-    } pre;
+    } pre, half1, half2;
     auto precondition = [&]() -> int {
       if (!pre.g) return mmf_graph_capture(h, 1, R.as<float>(), Z.as<float>(), nrhs, ld, stream, &pre.g);
       return mmf_graph_launch(pre.g, stream);
+    };
+    Buf T1(split ? N * 4 : 16), T2(split ? N * 4 : 16);
+    if (!T1.p || !T2.p) throw PcgErr{MMF_ENOMEM, "PCG workspace allocation failed"};
+    auto half = [&](GraphGuard& gg, const float* src, float* dst) -> int {
+      if (!gg.g) return mmf_graph_capture(h, 2, src, dst, nrhs, ld, stream, &gg.g);
+      return mmf_graph_launch(gg.g, stream);
+    };
+    // split form: AP = M^{-1/2} A M^{-1/2} P
+    auto split_product = [&]() -> int {
+      int r2 = half(half1, P.as<float>(), T1.as<float>());
+      if (r2 != MMF_OK) return r2;
+      k_spmm_f32<<<(unsigned)((n + 3) / 4), 256, 0, s>>>(n, d_rowptr, d_colind, d_val,
+                                                         T1.as<float>(), T2.as<float>(), nrhs, ld);
+      return half(half2, T2.as<float>(), AP.as<float>());
     };
     std::vector<double> bn(nrhs), rn(nrhs), rzh(nrhs);
     chk(hipMemcpy(bn.data(), bb.p, nrhs * 8, hipMemcpyDeviceToHost), "copy");
@@ -258,13 +275,30 @@ extern "C" int mmf_pcg(mmf_handle h, int64_t n, const int64_t* d_rowptr, const i
       k_to_f32_scaled<<<ewb, 256, 0, s>>>(n, nrhs, ld, R64.as<double>(), scale.as<double>(),
                                           R.as<float>());
       chk(hipMemsetAsync(Dx.p, 0, N * 4, s), "memset");
-      rc = precondition();
-      if (rc != MMF_OK) return rc;
+      std::vector<double> r0n(nrhs, 1.0);  // split form: ||M^{-1/2} r|| at the start
+      if (split) {
+        // R <- M^{-1/2} R: the residual of the symmetric system in y (Dx holds y)
+        rc = mmf_apply_inverse_sqrt(h, R.as<float>(), Z.as<float>(), nrhs, ld, stream);
+        if (rc != MMF_OK) return rc;
+        chk(hipMemcpyAsync(R.p, Z.p, N * 4, hipMemcpyDeviceToDevice, s), "copy");
+        coldot32(R.as<float>(), R.as<float>(), rr.as<double>());
+        chk(hipMemcpyAsync(r0n.data(), rr.p, nrhs * 8, hipMemcpyDeviceToHost, s), "copy");
+        chk(hipStreamSynchronize(s), "sync");
+        for (auto& v : r0n) v = std::sqrt(v);
+      } else {
+        rc = precondition();
+        if (rc != MMF_OK) return rc;
+      }
       chk(hipMemcpyAsync(P.p, Z.p, N * 4, hipMemcpyDeviceToDevice, s), "copy");
       coldot32(R.as<float>(), Z.as<float>(), rz.as<double>());
       while (total_it < max_iter) {
-        k_spmm_f32<<<rowb, 256, 0, s>>>(n, d_rowptr, d_colind, d_val, P.as<float>(), AP.as<float>(),
-                                        nrhs, ld);
+        if (split) {
+          rc = split_product();
+          if (rc != MMF_OK) return rc;
+        } else {
+          k_spmm_f32<<<rowb, 256, 0, s>>>(n, d_rowptr, d_colind, d_val, P.as<float>(),
+                                          AP.as<float>(), nrhs, ld);
+        }
         coldot32(P.as<float>(), AP.as<float>(), pap.as<double>());
         k_cg_alpha<<<(unsigned)((nrhs + 255) / 256), 256, 0, s>>>(
             nrhs, rz.as<double>(), pap.as<double>(), active.as<int32_t>(), alpha.as<float>());
@@ -278,16 +312,27 @@ extern "C" int mmf_pcg(mmf_handle h, int64_t n, const int64_t* d_rowptr, const i
         chk(hipStreamSynchronize(s), "sync");
         bool inner_done = true;
         for (int64_t j = 0; j < nrhs; ++j)
-          if (act[j] && !(std::sqrt(rn[j]) <= inner_reduction)) inner_done = false;
+          if (act[j] && !(std::sqrt(rn[j]) <= inner_reduction * r0n[j])) inner_done = false;
         if (inner_done) break;
-        rc = precondition();
-        if (rc != MMF_OK) return rc;
+        if (split) {
+          // unpreconditioned CG on the symmetric operator: the direction follows the residual
+          chk(hipMemcpyAsync(Z.p, R.p, N * 4, hipMemcpyDeviceToDevice, s), "copy");
+        } else {
+          rc = precondition();
+          if (rc != MMF_OK) return rc;
+        }
         coldot32(R.as<float>(), Z.as<float>(), rz2.as<double>());
         k_cg_beta<<<(unsigned)((nrhs + 255) / 256), 256, 0, s>>>(nrhs, rz2.as<double>(),
                                                                  rz.as<double>(), beta.as<float>());
         k_cg_direction<<<ewb, 256, 0, s>>>(n, nrhs, ld, beta.as<float>(), Z.as<float>(),
                                            P.as<float>());
         chk(hipMemcpyAsync(rz.p, rz2.p, nrhs * 8, hipMemcpyDeviceToDevice, s), "copy");
+      }
+      if (split) {
+        // d = M^{-1/2} y
+        rc = mmf_apply_inverse_sqrt(h, Dx.as<float>(), T1.as<float>(), nrhs, ld, stream);
+        if (rc != MMF_OK) return rc;
+        chk(hipMemcpyAsync(Dx.p, T1.p, N * 4, hipMemcpyDeviceToDevice, s), "copy");
       }
       k_accumulate_scaled<<<ewb, 256, 0, s>>>(n, nrhs, ld, scale.as<double>(), Dx.as<float>(),
                                               d_x);
@@ -314,6 +359,22 @@ extern "C" int mmf_pcg(mmf_handle h, int64_t n, const int64_t* d_rowptr, const i
     pmmf_host_detail::set_error(e.msg);
     return e.code;
   }
+}
+
+extern "C" int mmf_pcg(mmf_handle h, int64_t n, const int64_t* d_rowptr, const int32_t* d_colind,
+                       const float* d_val, const float* d_b, double* d_x, int64_t nrhs,
+                       double tol, int32_t max_iter, double inner_reduction, void* stream,
+                       mmf_pcg_info* out) {
+  return pcg_impl(h, n, d_rowptr, d_colind, d_val, d_b, d_x, nrhs, tol, max_iter,
+                  inner_reduction, stream, out, false);
+}
+
+extern "C" int mmf_pcg_split(mmf_handle h, int64_t n, const int64_t* d_rowptr,
+                             const int32_t* d_colind, const float* d_val, const float* d_b,
+                             double* d_x, int64_t nrhs, double tol, int32_t max_iter,
+                             double inner_reduction, void* stream, mmf_pcg_info* out) {
+  return pcg_impl(h, n, d_rowptr, d_colind, d_val, d_b, d_x, nrhs, tol, max_iter,
+                  inner_reduction, stream, out, true);
 }
 
 extern "C" int mmf_spmm(int64_t n, const int64_t* d_rowptr, const int32_t* d_colind,

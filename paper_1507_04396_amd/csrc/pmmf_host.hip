@@ -37,8 +37,9 @@ struct Block {
   void* p;
   size_t bytes;
   int dev;
-  void* stream;  // stream of the releasing call
-  bool idle;     // the device has been synchronized since the release
+  void* stream;    // stream of the releasing call
+  bool idle;       // the device has been synchronized since the release
+  uint64_t epoch;  // release count when it was released
 };
 struct Live {
   size_t bytes;
@@ -47,6 +48,7 @@ struct Live {
 std::vector<Block> g_kept;               // released blocks, oldest first
 std::map<void*, Live> g_out;            // blocks handed out by the default allocator
 size_t g_kept_bytes = 0;
+uint64_t g_releases = 0;  // releases so far (a synchronization covers those made before it)
 constexpr size_t kKeepMax = 64ull << 30;  // at most this much is kept for reuse
 
 // best-fitting kept block for `bytes` on `dev` (sizes up to twice the request), or -1
@@ -89,10 +91,18 @@ void* default_alloc(size_t bytes) {
       }
       if (pass == 1 || fit(bytes, dev, stream, false) < 0) break;
     }
-    // a kept block would fit once the work that used it has finished
+    // a kept block would fit once the work that used it has finished: a device
+    // synchronization covers the blocks released before it starts, not those released by
+    // other threads meanwhile
+    uint64_t before;
+    {
+      std::lock_guard<std::mutex> lk(g_mu);
+      before = g_releases;
+    }
     (void)hipDeviceSynchronize();
     std::lock_guard<std::mutex> lk(g_mu);
-    for (Block& b : g_kept) b.idle = true;
+    for (Block& b : g_kept)
+      if (b.epoch <= before) b.idle = true;
   }
   void* p = nullptr;
   if (hipMalloc(&p, bytes) != hipSuccess) {
@@ -112,7 +122,7 @@ void default_release(void* p) {
     std::lock_guard<std::mutex> lk(g_mu);
     auto it = g_out.find(p);
     if (it == g_out.end()) return;
-    g_kept.push_back(Block{p, it->second.bytes, it->second.dev, g_stream, false});
+    g_kept.push_back(Block{p, it->second.bytes, it->second.dev, g_stream, false, ++g_releases});
     g_kept_bytes += it->second.bytes;
     g_out.erase(it);
     while (g_kept_bytes > kKeepMax && !g_kept.empty()) {
@@ -2115,6 +2125,23 @@ extern "C" int mmf_set_params(mmf_handle hh, const float* d_theta, const float* 
   ABI_END
 }
 
+extern "C" int mmf_get_params(mmf_handle hh, float* d_theta, float* d_hdiag, float* d_hcore,
+                              void* stream) {
+  ABI_BEGIN
+  mmf_plan& h = *checked(hh);
+  hipStream_t s = as_stream(stream);
+  if (d_hdiag)
+    HIPCHK(hipMemcpyAsync(d_hdiag, h.hdiag.p, h.n * sizeof(float), hipMemcpyDeviceToDevice, s));
+  if (d_hcore && h.core)
+    HIPCHK(hipMemcpyAsync(d_hcore, h.hcore.p, h.core * h.core * sizeof(float),
+                          hipMemcpyDeviceToDevice, s));
+  if (d_theta && h.R)
+    HIPCHK(hipMemcpyAsync(d_theta, h.theta.p, h.R * (h.k == 3 ? 3 : 1) * sizeof(float),
+                          hipMemcpyDeviceToDevice, s));
+  return MMF_OK;
+  ABI_END
+}
+
 extern "C" int mmf_destroy(mmf_handle hh) {
   ABI_BEGIN
   checked(hh);
@@ -2122,7 +2149,10 @@ extern "C" int mmf_destroy(mmf_handle hh) {
     std::lock_guard<std::mutex> lk(g_live_mu);
     g_live.erase(hh);
   }
-  (void)hipStreamSynchronize(hh->stream);
+  // the handle's buffers may still be read by work on any stream (products run on the caller's
+  // streams), and a released block is reused at once by later work on the stream it is released
+  // with: wait for the whole device before releasing them
+  (void)hipDeviceSynchronize();
   delete hh;
   return MMF_OK;
   ABI_END

@@ -305,6 +305,28 @@ def test_autograd_function_matches_backward():
     assert rel_err(hc.grad.cpu().numpy(), rhc) <= 1e-5
 
 
+def test_autograd_backward_uses_the_parameters_of_its_forward():
+    """Two products with different parameters on one factorization, then the backward of the
+    first: it must use the first forward's parameters, not the ones the handle holds by then."""
+    from paper_1507_04396_amd.api import MMFApply
+    A = workloads.small_grid((10, 10), seed=2)
+    ref = oracle.factor(A, k=2, core=12, cluster=(8, 30), seed=3)
+    fac = _import(ref)
+    theta, hd, hc = fac.params()
+    np.testing.assert_allclose(theta.cpu().numpy(), om.angles(ref), atol=1e-6)
+    theta.requires_grad_(True)
+    x = torch.randn(A.n, 3, device="cuda", requires_grad=True)
+    _say("[adjoint] two forwards, one backward")
+    y = MMFApply.apply(x, theta, hd, hc, fac)
+    MMFApply.apply(x.detach(), theta.detach() + 0.3, hd * 2.0, hc, fac)   # other parameters
+    w = torch.randn_like(y)
+    (y * w).sum().backward()
+    rx, rhd, rhc, rth = oracle.backward(ref, x.detach().cpu().numpy().astype(np.float64),
+                                        w.cpu().numpy().astype(np.float64))
+    assert rel_err(theta.grad.cpu().numpy(), rth) <= 1e-4
+    assert rel_err(x.grad.cpu().numpy(), rx) <= 1e-5
+
+
 # --------------------------------------------------------------------------- errors
 
 def test_factor_reports_input_errors():
@@ -359,6 +381,30 @@ def test_pcg_small_spd_grid_matches_dense_solve():
     assert rel_err(Xn, Xref) <= 1e-6 * cond
 
 
+def test_split_symmetric_pcg_small_spd_grid_matches_dense_solve():
+    """The split-symmetric form of Sec. 4: CG on A~^{-1/2} A A~^{-1/2} y = A~^{-1/2} b, x =
+    A~^{-1/2} y; same solution as the dense solve and the left-preconditioned form."""
+    from paper_1507_04396_amd.api import Factorization
+    A = workloads.small_grid((12, 14, 15), sigma=1.5, shift=1e-2, seed=5)
+    rp, ci, cv = _device_csr(A)
+    _say(f"[pcg-split] factor n={A.n}")
+    fac = Factorization.factor(rp, ci, cv, k=2, eta=0.5, core=64, cluster=(32, 128), seed=0)
+    B = workloads.gaussian_block(A.n, 5, seed=11)
+    Bd = torch.from_numpy(B).cuda()
+    X, info = fac.pcg(rp, ci, cv, Bd, tol=1e-6, max_iter=2000, split=True)
+    X1, info1 = fac.pcg(rp, ci, cv, Bd, tol=1e-6, max_iter=2000)
+    _say(f"[pcg-split] split {info}, left {info1}")
+    assert info["converged"] == 5
+    Ad = A.to_dense()
+    Xn = X.cpu().numpy()
+    res = np.linalg.norm(B.astype(np.float64) - Ad @ Xn, axis=0) / np.linalg.norm(B, axis=0)
+    assert res.max() <= 1e-6, res
+    Xref = np.linalg.solve(Ad, B.astype(np.float64))
+    assert rel_err(Xn, Xref) <= 1e-6 * np.linalg.cond(Ad)
+    # the two forms produce the same iterates in exact arithmetic: similar iteration counts
+    assert abs(info["iterations"] - info1["iterations"]) <= max(5, 0.25 * info1["iterations"])
+
+
 def test_pcg_full_size_grid3d_n1050703():
     """The 101 x 101 x 103 preconditioning workload with 128 right-hand sides."""
     from paper_1507_04396_amd.api import Factorization
@@ -374,6 +420,9 @@ def test_pcg_full_size_grid3d_n1050703():
     X, info = fac.pcg(rp, ci, cv, B, tol=1e-6, max_iter=2000)
     _say(f"[pcg] {info}")
     assert info["converged"] == 128 and info["max_rel_residual"] <= 1e-6
+    Xs, infs = fac.pcg(rp, ci, cv, B[:, :16].contiguous(), tol=1e-6, max_iter=2000, split=True)
+    _say(f"[pcg] split-symmetric form, 16 columns: {infs}")
+    assert infs["converged"] == 16 and infs["max_rel_residual"] <= 1e-6
     # independent FP64 residual check on the host for a few columns
     As = A.to_scipy()
     Xh = X[:, :4].cpu().numpy()
