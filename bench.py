@@ -331,6 +331,23 @@ def main():
                               "factor_ms_median": round(float(np.median(t_ms)), 3),
                               "loss_mean": round(float(np.mean(losses)), 4),
                               "loss_std": round(float(np.std(losses)), 4)}}
+    # ----------------------------------------------------------------- two eliminations per rotation
+    two_elim = None
+    if not args.factor_only and prm["k"] == 3:
+        t_ms = []
+        for _ in range(3):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            f2 = Factorization.factor(rp, ci, cv, elims=2, **prm)
+            torch.cuda.synchronize()
+            t_ms.append(1e3 * (time.perf_counter() - t0))
+            inf2, st2 = f2.info(), f2.stage_info()
+            f2.close()
+        two_elim = {"factor_ms_median": round(float(np.median(t_ms)), 3),
+                    "find_ms": round(sum(st["find_ms"] for st in st2), 3),
+                    "loss": inf2["loss"],
+                    "retired_per_s": round(R / (float(np.median(t_ms)) / 1e3), 1)}
+        log(f"[bench] two eliminations per rotation: {np.round(t_ms, 1)} ms, loss {inf2['loss']:.6g}")
     del rp, ci, cv
 
     # ----------------------------------------------------------------- apply / adjoint
@@ -415,6 +432,7 @@ def main():
         "refine": refine,
         "gram_forms": gram_forms,
         "clustering": clustering,
+        "two_eliminations": two_elim,
         "pcg": pcg,
         "roofline": roofline,
         "cpu_baseline": cpu,

@@ -52,6 +52,13 @@ enum {
                                       separate the fewest entries of the stage's active matrix,
                                       chosen at the start of each stage; excludes
                                       MMF_EVEN_CLUSTERS                                          */
+#define MMF_TWO_ELIMINATIONS 0x8u  /* k = 3 only: each rotation retires its two slots with the
+                                      smallest off-diagonal norms (Sec. 2: a k-point rotation may
+                                      set several wavelets), so a cluster retiring r_u indices
+                                      takes ceil(r_u / 2) rotations; the log keeps one entry per
+                                      retired index, a rotation's second retirement as the next
+                                      entry on the same tuple with the identity block.  FP32 Gram
+                                      form only (MMF_EINVAL with gram_mode 1 or k = 2)          */
 
 /* Factorization parameters (Sec. 2, Alg. 1 and Alg. 2). */
 typedef struct {

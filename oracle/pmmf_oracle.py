@@ -53,6 +53,11 @@ Readings of points the paper leaves open (each is also listed in the design note
       O(w) = expm(w_0 G_01 + w_1 G_02 + w_2 G_12) O0, with O0 the rotation the search found and
       G_pq = E_qp - E_pq the generator of the (p, q) plane in slot order (G_01 extends the Givens
       J = [[0, -1], [1, 0]]); w = 0 at the start.
+  R17 Several eliminations per rotation (optional; Sec. 2 allows more than one wavelet per
+      k-point rotation): a rotation retires its `elims` slots with the smallest off-diagonal
+      norms, smallest first (ties to the later slot), elims <= k - 1; a cluster still retires
+      its r_u indices, so it takes ceil(r_u / elims) rotations, the last one retiring what is
+      left.  Seeds are drawn per rotation (step s of the hash is the rotation's index).
   R16 A data-driven clustering (optional, Alg. 1 "cluster"): clusters stay contiguous chunks of
       the active list, with sizes in [lo, hi], but their boundaries are chosen to cut the fewest
       entries of the active matrix: boundary b (between positions b-1 and b) cuts the entries
@@ -411,8 +416,9 @@ def _as_csr64(A) -> sp.csr_matrix:
 
 
 def _search_cluster(slab, D, gids, r_u, k, seed, p, u, replay=None, on_step=None, ctx=None,
-                    slab_abs=None, D_abs=None):
-    """Algorithm 2 on one cluster: r_u greedy steps on its Gram and diagonal block.
+                    slab_abs=None, D_abs=None, elims=1):
+    """Algorithm 2 on one cluster: greedy steps on its Gram and diagonal block until r_u indices
+    are retired, ``elims`` per rotation (R17; the last step may retire fewer).
 
     ``slab`` is the column slab M[S_{p-1}, B_u] (sparse), ``D`` the diagonal block, ``gids`` the
     global ids of the cluster's columns.  ``replay`` (ids [r_u][k], retired [r_u], O [r_u][k][k]:
@@ -442,7 +448,8 @@ def _search_cluster(slab, D, gids, r_u, k, seed, p, u, replay=None, on_step=None
     Qu = np.eye(c)
     active = np.ones(c, dtype=bool)                      # I = [c]
     rots, retired, hd, literal = [], [], [], []
-    for s in range(r_u):
+    ent, s = 0, 0                                        # log entries (one per retiree), steps
+    while ent < r_u:
         live = np.flatnonzero(active)
         i = int(live[mulhi(chain_hash(seed, TAG_SEED_ROW, p, u, s), live.size)])
         kk = k if live.size >= k else 2
@@ -461,11 +468,11 @@ def _search_cluster(slab, D, gids, r_u, k, seed, p, u, replay=None, on_step=None
         score_err = np.array([err(j) for j in order[:kk]])
         m_part, tie_part = partner_decision(score[order[:kk]], kk, score_err)
         adopted = []
-        rp_s = replay is not None and bool(replay["use"][s])
+        rp_s = replay is not None and bool(replay["use"][ent])
         if rp_s:
-            g_ids = np.minimum(np.searchsorted(gids, replay["ids"][s][:kk]), c - 1)
+            g_ids = np.minimum(np.searchsorted(gids, replay["ids"][ent][:kk]), c - 1)
             g_T = [int(x) for x in g_ids]
-            if not np.array_equal(gids[g_ids], replay["ids"][s][:kk]):
+            if not np.array_equal(gids[g_ids], replay["ids"][ent][:kk]):
                 adopted.append(("partners", False, m_part))   # not a tuple of this cluster
             elif g_T != T:
                 # the other log's tuple is correct if its seed is this seed and each of its
@@ -485,7 +492,7 @@ def _search_cluster(slab, D, gids, r_u, k, seed, p, u, replay=None, on_step=None
         O = rotation_k2(gTT)[0] if kk == 2 else rotation_k3(gTT)[0]
         m_rot, tie_rot, eig_gap, vec_err = rotation_decision(gTT, ErrG[np.ix_(T, T)])
         if rp_s:
-            g_O = np.asarray(replay["O"][s][:kk, :kk], dtype=np.float64)
+            g_O = np.asarray(replay["O"][ent][:kk, :kk], dtype=np.float64)
             alt = O
             if np.abs(O - g_O).max() > 1e-3:
                 if kk == 2:
@@ -512,35 +519,56 @@ def _search_cluster(slab, D, gids, r_u, k, seed, p, u, replay=None, on_step=None
                          + (kk + 1) * U32 * (Xa @ Oabs.T) + TINY32)
             X[:, T] = X[:, T] @ O.T
         Qu[T, :] = O @ Qu[T, :]
-        # eliminate the slot with the smallest off-diagonal norm, ties to the later (R5)
+        # eliminate the slot with the smallest off-diagonal norm, ties to the later (R5); with
+        # several eliminations per rotation (R17) the next smallest of the remaining slots, and so
+        # on, each logged as its own entry on T (the later ones with the identity block)
         off2 = [max(0.0, G[tt, tt] - D[tt, tt] ** 2) for tt in T]
-        e_slot = 0
-        for sl in range(1, kk):
-            if off2[sl] <= off2[e_slot]:
-                e_slot = sl
         off2_err = [ErrG[tt, tt] + 2.0 * abs(D[tt, tt]) * ErrD[tt, tt] for tt in T]
-        m_elim, tie_elim = elimination_decision(off2, off2_err)
-        if rp_s:
-            g_e = int(np.searchsorted(gids, replay["retired"][s]))
-            if g_e != T[e_slot] and g_e in T:
-                adopted.append(("elimination", tie_elim, m_elim))
-                e_slot = T.index(g_e)
-            elif g_e != T[e_slot]:
-                adopted.append(("elimination", False, m_elim))
-        e = T[e_slot]
-        active[e] = False
-        retired.append(e)
-        hd.append(float(D[e, e]))
-        literal.append(2.0 * off2[e_slot])
-        rots.append(Rotation(stage=p, cluster=u, step=s, ids=gids[np.asarray(T)].copy(),
-                             O=O.copy(), retired=int(gids[e]), seed_pos=i,
-                             margin=float(min(m_part, m_rot, m_elim)),
-                             margins=(m_part, m_rot, m_elim), eig_gap=eig_gap, o_err=vec_err,
-                             near_ties=(tie_part, tie_rot, tie_elim), adopted=tuple(adopted)))
+        left = list(range(kk))
+        first_e = None
+        for q in range(min(elims, kk - 1, r_u - ent)):
+            e_slot = left[0]
+            for sl in left[1:]:
+                if off2[sl] <= off2[e_slot]:
+                    e_slot = sl
+            m_elim, tie_elim = elimination_decision([off2[sl] for sl in left],
+                                                    [off2_err[sl] for sl in left])
+            adopted_e = list(adopted) if q == 0 else []
+            if replay is not None and bool(replay["use"][ent]):
+                g_e = int(np.searchsorted(gids, replay["retired"][ent]))
+                if q > 0 and not np.array_equal(replay["ids"][ent][:kk], gids[np.asarray(T)]):
+                    adopted_e.append(("partners", False, math.inf))  # not this step's tuple
+                if g_e != T[e_slot] and g_e in [T[sl] for sl in left]:
+                    adopted_e.append(("elimination", tie_elim, m_elim))
+                    e_slot = T.index(g_e)
+                elif g_e != T[e_slot]:
+                    adopted_e.append(("elimination", False, m_elim))
+            left.remove(e_slot)
+            e = T[e_slot]
+            first_e = e if first_e is None else first_e
+            active[e] = False
+            retired.append(e)
+            hd.append(float(D[e, e]))
+            literal.append(2.0 * off2[e_slot])
+            if q == 0:
+                rots.append(Rotation(stage=p, cluster=u, step=s, ids=gids[np.asarray(T)].copy(),
+                                     O=O.copy(), retired=int(gids[e]), seed_pos=i,
+                                     margin=float(min(m_part, m_rot, m_elim)),
+                                     margins=(m_part, m_rot, m_elim), eig_gap=eig_gap,
+                                     o_err=vec_err, near_ties=(tie_part, tie_rot, tie_elim),
+                                     adopted=tuple(adopted_e)))
+            else:
+                rots.append(Rotation(stage=p, cluster=u, step=s, ids=gids[np.asarray(T)].copy(),
+                                     O=np.eye(kk), retired=int(gids[e]), seed_pos=i,
+                                     margin=float(m_elim), margins=(math.inf, math.inf, m_elim),
+                                     near_ties=(False, False, tie_elim),
+                                     adopted=tuple(adopted_e)))
+            ent += 1
         if on_step is not None:
-            on_step(dict(stage=p, cluster=u, step=s, G=G, D=D, T=list(T), O=O, e=e,
+            on_step(dict(stage=p, cluster=u, step=s, G=G, D=D, T=list(T), O=O, e=first_e,
                          active=active.copy(), ranked=[int(j) for j in order[:kk]],
                          score_err=score_err, off2_err=off2_err, **(ctx or {})))
+        s += 1
     Qs = sp.csr_matrix(Qu)
     Qs.eliminate_zeros()
     return dict(rots=rots, Q=Qs, retired=retired, hd=hd, literal=literal)
@@ -579,7 +607,8 @@ def _cluster_task(u: int):
                            st["M"][off:off + c, off:off + c],  # [[A]]_{u,u}
                            st["S"][off:off + c].copy(), st["r_u"][u], st["k"], st["seed"],
                            st["p"], u, rp, st["on_step"], ctx,
-                           st["Mabs_c"][:, off:off + c], st["Mabs"][off:off + c, off:off + c])
+                           st["Mabs_c"][:, off:off + c], st["Mabs"][off:off + c, off:off + c],
+                           st["elims"])
 
 
 def _rotate_rows_task(u: int):
@@ -612,7 +641,7 @@ def _rotate_rows_task(u: int):
 def factor(A, k: int = 2, eta: float = 0.5, core: int = 64, cluster=(0, 0), seed: int = 0,
            even_clusters: bool = False, cut_clusters: bool = False,
            on_step: Optional[Callable[[dict], None]] = None, replay: Optional[dict] = None,
-           workers: int = 1) -> Factorization:
+           workers: int = 1, elims: int = 1) -> Factorization:
     """pMMF factorization A ~ U^T H U (Eq. 1 / Eq. 4) by Algorithm 1 with Algorithm 2 inside.
 
     ``A`` is symmetric (a CSR from ``workloads``, a SciPy sparse matrix or a dense array).
@@ -625,9 +654,14 @@ def factor(A, k: int = 2, eta: float = 0.5, core: int = 64, cluster=(0, 0), seed
     ``workers`` > 1 runs the clusters of a stage (their searches, and their block rows of the
     two-sided rotation) in that many forked processes: clusters are independent (Sec. 2.3), and
     the result does not depend on it.
+    ``elims`` (R17): indices retired per rotation, 1 <= elims <= k - 1.  The log keeps one entry
+    per retired index: a rotation's later eliminations follow it as entries on the same tuple with
+    the identity block.
     """
     if k not in (2, 3):
         raise ValueError("k must be 2 or 3")
+    if not (1 <= elims <= k - 1):
+        raise ValueError("elims must lie in [1, k - 1]")
     M = _as_csr64(A)
     n = M.shape[0]
     if (abs(M - M.T) > 0).nnz:
@@ -659,7 +693,7 @@ def factor(A, k: int = 2, eta: float = 0.5, core: int = 64, cluster=(0, 0), seed
         fro_start = math.sqrt((M.data ** 2).sum())
         _STAGE.clear()
         _STAGE.update(M=M, Mc=M.tocsc(), Mabs=Mabs, Mabs_c=Mabs.tocsc(), S=S, offsets=offsets,
-                      sizes=sizes, r_u=r_u, k=k,
+                      sizes=sizes, r_u=r_u, k=k, elims=elims,
                       seed=seed, p=p, replay=replay, r_base=len(rotations), on_step=on_step)
         results = _stage_map(_cluster_task, list(range(len(sizes))), workers)
         retired_pos = []                # compact positions retired in this stage, in order

@@ -15,6 +15,7 @@ ERRORS = {
 MMF_CHECK_SYMMETRY = 0x1
 MMF_EVEN_CLUSTERS = 0x2
 MMF_CUT_CLUSTERS = 0x4
+MMF_TWO_ELIMINATIONS = 0x8
 
 
 class MMFError(RuntimeError):

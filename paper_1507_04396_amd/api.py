@@ -80,11 +80,12 @@ class Factorization:
     def factor(cls, rowptr: torch.Tensor, colind: torch.Tensor, val: torch.Tensor, *, k: int = 2,
                eta: float = 0.5, core: int = 64, cluster=(0, 0), seed: int = 0,
                check_symmetry: bool = False, even_clusters: bool = False, gram_mode: int = 0,
-               cut_clusters: bool = False, stream=None) -> "Factorization":
+               cut_clusters: bool = False, elims: int = 1, stream=None) -> "Factorization":
         """mmf_factor on a device CSR (int64 rowptr, int32 colind, float32 val).
 
         ``cut_clusters`` chooses each stage's cluster boundaries to separate the fewest entries of
-        the active matrix (MMF_CUT_CLUSTERS) instead of the seeded sizes."""
+        the active matrix (MMF_CUT_CLUSTERS) instead of the seeded sizes; ``elims=2`` retires two
+        indices per 3-point rotation (MMF_TWO_ELIMINATIONS)."""
         lib = _lib.load()
         _require_device(rowptr, torch.int64, "rowptr")
         _require_device(colind, torch.int32, "colind")
@@ -94,7 +95,10 @@ class Factorization:
                               cluster_max=cluster[1], seed=seed, gram_mode=gram_mode,
                               flags=(_lib.MMF_CHECK_SYMMETRY if check_symmetry else 0)
                               | (_lib.MMF_EVEN_CLUSTERS if even_clusters else 0)
-                              | (_lib.MMF_CUT_CLUSTERS if cut_clusters else 0))
+                              | (_lib.MMF_CUT_CLUSTERS if cut_clusters else 0)
+                              | (_lib.MMF_TWO_ELIMINATIONS if elims == 2 else 0))
+        if elims not in (1, 2):
+            raise ValueError("elims must be 1 or 2")
         h = ctypes.c_void_p()
         check(lib.mmf_factor(n, val.numel(), _ptr(rowptr), _ptr(colind), _ptr(val),
                              ctypes.byref(prm), _stream(stream), ctypes.byref(h)))

@@ -12,10 +12,11 @@ namespace pmmf {
 struct FindArgs {
   int p;                     // stage number, 1-based (enters the seed-row hash)
   int k;                     // 2 or 3
+  int elims = 1;             // indices retired per rotation (2 only with k = 3)
   uint64_t seed;
   const int32_t* order;      // launch slot -> cluster id (largest clusters first)
   const int32_t* off;        // [m+1] cluster offsets (positions)
-  const int32_t* rcnt;       // [m] rotations of each cluster
+  const int32_t* rcnt;       // [m] log entries (retired indices) of each cluster
   const int32_t* roff;       // [m+1] first stage-local rotation of each cluster
   const int64_t* gbase;      // [m] offset of each cluster's c x c blocks in the pools
   float2* GD;                // (Gram, diagonal block) pool, interleaved

@@ -877,9 +877,10 @@ __device__ inline void rot3_polished(const double (&g)[3][3], double (&O)[3][3],
 
 // ------------------------------------------------------------------------------------------
 // Randomized greedy rotation search inside one cluster (Alg. 2), one workgroup per cluster.
-// rank-th, (rank+1)-th and (rank+2)-th set bits of the active bitmask in LDS (-1 where absent);
-// called by one whole wave
-__device__ inline void select_active3(const uint32_t* mask, int nw, int rank, int (&out)[3]) {
+// rank-th, ..., (rank+N-1)-th set bits of the active bitmask in LDS (-1 where absent); called by
+// one whole wave
+template <int N>
+__device__ inline void select_activeN(const uint32_t* mask, int nw, int rank, int (&out)[N]) {
   const int lane = pmmf_lane();
   const int wpl = (nw + PMMF_WAVE - 1) / PMMF_WAVE;
   const int w0 = lane * wpl;
@@ -890,20 +891,22 @@ __device__ inline void select_active3(const uint32_t* mask, int nw, int rank, in
   }
   const int incl = pmmf_wave_incl_scan_dpp(cnt);
   int base = incl - cnt;
-  int f[3] = {-1, -1, -1};
+  int f[N];
+#pragma unroll
+  for (int d = 0; d < N; ++d) f[d] = -1;
   for (int t = 0; t < wpl; ++t) {
     const int wi = w0 + t;
     const uint32_t m = wi < nw ? mask[wi] : 0u;
     const int pc = __popc(m);
 #pragma unroll
-    for (int d = 0; d < 3; ++d) {
+    for (int d = 0; d < N; ++d) {
       const int want = rank + d - base;
       if (want >= 0 && want < pc) f[d] = wi * 32 + pmmf_nth_bit(m, want);
     }
     base += pc;
   }
 #pragma unroll
-  for (int d = 0; d < 3; ++d) {
+  for (int d = 0; d < N; ++d) {
     const uint64_t bb = __ballot(f[d] >= 0);
     out[d] = bb ? __shfl(f[d], __ffsll((unsigned long long)bb) - 1) : -1;
   }
@@ -1046,9 +1049,13 @@ __device__ inline float2 rot_entry(const float* o, int a, const float2* v) {
 // stores before the partner rows are read.  The retirement is applied to the active mask one
 // step late (the scoring also skips the previous retiree explicitly), so wave 1 can read a mask
 // that nobody writes during the serial section.
-template <int NT, int PER, int K>
+// E = indices retired per rotation (1, or 2 with k = 3): a step's rotation retires its E slots with
+// the smallest off-diagonal norms and writes E log entries, the later ones on the same tuple with
+// the identity block.
+template <int NT, int PER, int K, int E>
 __global__ void __launch_bounds__(NT) k_find(FindArgs A, int cmax) {
   static_assert(NT >= 2 * PMMF_WAVE, "wave 1 selects the next seed");
+  static_assert(E == 1 || (E == 2 && K == 3), "two eliminations need a 3-point rotation");
   extern __shared__ float lds_f[];
   float* gdiag = lds_f;
   float* ddiag = gdiag + cmax;
@@ -1058,14 +1065,15 @@ __global__ void __launch_bounds__(NT) k_find(FindArgs A, int cmax) {
   float* gsq = reinterpret_cast<float*>(mask + (cmax + 31) / 32);  // sqrt(G_jj), for the scores
   constexpr int NW = NT / PMMF_WAVE;
   __shared__ Cand red1[NW], red2[NW];
-  __shared__ int sh_i, sh_e, sh_c0, sh_c1, sh_k[3];
+  __shared__ int sh_i, sh_e, sh_e2, sh_c[E + 1], sh_k[2 * E + 1];
   __shared__ float sh_O[9], sh_gn[9], sh_dn[9];
 
   const int tid = threadIdx.x;
   const int u = A.order[blockIdx.x];
   const int o = A.off[u];
   const int c = A.off[u + 1] - o;
-  const int r = A.rcnt[u];
+  const int nent = A.rcnt[u];                 // log entries: indices the cluster retires
+  const int r = (nent + E - 1) / E;           // rotations (steps)
   const int rb = A.roff[u];
   const int nw = (c + 31) / 32;
   constexpr int kk = K;
@@ -1089,17 +1097,19 @@ __global__ void __launch_bounds__(NT) k_find(FindArgs A, int cmax) {
     const uint64_t h = pmmf_hash4(A.seed, PMMF_TAG_SEED_ROW, (uint64_t)A.p, (uint64_t)u, 0);
     const int i0 = select_active(mask, nw, (int)pmmf_mulhi(h, (uint64_t)c));
     if (tid == 0) sh_i = i0;
-    if (r > 1) {  // the two candidates for the second seed (see the next-seed rule below)
+    if (r > 1) {  // the E + 1 candidates for the second seed (see the next-seed rule below)
       const uint64_t h1 = pmmf_hash4(A.seed, PMMF_TAG_SEED_ROW, (uint64_t)A.p, (uint64_t)u, 1);
-      const int rank1 = (int)pmmf_mulhi(h1, (uint64_t)(c - 1));
-      const int c0 = select_active(mask, nw, rank1);
-      const int c1 = select_active(mask, nw, rank1 + 1);
-      if (tid == 0) { sh_c0 = c0; sh_c1 = c1; }
+      const int rank1 = (int)pmmf_mulhi(h1, (uint64_t)(c - E));
+      int cs[E + 1];
+      select_activeN<E + 1>(mask, nw, rank1, cs);
+      if (tid == 0)
+#pragma unroll
+        for (int d = 0; d <= E; ++d) sh_c[d] = cs[d];
     }
   }
   __syncthreads();
   int i = r > 0 ? sh_i : 0;
-  int e_prev = -1;
+  int e_prev = -1, e_prev2 = -1;
   // column stores of the previous step, issued during this step's rotation (see below): their
   // values, which of them are real, the T they belong to and that step's retiree, whose column
   // is dead and takes the lanes with nothing to store
@@ -1107,8 +1117,10 @@ __global__ void __launch_bounds__(NT) k_find(FindArgs A, int cmax) {
   uint64_t cmask = 0;
   int tq0 = -1, tq1 = -1, tq2 = -1, edead = -1;
   int jl[PER];  // this thread's columns, clamped into the cluster for address forming
-  // candidates for the next seed (their rows are loaded during this step's rotation)
-  int cc0 = r > 1 ? sh_c0 : 0, cc1 = r > 1 ? sh_c1 : 0;
+  // candidates for the next seed (k = 2: their rows are loaded during this step's rotation)
+  int cc[E + 1];
+#pragma unroll
+  for (int d = 0; d <= E; ++d) cc[d] = r > 1 ? sh_c[d] : 0;
   float2 c0r[PER], c1r[PER];
   float2 cur[PER];
 #pragma unroll
@@ -1133,7 +1145,7 @@ __global__ void __launch_bounds__(NT) k_find(FindArgs A, int cmax) {
       const int j = tid + q * NT;
       if (j < c) {
         R0s[j] = cur[q];
-        const bool act = ((mask[j >> 5] >> (j & 31)) & 1u) && j != e_prev;
+        const bool act = ((mask[j >> 5] >> (j & 31)) & 1u) && j != e_prev && j != e_prev2;
         if (act && j != i) {
           const float gq = gsq[j];  // > 0 exactly when G_jj > 0
           float sc = gq > 0.f ? fabsf(cur[q].x) / gq : 0.f;
@@ -1208,14 +1220,14 @@ __global__ void __launch_bounds__(NT) k_find(FindArgs A, int cmax) {
     // (k = 2 only: with k = 3 the extra loads delay the lane-0 entries more than the prefetch
     // saves after barrier B)
     if constexpr (K == 2) {
-      const int sc0 = slot_of(cc0, tq0, tq1, tq2), sc1 = slot_of(cc1, tq0, tq1, tq2);
+      const int sc0 = slot_of(cc[0], tq0, tq1, tq2), sc1 = slot_of(cc[1], tq0, tq1, tq2);
 #pragma unroll
       for (int q = 0; q < PER; ++q) {
         const int j = tid + q * NT;
         const int sj = slot_of(j, tq0, tq1, tq2);
         const uint32_t jq = (uint32_t)jl[q];
-        c0r[q] = GD[(sj >= 0 && sc0 < 0) ? (uint32_t)(j * c + cc0) : (uint32_t)(cc0 * c) + jq];
-        c1r[q] = GD[(sj >= 0 && sc1 < 0) ? (uint32_t)(j * c + cc1) : (uint32_t)(cc1 * c) + jq];
+        c0r[q] = GD[(sj >= 0 && sc0 < 0) ? (uint32_t)(j * c + cc[0]) : (uint32_t)(cc[0] * c) + jq];
+        c1r[q] = GD[(sj >= 0 && sc1 < 0) ? (uint32_t)(j * c + cc[1]) : (uint32_t)(cc[1] * c) + jq];
       }
     }
 
@@ -1288,6 +1300,15 @@ __global__ void __launch_bounds__(NT) k_find(FindArgs A, int cmax) {
       const int e = es == 0 ? t0 : (es == 1 ? t1 : t2);
       const double dee = es == 0 ? dn[0][0] : (es == 1 ? dn[1][1] : dn[2][2]);
       const double off2e = fmin_;
+      // second elimination (E = 2): the smaller of the two remaining slots, ties to the later
+      const int sa = es == 0 ? 1 : 0, sb = es == 2 ? 1 : 2;
+      const double fa = sa == 0 ? f0 : f1v, fb = sb == 1 ? f1v : f2v;
+      const int es2 = fb <= fa ? sb : sa;
+      const int e2 = es2 == 0 ? t0 : (es2 == 1 ? t1 : t2);
+      const double dee2 = es2 == 0 ? dn[0][0] : (es2 == 1 ? dn[1][1] : dn[2][2]);
+      const double off2e2 = fmin(fa, fb);
+      const double margin2 = fmax(fa, fb) > 0.0 ? fabs(fb - fa) / fmax(fa, fb) : 0.0;
+      const bool second = E == 2 && E * s + 1 < nent;
       gdiag[t0] = (float)gn[0][0];
       ddiag[t0] = (float)dn[0][0];
       gdiag[t1] = (float)gn[1][1];
@@ -1300,6 +1321,7 @@ __global__ void __launch_bounds__(NT) k_find(FindArgs A, int cmax) {
         gsq[t2] = sqrtf((float)gn[2][2]);
       }
       sh_e = e;
+      sh_e2 = second ? e2 : -1;
 #pragma unroll
       for (int a = 0; a < 9; ++a) { sh_O[a] = 0.f; sh_gn[a] = 0.f; sh_dn[a] = 0.f; }
 #pragma unroll
@@ -1311,7 +1333,7 @@ __global__ void __launch_bounds__(NT) k_find(FindArgs A, int cmax) {
           sh_dn[a * 3 + b] = (float)dn[a][b];
         }
       // rotation log (stores only: nothing on this lane waits for them)
-      const int64_t ridx = A.rot0 + rb + s;
+      const int64_t ridx = A.rot0 + rb + (int64_t)E * s;
       A.rot_loc[ridx * 3 + 0] = t0;
       A.rot_loc[ridx * 3 + 1] = t1;
       A.rot_loc[ridx * 3 + 2] = kk == 3 ? t2 : -1;
@@ -1325,17 +1347,35 @@ __global__ void __launch_bounds__(NT) k_find(FindArgs A, int cmax) {
       A.rot_lit[ridx] = 2.0 * off2e;
       A.hdiag[lgid[e]] = (float)dee;
       A.retflag[o + e] = 1;
+      if (second) {  // the same tuple with the identity block, retiring e2
+        const int64_t r2 = ridx + 1;
+        A.rot_loc[r2 * 3 + 0] = t0;
+        A.rot_loc[r2 * 3 + 1] = t1;
+        A.rot_loc[r2 * 3 + 2] = t2;
+        A.rot_gid[r2 * 3 + 0] = lgid[t0];
+        A.rot_gid[r2 * 3 + 1] = lgid[t1];
+        A.rot_gid[r2 * 3 + 2] = lgid[t2];
+#pragma unroll
+        for (int a = 0; a < 9; ++a) A.rot_o[r2 * 9 + a] = (a % 4 == 0) ? 1.f : 0.f;
+        A.rot_ret[r2] = lgid[e2];
+        A.rot_margin[r2] = (float)margin2;
+        A.rot_lit[r2] = 2.0 * off2e2;
+        A.hdiag[lgid[e2]] = (float)dee2;
+        A.retflag[o + e2] = 1;
+      }
     }
     if (tid >= PMMF_WAVE && tid < 2 * PMMF_WAVE && s + 2 < r) {
       // next-seed rule: the rank-th active index after a retirement e is the rank-th one before
       // it if that lies below e, else the (rank + 1)-th.  The seed of step s+2 is picked after
-      // two more retirements (e_s, e_{s+1}), so the (rank + m)-th indices, m < 3, are taken now;
-      // after this step the two candidates for it follow, after the next step the seed.
+      // 2E more retirements (steps s and s+1), so the (rank + m)-th indices, m <= 2E, are taken
+      // now; after this step E + 1 candidates for it remain, after the next step the seed.
       const uint64_t h = pmmf_hash4(A.seed, PMMF_TAG_SEED_ROW, (uint64_t)A.p, (uint64_t)u,
                                     (uint64_t)(s + 2));
-      int k3[3];
-      select_active3(mask, nw, (int)pmmf_mulhi(h, (uint64_t)(c - s - 2)), k3);
-      if (tid == PMMF_WAVE) { sh_k[0] = k3[0]; sh_k[1] = k3[1]; sh_k[2] = k3[2]; }
+      int kn[2 * E + 1];
+      select_activeN<2 * E + 1>(mask, nw, (int)pmmf_mulhi(h, (uint64_t)(c - E * (s + 2))), kn);
+      if (tid == PMMF_WAVE)
+#pragma unroll
+        for (int d = 0; d <= 2 * E; ++d) sh_k[d] = kn[d];
     }
     // pre-rotation partner rows, for re-forming the next seed row's entries at T
 #pragma unroll
@@ -1353,8 +1393,16 @@ __global__ void __launch_bounds__(NT) k_find(FindArgs A, int cmax) {
 #pragma unroll
     for (int a = 0; a < 9; ++a) o_[a] = sh_O[a];
     const int e = sh_e;
+    const int e2 = E == 2 ? sh_e2 : -1;
     const bool more = s + 1 < r;
-    const int nxt = more ? (cc0 < e ? cc0 : cc1) : -1;
+    // the next seed: the candidates with this step's retirements removed in turn
+    int nxt = -1;
+    if (E == 1) {
+      nxt = more ? (cc[0] < e ? cc[0] : cc[1]) : -1;
+    } else if (more) {
+      const int m0 = cc[0] < e ? cc[0] : cc[1], m1 = cc[1] < e ? cc[1] : cc[E];
+      nxt = m0 < e2 ? m0 : m1;
+    }
     const int aslot = nxt == t0 ? 0 : (nxt == t1 ? 1 : ((kk == 3 && nxt == t2) ? 2 : -1));
     const int Tt[3] = {t0, t1, t2};
     if (tid < kk * kk) {
@@ -1364,16 +1412,24 @@ __global__ void __launch_bounds__(NT) k_find(FindArgs A, int cmax) {
     float2 nrow[PER];
     if constexpr (K == 2) {
 #pragma unroll
-      for (int q = 0; q < PER; ++q) nrow[q] = nxt == cc0 ? c0r[q] : c1r[q];
+      for (int q = 0; q < PER; ++q) nrow[q] = nxt == cc[0] ? c0r[q] : c1r[q];
     } else {
       const uint32_t nb = (uint32_t)((more && aslot < 0 ? nxt : 0) * c);
 #pragma unroll
       for (int q = 0; q < PER; ++q) nrow[q] = GD[nb + (uint32_t)jl[q]];
     }
     if (s + 2 < r) {  // candidates for the seed of step s+2
-      const int k0 = sh_k[0], k1 = sh_k[1], k2 = sh_k[2];
-      cc0 = k0 < e ? k0 : k1;
-      cc1 = k1 < e ? k1 : k2;
+      int kn[2 * E + 1];
+#pragma unroll
+      for (int d = 0; d <= 2 * E; ++d) kn[d] = sh_k[d];
+#pragma unroll
+      for (int d = 0; d < 2 * E; ++d) kn[d] = kn[d] < e ? kn[d] : kn[d + 1];
+      if (E == 2) {
+#pragma unroll
+        for (int d = 0; d < E + 1; ++d) kn[d] = kn[d] < e2 ? kn[d] : kn[d + 1];
+      }
+#pragma unroll
+      for (int d = 0; d <= E; ++d) cc[d] = kn[d];
     }
     // pre-rotation values of rows T at column nxt (used when nxt is not in T)
     float2 vn[3] = {make_float2(0.f, 0.f), make_float2(0.f, 0.f), make_float2(0.f, 0.f)};
@@ -1382,7 +1438,10 @@ __global__ void __launch_bounds__(NT) k_find(FindArgs A, int cmax) {
       vn[1] = R1[nxt];
       if (kk == 3) vn[2] = R2[nxt];
     }
-    if (tid == 0) mask[e >> 5] &= ~(1u << (e & 31));
+    if (tid == 0) {
+      mask[e >> 5] &= ~(1u << (e & 31));
+      if (E == 2 && e2 >= 0) mask[e2 >> 5] &= ~(1u << (e2 & 31));
+    }
 
     // stores: GD <- O GD O^T on rows T now (the k x k block above; a column in T or beyond the
     // cluster writes into the dead column of this step's retiree, and a retired column's entry
@@ -1422,27 +1481,29 @@ __global__ void __launch_bounds__(NT) k_find(FindArgs A, int cmax) {
 #pragma unroll
     for (int q = 0; q < PER; ++q) cur[q] = nrow[q];
     e_prev = e;
+    e_prev2 = e2;
     i = nxt;
     if (more) score_seed(s + 1);
   }
 }
 
-template <int NT, int PER, int K>
+template <int NT, int PER, int K, int E>
 static hipError_t find_launch(const FindArgs& a, int m, int cmax, size_t lds0, hipStream_t s) {
   const size_t lds = lds0 + (size_t)cmax * sizeof(float);  // + sqrt(G_jj)
   if (lds > 64 * 1024) {
-    hipError_t e = hipFuncSetAttribute((const void*)&k_find<NT, PER, K>,
+    hipError_t e = hipFuncSetAttribute((const void*)&k_find<NT, PER, K, E>,
                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess) return e;
   }
-  k_find<NT, PER, K><<<m, NT, lds, s>>>(a, cmax);
+  k_find<NT, PER, K, E><<<m, NT, lds, s>>>(a, cmax);
   return hipGetLastError();
 }
 
 template <int NT, int PER>
 static hipError_t find_launch_k(const FindArgs& a, int m, int cmax, size_t lds, hipStream_t s) {
-  return a.k == 3 ? find_launch<NT, PER, 3>(a, m, cmax, lds, s)
-                  : find_launch<NT, PER, 2>(a, m, cmax, lds, s);
+  if (a.k != 3) return find_launch<NT, PER, 2, 1>(a, m, cmax, lds, s);
+  return a.elims == 2 ? find_launch<NT, PER, 3, 2>(a, m, cmax, lds, s)
+                      : find_launch<NT, PER, 3, 1>(a, m, cmax, lds, s);
 }
 
 // ------------------------------------------------------------------------------------------

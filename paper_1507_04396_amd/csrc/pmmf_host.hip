@@ -335,6 +335,7 @@ struct SweepCfg {
 
 struct mmf_plan {
   int64_t n = 0, core = 0, R = 0;
+  int elims = 1;  // indices retired per rotation (MMF_TWO_ELIMINATIONS: 2)
   int k = 2;
   mmf_params prm{};
   std::vector<std::unique_ptr<StageDev>> st;
@@ -479,6 +480,8 @@ void validate(int64_t n, const mmf_params* p) {
     raise(MMF_EINVAL, "cluster bounds need cluster_min >= 2 and cluster_max >= 2 cluster_min");
   if (p->gram_mode != 0 && p->gram_mode != 1)
     raise(MMF_EINVAL, "gram_mode must be 0 (FP32 Gram) or 1 (BF16 Gram, FP32 rescoring)");
+  if ((p->flags & MMF_TWO_ELIMINATIONS) && (p->k != 3 || p->gram_mode != 0))
+    raise(MMF_EINVAL, "MMF_TWO_ELIMINATIONS needs k = 3 and the FP32 Gram form");
 }
 
 // sparse matrix in CSR
@@ -797,6 +800,7 @@ extern "C" int mmf_factor(int64_t n, int64_t nnz, const int64_t* d_rowptr, const
   h->core = p->core_size;
   h->k = p->k;
   h->prm = *p;
+  h->elims = (p->flags & MMF_TWO_ELIMINATIONS) ? 2 : 1;
   h->stream = s;
   h->R = n - p->core_size;
   std::vector<SchedStage> sched = make_schedule(*p, n);
@@ -998,6 +1002,7 @@ extern "C" int mmf_factor(int64_t n, int64_t nnz, const int64_t* d_rowptr, const
     pmmf::FindArgs fa;
     fa.p = (int)pi + 1;
     fa.k = h->k;
+    fa.elims = (p->flags & MMF_TWO_ELIMINATIONS) ? 2 : 1;
     fa.seed = p->seed;
     fa.order = sd.order.as<int32_t>();
     fa.off = sd.off.as<int32_t>();
@@ -1889,7 +1894,8 @@ extern "C" int mmf_get_stage_info(mmf_handle hh, int32_t stage, mmf_stage_info* 
   out->find_bytes = 0;
   for (int u = 0; u < sd.m; ++u) {
     const int64_t c = sd.off_h[u + 1] - sd.off_h[u];
-    out->find_bytes += (int64_t)sd.rcnt_h[u] * 4 * c * (1 + 8 * h.k);
+    const int64_t steps = (sd.rcnt_h[u] + h.elims - 1) / h.elims;
+    out->find_bytes += steps * 4 * c * (1 + 8 * h.k);
   }
   out->gram_flops = sd.gram_flops;
   out->gram_useful_flops = sd.gram_useful_flops;

@@ -66,6 +66,29 @@ def test_factor_matches_oracle_small(name, make, params):
     _check_factor(A, dict(params), fac, name)
 
 
+TWO_ELIM = [
+    ("knn2d_n700_k3_clusters_2elim", lambda: workloads.knn_points_matrix(700, 2, 8, 0.01, 4),
+     dict(k=3, eta=0.5, core=50, cluster=(40, 120), seed=1, elims=2)),
+    ("knn3d_n1500_single_2elim", lambda: workloads.knn_points_matrix(1500, 3, 10, 0.01, 2),
+     dict(k=3, eta=0.5, core=64, cluster=(0, 0), seed=0, elims=2)),
+    ("grid20x25_k3_odd_2elim", lambda: workloads.small_grid((20, 25), seed=8),
+     dict(k=3, eta=0.3, core=21, cluster=(24, 80), seed=6, elims=2)),
+]
+
+
+@pytest.mark.parametrize("name,make,params", TWO_ELIM, ids=[c[0] for c in TWO_ELIM])
+def test_two_eliminations_per_rotation_match_oracle(name, make, params):
+    """Each 3-point rotation retires its two slots with the smallest off-diagonal norms
+    (MMF_TWO_ELIMINATIONS); the log's second entry of a rotation is the identity on its tuple."""
+    A = make()
+    fac = _factor_gpu(A, dict(params), name)
+    ex = fac.export()
+    ident = np.all(np.abs(ex["rot_o"] - np.eye(3, dtype=np.float32)[None]) == 0, axis=(1, 2))
+    _say(f"[parity] {name}: {int(ident.sum())} second retirements of {len(ident)} entries")
+    assert ident.sum() >= len(ident) // 2 - len(fac.stage_info()) * 64
+    _check_factor(A, dict(params), fac, name)
+
+
 def test_plain_mmf_knn2d_n512_matches_every_decision():
     """The plain-MMF workload (one cluster per stage, Givens rotations) has no near-tie: every
     decision must equal the oracle's, with nothing taken from the GPU."""

@@ -341,3 +341,85 @@ def test_greedy_step_against_exhaustive_pair_search(seed):
     assert greedy_sum[0] == pytest.approx(fac.loss_literal, rel=1e-10, abs=1e-12)
     print(f"greedy / exhaustive increment: median {np.median(ratios):.3f}, max {max(ratios):.3f}")
     assert min(ratios) >= 1.0 - 1e-9
+
+
+# --------------------------------------------------------------------------- several eliminations
+
+def _dense_U(fac):
+    U = np.eye(fac.n)
+    for r in fac.rotations:
+        Q = np.eye(fac.n)
+        Q[np.ix_(r.ids, r.ids)] = r.O
+        U = Q @ U
+    return U
+
+
+@pytest.mark.parametrize("cluster", [(0, 0), (12, 30)])
+def test_two_eliminations_per_rotation_by_brute_force_and_three_way_loss(cluster):
+    """k = 3 with two indices retired per rotation (R17) on n = 48: every step's two retirees are
+    the two slots with the smallest off-diagonal norms recomputed from the dense current matrix,
+    the cluster takes ceil(r_u / 2) rotations, and the exact loss, ||A||^2 - ||H||^2 and the dense
+    residual from the log agree."""
+    n = 48
+    A = workloads.random_symmetric(n, 0.2, 31)
+    Ad = A.to_dense()
+    state = {"M": Ad.copy(), "stage": 0, "rows": None}
+    steps = []
+
+    def on_step(d):
+        if d["stage"] != state["stage"]:
+            state["stage"] = d["stage"]
+            state["rows"] = d["S"].copy()
+        S, off = state["rows"], d["offset"]
+        c = d["G"].shape[0]
+        cols = S[off:off + c]
+        ids = cols[np.asarray(d["T"])]
+        Q = np.eye(n)
+        Q[np.ix_(ids, ids)] = d["O"]
+        state["M"] = Q @ state["M"] @ Q.T
+        M1 = state["M"]
+        off2 = [float(np.sum(M1[np.ix_(S, [g])] ** 2) - M1[g, g] ** 2) for g in ids]
+        steps.append((d["stage"], d["cluster"], list(ids), off2))
+
+    fac = oracle.factor(A, k=3, core=8, cluster=cluster, seed=4, elims=2, on_step=on_step)
+    assert len(fac.rotations) == n - 8                     # one log entry per retired index
+    # entries of a step: the rotation, then the identity block on the same tuple
+    real = [r for r in fac.rotations if not np.array_equal(r.O, np.eye(3))]
+    assert len(real) == len(steps)
+    it = iter(fac.rotations)
+    for (p, u, ids, off2) in steps:
+        r1 = next(it)
+        assert list(r1.ids) == ids
+        order = sorted(range(3), key=lambda t: (off2[t], -t))   # smallest first, ties: later slot
+        assert r1.retired == ids[order[0]]
+        st = fac.stages[p - 1]
+        # a second entry unless this was the cluster's last, odd retirement
+        nxt = fac.rotations.index(r1) + 1
+        if nxt < len(fac.rotations) and list(fac.rotations[nxt].ids) == ids:
+            r2 = fac.rotations[nxt]
+            np.testing.assert_array_equal(r2.O, np.eye(3))
+            rest = [t for t in range(3) if t != order[0]]
+            second = min(rest, key=lambda t: (off2[t], -t))
+            assert r2.retired == ids[second]
+            next(it)
+    for st in fac.stages:
+        for ru, c in zip(st["cluster_rotations"], st["cluster_sizes"]):
+            assert ru <= c - 2
+    U = _dense_U(fac)
+    H = np.diag(fac.hdiag)
+    H[np.ix_(fac.core_ids, fac.core_ids)] = fac.hcore
+    dense = float(((Ad - U.T @ H @ U) ** 2).sum())
+    scale = float((Ad ** 2).sum())
+    assert abs(fac.loss - dense) <= 1e-10 * scale
+    assert abs(fac.loss - (scale - float((H ** 2).sum()))) <= 1e-10 * scale
+    np.testing.assert_allclose(U @ U.T, np.eye(n), atol=1e-12)
+
+
+def test_several_eliminations_bounds_and_default():
+    A = workloads.random_symmetric(30, 0.2, 3)
+    with pytest.raises(ValueError):
+        oracle.factor(A, k=2, core=6, elims=2)
+    a = oracle.factor(A, k=3, core=6, elims=1)
+    b = oracle.factor(A, k=3, core=6)
+    assert a.loss == b.loss
+    np.testing.assert_array_equal(a.retired_order, b.retired_order)
