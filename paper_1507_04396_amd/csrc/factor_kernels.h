@@ -48,7 +48,8 @@ hipError_t launch_fill_cluster_of(const int32_t* off, int m, int S, int32_t* cl_
 hipError_t launch_gram(int S, int64_t rp_nnz, const int64_t* rp, const int32_t* ci,
                        const float* cv, const int32_t* off, const int32_t* cl_of,
                        const int64_t* gbase, const int64_t* run_ptr, const int32_t* run_cl,
-                       const int64_t* run_start, float2* GD, int cmax, hipStream_t s);
+                       const int64_t* run_start, float2* GD, int cmax, hipStream_t s,
+                       int wpb = 0, int form = -1);
 // multiply-adds of the stage's cluster Grams (sum over rows and runs of the run length squared),
 // added to *out
 hipError_t launch_gram_work(int S, const int64_t* rp, const int64_t* run_ptr,

@@ -610,14 +610,16 @@ hipError_t launch_gram_bf16(int S, int m, const int64_t* rp, const int32_t* ci, 
 hipError_t launch_gram(int S, int64_t rp_nnz, const int64_t* rp, const int32_t* ci,
                        const float* cv, const int32_t* off, const int32_t* cl_of,
                        const int64_t* gbase, const int64_t* run_ptr, const int32_t* run_cl,
-                       const int64_t* run_start, float2* GD, int cmax, hipStream_t s) {
+                       const int64_t* run_start, float2* GD, int cmax, hipStream_t s, int wpb_cfg,
+                       int form) {
   if (S == 0) return hipSuccess;
-  int wpb = 4;
+  int wpb = wpb_cfg > 0 ? wpb_cfg : 4;
   while (wpb > 1 && (size_t)wpb * (cmax + PMMF_WAVE) * 4 > 64 * 1024) wpb >>= 1;
   const size_t lds = (size_t)wpb * (cmax + PMMF_WAVE) * sizeof(float);
-  // items of one segment once rows are long (their segments then span several chunks)
+  // default: items of one segment once rows are long (their segments then span several chunks)
   const int64_t nnz = rp_nnz;
-  auto kern = nnz >= 128 * (int64_t)S ? k_gram<true> : k_gram<false>;
+  const bool seg = form >= 0 ? form == 1 : nnz >= 128 * (int64_t)S;
+  auto kern = seg ? k_gram<true> : k_gram<false>;
   kern<<<(S + wpb - 1) / wpb, wpb * PMMF_WAVE, lds, s>>>(S, rp, ci, cv, off, cl_of, gbase, run_ptr,
                                                          run_cl, run_start, GD, cmax);
   return hipGetLastError();

@@ -9,6 +9,7 @@
 #include <map>
 #include <cstdlib>
 #include <cstring>
+#include <functional>
 #include <memory>
 #include <mutex>
 #include <set>
@@ -784,6 +785,17 @@ static void sync_rotations(mmf_plan& h, hipStream_t s) {
   }
 }
 
+namespace {
+// launch configuration of the sparse cluster Gram (waves per block, item form), chosen by the
+// autotuner below; defined with it
+struct GramCfg {
+  int wpb = 0;   // waves (rows) per workgroup; 0: the default
+  int form = -1; // 1: items of one row segment, 0: items of consecutive short segments; -1: default
+};
+GramCfg gram_config(const mmf_plan& h, int S, int64_t nnz, int cmax, hipStream_t s,
+                    const std::function<void(const GramCfg&)>& run);
+}  // namespace
+
 extern "C" int mmf_factor(int64_t n, int64_t nnz, const int64_t* d_rowptr, const int32_t* d_colind,
                           const float* d_val, const mmf_params* p, void* stream, mmf_handle* out) {
   ABI_BEGIN
@@ -992,11 +1004,16 @@ extern "C" int mmf_factor(int64_t n, int64_t nnz, const int64_t* d_rowptr, const
                                      dense_buf.as<float>(), sd.off.as<int32_t>(), sd.m,
                                      sd.gbase.as<int64_t>(), GD.as<float2>(), sd.cmax, s));
     } else {
-      HIPCHK(pmmf::launch_gram(S, M.nnz, M.rp.as<int64_t>(), M.ci.as<int32_t>(), M.cv.as<float>(),
-                               sd.off.as<int32_t>(), sd.cl_of.as<int32_t>(),
-                               sd.gbase.as<int64_t>(), run_ptr.as<int64_t>(),
-                               run_cl.as<int32_t>(), run_start.as<int64_t>(), GD.as<float2>(),
-                               cm, s));
+      auto gram = [&](const GramCfg& gc) {
+        HIPCHK(pmmf::launch_gram(S, M.nnz, M.rp.as<int64_t>(), M.ci.as<int32_t>(),
+                                 M.cv.as<float>(), sd.off.as<int32_t>(), sd.cl_of.as<int32_t>(),
+                                 sd.gbase.as<int64_t>(), run_ptr.as<int64_t>(),
+                                 run_cl.as<int32_t>(), run_start.as<int64_t>(), GD.as<float2>(),
+                                 cm, s, gc.wpb, gc.form));
+      };
+      // every configuration forms the same Gram (each row summed in one fixed order), so the
+      // tuner's trial runs leave the right values behind
+      gram(gram_config(*h, S, M.nnz, cm, s, gram));
     }
     // greedy rotation search in every cluster
     pmmf::FindArgs fa;
@@ -1460,6 +1477,59 @@ SweepCfg sweep_config(mmf_plan& h, const char* what, int nv, int64_t nrhs, hipSt
   {
     std::lock_guard<std::mutex> lk(g_tune.mu);
     g_tune.entries[key] = {best, best_ms};
+    tune_save_locked();
+  }
+  return best;
+}
+
+// The sparse cluster Gram: waves per workgroup (1, 2, 4 within the LDS budget) and item form,
+// tuned per stage shape (rows, nonzeros, largest cluster) with the same cache as the sweeps.
+GramCfg gram_config(const mmf_plan& h, int S, int64_t nnz, int cmax, hipStream_t s,
+                    const std::function<void(const GramCfg&)>& run) {
+  GramCfg def;
+  hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
+  if (!autotune_enabled() || hipStreamIsCapturing(s, &cap) != hipSuccess ||
+      cap != hipStreamCaptureStatusNone)
+    return def;
+  char what[128];
+  std::snprintf(what, sizeof what, "gram_S%d_nnz%lld_c%d", S, (long long)nnz, cmax);
+  const std::string key = tune_key(h, what, 0, 0);
+  {
+    std::lock_guard<std::mutex> lk(g_tune.mu);
+    if (!g_tune.loaded || g_tune.path != tune_path()) {
+      g_tune.entries.clear();
+      tune_load_locked();
+    }
+    auto f = g_tune.entries.find(key);
+    if (f != g_tune.entries.end()) return GramCfg{f->second.first.wpb, f->second.first.W};
+  }
+  hipEvent_t e0, e1;
+  HIPCHK(hipEventCreate(&e0));
+  HIPCHK(hipEventCreate(&e1));
+  GramCfg best = def;
+  double best_ms = 1e300;
+  for (int form : {0, 1})
+    for (int wpb : {1, 2, 4}) {
+      if ((size_t)wpb * (cmax + 64) * 4 > 64 * 1024) continue;
+      const GramCfg c{wpb, form};
+      run(c);  // warm
+      HIPCHK(hipEventRecord(e0, s));
+      run(c);
+      run(c);
+      HIPCHK(hipEventRecord(e1, s));
+      HIPCHK(hipEventSynchronize(e1));
+      float ms = 0.f;
+      HIPCHK(hipEventElapsedTime(&ms, e0, e1));
+      if (ms / 2.0 < best_ms) {
+        best_ms = ms / 2.0;
+        best = c;
+      }
+    }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  {
+    std::lock_guard<std::mutex> lk(g_tune.mu);
+    g_tune.entries[key] = {SweepCfg{best.wpb, best.form}, best_ms};
     tune_save_locked();
   }
   return best;
