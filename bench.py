@@ -219,6 +219,10 @@ def main():
     ap.add_argument("--pcg-workload", default="grid3d_n1050703")
     ap.add_argument("--pcg-nrhs", type=int, default=128)
     ap.add_argument("--no-pcg", action="store_true")
+    ap.add_argument("--gram-mode", type=int, default=0,
+                    help="Gram form of the timed factorizations (0 FP32, 1 BF16 with rescoring)")
+    ap.add_argument("--apply-only", action="store_true",
+                    help="time apply, adjoint and refinement only (counter runs of the sweeps)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "
@@ -249,9 +253,18 @@ def main():
     copy_gbs = 2 * 4 * copy_elems / (copy_ms * 1e-3) / 1e9
     del src, dst
 
+    if args.apply_only:
+        apply_res, back_res, refine = measure_apply(args, torch, workloads, Factorization, log)
+        print(json.dumps({"apply": apply_res, "backward": back_res, "refine": refine}), flush=True)
+        return
+
     # ----------------------------------------------------------------- factorization (headline)
     wl = workloads.WORKLOADS[args.workload]
     prm = dict(wl["params"])
+    if args.gram_mode:
+        if not args.factor_only:
+            raise SystemExit("--gram-mode applies to --factor-only runs")
+        prm["gram_mode"] = args.gram_mode
     log(f"[bench] generating {args.workload}")
     A = workloads.make_matrix(args.workload)
     rp, ci, cv = device_csr(A, torch)
