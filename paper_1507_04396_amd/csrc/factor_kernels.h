@@ -9,6 +9,10 @@
 
 namespace pmmf {
 
+// row stride of a cluster's c x c (G, D) array: even, so every row starts 16-byte aligned and a
+// pair of adjacent entries moves in one 16-byte access
+__host__ __device__ inline int gd_stride(int c) { return c + (c & 1); }
+
 struct FindArgs {
   int p;                     // stage number, 1-based (enters the seed-row hash)
   int k;                     // 2 or 3

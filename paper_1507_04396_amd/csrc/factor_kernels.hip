@@ -1,6 +1,7 @@
 // Factorization kernels for pMMF on gfx950 (wave64).  See factor_kernels.h for the data layout.
 #include "factor_kernels.h"
 
+#include <algorithm>
 #include <climits>
 
 namespace pmmf {
@@ -312,7 +313,7 @@ __global__ void __launch_bounds__(256) k_gram(int S, const int64_t* __restrict__
   }
   // Gram halves of the interleaved (G, D) row, then the diagonal-block halves through the same
   // accumulator (the two store passes write disjoint words)
-  const size_t base = (size_t)gbase[u] + (size_t)la * c;
+  const size_t base = (size_t)gbase[u] + (size_t)la * gd_stride(c);
   float* gd = reinterpret_cast<float*>(GD + base);
   for (int j = lane; j < c; j += PMMF_WAVE) {
     gd[2 * j] = acc[j];
@@ -398,9 +399,11 @@ __global__ void __launch_bounds__(256) k_gram_dense(int S, const float* __restri
     const int i = ti * DG_T + wm + 4 * (lane >> 4) + r;
     const int j = tj * DG_T + wn + (lane & 15);
     if (i < c && j < c) {
-      GD[base + (size_t)i * c + j] = make_float2(acc[r], dense[(size_t)(o + i) * S + o + j]);
+      GD[base + (size_t)i * gd_stride(c) + j] =
+          make_float2(acc[r], dense[(size_t)(o + i) * S + o + j]);
       if (ti != tj)
-        GD[base + (size_t)j * c + i] = make_float2(acc[r], dense[(size_t)(o + j) * S + o + i]);
+        GD[base + (size_t)j * gd_stride(c) + i] =
+            make_float2(acc[r], dense[(size_t)(o + j) * S + o + i]);
     }
   }
 }
@@ -546,8 +549,8 @@ __global__ void __launch_bounds__(256) k_gram_bf16(const unsigned short* __restr
     const int i = ti * BG_T + wm + 4 * (lane >> 4) + r;
     const int j = tj * BG_T + wn + (lane & 15);
     if (i < c && j < c) {
-      GD[base + (size_t)i * c + j] = make_float2(acc[r], 0.f);
-      if (ti != tj) GD[base + (size_t)j * c + i] = make_float2(acc[r], 0.f);
+      GD[base + (size_t)i * gd_stride(c) + j] = make_float2(acc[r], 0.f);
+      if (ti != tj) GD[base + (size_t)j * gd_stride(c) + i] = make_float2(acc[r], 0.f);
     }
   }
 }
@@ -564,7 +567,7 @@ __global__ void k_slab_finish(int S, const int64_t* __restrict__ rp, const int32
   const int lane = pmmf_lane();
   const int u = cl_of[a];
   const int o = off[u], c = off[u + 1] - o, j = a - o;
-  float* gd = reinterpret_cast<float*>(GD + (size_t)gbase[u] + (size_t)j * c);
+  float* gd = reinterpret_cast<float*>(GD + (size_t)gbase[u] + (size_t)j * gd_stride(c));
   for (int64_t t = rp[a] + lane; t < rp[a + 1]; t += PMMF_WAVE) {
     const int col = ci[t];
     if (col >= o && col < o + c) gd[2 * (col - o) + 1] = cv[t];
@@ -698,19 +701,11 @@ __device__ inline void jacobi_pair(double (&A)[3][3], double (&V)[3][3], int p, 
   }
 }
 
-// FP64 cyclic Jacobi sweeps on A (accumulated into V, A = V^T g V on entry), then the arrangement
-// of the eigenvectors described above.
-__device__ inline void rot3_finish(double (&A)[3][3], double (&V)[3][3], double (&O)[3][3],
-                                   double& trace_margin, double& eig_margin) {
-  for (int sweep = 0; sweep < 12; ++sweep) {
-    bool rot = false;
-    jacobi_pair(A, V, 0, 1, rot);
-    jacobi_pair(A, V, 0, 2, rot);
-    jacobi_pair(A, V, 1, 2, rot);
-    if (!rot) break;
-  }
+// Arrangement of an eigendecomposition (eigenvalues e0..e2, eigenvectors the columns of V) as
+// described above.
+__device__ inline void arrange3(double e0, double e1, double e2, const double (&V)[3][3],
+                                double (&O)[3][3], double& trace_margin, double& eig_margin) {
   // columns of V sorted by descending eigenvalue (three compare-swaps on scalars)
-  double e0 = A[0][0], e1 = A[1][1], e2 = A[2][2];
   double b00 = V[0][0], b01 = V[1][0], b02 = V[2][0];   // b0 = eigenvector of e0 (column 0)
   double b10 = V[0][1], b11 = V[1][1], b12 = V[2][1];
   double b20 = V[0][2], b21 = V[1][2], b22 = V[2][2];
@@ -773,6 +768,19 @@ __device__ inline void rot3_finish(double (&A)[3][3], double (&V)[3][3], double 
     O[1][j] *= s1;
     O[2][j] *= s2;
   }
+}
+
+// FP64 cyclic Jacobi sweeps on A (accumulated into V, A = V^T g V on entry), then the arrangement.
+__device__ inline void rot3_finish(double (&A)[3][3], double (&V)[3][3], double (&O)[3][3],
+                                   double& trace_margin, double& eig_margin) {
+  for (int sweep = 0; sweep < 12; ++sweep) {
+    bool rot = false;
+    jacobi_pair(A, V, 0, 1, rot);
+    jacobi_pair(A, V, 0, 2, rot);
+    jacobi_pair(A, V, 1, 2, rot);
+    if (!rot) break;
+  }
+  arrange3(A[0][0], A[1][1], A[2][2], V, O, trace_margin, eig_margin);
 }
 
 __device__ inline void rot3(const double (&g)[3][3], double (&O)[3][3], double& trace_margin,
@@ -875,6 +883,119 @@ __device__ inline void rot3_polished(const double (&g)[3][3], double (&O)[3][3],
 #pragma unroll
     for (int j = 0; j < i; ++j) A[i][j] = A[j][i] = 0.5 * (A[i][j] + A[j][i]);
   rot3_finish(A, V, O, trace_margin, eig_margin);
+}
+
+// FP32 cyclic Jacobi sweeps from the identity: eigenvectors of g to FP32 accuracy (columns of V)
+__device__ inline void jacobi3_f(const double (&g)[3][3], float (&V)[3][3]) {
+  float Af[3][3];
+#pragma unroll
+  for (int i = 0; i < 3; ++i)
+#pragma unroll
+    for (int j = 0; j < 3; ++j) { Af[i][j] = (float)g[i][j]; V[i][j] = (i == j) ? 1.f : 0.f; }
+  for (int sweep = 0; sweep < 12; ++sweep) {
+    bool rot = false;
+    jacobi_pair_f(Af, V, 0, 1, rot);
+    jacobi_pair_f(Af, V, 0, 2, rot);
+    jacobi_pair_f(Af, V, 1, 2, rot);
+    if (!rot) break;
+  }
+}
+
+// One step of the eigenvector refinement of Ogita and Aishima (Japan J. Indust. Appl. Math. 35,
+// 2018) for a symmetric 3 x 3 g and approximate eigenvectors X (columns): with R = I - X^T X and
+// S = X^T g X the eigenvalues are lam_i = S_ii / (1 - R_ii), and X <- X (I + F) with
+// F_ii = R_ii / 2 and, for i != j, F_ij = (S_ij + lam_j R_ij) / (lam_j - lam_i), which is the
+// first-order solution of (I + F)^T (I - R) (I + F) = I, (I + F)^T S (I + F) diagonal.  The error
+// of X is squared (times |g| / gap).  Returns false, leaving X unchanged, when two eigenvalues
+// lie within delta = 2 (|S - diag(lam)| + |g| |R|) (Frobenius norms), a cluster one step cannot
+// separate; fmx = max |F_ij| over i != j, mingap = the smallest eigenvalue gap.
+__device__ inline bool oa_step(const double (&g)[3][3], double (&X)[3][3], double (&lam)[3],
+                               double& fmx, double& mingap) {
+  double W[3][3];
+#pragma unroll
+  for (int i = 0; i < 3; ++i)
+#pragma unroll
+    for (int j = 0; j < 3; ++j) W[i][j] = g[i][0] * X[0][j] + g[i][1] * X[1][j] + g[i][2] * X[2][j];
+  double S[3][3], R[3][3];
+#pragma unroll
+  for (int i = 0; i < 3; ++i)
+#pragma unroll
+    for (int j = i; j < 3; ++j) {
+      S[i][j] = X[0][i] * W[0][j] + X[1][i] * W[1][j] + X[2][i] * W[2][j];
+      R[i][j] = (i == j ? 1.0 : 0.0) - (X[0][i] * X[0][j] + X[1][i] * X[1][j] + X[2][i] * X[2][j]);
+    }
+#pragma unroll
+  for (int i = 0; i < 3; ++i) lam[i] = S[i][i] * nr_rcp(1.0 - R[i][i]);
+  const double so = 2.0 * (S[0][1] * S[0][1] + S[0][2] * S[0][2] + S[1][2] * S[1][2]) +
+                    (S[0][0] - lam[0]) * (S[0][0] - lam[0]) +
+                    (S[1][1] - lam[1]) * (S[1][1] - lam[1]) + (S[2][2] - lam[2]) * (S[2][2] - lam[2]);
+  const double rr = 2.0 * (R[0][1] * R[0][1] + R[0][2] * R[0][2] + R[1][2] * R[1][2]) +
+                    R[0][0] * R[0][0] + R[1][1] * R[1][1] + R[2][2] * R[2][2];
+  double gg = 0.0;
+#pragma unroll
+  for (int i = 0; i < 3; ++i)
+#pragma unroll
+    for (int j = 0; j < 3; ++j) gg += g[i][j] * g[i][j];
+  const double delta = 2.0 * (sqrt(so) + sqrt(gg * rr));
+  const double d01 = lam[1] - lam[0], d02 = lam[2] - lam[0], d12 = lam[2] - lam[1];
+  mingap = fmin(fabs(d01), fmin(fabs(d02), fabs(d12)));
+  if (!(mingap > delta)) return false;
+  const double r01 = nr_rcp(d01), r02 = nr_rcp(d02), r12 = nr_rcp(d12);
+  double F[3][3];
+  F[0][0] = 0.5 * R[0][0];
+  F[1][1] = 0.5 * R[1][1];
+  F[2][2] = 0.5 * R[2][2];
+  F[0][1] = (S[0][1] + lam[1] * R[0][1]) * r01;
+  F[1][0] = -(S[0][1] + lam[0] * R[0][1]) * r01;
+  F[0][2] = (S[0][2] + lam[2] * R[0][2]) * r02;
+  F[2][0] = -(S[0][2] + lam[0] * R[0][2]) * r02;
+  F[1][2] = (S[1][2] + lam[2] * R[1][2]) * r12;
+  F[2][1] = -(S[1][2] + lam[1] * R[1][2]) * r12;
+  fmx = fmax(fmax(fmax(fabs(F[0][1]), fabs(F[1][0])), fmax(fabs(F[0][2]), fabs(F[2][0]))),
+             fmax(fabs(F[1][2]), fabs(F[2][1])));
+  double Xn[3][3];
+#pragma unroll
+  for (int i = 0; i < 3; ++i)
+#pragma unroll
+    for (int j = 0; j < 3; ++j)
+      Xn[i][j] = X[i][j] + (X[i][0] * F[0][j] + X[i][1] * F[1][j] + X[i][2] * F[2][j]);
+#pragma unroll
+  for (int i = 0; i < 3; ++i)
+#pragma unroll
+    for (int j = 0; j < 3; ++j) X[i][j] = Xn[i][j];
+  return true;
+}
+
+// FP64 eigendecomposition of a symmetric 3 x 3 g for the rotation (arranged as in rot3): FP32
+// Jacobi sweeps, then FP64 refinement steps until the error left, about fmx^2 |g| / gap, is below
+// 1e-12 (at most three steps; one or two from the FP32 start).  Eigenvalues closer than one step
+// can separate are finished by FP64 Jacobi sweeps instead (rot3_polished).
+__device__ inline void rot3_refined(const double (&g)[3][3], double (&O)[3][3],
+                                    double& trace_margin, double& eig_margin) {
+  float Vf[3][3];
+  jacobi3_f(g, Vf);
+  double X[3][3], lam[3];
+#pragma unroll
+  for (int i = 0; i < 3; ++i)
+#pragma unroll
+    for (int j = 0; j < 3; ++j) X[i][j] = (double)Vf[i][j];
+  double gg = 0.0;
+#pragma unroll
+  for (int i = 0; i < 3; ++i)
+#pragma unroll
+    for (int j = 0; j < 3; ++j) gg += g[i][j] * g[i][j];
+  const double gn = sqrt(gg);
+  bool ok = false;
+  for (int it = 0; it < 3; ++it) {
+    double fm, mg;
+    ok = oa_step(g, X, lam, fm, mg);
+    if (!ok || fm * fm * gn <= 1e-12 * mg) break;
+  }
+  if (ok) {
+    arrange3(lam[0], lam[1], lam[2], X, O, trace_margin, eig_margin);
+    return;
+  }
+  rot3_polished(g, O, trace_margin, eig_margin);
 }
 
 // ------------------------------------------------------------------------------------------
@@ -1051,9 +1172,14 @@ __device__ inline float2 rot_entry(const float* o, int a, const float2* v) {
 // stores before the partner rows are read.  The retirement is applied to the active mask one
 // step late (the scoring also skips the previous retiree explicitly), so wave 1 can read a mask
 // that nobody writes during the serial section.
-// E = indices retired per rotation (1, or 2 with k = 3): a step's rotation retires its E slots with
-// the smallest off-diagonal norms and writes E log entries, the later ones on the same tuple with
-// the identity block.
+// E = indices retired per rotation: a step's rotation retires its E slots with the smallest
+// off-diagonal norms and writes E log entries, the later ones on the same tuple with the identity
+// block.  Launched for two retirements per 3-point rotation (E = 2); one retirement per rotation
+// runs k_search below.
+// target of the column stores a step has none to make (the first step): written, never read, so the
+// workgroups that share it may overwrite one another
+__device__ float2 g_find_sink[4096];
+
 template <int NT, int PER, int K, int E>
 __global__ void __launch_bounds__(NT) k_find(FindArgs A, int cmax) {
   static_assert(NT >= 2 * PMMF_WAVE, "wave 1 selects the next seed");
@@ -1068,12 +1194,14 @@ __global__ void __launch_bounds__(NT) k_find(FindArgs A, int cmax) {
   constexpr int NW = NT / PMMF_WAVE;
   __shared__ Cand red1[NW], red2[NW];
   __shared__ int sh_i, sh_e, sh_e2, sh_c[E + 1], sh_k[2 * E + 1];
-  __shared__ float sh_O[9], sh_gn[9], sh_dn[9];
+  __shared__ float sh_O[9], sh_gn[9], sh_dn[9], sh_mg[2], sh_de[2];
+  __shared__ double sh_lit[2];
 
   const int tid = threadIdx.x;
   const int u = A.order[blockIdx.x];
   const int o = A.off[u];
   const int c = A.off[u + 1] - o;
+  const int ld = gd_stride(c);  // row stride of the cluster's (G, D) array
   const int nent = A.rcnt[u];                 // log entries: indices the cluster retires
   const int r = (nent + E - 1) / E;           // rotations (steps)
   const int rb = A.roff[u];
@@ -1084,7 +1212,7 @@ __global__ void __launch_bounds__(NT) k_find(FindArgs A, int cmax) {
   float2* R2 = rowbuf + 3 * (size_t)cmax;
 
   for (int j = tid; j < c; j += NT) {
-    const float2 dg = GD[(size_t)j * c + j];
+    const float2 dg = GD[(size_t)j * ld + j];
     gdiag[j] = dg.x;
     gsq[j] = sqrtf(dg.x);
     ddiag[j] = dg.y;
@@ -1117,7 +1245,7 @@ __global__ void __launch_bounds__(NT) k_find(FindArgs A, int cmax) {
   // is dead and takes the lanes with nothing to store
   float2 cst[3][PER];
   uint64_t cmask = 0;
-  int tq0 = -1, tq1 = -1, tq2 = -1, edead = -1;
+  int tq0 = -1, tq1 = -1, tq2 = -1, edead = 0;
   int jl[PER];  // this thread's columns, clamped into the cluster for address forming
   // candidates for the next seed (k = 2: their rows are loaded during this step's rotation)
   int cc[E + 1];
@@ -1129,7 +1257,7 @@ __global__ void __launch_bounds__(NT) k_find(FindArgs A, int cmax) {
   for (int q = 0; q < PER; ++q) {
     const int j = tid + q * NT;
     jl[q] = min(j, c - 1);
-    cur[q] = (r > 0 && j < c) ? GD[(size_t)i * c + j] : make_float2(0.f, 0.f);
+    cur[q] = (r > 0 && j < c) ? GD[(size_t)i * ld + j] : make_float2(0.f, 0.f);
 #pragma unroll
     for (int a = 0; a < 3; ++a) cst[a][q] = make_float2(0.f, 0.f);
   }
@@ -1186,23 +1314,27 @@ __global__ void __launch_bounds__(NT) k_find(FindArgs A, int cmax) {
     // the (t1, t2) entries first (lane 0 needs them before anything else), then the partner rows
     float2 x12 = make_float2(0.f, 0.f), x21 = make_float2(0.f, 0.f);
     if (kk == 3 && tid < PMMF_WAVE) {
-      x12 = GD[(size_t)t1 * c + t2];
-      x21 = GD[(size_t)t2 * c + t1];
+      x12 = GD[(size_t)t1 * ld + t2];
+      x21 = GD[(size_t)t2 * ld + t1];
     }
+    // the other waves' loads and stores queue behind these two in the compute unit's memory
+    // pipeline (a barrier does not wait for loads in flight)
+    if (kk == 3) __syncthreads();  // A'
     float2 p1[PER], p2[PER];
 #pragma unroll
     for (int q = 0; q < PER; ++q) {
       const int j = tid + q * NT;
       const int sj = slot_of(j, tq0, tq1, tq2);
       const uint32_t jq = (uint32_t)jl[q];
-      p1[q] = GD[(sj >= 0 && st1 < 0) ? (uint32_t)(j * c + t1) : (uint32_t)(t1 * c) + jq];
-      p2[q] = kk == 3 ? GD[(sj >= 0 && st2 < 0) ? (uint32_t)(j * c + t2) : (uint32_t)(t2 * c) + jq]
+      p1[q] = GD[(sj >= 0 && st1 < 0) ? (uint32_t)(j * ld + t1) : (uint32_t)(t1 * ld) + jq];
+      p2[q] = kk == 3 ? GD[(sj >= 0 && st2 < 0) ? (uint32_t)(j * ld + t2) : (uint32_t)(t2 * ld) + jq]
                       : make_float2(0.f, 0.f);
     }
-    // the previous step's column stores, after this step's loads (wave 0 issues its share after
-    // lane 0's rotation); a lane with no real entry writes into the dead row of that step's
-    // retiree, contiguous across the wave.  Branch-free, so a wait for the loads above does not
-    // wait for these stores.
+    // the previous step's column stores, after this step's loads; a lane with no real entry
+    // writes into the dead row of that step's retiree, contiguous across the wave (the first step
+    // writes its zeros into the sink).  Branch-free, so a wait for the loads above does not wait
+    // for these stores.
+    float2* const cbase = s > 0 ? GD : g_find_sink;
     auto column_stores = [&]() {
 #pragma unroll
       for (int q = 0; q < PER; ++q) {
@@ -1211,27 +1343,27 @@ __global__ void __launch_bounds__(NT) k_find(FindArgs A, int cmax) {
         for (int a = 0; a < K; ++a) {
           const int ta = a == 0 ? tq0 : (a == 1 ? tq1 : tq2);
           const bool real = (cmask >> (a * PER + q)) & 1ull;
-          GD[real ? (uint32_t)(j * c + ta) : (uint32_t)(edead * c + jl[q])] = cst[a][q];
+          cbase[real ? (uint32_t)(j * ld + ta) : (uint32_t)(edead * ld + jl[q])] = cst[a][q];
         }
       }
     };
-    if (s > 0 && pmmf_wave() != 0) column_stores();
     // the rows of the two candidates for the next seed, read the same way (their entries at T
-    // are re-formed after this step's rotation); issued after the stores, as nothing before
-    // barrier B needs them
-    // (k = 2 only: with k = 3 the extra loads delay the lane-0 entries more than the prefetch
-    // saves after barrier B)
-    if constexpr (K == 2) {
+    // are re-formed after this step's rotation; one retirement per step only: with two the three
+    // candidate rows would not fit in registers)
+    if constexpr (E == 1) {
       const int sc0 = slot_of(cc[0], tq0, tq1, tq2), sc1 = slot_of(cc[1], tq0, tq1, tq2);
 #pragma unroll
       for (int q = 0; q < PER; ++q) {
         const int j = tid + q * NT;
         const int sj = slot_of(j, tq0, tq1, tq2);
         const uint32_t jq = (uint32_t)jl[q];
-        c0r[q] = GD[(sj >= 0 && sc0 < 0) ? (uint32_t)(j * c + cc[0]) : (uint32_t)(cc[0] * c) + jq];
-        c1r[q] = GD[(sj >= 0 && sc1 < 0) ? (uint32_t)(j * c + cc[1]) : (uint32_t)(cc[1] * c) + jq];
+        c0r[q] = GD[(sj >= 0 && sc0 < 0) ? (uint32_t)(j * ld + cc[0]) : (uint32_t)(cc[0] * ld) + jq];
+        c1r[q] = GD[(sj >= 0 && sc1 < 0) ? (uint32_t)(j * ld + cc[1]) : (uint32_t)(cc[1] * ld) + jq];
       }
     }
+    // the stores last: vector memory operations complete in issue order, so lane 0's wait for the
+    // (t1, t2) entries does not wait for a store
+    column_stores();
 
     if (tid == 0) {
       double g[3][3] = {}, d[3][3] = {}, O[3][3] = {};
@@ -1334,36 +1466,14 @@ __global__ void __launch_bounds__(NT) k_find(FindArgs A, int cmax) {
           sh_gn[a * 3 + b] = (float)gn[a][b];
           sh_dn[a * 3 + b] = (float)dn[a][b];
         }
-      // rotation log (stores only: nothing on this lane waits for them)
-      const int64_t ridx = A.rot0 + rb + (int64_t)E * s;
-      A.rot_loc[ridx * 3 + 0] = t0;
-      A.rot_loc[ridx * 3 + 1] = t1;
-      A.rot_loc[ridx * 3 + 2] = kk == 3 ? t2 : -1;
-      A.rot_gid[ridx * 3 + 0] = lgid[t0];
-      A.rot_gid[ridx * 3 + 1] = lgid[t1];
-      A.rot_gid[ridx * 3 + 2] = kk == 3 ? lgid[t2] : -1;
-#pragma unroll
-      for (int a = 0; a < 9; ++a) A.rot_o[ridx * 9 + a] = sh_O[a];
-      A.rot_ret[ridx] = lgid[e];
-      A.rot_margin[ridx] = (float)margin;
-      A.rot_lit[ridx] = 2.0 * off2e;
-      A.hdiag[lgid[e]] = (float)dee;
-      A.retflag[o + e] = 1;
-      if (second) {  // the same tuple with the identity block, retiring e2
-        const int64_t r2 = ridx + 1;
-        A.rot_loc[r2 * 3 + 0] = t0;
-        A.rot_loc[r2 * 3 + 1] = t1;
-        A.rot_loc[r2 * 3 + 2] = t2;
-        A.rot_gid[r2 * 3 + 0] = lgid[t0];
-        A.rot_gid[r2 * 3 + 1] = lgid[t1];
-        A.rot_gid[r2 * 3 + 2] = lgid[t2];
-#pragma unroll
-        for (int a = 0; a < 9; ++a) A.rot_o[r2 * 9 + a] = (a % 4 == 0) ? 1.f : 0.f;
-        A.rot_ret[r2] = lgid[e2];
-        A.rot_margin[r2] = (float)margin2;
-        A.rot_lit[r2] = 2.0 * off2e2;
-        A.hdiag[lgid[e2]] = (float)dee2;
-        A.retflag[o + e2] = 1;
+      // the rotation log is written by wave 1 after barrier B
+      sh_mg[0] = (float)margin;
+      sh_de[0] = (float)dee;
+      sh_lit[0] = 2.0 * off2e;
+      if (E == 2) {
+        sh_mg[1] = (float)margin2;
+        sh_de[1] = (float)dee2;
+        sh_lit[1] = 2.0 * off2e2;
       }
     }
     if (tid >= PMMF_WAVE && tid < 2 * PMMF_WAVE && s + 2 < r) {
@@ -1388,7 +1498,6 @@ __global__ void __launch_bounds__(NT) k_find(FindArgs A, int cmax) {
         if (kk == 3) R2[j] = p2[q];
       }
     }
-    if (s > 0 && pmmf_wave() == 0) column_stores();
     __syncthreads();  // B
 
     float o_[9];
@@ -1409,14 +1518,14 @@ __global__ void __launch_bounds__(NT) k_find(FindArgs A, int cmax) {
     const int Tt[3] = {t0, t1, t2};
     if (tid < kk * kk) {
       const int a = tid / kk, b = tid % kk;
-      GD[(size_t)Tt[a] * c + Tt[b]] = make_float2(sh_gn[a * 3 + b], sh_dn[a * 3 + b]);
+      GD[(size_t)Tt[a] * ld + Tt[b]] = make_float2(sh_gn[a * 3 + b], sh_dn[a * 3 + b]);
     }
     float2 nrow[PER];
-    if constexpr (K == 2) {
+    if constexpr (E == 1) {
 #pragma unroll
       for (int q = 0; q < PER; ++q) nrow[q] = nxt == cc[0] ? c0r[q] : c1r[q];
     } else {
-      const uint32_t nb = (uint32_t)((more && aslot < 0 ? nxt : 0) * c);
+      const uint32_t nb = (uint32_t)((more && aslot < 0 ? nxt : 0) * ld);
 #pragma unroll
       for (int q = 0; q < PER; ++q) nrow[q] = GD[nb + (uint32_t)jl[q]];
     }
@@ -1444,6 +1553,39 @@ __global__ void __launch_bounds__(NT) k_find(FindArgs A, int cmax) {
       mask[e >> 5] &= ~(1u << (e & 31));
       if (E == 2 && e2 >= 0) mask[e2 >> 5] &= ~(1u << (e2 & 31));
     }
+    if (pmmf_wave() == 1) {  // rotation log, one entry per lane (stores only: nothing waits)
+      const int l = pmmf_lane();
+      const int64_t ridx = A.rot0 + rb + (int64_t)E * s;
+      if (l < 9) A.rot_o[ridx * 9 + l] = sh_O[l];
+      if (l < 3) {
+        const int tl = l == 0 ? t0 : (l == 1 ? t1 : t2);
+        A.rot_loc[ridx * 3 + l] = tl;
+        A.rot_gid[ridx * 3 + l] = tl >= 0 ? lgid[tl] : -1;
+      }
+      if (l == 0) {
+        A.rot_ret[ridx] = lgid[e];
+        A.rot_margin[ridx] = sh_mg[0];
+        A.rot_lit[ridx] = sh_lit[0];
+        A.hdiag[lgid[e]] = sh_de[0];
+        A.retflag[o + e] = 1;
+      }
+      if (E == 2 && e2 >= 0) {  // the same tuple with the identity block, retiring e2
+        const int64_t r2 = ridx + 1;
+        if (l < 9) A.rot_o[r2 * 9 + l] = (l % 4 == 0) ? 1.f : 0.f;
+        if (l < 3) {
+          const int tl = l == 0 ? t0 : (l == 1 ? t1 : t2);
+          A.rot_loc[r2 * 3 + l] = tl;
+          A.rot_gid[r2 * 3 + l] = lgid[tl];
+        }
+        if (l == 0) {
+          A.rot_ret[r2] = lgid[e2];
+          A.rot_margin[r2] = sh_mg[1];
+          A.rot_lit[r2] = sh_lit[1];
+          A.hdiag[lgid[e2]] = sh_de[1];
+          A.retflag[o + e2] = 1;
+        }
+      }
+    }
 
     // stores: GD <- O GD O^T on rows T now (the k x k block above; a column in T or beyond the
     // cluster writes into the dead column of this step's retiree, and a retired column's entry
@@ -1460,7 +1602,7 @@ __global__ void __launch_bounds__(NT) k_find(FindArgs A, int cmax) {
 #pragma unroll
       for (int a = 0; a < K; ++a) {
         nv[a] = rot_entry<K>(o_, a, v);
-        GD[(uint32_t)(Tt[a] * c) + (uint32_t)(in ? j : e)] = nv[a];
+        GD[(uint32_t)(Tt[a] * ld) + (uint32_t)(in ? j : e)] = nv[a];
         cst[a][q] = nv[a];
         const uint32_t m = __float_as_uint(nv[a].x) | __float_as_uint(nv[a].y) |
                            __float_as_uint(v[a].x) | __float_as_uint(v[a].y);
@@ -1503,9 +1645,546 @@ static hipError_t find_launch(const FindArgs& a, int m, int cmax, size_t lds0, h
 
 template <int NT, int PER>
 static hipError_t find_launch_k(const FindArgs& a, int m, int cmax, size_t lds, hipStream_t s) {
-  if (a.k != 3) return find_launch<NT, PER, 2, 1>(a, m, cmax, lds, s);
-  return a.elims == 2 ? find_launch<NT, PER, 3, 2>(a, m, cmax, lds, s)
-                      : find_launch<NT, PER, 3, 1>(a, m, cmax, lds, s);
+  if (a.k != 3 || a.elims != 2) return hipErrorInvalidValue;  // one retirement: k_search
+  return find_launch<NT, PER, 3, 2>(a, m, cmax, lds, s);
+}
+
+// ------------------------------------------------------------------------------------------
+// Greedy search with one retirement per rotation (Alg. 2), one workgroup per cluster, wave 0 a
+// control wave and the other waves column waves.
+//
+// The control wave owns no columns: it fetches G_{t1 t2}, selects the seed candidates two steps
+// ahead while that entry is in flight, computes the FP64 rotation on lane 0 and writes the log.
+// Column thread x = tid - 64 owns the columns j = x + q (NT - 64), q < PER, and keeps its slices
+// of the seed row, the partner rows and the two candidate rows of the next seed in registers.
+// Step s (seed i, partners t1, t2 from the merged scores of row i):
+//   after barrier A the column waves request the partner rows and the rows of the two candidates
+//   for the next seed (one of them becomes the seed once the step's retiree is known), and store
+//   the previous step's columns.  While lane 0 rotates they score both candidate rows over every
+//   column outside T: those entries and G_jj are not changed by the rotation, and the retiree is
+//   in T.
+//   after barrier B the column waves rotate and store rows T and assemble the next seed row; the
+//   control wave scores that row's entries at T, re-formed from the pre-rotation rows.  The next
+//   merge takes the chosen candidate's per-wave winners and these three entries.  When the next
+//   seed is itself in T its row is the one just formed, and it is scored in full.
+// A column entry (j, t), t in T, is stored at the end of the next step's first half if it is not
+// zero (a zero stays zero); until then that step's loads take its transpose from row t, which is
+// stored before barrier A.
+__device__ inline float inv_sqrt_pos(float g) { return g > 0.f ? 1.f / sqrtf(g) : 0.f; }
+// partner score |G_xj| / sqrt(G_jj) from 1 / sqrt(G_jj); NaN (an overflowed entry) scores 0
+__device__ inline float partner_score(float gxj, float rg) {
+  const float sc = fabsf(gxj) * rg;
+  return sc >= 0.f ? sc : 0.f;
+}
+template <int K>
+__device__ inline void take(Cand& b1, Cand& b2, Cand c) {
+  if (K == 3) {
+    if (better(c, b1)) { b2 = b1; b1 = c; }
+    else if (better(c, b2)) b2 = c;
+  } else if (better(c, b1)) {
+    b1 = c;
+  }
+}
+
+template <int NT, int PER, int K>
+__global__ void __launch_bounds__(NT) k_search(FindArgs A, int cmax) {
+  static_assert(NT >= 2 * PMMF_WAVE, "a control wave and at least one column wave");
+  constexpr int NW = NT / PMMF_WAVE;
+  constexpr int NC = NT - PMMF_WAVE;  // column threads
+  extern __shared__ float lds_f[];
+  float2* rowbuf = reinterpret_cast<float2*>(lds_f);  // seed rows (2 parities), partner rows
+  float* gdiag = reinterpret_cast<float*>(rowbuf + 4 * (size_t)cmax);
+  float* ddiag = gdiag + cmax;
+  float* rgs = ddiag + cmax;  // 1 / sqrt(G_jj), 0 where G_jj <= 0
+  int* lgid = reinterpret_cast<int*>(rgs + cmax);
+  uint32_t* mask = reinterpret_cast<uint32_t*>(lgid + cmax);
+  // per-wave winners [parity][0, 1: candidate rows, 2: full scoring][wave]; entries at T
+  __shared__ Cand red1[2][3][NW], red2[2][3][NW], sh_tc[3];
+  __shared__ int sh_i, sh_e, sh_c[2], sh_k[3];
+  __shared__ float sh_O[9], sh_gn[9], sh_dn[9], sh_mg, sh_de;
+  __shared__ double sh_lit;
+
+  const int tid = threadIdx.x;
+  const int wv = pmmf_wave(), lane = pmmf_lane();
+  const int u = A.order[blockIdx.x];
+  const int o = A.off[u];
+  const int c = A.off[u + 1] - o;
+  const int ld = gd_stride(c);  // row stride of the cluster's (G, D) array
+  const int r = A.rcnt[u];      // rotations = retirements
+  const int rb = A.roff[u];
+  const int nw = (c + 31) / 32;
+  float2* __restrict__ GD = A.GD + A.gbase[u];
+  float2* R1 = rowbuf + 2 * (size_t)cmax;
+  float2* R2 = rowbuf + 3 * (size_t)cmax;
+
+  for (int j = tid; j < c; j += NT) {
+    const float2 dg = GD[(size_t)j * ld + j];
+    gdiag[j] = dg.x;
+    ddiag[j] = dg.y;
+    rgs[j] = inv_sqrt_pos(dg.x);
+    lgid[j] = A.gid[o + j];
+  }
+  for (int q = tid; q < nw; q += NT) {
+    const int rem = c - q * 32;
+    mask[q] = rem >= 32 ? 0xffffffffu : ((1u << rem) - 1u);
+  }
+  __syncthreads();
+  if (wv == 0 && r > 0) {  // first seed row, uniform over the active set; candidates for the second
+    const uint64_t h = pmmf_hash4(A.seed, PMMF_TAG_SEED_ROW, (uint64_t)A.p, (uint64_t)u, 0);
+    const int i0 = select_active(mask, nw, (int)pmmf_mulhi(h, (uint64_t)c));
+    if (lane == 0) sh_i = i0;
+    if (r > 1) {
+      const uint64_t h1 = pmmf_hash4(A.seed, PMMF_TAG_SEED_ROW, (uint64_t)A.p, (uint64_t)u, 1);
+      int cs[2];
+      select_activeN<2>(mask, nw, (int)pmmf_mulhi(h1, (uint64_t)(c - 1)), cs);
+      if (lane == 0) { sh_c[0] = cs[0]; sh_c[1] = cs[1]; }
+    }
+  }
+  __syncthreads();
+
+  // state of every wave: seed, the two candidates for the next seed, the previous T, and which
+  // per-wave winners the next merge takes
+  int i = r > 0 ? sh_i : 0;
+  int cc0 = r > 1 ? sh_c[0] : 0, cc1 = r > 1 ? sh_c[1] : 0;
+  int tq0 = -1, tq1 = -1, tq2 = -1;
+  int sel = 2;
+  // The control wave and the column waves run separate copies of the step loop (so that neither
+  // holds the other's registers); both pass the same two barriers per step.  Parts both take:
+  // the merge after barrier A (every thread forms the same partners) ...
+  auto merge = [&](int par, Cand& f1, Cand& f2) {
+    f1 = Cand{-1.f, INT_MAX};
+    f2 = Cand{-1.f, INT_MAX};
+#pragma unroll
+    for (int w = 1; w < NW; ++w) {
+      if (K == 3) merge2(f1, f2, red1[par][sel][w], red2[par][sel][w]);
+      else take<K>(f1, f2, red1[par][sel][w]);
+    }
+    if (sel < 2) {
+#pragma unroll
+      for (int a = 0; a < 3; ++a) take<K>(f1, f2, sh_tc[a]);
+    }
+  };
+  // ... and after barrier B the retiree, the next seed, the candidates for the seed after it and
+  // the pre-rotation entries of rows T at the next seed's column
+  auto after_b = [&](int s, int t0, int t1, int t2, const float2* R0, float (&o_)[9], int& e,
+                     int& nxt, int& aslot, int& nsel, float2 (&vn)[3]) {
+    const bool more = s + 1 < r;
+#pragma unroll
+    for (int a = 0; a < 9; ++a) o_[a] = sh_O[a];
+    e = sh_e;
+    nxt = more ? (cc0 < e ? cc0 : cc1) : -1;
+    aslot = nxt == t0 ? 0 : (nxt == t1 ? 1 : ((K == 3 && nxt == t2) ? 2 : -1));
+    nsel = aslot >= 0 ? 2 : (nxt == cc0 ? 0 : 1);
+    vn[0] = vn[1] = vn[2] = make_float2(0.f, 0.f);
+    if (more && aslot < 0) {
+      vn[0] = R0[nxt];
+      vn[1] = R1[nxt];
+      if (K == 3) vn[2] = R2[nxt];
+    }
+    if (s + 2 < r) {  // the candidates for the seed of step s+2, without this step's retiree
+      const int k0 = sh_k[0], k1 = sh_k[1], k2 = sh_k[2];
+      cc0 = k0 < e ? k0 : k1;
+      cc1 = k1 < e ? k1 : k2;
+    }
+  };
+
+  if (wv == 0) {
+    // ---------------------------------------------------------------- control wave
+    // G and D entries (t1, t2) and (t2, t1) of the next step, requested (or formed) after the
+    // previous barrier B when that step's partners were known then
+    bool pre = false;
+    float2 x12 = make_float2(0.f, 0.f), x21 = make_float2(0.f, 0.f);
+    for (int s = 0; s < r; ++s) {
+      const int par = s & 1;
+      const float2* R0 = rowbuf + (size_t)par * cmax;
+      const bool more = s + 1 < r;
+      __syncthreads();  // A
+      Cand f1, f2;
+      merge(par, f1, f2);
+      if (f1.j >= c || (K == 3 && f2.j >= c)) {  // impossible with >= k live indices
+        if (lane == 0) atomicOr(A.err, 1);
+        return;
+      }
+      const int t0 = i, t1 = f1.j, t2 = K == 3 ? f2.j : -1;
+      // an entry of a row outside T_{s-1} at a column in T_{s-1} may be stale until this step's
+      // column stores land: its transpose is taken instead
+      const int st1 = slot_of(t1, tq0, tq1, tq2), st2 = K == 3 ? slot_of(t2, tq0, tq1, tq2) : -1;
+      if (K == 3 && !pre) {
+        x12 = GD[(size_t)t1 * ld + t2];
+        x21 = GD[(size_t)t2 * ld + t1];
+      }
+      if (s + 2 < r) {
+        // next-seed rule: the rank-th active index after a retirement e is the rank-th one before
+        // it if that lies below e, else the (rank + 1)-th.  The seed of step s+2 follows two more
+        // retirements (steps s and s+1), so the rank-th to (rank + 2)-th indices are taken now;
+        // after this step two candidates remain, after the next one the seed.
+        const uint64_t h = pmmf_hash4(A.seed, PMMF_TAG_SEED_ROW, (uint64_t)A.p, (uint64_t)u,
+                                      (uint64_t)(s + 2));
+        int kn[3];
+        select_activeN<3>(mask, nw, (int)pmmf_mulhi(h, (uint64_t)(c - (s + 2))), kn);
+        if (lane == 0) { sh_k[0] = kn[0]; sh_k[1] = kn[1]; sh_k[2] = kn[2]; }
+      }
+      if (lane == 0) {
+        double g[3][3] = {}, d[3][3] = {}, O[3][3] = {};
+        g[0][0] = gdiag[t0];
+        d[0][0] = ddiag[t0];
+        g[1][1] = gdiag[t1];
+        d[1][1] = ddiag[t1];
+        const float2 s01 = R0[t1];
+        g[0][1] = g[1][0] = s01.x;
+        d[0][1] = d[1][0] = s01.y;
+        double margin = 3.0e38;
+        if (K == 3) {
+          g[2][2] = gdiag[t2];
+          d[2][2] = ddiag[t2];
+          const float2 s02 = R0[t2];
+          g[0][2] = g[2][0] = s02.x;
+          d[0][2] = d[2][0] = s02.y;
+          const bool fresh12 = pre || st1 >= 0 || st2 < 0, fresh21 = pre || st2 >= 0 || st1 < 0;
+          const float2 y12 = fresh12 ? x12 : x21, y21 = fresh21 ? x21 : x12;
+          const double g12 = 0.5 * ((double)y12.x + (double)y21.x);
+          const double d12 = 0.5 * ((double)y12.y + (double)y21.y);
+          g[1][2] = g[2][1] = g12;
+          d[1][2] = d[2][1] = d12;
+          double tm, em;
+          rot3_refined(g, O, tm, em);
+          margin = fmin(tm, em);
+        } else {
+          double cs, sn, ta;
+          rot2(g[0][0], g[0][1], g[1][1], cs, sn, ta);
+          O[0][0] = cs; O[0][1] = -sn; O[1][0] = sn; O[1][1] = cs;
+          margin = ta;
+        }
+        // rotated k x k blocks O g O^T and O d O^T
+        double gn[3][3] = {}, dn[3][3] = {};
+#pragma unroll
+        for (int a = 0; a < K; ++a)
+#pragma unroll
+          for (int b = 0; b < K; ++b) {
+            double sg = 0.0, sd = 0.0;
+#pragma unroll
+            for (int x = 0; x < K; ++x) {
+              double tg = 0.0, td = 0.0;
+#pragma unroll
+              for (int y = 0; y < K; ++y) { tg += g[x][y] * O[b][y]; td += d[x][y] * O[b][y]; }
+              sg += O[a][x] * tg;
+              sd += O[a][x] * td;
+            }
+            gn[a][b] = sg;
+            dn[a][b] = sd;
+          }
+        // eliminate the slot with the smallest off-diagonal norm (ties: later slot)
+        const double f0 = fmax(0.0, gn[0][0] - dn[0][0] * dn[0][0]);
+        const double fv1 = fmax(0.0, gn[1][1] - dn[1][1] * dn[1][1]);
+        const double fv2 = K == 3 ? fmax(0.0, gn[2][2] - dn[2][2] * dn[2][2]) : 1e300;
+        int es = fv1 <= f0 ? 1 : 0;
+        double fm = es == 1 ? fv1 : f0;
+        if (K == 3 && fv2 <= fm) { es = 2; fm = fv2; }
+        {  // second smallest, for the (diagnostic) elimination margin
+          const double hi01 = fmax(f0, fv1), lo01 = fmin(f0, fv1);
+          const double lo2 = K == 3 ? (fv2 <= lo01 ? lo01 : fmin(hi01, fv2)) : hi01;
+          const double lo1 = fmin(lo01, fv2);
+          margin = fmin(margin, lo2 > 0.0 ? (lo2 - lo1) / lo2 : 0.0);
+        }
+        const int e = es == 0 ? t0 : (es == 1 ? t1 : t2);
+        const int ta[3] = {t0, t1, t2};
+#pragma unroll
+        for (int a = 0; a < K; ++a) {
+          gdiag[ta[a]] = (float)gn[a][a];
+          ddiag[ta[a]] = (float)dn[a][a];
+          rgs[ta[a]] = inv_sqrt_pos((float)gn[a][a]);
+        }
+#pragma unroll
+        for (int a = 0; a < 9; ++a) { sh_O[a] = 0.f; sh_gn[a] = 0.f; sh_dn[a] = 0.f; }
+#pragma unroll
+        for (int a = 0; a < K; ++a)
+#pragma unroll
+          for (int b = 0; b < K; ++b) {
+            sh_O[a * 3 + b] = (float)O[a][b];
+            sh_gn[a * 3 + b] = (float)gn[a][b];
+            sh_dn[a * 3 + b] = (float)dn[a][b];
+          }
+        sh_e = e;
+        sh_mg = (float)margin;
+        sh_de = (float)(es == 0 ? dn[0][0] : (es == 1 ? dn[1][1] : dn[2][2]));
+        sh_lit = 2.0 * fm;
+      }
+      __syncthreads();  // B
+
+      float o_[9];
+      float2 vn[3];
+      int e, nxt, aslot, nsel;
+      after_b(s, t0, t1, t2, R0, o_, e, nxt, aslot, nsel, vn);
+      const int Tt[3] = {t0, t1, t2};
+      {  // the next seed row's entries at T (a column of T other than the retiree), lane a
+        Cand tc{-1.f, INT_MAX};
+#pragma unroll
+        for (int a = 0; a < K; ++a)
+          if (lane == a && more && aslot < 0 && Tt[a] != e)
+            tc = Cand{partner_score(rot_entry<K>(o_, a, vn).x, rgs[Tt[a]]), Tt[a]};
+        if (lane < 3) sh_tc[lane] = tc;
+      }
+      // The next step's partners are known now unless its seed is in T (it is then scored in
+      // full by the column waves): merge as after barrier A and request G_{t1 t2} at once, so
+      // its latency passes during the column waves' half of the step.  An entry in a row or
+      // column of this step's T is formed from the pre-rotation rows instead (its stores are
+      // pending); every other entry is current.
+      pre = false;
+      if (K == 3 && more && nsel < 2) {
+        const int sv = sel;
+        sel = nsel;
+        Cand g1, g2;
+        merge(par ^ 1, g1, g2);
+        sel = sv;
+        const int n1 = g1.j, n2 = g2.j;
+        if (n1 < c && n2 < c) {
+          pre = true;
+          const int a1 = slot_of(n1, t0, t1, t2), a2 = slot_of(n2, t0, t1, t2);
+          if (a1 < 0 && a2 < 0) {
+            x12 = GD[(size_t)n1 * ld + n2];
+            x21 = GD[(size_t)n2 * ld + n1];
+          } else if (a1 >= 0 && a2 >= 0) {
+            x12 = make_float2(sh_gn[a1 * 3 + a2], sh_dn[a1 * 3 + a2]);
+            x21 = make_float2(sh_gn[a2 * 3 + a1], sh_dn[a2 * 3 + a1]);
+          } else {
+            const int a = a1 >= 0 ? a1 : a2, x = a1 >= 0 ? n2 : n1;
+            const float2 v[3] = {R0[x], R1[x], R2[x]};
+            x12 = x21 = pick3(a, rot_entry<K>(o_, 0, v), rot_entry<K>(o_, 1, v),
+                              rot_entry<K>(o_, 2, v));
+          }
+        }
+      }
+      if (lane == 0) mask[e >> 5] &= ~(1u << (e & 31));
+      // the rotated k x k block and the rotation log, lane by lane; lanes past the last entry
+      // repeat it, so the stores need no branch and the wait for the entries above counts them
+      // exactly
+      {
+        const int kb = min(lane, K * K - 1), ka = kb / K, kc = kb % K;
+        GD[(size_t)pick3(ka, t0, t1, t2) * ld + pick3(kc, t0, t1, t2)] =
+            make_float2(sh_gn[ka * 3 + kc], sh_dn[ka * 3 + kc]);
+        const int64_t ridx = A.rot0 + rb + s;
+        const int l9 = min(lane, 8), l3 = min(lane, 2);
+        A.rot_o[ridx * 9 + l9] = sh_O[l9];
+        const int tl = l3 < K ? pick3(l3, t0, t1, t2) : -1;
+        A.rot_loc[ridx * 3 + l3] = tl;
+        A.rot_gid[ridx * 3 + l3] = tl >= 0 ? lgid[tl] : -1;
+        A.rot_ret[ridx] = lgid[e];
+        A.rot_margin[ridx] = sh_mg;
+        A.rot_lit[ridx] = sh_lit;
+        A.hdiag[lgid[e]] = sh_de;
+        A.retflag[o + e] = 1;
+      }
+      tq0 = t0;
+      tq1 = t1;
+      tq2 = t2;
+      i = nxt;
+      sel = nsel;
+    }
+    return;
+  }
+
+  // ------------------------------------------------------------------ column waves
+  const int ct = tid - PMMF_WAVE;
+  int jl[PER];           // own columns clamped into the cluster, for address forming
+  float rg[PER];         // 1 / sqrt(G_jj) of the own columns
+  uint32_t act = 0;      // bit q: own column q active
+  float2 cur[PER], c0r[PER], c1r[PER], p1[PER], p2[PER];
+  float2 cst[3][PER];    // column stores of the previous step
+  uint64_t cmask = 0;    // which of them are real
+#pragma unroll
+  for (int q = 0; q < PER; ++q) {
+    const int j = ct + q * NC;
+    const bool in = j < c;
+    jl[q] = min(j, c - 1);
+    act |= (uint32_t)in << q;
+    rg[q] = in ? rgs[j] : 0.f;
+    cur[q] = (in && r > 0) ? GD[(size_t)i * ld + j] : make_float2(0.f, 0.f);
+    c0r[q] = c1r[q] = p1[q] = p2[q] = make_float2(0.f, 0.f);
+#pragma unroll
+    for (int a = 0; a < 3; ++a) cst[a][q] = make_float2(0.f, 0.f);
+  }
+  // full scoring of the seed row held in cur (seed x; ex is skipped too) into slot 2 of parity par
+  auto score_full = [&](int par, int x, int ex) {
+    Cand b1{-1.f, INT_MAX}, b2{-1.f, INT_MAX};
+#pragma unroll
+    for (int q = 0; q < PER; ++q) {
+      const int j = ct + q * NC;
+      if (((act >> q) & 1u) && j != x && j != ex)
+        take<K>(b1, b2, Cand{partner_score(cur[q].x, rg[q]), j});
+    }
+    wave_top<K>(b1, b2);
+    if (lane == 0) { red1[par][2][wv] = b1; red2[par][2][wv] = b2; }
+  };
+  if (r > 0) {
+#pragma unroll
+    for (int q = 0; q < PER; ++q) {
+      const int j = ct + q * NC;
+      if (j < c) rowbuf[j] = cur[q];
+    }
+    score_full(0, i, -1);
+  }
+
+  for (int s = 0; s < r; ++s) {
+    const int par = s & 1;
+    const float2* R0 = rowbuf + (size_t)par * cmax;
+    const bool more = s + 1 < r;
+    __syncthreads();  // A
+    Cand f1, f2;
+    merge(par, f1, f2);
+    if (f1.j >= c || (K == 3 && f2.j >= c)) return;  // reported by the control wave
+    const int t0 = i, t1 = f1.j, t2 = K == 3 ? f2.j : -1;
+    const int st1 = slot_of(t1, tq0, tq1, tq2), st2 = K == 3 ? slot_of(t2, tq0, tq1, tq2) : -1;
+    // the next seed is cc0 if cc0 lies below this step's retiree e (one of T), else cc1: only the
+    // rows that can be chosen are fetched and scored
+    const int tmin = K == 3 ? min(t0, min(t1, t2)) : min(t0, t1);
+    const int tmax = K == 3 ? max(t0, max(t1, t2)) : max(t0, t1);
+    const bool need0 = more && cc0 < tmax, need1 = more && cc0 >= tmin;
+
+    // partner rows (pre-rotation), then the candidate rows of the next seed, read the same way
+#pragma unroll
+    for (int q = 0; q < PER; ++q) {
+      const int j = ct + q * NC;
+      const int sj = slot_of(j, tq0, tq1, tq2);
+      const uint32_t jq = (uint32_t)jl[q];
+      p1[q] = GD[(sj >= 0 && st1 < 0) ? (uint32_t)(j * ld + t1) : (uint32_t)(t1 * ld) + jq];
+      if (K == 3)
+        p2[q] = GD[(sj >= 0 && st2 < 0) ? (uint32_t)(j * ld + t2) : (uint32_t)(t2 * ld) + jq];
+    }
+    if (need0) {
+      const int sc0 = slot_of(cc0, tq0, tq1, tq2);
+#pragma unroll
+      for (int q = 0; q < PER; ++q) {
+        const int j = ct + q * NC;
+        const int sj = slot_of(j, tq0, tq1, tq2);
+        c0r[q] = GD[(sj >= 0 && sc0 < 0) ? (uint32_t)(j * ld + cc0) : (uint32_t)(cc0 * ld + jl[q])];
+      }
+    }
+    if (need1) {
+      const int sc1 = slot_of(cc1, tq0, tq1, tq2);
+#pragma unroll
+      for (int q = 0; q < PER; ++q) {
+        const int j = ct + q * NC;
+        const int sj = slot_of(j, tq0, tq1, tq2);
+        c1r[q] = GD[(sj >= 0 && sc1 < 0) ? (uint32_t)(j * ld + cc1) : (uint32_t)(cc1 * ld + jl[q])];
+      }
+    }
+    // pre-rotation partner rows, for re-forming the next seed row's entries at T
+#pragma unroll
+    for (int q = 0; q < PER; ++q) {
+      const int j = ct + q * NC;
+      if (j < c) {
+        R1[j] = p1[q];
+        if (K == 3) R2[j] = p2[q];
+      }
+    }
+    // the candidate rows that can become the next seed, scored outside T (for the merge of
+    // step s+1)
+    if (need0 || need1) {
+      Cand a1{-1.f, INT_MAX}, a2{-1.f, INT_MAX}, b1{-1.f, INT_MAX}, b2{-1.f, INT_MAX};
+#pragma unroll
+      for (int q = 0; q < PER; ++q) {
+        const int j = ct + q * NC;
+        const bool ok = ((act >> q) & 1u) && slot_of(j, t0, t1, t2) < 0;
+        if (need0 && ok && j != cc0) take<K>(a1, a2, Cand{partner_score(c0r[q].x, rg[q]), j});
+        if (need1 && ok && j != cc1) take<K>(b1, b2, Cand{partner_score(c1r[q].x, rg[q]), j});
+      }
+      const int np = par ^ 1;
+      if (need0) {
+        wave_top<K>(a1, a2);
+        if (lane == 0) { red1[np][0][wv] = a1; red2[np][0][wv] = a2; }
+      }
+      if (need1) {
+        wave_top<K>(b1, b2);
+        if (lane == 0) { red1[np][1][wv] = b1; red2[np][1][wv] = b2; }
+      }
+    }
+    // the previous step's column stores (the entries that are not zero), last: nothing before
+    // barrier B waits for them, and the loads above take the transposes of these entries
+#pragma unroll
+    for (int q = 0; q < PER; ++q) {
+      const int j = ct + q * NC;
+#pragma unroll
+      for (int a = 0; a < K; ++a) {
+        const int ta = a == 0 ? tq0 : (a == 1 ? tq1 : tq2);
+        if ((cmask >> (a * PER + q)) & 1ull) GD[(uint32_t)(j * ld + ta)] = cst[a][q];
+      }
+    }
+    __syncthreads();  // B
+
+    float o_[9];
+    float2 vn[3];
+    int e, nxt, aslot, nsel;
+    after_b(s, t0, t1, t2, R0, o_, e, nxt, aslot, nsel, vn);
+    const int Tt[3] = {t0, t1, t2};
+    float2 nrow[PER];
+    cmask = 0;
+#pragma unroll
+    for (int q = 0; q < PER; ++q) {
+      const int j = ct + q * NC;
+      const int bj = slot_of(j, t0, t1, t2);
+      if (bj >= 0) rg[q] = rgs[j];                  // new G_jj of a column in T
+      if (j == e) act &= ~(1u << q);                // this step's retiree
+      nrow[q] = nsel == 0 ? c0r[q] : c1r[q];
+      const bool in = j < c && bj < 0;
+      const bool a_now = in && ((act >> q) & 1u);
+      const float2 v[3] = {cur[q], p1[q], p2[q]};
+      // rows T: O applied to the pre-rotation rows (a column in T or beyond the cluster writes
+      // into the dead column of the retiree; a retired column's entry is dead too)
+      float2 nv[3] = {make_float2(0.f, 0.f), make_float2(0.f, 0.f), make_float2(0.f, 0.f)};
+#pragma unroll
+      for (int a = 0; a < K; ++a) {
+        nv[a] = rot_entry<K>(o_, a, v);
+        GD[(uint32_t)(Tt[a] * ld) + (uint32_t)(in ? j : e)] = nv[a];
+        cst[a][q] = nv[a];
+        const uint32_t m = __float_as_uint(nv[a].x) | __float_as_uint(nv[a].y) |
+                           __float_as_uint(v[a].x) | __float_as_uint(v[a].y);
+        cmask |= (uint64_t)(a_now && (m << 1) != 0u) << (a * PER + q);
+      }
+      // the next seed row at column j
+      if (more) {
+        if (bj >= 0) {
+          nrow[q] = aslot >= 0 ? make_float2(sh_gn[aslot * 3 + bj], sh_dn[aslot * 3 + bj])
+                               : pick3(bj, rot_entry<K>(o_, 0, vn), rot_entry<K>(o_, 1, vn),
+                                       rot_entry<K>(o_, 2, vn));
+        } else if (aslot >= 0) {
+          nrow[q] = pick3(aslot, nv[0], nv[1], nv[2]);
+        }
+      }
+    }
+#pragma unroll
+    for (int q = 0; q < PER; ++q) cur[q] = nrow[q];
+    if (more) {
+      float2* R0n = rowbuf + (size_t)(par ^ 1) * cmax;
+#pragma unroll
+      for (int q = 0; q < PER; ++q) {
+        const int j = ct + q * NC;
+        if (j < c) R0n[j] = cur[q];
+      }
+      if (nsel == 2) score_full(par ^ 1, nxt, e);
+    }
+    tq0 = t0;
+    tq1 = t1;
+    tq2 = t2;
+    i = nxt;
+    sel = nsel;
+  }
+}
+
+template <int NT, int PER, int K>
+static hipError_t search_launch(const FindArgs& a, int m, int cmax, hipStream_t s) {
+  const size_t lds = find_lds_bytes(cmax) + (size_t)cmax * sizeof(float);
+  if (lds > 64 * 1024) {
+    hipError_t e = hipFuncSetAttribute((const void*)&k_search<NT, PER, K>,
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e != hipSuccess) return e;
+  }
+  k_search<NT, PER, K><<<m, NT, lds, s>>>(a, cmax);
+  return hipGetLastError();
+}
+template <int PER>
+static hipError_t search_launch_k(const FindArgs& a, int m, int cmax, hipStream_t s) {
+  return a.k == 3 ? search_launch<512, PER, 3>(a, m, cmax, s)
+                  : search_launch<512, PER, 2>(a, m, cmax, s);
 }
 
 // ------------------------------------------------------------------------------------------
@@ -1561,6 +2240,7 @@ __global__ void __launch_bounds__(256) k_find_bf16(FindArgs A, int cmax) {
   const int u = A.order[blockIdx.x];
   const int o = A.off[u];
   const int c = A.off[u + 1] - o;
+  const int ld = gd_stride(c);  // row stride of the cluster's (G, D) array
   const int r = A.rcnt[u];
   const int rb = A.roff[u];
   const int nw = (c + 31) / 32;
@@ -1573,7 +2253,7 @@ __global__ void __launch_bounds__(256) k_find_bf16(FindArgs A, int cmax) {
   const float gamma = BF16_SAFETY * (0.0078125f + (float)Ru * 5.9604645e-8f);
 
   for (int j = tid; j < c; j += NT) {
-    const float2 dg = GD[(size_t)j * c + j];
+    const float2 dg = GD[(size_t)j * ld + j];
     gdiag[j] = dg.x;
     ddiag[j] = dg.y;
     lgid[j] = A.gid[o + j];
@@ -1595,7 +2275,7 @@ __global__ void __launch_bounds__(256) k_find_bf16(FindArgs A, int cmax) {
 #pragma unroll
   for (int q = 0; q < PER; ++q) {
     const int j = tid + q * NT;
-    cur[q] = (r > 0 && j < c) ? GD[(size_t)i * c + j] : make_float2(0.f, 0.f);
+    cur[q] = (r > 0 && j < c) ? GD[(size_t)i * ld + j] : make_float2(0.f, 0.f);
   }
   unsigned long long n_cut = 0, n_scored = 0;
 
@@ -1729,8 +2409,8 @@ __global__ void __launch_bounds__(256) k_find_bf16(FindArgs A, int cmax) {
       const int j = tid + q * NT;
       p1[q] = p2[q] = make_float2(0.f, 0.f);
       if (j < c) {
-        p1[q] = GD[(size_t)t1 * c + j];
-        if (kk == 3) p2[q] = GD[(size_t)t2 * c + j];
+        p1[q] = GD[(size_t)t1 * ld + j];
+        if (kk == 3) p2[q] = GD[(size_t)t2 * ld + j];
       }
     }
     float g12 = 0.f;
@@ -1749,7 +2429,7 @@ __global__ void __launch_bounds__(256) k_find_bf16(FindArgs A, int cmax) {
         g[0][2] = g[2][0] = d2;
         d[0][2] = d[2][0] = R0[t2].y;
         g[1][2] = g[2][1] = g12;
-        const float2 a12 = GD[(size_t)t1 * c + t2], a21 = GD[(size_t)t2 * c + t1];
+        const float2 a12 = GD[(size_t)t1 * ld + t2], a21 = GD[(size_t)t2 * ld + t1];
         d[1][2] = d[2][1] = 0.5 * ((double)a12.y + (double)a21.y);
       }
       double margin = 3.0e38;
@@ -1857,7 +2537,7 @@ __global__ void __launch_bounds__(256) k_find_bf16(FindArgs A, int cmax) {
     for (int q = 0; q < PER; ++q) {
       const int j = tid + q * NT;
       nrow[q] = make_float2(0.f, 0.f);
-      if (more && aslot < 0 && j < c) nrow[q] = GD[(size_t)nxt * c + j];
+      if (more && aslot < 0 && j < c) nrow[q] = GD[(size_t)nxt * ld + j];
     }
     float2 vn[3] = {make_float2(0.f, 0.f), make_float2(0.f, 0.f), make_float2(0.f, 0.f)};
     if (more && aslot < 0) {
@@ -1869,7 +2549,7 @@ __global__ void __launch_bounds__(256) k_find_bf16(FindArgs A, int cmax) {
     const int Tt[3] = {t0, t1, t2};
     if (tid < kk * kk) {
       const int a = tid / kk, b = tid % kk;
-      GD[(size_t)Tt[a] * c + Tt[b]] = make_float2(sh_gn[a * 3 + b], sh_dn[a * 3 + b]);
+      GD[(size_t)Tt[a] * ld + Tt[b]] = make_float2(sh_gn[a * 3 + b], sh_dn[a * 3 + b]);
     }
     // slab columns T right-rotated: S[:, T] <- S[:, T] O^T
     for (int rr = tid; rr < Ru; rr += NT) {
@@ -1901,9 +2581,9 @@ __global__ void __launch_bounds__(256) k_find_bf16(FindArgs A, int cmax) {
 #pragma unroll
       for (int a = 0; a < K; ++a) {
         const float2 nv = rot_entry<K>(o_, a, v);
-        GD[(size_t)Tt[a] * c + j] = nv;
+        GD[(size_t)Tt[a] * ld + j] = nv;
         if (nv.x != 0.f || nv.y != 0.f || v[a].x != 0.f || v[a].y != 0.f)
-          GD[(size_t)j * c + Tt[a]] = nv;
+          GD[(size_t)j * ld + Tt[a]] = nv;
         if (a == aslot) nrow[q] = nv;
       }
     }
@@ -1955,6 +2635,14 @@ size_t find_lds_bytes(int cmax) {
 
 hipError_t launch_find(const FindArgs& a, int m, int cmax, int nt, hipStream_t s) {
   if (m == 0) return hipSuccess;
+  if (a.elims != 2) {  // one retirement per rotation: control wave + 7 column waves
+    if (cmax <= 448) return search_launch_k<1>(a, m, cmax, s);
+    if (cmax <= 896) return search_launch_k<2>(a, m, cmax, s);
+    if (cmax <= 1344) return search_launch_k<3>(a, m, cmax, s);
+    if (cmax <= 2240) return search_launch_k<5>(a, m, cmax, s);
+    if (cmax <= 3072) return search_launch_k<7>(a, m, cmax, s);
+    return hipErrorInvalidValue;
+  }
   const size_t lds = find_lds_bytes(cmax);
   if (nt == 512) {
     if (cmax <= 512) return find_launch_k<512, 1>(a, m, cmax, lds, s);

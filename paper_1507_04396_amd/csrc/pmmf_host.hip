@@ -507,7 +507,7 @@ void build_stage_geometry(StageDev& sd, const SchedStage& sc, int64_t rot_base, 
     sd.off_h[u + 1] = sd.off_h[u] + sc.sizes[u];
     sd.roff_h[u + 1] = sd.roff_h[u] + sc.rcnt[u];
     sd.gbase_h[u] = gb;
-    gb += (int64_t)sc.sizes[u] * sc.sizes[u];
+    gb += (int64_t)sc.sizes[u] * pmmf::gd_stride(sc.sizes[u]);
     sd.cmax = std::max(sd.cmax, sc.sizes[u]);
     sd.rmax = std::max(sd.rmax, sc.rcnt[u]);
   }
@@ -868,9 +868,9 @@ extern "C" int mmf_factor(int64_t n, int64_t nnz, const int64_t* d_rowptr, const
   int64_t pool = 1;
   for (auto& sc : sched) {
     int64_t g = 0;
-    for (int32_t c : sc.sizes) g += (int64_t)c * c;
+    for (int32_t c : sc.sizes) g += (int64_t)c * pmmf::gd_stride(c);
     // sizes chosen during the factorization: every cluster has at most cluster_max positions
-    if (sc.sizes.empty()) g = sc.size * std::min<int64_t>(sc.size, p->cluster_max);
+    if (sc.sizes.empty()) g = sc.size * (std::min<int64_t>(sc.size, p->cluster_max) + 1);
     pool = std::max(pool, g);
   }
   DBuf GD, Q, retflag, keep, scan, cnt, loss_row, overflow, gid_cur, dense_buf;
