@@ -371,10 +371,10 @@ def main():
     # ----------------------------------------------------------------- roofline (dominant kernel)
     find_launches = len(stages)
     find_gbs = fbytes / (find_ms * 1e-3) / 1e9
-    roofline = {"kernel": "k_find (greedy rotation search, one launch per stage)",
+    roofline = {"kernel": "k_search (greedy rotation search, one launch per stage)",
                 "bound": "hbm", "achieved": round(find_gbs, 2), "peak": HBM_PEAK_GBS,
                 "unit": "GB/s", "frac": round(find_gbs / HBM_PEAK_GBS, 5),
-                "traffic": measured_traffic("k_find", "knn3d_n262144"),
+                "traffic": measured_traffic("k_search", "knn3d_n262144"),
                 "launches": find_launches,
                 "avg_launch_ms": round(find_ms / max(1, find_launches), 4),
                 "algorithmic_bytes_per_launch": int(fbytes / max(1, find_launches)),

@@ -22,7 +22,7 @@ struct FindArgs {
   const int32_t* off;        // [m+1] cluster offsets (positions)
   const int32_t* rcnt;       // [m] log entries (retired indices) of each cluster
   const int32_t* roff;       // [m+1] first stage-local rotation of each cluster
-  const int64_t* gbase;      // [m] offset of each cluster's c x c blocks in the pools
+  const int64_t* gbase;      // [m] offset of each cluster's (G, D) array in the pool
   float2* GD;                // (Gram, diagonal block) pool, interleaved
   const int32_t* gid;        // [S] global id of each position
   int64_t rot0;              // global index of the stage's first rotation
@@ -81,15 +81,19 @@ hipError_t launch_levelize(int m, int k, const int32_t* off, const int32_t* rcnt
                            const float* rot_o, int lvl_stride, int32_t* lvl_ptr, int32_t* depth,
                            int32_t* sw_loc, float* sw_o, int32_t* sw_idx, float* theta, int cmax,
                            hipStream_t s);
-hipError_t launch_build_q(int m, int k, const int32_t* off, const int64_t* gbase,
+// the clusters' accumulated rotations from the levelized sweep log: column j of Qbar_u (row j of
+// Qbar^T, rows ascending) into the c_u scratch slots at gbase[u] + j c_u of sci/scv, its count to
+// cnt[j]; launch_qt_compact packs them into the CSR of Qbar^T with row pointers rp
+hipError_t launch_qsparse(int m, int k, const int32_t* off, const int64_t* gbase,
                           const int32_t* lvl_ptr, int lvl_stride, const int32_t* depth,
-                          const int32_t* sw_loc, const float* sw_o, float* Q, int cmax,
-                          hipStream_t s);
-hipError_t launch_qbar_count(int S, const int32_t* off, const int32_t* cl_of,
-                             const int64_t* gbase, const float* Q, int32_t* cnt, hipStream_t s);
-hipError_t launch_qbar_fill(int S, const int32_t* off, const int32_t* cl_of,
-                            const int64_t* gbase, const float* Q, const int64_t* rp, int32_t* ci,
-                            float* cv, hipStream_t s);
+                          const int32_t* sw_loc, const float* sw_o, int32_t* cnt, int32_t* sci,
+                          float* scv, int cmax, hipStream_t s);
+hipError_t launch_qt_compact(int S, const int32_t* off, const int32_t* cl_of,
+                             const int64_t* gbase, const int32_t* sci, const float* scv,
+                             const int64_t* rp, int32_t* qci, float* qcv, hipStream_t s);
+// each row of a CSR (distinct columns) in ascending column order, out of place
+hipError_t launch_sort_rows(int n, const int64_t* rp, const int32_t* ci, const float* cv,
+                            int32_t* oci, float* ocv, hipStream_t s);
 // W = M Qbar^T; with fill = 1 it also records where each run of row x (the runs of the run table
 // run_ptr of M) starts in W's staging row: wrs[run_ptr[x] + r]
 hipError_t launch_right(int S, int fill, const int64_t* rp, const int32_t* ci, const float* cv,

@@ -142,7 +142,8 @@ __global__ void __launch_bounds__(256) k_gram(int S, const int64_t* __restrict__
   // lanes past a segment's end (so every lane adds unconditionally and no two lanes of one
   // chunk touch the same slot)
   float* acc = lds_f + (size_t)w * (cmax + PMMF_WAVE);
-  const int a = blockIdx.x * wpb + w;
+  // the positions of a cluster read the same row segments: keep them on one XCD (one L2)
+  const int a = pmmf_xcd_block(blockIdx.x, gridDim.x) * wpb + w;
   if (a >= S) return;
   const int u = cl_of[a];
   const int o = off[u];
@@ -1158,7 +1159,7 @@ __device__ inline float2 rot_entry(const float* o, int a, const float2* v) {
 
 // The cluster's state lives in HBM as a dense c x c array GD (Gram and diagonal block of the
 // active matrix, interleaved so one 8-byte access moves both); the accumulated rotation Qbar is
-// rebuilt from the log afterwards (k_build_q).
+// rebuilt from the log afterwards (k_qsparse).
 // Each thread owns the columns j = tid + q NT (q < PER) and keeps its slice of the rows it needs
 // in registers.  A step has two barriers:
 //   A  after the partner argmax;
@@ -2660,22 +2661,29 @@ hipError_t launch_find(const FindArgs& a, int m, int cmax, int nt, hipStream_t s
 }
 
 // ------------------------------------------------------------------------------------------
-// Dense accumulated rotation of each cluster, Qbar_u = O_r ... O_1 (row-major c x c in the pool),
-// rebuilt from the stage's sweep log: one workgroup per (cluster, 8-column slice) holds the slice
-// of the identity in LDS and applies the rotations level by level (a level's rotations touch
-// disjoint rows); x[T] <- O x[T] on each column of the slice.
+// Accumulated rotation of each cluster, Qbar_u = O_r ... O_1, rebuilt from the stage's sweep log:
+// one workgroup per (cluster, 8-column slice) holds the slice of the identity in LDS and applies
+// the rotations level by level (a level's rotations touch disjoint rows); x[T] <- O x[T] on each
+// column of the slice.  Only the nonzeros leave the workgroup: column j of Qbar_u (row j of
+// Qbar^T, rows ascending) goes to its own c_u slots of a scratch pool at gbase[u] + j c_u, with
+// its count; k_qt_compact then packs the columns into the CSR of Qbar^T.
 constexpr int BQ_W = 8;
 template <int K>
-__global__ void __launch_bounds__(256) k_build_q(const int32_t* __restrict__ off,
+__global__ void __launch_bounds__(256) k_qsparse(const int32_t* __restrict__ off,
                                                  const int64_t* __restrict__ gbase,
                                                  const int32_t* __restrict__ lvl_ptr,
                                                  int lvl_stride, const int32_t* __restrict__ depth,
                                                  const int32_t* __restrict__ sw_loc,
                                                  const float* __restrict__ sw_o,
-                                                 float* __restrict__ Q) {
+                                                 int32_t* __restrict__ cnt,
+                                                 int32_t* __restrict__ sci,
+                                                 float* __restrict__ scv) {
   extern __shared__ float tile[];  // [c][BQ_W]
+  constexpr int NWV = 256 / PMMF_WAVE;
+  __shared__ int part[NWV][BQ_W];
   const int u = blockIdx.y;
-  const int c = off[u + 1] - off[u];
+  const int o = off[u];
+  const int c = off[u + 1] - o;
   const int col0 = blockIdx.x * BQ_W;
   if (col0 >= c) return;
   const int tid = threadIdx.x;
@@ -2697,46 +2705,134 @@ __global__ void __launch_bounds__(256) k_build_q(const int32_t* __restrict__ off
         id[a] = sw_loc[(size_t)rr * K + a];
         x[a] = tile[id[a] * BQ_W + w];
       }
-      const float* o = sw_o + (size_t)rr * K * K;
+      const float* om = sw_o + (size_t)rr * K * K;
 #pragma unroll
       for (int a = 0; a < K; ++a) {
         float acc = 0.f;
 #pragma unroll
-        for (int b = 0; b < K; ++b) acc = fmaf(o[a * K + b], x[b], acc);
+        for (int b = 0; b < K; ++b) acc = fmaf(om[a * K + b], x[b], acc);
         tile[id[a] * BQ_W + w] = acc;
       }
     }
     __syncthreads();
   }
-  float* Qu = Q + gbase[u];
-  for (int q = tid; q < c * BQ_W; q += blockDim.x) {
-    const int row = q / BQ_W, w = q % BQ_W;
-    if (col0 + w < c) Qu[(size_t)row * c + col0 + w] = tile[q];
+  // each thread takes a contiguous block of rows; per column, the nonzeros of the earlier blocks
+  // (a scan over the waves and their lanes) place its own, so each column's rows ascend
+  const int rpt = (c + blockDim.x - 1) / blockDim.x;
+  const int r0 = min(c, tid * rpt), r1 = min(c, r0 + rpt);
+  const int wv = tid / PMMF_WAVE, lane = pmmf_lane();
+  int ex[BQ_W];
+#pragma unroll
+  for (int w = 0; w < BQ_W; ++w) {
+    int n = 0;
+    for (int row = r0; row < r1; ++row) n += tile[row * BQ_W + w] != 0.f;
+    const int incl = pmmf_wave_incl_scan_dpp(n);
+    ex[w] = incl - n;
+    if (lane == PMMF_WAVE - 1) part[wv][w] = incl;
+  }
+  __syncthreads();
+#pragma unroll
+  for (int w = 0; w < BQ_W; ++w) {
+    if (col0 + w >= c) continue;
+    int before = 0, total = 0;
+#pragma unroll
+    for (int v = 0; v < NWV; ++v) {
+      before += v < wv ? part[v][w] : 0;
+      total += part[v][w];
+    }
+    if (tid == 0) cnt[o + col0 + w] = total;
+    const size_t cb = (size_t)gbase[u] + (size_t)(col0 + w) * c;
+    int pos = before + ex[w];
+    for (int row = r0; row < r1; ++row) {
+      const float v = tile[row * BQ_W + w];
+      if (v != 0.f) {
+        sci[cb + pos] = o + row;
+        scv[cb + pos] = v;
+        ++pos;
+      }
+    }
   }
 }
 
-hipError_t launch_build_q(int m, int k, const int32_t* off, const int64_t* gbase,
+hipError_t launch_qsparse(int m, int k, const int32_t* off, const int64_t* gbase,
                           const int32_t* lvl_ptr, int lvl_stride, const int32_t* depth,
-                          const int32_t* sw_loc, const float* sw_o, float* Q, int cmax,
-                          hipStream_t s) {
+                          const int32_t* sw_loc, const float* sw_o, int32_t* cnt, int32_t* sci,
+                          float* scv, int cmax, hipStream_t s) {
   if (m == 0) return hipSuccess;
   const size_t lds = (size_t)cmax * BQ_W * sizeof(float);
   dim3 grid((unsigned)((cmax + BQ_W - 1) / BQ_W), (unsigned)m);
-  if (k == 3) {
+  auto go = [&](auto kern) -> hipError_t {
     if (lds > 64 * 1024) {
-      hipError_t e = hipFuncSetAttribute((const void*)&k_build_q<3>,
+      hipError_t e = hipFuncSetAttribute((const void*)kern,
                                          hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
       if (e != hipSuccess) return e;
     }
-    k_build_q<3><<<grid, 256, lds, s>>>(off, gbase, lvl_ptr, lvl_stride, depth, sw_loc, sw_o, Q);
-  } else {
-    if (lds > 64 * 1024) {
-      hipError_t e = hipFuncSetAttribute((const void*)&k_build_q<2>,
-                                         hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-      if (e != hipSuccess) return e;
-    }
-    k_build_q<2><<<grid, 256, lds, s>>>(off, gbase, lvl_ptr, lvl_stride, depth, sw_loc, sw_o, Q);
+    kern<<<grid, 256, lds, s>>>(off, gbase, lvl_ptr, lvl_stride, depth, sw_loc, sw_o, cnt, sci,
+                                scv);
+    return hipGetLastError();
+  };
+  return k == 3 ? go(&k_qsparse<3>) : go(&k_qsparse<2>);
+}
+
+// Packs the columns left by k_qsparse into the CSR of Qbar^T (row pointers rp from the scan of
+// their counts): one wave per position j.
+__global__ void k_qt_compact(int S, const int32_t* __restrict__ off,
+                             const int32_t* __restrict__ cl_of, const int64_t* __restrict__ gbase,
+                             const int32_t* __restrict__ sci, const float* __restrict__ scv,
+                             const int64_t* __restrict__ rp, int32_t* __restrict__ qci,
+                             float* __restrict__ qcv) {
+  const int j = blockIdx.x * (blockDim.x / PMMF_WAVE) + pmmf_wave();
+  if (j >= S) return;
+  const int u = cl_of[j];
+  const int o = off[u], c = off[u + 1] - o;
+  const size_t cb = (size_t)gbase[u] + (size_t)(j - o) * c;
+  const int64_t q0 = rp[j];
+  const int n = (int)(rp[j + 1] - q0);
+  for (int t = pmmf_lane(); t < n; t += PMMF_WAVE) {
+    qci[q0 + t] = sci[cb + t];
+    qcv[q0 + t] = scv[cb + t];
   }
+}
+
+hipError_t launch_qt_compact(int S, const int32_t* off, const int32_t* cl_of,
+                             const int64_t* gbase, const int32_t* sci, const float* scv,
+                             const int64_t* rp, int32_t* qci, float* qcv, hipStream_t s) {
+  if (S == 0) return hipSuccess;
+  k_qt_compact<<<(S + 3) / 4, 256, 0, s>>>(S, off, cl_of, gbase, sci, scv, rp, qci, qcv);
+  return hipGetLastError();
+}
+
+// Rows of a CSR put in ascending column order (out of place): one wave per row, each entry's rank
+// among its row's columns (distinct) is its place.
+__global__ void k_sort_rows(int n, const int64_t* __restrict__ rp, const int32_t* __restrict__ ci,
+                            const float* __restrict__ cv, int32_t* __restrict__ oci,
+                            float* __restrict__ ocv) {
+  const int r = blockIdx.x * (blockDim.x / PMMF_WAVE) + pmmf_wave();
+  if (r >= n) return;
+  const int lane = pmmf_lane();
+  const int64_t base = rp[r];
+  const int len = (int)(rp[r + 1] - base);
+  for (int i0 = 0; i0 < len; i0 += PMMF_WAVE) {
+    const int i = i0 + lane;
+    const int key = i < len ? ci[base + i] : INT_MAX;
+    const float val = i < len ? cv[base + i] : 0.f;
+    int rank = 0;
+    for (int j0 = 0; j0 < len; j0 += PMMF_WAVE) {
+      const int kj = j0 + lane < len ? ci[base + j0 + lane] : INT_MAX;
+      const int m = min(PMMF_WAVE, len - j0);
+      for (int l = 0; l < m; ++l) rank += __shfl(kj, l) < key;
+    }
+    if (i < len) {
+      oci[base + rank] = key;
+      ocv[base + rank] = val;
+    }
+  }
+}
+
+hipError_t launch_sort_rows(int n, const int64_t* rp, const int32_t* ci, const float* cv,
+                            int32_t* oci, float* ocv, hipStream_t s) {
+  if (n == 0) return hipSuccess;
+  k_sort_rows<<<(n + 3) / 4, 256, 0, s>>>(n, rp, ci, cv, oci, ocv);
   return hipGetLastError();
 }
 
@@ -2884,44 +2980,8 @@ hipError_t launch_levelize(int m, int k, const int32_t* off, const int32_t* rcnt
 }
 
 
-// ------------------------------------------------------------------------------------------
-// Sparse rows of Qbar from the dense per-cluster accumulators (rows of Qbar^T from their
-// transposes); one wave per position, entries in ascending column order.
-__global__ void k_qbar(int S, int fill, const int32_t* __restrict__ off,
-                       const int32_t* __restrict__ cl_of, const int64_t* __restrict__ gbase,
-                       const float* __restrict__ Q, int32_t* __restrict__ cnt,
-                       const int64_t* __restrict__ rp, int32_t* __restrict__ ci,
-                       float* __restrict__ cv) {
-  const int wpb = blockDim.x / PMMF_WAVE;
-  const int a = blockIdx.x * wpb + pmmf_wave();
-  const int lane = pmmf_lane();
-  if (a >= S) return;
-  const int u = cl_of[a];
-  const int o = off[u];
-  const int c = off[u + 1] - o;
-  const int la = a - o;
-  const float* Qu = Q + gbase[u];
-  int64_t cur = fill ? rp[a] : 0;
-  int total = 0;
-  for (int j0 = 0; j0 < c; j0 += PMMF_WAVE) {
-    const int j = j0 + lane;
-    float v = 0.f;
-    if (j < c) v = Qu[(size_t)la * c + j];
-    const uint64_t b = __ballot(v != 0.f);
-    if (fill && v != 0.f) {
-      const int64_t pos = cur + pmmf_lanes_below(b);
-      ci[pos] = o + j;
-      cv[pos] = v;
-    }
-    cur += __popcll(b);
-    total += __popcll(b);
-  }
-  if (!fill && lane == 0) cnt[a] = total;
-}
-
 // Transpose of a CSR matrix (n x n): column counts, then each entry placed at its column's next
-// free slot.  Entries of one output row land in arbitrary order, which is enough for Qbar^T: its
-// rows are only expanded as whole lists whose entries hit distinct columns.
+// free slot.  Entries of one output row land in arbitrary order (k_sort_rows orders them).
 __global__ void k_csr_col_count(int64_t nnz, const int32_t* __restrict__ ci,
                                 int32_t* __restrict__ cnt) {
   const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -2987,20 +3047,6 @@ hipError_t launch_cut_counts(int S, const int64_t* rp, const int32_t* ci, int32_
   return launch_scan(d, w, S + 1, tmp, s);
 }
 
-hipError_t launch_qbar_count(int S, const int32_t* off, const int32_t* cl_of,
-                             const int64_t* gbase, const float* Q, int32_t* cnt, hipStream_t s) {
-  if (S == 0) return hipSuccess;
-  k_qbar<<<(S + 3) / 4, 256, 0, s>>>(S, 0, off, cl_of, gbase, Q, cnt, nullptr, nullptr,
-                                     nullptr);
-  return hipGetLastError();
-}
-hipError_t launch_qbar_fill(int S, const int32_t* off, const int32_t* cl_of,
-                            const int64_t* gbase, const float* Q, const int64_t* rp, int32_t* ci,
-                            float* cv, hipStream_t s) {
-  if (S == 0) return hipSuccess;
-  k_qbar<<<(S + 3) / 4, 256, 0, s>>>(S, 1, off, cl_of, gbase, Q, nullptr, rp, ci, cv);
-  return hipGetLastError();
-}
 
 // ------------------------------------------------------------------------------------------
 // Right rotation W = M Qbar^T (the column half of [[A_p]]_{u,v} = Qbar_u [[A_{p-1}]]_{u,v}

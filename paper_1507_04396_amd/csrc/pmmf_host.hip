@@ -873,14 +873,17 @@ extern "C" int mmf_factor(int64_t n, int64_t nnz, const int64_t* d_rowptr, const
     if (sc.sizes.empty()) g = sc.size * (std::min<int64_t>(sc.size, p->cluster_max) + 1);
     pool = std::max(pool, g);
   }
-  DBuf GD, Q, retflag, keep, scan, cnt, loss_row, overflow, gid_cur, dense_buf;
+  DBuf GD, retflag, keep, scan, cnt, loss_row, overflow, gid_cur, dense_buf;
+  DBuf qs_ci, qs_cv;  // per-column scratch slots of the accumulated rotations (nonzeros only)
   DBuf bf_bm, bf_pre, bf_R, bf_off, bf_slab, bf_slab16, bf_stats;  // BF16 form only
   DBuf wstart, wcnt, abase, stage_ci, stage_cv;  // staging rows of the two products
   DBuf tcur;                                     // column cursors of the Qbar transpose
+  DBuf qtmp_ci, qtmp_cv;                         // Qbar's rows before they are put in order
   DBuf run_ptr, run_cl, run_start, wrs;            // run table of the active matrix, run starts in W
   if (p->gram_mode == 1) bf_stats.ensure(2 * sizeof(unsigned long long));
   GD.ensure(pool * sizeof(float2));
-  Q.ensure(pool * sizeof(float));
+  qs_ci.ensure(pool * sizeof(int32_t));
+  qs_cv.ensure(pool * sizeof(float));
   retflag.ensure(n);
   keep.ensure((n + 1) * sizeof(int32_t));
   scan.ensure((n + 2) * sizeof(int64_t));
@@ -1064,11 +1067,6 @@ extern "C" int mmf_factor(int64_t n, int64_t nnz, const int64_t* d_rowptr, const
                                  sd.depth.as<int32_t>(), sd.sw_loc.as<int32_t>(),
                                  sd.sw_o.as<float>(), sd.sw_idx.as<int32_t>(),
                                  h->theta.as<float>(), cm, s));
-    // the clusters' accumulated rotations, rebuilt from the sweep log
-    HIPCHK(pmmf::launch_build_q(sd.m, h->k, sd.off.as<int32_t>(), sd.gbase.as<int64_t>(),
-                                sd.lvl_ptr.as<int32_t>(), sd.lvl_stride, sd.depth.as<int32_t>(),
-                                sd.sw_loc.as<int32_t>(), sd.sw_o.as<float>(), Q.as<float>(),
-                                sd.cmax, s));
     // survivors' positions in the next stage
     HIPCHK(pmmf::launch_keep_flags(S, retflag.as<uint8_t>(), keep.as<int32_t>(), s));
     HIPCHK(pmmf::launch_scan(keep.as<int32_t>(), scan.as<int64_t>(), S, scan_tmp.as<int64_t>(), s));
@@ -1080,28 +1078,36 @@ extern "C" int mmf_factor(int64_t n, int64_t nnz, const int64_t* d_rowptr, const
                                        gid_new.as<int32_t>(), s));
     const int64_t Snext = sd.size - sd.t;
 
-    // sparse Qbar from the dense per-cluster accumulators, then its transpose
-    Qr.n = S;
-    Qr.rp.ensure((S + 1) * sizeof(int64_t));
-    HIPCHK(pmmf::launch_qbar_count(S, sd.off.as<int32_t>(), sd.cl_of.as<int32_t>(),
-                                   sd.gbase.as<int64_t>(), Q.as<float>(), cnt.as<int32_t>(), s));
-    HIPCHK(pmmf::launch_scan(cnt.as<int32_t>(), Qr.rp.as<int64_t>(), S, scan_tmp.as<int64_t>(), s));
-    Qr.nnz = read_i64(Qr.rp.as<int64_t>() + S, s);
-    Qr.ci.ensure(std::max<int64_t>(Qr.nnz, 1) * sizeof(int32_t));
-    Qr.cv.ensure(std::max<int64_t>(Qr.nnz, 1) * sizeof(float));
-    HIPCHK(pmmf::launch_qbar_fill(S, sd.off.as<int32_t>(), sd.cl_of.as<int32_t>(),
-                                  sd.gbase.as<int64_t>(), Q.as<float>(), Qr.rp.as<int64_t>(),
-                                  Qr.ci.as<int32_t>(), Qr.cv.as<float>(), s));
+    // the clusters' accumulated rotations Qbar, rebuilt from the sweep log: each column's nonzeros
+    // into its scratch slots, then packed into the CSR of Qbar^T; Qbar's rows from its transpose,
+    // put in column order
     Qt.n = S;
-    Qt.nnz = Qr.nnz;
     Qt.rp.ensure((S + 1) * sizeof(int64_t));
+    HIPCHK(pmmf::launch_qsparse(sd.m, h->k, sd.off.as<int32_t>(), sd.gbase.as<int64_t>(),
+                                sd.lvl_ptr.as<int32_t>(), sd.lvl_stride, sd.depth.as<int32_t>(),
+                                sd.sw_loc.as<int32_t>(), sd.sw_o.as<float>(), cnt.as<int32_t>(),
+                                qs_ci.as<int32_t>(), qs_cv.as<float>(), sd.cmax, s));
+    HIPCHK(pmmf::launch_scan(cnt.as<int32_t>(), Qt.rp.as<int64_t>(), S, scan_tmp.as<int64_t>(), s));
+    Qt.nnz = read_i64(Qt.rp.as<int64_t>() + S, s);
     Qt.ci.ensure(std::max<int64_t>(Qt.nnz, 1) * sizeof(int32_t));
     Qt.cv.ensure(std::max<int64_t>(Qt.nnz, 1) * sizeof(float));
+    HIPCHK(pmmf::launch_qt_compact(S, sd.off.as<int32_t>(), sd.cl_of.as<int32_t>(),
+                                   sd.gbase.as<int64_t>(), qs_ci.as<int32_t>(), qs_cv.as<float>(),
+                                   Qt.rp.as<int64_t>(), Qt.ci.as<int32_t>(), Qt.cv.as<float>(), s));
+    Qr.n = S;
+    Qr.nnz = Qt.nnz;
+    Qr.rp.ensure((S + 1) * sizeof(int64_t));
+    Qr.ci.ensure(std::max<int64_t>(Qr.nnz, 1) * sizeof(int32_t));
+    Qr.cv.ensure(std::max<int64_t>(Qr.nnz, 1) * sizeof(float));
+    qtmp_ci.ensure(std::max<int64_t>(Qr.nnz, 1) * sizeof(int32_t));
+    qtmp_cv.ensure(std::max<int64_t>(Qr.nnz, 1) * sizeof(float));
     tcur.ensure(std::max<int64_t>(S, 1) * sizeof(int64_t));
-    HIPCHK(pmmf::launch_csr_transpose(S, Qr.nnz, Qr.rp.as<int64_t>(), Qr.ci.as<int32_t>(),
-                                      Qr.cv.as<float>(), cnt.as<int32_t>(), Qt.rp.as<int64_t>(),
+    HIPCHK(pmmf::launch_csr_transpose(S, Qt.nnz, Qt.rp.as<int64_t>(), Qt.ci.as<int32_t>(),
+                                      Qt.cv.as<float>(), cnt.as<int32_t>(), Qr.rp.as<int64_t>(),
                                       scan_tmp.as<int64_t>(), tcur.as<int64_t>(),
-                                      Qt.ci.as<int32_t>(), Qt.cv.as<float>(), s));
+                                      qtmp_ci.as<int32_t>(), qtmp_cv.as<float>(), s));
+    HIPCHK(pmmf::launch_sort_rows(S, Qr.rp.as<int64_t>(), qtmp_ci.as<int32_t>(),
+                                  qtmp_cv.as<float>(), Qr.ci.as<int32_t>(), Qr.cv.as<float>(), s));
     // W = M Qbar^T, written once into staging rows sized by a capacity bound (row x of W keeps
     // its entries at [wstart[x], wstart[x] + wcnt[x]); k_left reads it in that form)
     HIPCHK(pmmf::launch_bound_right(S, M.rp.as<int64_t>(), M.ci.as<int32_t>(), Qt.rp.as<int64_t>(),
