@@ -35,6 +35,8 @@ struct FindArgs {
   float* hdiag;              // [n] retired diagonal of H
   uint8_t* retflag;          // [S] 1 if the position retires in this stage
   int32_t* err;              // set to 1 if a cluster finds no partner (never expected)
+  int32_t* rot_lvl = nullptr;  // [R] level of each rotation in its cluster's dependency order
+                               // (1 + the latest level touching one of its indices), if wanted
   // BF16 form only: FP32 slabs (column-major, R_u rows per cluster) for exact rescoring, and
   // counters {steps with more than one rescoring round, candidates rescored}
   float* slab = nullptr;
@@ -76,11 +78,13 @@ hipError_t launch_gram_bf16(int S, int m, const int64_t* rp, const int32_t* ci, 
                             unsigned short* slab_bf, const int64_t* gbase, float2* GD,
                             int cmax, hipStream_t s);
 size_t find_lds_bytes(int cmax);
+// levels of the stage's rotations (from lvl_in when the search recorded them, else walked here),
+// the level pointers and the sweep log in level order
 hipError_t launch_levelize(int m, int k, const int32_t* off, const int32_t* rcnt,
                            const int32_t* roff, int64_t rot0, const int32_t* rot_loc,
-                           const float* rot_o, int lvl_stride, int32_t* lvl_ptr, int32_t* depth,
-                           int32_t* sw_loc, float* sw_o, int32_t* sw_idx, float* theta, int cmax,
-                           hipStream_t s);
+                           const float* rot_o, const int32_t* lvl_in, int lvl_stride,
+                           int32_t* lvl_ptr, int32_t* depth, int32_t* sw_loc, float* sw_o,
+                           int32_t* sw_idx, float* theta, int cmax, hipStream_t s);
 // the clusters' accumulated rotations from the levelized sweep log: column j of Qbar_u (row j of
 // Qbar^T, rows ascending) into the c_u scratch slots at gbase[u] + j c_u of sci/scv, its count to
 // cnt[j]; launch_qt_compact packs them into the CSR of Qbar^T with row pointers rp

@@ -1699,6 +1699,8 @@ __global__ void __launch_bounds__(NT) k_search(FindArgs A, int cmax) {
   float* rgs = ddiag + cmax;  // 1 / sqrt(G_jj), 0 where G_jj <= 0
   int* lgid = reinterpret_cast<int*>(rgs + cmax);
   uint32_t* mask = reinterpret_cast<uint32_t*>(lgid + cmax);
+  // latest rotation level touching each index (16 bits: a stage has fewer than 65536 levels)
+  unsigned short* lastlv = reinterpret_cast<unsigned short*>(mask + (cmax + 31) / 32);
   // per-wave winners [parity][0, 1: candidate rows, 2: full scoring][wave]; entries at T
   __shared__ Cand red1[2][3][NW], red2[2][3][NW], sh_tc[3];
   __shared__ int sh_i, sh_e, sh_c[2], sh_k[3];
@@ -1724,6 +1726,7 @@ __global__ void __launch_bounds__(NT) k_search(FindArgs A, int cmax) {
     ddiag[j] = dg.y;
     rgs[j] = inv_sqrt_pos(dg.x);
     lgid[j] = A.gid[o + j];
+    lastlv[j] = 0;
   }
   for (int q = tid; q < nw; q += NT) {
     const int rem = c - q * 32;
@@ -1955,7 +1958,15 @@ __global__ void __launch_bounds__(NT) k_search(FindArgs A, int cmax) {
           }
         }
       }
-      if (lane == 0) mask[e >> 5] &= ~(1u << (e & 31));
+      if (lane == 0) {
+        mask[e >> 5] &= ~(1u << (e & 31));
+        // the rotation's level: one past the latest level touching its indices
+        const int lv = 1 + max(max((int)lastlv[t0], (int)lastlv[t1]), K == 3 ? (int)lastlv[t2] : 0);
+        lastlv[t0] = (unsigned short)lv;
+        lastlv[t1] = (unsigned short)lv;
+        if (K == 3) lastlv[t2] = (unsigned short)lv;
+        if (A.rot_lvl) A.rot_lvl[A.rot0 + rb + s] = lv;
+      }
       // the rotated k x k block and the rotation log, lane by lane; lanes past the last entry
       // repeat it, so the stores need no branch and the wait for the entries above counts them
       // exactly
@@ -2173,7 +2184,7 @@ __global__ void __launch_bounds__(NT) k_search(FindArgs A, int cmax) {
 
 template <int NT, int PER, int K>
 static hipError_t search_launch(const FindArgs& a, int m, int cmax, hipStream_t s) {
-  const size_t lds = find_lds_bytes(cmax) + (size_t)cmax * sizeof(float);
+  const size_t lds = find_lds_bytes(cmax) + (size_t)cmax * (sizeof(float) + sizeof(unsigned short));
   if (lds > 64 * 1024) {
     hipError_t e = hipFuncSetAttribute((const void*)&k_search<NT, PER, K>,
                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
@@ -2667,9 +2678,8 @@ hipError_t launch_find(const FindArgs& a, int m, int cmax, int nt, hipStream_t s
 // column of the slice.  Only the nonzeros leave the workgroup: column j of Qbar_u (row j of
 // Qbar^T, rows ascending) goes to its own c_u slots of a scratch pool at gbase[u] + j c_u, with
 // its count; k_qt_compact then packs the columns into the CSR of Qbar^T.
-constexpr int BQ_W = 8;
-template <int K>
-__global__ void __launch_bounds__(256) k_qsparse(const int32_t* __restrict__ off,
+template <int K, int BQ_W, int NT>
+__global__ void __launch_bounds__(NT) k_qsparse(const int32_t* __restrict__ off,
                                                  const int64_t* __restrict__ gbase,
                                                  const int32_t* __restrict__ lvl_ptr,
                                                  int lvl_stride, const int32_t* __restrict__ depth,
@@ -2679,7 +2689,7 @@ __global__ void __launch_bounds__(256) k_qsparse(const int32_t* __restrict__ off
                                                  int32_t* __restrict__ sci,
                                                  float* __restrict__ scv) {
   extern __shared__ float tile[];  // [c][BQ_W]
-  constexpr int NWV = 256 / PMMF_WAVE;
+  constexpr int NWV = NT / PMMF_WAVE;
   __shared__ int part[NWV][BQ_W];
   const int u = blockIdx.y;
   const int o = off[u];
@@ -2759,8 +2769,11 @@ hipError_t launch_qsparse(int m, int k, const int32_t* off, const int64_t* gbase
                           const int32_t* sw_loc, const float* sw_o, int32_t* cnt, int32_t* sci,
                           float* scv, int cmax, hipStream_t s) {
   if (m == 0) return hipSuccess;
-  const size_t lds = (size_t)cmax * BQ_W * sizeof(float);
-  dim3 grid((unsigned)((cmax + BQ_W - 1) / BQ_W), (unsigned)m);
+  // 8-column slices, 256 threads (16 columns with 512 threads measured slower: half as many
+  // workgroups fit a compute unit, and each level's latency is the same)
+  constexpr int bw = 8;
+  const size_t lds = (size_t)cmax * bw * sizeof(float);
+  dim3 grid((unsigned)((cmax + bw - 1) / bw), (unsigned)m);
   auto go = [&](auto kern) -> hipError_t {
     if (lds > 64 * 1024) {
       hipError_t e = hipFuncSetAttribute((const void*)kern,
@@ -2771,7 +2784,7 @@ hipError_t launch_qsparse(int m, int k, const int32_t* off, const int64_t* gbase
                                 scv);
     return hipGetLastError();
   };
-  return k == 3 ? go(&k_qsparse<3>) : go(&k_qsparse<2>);
+  return k == 3 ? go(&k_qsparse<3, bw, 256>) : go(&k_qsparse<2, bw, 256>);
 }
 
 // Packs the columns left by k_qsparse into the CSR of Qbar^T (row pointers rp from the scan of
@@ -2843,7 +2856,8 @@ hipError_t launch_sort_rows(int n, const int64_t* rp, const int32_t* ci, const f
 __global__ void k_levelize(int k, const int32_t* __restrict__ off, const int32_t* __restrict__ rcnt,
                            const int32_t* __restrict__ roff, int64_t rot0,
                            const int32_t* __restrict__ rot_loc, const float* __restrict__ rot_o,
-                           int lvl_stride, int32_t* __restrict__ lvl_ptr,
+                           const int32_t* __restrict__ lvl_in, int lvl_stride,
+                           int32_t* __restrict__ lvl_ptr,
                            int32_t* __restrict__ depth_out, int32_t* __restrict__ sw_loc,
                            float* __restrict__ sw_o, int32_t* __restrict__ sw_idx,
                            float* __restrict__ theta, int cmax) {
@@ -2874,20 +2888,26 @@ __global__ void k_levelize(int k, const int32_t* __restrict__ off, const int32_t
       const int c0 = ids[sl * 3], c1 = ids[sl * 3 + 1], c2 = ids[sl * 3 + 2];
       const int n = min(PMMF_WAVE, r - s0);
       int lv = 0;
-      for (int t = 0; t < n; ++t) {
-        const int i0 = __builtin_amdgcn_readlane(c0, t), i1 = __builtin_amdgcn_readlane(c1, t),
-                  i2 = __builtin_amdgcn_readlane(c2, t);
-        int L = max(last[i0], last[i1]);
-        if (i2 >= 0) L = max(L, last[i2]);
-        L += 1;
-        // every lane writes the same value at the same address, so each lane reads back its own
-        // writes (no lane depends on another lane's LDS write)
-        last[i0] = L;
-        last[i1] = L;
-        if (i2 >= 0) last[i2] = L;
-        cnt_v += lane == L ? 1 : 0;
-        lv = lane == t ? L : lv;
-        depth = max(depth, L);
+      if (lvl_in) {  // levels recorded by the search
+        lv = lane < n ? lvl_in[rot0 + rb + s0 + lane] : 0;
+        for (int t = 0; t < n; ++t) cnt_v += lane == __builtin_amdgcn_readlane(lv, t) ? 1 : 0;
+        depth = max(depth, pmmf_wave_max_int(lv));
+      } else {
+        for (int t = 0; t < n; ++t) {
+          const int i0 = __builtin_amdgcn_readlane(c0, t), i1 = __builtin_amdgcn_readlane(c1, t),
+                    i2 = __builtin_amdgcn_readlane(c2, t);
+          int L = max(last[i0], last[i1]);
+          if (i2 >= 0) L = max(L, last[i2]);
+          L += 1;
+          // every lane writes the same value at the same address, so each lane reads back its
+          // own writes (no lane depends on another lane's LDS write)
+          last[i0] = L;
+          last[i1] = L;
+          if (i2 >= 0) last[i2] = L;
+          cnt_v += lane == L ? 1 : 0;
+          lv = lane == t ? L : lv;
+          depth = max(depth, L);
+        }
       }
       if (lane < n) lvl[s0 + lane] = lv;
     }
@@ -2964,9 +2984,9 @@ __global__ void k_levelize(int k, const int32_t* __restrict__ off, const int32_t
 
 hipError_t launch_levelize(int m, int k, const int32_t* off, const int32_t* rcnt,
                            const int32_t* roff, int64_t rot0, const int32_t* rot_loc,
-                           const float* rot_o, int lvl_stride, int32_t* lvl_ptr, int32_t* depth,
-                           int32_t* sw_loc, float* sw_o, int32_t* sw_idx, float* theta,
-                           int cmax, hipStream_t s) {
+                           const float* rot_o, const int32_t* lvl_in, int lvl_stride,
+                           int32_t* lvl_ptr, int32_t* depth, int32_t* sw_loc, float* sw_o,
+                           int32_t* sw_idx, float* theta, int cmax, hipStream_t s) {
   if (m == 0) return hipSuccess;
   const size_t lds = (size_t)(6 * cmax + 2) * sizeof(int);
   if (lds > 64 * 1024) {
@@ -2974,8 +2994,8 @@ hipError_t launch_levelize(int m, int k, const int32_t* off, const int32_t* rcnt
                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess) return e;
   }
-  k_levelize<<<m, 64, lds, s>>>(k, off, rcnt, roff, rot0, rot_loc, rot_o, lvl_stride, lvl_ptr,
-                                depth, sw_loc, sw_o, sw_idx, theta, cmax);
+  k_levelize<<<m, 256, lds, s>>>(k, off, rcnt, roff, rot0, rot_loc, rot_o, lvl_in, lvl_stride,
+                                lvl_ptr, depth, sw_loc, sw_o, sw_idx, theta, cmax);
   return hipGetLastError();
 }
 

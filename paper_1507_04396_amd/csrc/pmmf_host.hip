@@ -341,6 +341,7 @@ struct mmf_plan {
   mmf_params prm{};
   std::vector<std::unique_ptr<StageDev>> st;
   DBuf rot_loc, rot_gid, rot_o, rot_ret, rot_margin, theta, rot_lit;
+  DBuf rot_lvl;  // level of each rotation, recorded by the search (one retirement per rotation)
   DBuf rot_o0;  // k = 3: the rotations as found (angles w = 0), O_t = expm(W(w_t)) O0_t
   DBuf hdiag, hcore, core_ids, is_core;
   DBuf hinv, chol_L, chol_X, status;
@@ -851,6 +852,7 @@ extern "C" int mmf_factor(int64_t n, int64_t nnz, const int64_t* d_rowptr, const
   h->rot_margin.ensure(std::max<int64_t>(R, 1) * sizeof(float));
   h->theta.ensure(std::max<int64_t>(R, 1) * sizeof(float));
   h->rot_lit.ensure(std::max<int64_t>(R, 1) * sizeof(double));
+  h->rot_lvl.ensure(std::max<int64_t>(R, 1) * sizeof(int32_t));
   h->hdiag.ensure(n * sizeof(float));
   HIPCHK(hipMemsetAsync(h->hdiag.p, 0, n * sizeof(float), s));
   HIPCHK(hipMemsetAsync(h->theta.p, 0, std::max<int64_t>(R, 1) * sizeof(float), s));
@@ -1038,6 +1040,7 @@ extern "C" int mmf_factor(int64_t n, int64_t nnz, const int64_t* d_rowptr, const
     fa.rot_ret = h->rot_ret.as<int32_t>();
     fa.rot_margin = h->rot_margin.as<float>();
     fa.rot_lit = h->rot_lit.as<double>();
+    fa.rot_lvl = h->rot_lvl.as<int32_t>();
     fa.hdiag = h->hdiag.as<float>();
     fa.retflag = retflag.as<uint8_t>();
     fa.err = overflow.as<int32_t>() + 1;
@@ -1058,12 +1061,14 @@ extern "C" int mmf_factor(int64_t n, int64_t nnz, const int64_t* d_rowptr, const
       HIPCHK(pmmf::launch_find(fa, sd.m, cm, find_threads(), s));
     }
     HIPCHK(hipEventRecord(pev.e[2], s));
-    // rotation levels and the sweep log
+    // rotation levels (recorded by the search for one retirement per rotation) and the sweep log
+    const int32_t* lvl_in = (!bf16 && h->elims != 2) ? h->rot_lvl.as<int32_t>() : nullptr;
     sd.sw_loc.ensure(sd.t * h->k * sizeof(int32_t));
     sd.sw_o.ensure(sd.t * h->k * h->k * sizeof(float));
     HIPCHK(pmmf::launch_levelize(sd.m, h->k, sd.off.as<int32_t>(), sd.rcnt.as<int32_t>(),
                                  sd.roff.as<int32_t>(), rot_base, h->rot_loc.as<int32_t>(),
-                                 h->rot_o.as<float>(), sd.lvl_stride, sd.lvl_ptr.as<int32_t>(),
+                                 h->rot_o.as<float>(), lvl_in, sd.lvl_stride,
+                                 sd.lvl_ptr.as<int32_t>(),
                                  sd.depth.as<int32_t>(), sd.sw_loc.as<int32_t>(),
                                  sd.sw_o.as<float>(), sd.sw_idx.as<int32_t>(),
                                  h->theta.as<float>(), cm, s));
@@ -2126,7 +2131,8 @@ extern "C" int mmf_import(int64_t n, int32_t k, int64_t core_size, int32_t num_s
     sd.sw_o.ensure(sd.t * k * k * sizeof(float));
     HIPCHK(pmmf::launch_levelize(sd.m, k, sd.off.as<int32_t>(), sd.rcnt.as<int32_t>(),
                                  sd.roff.as<int32_t>(), sd.rot_base, h->rot_loc.as<int32_t>(),
-                                 h->rot_o.as<float>(), sd.lvl_stride, sd.lvl_ptr.as<int32_t>(),
+                                 h->rot_o.as<float>(), nullptr, sd.lvl_stride,
+                                 sd.lvl_ptr.as<int32_t>(),
                                  sd.depth.as<int32_t>(), sd.sw_loc.as<int32_t>(),
                                  sd.sw_o.as<float>(), sd.sw_idx.as<int32_t>(),
                                  h->theta.as<float>(), round_cmax(sd.cmax), s));
