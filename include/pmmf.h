@@ -337,6 +337,19 @@ int mmf_spmm(int64_t n, const int64_t* d_rowptr, const int32_t* d_colind, const 
 int mmf_apply_noalloc(mmf_handle h, const float* d_x, float* d_y, int64_t nrhs, int64_t ld,
                       void* stream);
 
+/*
+ * mmf_set_tail_rows — how the products (mmf_apply, mmf_apply_inverse, mmf_apply_inverse_sqrt,
+ * mmf_apply_noalloc and graphs captured afterwards) run the last stages of U and U^T (Sec. 2.4):
+ * the trailing stages whose first active set has at most `rows` rows, all of whose rotation
+ * components have at most 32 rows, and whose rows and programs fit one workgroup's LDS, run as
+ * one launch per direction that keeps each column's active rows on chip between stages (at most
+ * 16 stages and 8192 rows; fewer than two such stages: none).  `rows` caps the threshold the
+ * library itself takes (the fastest of 0, 2048, 4096 and 8192 when autotuning is on, else 4096);
+ * rows = 0 runs every stage as its own launch.  The default cap is 8192.  Results are the same
+ * either way (same arithmetic, same order).  Errors: MMF_ESTATE (bad handle), MMF_EINVAL (rows < 0).
+ */
+int mmf_set_tail_rows(mmf_handle h, int64_t rows);
+
 /* Free the handle and all device memory it owns (synchronizes its stream). */
 int mmf_destroy(mmf_handle h);
 

@@ -89,6 +89,7 @@ SIGNATURES = {
     "mmf_graph_capture": [H, I32, P, P, I64, I64, P, ctypes.POINTER(H)],
     "mmf_graph_launch": [H, P],
     "mmf_graph_destroy": [H],
+    "mmf_set_tail_rows": [H, I64],
     "mmf_destroy": [H],
     "mmf_set_allocator": [ALLOC_FN, RELEASE_FN, P],
     "mmf_trim": [],

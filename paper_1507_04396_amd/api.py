@@ -210,6 +210,11 @@ class Factorization:
                       stream=None) -> torch.Tensor:
         return self.apply(x, out=out, stream=stream, inverse=True)
 
+    def set_tail_rows(self, rows: int) -> None:
+        """mmf_set_tail_rows: the products run the trailing stages whose first active set has at
+        most ``rows`` rows as one launch per direction (0: every stage as its own launch)."""
+        check(_lib.load().mmf_set_tail_rows(self.handle, int(rows)))
+
     def backward(self, x: torch.Tensor, ybar: torch.Tensor, want=("x", "hdiag", "hcore", "theta"),
                  stream=None):
         """Adjoint of Y = U^T H U X: returns (xbar, hdiag_bar, hcore_bar, theta_bar)."""

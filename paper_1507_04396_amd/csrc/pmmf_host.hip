@@ -332,6 +332,10 @@ struct PhaseEvents {
 struct SweepCfg {
   int wpb = 2;  // units (waves) per workgroup of the unit sweep
   int W = 0;    // column tile of the level sweep
+  // largest first active set of the fused trailing stages of the products (capped by the
+  // handle's mmf_set_tail_rows); untuned: 4096, the best of 0 / 2048 / 4096 / 8192 measured on
+  // the 256 x 256 grid factorization with 256 vectors
+  int tail = 4096;
 };
 
 struct mmf_plan {
@@ -349,6 +353,14 @@ struct mmf_plan {
   bool inv_ready = false;
   bool isqrt_ready = false;
   bool units_ready = false;
+  // trailing stages as one launch per direction (tables built with the units, for the stages
+  // from tail_first on that qualify; tail_plan picks the first trailing stage per call)
+  int tail_first = -1;
+  int64_t tail_rows = (int64_t)pmmf::TAIL_THREADS * pmmf::TAIL_J;  // mmf_set_tail_rows
+  int lds_cap = 0;
+  std::vector<pmmf::TailStage> tail_st;
+  DBuf tail_blob, tail_trans, tail_pos, tail_gid, tail_pidx, tail_odst;
+  int64_t tail_entries = 0;
   uint64_t version = 0;  // bumped whenever theta, H or the rotations change
   std::map<std::pair<std::string, int64_t>, SweepCfg> tune;  // (product, width) -> config
   DBuf ws[16];
@@ -578,10 +590,15 @@ pmmf::UnitStage unit_view(const mmf_plan& h, const StageDev& sd) {
   return v;
 }
 
+void build_tail(mmf_plan& h, const std::vector<std::vector<int32_t>>& all_cnt,
+                const std::vector<std::vector<int32_t>>& all_slot,
+                const std::vector<std::vector<int32_t>>& all_rot, hipStream_t s);
+
 void ensure_units(mmf_plan& h, hipStream_t s) {
   if (h.units_ready) return;
   const int k = h.k;
   constexpr int UM = pmmf::UNIT_MAX;
+  std::vector<std::vector<int32_t>> all_cnt, all_slot, all_rot;
   for (auto& sp : h.st) {
     StageDev& sd = *sp;
     std::vector<int32_t> loc3(std::max<int64_t>(sd.t, 1) * 3);
@@ -686,8 +703,136 @@ void ensure_units(mmf_plan& h, hipStream_t s) {
     upload(sd.u_slot, uslot, s);
     upload(sd.u_rot, urot, s);
     upload(sd.big_list, big, s);
+    all_cnt.push_back(std::move(ucnt));
+    all_slot.push_back(std::move(uslot));
+    all_rot.push_back(std::move(urot));
   }
+  build_tail(h, all_cnt, all_slot, all_rot, s);
+  HIPCHK(hipStreamSynchronize(s));
   h.units_ready = true;
+}
+
+// Tables of the trailing stages: every stage from the first one on after which all stages are
+// made of units and have at most TAIL_THREADS * TAIL_J rows (and at most TAIL_MAX_STAGES of them).
+// Per stage: the program block (units, unit-local slots, rotation blocks filled from the
+// canonical blocks by k_tail_params), and per LDS slot (units' rows in unit order) the slot of the
+// next stage (or the core position, or -(gid + 1)), the position in S_{p-1} and the global id.
+void build_tail(mmf_plan& h, const std::vector<std::vector<int32_t>>& all_cnt,
+                const std::vector<std::vector<int32_t>>& all_slot,
+                const std::vector<std::vector<int32_t>>& all_rot, hipStream_t s) {
+  constexpr int UM = pmmf::UNIT_MAX;
+  h.tail_first = -1;
+  h.tail_st.clear();
+  h.tail_entries = 0;
+  const int P = (int)h.st.size();
+  int first = P;
+  while (first > 0 && P - (first - 1) <= pmmf::TAIL_MAX_STAGES) {
+    const StageDev& sd = *h.st[first - 1];
+    if (sd.nbig != 0 || sd.size > (int64_t)pmmf::TAIL_THREADS * pmmf::TAIL_J) break;
+    --first;
+  }
+  if (P - first < 2) return;
+  int dev = 0;
+  HIPCHK(hipGetDevice(&dev));
+  HIPCHK(hipDeviceGetAttribute(&h.lds_cap, hipDeviceAttributeMaxSharedMemoryPerBlock, dev));
+  const int k = h.k, KK = k * k;
+  // LDS slot of each position, per stage
+  std::vector<std::vector<int32_t>> slot_of(P);
+  for (int i = first; i < P; ++i) {
+    const StageDev& sd = *h.st[i];
+    slot_of[i].assign(sd.size, -1);
+    const int nu = (int)(all_cnt[i].size() / 2);
+    int sb = 0;
+    for (int u = 0; u < nu; ++u) {
+      const int ns = all_cnt[i][2 * u];
+      for (int li = 0; li < ns; ++li) slot_of[i][all_slot[i][((size_t)u * UM + li) * 4]] = sb + li;
+      sb += ns;
+    }
+    if (sb != sd.size) raise(MMF_EDEVICE, "trailing stage: units do not cover the active set");
+  }
+  std::vector<uint8_t> blob;
+  std::vector<int32_t> trans, pos, gid, pidx;
+  std::vector<int64_t> odst;
+  for (int i = first; i < P; ++i) {
+    const StageDev& sd = *h.st[i];
+    const int nu = (int)(all_cnt[i].size() / 2);
+    const int t = (int)sd.t;
+    pmmf::TailStage ts{};
+    ts.rows = (int)sd.size;
+    ts.t = t;
+    ts.nu = nu;
+    ts.blob_bytes = pmmf::tail_blob_bytes(nu, t, k);
+    ts.blob_off = (int64_t)blob.size();
+    ts.slot_off = (int64_t)trans.size();
+    blob.resize(blob.size() + ts.blob_bytes, 0);
+    int32_t* units = reinterpret_cast<int32_t*>(blob.data() + ts.blob_off);
+    int32_t* prog = reinterpret_cast<int32_t*>(blob.data() + ts.blob_off + pmmf::tail_prog_off(nu));
+    const int64_t o_base = (ts.blob_off + pmmf::tail_o_off(nu, t)) / 4;
+    int sb = 0, rb = 0;
+    for (int u = 0; u < nu; ++u) {
+      const int ns = all_cnt[i][2 * u], nq = all_cnt[i][2 * u + 1];
+      units[2 * u] = sb;
+      units[2 * u + 1] = rb;
+      for (int li = 0; li < ns; ++li) {
+        const int32_t* e = &all_slot[i][((size_t)u * UM + li) * 4];
+        const int nx = e[1];
+        trans.push_back(nx >= 0 && i + 1 < P ? slot_of[i + 1][nx] : nx);
+        pos.push_back(e[0]);
+        gid.push_back(e[2]);
+      }
+      for (int q = 0; q < nq; ++q) {
+        prog[rb + q] = all_rot[i][((size_t)u * UM + q) * 2];
+        pidx.push_back(all_rot[i][((size_t)u * UM + q) * 2 + 1]);
+        odst.push_back(o_base + (int64_t)(rb + q) * KK);
+      }
+      sb += ns;
+      rb += nq;
+    }
+    if (rb != t) raise(MMF_EDEVICE, "trailing stage: units do not hold every rotation");
+    units[2 * nu] = sb;
+    units[2 * nu + 1] = rb;
+    h.tail_st.push_back(ts);
+  }
+  upload(h.tail_blob, blob, s);
+  upload(h.tail_trans, trans, s);
+  upload(h.tail_pos, pos, s);
+  upload(h.tail_gid, gid, s);
+  upload(h.tail_pidx, pidx, s);
+  upload(h.tail_odst, odst, s);
+  h.tail_entries = (int64_t)pidx.size();
+  h.tail_first = first;
+  HIPCHK(pmmf::launch_tail_params(h.tail_entries, k, h.tail_pidx.as<int32_t>(),
+                                  h.tail_odst.as<int64_t>(), h.rot_o.as<float>(),
+                                  h.tail_blob.as<uint8_t>(), s));
+}
+
+// The trailing stages this call runs as one launch per direction: from the first stage with
+// tail tables whose rows are within max_rows and h.tail_rows and whose rows and consecutive program blocks fit
+// one workgroup's LDS (nst = 0: none)
+pmmf::TailPlan tail_plan(const mmf_plan& h, int64_t max_rows) {
+  pmmf::TailPlan tp;
+  if (h.tail_first < 0) return tp;
+  const int P = (int)h.st.size();
+  for (int i = h.tail_first; i + 2 <= P; ++i) {
+    const pmmf::TailStage& f = h.tail_st[i - h.tail_first];
+    if (f.rows > std::min(max_rows, h.tail_rows)) continue;
+    int maxpair = 0;
+    for (int q = i; q + 1 < P; ++q)
+      maxpair = std::max(maxpair, h.tail_st[q - h.tail_first].blob_bytes +
+                                      h.tail_st[q + 1 - h.tail_first].blob_bytes);
+    const int data_bytes = (4 * f.rows + 15) & ~15;
+    if (data_bytes + maxpair > h.lds_cap) continue;
+    tp.nst = P - i;
+    tp.data_bytes = data_bytes;
+    tp.lds_bytes = data_bytes + maxpair;
+    tp.blob = h.tail_blob.as<uint8_t>();
+    tp.trans = h.tail_trans.as<int32_t>();
+    tp.pos = h.tail_pos.as<int32_t>();
+    tp.gid = h.tail_gid.as<int32_t>();
+    for (int q = i; q < P; ++q) tp.st[q - i] = h.tail_st[q - h.tail_first];
+    return tp;
+  }
+  return tp;
 }
 
 // widest column tile whose LDS footprint allows two workgroups per CU (fallback: one)
@@ -784,6 +929,10 @@ static void sync_rotations(mmf_plan& h, hipStream_t s) {
       HIPCHK(pmmf::launch_sync_sweep3((int)sp->t, sp->sw_idx.as<int32_t>(), h.rot_o.as<float>(),
                                       sp->sw_o.as<float>(), s));
   }
+  if (h.tail_entries)
+    HIPCHK(pmmf::launch_tail_params(h.tail_entries, h.k, h.tail_pidx.as<int32_t>(),
+                                    h.tail_odst.as<int64_t>(), h.rot_o.as<float>(),
+                                    h.tail_blob.as<uint8_t>(), s));
 }
 
 namespace {
@@ -1367,7 +1516,7 @@ std::string tune_path() {
   return std::string(home && *home ? home : "/tmp") + "/.cache/pmmf_tune.json";
 }
 
-// one entry per line:  "key": {"wpb": 2, "W": 16, "ms": 0.123},
+// one entry per line:  "key": {"wpb": 2, "W": 16, "tail": 4096, "ms": 0.123},
 void tune_load_locked() {
   g_tune.path = tune_path();
   g_tune.loaded = true;
@@ -1381,7 +1530,9 @@ void tune_load_locked() {
     if (!br) continue;
     SweepCfg c;
     double ms = 0.0;
-    if (std::sscanf(br, "{\"wpb\": %d, \"W\": %d, \"ms\": %lf}", &c.wpb, &c.W, &ms) == 3)
+    if (std::sscanf(br, "{\"wpb\": %d, \"W\": %d, \"tail\": %d, \"ms\": %lf}", &c.wpb, &c.W,
+                    &c.tail, &ms) == 4 ||
+        std::sscanf(br, "{\"wpb\": %d, \"W\": %d, \"ms\": %lf}", &c.wpb, &c.W, &ms) == 3)
       g_tune.entries[std::string(q0 + 1, q1)] = {c, ms};
   }
   std::fclose(f);
@@ -1401,9 +1552,9 @@ void tune_save_locked() {
   std::fprintf(f, "{\n");
   size_t k = 0;
   for (const auto& kv : g_tune.entries) {
-    std::fprintf(f, "  \"%s\": {\"wpb\": %d, \"W\": %d, \"ms\": %.6f}%s\n", kv.first.c_str(),
-                 kv.second.first.wpb, kv.second.first.W, kv.second.second,
-                 ++k < g_tune.entries.size() ? "," : "");
+    std::fprintf(f, "  \"%s\": {\"wpb\": %d, \"W\": %d, \"tail\": %d, \"ms\": %.6f}%s\n",
+                 kv.first.c_str(), kv.second.first.wpb, kv.second.first.W, kv.second.first.tail,
+                 kv.second.second, ++k < g_tune.entries.size() ? "," : "");
   }
   std::fprintf(f, "}\n");
   std::fclose(f);
@@ -1467,9 +1618,13 @@ SweepCfg sweep_config(mmf_plan& h, const char* what, int nv, int64_t nrhs, hipSt
   HIPCHK(hipEventCreate(&e1));
   SweepCfg best = def;
   double best_ms = 1e300;
+  // fused trailing stages: only the one-vector products use them; otherwise one candidate
+  std::vector<int> tails{def.tail};
+  if (nv == 1 && h.tail_first >= 0) tails = {0, 2048, 4096, 8192};
+  for (int tl : tails)
   for (int wpb : {1, 2, 4})
     for (int W : Ws) {
-      SweepCfg c{wpb, W};
+      SweepCfg c{wpb, W, tl};
       run(c);  // warm
       HIPCHK(hipEventRecord(e0, s));
       for (int r = 0; r < 3; ++r) run(c);
@@ -1540,7 +1695,7 @@ GramCfg gram_config(const mmf_plan& h, int S, int64_t nnz, int cmax, hipStream_t
   (void)hipEventDestroy(e1);
   {
     std::lock_guard<std::mutex> lk(g_tune.mu);
-    g_tune.entries[key] = {SweepCfg{best.wpb, best.form}, best_ms};
+    g_tune.entries[key] = {SweepCfg{best.wpb, best.form, 0}, best_ms};
     tune_save_locked();
   }
   return best;
@@ -1560,6 +1715,8 @@ void apply_body(mmf_plan& h, const float* x, float* y, int64_t nrhs, int64_t ld,
   const int64_t s1 = h.st[0]->size - h.st[0]->t;
   float* buf[2] = {ws0 ? ws0 : wsbuf(h, 0, s1 * nrhs), ws1 ? ws1 : wsbuf(h, 1, s1 * nrhs)};
   const int W = cfg.W;
+  const pmmf::TailPlan tp = tail_plan(h, cfg.tail);
+  const int p0 = tp.nst ? P - tp.nst + 1 : P + 1;  // first trailing stage
   for (int p = 1; p <= P; ++p) {
     const StageDev& sd = *h.st[p - 1];
     pmmf::FwdIO io{};
@@ -1572,12 +1729,18 @@ void apply_body(mmf_plan& h, const float* x, float* y, int64_t nrhs, int64_t ld,
     io.mode[0] = which == 2 ? 3 : (which == 1 ? 2 : 1);
     io.hdiag = h.hdiag.as<float>();
     io.nrhs = nrhs;
+    if (p == p0) {
+      io.dst_c[0] = buf[P % 2];
+      HIPCHK(pmmf::launch_tail_fwd(h.k, tp, io, s));
+      break;
+    }
     HIPCHK(pmmf::launch_unit_fwd(unit_view(h, sd), io, 1, cfg.wpb, s));
     HIPCHK(pmmf::launch_sweep_fwd(sweep_view(h, sd), io, W, 1, s));
   }
   HIPCHK(pmmf::launch_gemm((int)core, (int)nrhs, (int)core, Hc, (int)core, 0, buf[P % 2],
                            (int)nrhs, 0, buf[(P + 1) % 2], (int)nrhs, 0.f, s));
   for (int p = P; p >= 1; --p) {
+    if (p >= p0 && p != p0) continue;
     const StageDev& sd = *h.st[p - 1];
     pmmf::RevIO io{};
     io.src_c[0] = buf[(p + 1) % 2];
@@ -1594,6 +1757,11 @@ void apply_body(mmf_plan& h, const float* x, float* y, int64_t nrhs, int64_t ld,
       io.ld_out = nrhs;
     }
     io.nrhs = nrhs;
+    if (p == p0) {
+      io.src_c[0] = buf[(P + 1) % 2];
+      HIPCHK(pmmf::launch_tail_rev(h.k, tp, io, s));
+      continue;
+    }
     HIPCHK(pmmf::launch_unit_rev(unit_view(h, sd), io, 1, false, cfg.wpb, s));
     HIPCHK(pmmf::launch_sweep_rev(sweep_view(h, sd), io, W, 1, false, s));
   }
@@ -1641,6 +1809,15 @@ extern "C" int mmf_apply_inverse_sqrt(mmf_handle hh, const float* d_x, float* d_
   mmf_plan& h = *checked(hh);
   pmmf_alloc::StreamScope alloc_scope(stream);
   apply_impl(h, d_x, d_y, nrhs, ld, as_stream(stream), 2);
+  return MMF_OK;
+  ABI_END
+}
+
+extern "C" int mmf_set_tail_rows(mmf_handle hh, int64_t rows) {
+  ABI_BEGIN
+  mmf_plan& h = *checked(hh);
+  if (rows < 0) raise(MMF_EINVAL, "mmf_set_tail_rows: rows < 0");
+  h.tail_rows = rows;
   return MMF_OK;
   ABI_END
 }
@@ -1885,6 +2062,10 @@ void backward_body(mmf_plan& h, const float* d_x, const float* d_ybar, float* d_
   for (int p = P; p >= 1; --p) {
     const StageDev& sd = *h.st[p - 1];
     const pmmf::SweepStage v = sweep_view(h, sd);
+    // column tiles of this stage's partials: the unit sweep's (64 columns) and, for clusters with
+    // a larger component, the level sweep's (W2 columns); the launch with fewer zero-fills the rest
+    const int nt_stage = (int)std::max(sd.nu > 0 ? (nrhs + 63) / 64 : 0,
+                                       sd.nbig > 0 ? (nrhs + W2 - 1) / W2 : 0);
     for (int pass = 0; pass < 2; ++pass) {
       float* (*Rb)[2] = pass == 0 ? RA : RB;
       pmmf::RevIO io{};
@@ -1914,13 +2095,12 @@ void backward_body(mmf_plan& h, const float* d_x, const float* d_ybar, float* d_
       io.nrhs = nrhs;
       io.theta_part = pass == 0 ? pa_buf.as<float>() : pb_buf.as<float>();
       io.theta_stride = sd.t * NP;
-      if (want_theta)
-        HIPCHK(hipMemsetAsync(io.theta_part, 0, (size_t)ntiles * sd.t * NP * sizeof(float), s));
+      io.theta_tiles = nt_stage;
       HIPCHK(pmmf::launch_unit_rev(unit_view(h, sd), io, 2, want_theta, cfg.wpb, s));
       HIPCHK(pmmf::launch_sweep_rev(v, io, W2, 2, want_theta, s));
     }
     if (d_theta_bar)
-      HIPCHK(pmmf::launch_theta_reduce((int)(sd.t * NP), ntiles, sd.t * NP, pa_buf.as<float>(),
+      HIPCHK(pmmf::launch_theta_reduce((int)(sd.t * NP), nt_stage, sd.t * NP, pa_buf.as<float>(),
                                        pb_buf.as<float>(), sd.rot_base * NP, d_theta_bar, s));
   }
   // k = 3: plane derivatives -> derivatives in the angles (derivative of the exponential map)

@@ -42,6 +42,45 @@ struct UnitStage {
   int64_t rot_base;          // canonical index of the stage's first rotation
 };
 
+// The trailing stages, whose active sets are small, as one launch per direction.  A workgroup
+// owns one column of the vector block and keeps that column of the whole active set in LDS from
+// the first trailing stage to the core: each stage's rows sit in unit order (unit u's rows at
+// consecutive slots), one thread walks one unit's rotations, and between stages the survivors
+// move to their slots of the next stage.  A stage's program is one contiguous block of device
+// memory, [nu + 1] {first slot, first rotation} per unit, then [t] unit-local slots (5 bits each,
+// slot a at bit 5a), then [t][k*k] rotation blocks (each part 16-byte aligned); it is copied into
+// LDS by direct-to-LDS loads while the stage before it is computed.
+constexpr int TAIL_MAX_STAGES = 16;
+constexpr int TAIL_THREADS = 1024;
+constexpr int TAIL_J = 8;  // slots per thread: a trailing stage has at most TAIL_THREADS * TAIL_J rows
+struct TailStage {
+  int rows;           // |S_{p-1}|
+  int t;              // rotations
+  int nu;             // units
+  int blob_bytes;     // size of the program block (a multiple of 16)
+  int64_t blob_off;   // byte offset of the block in TailPlan::blob
+  int64_t slot_off;   // offset of the stage's per-slot entries in trans, pos, gid
+};
+struct TailPlan {
+  int nst = 0;        // trailing stages (0: none)
+  int data_bytes = 0; // LDS bytes of the rows (first stage's rows, 16-byte aligned)
+  int lds_bytes = 0;  // data_bytes + the largest pair of consecutive program blocks
+  const uint8_t* blob = nullptr;
+  const int32_t* trans = nullptr;  // per slot: >= 0 the slot in the next stage (last stage: the
+                                   // position in the core's compact rows), < 0: -(gid + 1)
+  const int32_t* pos = nullptr;    // per slot: position in S_{p-1}
+  const int32_t* gid = nullptr;    // per slot: global id
+  TailStage st[TAIL_MAX_STAGES];
+};
+// program block layout shared by the host that builds it and the kernels that read it
+__host__ __device__ inline int tail_prog_off(int nu) { return 8 * (nu + 1); }
+__host__ __device__ inline int tail_o_off(int nu, int t) {
+  return (tail_prog_off(nu) + 4 * t + 15) & ~15;
+}
+__host__ __device__ inline int tail_blob_bytes(int nu, int t, int k) {
+  return (tail_o_off(nu, t) + 4 * t * k * k + 15) & ~15;
+}
+
 struct FwdIO {
   const float* src[2];       // compact rows of S_{p-1}
   int64_t ld_src;
@@ -67,11 +106,23 @@ struct RevIO {
   float* dst_nat[2];         // if set: write natural rows instead (first stage)
   int64_t ld_dnat;
   int64_t nrhs;
-  float* theta_part;         // [ntiles][theta_stride] per-tile angle-gradient partials
-  int64_t theta_stride;
+  float* theta_part;         // [theta_tiles][theta_stride] per-tile angle-gradient partials; a
+  int64_t theta_stride;      // launch with fewer column tiles writes zeros into the rows past
+  int theta_tiles;           // its own, so the buffer needs no clearing
 };
 
 size_t sweep_lds_bytes(int k, int W, int nv, int cmax, int rmax);
+// trailing stages of U (from the compact rows io.src[0] to the core's compact rows io.dst_c[0],
+// retired rows to io.dst_nat[0] scaled by io.mode[0]) and of U^T (from the core's rows
+// io.src_c[0] and the retired rows io.src_nat[0], which are copied (mode 0 only), to the compact
+// rows io.dst_c[0] of the first trailing stage or, if io.dst_nat[0] is set, to natural rows);
+// one vector, grid = nrhs workgroups
+hipError_t launch_tail_fwd(int k, const TailPlan& tp, const FwdIO& io, hipStream_t s);
+hipError_t launch_tail_rev(int k, const TailPlan& tp, const RevIO& io, hipStream_t s);
+// the rotation blocks of the program blocks from the canonical blocks: entry e of the programs
+// (canonical rotation idx[e]) at float offset dst[e] of the blob
+hipError_t launch_tail_params(int64_t n, int k, const int32_t* idx, const int64_t* dst,
+                              const float* rot_o, uint8_t* blob, hipStream_t s);
 // wpb: waves (units) per workgroup, 1, 2 or 4
 hipError_t launch_unit_fwd(const UnitStage& st, const FwdIO& io, int nv, int wpb, hipStream_t s);
 hipError_t launch_unit_rev(const UnitStage& st, const RevIO& io, int nv, bool theta, int wpb,

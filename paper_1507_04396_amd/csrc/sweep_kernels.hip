@@ -168,9 +168,13 @@ __global__ void __launch_bounds__(256) k_sweep_rev(SweepStage st, RevIO io) {
           // reduce over the W consecutive lanes holding one rotation's columns
 #pragma unroll
           for (int ofs = W / 2; ofs > 0; ofs >>= 1) part += __shfl_xor(part, ofs, W);
-          if (live && w == 0)
-            io.theta_part[(size_t)blockIdx.y * io.theta_stride +
-                          (size_t)(st.sw_idx[rr + rb] - st.rot_base) * NP + m] = part;
+          if (live && w == 0) {
+            const size_t at = (size_t)(st.sw_idx[rr + rb] - st.rot_base) * NP + m;
+            io.theta_part[(size_t)blockIdx.y * io.theta_stride + at] = part;
+            if (blockIdx.y == gridDim.y - 1)
+              for (int y = blockIdx.y + 1; y < io.theta_tiles; ++y)
+                io.theta_part[(size_t)y * io.theta_stride + at] = 0.f;
+          }
         }
       }
       if (live) rotate_cols<K, W, NV, true>(tile, cstride, rid + rr * K, rob + rr * K * K, w);
@@ -262,69 +266,99 @@ hipError_t launch_sweep_rev(const SweepStage& st, const RevIO& io, int W, int nv
 
 // ------------------------------------------------------------------------------------------
 // dense FP32 GEMM  C[M][N] = op(A)[M][K] * op(B)[K][N] (+ beta C), row-major, op = transpose if
-// flagged.  32 x 32 output tile per workgroup, one 16 x 16 quarter per wave on
-// v_mfma_f32_16x16x4f32 (A operand: lane l holds A[l % 16][l / 16], B operand B[l / 16][l % 16],
-// result row 4 (l / 16) + r, column l % 16 in register r).  K advances in 128-deep slices staged
-// in LDS; the next slice is fetched into registers while the current one is multiplied.
+// flagged.  The products here are small (a core of a few hundred to a few thousand rows against
+// at most a few hundred vectors), so a workgroup takes one 16 x 16 output tile and its four waves
+// split K: K is cut into 16-deep blocks, wave w takes blocks w, w + 4, ..., and each block is four
+// v_mfma_f32_16x16x4f32 (A operand: lane l holds A[l % 16][.], B operand B[.][l % 16]; lane group
+// l / 16 takes k = 4 (l / 16) + s of the block in step s, the same k for both operands, so the sum
+// runs over every k once).  Lanes read their operands straight from memory (the core and the
+// vectors stay in L2), four blocks per wave at a time with the next four in flight; the four
+// partial tiles are added in LDS in wave order, so the result does not depend on timing.
 typedef float pmmf_f4 __attribute__((ext_vector_type(4)));
-constexpr int GEMM_T = 32, GEMM_K = 128, GEMM_PER = GEMM_T * GEMM_K / 256;
+constexpr int GEMM_T = 16, GEMM_KB = 16, GEMM_WAVES = 4, GEMM_BPW = 4;
+// VA / VB: the operand's k runs along its rows (A not transposed / B transposed) in 16-byte
+// aligned rows with K a multiple of 4: a lane's four k of a block are one 16-byte load
+template <bool VA, bool VB>
 __global__ void __launch_bounds__(256) k_gemm(int M, int N, int K, const float* __restrict__ A,
                                               int lda, int ta, const float* __restrict__ B,
                                               int ldb, int tb, float* __restrict__ C, int ldc,
                                               float beta) {
-  __shared__ float As[GEMM_T][GEMM_K + 1];
-  __shared__ float Bs[GEMM_K][GEMM_T + 1];
-  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  __shared__ pmmf_f4 part[GEMM_WAVES - 1][PMMF_WAVE];
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int r = lane & 15, grp = lane >> 4;
   const int m0 = blockIdx.y * GEMM_T, n0 = blockIdx.x * GEMM_T;
-  const int wm = (w >> 1) * 16, wn = (w & 1) * 16;
-  float ra[GEMM_PER], rb[GEMM_PER];
-  auto a_index = [&](int q, int& m, int& k) {
-    if (ta) { k = q / GEMM_T; m = q % GEMM_T; } else { m = q / GEMM_K; k = q % GEMM_K; }
-  };
-  auto b_index = [&](int q, int& k, int& n) {
-    if (tb) { n = q / GEMM_K; k = q % GEMM_K; } else { k = q / GEMM_T; n = q % GEMM_T; }
-  };
-  auto fetch = [&](int k0) {
+  const bool mok = m0 + r < M, nok = n0 + r < N;
+  const int64_t gm = min(m0 + r, M - 1), gn = min(n0 + r, N - 1);
+  const int nb = (K + GEMM_KB - 1) / GEMM_KB;
+  constexpr int PER_IT = GEMM_WAVES * GEMM_BPW;  // blocks per iteration of the whole workgroup
+  const int nit = (nb + PER_IT - 1) / PER_IT;
+  float fa0[GEMM_BPW][4], fb0[GEMM_BPW][4], fa1[GEMM_BPW][4], fb1[GEMM_BPW][4];
+  // block it * PER_IT + j * GEMM_WAVES + w; addresses clamped into the matrices, values past the
+  // edges replaced by zero after the load
+  auto fetch = [&](int it, float (&xa)[GEMM_BPW][4], float (&xb)[GEMM_BPW][4]) {
 #pragma unroll
-    for (int p = 0; p < GEMM_PER; ++p) {
-      const int q = tid + p * 256;
-      int m, k, n, kb;
-      a_index(q, m, k);
-      b_index(q, kb, n);
-      const int gm = m0 + m, gk = k0 + k, gn = n0 + n, gkb = k0 + kb;
-      ra[p] = (gm < M && gk < K) ? (ta ? A[(size_t)gk * lda + gm] : A[(size_t)gm * lda + gk]) : 0.f;
-      rb[p] = (gn < N && gkb < K) ? (tb ? B[(size_t)gn * ldb + gkb] : B[(size_t)gkb * ldb + gn])
-                                  : 0.f;
+    for (int j = 0; j < GEMM_BPW; ++j) {
+      const int kb = (it * PER_IT + j * GEMM_WAVES + w) * GEMM_KB + 4 * grp;
+      if constexpr (VA) {
+        const pmmf_f4 a4 = *reinterpret_cast<const pmmf_f4*>(A + gm * lda + min(kb, K - 4));
+        const bool ok = mok && kb < K;
+#pragma unroll
+        for (int s4 = 0; s4 < 4; ++s4) xa[j][s4] = ok ? a4[s4] : 0.f;
+      }
+      if constexpr (VB) {
+        const pmmf_f4 b4 = *reinterpret_cast<const pmmf_f4*>(B + gn * ldb + min(kb, K - 4));
+        const bool ok = nok && kb < K;
+#pragma unroll
+        for (int s4 = 0; s4 < 4; ++s4) xb[j][s4] = ok ? b4[s4] : 0.f;
+      }
+#pragma unroll
+      for (int s4 = 0; s4 < 4; ++s4) {
+        const int k = kb + s4;
+        const int64_t kc = min(k, K - 1);
+        if constexpr (!VA) {
+          const float va = ta ? A[kc * lda + gm] : A[gm * lda + kc];
+          xa[j][s4] = (mok && k < K) ? va : 0.f;
+        }
+        if constexpr (!VB) {
+          const float vb = tb ? B[gn * ldb + kc] : B[kc * ldb + gn];
+          xb[j][s4] = (nok && k < K) ? vb : 0.f;
+        }
+      }
     }
   };
-  pmmf_f4 acc = {0.f, 0.f, 0.f, 0.f};
-  fetch(0);
-  for (int k0 = 0; k0 < K; k0 += GEMM_K) {
+  pmmf_f4 acc0 = {0.f, 0.f, 0.f, 0.f}, acc1 = {0.f, 0.f, 0.f, 0.f};
+  auto mult = [&](const float (&xa)[GEMM_BPW][4], const float (&xb)[GEMM_BPW][4]) {
 #pragma unroll
-    for (int p = 0; p < GEMM_PER; ++p) {
-      const int q = tid + p * 256;
-      int m, k, n, kb;
-      a_index(q, m, k);
-      b_index(q, kb, n);
-      As[m][k] = ra[p];
-      Bs[kb][n] = rb[p];
+    for (int j = 0; j < GEMM_BPW; ++j) {
+#pragma unroll
+      for (int s4 = 0; s4 < 4; s4 += 2) {
+        acc0 = __builtin_amdgcn_mfma_f32_16x16x4f32(xa[j][s4], xb[j][s4], acc0, 0, 0, 0);
+        acc1 = __builtin_amdgcn_mfma_f32_16x16x4f32(xa[j][s4 + 1], xb[j][s4 + 1], acc1, 0, 0, 0);
+      }
     }
-    __syncthreads();
-    if (k0 + GEMM_K < K) fetch(k0 + GEMM_K);
-#pragma unroll 8
-    for (int kk = 0; kk < GEMM_K; kk += 4) {
-      const float av = As[wm + (lane & 15)][kk + (lane >> 4)];
-      const float bv = Bs[kk + (lane >> 4)][wn + (lane & 15)];
-      acc = __builtin_amdgcn_mfma_f32_16x16x4f32(av, bv, acc, 0, 0, 0);
-    }
-    __syncthreads();
+  };
+  // two register sets used in turn: the next iteration's operands are in flight while the
+  // current ones are multiplied
+  if (nit > 0) fetch(0, fa0, fb0);
+  for (int it = 0; it < nit; it += 2) {
+    if (it + 1 < nit) fetch(it + 1, fa1, fb1);
+    mult(fa0, fb0);
+    if (it + 1 >= nit) break;
+    if (it + 2 < nit) fetch(it + 2, fa0, fb0);
+    mult(fa1, fb1);
   }
+  pmmf_f4 acc = acc0 + acc1;
+  if (w > 0) part[w - 1][lane] = acc;
+  __syncthreads();
+  if (w != 0) return;
 #pragma unroll
-  for (int r = 0; r < 4; ++r) {
-    const int gm = m0 + wm + 4 * (lane >> 4) + r, gn = n0 + wn + (lane & 15);
-    if (gm < M && gn < N) {
-      float* cp = C + (size_t)gm * ldc + gn;
-      *cp = beta == 0.f ? acc[r] : beta * *cp + acc[r];
+  for (int q = 0; q < GEMM_WAVES - 1; ++q) acc += part[q][lane];
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    const int cm = m0 + 4 * grp + i, cn = n0 + r;
+    if (cm < M && cn < N) {
+      float* cp = C + (size_t)cm * ldc + cn;
+      *cp = beta == 0.f ? acc[i] : beta * *cp + acc[i];
     }
   }
 }
@@ -333,7 +367,15 @@ hipError_t launch_gemm(int M, int N, int K, const float* A, int lda, int ta, con
                        int ldb, int tb, float* C, int ldc, float beta, hipStream_t s) {
   if (M == 0 || N == 0) return hipSuccess;
   dim3 grid((N + GEMM_T - 1) / GEMM_T, (M + GEMM_T - 1) / GEMM_T);
-  k_gemm<<<grid, 256, 0, s>>>(M, N, K, A, lda, ta, B, ldb, tb, C, ldc, beta);
+  auto rows16 = [&](const float* p, int ld) {
+    return K % 4 == 0 && ld % 4 == 0 && (reinterpret_cast<uintptr_t>(p) & 15) == 0;
+  };
+  const bool va = !ta && rows16(A, lda), vb = tb && rows16(B, ldb);
+  const int th = GEMM_WAVES * PMMF_WAVE;
+  if (va && vb) k_gemm<true, true><<<grid, th, 0, s>>>(M, N, K, A, lda, ta, B, ldb, tb, C, ldc, beta);
+  else if (va) k_gemm<true, false><<<grid, th, 0, s>>>(M, N, K, A, lda, ta, B, ldb, tb, C, ldc, beta);
+  else if (vb) k_gemm<false, true><<<grid, th, 0, s>>>(M, N, K, A, lda, ta, B, ldb, tb, C, ldc, beta);
+  else k_gemm<false, false><<<grid, th, 0, s>>>(M, N, K, A, lda, ta, B, ldb, tb, C, ldc, beta);
   return hipGetLastError();
 }
 
@@ -608,7 +650,12 @@ __global__ void __launch_bounds__(256) k_unit_sweep(UnitStage st, FwdIO fio, Rev
           const int pp = m == 2 ? 1 : 0, qq = m == 0 ? 1 : 2;
           float part = cok ? T(1, id[qq]) * T(0, id[pp]) - T(1, id[pp]) * T(0, id[qq]) : 0.f;
           part = pmmf_wave_sum_dpp(part);
-          if (lane == 0) rio.theta_part[at + m] = part;
+          if (lane == 0) {
+            rio.theta_part[at + m] = part;
+            if (blockIdx.y == gridDim.y - 1)
+              for (int y = blockIdx.y + 1; y < rio.theta_tiles; ++y)
+                rio.theta_part[at + (int64_t)(y - blockIdx.y) * rio.theta_stride + m] = 0.f;
+          }
         }
       }
 #pragma unroll
@@ -686,6 +733,292 @@ hipError_t launch_unit_rev(const UnitStage& st, const RevIO& io, int nv, bool th
   if (theta) return unit_launch<3, 2, 2>(st, none, io, wpb, s);
   return nv == 1 ? unit_launch<3, 1, 1>(st, none, io, wpb, s)
                  : unit_launch<3, 2, 1>(st, none, io, wpb, s);
+}
+
+// ------------------------------------------------------------------------------------------
+// Trailing stages (TailPlan): one workgroup of TAIL_THREADS per column.  Thread tid owns the slots
+// tid + j * TAIL_THREADS (j < TAIL_J) for the moves between stages, and unit tid (+ multiples of
+// TAIL_THREADS) for the rotations.  Loads go out one stage ahead (the next program block straight
+// into LDS, the next stage's slot table and the values it needs into registers), the current
+// stage is computed from LDS meanwhile, and stores are issued at the start of the following
+// stage, so the wait for the loads at the end of a stage does not also wait for fresh stores.
+typedef __attribute__((address_space(3))) void* pmmf_lds_ptr;
+
+// issue the copy of stage s's program block into LDS at dst (16 bytes per lane; the LDS address
+// of a wave's request is the wave's first chunk, lanes follow at 16-byte steps)
+__device__ inline void tail_copy_block(const TailPlan& tp, int s, unsigned char* dst) {
+  const int nch = tp.st[s].blob_bytes >> 4;
+  const unsigned char* src = tp.blob + tp.st[s].blob_off;
+  const int tid = threadIdx.x;
+  for (int c0 = 0; c0 < nch; c0 += TAIL_THREADS) {
+    const int wfirst = __builtin_amdgcn_readfirstlane(c0 + (tid & ~(PMMF_WAVE - 1)));
+    if (wfirst >= nch) break;
+    const int c = c0 + tid;
+    if (c < nch)
+      __builtin_amdgcn_global_load_lds((const void*)(src + (size_t)c * 16),
+                                       (pmmf_lds_ptr)(dst + (size_t)wfirst * 16), 16, 0, 0);
+  }
+}
+
+// stage s's program block: even stages right after the rows, odd stages at the end of the
+// workgroup's LDS, so two consecutive blocks never overlap
+__device__ inline unsigned char* tail_block(const TailPlan& tp, unsigned char* lds, int s) {
+  return (s & 1) ? lds + tp.lds_bytes - tp.st[s].blob_bytes : lds + tp.data_bytes;
+}
+
+// wait for every outstanding vector memory operation (the direct-to-LDS copies included)
+__device__ inline void tail_wait_mem() { __builtin_amdgcn_s_waitcnt(0x0F70); }
+
+// the rotations of one stage: thread per unit, in order (forward: O) or reversed with transposed
+// blocks (U^T), on the rows in LDS.  Same arithmetic as the unit sweep.
+template <int K, bool REV>
+__device__ inline void tail_rotate(const unsigned char* blk, int nu, int t, float* data) {
+  const int2* units = reinterpret_cast<const int2*>(blk);
+  const int* prog = reinterpret_cast<const int*>(blk + tail_prog_off(nu));
+  const float* ob = reinterpret_cast<const float*>(blk + tail_o_off(nu, t));
+  for (int u = threadIdx.x; u < nu; u += TAIL_THREADS) {
+    const int2 a = units[u], b = units[u + 1];
+    const int sb = a.x;
+    const int n = b.y - a.y;
+    for (int i = 0; i < n; ++i) {
+      const int q = REV ? b.y - 1 - i : a.y + i;
+      const int packed = prog[q];
+      float o[K * K];
+#pragma unroll
+      for (int ab = 0; ab < K * K; ++ab) o[ab] = ob[(size_t)q * K * K + ab];
+      int id[K];
+      float y[K];
+#pragma unroll
+      for (int c = 0; c < K; ++c) {
+        id[c] = sb + ((packed >> (5 * c)) & 31);
+        y[c] = data[id[c]];
+      }
+#pragma unroll
+      for (int c = 0; c < K; ++c) {
+        float acc = 0.f;
+#pragma unroll
+        for (int d = 0; d < K; ++d) acc += (REV ? o[d * K + c] : o[c * K + d]) * y[d];
+        data[id[c]] = acc;
+      }
+    }
+  }
+}
+
+template <int K>
+__global__ void __launch_bounds__(TAIL_THREADS) k_tail_fwd(TailPlan tp, FwdIO io) {
+  extern __shared__ __align__(16) unsigned char tail_lds[];
+  float* data = reinterpret_cast<float*>(tail_lds);
+  const int tid = threadIdx.x;
+  const int64_t col = pmmf_xcd_block(blockIdx.x, gridDim.x);
+  const int nst = tp.nst;
+  tail_copy_block(tp, 0, tail_block(tp, tail_lds, 0));
+  int tc[TAIL_J], tn[TAIL_J], rg[TAIL_J];
+  float v[TAIL_J], rv[TAIL_J];
+  {
+    const int rows = tp.st[0].rows;
+    int ps[TAIL_J];
+#pragma unroll
+    for (int j = 0; j < TAIL_J; ++j) {
+      const int i = min(tid + j * TAIL_THREADS, rows - 1);
+      ps[j] = tp.pos[tp.st[0].slot_off + i];
+      tc[j] = tp.trans[tp.st[0].slot_off + i];
+    }
+#pragma unroll
+    for (int j = 0; j < TAIL_J; ++j) v[j] = io.src[0][(int64_t)ps[j] * io.ld_src + col];
+#pragma unroll
+    for (int j = 0; j < TAIL_J; ++j) {
+      const int i = tid + j * TAIL_THREADS;
+      if (i < rows) data[i] = v[j];
+      rg[j] = -1;
+      rv[j] = 0.f;
+    }
+  }
+  tail_wait_mem();
+  __syncthreads();
+  for (int s = 0; s < nst; ++s) {
+    const int rows = tp.st[s].rows;
+    // retired rows of the previous stage
+#pragma unroll
+    for (int j = 0; j < TAIL_J; ++j)
+      if (rg[j] >= 0) io.dst_nat[0][(int64_t)rg[j] * io.ld_nat + col] = rv[j];
+    if (s + 1 < nst) {
+      tail_copy_block(tp, s + 1, tail_block(tp, tail_lds, s + 1));
+      const int rn = tp.st[s + 1].rows;
+#pragma unroll
+      for (int j = 0; j < TAIL_J; ++j)
+        tn[j] = tp.trans[tp.st[s + 1].slot_off + min(tid + j * TAIL_THREADS, rn - 1)];
+    }
+    float hd[TAIL_J];
+#pragma unroll
+    for (int j = 0; j < TAIL_J; ++j)
+      hd[j] = io.mode[0] != 0 ? io.hdiag[tc[j] < 0 ? -tc[j] - 1 : 0] : 1.f;
+    tail_rotate<K, false>(tail_block(tp, tail_lds, s), tp.st[s].nu, tp.st[s].t, data);
+    __syncthreads();
+#pragma unroll
+    for (int j = 0; j < TAIL_J; ++j) {
+      const int i = min(tid + j * TAIL_THREADS, rows - 1);
+      v[j] = data[i];
+    }
+    __syncthreads();
+    const bool last = s + 1 == nst;
+#pragma unroll
+    for (int j = 0; j < TAIL_J; ++j) {
+      rg[j] = -1;
+      if (tid + j * TAIL_THREADS >= rows) continue;
+      if (tc[j] >= 0) {
+        if (!last) data[tc[j]] = v[j];
+        else io.dst_c[0][(int64_t)tc[j] * io.ld_c + col] = v[j];
+      } else {
+        float val = v[j];
+        if (io.mode[0] == 1) val *= hd[j];
+        else if (io.mode[0] == 2) val /= hd[j];
+        else if (io.mode[0] == 3) val /= sqrtf(hd[j]);
+        rv[j] = val;
+        rg[j] = -tc[j] - 1;
+      }
+    }
+    if (last) break;
+    tail_wait_mem();
+    __syncthreads();
+#pragma unroll
+    for (int j = 0; j < TAIL_J; ++j) tc[j] = tn[j];
+  }
+#pragma unroll
+  for (int j = 0; j < TAIL_J; ++j)
+    if (rg[j] >= 0) io.dst_nat[0][(int64_t)rg[j] * io.ld_nat + col] = rv[j];
+}
+
+template <int K>
+__global__ void __launch_bounds__(TAIL_THREADS) k_tail_rev(TailPlan tp, RevIO io) {
+  extern __shared__ __align__(16) unsigned char tail_lds[];
+  float* data = reinterpret_cast<float*>(tail_lds);
+  const int tid = threadIdx.x;
+  const int64_t col = pmmf_xcd_block(blockIdx.x, gridDim.x);
+  const int L = tp.nst - 1;
+  tail_copy_block(tp, L, tail_block(tp, tail_lds, L));
+  // tc: this stage's slot table, t1 / t2: the next two stages down; rv: the retired rows the
+  // next stage down takes from natural order
+  int tc[TAIL_J], t1[TAIL_J], t2[TAIL_J];
+  float v[TAIL_J], rv[TAIL_J];
+  {
+    const int rows = tp.st[L].rows, r1 = tp.st[L - 1].rows;
+#pragma unroll
+    for (int j = 0; j < TAIL_J; ++j) {
+      tc[j] = tp.trans[tp.st[L].slot_off + min(tid + j * TAIL_THREADS, rows - 1)];
+      t1[j] = tp.trans[tp.st[L - 1].slot_off + min(tid + j * TAIL_THREADS, r1 - 1)];
+    }
+#pragma unroll
+    for (int j = 0; j < TAIL_J; ++j) {
+      const float a = io.src_c[0][(int64_t)max(tc[j], 0) * io.ld_c + col];
+      const float b = io.src_nat[0][(int64_t)(tc[j] < 0 ? -tc[j] - 1 : 0) * io.ld_nat + col];
+      v[j] = tc[j] >= 0 ? a : b;
+    }
+#pragma unroll
+    for (int j = 0; j < TAIL_J; ++j) {
+      const int i = tid + j * TAIL_THREADS;
+      if (i < rows) data[i] = v[j];
+    }
+  }
+  tail_wait_mem();
+  __syncthreads();
+  for (int s = L; s >= 0; --s) {
+    if (s > 0) {
+      tail_copy_block(tp, s - 1, tail_block(tp, tail_lds, s - 1));
+#pragma unroll
+      for (int j = 0; j < TAIL_J; ++j)
+        rv[j] = io.src_nat[0][(int64_t)(t1[j] < 0 ? -t1[j] - 1 : 0) * io.ld_nat + col];
+      if (s > 1) {
+        const int r2 = tp.st[s - 2].rows;
+#pragma unroll
+        for (int j = 0; j < TAIL_J; ++j)
+          t2[j] = tp.trans[tp.st[s - 2].slot_off + min(tid + j * TAIL_THREADS, r2 - 1)];
+      }
+    } else {
+      // output rows of the first trailing stage: positions of S_{p-1}, or global ids
+      const int r0 = tp.st[0].rows;
+      const int32_t* map = io.dst_nat[0] ? tp.gid : tp.pos;
+#pragma unroll
+      for (int j = 0; j < TAIL_J; ++j) t2[j] = map[tp.st[0].slot_off + min(tid + j * TAIL_THREADS, r0 - 1)];
+    }
+    tail_rotate<K, true>(tail_block(tp, tail_lds, s), tp.st[s].nu, tp.st[s].t, data);
+    __syncthreads();
+    if (s == 0) break;
+    const int rn = tp.st[s - 1].rows;
+#pragma unroll
+    for (int j = 0; j < TAIL_J; ++j) {
+      const float a = data[max(t1[j], 0)];
+      v[j] = t1[j] >= 0 ? a : rv[j];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int j = 0; j < TAIL_J; ++j) {
+      const int i = tid + j * TAIL_THREADS;
+      if (i < rn) data[i] = v[j];
+    }
+    tail_wait_mem();
+    __syncthreads();
+#pragma unroll
+    for (int j = 0; j < TAIL_J; ++j) {
+      tc[j] = t1[j];
+      t1[j] = t2[j];
+    }
+  }
+  const int r0 = tp.st[0].rows;
+  float* out = io.dst_nat[0] ? io.dst_nat[0] : io.dst_c[0];
+  const int64_t ldo = io.dst_nat[0] ? io.ld_dnat : io.ld_out;
+#pragma unroll
+  for (int j = 0; j < TAIL_J; ++j) {
+    const int i = tid + j * TAIL_THREADS;
+    if (i < r0) out[(int64_t)t2[j] * ldo + col] = data[i];
+  }
+}
+
+template <int K>
+static hipError_t tail_launch_fwd(const TailPlan& tp, const FwdIO& io, hipStream_t s) {
+  hipError_t e = hipFuncSetAttribute((const void*)k_tail_fwd<K>,
+                                     hipFuncAttributeMaxDynamicSharedMemorySize, tp.lds_bytes);
+  if (e != hipSuccess) return e;
+  k_tail_fwd<K><<<(unsigned)io.nrhs, TAIL_THREADS, tp.lds_bytes, s>>>(tp, io);
+  return hipGetLastError();
+}
+template <int K>
+static hipError_t tail_launch_rev(const TailPlan& tp, const RevIO& io, hipStream_t s) {
+  hipError_t e = hipFuncSetAttribute((const void*)k_tail_rev<K>,
+                                     hipFuncAttributeMaxDynamicSharedMemorySize, tp.lds_bytes);
+  if (e != hipSuccess) return e;
+  k_tail_rev<K><<<(unsigned)io.nrhs, TAIL_THREADS, tp.lds_bytes, s>>>(tp, io);
+  return hipGetLastError();
+}
+
+hipError_t launch_tail_fwd(int k, const TailPlan& tp, const FwdIO& io, hipStream_t s) {
+  if (io.nrhs == 0 || tp.nst == 0) return hipSuccess;
+  if (tp.nst < 2 || tp.nst > TAIL_MAX_STAGES || tp.st[0].rows > TAIL_THREADS * TAIL_J)
+    return hipErrorInvalidValue;
+  return k == 2 ? tail_launch_fwd<2>(tp, io, s) : tail_launch_fwd<3>(tp, io, s);
+}
+hipError_t launch_tail_rev(int k, const TailPlan& tp, const RevIO& io, hipStream_t s) {
+  if (io.nrhs == 0 || tp.nst == 0) return hipSuccess;
+  if (tp.nst < 2 || tp.nst > TAIL_MAX_STAGES || tp.st[0].rows > TAIL_THREADS * TAIL_J ||
+      io.mode[0] != 0)
+    return hipErrorInvalidValue;
+  return k == 2 ? tail_launch_rev<2>(tp, io, s) : tail_launch_rev<3>(tp, io, s);
+}
+
+__global__ void k_tail_params(int64_t n, int k, const int32_t* __restrict__ idx,
+                              const int64_t* __restrict__ dst, const float* __restrict__ rot_o,
+                              float* __restrict__ blob) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= n) return;
+  const int64_t r = idx[e], d = dst[e];
+  for (int a = 0; a < k; ++a)
+    for (int b = 0; b < k; ++b) blob[d + a * k + b] = rot_o[r * 9 + a * 3 + b];
+}
+hipError_t launch_tail_params(int64_t n, int k, const int32_t* idx, const int64_t* dst,
+                              const float* rot_o, uint8_t* blob, hipStream_t s) {
+  if (n == 0) return hipSuccess;
+  k_tail_params<<<(unsigned)((n + 255) / 256), 256, 0, s>>>(n, k, idx, dst, rot_o,
+                                                          reinterpret_cast<float*>(blob));
+  return hipGetLastError();
 }
 
 // core rows: compact buffer of the final active set -> natural rows of the core ids

@@ -424,8 +424,12 @@ def test_split_symmetric_pcg_small_spd_grid_matches_dense_solve():
     assert res.max() <= 1e-6, res
     Xref = np.linalg.solve(Ad, B.astype(np.float64))
     assert rel_err(Xn, Xref) <= 1e-6 * np.linalg.cond(Ad)
-    # the two forms produce the same iterates in exact arithmetic: similar iteration counts
-    assert abs(info["iterations"] - info1["iterations"]) <= max(5, 0.25 * info1["iterations"])
+    # the two forms produce the same iterates in exact arithmetic: each inner solve (one
+    # refinement, a fixed residual reduction) takes a similar number of iterations.  Whether the
+    # last refinement lands just under the tolerance or needs one more depends on rounding, so the
+    # totals are compared per refinement.
+    per, per1 = info["iterations"] / info["refinements"], info1["iterations"] / info1["refinements"]
+    assert abs(per - per1) <= max(5, 0.25 * per1), (info, info1)
 
 
 def test_pcg_full_size_grid3d_n1050703():
