@@ -1996,6 +1996,11 @@ __global__ void __launch_bounds__(NT) k_search(FindArgs A, int cmax) {
   }
 
   // ------------------------------------------------------------------ column waves
+  // At equal priority wave 4 reaches barrier B last in nearly every step, ~2.5k cycles after the
+  // other waves (per-wave timestamps), as a wave sharing a SIMD with the control wave's FP64
+  // rotation arithmetic would; at a higher issue priority it no longer does, and the step
+  // shortens by ~2% (the control wave then arrives last).
+  if (wv == 4) __builtin_amdgcn_s_setprio(2);
   const int ct = tid - PMMF_WAVE;
   int jl[PER];           // own columns clamped into the cluster, for address forming
   float rg[PER];         // 1 / sqrt(G_jj) of the own columns
@@ -3832,10 +3837,21 @@ hipError_t launch_scan(const int32_t* in, int64_t* out, int64_t n, int64_t* tmp,
 }
 
 // deterministic FP64 sum (one block, fixed order)
+// one workgroup, a fixed summation order (four interleaved partial sums per thread, so four
+// loads are in flight per thread, then the waves' sums in wave order)
 __global__ void k_sum_double(const double* __restrict__ in, int64_t n, double* __restrict__ out) {
   __shared__ double part[1024 / PMMF_WAVE];
-  double v = 0.0;
-  for (int64_t i = threadIdx.x; i < n; i += blockDim.x) v += in[i];
+  const int64_t bd = blockDim.x;
+  double v0 = 0.0, v1 = 0.0, v2 = 0.0, v3 = 0.0;
+  int64_t i = threadIdx.x;
+  for (; i + 3 * bd < n; i += 4 * bd) {
+    v0 += in[i];
+    v1 += in[i + bd];
+    v2 += in[i + 2 * bd];
+    v3 += in[i + 3 * bd];
+  }
+  for (; i < n; i += bd) v0 += in[i];
+  double v = (v0 + v1) + (v2 + v3);
   v = pmmf_wave_sum_double(v);
   if (pmmf_lane() == 0) part[pmmf_wave()] = v;
   __syncthreads();
@@ -3901,17 +3917,34 @@ hipError_t launch_core_dense(int S, const int64_t* rp, const int32_t* ci, const 
 __global__ void k_h_stats(int64_t n, const float* __restrict__ hdiag, int64_t core,
                           const float* __restrict__ hcore, double* __restrict__ out) {
   __shared__ double p1[1024 / PMMF_WAVE], p2[1024 / PMMF_WAVE];
-  double f = 0.0, t = 0.0;
-  for (int64_t i = threadIdx.x; i < n; i += blockDim.x) {
-    const double v = hdiag[i];
-    f += v * v;
-    t += v;
+  const int64_t bd = blockDim.x;
+  // sums of squares over hdiag and hcore, two interleaved partial sums per thread; trace of
+  // hdiag plus the core's diagonal
+  double f0 = 0.0, f1 = 0.0, t = 0.0;
+  int64_t i = threadIdx.x;
+  for (; i + bd < n; i += 2 * bd) {
+    const double a = hdiag[i], b = hdiag[i + bd];
+    f0 += a * a;
+    f1 += b * b;
+    t += a + b;
   }
-  for (int64_t i = threadIdx.x; i < core * core; i += blockDim.x) {
-    const double v = hcore[i];
-    f += v * v;
-    if (i / core == i % core) t += v;
+  for (; i < n; i += bd) {
+    const double a = hdiag[i];
+    f0 += a * a;
+    t += a;
   }
+  const int64_t cc = core * core;
+  for (i = threadIdx.x; i + bd < cc; i += 2 * bd) {
+    const double a = hcore[i], b = hcore[i + bd];
+    f0 += a * a;
+    f1 += b * b;
+  }
+  for (; i < cc; i += bd) {
+    const double a = hcore[i];
+    f0 += a * a;
+  }
+  for (i = threadIdx.x; i < core; i += bd) t += hcore[i * core + i];
+  double f = f0 + f1;
   f = pmmf_wave_sum_double(f);
   t = pmmf_wave_sum_double(t);
   if (pmmf_lane() == 0) { p1[pmmf_wave()] = f; p2[pmmf_wave()] = t; }
