@@ -540,9 +540,15 @@ __global__ void __launch_bounds__(256) k_unit_sweep(UnitStage st, FwdIO fio, Rev
   const int lane = pmmf_lane();
   const int wv = __builtin_amdgcn_readfirstlane(pmmf_wave());
   float* tile = lds_f + (size_t)wv * NV * UNIT_MAX * PMMF_WAVE;
-  const int g = blockIdx.x * (blockDim.x / PMMF_WAVE) + __builtin_amdgcn_readfirstlane(pmmf_wave());
+  // one-dimensional grid, column tile fastest and consecutive blocks on one XCD: the tiles of a
+  // unit run side by side in one L2, which fetches the unit's description once
+  const int ntile = (int)(((MODE == 0 ? fio.nrhs : rio.nrhs) + PMMF_WAVE - 1) / PMMF_WAVE);
+  const unsigned lb = (unsigned)pmmf_xcd_block((int)blockIdx.x, (int)gridDim.x);
+  const int ctile = (int)(lb % (unsigned)ntile);
+  const int g = (int)(lb / (unsigned)ntile) * (blockDim.x / PMMF_WAVE) +
+                __builtin_amdgcn_readfirstlane(pmmf_wave());
   if (g >= st.nu) return;
-  const int64_t col = (int64_t)blockIdx.y * PMMF_WAVE + lane;
+  const int64_t col = (int64_t)ctile * PMMF_WAVE + lane;
   const int64_t nrhs = MODE == 0 ? fio.nrhs : rio.nrhs;
   const bool cok = col < nrhs;
   const int2 cnt = st.cnt[g];
@@ -643,7 +649,7 @@ __global__ void __launch_bounds__(256) k_unit_sweep(UnitStage st, FwdIO fio, Rev
         // lanes past the last column hold a copy of it: they add nothing.  k = 3: one partial
         // per plane (0,1), (0,2), (1,2) of the slots, <g, G_pq z> = g_q z_p - g_p z_q
         constexpr int NP = K == 3 ? 3 : 1;
-        const int64_t at = (int64_t)blockIdx.y * rio.theta_stride +
+        const int64_t at = (int64_t)ctile * rio.theta_stride +
                            (int64_t)(__builtin_amdgcn_readlane(rt.y, q) - st.rot_base) * NP;
 #pragma unroll
         for (int m = 0; m < NP; ++m) {
@@ -652,9 +658,9 @@ __global__ void __launch_bounds__(256) k_unit_sweep(UnitStage st, FwdIO fio, Rev
           part = pmmf_wave_sum_dpp(part);
           if (lane == 0) {
             rio.theta_part[at + m] = part;
-            if (blockIdx.y == gridDim.y - 1)
-              for (int y = blockIdx.y + 1; y < rio.theta_tiles; ++y)
-                rio.theta_part[at + (int64_t)(y - blockIdx.y) * rio.theta_stride + m] = 0.f;
+            if (ctile == ntile - 1)
+              for (int y = ctile + 1; y < rio.theta_tiles; ++y)
+                rio.theta_part[at + (int64_t)(y - ctile) * rio.theta_stride + m] = 0.f;
           }
         }
       }
@@ -708,8 +714,9 @@ static hipError_t unit_launch(const UnitStage& st, const FwdIO& fio, const RevIO
   if (wpb != 1 && wpb != 2 && wpb != 4) return hipErrorInvalidValue;
   const size_t lds = (size_t)wpb * NV * UNIT_MAX * PMMF_WAVE * sizeof(float);
   const int64_t nrhs = MODE == 0 ? fio.nrhs : rio.nrhs;
-  dim3 grid((st.nu + wpb - 1) / wpb, (unsigned)((nrhs + PMMF_WAVE - 1) / PMMF_WAVE));
-  k_unit_sweep<K, NV, MODE><<<grid, wpb * PMMF_WAVE, lds, s>>>(st, fio, rio);
+  const int64_t blocks = (int64_t)((st.nu + wpb - 1) / wpb) * ((nrhs + PMMF_WAVE - 1) / PMMF_WAVE);
+  if (blocks > 0x7fffffff) return hipErrorInvalidValue;
+  k_unit_sweep<K, NV, MODE><<<(unsigned)blocks, wpb * PMMF_WAVE, lds, s>>>(st, fio, rio);
   return hipGetLastError();
 }
 
