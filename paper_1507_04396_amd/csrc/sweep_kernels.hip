@@ -529,17 +529,17 @@ hipError_t launch_theta_reduce(int t, int ntiles, int64_t stride, const float* p
 // ------------------------------------------------------------------------------------------
 // Unit sweeps: one wave per (unit, 64-column slice), lane = column.  The unit's description (row
 // slots, rotation slots) is read in one step, every row segment is then requested at once into
-// registers and parked in the wave's own LDS tile, the rotations are applied in order (MODE 0: O,
-// forward) or in reverse with transposed blocks (MODE 1; MODE 2 also adds the angle-gradient
-// partial sum_w <g[T], J z[T]> of each rotation before undoing it, vector 0 = z, vector 1 = g),
-// and the rows are written back.  Rotation parameters live in the lane of their slot and are
-// broadcast with readlane; the tile is private to the wave, so no barrier is needed.
+// registers, the rotations are applied in order (MODE 0: O, forward) or in reverse with
+// transposed blocks (MODE 1; MODE 2 also adds the angle-gradient partial sum_w <g[T], J z[T]> of
+// each rotation before undoing it, vector 0 = z, vector 1 = g), and the rows are written back.
+// Rotation parameters live in the lane of their slot and are broadcast with readlane; the rows
+// are private to the wave (registers, or its own LDS tile), so no barrier is needed.
 template <int K, int NV, int MODE>
 __global__ void __launch_bounds__(256) k_unit_sweep(UnitStage st, FwdIO fio, RevIO rio) {
   extern __shared__ float lds_f[];
   const int lane = pmmf_lane();
   const int wv = __builtin_amdgcn_readfirstlane(pmmf_wave());
-  float* tile = lds_f + (size_t)wv * NV * UNIT_MAX * PMMF_WAVE;
+  float* tile = lds_f + (size_t)wv * NV * UNIT_MAX * PMMF_WAVE;  // NV = 2 only
   // one-dimensional grid, column tile fastest and consecutive blocks on one XCD: the tiles of a
   // unit run side by side in one L2, which fetches the unit's description once
   const int ntile = (int)(((MODE == 0 ? fio.nrhs : rio.nrhs) + PMMF_WAVE - 1) / PMMF_WAVE);
@@ -603,16 +603,24 @@ __global__ void __launch_bounds__(256) k_unit_sweep(UnitStage st, FwdIO fio, Rev
         if (rio.mode[v] == 1) x[v][i] *= f;
     }
   }
+  // one vector: the rows stay in registers (a rotation names its rows by wave-uniform slot
+  // numbers, which index the register array directly with s_set_gpr_idx); two vectors: the rows
+  // are parked in the wave's own LDS tile (64 indexed registers would go to scratch memory)
+  if constexpr (NV > 1) {
 #pragma unroll
-  for (int c8 = 0; c8 < UNIT_MAX; c8 += 8) {
-    if (c8 < ns) {
+    for (int c8 = 0; c8 < UNIT_MAX; c8 += 8) {
+      if (c8 < ns) {
 #pragma unroll
-      for (int i = c8; i < c8 + 8; ++i)
+        for (int i = c8; i < c8 + 8; ++i)
 #pragma unroll
-        for (int v = 0; v < NV; ++v) tile[(v * UNIT_MAX + i) * PMMF_WAVE + lane] = x[v][i];
+          for (int v = 0; v < NV; ++v) tile[(v * UNIT_MAX + i) * PMMF_WAVE + lane] = x[v][i];
+      }
     }
   }
-  auto T = [&](int v, int i) -> float& { return tile[(v * UNIT_MAX + i) * PMMF_WAVE + lane]; };
+  auto T = [&](int v, int i) -> float& {
+    if constexpr (NV == 1) return x[v][i];
+    else return tile[(v * UNIT_MAX + i) * PMMF_WAVE + lane];
+  };
   if (MODE == 0) {
     for (int q = 0; q < nr; ++q) {
       const int locs = __builtin_amdgcn_readlane(rt.x, q);
@@ -712,7 +720,7 @@ static hipError_t unit_launch(const UnitStage& st, const FwdIO& fio, const RevIO
                               hipStream_t s) {
   if (st.nu == 0) return hipSuccess;
   if (wpb != 1 && wpb != 2 && wpb != 4) return hipErrorInvalidValue;
-  const size_t lds = (size_t)wpb * NV * UNIT_MAX * PMMF_WAVE * sizeof(float);
+  const size_t lds = NV == 1 ? 0 : (size_t)wpb * NV * UNIT_MAX * PMMF_WAVE * sizeof(float);
   const int64_t nrhs = MODE == 0 ? fio.nrhs : rio.nrhs;
   const int64_t blocks = (int64_t)((st.nu + wpb - 1) / wpb) * ((nrhs + PMMF_WAVE - 1) / PMMF_WAVE);
   if (blocks > 0x7fffffff) return hipErrorInvalidValue;
