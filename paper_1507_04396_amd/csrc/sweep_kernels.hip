@@ -8,6 +8,10 @@
 // read and written once per stage.
 #include "sweep_kernels.h"
 
+#include <mutex>
+#include <set>
+#include <utility>
+
 namespace pmmf {
 
 // dynamic LDS of a sweep workgroup: tile[NV][cmax][W] floats, then the cluster's rotation ids
@@ -988,18 +992,34 @@ __global__ void __launch_bounds__(TAIL_THREADS) k_tail_rev(TailPlan tp, RevIO io
   }
 }
 
+// the kernel's dynamic LDS limit raised to the device's per-workgroup maximum, once per kernel
+// and device (the plans never ask for more than that)
+template <class F>
+static hipError_t tail_lds_limit(F* kernel) {
+  static std::mutex mu;
+  static std::set<std::pair<const void*, int>> done;  // (kernel, device)
+  int dev = 0, cap = 0;
+  hipError_t err = hipGetDevice(&dev);
+  if (err != hipSuccess) return err;
+  const auto key = std::make_pair((const void*)kernel, dev);
+  std::lock_guard<std::mutex> lk(mu);
+  if (done.count(key)) return hipSuccess;
+  err = hipDeviceGetAttribute(&cap, hipDeviceAttributeMaxSharedMemoryPerBlock, dev);
+  if (err == hipSuccess)
+    err = hipFuncSetAttribute((const void*)kernel, hipFuncAttributeMaxDynamicSharedMemorySize, cap);
+  if (err == hipSuccess) done.insert(key);
+  return err;
+}
 template <int K>
 static hipError_t tail_launch_fwd(const TailPlan& tp, const FwdIO& io, hipStream_t s) {
-  hipError_t e = hipFuncSetAttribute((const void*)k_tail_fwd<K>,
-                                     hipFuncAttributeMaxDynamicSharedMemorySize, tp.lds_bytes);
+  const hipError_t e = tail_lds_limit(k_tail_fwd<K>);
   if (e != hipSuccess) return e;
   k_tail_fwd<K><<<(unsigned)io.nrhs, TAIL_THREADS, tp.lds_bytes, s>>>(tp, io);
   return hipGetLastError();
 }
 template <int K>
 static hipError_t tail_launch_rev(const TailPlan& tp, const RevIO& io, hipStream_t s) {
-  hipError_t e = hipFuncSetAttribute((const void*)k_tail_rev<K>,
-                                     hipFuncAttributeMaxDynamicSharedMemorySize, tp.lds_bytes);
+  const hipError_t e = tail_lds_limit(k_tail_rev<K>);
   if (e != hipSuccess) return e;
   k_tail_rev<K><<<(unsigned)io.nrhs, TAIL_THREADS, tp.lds_bytes, s>>>(tp, io);
   return hipGetLastError();
