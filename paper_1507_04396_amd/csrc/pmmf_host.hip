@@ -2066,9 +2066,12 @@ void backward_body(mmf_plan& h, const float* d_x, const float* d_ybar, float* d_
     // a larger component, the level sweep's (W2 columns); the launch with fewer zero-fills the rest
     const int nt_stage = (int)std::max(sd.nu > 0 ? (nrhs + 63) / 64 : 0,
                                        sd.nbig > 0 ? (nrhs + W2 - 1) / W2 : 0);
+    // the two passes touch disjoint buffers: their unit sweeps share one launch
+    pmmf::RevIO iop[2];
     for (int pass = 0; pass < 2; ++pass) {
       float* (*Rb)[2] = pass == 0 ? RA : RB;
-      pmmf::RevIO io{};
+      pmmf::RevIO& io = iop[pass];
+      io = pmmf::RevIO{};
       if (p == P) {
         io.src_c[0] = pass == 0 ? bcopy.as<float>() : acopy.as<float>();
         io.src_c[1] = pass == 0 ? ga_core : gb_core;
@@ -2096,9 +2099,9 @@ void backward_body(mmf_plan& h, const float* d_x, const float* d_ybar, float* d_
       io.theta_part = pass == 0 ? pa_buf.as<float>() : pb_buf.as<float>();
       io.theta_stride = sd.t * NP;
       io.theta_tiles = nt_stage;
-      HIPCHK(pmmf::launch_unit_rev(unit_view(h, sd), io, 2, want_theta, cfg.wpb, s));
       HIPCHK(pmmf::launch_sweep_rev(v, io, W2, 2, want_theta, s));
     }
+    HIPCHK(pmmf::launch_unit_rev(unit_view(h, sd), iop[0], 2, want_theta, cfg.wpb, s, &iop[1]));
     if (d_theta_bar)
       HIPCHK(pmmf::launch_theta_reduce((int)(sd.t * NP), nt_stage, sd.t * NP, pa_buf.as<float>(),
                                        pb_buf.as<float>(), sd.rot_base * NP, d_theta_bar, s));

@@ -125,8 +125,9 @@ hipError_t launch_tail_params(int64_t n, int k, const int32_t* idx, const int64_
                               const float* rot_o, uint8_t* blob, hipStream_t s);
 // wpb: waves (units) per workgroup, 1, 2 or 4
 hipError_t launch_unit_fwd(const UnitStage& st, const FwdIO& io, int nv, int wpb, hipStream_t s);
+// io2: a second, independent pass over the same stage in the same launch (same nrhs)
 hipError_t launch_unit_rev(const UnitStage& st, const RevIO& io, int nv, bool theta, int wpb,
-                           hipStream_t s);
+                           hipStream_t s, const RevIO* io2 = nullptr);
 hipError_t launch_sweep_fwd(const SweepStage& st, const FwdIO& io, int W, int nv, hipStream_t s);
 hipError_t launch_sweep_rev(const SweepStage& st, const RevIO& io, int W, int nv, bool theta,
                             hipStream_t s);

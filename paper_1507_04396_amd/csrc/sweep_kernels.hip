@@ -539,15 +539,21 @@ hipError_t launch_theta_reduce(int t, int ntiles, int64_t stride, const float* p
 // Rotation parameters live in the lane of their slot and are broadcast with readlane; the rows
 // are private to the wave (registers, or its own LDS tile), so no barrier is needed.
 template <int K, int NV, int MODE>
-__global__ void __launch_bounds__(256) k_unit_sweep(UnitStage st, FwdIO fio, RevIO rio) {
+__global__ void __launch_bounds__(256) k_unit_sweep(UnitStage st, FwdIO fio, RevIO rio0,
+                                                    RevIO rio1, unsigned per_pass) {
   extern __shared__ float lds_f[];
   const int lane = pmmf_lane();
   const int wv = __builtin_amdgcn_readfirstlane(pmmf_wave());
   float* tile = lds_f + (size_t)wv * NV * UNIT_MAX * PMMF_WAVE;  // NV = 2 only
+  // U^T sweeps may carry two independent passes over the same stage (the adjoint's two vector
+  // pairs) in one launch: blocks [0, per_pass) take rio0, the rest rio1
+  const bool second = MODE != 0 && blockIdx.x >= per_pass;
+  const RevIO& rio = second ? rio1 : rio0;
+  const unsigned bx = second ? blockIdx.x - per_pass : blockIdx.x;
   // one-dimensional grid, column tile fastest and consecutive blocks on one XCD: the tiles of a
   // unit run side by side in one L2, which fetches the unit's description once
   const int ntile = (int)(((MODE == 0 ? fio.nrhs : rio.nrhs) + PMMF_WAVE - 1) / PMMF_WAVE);
-  const unsigned lb = (unsigned)pmmf_xcd_block((int)blockIdx.x, (int)gridDim.x);
+  const unsigned lb = (unsigned)pmmf_xcd_block((int)bx, (int)per_pass);
   const int ctile = (int)(lb % (unsigned)ntile);
   const int g = (int)(lb / (unsigned)ntile) * (blockDim.x / PMMF_WAVE) +
                 __builtin_amdgcn_readfirstlane(pmmf_wave());
@@ -721,14 +727,16 @@ __global__ void __launch_bounds__(256) k_unit_sweep(UnitStage st, FwdIO fio, Rev
 
 template <int K, int NV, int MODE>
 static hipError_t unit_launch(const UnitStage& st, const FwdIO& fio, const RevIO& rio, int wpb,
-                              hipStream_t s) {
+                              hipStream_t s, const RevIO* rio2 = nullptr) {
   if (st.nu == 0) return hipSuccess;
   if (wpb != 1 && wpb != 2 && wpb != 4) return hipErrorInvalidValue;
   const size_t lds = NV == 1 ? 0 : (size_t)wpb * NV * UNIT_MAX * PMMF_WAVE * sizeof(float);
   const int64_t nrhs = MODE == 0 ? fio.nrhs : rio.nrhs;
+  if (rio2 && rio2->nrhs != nrhs) return hipErrorInvalidValue;
   const int64_t blocks = (int64_t)((st.nu + wpb - 1) / wpb) * ((nrhs + PMMF_WAVE - 1) / PMMF_WAVE);
-  if (blocks > 0x7fffffff) return hipErrorInvalidValue;
-  k_unit_sweep<K, NV, MODE><<<(unsigned)blocks, wpb * PMMF_WAVE, lds, s>>>(st, fio, rio);
+  if (blocks * (rio2 ? 2 : 1) > 0x7fffffff) return hipErrorInvalidValue;
+  k_unit_sweep<K, NV, MODE><<<(unsigned)(blocks * (rio2 ? 2 : 1)), wpb * PMMF_WAVE, lds, s>>>(
+      st, fio, rio, rio2 ? *rio2 : rio, (unsigned)blocks);
   return hipGetLastError();
 }
 
@@ -742,16 +750,16 @@ hipError_t launch_unit_fwd(const UnitStage& st, const FwdIO& io, int nv, int wpb
 }
 
 hipError_t launch_unit_rev(const UnitStage& st, const RevIO& io, int nv, bool theta, int wpb,
-                           hipStream_t s) {
+                           hipStream_t s, const RevIO* io2) {
   FwdIO none{};
   if (st.k == 2) {
-    if (theta) return unit_launch<2, 2, 2>(st, none, io, wpb, s);
-    return nv == 1 ? unit_launch<2, 1, 1>(st, none, io, wpb, s)
-                   : unit_launch<2, 2, 1>(st, none, io, wpb, s);
+    if (theta) return unit_launch<2, 2, 2>(st, none, io, wpb, s, io2);
+    return nv == 1 ? unit_launch<2, 1, 1>(st, none, io, wpb, s, io2)
+                   : unit_launch<2, 2, 1>(st, none, io, wpb, s, io2);
   }
-  if (theta) return unit_launch<3, 2, 2>(st, none, io, wpb, s);
-  return nv == 1 ? unit_launch<3, 1, 1>(st, none, io, wpb, s)
-                 : unit_launch<3, 2, 1>(st, none, io, wpb, s);
+  if (theta) return unit_launch<3, 2, 2>(st, none, io, wpb, s, io2);
+  return nv == 1 ? unit_launch<3, 1, 1>(st, none, io, wpb, s, io2)
+                 : unit_launch<3, 2, 1>(st, none, io, wpb, s, io2);
 }
 
 // ------------------------------------------------------------------------------------------
