@@ -271,19 +271,20 @@ hipError_t launch_sweep_rev(const SweepStage& st, const RevIO& io, int W, int nv
 // ------------------------------------------------------------------------------------------
 // dense FP32 GEMM  C[M][N] = op(A)[M][K] * op(B)[K][N] (+ beta C), row-major, op = transpose if
 // flagged.  The products here are small (a core of a few hundred to a few thousand rows against
-// at most a few hundred vectors), so a workgroup takes one 16 x 16 output tile and its four waves
-// split K: K is cut into 16-deep blocks, wave w takes blocks w, w + 4, ..., and each block is four
+// at most a few hundred vectors), so a workgroup takes one 16 x 16 output tile and its eight waves
+// split K: K is cut into 16-deep blocks, wave w takes blocks w, w + 8, ..., and each block is four
 // v_mfma_f32_16x16x4f32 (A operand: lane l holds A[l % 16][.], B operand B[.][l % 16]; lane group
 // l / 16 takes k = 4 (l / 16) + s of the block in step s, the same k for both operands, so the sum
 // runs over every k once).  Lanes read their operands straight from memory (the core and the
-// vectors stay in L2), four blocks per wave at a time with the next four in flight; the four
-// partial tiles are added in LDS in wave order, so the result does not depend on timing.
+// vectors stay in L2), four blocks per wave at a time with the next four in flight (a K of 512
+// is one round); the eight partial tiles are added in LDS in wave order, so the result does not
+// depend on timing.
 typedef float pmmf_f4 __attribute__((ext_vector_type(4)));
-constexpr int GEMM_T = 16, GEMM_KB = 16, GEMM_WAVES = 4, GEMM_BPW = 4;
+constexpr int GEMM_T = 16, GEMM_KB = 16, GEMM_WAVES = 8, GEMM_BPW = 4;
 // VA / VB: the operand's k runs along its rows (A not transposed / B transposed) in 16-byte
 // aligned rows with K a multiple of 4: a lane's four k of a block are one 16-byte load
 template <bool VA, bool VB>
-__global__ void __launch_bounds__(256) k_gemm(int M, int N, int K, const float* __restrict__ A,
+__global__ void __launch_bounds__(GEMM_WAVES * PMMF_WAVE) k_gemm(int M, int N, int K, const float* __restrict__ A,
                                               int lda, int ta, const float* __restrict__ B,
                                               int ldb, int tb, float* __restrict__ C, int ldc,
                                               float beta) {
