@@ -2044,15 +2044,21 @@ void backward_body(mmf_plan& h, const float* d_x, const float* d_ybar, float* d_
                      {wsbuf(h, 14, s1 * nrhs), wsbuf(h, 15, s1 * nrhs)}};
   // RB[0] reuses the buffers of F[0]; the core states are copied first (below), so no buffer is
   // read and written by the same sweep
-  const int ntiles = (int)std::max((nrhs + W2 - 1) / W2, (nrhs + 63) / 64);
-  int64_t tmax = 1;
-  for (auto& sp : h.st) tmax = std::max(tmax, sp->t);
+  // column tiles of the angle partials: the unit sweep's (64 columns) and, where a stage has
+  // clusters with a larger component, the level sweep's (W2 columns); a launch with fewer tiles
+  // zero-fills the rest
+  int ntiles = 1;
+  for (auto& sp : h.st)
+    ntiles = (int)std::max<int64_t>(ntiles, std::max(sp->nu > 0 ? (nrhs + 63) / 64 : 0,
+                                                     sp->nbig > 0 ? (nrhs + W2 - 1) / W2 : 0));
+  // per-tile angle partials of every rotation, [tile][rotation * NP], reduced once at the end
+  const int64_t RT = std::max<int64_t>(h.R, 1);
   // angle partials per rotation: one (k = 2) or one per plane of its slots (k = 3)
   const int NP = h.k == 3 ? 3 : 1;
   const bool want_theta = h.k == 2 || d_theta_bar;
   DBuf pa_buf, pb_buf;
-  pa_buf.ensure((size_t)ntiles * tmax * NP * sizeof(float));
-  pb_buf.ensure((size_t)ntiles * tmax * NP * sizeof(float));
+  pa_buf.ensure((size_t)ntiles * RT * NP * sizeof(float));
+  pb_buf.ensure((size_t)ntiles * RT * NP * sizeof(float));
   // copy of the core states so the ping-pong buffers are free for pass B
   DBuf acopy, bcopy;
   acopy.ensure(std::max<int64_t>(core * nrhs, 1) * sizeof(float));
@@ -2062,10 +2068,6 @@ void backward_body(mmf_plan& h, const float* d_x, const float* d_ybar, float* d_
   for (int p = P; p >= 1; --p) {
     const StageDev& sd = *h.st[p - 1];
     const pmmf::SweepStage v = sweep_view(h, sd);
-    // column tiles of this stage's partials: the unit sweep's (64 columns) and, for clusters with
-    // a larger component, the level sweep's (W2 columns); the launch with fewer zero-fills the rest
-    const int nt_stage = (int)std::max(sd.nu > 0 ? (nrhs + 63) / 64 : 0,
-                                       sd.nbig > 0 ? (nrhs + W2 - 1) / W2 : 0);
     // the two passes touch disjoint buffers: their unit sweeps share one launch
     pmmf::RevIO iop[2];
     for (int pass = 0; pass < 2; ++pass) {
@@ -2096,16 +2098,16 @@ void backward_body(mmf_plan& h, const float* d_x, const float* d_ybar, float* d_
         io.ld_out = nrhs;
       }
       io.nrhs = nrhs;
-      io.theta_part = pass == 0 ? pa_buf.as<float>() : pb_buf.as<float>();
-      io.theta_stride = sd.t * NP;
-      io.theta_tiles = nt_stage;
+      io.theta_part = (pass == 0 ? pa_buf.as<float>() : pb_buf.as<float>()) + sd.rot_base * NP;
+      io.theta_stride = RT * NP;
+      io.theta_tiles = ntiles;
       HIPCHK(pmmf::launch_sweep_rev(v, io, W2, 2, want_theta, s));
     }
     HIPCHK(pmmf::launch_unit_rev(unit_view(h, sd), iop[0], 2, want_theta, cfg.wpb, s, &iop[1]));
-    if (d_theta_bar)
-      HIPCHK(pmmf::launch_theta_reduce((int)(sd.t * NP), nt_stage, sd.t * NP, pa_buf.as<float>(),
-                                       pb_buf.as<float>(), sd.rot_base * NP, d_theta_bar, s));
   }
+  if (d_theta_bar)
+    HIPCHK(pmmf::launch_theta_reduce((int)(h.R * NP), ntiles, RT * NP, pa_buf.as<float>(),
+                                     pb_buf.as<float>(), 0, d_theta_bar, s));
   // k = 3: plane derivatives -> derivatives in the angles (derivative of the exponential map)
   if (d_theta_bar && h.k == 3)
     HIPCHK(pmmf::launch_theta3_chain(h.R, h.theta.as<float>(), d_theta_bar, s));
