@@ -363,7 +363,7 @@ struct mmf_plan {
   int64_t tail_entries = 0;
   uint64_t version = 0;  // bumped whenever theta, H or the rotations change
   std::map<std::pair<std::string, int64_t>, SweepCfg> tune;  // (product, width) -> config
-  DBuf ws[16];
+  DBuf ws[18];
   mmf_info info{};
   hipStream_t stream = nullptr;
 };
@@ -2023,14 +2023,18 @@ void backward_body(mmf_plan& h, const float* d_x, const float* d_ybar, float* d_
     else
       HIPCHK(hipMemsetAsync(d_hdiag_bar, 0, n * sizeof(float), s));
   }
-  if (d_hcore_bar)
-    HIPCHK(pmmf::launch_gemm((int)core, (int)core, (int)nrhs, b_core, (int)lda_core, 0, a_core,
-                             (int)lda_core, 1, d_hcore_bar, (int)core, 0.f, s));
-  // adjoint seeds on the core: g_a = H a, g_b = H^T b
-  HIPCHK(pmmf::launch_gemm((int)core, (int)nrhs, (int)core, Hc, (int)core, 0, a_core,
-                           (int)lda_core, 0, ga_core, (int)nrhs, 0.f, s));
-  HIPCHK(pmmf::launch_gemm((int)core, (int)nrhs, (int)core, Hc, (int)core, 1, b_core,
-                           (int)lda_core, 0, gb_core, (int)nrhs, 0.f, s));
+  // adjoint seeds on the core, g_a = H a and g_b = H^T b, and hcore_bar = b_core a_core^T: three
+  // independent products in one launch
+  {
+    pmmf::GemmArgs ga[3] = {
+        {(int)core, (int)nrhs, (int)core, Hc, (int)core, 0, a_core, (int)lda_core, 0, ga_core,
+         (int)nrhs, 0.f},
+        {(int)core, (int)nrhs, (int)core, Hc, (int)core, 1, b_core, (int)lda_core, 0, gb_core,
+         (int)nrhs, 0.f},
+        {(int)core, (int)core, (int)nrhs, b_core, (int)lda_core, 0, a_core, (int)lda_core, 1,
+         d_hcore_bar, (int)core, 0.f}};
+    HIPCHK(pmmf::launch_gemm_batch(d_hcore_bar ? 3 : 2, ga, s));
+  }
   if (P == 0) {
     if (d_xbar)
       HIPCHK(hipMemcpy2DAsync(d_xbar, ld * sizeof(float), gb_core, nrhs * sizeof(float),
@@ -2040,9 +2044,9 @@ void backward_body(mmf_plan& h, const float* d_x, const float* d_ybar, float* d_
   // reverse passes: A carries (z = U-states of ybar, g_a), B carries (z = states of x, g_b)
   float* RA[2][2] = {{wsbuf(h, 10, s1 * nrhs), wsbuf(h, 11, s1 * nrhs)},
                      {wsbuf(h, 12, s1 * nrhs), wsbuf(h, 13, s1 * nrhs)}};
-  float* RB[2][2] = {{wsbuf(h, 4, s1 * nrhs), wsbuf(h, 5, s1 * nrhs)},
+  float* RB[2][2] = {{wsbuf(h, 16, s1 * nrhs), wsbuf(h, 17, s1 * nrhs)},
                      {wsbuf(h, 14, s1 * nrhs), wsbuf(h, 15, s1 * nrhs)}};
-  // RB[0] reuses the buffers of F[0]; the core states are copied first (below), so no buffer is
+  // the reverse passes read the forward states of the core (F[.][P % 2]) in place: no buffer is
   // read and written by the same sweep
   // column tiles of the angle partials: the unit sweep's (64 columns) and, where a stage has
   // clusters with a larger component, the level sweep's (W2 columns); a launch with fewer tiles
@@ -2059,12 +2063,6 @@ void backward_body(mmf_plan& h, const float* d_x, const float* d_ybar, float* d_
   DBuf pa_buf, pb_buf;
   pa_buf.ensure((size_t)ntiles * RT * NP * sizeof(float));
   pb_buf.ensure((size_t)ntiles * RT * NP * sizeof(float));
-  // copy of the core states so the ping-pong buffers are free for pass B
-  DBuf acopy, bcopy;
-  acopy.ensure(std::max<int64_t>(core * nrhs, 1) * sizeof(float));
-  bcopy.ensure(std::max<int64_t>(core * nrhs, 1) * sizeof(float));
-  HIPCHK(hipMemcpyAsync(acopy.p, a_core, core * nrhs * sizeof(float), hipMemcpyDeviceToDevice, s));
-  HIPCHK(hipMemcpyAsync(bcopy.p, b_core, core * nrhs * sizeof(float), hipMemcpyDeviceToDevice, s));
   for (int p = P; p >= 1; --p) {
     const StageDev& sd = *h.st[p - 1];
     const pmmf::SweepStage v = sweep_view(h, sd);
@@ -2075,7 +2073,7 @@ void backward_body(mmf_plan& h, const float* d_x, const float* d_ybar, float* d_
       pmmf::RevIO& io = iop[pass];
       io = pmmf::RevIO{};
       if (p == P) {
-        io.src_c[0] = pass == 0 ? bcopy.as<float>() : acopy.as<float>();
+        io.src_c[0] = pass == 0 ? b_core : a_core;
         io.src_c[1] = pass == 0 ? ga_core : gb_core;
       } else {
         io.src_c[0] = Rb[0][(p + 1) % 2];

@@ -133,6 +133,18 @@ hipError_t launch_sweep_rev(const SweepStage& st, const RevIO& io, int W, int nv
                             hipStream_t s);
 hipError_t launch_gemm(int M, int N, int K, const float* A, int lda, int ta, const float* B,
                        int ldb, int tb, float* C, int ldc, float beta, hipStream_t s);
+// up to three independent products of launch_gemm's form in one launch
+struct GemmArgs {
+  int M, N, K;
+  const float* A;
+  int lda, ta;
+  const float* B;
+  int ldb, tb;
+  float* C;
+  int ldc;
+  float beta;
+};
+hipError_t launch_gemm_batch(int n, const GemmArgs* args, hipStream_t s);
 hipError_t launch_core_inverse(int n, float* work_L, float* work_X, float* out_inv,
                                int64_t nfull, const float* hdiag, const uint8_t* is_core,
                                int32_t* status, hipStream_t s);

@@ -8,6 +8,7 @@
 // read and written once per stage.
 #include "sweep_kernels.h"
 
+#include <algorithm>
 #include <mutex>
 #include <set>
 #include <utility>
@@ -283,15 +284,33 @@ typedef float pmmf_f4 __attribute__((ext_vector_type(4)));
 constexpr int GEMM_T = 16, GEMM_KB = 16, GEMM_WAVES = 8, GEMM_BPW = 4;
 // VA / VB: the operand's k runs along its rows (A not transposed / B transposed) in 16-byte
 // aligned rows with K a multiple of 4: a lane's four k of a block are one 16-byte load
+struct GemmProb {
+  int M, N, K;
+  const float* A;
+  int lda, ta;
+  const float* B;
+  int ldb, tb;
+  float* C;
+  int ldc;
+  float beta;
+  int va, vb;  // 16-byte operand loads (see gemm_tile)
+};
+struct GemmBatch {
+  int n;
+  GemmProb p[3];
+};
+
 template <bool VA, bool VB>
-__global__ void __launch_bounds__(GEMM_WAVES * PMMF_WAVE) k_gemm(int M, int N, int K, const float* __restrict__ A,
-                                              int lda, int ta, const float* __restrict__ B,
-                                              int ldb, int tb, float* __restrict__ C, int ldc,
-                                              float beta) {
+__device__ inline void gemm_tile(const GemmProb& g, int bx, int by) {
   __shared__ pmmf_f4 part[GEMM_WAVES - 1][PMMF_WAVE];
+  const int M = g.M, N = g.N, K = g.K, lda = g.lda, ta = g.ta, ldb = g.ldb, tb = g.tb, ldc = g.ldc;
+  const float* __restrict__ A = g.A;
+  const float* __restrict__ B = g.B;
+  float* __restrict__ C = g.C;
+  const float beta = g.beta;
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   const int r = lane & 15, grp = lane >> 4;
-  const int m0 = blockIdx.y * GEMM_T, n0 = blockIdx.x * GEMM_T;
+  const int m0 = by * GEMM_T, n0 = bx * GEMM_T;
   const bool mok = m0 + r < M, nok = n0 + r < N;
   const int64_t gm = min(m0 + r, M - 1), gn = min(n0 + r, N - 1);
   const int nb = (K + GEMM_KB - 1) / GEMM_KB;
@@ -368,19 +387,58 @@ __global__ void __launch_bounds__(GEMM_WAVES * PMMF_WAVE) k_gemm(int M, int N, i
   }
 }
 
+template <bool VA, bool VB>
+__global__ void __launch_bounds__(GEMM_WAVES * PMMF_WAVE) k_gemm(GemmProb g) {
+  gemm_tile<VA, VB>(g, blockIdx.x, blockIdx.y);
+}
+
+// up to three independent products in one launch (blockIdx.z picks the product)
+__global__ void __launch_bounds__(GEMM_WAVES * PMMF_WAVE) k_gemm_batch(GemmBatch b) {
+  const GemmProb& g = b.p[blockIdx.z];
+  if ((int)blockIdx.x * GEMM_T >= g.N || (int)blockIdx.y * GEMM_T >= g.M) return;
+  if (g.va && g.vb) gemm_tile<true, true>(g, blockIdx.x, blockIdx.y);
+  else if (g.va) gemm_tile<true, false>(g, blockIdx.x, blockIdx.y);
+  else if (g.vb) gemm_tile<false, true>(g, blockIdx.x, blockIdx.y);
+  else gemm_tile<false, false>(g, blockIdx.x, blockIdx.y);
+}
+
+static GemmProb gemm_prob(int M, int N, int K, const float* A, int lda, int ta, const float* B,
+                          int ldb, int tb, float* C, int ldc, float beta) {
+  auto rows16 = [&](const float* p, int ld) {
+    return K % 4 == 0 && ld % 4 == 0 && (reinterpret_cast<uintptr_t>(p) & 15) == 0;
+  };
+  GemmProb g{M, N, K, A, lda, ta, B, ldb, tb, C, ldc, beta, 0, 0};
+  g.va = !ta && rows16(A, lda);
+  g.vb = tb && rows16(B, ldb);
+  return g;
+}
+
 hipError_t launch_gemm(int M, int N, int K, const float* A, int lda, int ta, const float* B,
                        int ldb, int tb, float* C, int ldc, float beta, hipStream_t s) {
   if (M == 0 || N == 0) return hipSuccess;
   dim3 grid((N + GEMM_T - 1) / GEMM_T, (M + GEMM_T - 1) / GEMM_T);
-  auto rows16 = [&](const float* p, int ld) {
-    return K % 4 == 0 && ld % 4 == 0 && (reinterpret_cast<uintptr_t>(p) & 15) == 0;
-  };
-  const bool va = !ta && rows16(A, lda), vb = tb && rows16(B, ldb);
+  const GemmProb g = gemm_prob(M, N, K, A, lda, ta, B, ldb, tb, C, ldc, beta);
   const int th = GEMM_WAVES * PMMF_WAVE;
-  if (va && vb) k_gemm<true, true><<<grid, th, 0, s>>>(M, N, K, A, lda, ta, B, ldb, tb, C, ldc, beta);
-  else if (va) k_gemm<true, false><<<grid, th, 0, s>>>(M, N, K, A, lda, ta, B, ldb, tb, C, ldc, beta);
-  else if (vb) k_gemm<false, true><<<grid, th, 0, s>>>(M, N, K, A, lda, ta, B, ldb, tb, C, ldc, beta);
-  else k_gemm<false, false><<<grid, th, 0, s>>>(M, N, K, A, lda, ta, B, ldb, tb, C, ldc, beta);
+  if (g.va && g.vb) k_gemm<true, true><<<grid, th, 0, s>>>(g);
+  else if (g.va) k_gemm<true, false><<<grid, th, 0, s>>>(g);
+  else if (g.vb) k_gemm<false, true><<<grid, th, 0, s>>>(g);
+  else k_gemm<false, false><<<grid, th, 0, s>>>(g);
+  return hipGetLastError();
+}
+
+hipError_t launch_gemm_batch(int n, const GemmArgs* args, hipStream_t s) {
+  if (n < 1 || n > 3) return hipErrorInvalidValue;
+  GemmBatch b{};
+  b.n = n;
+  int gx = 0, gy = 0;
+  for (int q = 0; q < n; ++q) {
+    const GemmArgs& a = args[q];
+    b.p[q] = gemm_prob(a.M, a.N, a.K, a.A, a.lda, a.ta, a.B, a.ldb, a.tb, a.C, a.ldc, a.beta);
+    gx = std::max(gx, (a.N + GEMM_T - 1) / GEMM_T);
+    gy = std::max(gy, (a.M + GEMM_T - 1) / GEMM_T);
+  }
+  if (gx == 0 || gy == 0) return hipSuccess;
+  k_gemm_batch<<<dim3(gx, gy, n), GEMM_WAVES * PMMF_WAVE, 0, s>>>(b);
   return hipGetLastError();
 }
 
