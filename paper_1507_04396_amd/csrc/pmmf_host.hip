@@ -1990,6 +1990,9 @@ void backward_body(mmf_plan& h, const float* d_x, const float* d_ybar, float* d_
     b_core = d_ybar;
   }
   const int W2 = cfg.W;
+  // the trailing stages of both forward sweeps in one launch (as in the products)
+  const pmmf::TailPlan tp = tail_plan(h, cfg.tail);
+  const int p0 = tp.nst ? P - tp.nst + 1 : P + 1;
   for (int p = 1; p <= P; ++p) {
     const StageDev& sd = *h.st[p - 1];
     pmmf::FwdIO io{};
@@ -2005,6 +2008,12 @@ void backward_body(mmf_plan& h, const float* d_x, const float* d_ybar, float* d_
     io.mode[0] = io.mode[1] = 0;
     io.hdiag = h.hdiag.as<float>();
     io.nrhs = nrhs;
+    if (p == p0) {
+      io.dst_c[0] = F[0][P % 2];
+      io.dst_c[1] = F[1][P % 2];
+      HIPCHK(pmmf::launch_tail_fwd(h.k, tp, io, s));
+      break;
+    }
     HIPCHK(pmmf::launch_unit_fwd(unit_view(h, sd), io, 2, cfg.wpb, s));
     HIPCHK(pmmf::launch_sweep_fwd(sweep_view(h, sd), io, W2, 2, s));
   }

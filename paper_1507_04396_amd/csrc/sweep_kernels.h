@@ -112,11 +112,12 @@ struct RevIO {
 };
 
 size_t sweep_lds_bytes(int k, int W, int nv, int cmax, int rmax);
-// trailing stages of U (from the compact rows io.src[0] to the core's compact rows io.dst_c[0],
-// retired rows to io.dst_nat[0] scaled by io.mode[0]) and of U^T (from the core's rows
+// trailing stages of U (from the compact rows io.src[v] to the core's compact rows io.dst_c[v],
+// retired rows to io.dst_nat[v] scaled by io.mode[v]; v = 0, and v = 1 too if io.src[1] is set)
+// and of U^T (from the core's rows
 // io.src_c[0] and the retired rows io.src_nat[0], which are copied (mode 0 only), to the compact
 // rows io.dst_c[0] of the first trailing stage or, if io.dst_nat[0] is set, to natural rows);
-// one vector, grid = nrhs workgroups
+// one vector (U^T), grid = nrhs workgroups per vector
 hipError_t launch_tail_fwd(int k, const TailPlan& tp, const FwdIO& io, hipStream_t s);
 hipError_t launch_tail_rev(int k, const TailPlan& tp, const RevIO& io, hipStream_t s);
 // the rotation blocks of the program blocks from the canonical blocks: entry e of the programs

@@ -895,7 +895,14 @@ __global__ void __launch_bounds__(TAIL_THREADS) k_tail_fwd(TailPlan tp, FwdIO io
   extern __shared__ __align__(16) unsigned char tail_lds[];
   float* data = reinterpret_cast<float*>(tail_lds);
   const int tid = threadIdx.x;
-  const int64_t col = pmmf_xcd_block(blockIdx.x, gridDim.x);
+  // grid: nrhs workgroups per vector (io.src[1] set: two vectors, the second half of the grid)
+  const int64_t lb = pmmf_xcd_block(blockIdx.x, gridDim.x);
+  const int vsel = lb >= io.nrhs ? 1 : 0;
+  const int64_t col = lb - vsel * io.nrhs;
+  const float* __restrict__ src = vsel ? io.src[1] : io.src[0];
+  float* __restrict__ dst_c = vsel ? io.dst_c[1] : io.dst_c[0];
+  float* __restrict__ dst_nat = vsel ? io.dst_nat[1] : io.dst_nat[0];
+  const int mode = vsel ? io.mode[1] : io.mode[0];
   const int nst = tp.nst;
   tail_copy_block(tp, 0, tail_block(tp, tail_lds, 0));
   int tc[TAIL_J], tn[TAIL_J], rg[TAIL_J];
@@ -910,7 +917,7 @@ __global__ void __launch_bounds__(TAIL_THREADS) k_tail_fwd(TailPlan tp, FwdIO io
       tc[j] = tp.trans[tp.st[0].slot_off + i];
     }
 #pragma unroll
-    for (int j = 0; j < TAIL_J; ++j) v[j] = io.src[0][(int64_t)ps[j] * io.ld_src + col];
+    for (int j = 0; j < TAIL_J; ++j) v[j] = src[(int64_t)ps[j] * io.ld_src + col];
 #pragma unroll
     for (int j = 0; j < TAIL_J; ++j) {
       const int i = tid + j * TAIL_THREADS;
@@ -926,7 +933,7 @@ __global__ void __launch_bounds__(TAIL_THREADS) k_tail_fwd(TailPlan tp, FwdIO io
     // retired rows of the previous stage
 #pragma unroll
     for (int j = 0; j < TAIL_J; ++j)
-      if (rg[j] >= 0) io.dst_nat[0][(int64_t)rg[j] * io.ld_nat + col] = rv[j];
+      if (rg[j] >= 0) dst_nat[(int64_t)rg[j] * io.ld_nat + col] = rv[j];
     if (s + 1 < nst) {
       tail_copy_block(tp, s + 1, tail_block(tp, tail_lds, s + 1));
       const int rn = tp.st[s + 1].rows;
@@ -937,7 +944,7 @@ __global__ void __launch_bounds__(TAIL_THREADS) k_tail_fwd(TailPlan tp, FwdIO io
     float hd[TAIL_J];
 #pragma unroll
     for (int j = 0; j < TAIL_J; ++j)
-      hd[j] = io.mode[0] != 0 ? io.hdiag[tc[j] < 0 ? -tc[j] - 1 : 0] : 1.f;
+      hd[j] = mode != 0 ? io.hdiag[tc[j] < 0 ? -tc[j] - 1 : 0] : 1.f;
     tail_rotate<K, false>(tail_block(tp, tail_lds, s), tp.st[s].nu, tp.st[s].t, data);
     __syncthreads();
 #pragma unroll
@@ -953,12 +960,12 @@ __global__ void __launch_bounds__(TAIL_THREADS) k_tail_fwd(TailPlan tp, FwdIO io
       if (tid + j * TAIL_THREADS >= rows) continue;
       if (tc[j] >= 0) {
         if (!last) data[tc[j]] = v[j];
-        else io.dst_c[0][(int64_t)tc[j] * io.ld_c + col] = v[j];
+        else dst_c[(int64_t)tc[j] * io.ld_c + col] = v[j];
       } else {
         float val = v[j];
-        if (io.mode[0] == 1) val *= hd[j];
-        else if (io.mode[0] == 2) val /= hd[j];
-        else if (io.mode[0] == 3) val /= sqrtf(hd[j]);
+        if (mode == 1) val *= hd[j];
+        else if (mode == 2) val /= hd[j];
+        else if (mode == 3) val /= sqrtf(hd[j]);
         rv[j] = val;
         rg[j] = -tc[j] - 1;
       }
@@ -971,7 +978,7 @@ __global__ void __launch_bounds__(TAIL_THREADS) k_tail_fwd(TailPlan tp, FwdIO io
   }
 #pragma unroll
   for (int j = 0; j < TAIL_J; ++j)
-    if (rg[j] >= 0) io.dst_nat[0][(int64_t)rg[j] * io.ld_nat + col] = rv[j];
+    if (rg[j] >= 0) dst_nat[(int64_t)rg[j] * io.ld_nat + col] = rv[j];
 }
 
 template <int K>
@@ -1081,7 +1088,8 @@ template <int K>
 static hipError_t tail_launch_fwd(const TailPlan& tp, const FwdIO& io, hipStream_t s) {
   const hipError_t e = tail_lds_limit(k_tail_fwd<K>);
   if (e != hipSuccess) return e;
-  k_tail_fwd<K><<<(unsigned)io.nrhs, TAIL_THREADS, tp.lds_bytes, s>>>(tp, io);
+  k_tail_fwd<K><<<(unsigned)(io.nrhs * (io.src[1] ? 2 : 1)), TAIL_THREADS, tp.lds_bytes, s>>>(
+      tp, io);
   return hipGetLastError();
 }
 template <int K>
