@@ -2693,7 +2693,7 @@ __global__ void __launch_bounds__(NT) k_qsparse(const int32_t* __restrict__ off,
                                                  int32_t* __restrict__ cnt,
                                                  int32_t* __restrict__ sci,
                                                  float* __restrict__ scv) {
-  extern __shared__ float tile[];  // [c][BQ_W]
+  extern __shared__ float tile[];  // [c][BQ_W], then the cluster's level starts [depth + 1]
   constexpr int NWV = NT / PMMF_WAVE;
   __shared__ int part[NWV][BQ_W];
   const int u = blockIdx.y;
@@ -2702,34 +2702,73 @@ __global__ void __launch_bounds__(NT) k_qsparse(const int32_t* __restrict__ off,
   const int col0 = blockIdx.x * BQ_W;
   if (col0 >= c) return;
   const int tid = threadIdx.x;
-  for (int q = tid; q < c * BQ_W; q += blockDim.x) {
+  const int* lp = lvl_ptr + (size_t)u * lvl_stride;
+  const int dep = depth[u];
+  int* slp = reinterpret_cast<int*>(tile + (size_t)c * BQ_W);
+  for (int q = tid; q <= dep; q += NT) slp[q] = lp[q];
+  for (int q = tid; q < c * BQ_W; q += NT) {
     const int row = q / BQ_W, w = q % BQ_W;
     tile[q] = row == col0 + w ? 1.f : 0.f;
   }
   __syncthreads();
-  const int* lp = lvl_ptr + (size_t)u * lvl_stride;
-  const int dep = depth[u];
-  for (int l = 0; l < dep; ++l) {
-    const int r0 = lp[l], r1 = lp[l + 1];
-    for (int q = tid; q < (r1 - r0) * BQ_W; q += blockDim.x) {
-      const int rr = r0 + q / BQ_W, w = q % BQ_W;
+  // Thread tid takes items tid + i NT (i < QS_I) of each level (item = rotation x column); their
+  // slots and blocks are loaded one level ahead into a second register set, so a level waits for
+  // LDS only.  Items past QS_I NT in a level (a level of more than QS_I NT / BQ_W rotations) load
+  // their rotation when they are applied.
+  constexpr int QS_I = 4;
+  struct Items {
+    int id[QS_I][K];
+    float om[QS_I][K * K];
+  };
+  auto fetch = [&](int l, Items& it) {
+    if (l >= dep) return;
+    const int r0 = slp[l], n = (slp[l + 1] - r0) * BQ_W;
+#pragma unroll
+    for (int i = 0; i < QS_I; ++i) {
+      const int q = min(tid + i * NT, max(n - 1, 0));
+      const int rr = r0 + q / BQ_W;
+#pragma unroll
+      for (int a = 0; a < K; ++a) it.id[i][a] = sw_loc[(size_t)rr * K + a];
+#pragma unroll
+      for (int ab = 0; ab < K * K; ++ab) it.om[i][ab] = sw_o[(size_t)rr * K * K + ab];
+    }
+  };
+  auto rotate = [&](int w, const int (&id)[K], const float* om) {
+    float x[K];
+#pragma unroll
+    for (int a = 0; a < K; ++a) x[a] = tile[id[a] * BQ_W + w];
+#pragma unroll
+    for (int a = 0; a < K; ++a) {
+      float acc = 0.f;
+#pragma unroll
+      for (int b = 0; b < K; ++b) acc = fmaf(om[a * K + b], x[b], acc);
+      tile[id[a] * BQ_W + w] = acc;
+    }
+  };
+  auto level = [&](int l, const Items& it) {
+    const int r0 = slp[l], n = (slp[l + 1] - r0) * BQ_W;
+#pragma unroll
+    for (int i = 0; i < QS_I; ++i) {
+      const int q = tid + i * NT;
+      if (q < n) rotate(q % BQ_W, it.id[i], it.om[i]);
+    }
+    for (int q = tid + QS_I * NT; q < n; q += NT) {
+      const int rr = r0 + q / BQ_W;
       int id[K];
-      float x[K];
 #pragma unroll
-      for (int a = 0; a < K; ++a) {
-        id[a] = sw_loc[(size_t)rr * K + a];
-        x[a] = tile[id[a] * BQ_W + w];
-      }
-      const float* om = sw_o + (size_t)rr * K * K;
-#pragma unroll
-      for (int a = 0; a < K; ++a) {
-        float acc = 0.f;
-#pragma unroll
-        for (int b = 0; b < K; ++b) acc = fmaf(om[a * K + b], x[b], acc);
-        tile[id[a] * BQ_W + w] = acc;
-      }
+      for (int a = 0; a < K; ++a) id[a] = sw_loc[(size_t)rr * K + a];
+      rotate(q % BQ_W, id, sw_o + (size_t)rr * K * K);
     }
     __syncthreads();
+  };
+  Items ia, ib;
+  fetch(0, ia);
+  for (int l = 0; l < dep; l += 2) {
+    fetch(l + 1, ib);
+    level(l, ia);
+    if (l + 1 >= dep) break;
+    fetch(l + 2, ia);
+    level(l + 1, ib);
   }
   // each thread takes a contiguous block of rows; per column, the nonzeros of the earlier blocks
   // (a scan over the waves and their lanes) place its own, so each column's rows ascend
@@ -2777,7 +2816,7 @@ hipError_t launch_qsparse(int m, int k, const int32_t* off, const int64_t* gbase
   // 8-column slices, 256 threads (16 columns with 512 threads measured slower: half as many
   // workgroups fit a compute unit, and each level's latency is the same)
   constexpr int bw = 8;
-  const size_t lds = (size_t)cmax * bw * sizeof(float);
+  const size_t lds = (size_t)cmax * bw * sizeof(float) + (size_t)lvl_stride * sizeof(int);
   dim3 grid((unsigned)((cmax + bw - 1) / bw), (unsigned)m);
   auto go = [&](auto kern) -> hipError_t {
     if (lds > 64 * 1024) {
