@@ -2678,7 +2678,7 @@ hipError_t launch_find(const FindArgs& a, int m, int cmax, int nt, hipStream_t s
 
 // ------------------------------------------------------------------------------------------
 // Accumulated rotation of each cluster, Qbar_u = O_r ... O_1, rebuilt from the stage's sweep log:
-// one workgroup per (cluster, 8-column slice) holds the slice of the identity in LDS and applies
+// one workgroup per (cluster, 4-column slice) holds the slice of the identity in LDS and applies
 // the rotations level by level (a level's rotations touch disjoint rows); x[T] <- O x[T] on each
 // column of the slice.  Only the nonzeros leave the workgroup: column j of Qbar_u (row j of
 // Qbar^T, rows ascending) goes to its own c_u slots of a scratch pool at gbase[u] + j c_u, with
@@ -2693,7 +2693,7 @@ __global__ void __launch_bounds__(NT) k_qsparse(const int32_t* __restrict__ off,
                                                  int32_t* __restrict__ cnt,
                                                  int32_t* __restrict__ sci,
                                                  float* __restrict__ scv) {
-  extern __shared__ float tile[];  // [c][BQ_W], then the cluster's level starts [depth + 1]
+  extern __shared__ float tile[];  // [BQ_W][cs], then the cluster's level starts [depth + 1]
   constexpr int NWV = NT / PMMF_WAVE;
   __shared__ int part[NWV][BQ_W];
   const int u = blockIdx.y;
@@ -2702,12 +2702,15 @@ __global__ void __launch_bounds__(NT) k_qsparse(const int32_t* __restrict__ off,
   const int col0 = blockIdx.x * BQ_W;
   if (col0 >= c) return;
   const int tid = threadIdx.x;
+  // column-major slice with an odd column stride: the BQ_W columns of one row fall in distinct
+  // banks, and the extraction below reads 64 consecutive rows of one column per instruction
+  const int cs = c | 1;
   const int* lp = lvl_ptr + (size_t)u * lvl_stride;
   const int dep = depth[u];
-  int* slp = reinterpret_cast<int*>(tile + (size_t)c * BQ_W);
+  int* slp = reinterpret_cast<int*>(tile + (size_t)BQ_W * cs);
   for (int q = tid; q <= dep; q += NT) slp[q] = lp[q];
-  for (int q = tid; q < c * BQ_W; q += NT) {
-    const int row = q / BQ_W, w = q % BQ_W;
+  for (int q = tid; q < BQ_W * cs; q += NT) {
+    const int w = q / cs, row = q - w * cs;
     tile[q] = row == col0 + w ? 1.f : 0.f;
   }
   __syncthreads();
@@ -2734,15 +2737,16 @@ __global__ void __launch_bounds__(NT) k_qsparse(const int32_t* __restrict__ off,
     }
   };
   auto rotate = [&](int w, const int (&id)[K], const float* om) {
+    float* col = tile + w * cs;
     float x[K];
 #pragma unroll
-    for (int a = 0; a < K; ++a) x[a] = tile[id[a] * BQ_W + w];
+    for (int a = 0; a < K; ++a) x[a] = col[id[a]];
 #pragma unroll
     for (int a = 0; a < K; ++a) {
       float acc = 0.f;
 #pragma unroll
       for (int b = 0; b < K; ++b) acc = fmaf(om[a * K + b], x[b], acc);
-      tile[id[a] * BQ_W + w] = acc;
+      col[id[a]] = acc;
     }
   };
   auto level = [&](int l, const Items& it) {
@@ -2770,19 +2774,22 @@ __global__ void __launch_bounds__(NT) k_qsparse(const int32_t* __restrict__ off,
     fetch(l + 2, ia);
     level(l + 1, ib);
   }
-  // each thread takes a contiguous block of rows; per column, the nonzeros of the earlier blocks
-  // (a scan over the waves and their lanes) place its own, so each column's rows ascend
-  const int rpt = (c + blockDim.x - 1) / blockDim.x;
-  const int r0 = min(c, tid * rpt), r1 = min(c, r0 + rpt);
+  // nonzeros of each column in ascending rows: wave v takes rows [v rw, (v + 1) rw) in 64-row
+  // chunks; a ballot orders a chunk's nonzeros, the waves' counts (scanned in wave order) place
+  // each wave's run
   const int wv = tid / PMMF_WAVE, lane = pmmf_lane();
-  int ex[BQ_W];
+  const int rw = ((c + NWV * PMMF_WAVE - 1) / (NWV * PMMF_WAVE)) * PMMF_WAVE;
+  const int rb = min(c, wv * rw), re = min(c, rb + rw);
+  const uint64_t below = (1ull << lane) - 1ull;
 #pragma unroll
   for (int w = 0; w < BQ_W; ++w) {
+    const float* col = tile + w * cs;
     int n = 0;
-    for (int row = r0; row < r1; ++row) n += tile[row * BQ_W + w] != 0.f;
-    const int incl = pmmf_wave_incl_scan_dpp(n);
-    ex[w] = incl - n;
-    if (lane == PMMF_WAVE - 1) part[wv][w] = incl;
+    for (int r = rb; r < re; r += PMMF_WAVE) {
+      const int row = r + lane;
+      n += __popcll(__ballot(row < re && col[min(row, c - 1)] != 0.f));
+    }
+    if (lane == 0) part[wv][w] = n;
   }
   __syncthreads();
 #pragma unroll
@@ -2796,14 +2803,19 @@ __global__ void __launch_bounds__(NT) k_qsparse(const int32_t* __restrict__ off,
     }
     if (tid == 0) cnt[o + col0 + w] = total;
     const size_t cb = (size_t)gbase[u] + (size_t)(col0 + w) * c;
-    int pos = before + ex[w];
-    for (int row = r0; row < r1; ++row) {
-      const float v = tile[row * BQ_W + w];
-      if (v != 0.f) {
-        sci[cb + pos] = o + row;
-        scv[cb + pos] = v;
-        ++pos;
+    const float* col = tile + w * cs;
+    int pos = before;
+    for (int r = rb; r < re; r += PMMF_WAVE) {
+      const int row = r + lane;
+      const float v = col[min(row, c - 1)];
+      const bool nz = row < re && v != 0.f;
+      const uint64_t bm = __ballot(nz);
+      if (nz) {
+        const int at = pos + __popcll(bm & below);
+        sci[cb + at] = o + row;
+        scv[cb + at] = v;
       }
+      pos += __popcll(bm);
     }
   }
 }
@@ -2813,10 +2825,11 @@ hipError_t launch_qsparse(int m, int k, const int32_t* off, const int64_t* gbase
                           const int32_t* sw_loc, const float* sw_o, int32_t* cnt, int32_t* sci,
                           float* scv, int cmax, hipStream_t s) {
   if (m == 0) return hipSuccess;
-  // 8-column slices, 256 threads (16 columns with 512 threads measured slower: half as many
-  // workgroups fit a compute unit, and each level's latency is the same)
-  constexpr int bw = 8;
-  const size_t lds = (size_t)cmax * bw * sizeof(float) + (size_t)lvl_stride * sizeof(int);
+  // 4-column slices, 256 threads: the fastest of 2, 4, 8 and 16 columns with 128, 256 and 512
+  // threads on the 262k factor (each workgroup is bound by its chain of level barriers, so more
+  // resident workgroups win until the extra copies of the rotation loads cost more)
+  constexpr int bw = 4;
+  const size_t lds = (size_t)(cmax | 1) * bw * sizeof(float) + (size_t)lvl_stride * sizeof(int);
   dim3 grid((unsigned)((cmax + bw - 1) / bw), (unsigned)m);
   auto go = [&](auto kern) -> hipError_t {
     if (lds > 64 * 1024) {
