@@ -3990,16 +3990,21 @@ __global__ void k_h_stats(int64_t n, const float* __restrict__ hdiag, int64_t co
     f0 += a * a;
     t += a;
   }
+  // the core (up to a few million entries): eight loads in flight per thread
   const int64_t cc = core * core;
-  for (i = threadIdx.x; i + bd < cc; i += 2 * bd) {
-    const double a = hcore[i], b = hcore[i + bd];
-    f0 += a * a;
-    f1 += b * b;
+  double g[8] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+  for (i = threadIdx.x; i + 7 * bd < cc; i += 8 * bd) {
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+      const double a = hcore[i + q * bd];
+      g[q] += a * a;
+    }
   }
   for (; i < cc; i += bd) {
     const double a = hcore[i];
     f0 += a * a;
   }
+  f0 += ((g[0] + g[1]) + (g[2] + g[3])) + ((g[4] + g[5]) + (g[6] + g[7]));
   for (i = threadIdx.x; i < core; i += bd) t += hcore[i * core + i];
   double f = f0 + f1;
   f = pmmf_wave_sum_double(f);
