@@ -1817,17 +1817,6 @@ __global__ void __launch_bounds__(NT) k_search(FindArgs A, int cmax) {
         x12 = GD[(size_t)t1 * ld + t2];
         x21 = GD[(size_t)t2 * ld + t1];
       }
-      if (s + 2 < r) {
-        // next-seed rule: the rank-th active index after a retirement e is the rank-th one before
-        // it if that lies below e, else the (rank + 1)-th.  The seed of step s+2 follows two more
-        // retirements (steps s and s+1), so the rank-th to (rank + 2)-th indices are taken now;
-        // after this step two candidates remain, after the next one the seed.
-        const uint64_t h = pmmf_hash4(A.seed, PMMF_TAG_SEED_ROW, (uint64_t)A.p, (uint64_t)u,
-                                      (uint64_t)(s + 2));
-        int kn[3];
-        select_activeN<3>(mask, nw, (int)pmmf_mulhi(h, (uint64_t)(c - (s + 2))), kn);
-        if (lane == 0) { sh_k[0] = kn[0]; sh_k[1] = kn[1]; sh_k[2] = kn[2]; }
-      }
       if (lane == 0) {
         double g[3][3] = {}, d[3][3] = {}, O[3][3] = {};
         g[0][0] = gdiag[t0];
@@ -2051,6 +2040,18 @@ __global__ void __launch_bounds__(NT) k_search(FindArgs A, int cmax) {
     if (f1.j >= c || (K == 3 && f2.j >= c)) return;  // reported by the control wave
     const int t0 = i, t1 = f1.j, t2 = K == 3 ? f2.j : -1;
     const int st1 = slot_of(t1, tq0, tq1, tq2), st2 = K == 3 ? slot_of(t2, tq0, tq1, tq2) : -1;
+    if (wv == NW - 1 && s + 2 < r) {
+      // next-seed rule: the rank-th active index after a retirement e is the rank-th one before
+      // it if that lies below e, else the (rank + 1)-th.  The seed of step s+2 follows two more
+      // retirements (steps s and s+1), so the rank-th to (rank + 2)-th indices are taken now;
+      // after this step two candidates remain, after the next one the seed.  Taken by the last
+      // column wave (among the first to reach barrier B), off the control wave's chain.
+      const uint64_t h = pmmf_hash4(A.seed, PMMF_TAG_SEED_ROW, (uint64_t)A.p, (uint64_t)u,
+                                    (uint64_t)(s + 2));
+      int kn[3];
+      select_activeN<3>(mask, nw, (int)pmmf_mulhi(h, (uint64_t)(c - (s + 2))), kn);
+      if (lane == 0) { sh_k[0] = kn[0]; sh_k[1] = kn[1]; sh_k[2] = kn[2]; }
+    }
     // the next seed is cc0 if cc0 lies below this step's retiree e (one of T), else cc1: only the
     // rows that can be chosen are fetched and scored
     const int tmin = K == 3 ? min(t0, min(t1, t2)) : min(t0, t1);
