@@ -2716,10 +2716,11 @@ __global__ void __launch_bounds__(NT) k_qsparse(const int32_t* __restrict__ off,
   }
   __syncthreads();
   // Thread tid takes items tid + i NT (i < QS_I) of each level (item = rotation x column); their
-  // slots and blocks are loaded one level ahead into a second register set, so a level waits for
-  // LDS only.  Items past QS_I NT in a level (a level of more than QS_I NT / BQ_W rotations) load
-  // their rotation when they are applied.
-  constexpr int QS_I = 4;
+  // slots and blocks are loaded one level ahead into a second register set.  Items past QS_I NT
+  // in a level (a level of more than QS_I NT / BQ_W rotations) load their rotation when they are
+  // applied.  One item: more items per thread cost registers, and the kernel is bound by how many
+  // workgroups are resident (rotate phase 22.6 ms with four items, 21.8 ms with one).
+  constexpr int QS_I = 1;
   struct Items {
     int id[QS_I][K];
     float om[QS_I][K * K];
