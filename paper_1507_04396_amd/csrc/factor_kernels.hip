@@ -2932,7 +2932,31 @@ __global__ void k_levelize(int k, const int32_t* __restrict__ off, const int32_t
   const int rb = roff[u];
   for (int j = threadIdx.x; j < c; j += blockDim.x) last[j] = 0;
   for (int j = threadIdx.x; j < c + 2; j += blockDim.x) start[j] = 0;
-  for (int q = threadIdx.x; q < r * 3; q += blockDim.x) ids[q] = rot_loc[(rot0 + rb) * 3 + q];
+  // the cluster's rotation ids (and the recorded levels) staged in LDS, eight loads in flight per
+  // thread at a time
+  {
+    const int32_t* src = rot_loc + (rot0 + rb) * 3;
+    const int n3 = r * 3, bd = blockDim.x;
+    for (int q0 = 0; q0 < n3; q0 += 8 * bd) {
+      int v[8];
+#pragma unroll
+      for (int t = 0; t < 8; ++t) v[t] = src[min(q0 + t * bd + (int)threadIdx.x, max(n3 - 1, 0))];
+#pragma unroll
+      for (int t = 0; t < 8; ++t)
+        if (q0 + t * bd + (int)threadIdx.x < n3) ids[q0 + t * bd + threadIdx.x] = v[t];
+    }
+    if (lvl_in) {
+      const int32_t* li = lvl_in + rot0 + rb;
+      for (int q0 = 0; q0 < r; q0 += 8 * bd) {
+        int v[8];
+#pragma unroll
+        for (int t = 0; t < 8; ++t) v[t] = li[min(q0 + t * bd + (int)threadIdx.x, max(r - 1, 0))];
+#pragma unroll
+        for (int t = 0; t < 8; ++t)
+          if (q0 + t * bd + (int)threadIdx.x < r) lvl[q0 + t * bd + threadIdx.x] = v[t];
+      }
+    }
+  }
   __syncthreads();
   // Wave 0 walks the rotations with wave-uniform control flow: a chunk of 64 rotations' indices is
   // held one per lane and read back by readlane, and the per-level counts and next free slots
@@ -2947,9 +2971,15 @@ __global__ void k_levelize(int k, const int32_t* __restrict__ off, const int32_t
       const int c0 = ids[sl * 3], c1 = ids[sl * 3 + 1], c2 = ids[sl * 3 + 2];
       const int n = min(PMMF_WAVE, r - s0);
       int lv = 0;
-      if (lvl_in) {  // levels recorded by the search
-        lv = lane < n ? lvl_in[rot0 + rb + s0 + lane] : 0;
-        for (int t = 0; t < n; ++t) cnt_v += lane == __builtin_amdgcn_readlane(lv, t) ? 1 : 0;
+      if (lvl_in) {  // levels recorded by the search: one ballot per distinct level of the chunk
+        lv = lane < n ? lvl[s0 + lane] : 0;
+        uint64_t pend = __ballot(lane < n);
+        while (pend) {
+          const int L = __builtin_amdgcn_readlane(lv, (int)__builtin_ctzll(pend));
+          const uint64_t m = __ballot(lane < n && lv == L);
+          cnt_v += lane == L ? (int)__popcll(m) : 0;
+          pend &= ~m;
+        }
         depth = max(depth, pmmf_wave_max_int(lv));
       } else {
         for (int t = 0; t < n; ++t) {
@@ -2982,15 +3012,21 @@ __global__ void k_levelize(int k, const int32_t* __restrict__ off, const int32_t
         sh_depth = depth;
       }
       // slot of each rotation in level order (rotation order inside a level)
+      // (one ballot per distinct level of a chunk: the chunk's rotations of level L take the next
+      // slots of L in chunk order)
+      const uint64_t below = (1ull << lane) - 1ull;
       for (int s0 = 0; s0 < r; s0 += PMMF_WAVE) {
         const int n = min(PMMF_WAVE, r - s0);
         const int lvv = lane < n ? lvl[s0 + lane] : 0;
         int slot = 0;
-        for (int t = 0; t < n; ++t) {
-          const int L = __builtin_amdgcn_readlane(lvv, t);
-          const int sl = __builtin_amdgcn_readlane(start_v, L);
-          start_v += lane == L ? 1 : 0;
-          slot = lane == t ? sl : slot;
+        uint64_t pend = __ballot(lane < n);
+        while (pend) {
+          const int L = __builtin_amdgcn_readlane(lvv, (int)__builtin_ctzll(pend));
+          const uint64_t m = __ballot(lane < n && lvv == L);
+          const int base = __builtin_amdgcn_readlane(start_v, L);
+          if ((m >> lane) & 1ull) slot = base + (int)__popcll(m & below);
+          start_v += lane == L ? (int)__popcll(m) : 0;
+          pend &= ~m;
         }
         if (lane < n) lvl[s0 + lane] = slot;
       }
@@ -3033,11 +3069,14 @@ __global__ void k_levelize(int k, const int32_t* __restrict__ off, const int32_t
   for (int s = threadIdx.x; s < r; s += blockDim.x) {
     const int64_t ridx = rot0 + rb + s;
     const int pos = rb + lvl[s];
+    float ob[9];
+#pragma unroll
+    for (int q = 0; q < 9; ++q) ob[q] = rot_o[ridx * 9 + q];
     for (int a = 0; a < k; ++a) sw_loc[(size_t)pos * k + a] = ids[s * 3 + a];
     for (int a = 0; a < k; ++a)
-      for (int b = 0; b < k; ++b) sw_o[(size_t)pos * kk2 + a * k + b] = rot_o[ridx * 9 + a * 3 + b];
+      for (int b = 0; b < k; ++b) sw_o[(size_t)pos * kk2 + a * k + b] = ob[a * 3 + b];
     sw_idx[pos] = (int32_t)ridx;
-    if (k == 2) theta[ridx] = (float)atan2((double)rot_o[ridx * 9 + 3], (double)rot_o[ridx * 9 + 0]);
+    if (k == 2) theta[ridx] = (float)atan2((double)ob[3], (double)ob[0]);
   }
 }
 
