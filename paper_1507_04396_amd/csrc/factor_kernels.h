@@ -98,13 +98,14 @@ hipError_t launch_qt_compact(int S, const int32_t* off, const int32_t* cl_of,
 // each row of a CSR (distinct columns) in ascending column order, out of place
 hipError_t launch_sort_rows(int n, const int64_t* rp, const int32_t* ci, const float* cv,
                             int32_t* oci, float* ocv, hipStream_t s);
-// W = M Qbar^T; with fill = 1 it also records where each run of row x (the runs of the run table
-// run_ptr of M) starts in W's staging row: wrs[run_ptr[x] + r]
+// W = M Qbar^T, run by run of M's run table (run_ptr, run_cl, run_start as built by launch_runs);
+// with fill = 1 it also records where each run r of row x starts in W's staging row:
+// wrs[run_ptr[x] + r]
 hipError_t launch_right(int S, int fill, const int64_t* rp, const int32_t* ci, const float* cv,
-                        const int32_t* off, const int32_t* cl_of, const int64_t* qrp,
-                        const int32_t* qci, const float* qcv, int32_t* cnt, const int64_t* orp,
-                        int32_t* oci, float* ocv, const int64_t* run_ptr, int64_t* wrs,
-                        int cmax, hipStream_t s);
+                        const int32_t* off, const int64_t* run_ptr, const int32_t* run_cl,
+                        const int64_t* run_start, const int64_t* qrp, const int32_t* qci,
+                        const float* qcv, int32_t* cnt, const int64_t* orp, int32_t* oci,
+                        float* ocv, int64_t* wrs, int cmax, hipStream_t s);
 // A_p = Qbar W with peeling; W's rows are runs as recorded by launch_right (run table run_ptr,
 // run_cl of M, starts wrs)
 hipError_t launch_left(int S, int fill, const int64_t* qrp, const int32_t* qci, const float* qcv,

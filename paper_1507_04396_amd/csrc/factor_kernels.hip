@@ -3168,17 +3168,20 @@ hipError_t launch_cut_counts(int S, const int64_t* rp, const int32_t* ci, int32_
 
 // ------------------------------------------------------------------------------------------
 // Right rotation W = M Qbar^T (the column half of [[A_p]]_{u,v} = Qbar_u [[A_{p-1}]]_{u,v}
-// Qbar_v^T in Alg. 1).  One wave per row x; the row's entries are grouped into runs of one
-// cluster v, and each run is expanded through Qbar_v^T in a dense LDS accumulator of c_v slots,
-// list by list in ascending entry order (lanes of one chunk that meet at a column from different
-// lists are combined by the LDS atomic add, in the hardware's fixed lane order).  fill = 0 counts,
-// fill = 1 writes.
+// Qbar_v^T in Alg. 1).  One wave per row x; the row's entries come in runs of one cluster v (the
+// run table of M: starts and clusters), and each run is expanded through Qbar_v^T in a dense LDS
+// accumulator of c_v slots, 64 entries at a time, list by list in ascending entry order (lanes of
+// one chunk that meet at a column from different lists are combined by the LDS atomic add, in the
+// hardware's fixed lane order).  Up to 64 runs' bounds are held one per lane, so the next block's
+// entries are requested before the current block is expanded.  fill = 0 counts, fill = 1 writes.
 constexpr int RIGHT_CH = 2;  // flat 64-entry chunks whose loads are requested together
 __global__ void __launch_bounds__(256) k_right(int S, int fill, const int64_t* __restrict__ rp,
                                                const int32_t* __restrict__ ci,
                                                const float* __restrict__ cv,
                                                const int32_t* __restrict__ off,
-                                               const int32_t* __restrict__ cl_of,
+                                               const int64_t* __restrict__ run_ptr,
+                                               const int32_t* __restrict__ run_cl,
+                                               const int64_t* __restrict__ run_start,
                                                const int64_t* __restrict__ qrp,
                                                const int32_t* __restrict__ qci,
                                                const float* __restrict__ qcv,
@@ -3186,7 +3189,6 @@ __global__ void __launch_bounds__(256) k_right(int S, int fill, const int64_t* _
                                                const int64_t* __restrict__ orp,
                                                int32_t* __restrict__ oci,
                                                float* __restrict__ ocv,
-                                               const int64_t* __restrict__ run_ptr,
                                                int64_t* __restrict__ wrs, int cmax) {
   extern __shared__ float lds_f[];
   const int wpb = blockDim.x / PMMF_WAVE;
@@ -3197,118 +3199,153 @@ __global__ void __launch_bounds__(256) k_right(int S, int fill, const int64_t* _
   const int x = pmmf_xcd_block(blockIdx.x, gridDim.x) * wpb + w;
   if (x >= S) return;
   for (int j = lane; j < cmax; j += PMMF_WAVE) acc[j] = 0.f;
+  const int64_t r0 = rp[x];
   const int64_t end = rp[x + 1];
-  int64_t k = rp[x];
+  const int64_t rr0 = run_ptr[x], rr1 = run_ptr[x + 1];
   int64_t cur = fill ? orp[x] : 0;
-  int64_t rr = fill ? run_ptr[x] : 0;  // run index in the run table of M
-  while (k < end) {
-    const int v = cl_of[ci[k]];
-    const int ov = off[v];
-    const int lim = off[v + 1];
-    int64_t kend = k;
-    while (true) {
-      const int64_t idx = kend + lane;
-      const bool in = idx < end && ci[idx] < lim;
-      const int n = __popcll(__ballot(in));
-      kend += n;
-      if (n < PMMF_WAVE) break;
+  for (int64_t rg = rr0; rg < rr1; rg += PMMF_WAVE) {
+    // this group's runs, one per lane: entries [r0 + rb, r0 + re) of cluster offset rov
+    const int nr = (int)min<int64_t>(PMMF_WAVE, rr1 - rg);
+    int rb = 0, re = 0, rov = 0;
+    if (lane < nr) {
+      const int64_t g = rg + lane;
+      rb = (int)(run_start[g] - r0);
+      re = (int)((g + 1 < rr1 ? run_start[g + 1] : end) - r0);
+      rov = off[run_cl[g]];
     }
-    // W's entries of this run (cluster v) start here
-    if (fill && lane == 0) wrs[rr] = cur;
-    ++rr;
-    int bmin = INT_MAX, bmax = -1;
-    for (int64_t kb = k; kb < kend; kb += PMMF_WAVE) {
-      // lane-parallel lookup of the Qbar^T rows of up to 64 entries y of the run
-      const int nb = (int)min<int64_t>(PMMF_WAVE, kend - kb);
-      int64_t q0 = 0;
-      int len = 0;
-      float mv = 0.f;
-      if (lane < nb) {
-        const int y = ci[kb + lane];
-        mv = cv[kb + lane];
-        q0 = qrp[y];
-        len = (int)(qrp[y + 1] - q0);
-      }
-      // The lists, in entry order, form one flat sequence of T entries (a list of ~10-20 entries
-      // would leave most of a 64-lane chunk idle); flat position f of list l is entry
-      // q0_l + f - P_l.  Lanes of one chunk may hit the same column from different lists, hence
-      // the LDS atomic add.
-      const int incl = pmmf_wave_incl_scan_dpp(len);
-      const int P = incl - len;
-      const int T = __builtin_amdgcn_readlane(incl, PMMF_WAVE - 1);
-      const int64_t lbase = q0 - P;
-      int carry = -1;  // list of the last flat position so far
-      for (int f0 = 0; f0 < T; f0 += RIGHT_CH * PMMF_WAVE) {
-        int cc[RIGHT_CH];
-        float vv[RIGHT_CH];
-        bool ok[RIGHT_CH];
-#pragma unroll
-        for (int h = 0; h < RIGHT_CH; ++h) {
-          // the list of each flat position: list l marks its start, a running maximum fills in.
-          // The marks cross lanes through LDS, so they are atomic accesses ordered by a
-          // wavefront fence (plain accesses would let each lane see only its own writes).
-          int* hd = head + h * PMMF_WAVE;
-          __hip_atomic_store(hd + lane, -1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT);
-          const int rel = P - (f0 + h * PMMF_WAVE);
-          if (len > 0 && rel >= 0 && rel < PMMF_WAVE)
-            __hip_atomic_store(hd + rel, lane, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT);
-          __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-          __builtin_amdgcn_wave_barrier();
-          const int mark = __hip_atomic_load(hd + lane, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT);
-          int l = max(pmmf_wave_incl_max_dpp(mark), carry);
-          carry = __builtin_amdgcn_readlane(l, PMMF_WAVE - 1);
-          l = max(l, 0);
-          const int f = f0 + h * PMMF_WAVE + lane;
-          ok[h] = f < T;
-          const int64_t e = __shfl(lbase, l) + f;
-          vv[h] = __shfl(mv, l);
-          cc[h] = ok[h] ? qci[e] : ov;
-          vv[h] = ok[h] ? vv[h] * qcv[e] : 0.f;
+    // the block cursor: run ri, block start kb (relative to r0); blocks are a run's consecutive
+    // 64-entry pieces, in run order
+    int ri = 0;
+    int kb = __builtin_amdgcn_readlane(rb, 0);
+    int ke = __builtin_amdgcn_readlane(re, 0);
+    // the pending block's entries (lanes past its end repeat its last entry)
+    int py = ci[r0 + kb + min(lane, ke - kb - 1)];
+    float pm = cv[r0 + kb + min(lane, ke - kb - 1)];
+    while (ri < nr) {
+      const int ov = __builtin_amdgcn_readlane(rov, ri);
+      // W's entries of this run (cluster v) start here
+      if (fill && lane == 0) wrs[rg + ri] = cur;
+      int bmin = INT_MAX, bmax = -1;
+      bool more = true;
+      while (more) {
+        const int nb = min(PMMF_WAVE, ke - kb);
+        const int y = py;
+        const float mv = lane < nb ? pm : 0.f;
+        const int64_t q0 = qrp[y];
+        const int64_t q1 = qrp[y + 1];
+        // step the cursor and request the next block's entries (the current one again at the
+        // group's end: a valid address whose values are not used)
+        more = kb + PMMF_WAVE < ke;
+        int nkb, nke;
+        if (more) {
+          nkb = kb + PMMF_WAVE;
+          nke = ke;
+        } else if (ri + 1 < nr) {
+          nkb = __builtin_amdgcn_readlane(rb, ri + 1);
+          nke = __builtin_amdgcn_readlane(re, ri + 1);
+        } else {
+          nkb = kb;
+          nke = ke;
         }
+        py = ci[r0 + nkb + min(lane, nke - nkb - 1)];
+        pm = cv[r0 + nkb + min(lane, nke - nkb - 1)];
+        const int len = lane < nb ? (int)(q1 - q0) : 0;
+        // The lists, in entry order, form one flat sequence of T entries (a list of ~10-20
+        // entries would leave most of a 64-lane chunk idle); flat position f of list l is entry
+        // q0_l + f - P_l.  Lanes of one chunk may hit the same column from different lists,
+        // hence the LDS atomic add.
+        const int incl = pmmf_wave_incl_scan_dpp(len);
+        const int P = incl - len;
+        const int T = __builtin_amdgcn_readlane(incl, PMMF_WAVE - 1);
+        const int64_t lbase = q0 - P;
+        int carry = -1;  // list of the last flat position so far
+        for (int f0 = 0; f0 < T; f0 += RIGHT_CH * PMMF_WAVE) {
+          int cc[RIGHT_CH];
+          float vv[RIGHT_CH];
+          bool ok[RIGHT_CH];
 #pragma unroll
-        for (int h = 0; h < RIGHT_CH; ++h) {
-          if (ok[h]) {
-            const int b = cc[h] - ov;
-            __hip_atomic_fetch_add(acc + b, vv[h], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
-            bmin = min(bmin, b);
-            bmax = max(bmax, b);
+          for (int h = 0; h < RIGHT_CH; ++h) {
+            // the list of each flat position: list l marks its start, a running maximum fills
+            // in.  The marks cross lanes through LDS, so they are atomic accesses ordered by a
+            // wavefront fence (plain accesses would let each lane see only its own writes).
+            int* hd = head + h * PMMF_WAVE;
+            __hip_atomic_store(hd + lane, -1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT);
+            const int rel = P - (f0 + h * PMMF_WAVE);
+            if (len > 0 && rel >= 0 && rel < PMMF_WAVE)
+              __hip_atomic_store(hd + rel, lane, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT);
+            __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+            const int mark = __hip_atomic_load(hd + lane, __ATOMIC_RELAXED,
+                                               __HIP_MEMORY_SCOPE_WAVEFRONT);
+            int l = max(pmmf_wave_incl_max_dpp(mark), carry);
+            carry = __builtin_amdgcn_readlane(l, PMMF_WAVE - 1);
+            l = max(l, 0);
+            const int f = f0 + h * PMMF_WAVE + lane;
+            ok[h] = f < T;
+            const int64_t e = __shfl(lbase, l) + f;
+            vv[h] = __shfl(mv, l);
+            cc[h] = ok[h] ? qci[e] : ov;
+            vv[h] = ok[h] ? vv[h] * qcv[e] : 0.f;
+          }
+#pragma unroll
+          for (int h = 0; h < RIGHT_CH; ++h) {
+            if (ok[h]) {
+              const int b = cc[h] - ov;
+              __hip_atomic_fetch_add(acc + b, vv[h], __ATOMIC_RELAXED,
+                                     __HIP_MEMORY_SCOPE_WORKGROUP);
+              bmin = min(bmin, b);
+              bmax = max(bmax, b);
+            }
           }
         }
+        kb = nkb;
+        ke = nke;
       }
-    }
-    bmin = pmmf_wave_min_int(bmin);
-    bmax = pmmf_wave_max_int(bmax);
-    for (int base = bmin; base <= bmax; base += PMMF_WAVE) {
-      const int j = base + lane;
-      float val = 0.f;
-      if (j <= bmax) { val = acc[j]; acc[j] = 0.f; }
-      const uint64_t b = __ballot(val != 0.f);
-      if (fill && val != 0.f) {
-        const int64_t pos = cur + pmmf_lanes_below(b);
-        oci[pos] = ov + j;
-        ocv[pos] = val;
+      bmin = pmmf_wave_min_int(bmin);
+      bmax = pmmf_wave_max_int(bmax);
+      // the run's accumulated row segment, eight 64-column chunks per round
+      for (int bb0 = bmin; bb0 <= bmax; bb0 += 8 * PMMF_WAVE) {
+        float vals[8];
+#pragma unroll
+        for (int t = 0; t < 8; ++t) {
+          const int j = bb0 + t * PMMF_WAVE + lane;
+          vals[t] = 0.f;
+          if (j <= bmax) {
+            vals[t] = acc[j];
+            acc[j] = 0.f;
+          }
+        }
+#pragma unroll
+        for (int t = 0; t < 8; ++t) {
+          const uint64_t b = __ballot(vals[t] != 0.f);
+          if (fill && vals[t] != 0.f) {
+            const int64_t pos = cur + pmmf_lanes_below(b);
+            oci[pos] = ov + bb0 + t * PMMF_WAVE + lane;
+            ocv[pos] = vals[t];
+          }
+          cur += __popcll(b);
+        }
       }
-      cur += __popcll(b);
+      ++ri;
     }
-    k = kend;
   }
   if (lane == 0) cnt[x] = (int32_t)(fill ? cur - orp[x] : cur);
 }
 
 hipError_t launch_right(int S, int fill, const int64_t* rp, const int32_t* ci, const float* cv,
-                        const int32_t* off, const int32_t* cl_of, const int64_t* qrp,
-                        const int32_t* qci, const float* qcv, int32_t* cnt, const int64_t* orp,
-                        int32_t* oci, float* ocv, const int64_t* run_ptr, int64_t* wrs,
-                        int cmax, hipStream_t s) {
+                        const int32_t* off, const int64_t* run_ptr, const int32_t* run_cl,
+                        const int64_t* run_start, const int64_t* qrp, const int32_t* qci,
+                        const float* qcv, int32_t* cnt, const int64_t* orp, int32_t* oci,
+                        float* ocv, int64_t* wrs, int cmax, hipStream_t s) {
   if (S == 0) return hipSuccess;
   // one wave (one row) per workgroup, as in launch_left: the LDS of a finished row is released
   // at once instead of waiting for the slowest row of its workgroup
   int wpb = 1;
   while (wpb > 1 && (size_t)wpb * (cmax + RIGHT_CH * PMMF_WAVE) * 4 > 64 * 1024) wpb >>= 1;
   const size_t lds = (size_t)wpb * (cmax + RIGHT_CH * PMMF_WAVE) * sizeof(float);
-  k_right<<<(S + wpb - 1) / wpb, wpb * PMMF_WAVE, lds, s>>>(S, fill, rp, ci, cv, off, cl_of, qrp,
-                                                            qci, qcv, cnt, orp, oci, ocv, run_ptr,
-                                                            wrs, cmax);
+  k_right<<<(S + wpb - 1) / wpb, wpb * PMMF_WAVE, lds, s>>>(S, fill, rp, ci, cv, off, run_ptr,
+                                                            run_cl, run_start, qrp, qci, qcv,
+                                                            cnt, orp, oci, ocv, wrs, cmax);
   return hipGetLastError();
 }
 

@@ -1095,7 +1095,7 @@ extern "C" int mmf_factor(int64_t n, int64_t nnz, const int64_t* d_rowptr, const
     sd.dense_gram = dense_gram;
     const bool bf16 = h->prm.gram_mode == 1;
     // run table of the active matrix (each row's column runs per cluster): read by the sparse
-    // Gram and, through the runs' starts in W, by the left rotation
+    // Gram, the right rotation and, through the runs' starts in W, the left rotation
     {
       HIPCHK(pmmf::launch_runs(S, 0, M.rp.as<int64_t>(), M.ci.as<int32_t>(),
                                sd.cl_of.as<int32_t>(), cnt.as<int32_t>(), nullptr, nullptr,
@@ -1274,10 +1274,10 @@ extern "C" int mmf_factor(int64_t n, int64_t nnz, const int64_t* d_rowptr, const
     W.cv.ensure(std::max<int64_t>(wcap, 1) * sizeof(float));
     wcnt.ensure(S * sizeof(int32_t));
     HIPCHK(pmmf::launch_right(S, 1, M.rp.as<int64_t>(), M.ci.as<int32_t>(), M.cv.as<float>(),
-                              sd.off.as<int32_t>(), sd.cl_of.as<int32_t>(), Qt.rp.as<int64_t>(),
-                              Qt.ci.as<int32_t>(), Qt.cv.as<float>(), wcnt.as<int32_t>(),
-                              wstart.as<int64_t>(), W.ci.as<int32_t>(), W.cv.as<float>(),
-                              run_ptr.as<int64_t>(), wrs.as<int64_t>(), cm, s));
+                              sd.off.as<int32_t>(), run_ptr.as<int64_t>(), run_cl.as<int32_t>(),
+                              run_start.as<int64_t>(), Qt.rp.as<int64_t>(), Qt.ci.as<int32_t>(),
+                              Qt.cv.as<float>(), wcnt.as<int32_t>(), wstart.as<int64_t>(),
+                              W.ci.as<int32_t>(), W.cv.as<float>(), wrs.as<int64_t>(), cm, s));
     // A_p = Qbar W, peeled to the survivors, plus the exact residual of the retired rows: written
     // into staging rows, then compacted into the next stage's CSR
     HIPCHK(pmmf::launch_bound_left(S, Qr.rp.as<int64_t>(), Qr.ci.as<int32_t>(), wcnt.as<int32_t>(),
