@@ -3172,7 +3172,8 @@ hipError_t launch_cut_counts(int S, const int64_t* rp, const int32_t* ci, int32_
 // run table of M: starts and clusters), and each run is expanded through Qbar_v^T in a dense LDS
 // accumulator of c_v slots, 64 entries at a time, list by list in ascending entry order (lanes of
 // one chunk that meet at a column from different lists are combined by the LDS atomic add, in the
-// hardware's fixed lane order).  Up to 64 runs' bounds are held one per lane, so the next block's
+// hardware's fixed lane order; each position's list comes from the few lists that start in its
+// chunk, read lane by lane).  Up to 64 runs' bounds are held one per lane, so the next block's
 // entries are requested before the current block is expanded.  fill = 0 counts, fill = 1 writes.
 constexpr int RIGHT_CH = 2;  // flat 64-entry chunks whose loads are requested together
 __global__ void __launch_bounds__(256) k_right(int S, int fill, const int64_t* __restrict__ rp,
@@ -3193,9 +3194,8 @@ __global__ void __launch_bounds__(256) k_right(int S, int fill, const int64_t* _
   extern __shared__ float lds_f[];
   const int wpb = blockDim.x / PMMF_WAVE;
   const int w = pmmf_wave(), lane = pmmf_lane();
-  // cmax accumulator slots, then the list heads of RIGHT_CH flat chunks
-  float* acc = lds_f + (size_t)w * (cmax + RIGHT_CH * PMMF_WAVE);
-  int* head = reinterpret_cast<int*>(acc + cmax);
+  // cmax accumulator slots
+  float* acc = lds_f + (size_t)w * cmax;
   const int x = pmmf_xcd_block(blockIdx.x, gridDim.x) * wpb + w;
   if (x >= S) return;
   for (int j = lane; j < cmax; j += PMMF_WAVE) acc[j] = 0.f;
@@ -3258,40 +3258,48 @@ __global__ void __launch_bounds__(256) k_right(int S, int fill, const int64_t* _
         const int P = incl - len;
         const int T = __builtin_amdgcn_readlane(incl, PMMF_WAVE - 1);
         const int64_t lbase = q0 - P;
-        int carry = -1;  // list of the last flat position so far
+        // the list of the positions before this chunk's first list start: its entry base and
+        // weight (wave-uniform)
+        int64_t cbase = 0;
+        float cw = 0.f;
         for (int f0 = 0; f0 < T; f0 += RIGHT_CH * PMMF_WAVE) {
           int cc[RIGHT_CH];
-          float vv[RIGHT_CH];
+          float vv[RIGHT_CH], qv[RIGHT_CH];
           bool ok[RIGHT_CH];
 #pragma unroll
           for (int h = 0; h < RIGHT_CH; ++h) {
-            // the list of each flat position: list l marks its start, a running maximum fills
-            // in.  The marks cross lanes through LDS, so they are atomic accesses ordered by a
-            // wavefront fence (plain accesses would let each lane see only its own writes).
-            int* hd = head + h * PMMF_WAVE;
-            __hip_atomic_store(hd + lane, -1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT);
-            const int rel = P - (f0 + h * PMMF_WAVE);
-            if (len > 0 && rel >= 0 && rel < PMMF_WAVE)
-              __hip_atomic_store(hd + rel, lane, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT);
-            __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-            __builtin_amdgcn_wave_barrier();
-            const int mark = __hip_atomic_load(hd + lane, __ATOMIC_RELAXED,
-                                               __HIP_MEMORY_SCOPE_WAVEFRONT);
-            int l = max(pmmf_wave_incl_max_dpp(mark), carry);
-            carry = __builtin_amdgcn_readlane(l, PMMF_WAVE - 1);
-            l = max(l, 0);
-            const int f = f0 + h * PMMF_WAVE + lane;
+            // the list of each flat position: the lists that start in this chunk, in list order
+            // (a few per chunk), each take over the positions from their start on
+            const int fb = f0 + h * PMMF_WAVE;
+            const int f = fb + lane;
+            const int rel = P - fb;
+            uint64_t starts = __ballot(len > 0 && rel >= 0 && rel < PMMF_WAVE);
+            int64_t eb = cbase;
+            float wq = cw;
+            while (starts) {
+              const int l = (int)__builtin_ctzll(starts);
+              starts &= starts - 1;
+              const int pl = __builtin_amdgcn_readlane(P, l);
+              cbase = ((int64_t)__builtin_amdgcn_readlane((int)(lbase >> 32), l) << 32) |
+                      (uint32_t)__builtin_amdgcn_readlane((int)lbase, l);
+              cw = pmmf_readlane_f(mv, l);
+              const bool in = f >= pl;
+              eb = in ? cbase : eb;
+              wq = in ? cw : wq;
+            }
+            // a position past T loads the last list's last entry (a valid address) and adds
+            // nothing; the loads of all RIGHT_CH chunks are in flight before the first add
             ok[h] = f < T;
-            const int64_t e = __shfl(lbase, l) + f;
-            vv[h] = __shfl(mv, l);
-            cc[h] = ok[h] ? qci[e] : ov;
-            vv[h] = ok[h] ? vv[h] * qcv[e] : 0.f;
+            const int64_t e = eb + min(f, T - 1);
+            cc[h] = qci[e];
+            qv[h] = qcv[e];
+            vv[h] = wq;
           }
 #pragma unroll
           for (int h = 0; h < RIGHT_CH; ++h) {
             if (ok[h]) {
               const int b = cc[h] - ov;
-              __hip_atomic_fetch_add(acc + b, vv[h], __ATOMIC_RELAXED,
+              __hip_atomic_fetch_add(acc + b, vv[h] * qv[h], __ATOMIC_RELAXED,
                                      __HIP_MEMORY_SCOPE_WORKGROUP);
               bmin = min(bmin, b);
               bmax = max(bmax, b);
@@ -3341,8 +3349,8 @@ hipError_t launch_right(int S, int fill, const int64_t* rp, const int32_t* ci, c
   // one wave (one row) per workgroup, as in launch_left: the LDS of a finished row is released
   // at once instead of waiting for the slowest row of its workgroup
   int wpb = 1;
-  while (wpb > 1 && (size_t)wpb * (cmax + RIGHT_CH * PMMF_WAVE) * 4 > 64 * 1024) wpb >>= 1;
-  const size_t lds = (size_t)wpb * (cmax + RIGHT_CH * PMMF_WAVE) * sizeof(float);
+  while (wpb > 1 && (size_t)wpb * cmax * 4 > 64 * 1024) wpb >>= 1;
+  const size_t lds = (size_t)wpb * cmax * sizeof(float);
   k_right<<<(S + wpb - 1) / wpb, wpb * PMMF_WAVE, lds, s>>>(S, fill, rp, ci, cv, off, run_ptr,
                                                             run_cl, run_start, qrp, qci, qcv,
                                                             cnt, orp, oci, ocv, wrs, cmax);
