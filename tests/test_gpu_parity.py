@@ -56,6 +56,11 @@ SMALL = [
      dict(k=2, eta=0.3, core=20, cluster=(20, 60), seed=9)),
     ("grid_ragged_n257", lambda: workloads.small_grid((1, 257), seed=4),
      dict(k=2, eta=0.5, core=3, cluster=(5, 17), seed=4)),
+    # rows of about 250 entries over 81 clusters of 8-16: a row meets more than 64 clusters, so
+    # the right rotation takes its runs in several groups of 64
+    ("random_sym_n1000_rows_over_64_clusters",
+     lambda: workloads.random_symmetric(1000, 0.25, 12, diag_shift=2.0),
+     dict(k=2, eta=0.5, core=40, cluster=(8, 16), seed=3)),
 ]
 
 
