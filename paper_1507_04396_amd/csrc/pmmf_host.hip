@@ -278,12 +278,31 @@ void upload_async(DBuf& d, const std::vector<T>& h, hipStream_t s) {
   g.stream = s;
 }
 
+// Device -> host reads of a few values between the stages of a factorization: copied into a
+// pinned area of the calling thread (a copy into pageable memory goes through the runtime's own
+// staging buffer).  Each use waits for its copies before it returns, so one area per thread
+// serves every call.
+struct Readback {
+  char* buf = nullptr;
+  ~Readback() {
+    if (buf) (void)hipHostFree(buf);
+  }
+};
+thread_local Readback g_readback;
+constexpr size_t READBACK_BYTES = 256;
+
+char* readback_area() {
+  if (!g_readback.buf)
+    HIPCHK(hipHostMalloc((void**)&g_readback.buf, READBACK_BYTES, hipHostMallocDefault));
+  return g_readback.buf;
+}
+
 int64_t read_i64(const int64_t* dptr, hipStream_t s) {
-  int64_t v = 0;
-  HIPCHK(hipMemcpyAsync(&v, dptr, sizeof(v), hipMemcpyDeviceToHost, s));
+  int64_t* v = reinterpret_cast<int64_t*>(readback_area());
+  HIPCHK(hipMemcpyAsync(v, dptr, sizeof(int64_t), hipMemcpyDeviceToHost, s));
   HIPCHK(hipStreamSynchronize(s));
   staging_synced(s);
-  return v;
+  return *v;
 }
 
 // active matrices with at most this many rows and at least this fill get the dense Gram
@@ -1299,13 +1318,15 @@ extern "C" int mmf_factor(int64_t n, int64_t nnz, const int64_t* d_rowptr, const
     HIPCHK(pmmf::launch_scan(cnt.as<int32_t>(), M2.rp.as<int64_t>(), Snext, scan_tmp.as<int64_t>(), s));
     {
       // the error flags and the next active matrix's entry count, in one wait
-      int32_t fl2[2] = {0, 0};
-      int64_t nnz2 = 0;
+      char* rb = readback_area();
+      int32_t* fl2 = reinterpret_cast<int32_t*>(rb);
+      int64_t* nnz2p = reinterpret_cast<int64_t*>(rb + 8);
       HIPCHK(hipMemcpyAsync(fl2, overflow.p, 2 * sizeof(int32_t), hipMemcpyDeviceToHost, s));
-      HIPCHK(hipMemcpyAsync(&nnz2, M2.rp.as<int64_t>() + Snext, sizeof(int64_t),
+      HIPCHK(hipMemcpyAsync(nnz2p, M2.rp.as<int64_t>() + Snext, sizeof(int64_t),
                             hipMemcpyDeviceToHost, s));
       HIPCHK(hipStreamSynchronize(s));
       staging_synced(s);
+      const int64_t nnz2 = *nnz2p;
       if (fl2[1]) raise(MMF_EDEVICE, "greedy search found no partner in a cluster");
       if (fl2[0]) raise(MMF_ECAPACITY, "a row of Qbar has more than 512 entries");
       M2.nnz = nnz2;
