@@ -280,21 +280,28 @@ void upload_async(DBuf& d, const std::vector<T>& h, hipStream_t s) {
 
 // Device -> host reads of a few values between the stages of a factorization: copied into a
 // pinned area of the calling thread (a copy into pageable memory goes through the runtime's own
-// staging buffer).  Each use waits for its copies before it returns, so one area per thread
-// serves every call.
+// staging buffer).  Each use waits for its copies before it takes the area again, so one area
+// per thread serves every call; it grows to the largest request.
 struct Readback {
   char* buf = nullptr;
+  size_t cap = 0;
   ~Readback() {
     if (buf) (void)hipHostFree(buf);
   }
 };
 thread_local Readback g_readback;
-constexpr size_t READBACK_BYTES = 256;
 
-char* readback_area() {
-  if (!g_readback.buf)
-    HIPCHK(hipHostMalloc((void**)&g_readback.buf, READBACK_BYTES, hipHostMallocDefault));
-  return g_readback.buf;
+char* readback_area(size_t bytes = 64) {
+  Readback& r = g_readback;
+  if (bytes > r.cap) {
+    if (r.buf) HIPCHK(hipHostFree(r.buf));
+    r.buf = nullptr;
+    r.cap = 0;
+    const size_t cap = std::max<size_t>(bytes, 4096);
+    HIPCHK(hipHostMalloc((void**)&r.buf, cap, hipHostMallocDefault));
+    r.cap = cap;
+  }
+  return r.buf;
 }
 
 int64_t read_i64(const int64_t* dptr, hipStream_t s) {
@@ -1367,17 +1374,30 @@ extern "C" int mmf_factor(int64_t n, int64_t nnz, const int64_t* d_rowptr, const
   double hst[4] = {0, 0, 0, 0};
   std::vector<double> sl(sched.size(), 0.0);
   int32_t ovf = 0;
-  HIPCHK(hipMemcpyAsync(hst, dsum.as<double>() + 2, 3 * sizeof(double), hipMemcpyDeviceToHost, s));
   std::vector<unsigned long long> gw(sched.size(), 0);
-  if (!sched.empty()) {
-    HIPCHK(hipMemcpyAsync(sl.data(), stage_loss.p, sl.size() * sizeof(double),
+  {
+    // one wait for the H statistics, the overflow flag and the per-stage losses and Gram work
+    const size_t ns = sched.size();
+    char* rb = readback_area(32 + 16 * ns);
+    double* hst_p = reinterpret_cast<double*>(rb);
+    int32_t* ovf_p = reinterpret_cast<int32_t*>(rb + 24);
+    double* sl_p = reinterpret_cast<double*>(rb + 32);
+    unsigned long long* gw_p = reinterpret_cast<unsigned long long*>(rb + 32 + 8 * ns);
+    HIPCHK(hipMemcpyAsync(hst_p, dsum.as<double>() + 2, 3 * sizeof(double),
                           hipMemcpyDeviceToHost, s));
-    HIPCHK(hipMemcpyAsync(gw.data(), gram_work.p, gw.size() * sizeof(unsigned long long),
-                          hipMemcpyDeviceToHost, s));
+    if (ns > 0) {
+      HIPCHK(hipMemcpyAsync(sl_p, stage_loss.p, ns * sizeof(double), hipMemcpyDeviceToHost, s));
+      HIPCHK(hipMemcpyAsync(gw_p, gram_work.p, ns * sizeof(unsigned long long),
+                            hipMemcpyDeviceToHost, s));
+    }
+    HIPCHK(hipMemcpyAsync(ovf_p, overflow.p, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    staging_synced(s);
+    std::copy(hst_p, hst_p + 3, hst);
+    std::copy(sl_p, sl_p + ns, sl.begin());
+    std::copy(gw_p, gw_p + ns, gw.begin());
+    ovf = *ovf_p;
   }
-  HIPCHK(hipMemcpyAsync(&ovf, overflow.p, sizeof(ovf), hipMemcpyDeviceToHost, s));
-  HIPCHK(hipStreamSynchronize(s));
-  staging_synced(s);
   if (ovf) raise(MMF_ECAPACITY, "a row of a stage rotation had more than 512 terms");
   for (size_t pi = 0; pi < stage_events.size(); ++pi) {
     StageDev& sd = *h->st[pi];
